@@ -1,0 +1,459 @@
+"""Pins for the FP64 oracle: each test checks it against something other than
+itself (closed forms, textbook routines, brute force, hand-computed cases,
+invariants the paper's definitions imply)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+
+# ---------------------------------------------------------------- z-normalisation
+
+def test_znorm_closed_forms():
+    x = W.random_walk(300, 128, seed=11)
+    z = O.znorm(x).astype(np.float64)
+    # mean 0 and squared norm m (population std); fp32 storage bounds the error
+    assert np.abs(z.mean(axis=1)).max() < 1e-6
+    assert np.abs((z ** 2).sum(axis=1) / 128 - 1.0).max() < 1e-6
+    # affine invariance: z(a x + b) == z(x) for a > 0
+    z2 = O.znorm((3.0 * x.astype(np.float64) + 7.0).astype(np.float32)).astype(np.float64)
+    assert np.abs(z2 - z).max() < 1e-5
+
+
+def test_znorm_constant_series_and_c_matches_numpy():
+    x = W.random_walk(50, 64, seed=12)
+    x[3] = 5.0
+    x[7] = 0.0
+    z = O.znorm(x)
+    assert not z[3].any() and not z[7].any()
+    assert np.array_equal(z, O.znorm_py(x))
+
+
+# ---------------------------------------------------------------- distances and k-NN
+
+def _direct(data_s, q_s):
+    return np.sqrt(((q_s[:, None, :].astype(np.float64) - data_s[None].astype(np.float64)) ** 2).sum(-1))
+
+
+def test_distance_expansion_identity():
+    x = O.znorm(W.random_walk(400, 96, seed=13))
+    q = O.znorm(W.noisy_queries(W.random_walk(400, 96, seed=13), 20, 0.2, 1, 2)[0])
+    ids, d = O.knn(x, q, 400)
+    x64, q64 = x.astype(np.float64), q.astype(np.float64)
+    # ||q||^2 + ||x||^2 - 2 q.x, a different route to the same squared distance
+    d2 = (q64 ** 2).sum(1)[:, None] + (x64 ** 2).sum(1)[None] - 2 * q64 @ x64.T
+    got = np.take_along_axis(d2, ids, axis=1)
+    assert np.allclose(d ** 2, got, rtol=1e-9, atol=1e-9)
+    # z-normalised inputs: d^2 = 2m - 2 q.x up to the fp32 storage of ||x||^2 = m
+    approx = 2 * 96 - 2 * np.take_along_axis(q64 @ x64.T, ids, axis=1)
+    assert np.abs(d ** 2 - approx).max() < 1e-3
+
+
+def test_knn_matches_stable_argsort_with_planted_ties():
+    x = W.random_walk(1500, 32, seed=14)
+    x[900] = x[100]          # exact duplicates: equal distances, smaller id first
+    x[1400] = x[100]
+    x[50] = x[1200]
+    xs = O.znorm(x)
+    q = xs[[100, 1200, 7, 300]].copy()
+    q[2] += np.float32(0.01)
+    ids, d = O.knn(xs, q, 10)
+    ref = _direct(xs, q)
+    want = np.argsort(ref, axis=1, kind="stable")[:, :10]
+    assert np.array_equal(ids, want)
+    assert np.allclose(d, np.take_along_axis(ref, want, axis=1), rtol=1e-12)
+    assert list(ids[0, :3]) == [100, 900, 1400] and d[0, 0] == 0.0
+    assert list(ids[1, :2]) == [50, 1200]
+
+
+def test_knn_fewer_series_than_k():
+    xs = O.znorm(W.random_walk(5, 16, seed=15))
+    ids, d = O.knn(xs, xs[:2], 8)
+    assert (ids[:, 5:] == -1).all() and np.isinf(d[:, 5:]).all()
+    assert sorted(ids[0, :5]) == [0, 1, 2, 3, 4]
+
+
+def test_leaf_knn_is_restricted_bruteforce():
+    xs = O.znorm(W.random_walk(900, 48, seed=16))
+    q = O.znorm(W.noisy_queries(W.random_walk(900, 48, seed=16), 7, 0.3, 3, 4)[0])
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(900)
+    leaves = [np.sort(perm[:100]), np.sort(perm[100:650]), np.sort(perm[650:])]
+    d, ids = O.leaf_knn(xs, leaves, q, 4)
+    full = _direct(xs, q)
+    for L, mem in enumerate(leaves):
+        sub = full[:, mem]
+        o = np.argsort(sub, axis=1, kind="stable")[:, :4]
+        assert np.array_equal(ids[:, L], mem[o])
+        assert np.allclose(d[:, L], np.take_along_axis(sub, o, axis=1), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- tree and lower bounds
+
+def test_median_tree_sizes_and_partition():
+    xs = O.znorm(W.random_walk(20000, 256, seed=1001))
+    mu, sd = O.segment_stats(xs, 16)
+    t = O.build_tree(mu, sd, 256, 1000, "median")
+    sizes = [len(l) for l in t.leaves]
+    assert sizes == [625] * 32            # 20000 halves exactly five times
+    allm = np.sort(np.concatenate(t.leaves))
+    assert np.array_equal(allm, np.arange(20000))
+    for l in t.leaves:
+        assert np.all(np.diff(l) > 0)
+
+
+def test_tree_split_choice_hand_case():
+    # m = 4, S = 2: segment means/stds chosen by hand.  Member stats
+    # (seg0 mu, seg1 mu) = (0,0) (0,3) (0,1) (0,2): segment 1's mean has the
+    # largest range, so the median split sends ids {0, 2} (values 0, 1) left.
+    mu = np.array([[0, 0], [0, 3], [0, 1], [0, 2]], dtype=np.float32)
+    sd = np.array([[1, 1], [1, 1], [1, 1], [1, 1]], dtype=np.float32)
+    t = O.build_tree(mu, sd, 4, 2, "median")
+    assert [list(l) for l in t.leaves] == [[0, 2], [1, 3]]
+    assert t.root.split[:2] == (1, 0)
+    # now a std range wins: sd of segment 0 spans 0..2 (score 2*4 = 8) while
+    # mu of segment 1 spans 0..1.5 (score 2*2.25 = 4.5)
+    mu2 = np.array([[0, 0], [0, 1.5], [0, 1], [0, 0.5]], dtype=np.float32)
+    sd2 = np.array([[2, 1], [0, 1], [1, 1], [0.5, 1]], dtype=np.float32)
+    t2 = O.build_tree(mu2, sd2, 4, 2, "median")
+    assert t2.root.split[:2] == (0, 1)
+    assert [list(l) for l in t2.leaves] == [[1, 3], [0, 2]]
+    # midpoint rule: values 0, 0.1, 0.2, 10 split at 5 -> 3 left, 1 right
+    mu3 = np.array([[0, 0], [0, 0.1], [0, 0.2], [0, 10]], dtype=np.float32)
+    t3 = O.build_tree(mu3, sd, 4, 3, "midpoint")
+    assert [list(l) for l in t3.leaves] == [[0, 1, 2], [3]]
+
+
+def _piecewise_constant(vals, seglen):
+    return np.repeat(np.asarray(vals, dtype=np.float32), seglen, axis=-1)
+
+
+def test_lower_bound_is_exact_for_piecewise_constant_single_member():
+    # For piecewise-constant series the within-segment deviations vanish, so
+    # d^2 = sum_s l_s (mu_q - mu_x)^2 and the bound is tight (up to the one-ulp
+    # widening of the stored box).
+    S, l = 4, 5
+    x = _piecewise_constant([[0.3, -1.0, 2.0, 0.5]], l)
+    q = _piecewise_constant([[1.0, 0.0, -0.5, 0.25]], l)
+    mu, sd = O.segment_stats(x, S)
+    box = O.node_box(mu, sd, np.array([0]))[None]
+    qmu, qsd = O.query_stats(q, S)
+    lb = O.lower_bound(qmu, qsd, box, S * l)[0, 0]
+    d = math.sqrt(((q.astype(np.float64) - x) ** 2).sum())
+    assert lb <= d
+    assert abs(lb - d) < 1e-5 * d
+    assert abs(d - math.sqrt(5 * (0.7 ** 2 + 1.0 + 2.5 ** 2 + 0.25 ** 2))) < 1e-6
+
+
+def test_lower_bound_hand_box():
+    # one segment of length 4 with box mu in [0, 1], sd in [2, 3]; query mu 1.5, sd 1
+    box = np.array([[[0.0, 1.0, 2.0, 3.0]]], dtype=np.float32)
+    lb = O.lower_bound(np.array([[1.5]]), np.array([[1.0]]), box, 4)
+    assert abs(lb[0, 0] - math.sqrt(4 * (0.25 + 1.0))) < 1e-12
+    lb_in = O.lower_bound(np.array([[0.5]]), np.array([[2.5]]), box, 4)
+    assert lb_in[0, 0] == 0.0
+
+
+@pytest.mark.parametrize("rule", ["median", "midpoint"])
+def test_lower_bound_never_exceeds_node_distance(rule):
+    raw = W.random_walk(3000, 64, seed=21) if rule == "median" else W.gaussian_mixture(3000, 64, 20, 0.3, 5, 6)
+    xs = O.znorm(raw)
+    mu, sd = O.segment_stats(xs, 8)
+    t = O.build_tree(mu, sd, 64, 200, rule)
+    qraw = np.concatenate([W.noisy_queries(raw, 20, 0.1, 1, 2)[0], W.random_walk(10, 64, seed=99)])
+    q = O.znorm(qraw)
+    boxes = O.leaf_boxes(mu, sd, t)
+    qmu, qsd = O.query_stats(q, 8)
+    lb = O.lower_bound(qmu, qsd, boxes, 64)
+    d, _ = O.leaf_knn(xs, t.leaves, q, 1)
+    assert np.all(lb <= d[:, :, 0] * (1 + 1e-12))
+    assert (lb > 0).mean() > 0.3          # the bound is not trivially zero
+    # parent bound <= child bound
+    def walk(node):
+        if node.left is None:
+            return
+        bp = O.lower_bound(qmu, qsd, O.node_box(mu, sd, node.members)[None], 64)
+        for ch in (node.left, node.right):
+            bc = O.lower_bound(qmu, qsd, O.node_box(mu, sd, ch.members)[None], 64)
+            assert np.all(bp <= bc + 1e-12)
+            walk(ch)
+    walk(t.root)
+
+
+def test_visit_order_ties_by_leaf_id():
+    lb = np.array([[0.5, 0.1, 0.5, 0.0, 0.1]])
+    assert list(O.visit_order(lb)[0]) == [3, 1, 4, 0, 2]
+
+
+# ---------------------------------------------------------------- MLP filter
+
+def test_mlp_identity_special_case():
+    m = h = 8
+    w = np.zeros(m * h + 2 * h + 1)
+    w[: m * h] = np.eye(m).reshape(-1)
+    w[m * h + h: m * h + 2 * h] = 1.0
+    q = np.random.default_rng(3).standard_normal((5, m)).astype(np.float32)
+    got = O.mlp_forward(w, q, m, h)
+    assert np.allclose(got, np.maximum(q.astype(np.float64), 0).sum(1), rtol=1e-15)
+
+
+def test_mlp_matches_explicit_loops_and_layout():
+    m, h = 5, 3
+    w = W.mlp_weights(1, m, h, seed=4)[0].astype(np.float64)
+    q = np.random.default_rng(5).standard_normal((4, m))
+    out = O.mlp_forward(w, q, m, h)
+    for r in range(4):
+        acc = w[m * h + 2 * h]
+        for j in range(h):
+            z = w[m * h + j]
+            for i in range(m):
+                z += w[i * h + j] * q[r, i]       # input-major W1
+            acc += w[m * h + h + j] * max(z, 0.0)
+        assert abs(acc - out[r]) < 1e-12
+
+
+def test_mlp_gradient_central_differences():
+    m = h = 4
+    w = W.mlp_weights(1, m, h, seed=8)[0].astype(np.float64)
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((6, m))
+    y = rng.uniform(1, 3, 6)
+    loss, g = O.mlp_mse_grad(w, X, y, m, h)
+    eps = 1e-6
+    for p in range(len(w)):
+        wp, wm = w.copy(), w.copy()
+        wp[p] += eps
+        wm[p] -= eps
+        fd = (O.mlp_mse_grad(wp, X, y, m, h)[0] - O.mlp_mse_grad(wm, X, y, m, h)[0]) / (2 * eps)
+        assert abs(fd - g[p]) < 1e-6 * max(1.0, abs(fd))
+    assert abs(loss - ((O.mlp_forward(w, X, m, h) - y) ** 2).mean()) < 1e-12
+
+
+# ---------------------------------------------------------------- search (Algorithm 2)
+
+@pytest.fixture(scope="module")
+def small_index():
+    raw = W.random_walk(6000, 64, seed=31)
+    xs = O.znorm(raw)
+    mu, sd = O.segment_stats(xs, 8)
+    t = O.build_tree(mu, sd, 64, 400, "median")
+    q = O.znorm(W.noisy_queries(raw, 40, (0.05, 0.3), 7, 8)[0])
+    qmu, qsd = O.query_stats(q, 8)
+    lb = O.lower_bound(qmu, qsd, O.leaf_boxes(mu, sd, t), 64)
+    order = O.visit_order(lb)
+    kmax = 5
+    ld, li = O.leaf_knn(xs, t.leaves, q, kmax)
+    return dict(xs=xs, t=t, q=q, lb=lb, order=order, ld=ld, li=li, kmax=kmax)
+
+
+@pytest.mark.parametrize("schedule", [(1,), (2,), (1, 0), (0,), (1, 3)])
+@pytest.mark.parametrize("k", [1, 5])
+def test_plain_tree_search_is_exact(small_index, schedule, k):
+    s = small_index
+    r = O.leafi_search(s["lb"], s["order"], s["ld"], s["li"], k, schedule=schedule)
+    ids, d = O.knn(s["xs"], s["q"], k)
+    assert np.array_equal(r.ids, ids)
+    assert np.allclose(r.dist, d, rtol=1e-12)
+    if schedule == (1,):
+        assert r.lb_pruned.sum() > 0      # the bound prunes something
+
+
+def test_infinite_offsets_give_exact_results(small_index):
+    s = small_index
+    N = s["lb"].shape[1]
+    has = np.ones(N, dtype=bool)
+    dF = np.full_like(s["lb"], -np.inf)   # d^f - (+inf)
+    for sched in [(1,), (1, 0)]:
+        r = O.leafi_search(s["lb"], s["order"], s["ld"], s["li"], 3, has, dF, sched)
+        ids, _ = O.knn(s["xs"], s["q"], 3)
+        assert np.array_equal(r.ids, ids)
+        assert r.f_pruned.sum() == 0
+
+
+def test_minus_infinite_offsets_prune_every_filtered_leaf_after_first_results(small_index):
+    s = small_index
+    N = s["lb"].shape[1]
+    has = np.ones(N, dtype=bool)
+    dF = np.full_like(s["lb"], np.inf)    # d^f - (-inf)
+    r = O.leafi_search(s["lb"], s["order"], s["ld"], s["li"], 1, has, dF, (1,))
+    # only the first leaf in visit order is searched; all others are pruned
+    assert np.array_equal(r.scanned.sum(1), np.ones(len(s["q"])))
+    first = s["order"][:, 0]
+    assert np.all(r.scanned[np.arange(len(first)), first])
+    assert np.all(r.lb_pruned | r.f_pruned | r.scanned)
+
+
+def test_search_strictness_hand_case():
+    # Two leaves, k = 1.  Leaf 0 (visited first) holds distances 2.0 and 5.0;
+    # leaf 1 holds 1.0.  With tau = 2.0 after leaf 0: a bound or prediction
+    # equal to tau does not prune (prune only when strictly greater).
+    lb = np.array([[0.0, 2.0]])
+    order = np.array([[0, 1]])
+    ld = np.array([[[2.0, 5.0], [1.0, np.inf]]])
+    li = np.array([[[10, 11], [20, -1]]])
+    r = O.leafi_search(lb, order, ld, li, 1)
+    assert r.ids[0, 0] == 20 and r.scanned[0, 1]
+    has = np.array([False, True])
+    r = O.leafi_search(lb, order, ld, li, 1, has, np.array([[0.0, 2.0]]))
+    assert r.ids[0, 0] == 20
+    r = O.leafi_search(lb, order, ld, li, 1, has, np.array([[0.0, 2.0000001]]))
+    assert r.ids[0, 0] == 10 and r.f_pruned[0, 1]
+    r = O.leafi_search(np.array([[0.0, 2.0000001]]), order, ld, li, 1)
+    assert r.ids[0, 0] == 10 and r.lb_pruned[0, 1]
+    # k = 3: tau stays +inf until three results are held, so nothing is pruned
+    r = O.leafi_search(np.array([[0.0, 9.0]]), order, ld, li, 3, has, np.array([[0.0, 9.0]]))
+    assert list(r.ids[0]) == [20, 10, 11]
+
+
+def test_bsf_before_bruteforce(small_index):
+    s = small_index
+    xs, q, t = s["xs"], s["q"], s["t"]
+    full = _direct(xs, q)
+    leaf_of = np.empty(len(xs), dtype=np.int64)
+    for L, mem in enumerate(t.leaves):
+        leaf_of[mem] = L
+    for k in (1, 3):
+        got = O.bsf_before(s["ld"], s["order"], k)
+        for c in range(0, len(q), 7):
+            for pos in range(len(t.leaves)):
+                L = s["order"][c, pos]
+                prev = s["order"][c, :pos]
+                pool = np.sort(full[c, np.isin(leaf_of, prev)])
+                want = pool[k - 1] if len(pool) >= k else np.inf
+                assert got[c, L] == pytest.approx(want, rel=1e-12)
+        if k == 1:
+            # prefix minimum of d^L along the visit order
+            dl = np.take_along_axis(s["ld"][:, :, 0], s["order"], axis=1)
+            pm = np.concatenate([np.full((len(q), 1), np.inf), np.minimum.accumulate(dl, axis=1)[:, :-1]], 1)
+            assert np.allclose(np.take_along_axis(got, s["order"], axis=1), pm)
+
+
+def _true_nbr_leaf(s, k):
+    ids, _ = O.knn(s["xs"], s["q"], k)
+    leaf_of = np.empty(len(s["xs"]), dtype=np.int64)
+    for L, mem in enumerate(s["t"].leaves):
+        leaf_of[mem] = L
+    return leaf_of[ids], ids
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_simulated_recall_is_conservative(small_index, k):
+    s = small_index
+    N = s["lb"].shape[1]
+    rng = np.random.default_rng(41)
+    has = rng.random(N) < 0.8
+    dfilt = s["ld"][:, :, 0] + rng.normal(0, 0.5, size=s["lb"].shape)
+    dbsf = O.bsf_before(s["ld"], s["order"], k)
+    nbr_leaf, ids = _true_nbr_leaf(s, k)
+    _, true_d = O.knn(s["xs"], s["q"], k)
+    for trial in range(6):
+        offs = np.where(has, rng.uniform(-0.5, 1.0, N), np.inf)
+        sim = O.simulated_recall(dfilt, dbsf, nbr_leaf, has, offs)
+        for sched in [(1,), (2,), (1, 0)]:
+            r = O.leafi_search(s["lb"], s["order"], s["ld"], s["li"], k, has, dfilt - offs[None], sched)
+            ret_d = np.where(r.ids >= 0, r.dist, np.inf)
+            ach = O.recall_at_k(r.ids, ret_d, true_d).mean()
+            assert ach >= sim - 1e-12
+
+
+def test_calibration_hand_example():
+    # Two filtered leaves, four calibration queries, k = 1 (values chosen by hand).
+    dL = np.array([[1.0, 3.0], [2.0, 1.5], [1.2, 2.5], [4.0, 0.5]])
+    df = np.array([[1.5, 2.0], [2.5, 2.6], [3.0, 2.0], [3.5, 1.0]])
+    order = np.array([[0, 1], [0, 1], [1, 0], [1, 0]])
+    dbsf = O.bsf_before(dL[:, :, None], order, 1)
+    assert np.array_equal(dbsf, np.array([[np.inf, 1.0], [np.inf, 2.0], [2.5, np.inf], [0.5, np.inf]]))
+    nbr_leaf = np.array([[0], [1], [0], [1]])
+    has = np.array([True, True])
+    offs, q = O.autotune_curve(df, dL, dbsf, nbr_leaf, has)
+    # alpha sorted per filter: leaf 0 -> 0.5 0.5 0.5 1.8; leaf 1 -> 0.5 0.5 1.0 1.1
+    assert np.allclose(offs[:4, 0], [0.5, 0.5, 0.5, 1.8])
+    assert np.allclose(offs[:4, 1], [0.5, 0.5, 1.0, 1.1])
+    assert np.isinf(offs[4]).all()
+    # query 1's neighbour needs o_1 >= 0.6; query 2's is kept at equality (2.5 <= 2.5)
+    assert np.allclose(q, [0.75, 0.75, 1.0, 1.0, 1.0])
+    j, o = O.step_offsets(offs, q, 0.99, 4)
+    assert j == 2 and np.allclose(o, [0.5, 1.0])
+    j, o = O.step_offsets(offs, q, 0.7, 4, corrected=False)
+    assert j == 0
+    j, _ = O.step_offsets(offs, q, 0.7, 4)          # ceil(5 * 0.7) / 4 = 1
+    assert j == 2
+    j, _ = O.step_offsets(offs, q, 0.5, 4)          # ceil(2.5) / 4 = 0.75
+    assert j == 0
+
+
+def test_conformal_target_values():
+    assert O.conformal_target(0.99, 500) == pytest.approx(0.992)
+    assert O.conformal_target(0.95, 500) == pytest.approx(0.952)
+    assert O.conformal_target(0.99, 99) == pytest.approx(1.0)
+    assert O.conformal_target(1.0, 10) == 1.0
+
+
+def test_calibration_reaches_target_on_calibration_set(small_index):
+    s = small_index
+    N = s["lb"].shape[1]
+    rng = np.random.default_rng(44)
+    has = np.ones(N, dtype=bool)
+    dfilt = s["ld"][:, :, 0] * rng.uniform(0.7, 1.4, size=s["lb"].shape)
+    dbsf = O.bsf_before(s["ld"], s["order"], 1)
+    nbr_leaf, _ = _true_nbr_leaf(s, 1)
+    _, true_d = O.knn(s["xs"], s["q"], 1)
+    offs, q = O.autotune_curve(dfilt, s["ld"][:, :, 0], dbsf, nbr_leaf, has)
+    assert np.all(np.diff(q) >= 0)                   # larger offsets never lower recall
+    for tgt in (0.8, 0.9, 0.99):
+        j, o = O.step_offsets(offs, q, tgt, len(q) - 1)
+        r = O.leafi_search(s["lb"], s["order"], s["ld"], s["li"], 1, has, dfilt - o[None], (1,))
+        ach = O.recall_at_k(r.ids, np.where(r.ids >= 0, r.dist, np.inf), true_d).mean()
+        assert ach >= O.conformal_target(tgt, len(q) - 1) - 1e-12
+
+
+# ---------------------------------------------------------------- Steffen interpolant
+
+def test_steffen_hand_case_and_linear():
+    fit = O.steffen_fit(np.array([0.0, 1.0, 2.0]), np.array([0.0, 1.0, 4.0]))
+    # slopes: y'0 = 0 (one-sided parabola slope 0), y'1 = 2, y'2 = 4 -> both cubics are t^2
+    for t in (0.0, 0.25, 0.5, 1.0, 1.5, 2.0):
+        assert O.steffen_eval(fit, t) == pytest.approx(t * t, abs=1e-12)
+    xl = np.array([0.0, 0.3, 1.0, 2.5])
+    lin = O.steffen_fit(xl, 2 * xl + 1)
+    for t in np.linspace(0, 2.5, 11):
+        assert O.steffen_eval(lin, t) == pytest.approx(2 * t + 1, abs=1e-12)
+
+
+def test_steffen_knots_and_monotone():
+    rng = np.random.default_rng(51)
+    x = np.cumsum(rng.uniform(0.01, 1.0, 12))
+    y = np.cumsum(rng.exponential(1.0, 12) * (rng.random(12) < 0.7))
+    fit = O.steffen_fit(x, y)
+    for xi, yi in zip(x, y):
+        assert O.steffen_eval(fit, xi) == pytest.approx(yi, abs=1e-10)
+    grid = np.linspace(x[0], x[-1], 2000)
+    vals = np.array([O.steffen_eval(fit, t) for t in grid])
+    assert np.all(np.diff(vals) >= -1e-12)
+    # no overshoot: values stay within each interval's endpoint range
+    for i in range(len(x) - 1):
+        seg = vals[(grid >= x[i]) & (grid <= x[i + 1])]
+        assert seg.min() >= min(y[i], y[i + 1]) - 1e-10 and seg.max() <= max(y[i], y[i + 1]) + 1e-10
+
+
+# ---------------------------------------------------------------- leaf selection (Algorithm 3)
+
+def test_select_leaves_cases():
+    sizes = np.array([5, 10, 10, 3])
+    assert list(O.select_leaves(sizes, 4, 1.0, 2.0)) == [1, 2]
+    assert list(O.select_leaves(sizes, 0, 1.0, 100.0)) == [1, 2, 0, 3]
+    assert list(O.select_leaves(sizes, 0, 1.0, 0.5)) == []
+    assert list(O.select_leaves(sizes, 10, 1.0, 100.0)) == [1, 2]
+    assert O.size_threshold(2.0, 46.0, 0.16) == pytest.approx(575.0)
+
+
+# ---------------------------------------------------------------- recall
+
+def test_recall_at_k_hand_cases():
+    true_d = np.array([[1.0, 2.0, 3.0]])
+    assert O.recall_at_k(np.array([[4, 5, 6]]), np.array([[1.0, 2.0, 3.0]]), true_d)[0] == 1.0
+    assert O.recall_at_k(np.array([[4, 5, 6]]), np.array([[1.0, 2.0, 3.5]]), true_d)[0] == pytest.approx(2 / 3)
+    assert O.recall_at_k(np.array([[4, -1, -1]]), np.array([[1.0, np.inf, np.inf]]), true_d)[0] == pytest.approx(1 / 3)
