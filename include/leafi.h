@@ -1,0 +1,293 @@
+/*
+ * leafi.h -- C ABI of the MI355X (gfx950) LeaFi search library.
+ *
+ * LeaFi (Wang, Ileana, Palpanas, SIGMOD 2025) speeds up exact tree-based
+ * data-series k-NN search by placing small learned models ("filters") in leaf
+ * nodes.  A filter predicts the node-wise nearest-neighbour distance d^L of a
+ * query; after a conformal offset is subtracted the prediction acts as an
+ * extra lower bound that prunes leaves the summaries cannot prune.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: LEAFI_OK (0) or a negative LEAFI_E* code.  The message of
+ *     the last failure on the calling thread is available from
+ *     leafi_last_error().  No C++ exception crosses this boundary.  On error
+ *     no output buffer is guaranteed to have been written.
+ *   - Pointers named *_dev are device pointers (HIP global memory on the
+ *     current device); pointers named *_host are host memory.  The caller owns
+ *     every buffer it passes; the library never frees or keeps them.  Input
+ *     buffers are only read.  The library owns the index handle and all
+ *     resident device memory it allocates (leaf store, filters, tables); it
+ *     is released by leafi_destroy().
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Kernels are
+ *     enqueued on it; calls return once their results are on the device
+ *     (they may synchronise the stream to read small control values).
+ *   - Matrices are row-major.  Series and queries are raw fp32; the library
+ *     z-normalises them itself (mean and population standard deviation in
+ *     FP64; a series whose deviation is below 1e-8 becomes all zeros).
+ *   - Distances are Euclidean distances between z-normalised series (not
+ *     squared).  Result rows are sorted by (distance, id) ascending; ids are
+ *     row indices of the series array given to leafi_build_index.
+ *   - One index handle must not be used by two threads at the same time.
+ */
+#ifndef LEAFI_H
+#define LEAFI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LEAFI_OK 0
+#define LEAFI_EINVAL (-1)   /* invalid argument (shape, range, null pointer) */
+#define LEAFI_ENOMEM (-2)   /* device or host allocation failed */
+#define LEAFI_ESTATE (-3)   /* call out of order (e.g. search before build) */
+#define LEAFI_EHIP (-4)     /* a HIP runtime call failed */
+#define LEAFI_EAGAIN (-5)   /* serving: request not admitted now, retry later */
+#define LEAFI_EINTERNAL (-6)
+
+typedef struct leafi_index leafi_index;
+
+/* ------------------------------------------------------------------------
+ * Handle management
+ * ---------------------------------------------------------------------- */
+
+/* Create an empty index handle bound to the current HIP device. */
+int leafi_create(leafi_index **out);
+
+/* Release the handle and every device allocation it owns.  NULL is a no-op. */
+void leafi_destroy(leafi_index *index);
+
+/* Message of the last failure on this thread ("" if none).  The pointer stays
+ * valid until the next failing call on the same thread. */
+const char *leafi_last_error(void);
+
+/* Library version string. */
+const char *leafi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Index building (paper: Section "Preliminaries", tree-based indexes; the
+ * DSTree backbone of Section "Evaluation Setup")
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t leaf_capacity; /* split nodes holding more series than this (>= 1) */
+  int32_t n_segments;    /* S: equal segments of the node summaries, 1..64, <= m */
+  int32_t split_rule;    /* 0 = median split, 1 = midpoint of the range */
+  int32_t reserved;
+} leafi_build_opts;
+
+/*
+ * Build the index over n raw fp32 series of length m (series_dev [n, m]).
+ * Steps: z-normalisation, per-segment mean/std summaries, a binary tree
+ * split until every leaf holds <= leaf_capacity series (a node splits on the
+ * segment statistic with the largest seg_len * range^2, at the median or the
+ * range midpoint), then a device-resident leaf store: the normalised series
+ * grouped leaf by leaf in fp32 and in a bf16 copy, with per-leaf summaries
+ * (per segment the min/max of the members' mean and std).  Any previous
+ * index, filters and calibration in the handle are discarded.
+ * Limits: 1 <= n < 2^31, 8 <= m <= 1024, m a multiple of 8.
+ */
+int leafi_build_index(leafi_index *index, const float *series_dev, int64_t n, int32_t m,
+                      const leafi_build_opts *opts, void *stream);
+
+typedef struct {
+  int64_t n_series;
+  int32_t m;
+  int32_t n_leaves;
+  int32_t n_segments;
+  int32_t n_filters;   /* 0 until filters are trained or set */
+  int32_t hidden;      /* filter hidden width h */
+  int32_t n_calibrated;/* number of calibrated (k, target) pairs */
+  int64_t padded_rows; /* rows of the leaf store including per-leaf padding */
+  int64_t device_bytes;/* resident device memory owned by the handle */
+} leafi_info;
+
+int leafi_get_info(const leafi_index *index, leafi_info *out);
+
+/* Leaf partition: leaf_offsets_host [n_leaves + 1] (prefix sums of the leaf
+ * sizes) and member_ids_host [n_series] (ids of each leaf's members, leaf by
+ * leaf, ascending within a leaf).  Leaves are numbered depth-first, left child
+ * first.  Either pointer may be NULL. */
+int leafi_export_leaves(const leafi_index *index, int64_t *leaf_offsets_host, int64_t *member_ids_host);
+
+/* Leaf summaries: boxes_host [n_leaves, n_segments, 4] = (mean lo, mean hi,
+ * std lo, std hi) per segment, widened outward by one fp32 ulp. */
+int leafi_export_boxes(const leafi_index *index, float *boxes_host);
+
+/* ------------------------------------------------------------------------
+ * Learned filters (paper: Section "The LeaFi Framework", Algorithms 1 and 3,
+ * Section "Training Data Generation", Section "Evaluation Setup")
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t n_global;      /* global training queries, incl. validation (paper: 3/4 of 2,000) */
+  int32_t n_local;       /* local training queries per filtered leaf (paper: 1/4 of 2,000) */
+  float noise_lo;        /* training noise level range: each query draws its */
+  float noise_hi;        /*   level uniformly in [noise_lo, noise_hi] */
+  float a;               /* Algorithm 3 hyperparameter a = 1 / p^F (paper: 2) */
+  float val_fraction;    /* share of the global queries held out for validation (0.2) */
+  double th_override;    /* < 0: th = a * t^F / t^S measured on this GPU; >= 0: use as th */
+  int64_t mem_budget;    /* c^M: device bytes available for filter weights */
+  int32_t hidden;        /* h; 0 = m (paper: hidden width = series length) */
+  int32_t max_epochs;    /* paper: 1,000 */
+  float lr0;             /* paper: 0.01 */
+  float lr_min;          /* paper: 1e-5 (training stops below it) */
+  int32_t batch;         /* SGD mini-batch size */
+  int32_t patience;      /* epochs without validation improvement before lr /= 10 */
+  uint64_t seed;
+} leafi_train_opts;
+
+/* Fill opts with the defaults listed above (n_global 1500, n_local 500,
+ * noise 0.1..0.4, a 2, val 0.2, th measured, budget 8 GiB, h = m, 1000
+ * epochs, lr 0.01 -> 1e-5, batch 64, patience 10, seed 1). */
+void leafi_default_train_opts(leafi_train_opts *opts);
+
+typedef struct {
+  double t_filter_s;     /* measured t^F: seconds per (query, filter) inference */
+  double t_series_s;     /* measured t^S: seconds per (query, series) distance */
+  double th;             /* size threshold used */
+  int32_t n_filters;
+  int32_t epochs_max_run;/* largest epoch count any filter ran */
+  double ms_collect;     /* training-target collection (scan) time */
+  double ms_train;       /* SGD time */
+  double mean_val_mse;   /* mean final validation MSE over filters */
+} leafi_train_report;
+
+/*
+ * Algorithm 1: select leaves (Algorithm 3), generate global and local
+ * training queries (collection series plus Gaussian noise), compute their
+ * node-wise nearest-neighbour distances d^L with the leaf scan, and train one
+ * MLP per selected leaf by SGD on the mean squared error.  `report` may be
+ * NULL.  Replaces any previous filters and clears calibration.
+ */
+int leafi_train_filters(leafi_index *index, const leafi_train_opts *opts, leafi_train_report *report,
+                        void *stream);
+
+/*
+ * Install given filters instead of training them: n_filters filters on the
+ * leaves leaf_ids_host[n_filters] (distinct), weights_dev [n_filters, P] with
+ * P = h*m + 2h + 1 packed as [W1 (input-major: element (i, j) at i*h + j) |
+ * b1 (h) | w2 (h) | b2].  A filter predicts d^f(q) = w2 . ReLU(W1 q + b1) + b2
+ * for the z-normalised query q.  Clears calibration.
+ */
+int leafi_set_filters(leafi_index *index, int32_t n_filters, int32_t hidden, const int32_t *leaf_ids_host,
+                      const float *weights_dev, void *stream);
+
+/* Copy the filters out: leaf_ids_host [n_filters] and weights_dev [n_filters, P]
+ * (same packing as leafi_set_filters).  Either pointer may be NULL. */
+int leafi_get_filters(const leafi_index *index, int32_t *leaf_ids_host, float *weights_dev, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Conformal auto-tuning (paper: Section "Filter Conformal Auto-tuning",
+ * Algorithm 4; Section "Preliminaries", conformal regression)
+ * ---------------------------------------------------------------------- */
+
+#define LEAFI_CALIB_STEP 0         /* offsets of the first sorted position reaching the target */
+#define LEAFI_CALIB_STEFFEN 1      /* Steffen monotone interpolation of offset vs. recall */
+#define LEAFI_CALIB_NO_CORRECTION 2/* flag: use the raw target, not ceil((n_c+1) t) / n_c */
+
+/*
+ * Fit the auto-tuners on n_calib raw calibration queries (calib_dev [n_calib, m]):
+ * absolute prediction errors alpha = |d^f - d^L| per filter, sorted; for each
+ * sorted position j the offsets o_i = alpha_{i,(j)} and the recall of the
+ * simulated search on the calibration set (a true neighbour in a filtered
+ * leaf is lost iff d^f - o > d^bsf, the exact best-so-far before that leaf);
+ * then, for every (k, target) pair of ks_host[n_ks] x targets_host[n_targets],
+ * the offsets whose recall reaches the target.  `flags` = LEAFI_CALIB_STEP or
+ * LEAFI_CALIB_STEFFEN, optionally | LEAFI_CALIB_NO_CORRECTION.  Targets must
+ * lie in (0, 1]; ks in [1, 256].
+ */
+int leafi_calibrate(leafi_index *index, const float *calib_dev, int32_t n_calib, const int32_t *ks_host,
+                    int32_t n_ks, const float *targets_host, int32_t n_targets, int32_t flags, void *stream);
+
+/* Offsets of calibrated pair p (pairs are ordered k-major: p = ik * n_targets
+ * + it): offsets_host [n_pairs, n_filters]; +inf disables a filter. */
+int leafi_get_offsets(const leafi_index *index, float *offsets_host);
+
+/* Install offsets directly for the given (k, target) pairs (offsets_host
+ * [n_ks * n_targets, n_filters], k-major as above).  Replaces calibration. */
+int leafi_set_offsets(leafi_index *index, const int32_t *ks_host, int32_t n_ks, const float *targets_host,
+                      int32_t n_targets, const float *offsets_host);
+
+/* ------------------------------------------------------------------------
+ * Search (paper: Algorithm 2)
+ * ---------------------------------------------------------------------- */
+
+#define LEAFI_SCAN_BF16 0   /* batched: BF16 MFMA scan, FP32 rerank + FP64 band */
+#define LEAFI_SCAN_FP32 1   /* plain: FP32 direct-difference scan, one query at a time */
+
+typedef struct {
+  int32_t k_max;           /* width of the output rows, 1..256 */
+  int32_t scan;            /* LEAFI_SCAN_BF16 or LEAFI_SCAN_FP32 */
+  int32_t use_filters;     /* 0: summaries only (exact search) */
+  int32_t n_schedule;      /* entries used in schedule[] (>= 1) */
+  int32_t schedule[8];     /* leaves searched per query per round; the last entry
+                              repeats; 0 = every leaf that survives.  {1} is the
+                              paper's sequential loop. */
+  int32_t kprime;          /* BF16 candidates kept per (query, leaf); 0 = 4k */
+  int32_t reserved[3];
+} leafi_search_opts;
+
+void leafi_default_search_opts(leafi_search_opts *opts);
+
+typedef struct {
+  int64_t leaves_scanned;
+  int64_t leaves_lb_pruned;
+  int64_t leaves_filter_pruned;
+  int64_t series_scanned;   /* real series in scanned leaves */
+  int64_t fallback_items;   /* (query, leaf) pairs re-scanned exactly in FP32 */
+  int32_t rounds;
+  int32_t reserved;
+  double ms_total;
+  double ms_scan;           /* time in the leaf-scan kernels */
+  double scan_bytes;        /* unique leaf-store bytes the scan kernels had to read */
+} leafi_search_stats;
+
+/*
+ * k-NN search for nq raw queries (queries_dev [nq, m]).  k_dev [nq] (int32,
+ * 1 <= k <= k_max) and target_dev [nq] (float) give each query's k and recall
+ * target; a query whose (k, target) pair is not calibrated, or whose target is
+ * >= 1, runs without filters (exact).  Outputs ids_dev [nq, k_max] (int64) and
+ * dists_dev [nq, k_max] (fp32); slots beyond a query's k hold id -1 and +inf.
+ * `stats` (host) may be NULL.
+ */
+int leafi_search_knn(leafi_index *index, const float *queries_dev, int64_t nq, const int32_t *k_dev,
+                     const float *target_dev, const leafi_search_opts *opts, int64_t *ids_dev,
+                     float *dists_dev, leafi_search_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Building blocks, exposed for checking and for callers that compose them
+ * ---------------------------------------------------------------------- */
+
+/* z-normalise n rows of length m: out_dev [n, m] fp32 (may alias x_dev). */
+int leafi_znorm(const float *x_dev, int64_t n, int32_t m, float *out_dev, void *stream);
+
+/* Summary lower bounds d^lb for raw queries: lb_dev [nq, n_leaves] fp32. */
+int leafi_lower_bounds(leafi_index *index, const float *queries_dev, int64_t nq, float *lb_dev, void *stream);
+
+/* Filter predictions for already z-normalised inputs x_dev [nq, m]:
+ * out_dev [nq, n_filters] = d^f (before any offset), fp32. */
+int leafi_mlp_infer(const float *weights_dev, int32_t n_filters, int32_t m, int32_t hidden, const float *x_dev,
+                    int64_t nq, float *out_dev, void *stream);
+
+/* One plain SGD step per filter on its own batch: x_dev [n_filters, batch, m],
+ * y_dev [n_filters, batch]; weights_dev [n_filters, P] is updated in place with
+ * w -= lr * grad of mean((d^f - y)^2).  loss_dev [n_filters] receives the
+ * batch loss before the step (may be NULL). */
+int leafi_mlp_sgd_step(float *weights_dev, int32_t n_filters, int32_t m, int32_t hidden, const float *x_dev,
+                       const float *y_dev, int32_t batch, float lr, float *loss_dev, void *stream);
+
+/* Node-wise k nearest neighbours of raw queries in every leaf (the scan in
+ * all-pairs mode, used for the filters' training targets): d_dev
+ * [nq, n_leaves, k] fp32 and ids_dev [nq, n_leaves, k] int64, sorted by
+ * (distance, id), empty slots -1 / +inf.  d_dev[q, L, 0] is d^L(q, L). */
+int leafi_leaf_knn(leafi_index *index, const float *queries_dev, int64_t nq, int32_t k, float *d_dev,
+                   int64_t *ids_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEAFI_H */

@@ -1,0 +1,228 @@
+"""LeaFi learned-filter leaf-scan k-NN on MI355X (gfx950).
+
+Python face of libleafi (include/leafi.h).  Tensors must be CUDA (HIP)
+tensors on the current device; the current torch stream is passed to the
+library.  Nothing here computes: every call goes to the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import LeafiError, check, load, struct_dict
+
+__all__ = ["Index", "LeafiError", "load", "znorm", "mlp_infer", "mlp_sgd_step", "version"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def version() -> str:
+    return load().leafi_version().decode()
+
+
+class Index:
+    """One index handle: leaf store, filters and calibration on the current device."""
+
+    def __init__(self):
+        lib = load()
+        h = ctypes.c_void_p()
+        check(lib.leafi_create(ctypes.byref(h)))
+        self._h = h
+        self._m = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().leafi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- build
+    def build(self, series, leaf_capacity: int, n_segments: int = 16, split_rule: str = "median"):
+        torch = _torch()
+        n, m = series.shape
+        o = _lib.BuildOpts(leaf_capacity, n_segments, {"median": 0, "midpoint": 1}[split_rule], 0)
+        check(load().leafi_build_index(self._h, _dev(series, torch.float32, "series"), n, m, ctypes.byref(o),
+                                       _stream()))
+        self._m = m
+        return self
+
+    def info(self) -> dict:
+        i = _lib.Info()
+        check(load().leafi_get_info(self._h, ctypes.byref(i)))
+        return struct_dict(i)
+
+    def leaves(self):
+        inf = self.info()
+        off = np.zeros(inf["n_leaves"] + 1, dtype=np.int64)
+        mem = np.zeros(inf["n_series"], dtype=np.int64)
+        check(load().leafi_export_leaves(self._h, off.ctypes.data_as(ctypes.c_void_p),
+                                         mem.ctypes.data_as(ctypes.c_void_p)))
+        return off, mem
+
+    def boxes(self) -> np.ndarray:
+        inf = self.info()
+        b = np.zeros((inf["n_leaves"], inf["n_segments"], 4), dtype=np.float32)
+        check(load().leafi_export_boxes(self._h, b.ctypes.data_as(ctypes.c_void_p)))
+        return b
+
+    # -------------------------------------------------------------- filters
+    def train_filters(self, **kw) -> dict:
+        o = _lib.TrainOpts()
+        load().leafi_default_train_opts(ctypes.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown training option {k}")
+            setattr(o, k, v)
+        r = _lib.TrainReport()
+        check(load().leafi_train_filters(self._h, ctypes.byref(o), ctypes.byref(r), _stream()))
+        return struct_dict(r)
+
+    def set_filters(self, leaf_ids, weights, hidden: int):
+        torch = _torch()
+        ids = np.ascontiguousarray(leaf_ids, dtype=np.int32)
+        check(load().leafi_set_filters(self._h, len(ids), hidden, ids.ctypes.data_as(ctypes.c_void_p),
+                                       _dev(weights, torch.float32, "weights"), _stream()))
+
+    def get_filters(self):
+        torch = _torch()
+        inf = self.info()
+        F, h, m = inf["n_filters"], inf["hidden"], inf["m"]
+        ids = np.zeros(F, dtype=np.int32)
+        w = torch.empty((F, h * m + 2 * h + 1), dtype=torch.float32, device="cuda")
+        check(load().leafi_get_filters(self._h, ids.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.c_void_p(w.data_ptr()) if F else None, _stream()))
+        return ids, w
+
+    # -------------------------------------------------------------- calibration
+    def calibrate(self, calib, ks, targets, mapping: str = "step", corrected: bool = True):
+        torch = _torch()
+        ks_a = np.ascontiguousarray(ks, dtype=np.int32)
+        t_a = np.ascontiguousarray(targets, dtype=np.float32)
+        flags = {"step": _lib.LEAFI_CALIB_STEP, "steffen": _lib.LEAFI_CALIB_STEFFEN}[mapping]
+        if not corrected:
+            flags |= _lib.LEAFI_CALIB_NO_CORRECTION
+        check(load().leafi_calibrate(self._h, _dev(calib, torch.float32, "calib"), calib.shape[0],
+                                     ks_a.ctypes.data_as(ctypes.c_void_p), len(ks_a),
+                                     t_a.ctypes.data_as(ctypes.c_void_p), len(t_a), flags, _stream()))
+
+    def offsets(self) -> np.ndarray:
+        inf = self.info()
+        o = np.zeros((inf["n_calibrated"], inf["n_filters"]), dtype=np.float32)
+        check(load().leafi_get_offsets(self._h, o.ctypes.data_as(ctypes.c_void_p)))
+        return o
+
+    def set_offsets(self, ks, targets, offsets):
+        ks_a = np.ascontiguousarray(ks, dtype=np.int32)
+        t_a = np.ascontiguousarray(targets, dtype=np.float32)
+        o = np.ascontiguousarray(offsets, dtype=np.float32)
+        check(load().leafi_set_offsets(self._h, ks_a.ctypes.data_as(ctypes.c_void_p), len(ks_a),
+                                       t_a.ctypes.data_as(ctypes.c_void_p), len(t_a),
+                                       o.ctypes.data_as(ctypes.c_void_p)))
+
+    # -------------------------------------------------------------- search
+    def search(self, queries, k=1, target=1.0, k_max=None, scan: str = "bf16", use_filters: bool = True,
+               schedule=(1, 0), kprime: int = 0, with_stats: bool = False, out=None):
+        torch = _torch()
+        nq = queries.shape[0]
+        dev = queries.device
+        kt = k if isinstance(k, torch.Tensor) else torch.full((nq,), int(k), dtype=torch.int32, device=dev)
+        tt = target if isinstance(target, torch.Tensor) else torch.full((nq,), float(target), dtype=torch.float32,
+                                                                         device=dev)
+        if k_max is None:
+            k_max = int(k) if not isinstance(k, torch.Tensor) else int(kt.max().item()) if nq else 1
+        o = _lib.SearchOpts()
+        load().leafi_default_search_opts(ctypes.byref(o))
+        o.k_max = k_max
+        o.scan = {"bf16": _lib.LEAFI_SCAN_BF16, "fp32": _lib.LEAFI_SCAN_FP32}[scan]
+        o.use_filters = 1 if use_filters else 0
+        o.n_schedule = len(schedule)
+        for i, s in enumerate(schedule):
+            o.schedule[i] = s
+        o.kprime = kprime
+        if out is None:
+            ids = torch.empty((nq, k_max), dtype=torch.int64, device=dev)
+            dists = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
+        else:
+            ids, dists = out
+        st = _lib.SearchStats()
+        check(load().leafi_search_knn(self._h, _dev(queries, torch.float32, "queries"), nq,
+                                      _dev(kt, torch.int32, "k"), _dev(tt, torch.float32, "target"),
+                                      ctypes.byref(o), _dev(ids, torch.int64, "ids"),
+                                      _dev(dists, torch.float32, "dists"),
+                                      ctypes.byref(st) if with_stats else None, _stream()))
+        if with_stats:
+            return ids, dists, struct_dict(st)
+        return ids, dists
+
+    def lower_bounds(self, queries):
+        torch = _torch()
+        nq = queries.shape[0]
+        lb = torch.empty((nq, self.info()["n_leaves"]), dtype=torch.float32, device=queries.device)
+        check(load().leafi_lower_bounds(self._h, _dev(queries, torch.float32, "queries"), nq,
+                                        _dev(lb, torch.float32, "lb"), _stream()))
+        return lb
+
+    def leaf_knn(self, queries, k: int):
+        torch = _torch()
+        nq = queries.shape[0]
+        N = self.info()["n_leaves"]
+        d = torch.empty((nq, N, k), dtype=torch.float32, device=queries.device)
+        ids = torch.empty((nq, N, k), dtype=torch.int64, device=queries.device)
+        check(load().leafi_leaf_knn(self._h, _dev(queries, torch.float32, "queries"), nq, k,
+                                    _dev(d, torch.float32, "d"), _dev(ids, torch.int64, "ids"), _stream()))
+        return d, ids
+
+
+def znorm(x):
+    torch = _torch()
+    out = torch.empty_like(x)
+    n, m = x.shape
+    check(load().leafi_znorm(_dev(x, torch.float32, "x"), n, m, _dev(out, torch.float32, "out"), _stream()))
+    return out
+
+
+def mlp_infer(weights, m: int, hidden: int, x):
+    torch = _torch()
+    F = weights.shape[0]
+    nq = x.shape[0]
+    out = torch.empty((nq, F), dtype=torch.float32, device=x.device)
+    check(load().leafi_mlp_infer(_dev(weights, torch.float32, "weights"), F, m, hidden,
+                                 _dev(x, torch.float32, "x"), nq, _dev(out, torch.float32, "out"), _stream()))
+    return out
+
+
+def mlp_sgd_step(weights, m: int, hidden: int, x, y, lr: float):
+    """One SGD step per filter in place; x [F, B, m], y [F, B]; returns the batch losses."""
+    torch = _torch()
+    F, B, _ = x.shape
+    loss = torch.empty((F,), dtype=torch.float32, device=x.device)
+    check(load().leafi_mlp_sgd_step(_dev(weights, torch.float32, "weights"), F, m, hidden,
+                                    _dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), B, lr,
+                                    _dev(loss, torch.float32, "loss"), _stream()))
+    return loss

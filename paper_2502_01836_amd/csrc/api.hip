@@ -1,0 +1,1098 @@
+// C ABI of libleafi and the host orchestration of its device kernels:
+// index build, filter training (Algorithms 1 and 3), auto-tuner fitting
+// (Algorithm 4) and the batched round-based search (Algorithm 2).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <random>
+#include <string>
+
+#include "index.h"
+
+using namespace leafi;
+
+leafi_index::~leafi_index() {
+  if (ws.ev0) (void)hipEventDestroy(ws.ev0);
+  if (ws.ev1) (void)hipEventDestroy(ws.ev1);
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename Fn>
+int guarded(Fn &&fn) {
+  try {
+    fn();
+    return LEAFI_OK;
+  } catch (const Error &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return LEAFI_ENOMEM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return LEAFI_EINTERNAL;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return LEAFI_EINTERNAL;
+  }
+}
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void require_built(const leafi_index *ix) {
+  if (!ix) fail(LEAFI_EINVAL, "index handle is NULL");
+  if (!ix->built) fail(LEAFI_ESTATE, "index not built (call leafi_build_index first)");
+}
+
+template <typename T>
+void h2d(T *dst, const T *src, size_t n, hipStream_t st) {
+  if (n) HIP_OK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, st));
+}
+template <typename T>
+void d2h(T *dst, const T *src, size_t n, hipStream_t st) {
+  if (n) HIP_OK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, st));
+}
+
+// ---- small kernels of the orchestration --------------------------------------
+
+__global__ void k_fill_f32(float *p, int64_t n, float v) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+// Every query searches the same leaves list[0..cnt).
+__global__ void k_fill_allpairs(int32_t *qitem_leaf, int32_t *qitem_cnt, int32_t *leaf_cnt, int64_t nq, int N,
+                                const int32_t *list, int cnt) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nq * cnt) return;
+  int64_t q = i / cnt;
+  int r = static_cast<int>(i - q * cnt);
+  qitem_leaf[q * N + r] = list[r];
+  if (r == 0) qitem_cnt[q] = cnt;
+  if (q == 0) leaf_cnt[list[r]] = static_cast<int32_t>(nq);
+}
+// Per-query explicit lists (CSR): query q searches list[off[q] .. off[q+1]).
+__global__ void k_fill_lists(int32_t *qitem_leaf, int32_t *qitem_cnt, int32_t *leaf_cnt, int64_t nq, int N,
+                             const int64_t *off, const int32_t *list) {
+  int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int c = static_cast<int>(off[q + 1] - off[q]);
+  for (int r = 0; r < c; ++r) {
+    int L = list[off[q] + r];
+    qitem_leaf[q * N + r] = L;
+    atomicAdd(leaf_cnt + L, 1);
+  }
+  qitem_cnt[q] = c;
+}
+// All-pairs mode: queue every item whose certificate does not exceed its own
+// k-th distance (each item stands alone).
+__global__ void k_item_cert(int64_t n_items, int kmax, RoundBufs b) {
+  int64_t it = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (it >= n_items) return;
+  int k = b.kq[b.item_q[it]];
+  double kth = b.item_cnt[it] >= k ? sqrt(b.item_d2[it * kmax + k - 1]) : __builtin_inf();
+  if (!(static_cast<double>(b.item_bound[it]) > kth)) {
+    unsigned long long slot = atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFallback), 1ull);
+    b.fb_q[slot] = b.item_q[it];
+    b.fb_leaf[slot] = b.item_leaf[it];
+  }
+}
+// Training examples from items: d^L of (query, filtered leaf).
+__global__ void k_items_to_examples(int64_t n_items, int kmax, RoundBufs b, const int32_t *filt_of_leaf, int n_g,
+                                    int n_gt, int n_l, int n_ex, float *ex_y) {
+  int64_t it = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (it >= n_items) return;
+  int q = b.item_q[it];
+  int f = filt_of_leaf[b.item_leaf[it]];
+  if (f < 0) return;
+  int e;
+  if (q < n_gt) e = q;
+  else if (q < n_g) e = n_gt + n_l + (q - n_gt);
+  else e = n_gt + (q - n_g - f * n_l);
+  ex_y[static_cast<int64_t>(f) * n_ex + e] = static_cast<float>(sqrt(b.item_d2[it * kmax]));
+}
+
+void fill_f32(float *p, int64_t n, float v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f32, dim3(ceil_div(n, 256)), dim3(256), 0, st, p, n, v);
+  LAUNCH_OK("fill_f32");
+}
+void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(n, 256)), dim3(256), 0, st, p, n, v);
+  LAUNCH_OK("fill_i32");
+}
+
+// ---- workspace ----------------------------------------------------------------
+
+RoundBufs views(Workspace &w) {
+  RoundBufs b;
+  b.cursor = w.cursor.get();
+  b.tau = w.tau.get();
+  b.kq = w.kq.get();
+  b.pair = w.pair.get();
+  b.res_cnt = w.res_cnt.get();
+  b.res_d2 = w.res_d2.get();
+  b.res_row = w.res_row.get();
+  b.qitem_cnt = w.qitem_cnt.get();
+  b.qitem_leaf = w.qitem_leaf.get();
+  b.qitem_idx = w.qitem_idx.get();
+  b.leaf_cnt = w.leaf_cnt.get();
+  b.leaf_fill = w.leaf_fill.get();
+  b.leaf_istart = w.leaf_istart.get();
+  b.tile_start = w.tile_start.get();
+  b.item_q = w.item_q.get();
+  b.item_leaf = w.item_leaf.get();
+  b.item_d2 = w.item_d2.get();
+  b.item_row = w.item_row.get();
+  b.item_cnt = w.item_cnt.get();
+  b.item_bound = w.item_bound.get();
+  b.fb_q = w.fb_q.get();
+  b.fb_leaf = w.fb_leaf.get();
+  b.ctl = w.ctl.get();
+  return b;
+}
+
+StoreView store_view(const leafi_index *ix) {
+  StoreView s;
+  s.x32 = ix->x32.get();
+  s.x16 = ix->x16.get();
+  s.xn16 = ix->xn16.get();
+  s.leaf_off = ix->leaf_off.get();
+  s.leaf_n = ix->leaf_n.get();
+  s.leaf_eps = ix->leaf_eps.get();
+  s.m = ix->m;
+  s.N = ix->N;
+  return s;
+}
+
+QueryView query_view(Workspace &w) {
+  QueryView q;
+  q.q32 = w.q32.get();
+  q.q16 = w.q16.get();
+  q.qn16 = w.qn16.get();
+  q.qeps = w.qeps.get();
+  return q;
+}
+
+void ensure_queries(leafi_index *ix, int64_t nq, int kmax) {
+  Workspace &w = ix->ws;
+  const int64_t m = ix->m, N = ix->N, S = ix->S;
+  const int64_t F = std::max(ix->filt.F, 1);
+  nq = std::max<int64_t>(nq, 1);
+  w.q32.reserve(nq * m);
+  w.q16.reserve(nq * m);
+  w.qn16.reserve(nq);
+  w.qeps.reserve(nq);
+  w.qstat.reserve(nq * S * 2);
+  w.lb.reserve(nq * N);
+  w.order.reserve(nq * N);
+  w.dfilt.reserve(nq * F);
+  w.tau.reserve(nq);
+  w.cursor.reserve(nq);
+  w.kq.reserve(nq);
+  w.pair.reserve(nq);
+  w.res_cnt.reserve(nq);
+  w.res_d2.reserve(nq * kmax);
+  w.res_row.reserve(nq * kmax);
+  w.qitem_cnt.reserve(nq);
+  w.qitem_leaf.reserve(nq * N);
+  w.qitem_idx.reserve(nq * N);
+  w.leaf_cnt.reserve(N);
+  w.leaf_fill.reserve(N);
+  w.leaf_istart.reserve(N + 1);
+  w.tile_start.reserve(N + 1);
+  w.ctl.reserve(kCtlCount);
+  if (w.h_ctl.size() < static_cast<size_t>(kCtlCount)) w.h_ctl.resize(kCtlCount);
+  if (!w.ev0) {
+    HIP_OK(hipEventCreate(&w.ev0));
+    HIP_OK(hipEventCreate(&w.ev1));
+  }
+}
+
+void ensure_items(leafi_index *ix, int64_t items, int kmax) {
+  Workspace &w = ix->ws;
+  if (items <= 0) return;
+  if (static_cast<int64_t>(w.item_q.size()) < items || static_cast<int64_t>(w.item_d2.size()) < items * kmax) {
+    int64_t cap = std::max<int64_t>(items, static_cast<int64_t>(w.item_q.size()) * 3 / 2);
+    w.item_q.alloc(cap);
+    w.item_leaf.alloc(cap);
+    w.item_cnt.alloc(cap);
+    w.item_bound.alloc(cap);
+    w.fb_q.alloc(cap);
+    w.fb_leaf.alloc(cap);
+    w.item_d2.alloc(cap * kmax);
+    w.item_row.alloc(cap * kmax);
+  }
+}
+
+void read_ctl(leafi_index *ix, hipStream_t st) {
+  Workspace &w = ix->ws;
+  d2h(w.h_ctl.data(), w.ctl.get(), kCtlCount, st);
+  HIP_OK(hipStreamSynchronize(st));
+}
+
+// Zero the per-round control words (items, tiles, active, fallback); the
+// statistics words keep accumulating.
+void reset_round_ctl(Workspace &w, hipStream_t st) {
+  HIP_OK(hipMemsetAsync(w.ctl.get(), 0, 4 * sizeof(int64_t), st));
+}
+
+struct Timing {
+  double scan_ms = 0.0;
+  double scan_bytes = 0.0;
+};
+
+// Prepare nq raw queries: normalised copies, lower bounds and visit order.
+void prep_queries(leafi_index *ix, const float *raw, int64_t nq, hipStream_t st) {
+  Workspace &w = ix->ws;
+  launch_qprep(raw, nq, ix->m, ix->S, w.q32.get(), w.q16.get(), w.qn16.get(), w.qeps.get(), w.qstat.get(), st);
+  launch_lb(w.qstat.get(), nq, ix->boxes.get(), ix->N, ix->S, ix->m, w.lb.get(), st);
+  launch_order(w.lb.get(), nq, ix->N, w.order.get(), st);
+}
+
+// With the round's item lists in place (qitem_leaf / qitem_cnt / leaf_cnt)
+// and the round control words zeroed: lay out items and tiles, scan, rerank.
+// Returns the number of items (0: nothing enqueued after the layout).
+int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm) {
+  Workspace &w = ix->ws;
+  int mq, cap;
+  scan_geometry(kprime, &mq, &cap);
+  (void)cap;
+  launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, views(w), st);
+  read_ctl(ix, st);
+  int64_t items = w.h_ctl[kCtlItems], tiles = w.h_ctl[kCtlTiles];
+  if (items == 0) return 0;
+  ensure_items(ix, items, kmax);
+  w.cand.reserve(static_cast<size_t>(tiles) * mq * kprime);
+  RoundBufs b = views(w);
+  StoreView s = store_view(ix);
+  QueryView q = query_view(w);
+  launch_scatter(nq, ix->N, b, st);
+  int grid_scan = static_cast<int>(std::min<int64_t>(tiles, static_cast<int64_t>(ix->num_cus) * 2));
+  if (tm) HIP_OK(hipEventRecord(w.ev0, st));
+  if (bf16) launch_scan_bf16(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
+  else launch_scan_fp32(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
+  if (tm) HIP_OK(hipEventRecord(w.ev1, st));
+  int grid_r = static_cast<int>(std::min<int64_t>(items, static_cast<int64_t>(ix->num_cus) * 16));
+  launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks, st);
+  return items;
+}
+
+void add_scan_time(leafi_index *ix, Timing *tm) {
+  if (!tm) return;
+  float ms = 0.0f;
+  HIP_OK(hipEventSynchronize(ix->ws.ev1));
+  HIP_OK(hipEventElapsedTime(&ms, ix->ws.ev0, ix->ws.ev1));
+  tm->scan_ms += ms;
+}
+
+int default_kprime(int kmax, bool bf16) {
+  int kp = bf16 ? 4 * kmax : kmax + 8;
+  kp = std::min(kp, 128);
+  kp = std::max(kp, kmax);
+  return std::min(kp, 256);
+}
+
+// Unique leaf-store bytes one scan pass reads for the given leaves.
+double leaf_bytes(const leafi_index *ix, const std::vector<int32_t> &cnt, bool bf16) {
+  double per_row = bf16 ? 2.0 * ix->m + 4.0 : 4.0 * ix->m;
+  double tot = 0.0;
+  for (int L = 0; L < ix->N; ++L)
+    if (cnt[L] > 0) tot += static_cast<double>(ix->h_leaf_off[L + 1] - ix->h_leaf_off[L]) * per_row;
+  return tot;
+}
+
+struct SearchPlan {
+  int kmax = 1;
+  bool bf16 = true;
+  bool filters = false;
+  std::vector<int> schedule{1};
+  int kprime = 4;
+};
+
+// Batched search of nq raw queries (Algorithm 2 in rounds).
+void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
+                  const SearchPlan &p, int64_t *ids, float *dists, leafi_search_stats *stats, hipStream_t st) {
+  Workspace &w = ix->ws;
+  ensure_queries(ix, nq, p.kmax);
+  prep_queries(ix, raw, nq, st);
+  const int F = ix->filt.F;
+  const bool use_f = p.filters && F > 0 && ix->cal.pairs() > 0;
+  if (use_f) launch_mlp_infer(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), nq, w.dfilt.get(), st);
+  launch_select_pairs(nq, k_dev, t_dev, use_f ? ix->cal.pairs() : 0, use_f ? ix->cal.pair_k.get() : nullptr,
+                      use_f ? ix->cal.pair_t.get() : nullptr, p.kmax, w.pair.get(), w.kq.get(), st);
+  fill_i32(w.cursor.get(), nq, 0, st);
+  fill_f32(w.tau.get(), nq, INFINITY, st);
+  fill_i32(w.res_cnt.get(), nq, 0, st);
+  HIP_OK(hipMemsetAsync(w.ctl.get(), 0, kCtlCount * sizeof(int64_t), st));
+  const int kprime = p.kprime;
+  const int kprime_fb = default_kprime(p.kmax, false);
+  Timing tm;
+  int64_t fallback = 0;
+  int rounds = 0;
+  std::vector<int32_t> hcnt(ix->N);
+  for (int r = 0;; ++r) {
+    reset_round_ctl(w, st);
+    HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, ix->N * sizeof(int32_t), st));
+    int want = p.schedule[std::min<size_t>(r, p.schedule.size() - 1)];
+    RoundBufs b = views(w);
+    launch_worklist(nq, ix->N, w.lb.get(), w.order.get(), w.dfilt.get(), std::max(F, 1),
+                    use_f ? ix->filt.filt_of_leaf.get() : nullptr, use_f ? ix->cal.offsets.get() : nullptr,
+                    ix->leaf_n.get(), want, b, st);
+    if (stats) {
+      d2h(hcnt.data(), w.leaf_cnt.get(), ix->N, st);
+    }
+    int64_t items = scan_round(ix, nq, p.bf16, kprime, p.kmax, st, stats ? &tm : nullptr);
+    if (items == 0) break;
+    ++rounds;
+    if (stats) tm.scan_bytes += leaf_bytes(ix, hcnt, p.bf16);
+    launch_query_merge(nq, ix->N, p.kmax, true, false, views(w), st);
+    read_ctl(ix, st);
+    add_scan_time(ix, stats ? &tm : nullptr);
+    int64_t active = w.h_ctl[kCtlActive];
+    int64_t n_fb = w.h_ctl[kCtlFallback];
+    if (n_fb > 0) {
+      fallback += n_fb;
+      reset_round_ctl(w, st);
+      HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, ix->N * sizeof(int32_t), st));
+      fill_i32(w.qitem_cnt.get(), nq, 0, st);
+      launch_emit_fallback(n_fb, ix->N, views(w), st);
+      if (scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr) > 0)
+        launch_query_merge(nq, ix->N, p.kmax, false, true, views(w), st);
+    }
+    if (active == 0) break;
+  }
+  launch_finalize(nq, p.kmax, ix->rowid.get(), views(w), ids, dists, st);
+  if (stats) {
+    read_ctl(ix, st);
+    stats->leaves_scanned += w.h_ctl[kCtlScanned];
+    stats->leaves_lb_pruned += w.h_ctl[kCtlLbPruned];
+    stats->leaves_filter_pruned += w.h_ctl[kCtlFPruned];
+    stats->series_scanned += w.h_ctl[kCtlSeries];
+    stats->fallback_items += fallback;
+    stats->rounds += rounds;
+    stats->ms_scan += tm.scan_ms;
+    stats->scan_bytes += tm.scan_bytes;
+  }
+}
+
+// All-pairs leaf scan: items = (query, leaf) for the lists already in place;
+// each item's exact top-k (bf16 scan, certificate, FP32 rescan of the
+// uncertified).  `consume` is called with the item count after the bf16 pass
+// and again after the rescan pass (rescanned items overwrite).
+template <typename Consume>
+void allpairs_items(leafi_index *ix, int64_t nq, int k, hipStream_t st, Consume consume, Timing *tm,
+                    int64_t *n_fallback = nullptr) {
+  Workspace &w = ix->ws;
+  const bool bf16 = ix->m <= 256;
+  int kprime = default_kprime(k, bf16);
+  int64_t items = scan_round(ix, nq, bf16, kprime, k, st, tm);
+  if (items == 0) return;
+  RoundBufs b = views(w);
+  hipLaunchKernelGGL(k_item_cert, dim3(ceil_div(items, 256)), dim3(256), 0, st, items, k, b);
+  LAUNCH_OK("item_cert");
+  consume(items);
+  read_ctl(ix, st);
+  add_scan_time(ix, tm);
+  int64_t n_fb = w.h_ctl[kCtlFallback];
+  if (n_fallback) *n_fallback = n_fb;
+  if (n_fb > 0) {
+    reset_round_ctl(w, st);
+    HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, ix->N * sizeof(int32_t), st));
+    fill_i32(w.qitem_cnt.get(), nq, 0, st);
+    launch_emit_fallback(n_fb, ix->N, views(w), st);
+    int64_t it2 = scan_round(ix, nq, false, default_kprime(k, false), k, st, nullptr);
+    if (it2 > 0) consume(it2);
+  }
+}
+
+// Lay out "every query searches every leaf" item lists.
+void lists_all_leaves(leafi_index *ix, int64_t nq, DevBuf<int32_t> &tmp, hipStream_t st) {
+  Workspace &w = ix->ws;
+  std::vector<int32_t> all(ix->N);
+  for (int L = 0; L < ix->N; ++L) all[L] = L;
+  tmp.reserve(ix->N);
+  h2d(tmp.get(), all.data(), all.size(), st);
+  reset_round_ctl(w, st);
+  HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, ix->N * sizeof(int32_t), st));
+  hipLaunchKernelGGL(k_fill_allpairs, dim3(ceil_div(nq * ix->N, 256)), dim3(256), 0, st, w.qitem_leaf.get(),
+                     w.qitem_cnt.get(), w.leaf_cnt.get(), nq, ix->N, tmp.get(), ix->N);
+  LAUNCH_OK("fill_allpairs");
+}
+
+// Per-leaf exact top-k of nq prepared queries over all leaves.  Outputs
+// (device) d [nq, N, k] float and ids [nq, N, k] int64.
+void leaf_knn_prepared(leafi_index *ix, int64_t nq, int k, float *d_out, int64_t *ids_out, hipStream_t st,
+                       Timing *tm) {
+  Workspace &w = ix->ws;
+  DevBuf<int32_t> tmp;
+  fill_i32(w.kq.get(), nq, k, st);
+  lists_all_leaves(ix, nq, tmp, st);
+  allpairs_items(ix, nq, k, st, [&](int64_t items) {
+    launch_items_to_leaf_knn(items, ix->N, k, k, ix->rowid.get(), views(w), d_out, ids_out, st);
+  }, tm);
+  HIP_OK(hipStreamSynchronize(st));
+}
+
+void check_queries(const leafi_index *ix, const float *q, int64_t nq) {
+  LEAFI_CHECK_ARG(nq >= 0, "nq must be >= 0");
+  LEAFI_CHECK_ARG(nq == 0 || q != nullptr, "queries pointer is NULL");
+  LEAFI_CHECK_ARG(nq < (int64_t(1) << 31), "too many queries in one call");
+  (void)ix;
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+
+extern "C" {
+
+const char *leafi_last_error(void) { return g_last_error.c_str(); }
+
+const char *leafi_version(void) { return "leafi-gfx950 0.1"; }
+
+int leafi_create(leafi_index **out) {
+  return guarded([&] {
+    LEAFI_CHECK_ARG(out != nullptr, "out is NULL");
+    auto *ix = new leafi_index();
+    HIP_OK(hipGetDevice(&ix->device));
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device) == hipSuccess && cus > 0)
+      ix->num_cus = cus;
+    *out = ix;
+  });
+}
+
+void leafi_destroy(leafi_index *index) { delete index; }
+
+int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m, const leafi_build_opts *opts,
+                      void *stream) {
+  return guarded([&] {
+    LEAFI_CHECK_ARG(ix != nullptr, "index is NULL");
+    LEAFI_CHECK_ARG(series != nullptr, "series is NULL");
+    LEAFI_CHECK_ARG(opts != nullptr, "opts is NULL");
+    LEAFI_CHECK_ARG(n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    LEAFI_CHECK_ARG(m >= 32 && m <= 512 && m % 32 == 0, "m must be a multiple of 32 in [32, 512]");
+    LEAFI_CHECK_ARG(opts->leaf_capacity >= 1, "leaf_capacity must be >= 1");
+    LEAFI_CHECK_ARG(opts->n_segments >= 1 && opts->n_segments <= 64 && opts->n_segments <= m,
+                    "n_segments must be in [1, min(64, m)]");
+    LEAFI_CHECK_ARG(opts->split_rule == 0 || opts->split_rule == 1, "split_rule must be 0 or 1");
+    hipStream_t st = as_stream(stream);
+    const int S = opts->n_segments;
+    // discard previous state
+    ix->built = false;
+    ix->filt = Filters();
+    ix->cal = Calibration();
+    // 1. statistics
+    DevBuf<double> mean(n), sd(n);
+    DevBuf<float> smu(static_cast<size_t>(n) * S), ssd(static_cast<size_t>(n) * S);
+    launch_series_stats(series, n, m, S, mean.get(), sd.get(), smu.get(), ssd.get(), st);
+    std::vector<float> hmu(static_cast<size_t>(n) * S), hsd(static_cast<size_t>(n) * S);
+    d2h(hmu.data(), smu.get(), hmu.size(), st);
+    d2h(hsd.data(), ssd.get(), hsd.size(), st);
+    HIP_OK(hipStreamSynchronize(st));
+    smu.release();
+    ssd.release();
+    // 2. tree
+    TreeResult tree = build_tree(hmu, hsd, n, S, m, opts->leaf_capacity, opts->split_rule);
+    const int N = static_cast<int>(tree.leaves.size());
+    LEAFI_CHECK_ARG(N <= 8192, "more than 8192 leaves; raise leaf_capacity");
+    // 3. padded leaf-contiguous layout
+    std::vector<int64_t> off(N + 1, 0), lsz(N);
+    for (int L = 0; L < N; ++L) {
+      lsz[L] = static_cast<int64_t>(tree.leaves[L].size());
+      off[L + 1] = off[L] + round_up(lsz[L], kRowAlign);
+    }
+    const int64_t rows = off[N];
+    std::vector<int64_t> src(rows, -1);
+    std::vector<int32_t> leaf_of_row(rows);
+    std::vector<int64_t> members;
+    members.reserve(n);
+    int max_chunks = 1;
+    for (int L = 0; L < N; ++L) {
+      for (int64_t r = off[L]; r < off[L + 1]; ++r) leaf_of_row[r] = L;
+      for (size_t i = 0; i < tree.leaves[L].size(); ++i) src[off[L] + i] = tree.leaves[L][i];
+      members.insert(members.end(), tree.leaves[L].begin(), tree.leaves[L].end());
+      max_chunks = std::max<int>(max_chunks, static_cast<int>(ceil_div(off[L + 1] - off[L], kChunkRows)));
+    }
+    std::vector<float> boxes = leaf_boxes(hmu, hsd, S, tree);
+    // 4. device leaf store
+    ix->x32.alloc(static_cast<size_t>(rows) * m);
+    ix->x16.alloc(static_cast<size_t>(rows) * m);
+    ix->xn16.alloc(rows);
+    ix->rowid.alloc(rows);
+    ix->leaf_off.alloc(N + 1);
+    ix->leaf_n.alloc(N);
+    ix->boxes.alloc(boxes.size());
+    ix->leaf_eps.alloc(N);
+    DevBuf<int64_t> dsrc(rows);
+    DevBuf<int32_t> dleaf(rows);
+    h2d(dsrc.get(), src.data(), rows, st);
+    h2d(dleaf.get(), leaf_of_row.data(), rows, st);
+    HIP_OK(hipMemsetAsync(ix->leaf_eps.get(), 0, N * sizeof(float), st));
+    launch_pack(series, dsrc.get(), dleaf.get(), rows, m, mean.get(), sd.get(), ix->x32.get(), ix->x16.get(),
+                ix->xn16.get(), ix->rowid.get(), ix->leaf_eps.get(), st);
+    std::vector<int32_t> ln32(N);
+    for (int L = 0; L < N; ++L) ln32[L] = static_cast<int32_t>(lsz[L]);
+    h2d(ix->leaf_off.get(), off.data(), N + 1, st);
+    h2d(ix->leaf_n.get(), ln32.data(), N, st);
+    h2d(ix->boxes.get(), boxes.data(), boxes.size(), st);
+    HIP_OK(hipStreamSynchronize(st));
+    ix->n = n;
+    ix->m = m;
+    ix->S = S;
+    ix->N = N;
+    ix->rows = rows;
+    ix->max_chunks = max_chunks;
+    ix->h_leaf_off = std::move(off);
+    ix->h_leaf_n = std::move(lsz);
+    ix->h_members = std::move(members);
+    ix->h_boxes = std::move(boxes);
+    ix->built = true;
+  });
+}
+
+int leafi_get_info(const leafi_index *ix, leafi_info *out) {
+  return guarded([&] {
+    LEAFI_CHECK_ARG(ix != nullptr && out != nullptr, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->n_series = ix->n;
+    out->m = ix->m;
+    out->n_leaves = ix->N;
+    out->n_segments = ix->S;
+    out->n_filters = ix->filt.F;
+    out->hidden = ix->filt.h;
+    out->n_calibrated = ix->cal.pairs();
+    out->padded_rows = ix->rows;
+    out->device_bytes = static_cast<int64_t>(ix->x32.bytes() + ix->x16.bytes() + ix->xn16.bytes() + ix->rowid.bytes() +
+                                             ix->leaf_off.bytes() + ix->leaf_n.bytes() + ix->boxes.bytes() +
+                                             ix->leaf_eps.bytes() + ix->filt.w.bytes() + ix->cal.offsets.bytes());
+  });
+}
+
+int leafi_export_leaves(const leafi_index *ix, int64_t *leaf_offsets, int64_t *member_ids) {
+  return guarded([&] {
+    require_built(ix);
+    if (leaf_offsets) {
+      leaf_offsets[0] = 0;
+      for (int L = 0; L < ix->N; ++L) leaf_offsets[L + 1] = leaf_offsets[L] + ix->h_leaf_n[L];
+    }
+    if (member_ids) std::memcpy(member_ids, ix->h_members.data(), ix->h_members.size() * sizeof(int64_t));
+  });
+}
+
+int leafi_export_boxes(const leafi_index *ix, float *boxes) {
+  return guarded([&] {
+    require_built(ix);
+    LEAFI_CHECK_ARG(boxes != nullptr, "boxes is NULL");
+    std::memcpy(boxes, ix->h_boxes.data(), ix->h_boxes.size() * sizeof(float));
+  });
+}
+
+void leafi_default_train_opts(leafi_train_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->n_global = 1500;
+  o->n_local = 500;
+  o->noise_lo = 0.1f;
+  o->noise_hi = 0.4f;
+  o->a = 2.0f;
+  o->val_fraction = 0.2f;
+  o->th_override = -1.0;
+  o->mem_budget = int64_t(8) << 30;
+  o->hidden = 0;
+  o->max_epochs = 1000;
+  o->lr0 = 0.01f;
+  o->lr_min = 1e-5f;
+  o->batch = 64;
+  o->patience = 10;
+  o->seed = 1;
+}
+
+static void install_filters(leafi_index *ix, int F, int h, const std::vector<int32_t> &leaves, hipStream_t st) {
+  ix->filt.F = F;
+  ix->filt.h = h;
+  ix->filt.P = static_cast<int64_t>(h) * ix->m + 2 * h + 1;
+  ix->filt.leaf_of_filter = leaves;
+  std::vector<int32_t> fol(ix->N, -1);
+  for (int f = 0; f < F; ++f) fol[leaves[f]] = f;
+  ix->filt.filt_of_leaf.alloc(ix->N);
+  h2d(ix->filt.filt_of_leaf.get(), fol.data(), ix->N, st);
+  ix->cal = Calibration();
+}
+
+int leafi_set_filters(leafi_index *ix, int32_t F, int32_t hidden, const int32_t *leaf_ids, const float *weights,
+                      void *stream) {
+  return guarded([&] {
+    require_built(ix);
+    LEAFI_CHECK_ARG(F >= 0 && F <= ix->N, "n_filters must be in [0, n_leaves]");
+    LEAFI_CHECK_ARG(F == 0 || (leaf_ids && weights), "NULL leaf ids or weights");
+    LEAFI_CHECK_ARG(hidden >= 4 && hidden <= 1024 && hidden % 4 == 0, "hidden must be a multiple of 4 in [4, 1024]");
+    std::vector<int32_t> leaves(leaf_ids, leaf_ids + F);
+    std::vector<char> seen(ix->N, 0);
+    for (int32_t L : leaves) {
+      LEAFI_CHECK_ARG(L >= 0 && L < ix->N, "leaf id out of range");
+      LEAFI_CHECK_ARG(!seen[L], "duplicate leaf id");
+      seen[L] = 1;
+    }
+    hipStream_t st = as_stream(stream);
+    install_filters(ix, F, hidden, leaves, st);
+    ix->filt.w.alloc(static_cast<size_t>(F) * ix->filt.P);
+    if (F) HIP_OK(hipMemcpyAsync(ix->filt.w.get(), weights, static_cast<size_t>(F) * ix->filt.P * sizeof(float),
+                                 hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+  });
+}
+
+int leafi_get_filters(const leafi_index *ix, int32_t *leaf_ids, float *weights, void *stream) {
+  return guarded([&] {
+    require_built(ix);
+    if (leaf_ids) std::copy(ix->filt.leaf_of_filter.begin(), ix->filt.leaf_of_filter.end(), leaf_ids);
+    if (weights && ix->filt.F) {
+      hipStream_t st = as_stream(stream);
+      HIP_OK(hipMemcpyAsync(weights, ix->filt.w.get(), ix->filt.w.bytes(), hipMemcpyDeviceToDevice, st));
+      HIP_OK(hipStreamSynchronize(st));
+    }
+  });
+}
+
+int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_report *rep, void *stream) {
+  return guarded([&] {
+    require_built(ix);
+    LEAFI_CHECK_ARG(o != nullptr, "opts is NULL");
+    LEAFI_CHECK_ARG(o->n_global >= 2 && o->n_local >= 0, "need n_global >= 2 and n_local >= 0");
+    LEAFI_CHECK_ARG(o->noise_lo >= 0 && o->noise_hi >= o->noise_lo, "bad noise range");
+    LEAFI_CHECK_ARG(o->val_fraction > 0 && o->val_fraction < 1, "val_fraction must be in (0, 1)");
+    LEAFI_CHECK_ARG(o->batch >= 1 && o->batch <= 64, "batch must be in [1, 64]");
+    LEAFI_CHECK_ARG(o->max_epochs >= 1 && o->patience >= 1, "max_epochs and patience must be >= 1");
+    LEAFI_CHECK_ARG(o->lr0 > 0 && o->lr_min > 0, "learning rates must be > 0");
+    const int h = o->hidden > 0 ? o->hidden : ix->m;
+    LEAFI_CHECK_ARG(h <= 256 && h % 4 == 0, "training supports hidden <= 256, a multiple of 4");
+    hipStream_t st = as_stream(stream);
+    Workspace &w = ix->ws;
+    const int m = ix->m, N = ix->N;
+    const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
+    leafi_train_report report;
+    std::memset(&report, 0, sizeof(report));
+    std::mt19937_64 rng(o->seed);
+
+    // ---- Algorithm 3: size threshold and greedy selection
+    double th = o->th_override;
+    if (th < 0) {
+      // t^F: amortised time of one (query, filter) inference in a batch;
+      // t^S: amortised time of one (query, series) distance in the batched
+      // scan with one query group per leaf (the search regime).
+      const int qf = 1024, ff = std::min(N, 64);
+      DevBuf<float> wp(static_cast<size_t>(ff) * P), xp(static_cast<size_t>(qf) * m), outp(static_cast<size_t>(qf) * ff);
+      fill_f32(wp.get(), wp.size(), 0.01f, st);
+      fill_f32(xp.get(), xp.size(), 0.5f, st);
+      launch_mlp_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);  // warm-up
+      hipEvent_t a, b;
+      HIP_OK(hipEventCreate(&a));
+      HIP_OK(hipEventCreate(&b));
+      HIP_OK(hipEventRecord(a, st));
+      launch_mlp_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);
+      HIP_OK(hipEventRecord(b, st));
+      HIP_OK(hipEventSynchronize(b));
+      float msf = 0;
+      HIP_OK(hipEventElapsedTime(&msf, a, b));
+      report.t_filter_s = msf * 1e-3 / (static_cast<double>(qf) * ff);
+      // scan probe: 32 training-like queries against every leaf
+      const int qs = 32;
+      std::vector<int64_t> prow(qs);
+      std::vector<float> psig(qs, 0.1f);
+      for (int j = 0; j < qs; ++j) {
+        int L = static_cast<int>(rng() % N);
+        prow[j] = ix->h_leaf_off[L] + static_cast<int64_t>(rng() % ix->h_leaf_n[L]);
+      }
+      DevBuf<int64_t> drow(qs);
+      DevBuf<float> dsig(qs), qraw(static_cast<size_t>(qs) * m);
+      h2d(drow.get(), prow.data(), qs, st);
+      h2d(dsig.get(), psig.data(), qs, st);
+      launch_make_queries(ix->x32.get(), drow.get(), dsig.get(), qs, m, o->seed ^ 0x5eed, qraw.get(), st);
+      ensure_queries(ix, qs, 1);
+      prep_queries(ix, qraw.get(), qs, st);
+      DevBuf<float> pd(static_cast<size_t>(qs) * N);
+      DevBuf<int64_t> pi(static_cast<size_t>(qs) * N);
+      Timing tmp;
+      leaf_knn_prepared(ix, qs, 1, pd.get(), pi.get(), st, &tmp);
+      report.t_series_s = tmp.scan_ms * 1e-3 / (static_cast<double>(qs) * ix->n);
+      HIP_OK(hipEventDestroy(a));
+      HIP_OK(hipEventDestroy(b));
+      th = report.t_series_s > 0 ? o->a * report.t_filter_s / report.t_series_s : 0.0;
+    }
+    report.th = th;
+    std::vector<int32_t> sel = select_leaves(ix->h_leaf_n, th, static_cast<double>(P) * 4.0,
+                                             static_cast<double>(o->mem_budget));
+    const int F = static_cast<int>(sel.size());
+    install_filters(ix, F, h, sel, st);
+    ix->filt.w.alloc(static_cast<size_t>(std::max(F, 1)) * P);
+    report.n_filters = F;
+    if (F == 0) {
+      HIP_OK(hipStreamSynchronize(st));
+      if (rep) *rep = report;
+      return;
+    }
+
+    // ---- training queries: global (train + validation) and local per filter
+    const int n_g = o->n_global, n_l = o->n_local;
+    const int n_gv = std::max(1, static_cast<int>(std::lround(o->val_fraction * n_g)));
+    const int n_gt = n_g - n_gv;
+    const int64_t nqt = n_g + static_cast<int64_t>(F) * n_l;
+    std::vector<int64_t> rows(nqt);
+    std::vector<float> sig(nqt);
+    std::uniform_real_distribution<double> unif(o->noise_lo, o->noise_hi);
+    std::vector<int64_t> cum(N + 1, 0);
+    for (int L = 0; L < N; ++L) cum[L + 1] = cum[L] + ix->h_leaf_n[L];
+    for (int j = 0; j < n_g; ++j) {  // uniform over the collection
+      int64_t u = static_cast<int64_t>(rng() % static_cast<uint64_t>(ix->n));
+      int L = static_cast<int>(std::upper_bound(cum.begin(), cum.end(), u) - cum.begin()) - 1;
+      rows[j] = ix->h_leaf_off[L] + (u - cum[L]);
+      sig[j] = static_cast<float>(unif(rng));
+    }
+    for (int f = 0; f < F; ++f) {  // uniform over the filtered leaf
+      int L = sel[f];
+      for (int j = 0; j < n_l; ++j) {
+        int64_t i = n_g + static_cast<int64_t>(f) * n_l + j;
+        rows[i] = ix->h_leaf_off[L] + static_cast<int64_t>(rng() % static_cast<uint64_t>(ix->h_leaf_n[L]));
+        sig[i] = static_cast<float>(unif(rng));
+      }
+    }
+    DevBuf<int64_t> drows(nqt);
+    DevBuf<float> dsig(nqt), qraw(static_cast<size_t>(nqt) * m);
+    h2d(drows.get(), rows.data(), nqt, st);
+    h2d(dsig.get(), sig.data(), nqt, st);
+    launch_make_queries(ix->x32.get(), drows.get(), dsig.get(), nqt, m, o->seed, qraw.get(), st);
+    ensure_queries(ix, nqt, 1);
+    prep_queries(ix, qraw.get(), nqt, st);
+    qraw.release();
+
+    // ---- targets d^L with the leaf scan: global x filtered leaves, local x own leaf
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<int64_t> loff(nqt + 1, 0);
+    std::vector<int32_t> lst;
+    lst.reserve(static_cast<size_t>(n_g) * F + static_cast<size_t>(F) * n_l);
+    for (int j = 0; j < n_g; ++j) {
+      lst.insert(lst.end(), sel.begin(), sel.end());
+      loff[j + 1] = loff[j] + F;
+    }
+    for (int f = 0; f < F; ++f)
+      for (int j = 0; j < n_l; ++j) {
+        int64_t i = n_g + static_cast<int64_t>(f) * n_l + j;
+        lst.push_back(sel[f]);
+        loff[i + 1] = loff[i] + 1;
+      }
+    DevBuf<int64_t> dloff(nqt + 1);
+    DevBuf<int32_t> dlst(lst.size());
+    h2d(dloff.get(), loff.data(), loff.size(), st);
+    h2d(dlst.get(), lst.data(), lst.size(), st);
+    fill_i32(w.kq.get(), nqt, 1, st);
+    reset_round_ctl(w, st);
+    HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, N * sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_fill_lists, dim3(ceil_div(nqt, 256)), dim3(256), 0, st, w.qitem_leaf.get(),
+                       w.qitem_cnt.get(), w.leaf_cnt.get(), nqt, N, dloff.get(), dlst.get());
+    LAUNCH_OK("fill_lists");
+    const int n_ex = n_g + n_l, n_train = n_gt + n_l;
+    DevBuf<float> ex_y(static_cast<size_t>(F) * n_ex);
+    Timing tcol;
+    allpairs_items(ix, nqt, 1, st, [&](int64_t items) {
+      hipLaunchKernelGGL(k_items_to_examples, dim3(ceil_div(items, 256)), dim3(256), 0, st, items, 1, views(w),
+                         ix->filt.filt_of_leaf.get(), n_g, n_gt, n_l, n_ex, ex_y.get());
+      LAUNCH_OK("items_to_examples");
+    }, &tcol);
+    HIP_OK(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    report.ms_collect = std::chrono::duration<double, std::milli>(t1 - t0).count();
+
+    // ---- example tables: per filter [global train | local | global validation]
+    std::vector<int32_t> exq(static_cast<size_t>(F) * n_ex);
+    for (int f = 0; f < F; ++f) {
+      int32_t *e = &exq[static_cast<size_t>(f) * n_ex];
+      for (int j = 0; j < n_gt; ++j) e[j] = j;
+      for (int j = 0; j < n_l; ++j) e[n_gt + j] = n_g + f * n_l + j;
+      for (int j = 0; j < n_gv; ++j) e[n_gt + n_l + j] = n_gt + j;
+    }
+    DevBuf<int32_t> dexq(exq.size());
+    h2d(dexq.get(), exq.data(), exq.size(), st);
+
+    // ---- initial weights: uniform +-1/sqrt(fan_in) per layer
+    std::vector<float> w0(static_cast<size_t>(F) * P);
+    for (int f = 0; f < F; ++f) {
+      std::mt19937_64 g(o->seed * 0x9e3779b97f4a7c15ull + static_cast<uint64_t>(f) + 1);
+      float a1 = 1.0f / std::sqrt(static_cast<float>(m)), a2 = 1.0f / std::sqrt(static_cast<float>(h));
+      std::uniform_real_distribution<float> u1(-a1, a1), u2(-a2, a2);
+      float *wf = &w0[static_cast<size_t>(f) * P];
+      for (int64_t i = 0; i < static_cast<int64_t>(h) * m + h; ++i) wf[i] = u1(g);
+      for (int64_t i = static_cast<int64_t>(h) * m + h; i < P; ++i) wf[i] = u2(g);
+    }
+    h2d(ix->filt.w.get(), w0.data(), w0.size(), st);
+    DevBuf<float> wbest(static_cast<size_t>(F) * P), vmse(F);
+    DevBuf<int32_t> eruns(F);
+    TrainArgs ta;
+    ta.w = ix->filt.w.get();
+    ta.w_best = wbest.get();
+    ta.xq = w.q32.get();
+    ta.ex_q = dexq.get();
+    ta.ex_y = ex_y.get();
+    ta.n_train = n_train;
+    ta.n_ex = n_ex;
+    ta.F = F;
+    ta.m = m;
+    ta.h = h;
+    ta.batch = o->batch;
+    ta.max_epochs = o->max_epochs;
+    ta.patience = o->patience;
+    ta.lr0 = o->lr0;
+    ta.lr_min = o->lr_min;
+    ta.seed = o->seed;
+    ta.val_mse = vmse.get();
+    ta.epochs_run = eruns.get();
+    auto t2 = std::chrono::steady_clock::now();
+    launch_mlp_train(ta, st);
+    std::vector<float> hv(F);
+    std::vector<int32_t> he(F);
+    d2h(hv.data(), vmse.get(), F, st);
+    d2h(he.data(), eruns.get(), F, st);
+    HIP_OK(hipStreamSynchronize(st));
+    auto t3 = std::chrono::steady_clock::now();
+    report.ms_train = std::chrono::duration<double, std::milli>(t3 - t2).count();
+    double s = 0.0;
+    for (int f = 0; f < F; ++f) {
+      s += hv[f];
+      report.epochs_max_run = std::max(report.epochs_max_run, he[f]);
+    }
+    report.mean_val_mse = s / F;
+    if (rep) *rep = report;
+  });
+}
+
+int leafi_calibrate(leafi_index *ix, const float *calib, int32_t nc, const int32_t *ks, int32_t n_ks,
+                    const float *targets, int32_t n_targets, int32_t flags, void *stream) {
+  return guarded([&] {
+    require_built(ix);
+    LEAFI_CHECK_ARG(ix->filt.F > 0, "no filters (train or set them first)");
+    LEAFI_CHECK_ARG(nc >= 1 && calib != nullptr, "need calibration queries");
+    LEAFI_CHECK_ARG(n_ks >= 1 && ks != nullptr && n_targets >= 1 && targets != nullptr, "need ks and targets");
+    int kc = 1;
+    for (int i = 0; i < n_ks; ++i) {
+      LEAFI_CHECK_ARG(ks[i] >= 1 && ks[i] <= 256, "ks must be in [1, 256]");
+      kc = std::max(kc, ks[i]);
+    }
+    for (int i = 0; i < n_targets; ++i) LEAFI_CHECK_ARG(targets[i] > 0 && targets[i] <= 1, "targets must be in (0, 1]");
+    const int mapping = flags & 1;
+    const bool corrected = (flags & LEAFI_CALIB_NO_CORRECTION) == 0;
+    hipStream_t st = as_stream(stream);
+    Workspace &w = ix->ws;
+    const int N = ix->N, F = ix->filt.F;
+    ensure_queries(ix, nc, kc);
+    prep_queries(ix, calib, nc, st);
+    launch_mlp_infer(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), nc, w.dfilt.get(), st);
+    CalibInput in;
+    in.nc = nc;
+    in.N = N;
+    in.F = F;
+    in.kmax = kc;
+    in.order.resize(static_cast<size_t>(nc) * N);
+    in.dfilt.resize(static_cast<size_t>(nc) * F);
+    in.leaf_of_filter = ix->filt.leaf_of_filter;
+    d2h(in.order.data(), w.order.get(), in.order.size(), st);
+    d2h(in.dfilt.data(), w.dfilt.get(), in.dfilt.size(), st);
+    DevBuf<float> dd(static_cast<size_t>(nc) * N * kc);
+    DevBuf<int64_t> di(static_cast<size_t>(nc) * N * kc);
+    leaf_knn_prepared(ix, nc, kc, dd.get(), di.get(), st, nullptr);
+    std::vector<float> hd(dd.size());
+    in.leaf_ids.resize(di.size());
+    d2h(hd.data(), dd.get(), hd.size(), st);
+    d2h(in.leaf_ids.data(), di.get(), in.leaf_ids.size(), st);
+    HIP_OK(hipStreamSynchronize(st));
+    in.leaf_d.assign(hd.begin(), hd.end());
+    std::vector<float> tg(targets, targets + n_targets);
+    Calibration cal;
+    cal.ks.assign(ks, ks + n_ks);
+    cal.targets = tg;
+    cal.h_offsets.assign(static_cast<size_t>(n_ks) * n_targets * F, INFINITY);
+    for (int i = 0; i < n_ks; ++i) {
+      std::vector<float> o = calibrate_k(in, ks[i], tg, mapping, corrected);
+      std::copy(o.begin(), o.end(), cal.h_offsets.begin() + static_cast<size_t>(i) * n_targets * F);
+    }
+    std::vector<int32_t> pk;
+    std::vector<float> pt;
+    for (int i = 0; i < n_ks; ++i)
+      for (int t = 0; t < n_targets; ++t) {
+        pk.push_back(ks[i]);
+        pt.push_back(tg[t]);
+      }
+    cal.offsets.alloc(cal.h_offsets.size());
+    cal.pair_k.alloc(pk.size());
+    cal.pair_t.alloc(pt.size());
+    h2d(cal.offsets.get(), cal.h_offsets.data(), cal.h_offsets.size(), st);
+    h2d(cal.pair_k.get(), pk.data(), pk.size(), st);
+    h2d(cal.pair_t.get(), pt.data(), pt.size(), st);
+    HIP_OK(hipStreamSynchronize(st));
+    ix->cal = std::move(cal);
+  });
+}
+
+int leafi_get_offsets(const leafi_index *ix, float *offsets) {
+  return guarded([&] {
+    require_built(ix);
+    LEAFI_CHECK_ARG(offsets != nullptr, "offsets is NULL");
+    std::copy(ix->cal.h_offsets.begin(), ix->cal.h_offsets.end(), offsets);
+  });
+}
+
+int leafi_set_offsets(leafi_index *ix, const int32_t *ks, int32_t n_ks, const float *targets, int32_t n_targets,
+                      const float *offsets) {
+  return guarded([&] {
+    require_built(ix);
+    LEAFI_CHECK_ARG(ix->filt.F > 0, "no filters");
+    LEAFI_CHECK_ARG(n_ks >= 1 && n_targets >= 1 && ks && targets && offsets, "bad arguments");
+    const int F = ix->filt.F;
+    Calibration cal;
+    cal.ks.assign(ks, ks + n_ks);
+    cal.targets.assign(targets, targets + n_targets);
+    cal.h_offsets.assign(offsets, offsets + static_cast<size_t>(n_ks) * n_targets * F);
+    std::vector<int32_t> pk;
+    std::vector<float> pt;
+    for (int i = 0; i < n_ks; ++i)
+      for (int t = 0; t < n_targets; ++t) {
+        pk.push_back(ks[i]);
+        pt.push_back(targets[t]);
+      }
+    cal.offsets.alloc(cal.h_offsets.size());
+    cal.pair_k.alloc(pk.size());
+    cal.pair_t.alloc(pt.size());
+    HIP_OK(hipMemcpy(cal.offsets.get(), cal.h_offsets.data(), cal.h_offsets.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(cal.pair_k.get(), pk.data(), pk.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(cal.pair_t.get(), pt.data(), pt.size() * 4, hipMemcpyHostToDevice));
+    ix->cal = std::move(cal);
+  });
+}
+
+void leafi_default_search_opts(leafi_search_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->k_max = 1;
+  o->scan = LEAFI_SCAN_BF16;
+  o->use_filters = 1;
+  o->n_schedule = 2;
+  o->schedule[0] = 1;
+  o->schedule[1] = 0;
+  o->kprime = 0;
+}
+
+int leafi_search_knn(leafi_index *ix, const float *queries, int64_t nq, const int32_t *k_dev, const float *t_dev,
+                     const leafi_search_opts *o, int64_t *ids, float *dists, leafi_search_stats *stats,
+                     void *stream) {
+  return guarded([&] {
+    require_built(ix);
+    LEAFI_CHECK_ARG(o != nullptr, "opts is NULL");
+    check_queries(ix, queries, nq);
+    LEAFI_CHECK_ARG(o->k_max >= 1 && o->k_max <= 256, "k_max must be in [1, 256]");
+    LEAFI_CHECK_ARG(o->scan == LEAFI_SCAN_BF16 || o->scan == LEAFI_SCAN_FP32, "unknown scan kind");
+    LEAFI_CHECK_ARG(o->n_schedule >= 1 && o->n_schedule <= 8, "n_schedule must be in [1, 8]");
+    for (int i = 0; i < o->n_schedule; ++i) LEAFI_CHECK_ARG(o->schedule[i] >= 0, "schedule entries must be >= 0");
+    LEAFI_CHECK_ARG(o->kprime >= 0 && o->kprime <= 256, "kprime must be in [0, 256]");
+    LEAFI_CHECK_ARG(o->scan != LEAFI_SCAN_BF16 || ix->m <= 256, "the bf16 scan supports m <= 256");
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (nq == 0) return;
+    LEAFI_CHECK_ARG(k_dev && t_dev && ids && dists, "NULL k, target or output pointer");
+    hipStream_t st = as_stream(stream);
+    SearchPlan p;
+    p.kmax = o->k_max;
+    p.bf16 = o->scan == LEAFI_SCAN_BF16;
+    p.filters = o->use_filters != 0;
+    p.schedule.assign(o->schedule, o->schedule + o->n_schedule);
+    p.kprime = o->kprime > 0 ? std::max<int>(o->kprime, p.kmax) : default_kprime(p.kmax, p.bf16);
+    auto t0 = std::chrono::steady_clock::now();
+    if (p.bf16) {
+      search_batch(ix, queries, nq, k_dev, t_dev, p, ids, dists, stats, st);
+    } else {
+      // plain form: one query at a time
+      for (int64_t q = 0; q < nq; ++q)
+        search_batch(ix, queries + q * ix->m, 1, k_dev + q, t_dev + q, p, ids + q * p.kmax, dists + q * p.kmax,
+                     stats, st);
+    }
+    if (stats) {
+      HIP_OK(hipStreamSynchronize(st));
+      stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  });
+}
+
+int leafi_znorm(const float *x, int64_t n, int32_t m, float *out, void *stream) {
+  return guarded([&] {
+    LEAFI_CHECK_ARG(n >= 0 && (n == 0 || (x && out)), "bad arguments");
+    LEAFI_CHECK_ARG(m >= 1 && m <= 1024, "m must be in [1, 1024]");
+    if (n) launch_znorm(x, n, m, out, as_stream(stream));
+  });
+}
+
+int leafi_lower_bounds(leafi_index *ix, const float *queries, int64_t nq, float *lb, void *stream) {
+  return guarded([&] {
+    require_built(ix);
+    check_queries(ix, queries, nq);
+    if (nq == 0) return;
+    LEAFI_CHECK_ARG(lb != nullptr, "lb is NULL");
+    hipStream_t st = as_stream(stream);
+    ensure_queries(ix, nq, 1);
+    prep_queries(ix, queries, nq, st);
+    HIP_OK(hipMemcpyAsync(lb, ix->ws.lb.get(), static_cast<size_t>(nq) * ix->N * sizeof(float),
+                          hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+  });
+}
+
+int leafi_mlp_infer(const float *w, int32_t F, int32_t m, int32_t h, const float *x, int64_t nq, float *out,
+                    void *stream) {
+  return guarded([&] {
+    LEAFI_CHECK_ARG(F >= 0 && nq >= 0, "bad sizes");
+    LEAFI_CHECK_ARG(m >= 1 && m <= 4096, "m must be in [1, 4096]");
+    LEAFI_CHECK_ARG(h >= 4 && h <= 1024 && h % 4 == 0, "hidden must be a multiple of 4 in [4, 1024]");
+    if (F == 0 || nq == 0) return;
+    LEAFI_CHECK_ARG(w && x && out, "NULL pointer");
+    LEAFI_CHECK_ARG(F <= 65535 && ceil_div(nq, 64) <= 65535, "grid too large; split the call");
+    launch_mlp_infer(w, F, m, h, x, nq, out, as_stream(stream));
+  });
+}
+
+int leafi_mlp_sgd_step(float *w, int32_t F, int32_t m, int32_t h, const float *x, const float *y, int32_t batch,
+                       float lr, float *loss, void *stream) {
+  return guarded([&] {
+    LEAFI_CHECK_ARG(F >= 0, "bad sizes");
+    LEAFI_CHECK_ARG(m >= 4 && m <= 512 && m % 4 == 0, "m must be a multiple of 4 in [4, 512]");
+    LEAFI_CHECK_ARG(h >= 1 && h <= 256, "hidden must be in [1, 256]");
+    LEAFI_CHECK_ARG(batch >= 1 && batch <= 64, "batch must be in [1, 64]");
+    if (F == 0) return;
+    LEAFI_CHECK_ARG(w && x && y, "NULL pointer");
+    launch_mlp_sgd_step(w, F, m, h, x, y, batch, lr, loss, as_stream(stream));
+  });
+}
+
+int leafi_leaf_knn(leafi_index *ix, const float *queries, int64_t nq, int32_t k, float *d, int64_t *ids,
+                   void *stream) {
+  return guarded([&] {
+    require_built(ix);
+    check_queries(ix, queries, nq);
+    LEAFI_CHECK_ARG(k >= 1 && k <= 256, "k must be in [1, 256]");
+    if (nq == 0) return;
+    LEAFI_CHECK_ARG(d && ids, "NULL output");
+    hipStream_t st = as_stream(stream);
+    ensure_queries(ix, nq, k);
+    prep_queries(ix, queries, nq, st);
+    leaf_knn_prepared(ix, nq, k, d, ids, st, nullptr);
+  });
+}
+
+}  // extern "C"

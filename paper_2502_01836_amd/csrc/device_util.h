@@ -1,0 +1,118 @@
+// Device-side helpers for the gfx950 kernels (64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace leafi {
+
+constexpr int kWave = 64;
+constexpr uint64_t kKeyMax = ~0ull;
+
+__device__ __forceinline__ uint32_t f2u(float f) { return __float_as_uint(f); }
+__device__ __forceinline__ float u2f(uint32_t u) { return __uint_as_float(u); }
+
+// fp32 -> bf16 bits, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = f2u(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return u2f(static_cast<uint32_t>(b) << 16); }
+
+// Sort key of a non-negative squared distance and a row: orders by
+// (distance, row) as an unsigned integer.
+__device__ __forceinline__ uint64_t make_key(float d2, uint32_t row) {
+  return (static_cast<uint64_t>(f2u(d2)) << 32) | row;
+}
+__device__ __forceinline__ float key_d2(uint64_t k) { return u2f(static_cast<uint32_t>(k >> 32)); }
+__device__ __forceinline__ uint32_t key_row(uint64_t k) { return static_cast<uint32_t>(k); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, kWave);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// Orders LDS traffic of one wavefront between stages of a cooperative
+// algorithm (lanes read what other lanes wrote in the previous stage).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__host__ __device__ __forceinline__ int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Bitonic sort of P (power of two) 64-bit keys in LDS by one wavefront, ascending.
+__device__ inline void wave_sort_u64(volatile uint64_t *a, int P, int lane) {
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = lane; i < (P >> 1); i += kWave) {
+        int lo = 2 * i - (i & (stride - 1));
+        int hi = lo + stride;
+        bool up = (lo & size) == 0;
+        uint64_t x = a[lo], y = a[hi];
+        if ((x > y) == up) {
+          a[lo] = y;
+          a[hi] = x;
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
+// Bitonic sort of P (power of two) (double, uint32) pairs, ascending by
+// (value, tag), by one wavefront.
+__device__ inline void wave_sort_dbl_tag(volatile double *v, volatile uint32_t *t, int P, int lane) {
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = lane; i < (P >> 1); i += kWave) {
+        int lo = 2 * i - (i & (stride - 1));
+        int hi = lo + stride;
+        bool up = (lo & size) == 0;
+        double x = v[lo], y = v[hi];
+        uint32_t tx = t[lo], ty = t[hi];
+        bool gt = (x > y) || (x == y && tx > ty);
+        if (gt == up) {
+          v[lo] = y;
+          v[hi] = x;
+          t[lo] = ty;
+          t[hi] = tx;
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
+// Counter-based generator: SplitMix64 finaliser of a mixed counter.
+__device__ __host__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+__device__ __host__ __forceinline__ double u01(uint64_t z) {  // (0, 1)
+  return (static_cast<double>(z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace leafi

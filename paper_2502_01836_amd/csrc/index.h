@@ -1,0 +1,121 @@
+// Host-side state of an index handle and the host algorithms (tree build,
+// leaf selection, calibration) of libleafi.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace leafi {
+
+// ---- tree (tree.cpp) ------------------------------------------------------
+
+struct TreeResult {
+  std::vector<std::vector<int64_t>> leaves;  // member ids per leaf (ascending), depth-first order
+};
+
+// Split until every leaf holds <= capacity series.  seg_mu / seg_sd are
+// [n, S] fp32 summaries; rule 0 = median, 1 = range midpoint.
+TreeResult build_tree(const std::vector<float> &seg_mu, const std::vector<float> &seg_sd, int64_t n, int S, int m,
+                      int capacity, int rule);
+
+// Per-leaf boxes [N, S, 4] (mu lo, mu hi, sd lo, sd hi), widened by one fp32 ulp.
+std::vector<float> leaf_boxes(const std::vector<float> &seg_mu, const std::vector<float> &seg_sd, int S,
+                              const TreeResult &t);
+
+// ---- leaf selection (select.cpp) ---------------------------------------------
+
+// Algorithm 3: leaves by size (largest first, ties by id) with size >= th
+// while the filters fit in cM bytes.
+std::vector<int32_t> select_leaves(const std::vector<int64_t> &sizes, double th, double w, double cM);
+
+// ---- calibration (calib.cpp) ---------------------------------------------------
+
+struct CalibInput {
+  int nc = 0;        // calibration queries
+  int N = 0;         // leaves
+  int F = 0;         // filters
+  int kmax = 0;      // entries per (query, leaf) list
+  std::vector<int32_t> order;       // [nc, N] visit order
+  std::vector<double> leaf_d;       // [nc, N, kmax] per-leaf sorted distances (+inf padding)
+  std::vector<int64_t> leaf_ids;    // [nc, N, kmax] ids (-1 padding)
+  std::vector<float> dfilt;         // [nc, F] filter predictions
+  std::vector<int32_t> leaf_of_filter;  // [F]
+};
+
+// Algorithm 4 for one k: offsets [n_targets, F] for the given targets.
+// mapping 0 = step, 1 = Steffen; corrected = finite-sample target correction.
+std::vector<float> calibrate_k(const CalibInput &in, int k, const std::vector<float> &targets, int mapping,
+                               bool corrected);
+
+// Steffen (1990) monotone interpolant evaluation through (x, y) (x strictly
+// increasing), clamped to the end values outside [x0, xn].
+double steffen_eval(const std::vector<double> &x, const std::vector<double> &y, double t);
+
+// ---- index handle -----------------------------------------------------------------
+
+struct Filters {
+  int F = 0;
+  int h = 0;
+  int64_t P = 0;                       // floats per filter
+  DevBuf<float> w;                     // [F, P]
+  std::vector<int32_t> leaf_of_filter; // [F]
+  DevBuf<int32_t> filt_of_leaf;        // [N], -1 = no filter
+};
+
+struct Calibration {
+  std::vector<int32_t> ks;
+  std::vector<float> targets;
+  std::vector<float> h_offsets;   // [pairs, F]
+  DevBuf<float> offsets;          // [pairs, F]
+  DevBuf<int32_t> pair_k;         // [pairs]
+  DevBuf<float> pair_t;           // [pairs]
+  int pairs() const { return static_cast<int>(ks.size() * targets.size()); }
+};
+
+// Scratch buffers of one search / all-pairs pass, grown on demand.
+struct Workspace {
+  // queries
+  DevBuf<float> q32, qn16, qeps, qstat, lb, dfilt, tau;
+  DevBuf<uint16_t> q16;
+  DevBuf<int32_t> order, cursor, kq, pair, res_cnt, res_row, qitem_cnt, qitem_leaf, qitem_idx;
+  DevBuf<double> res_d2;
+  // leaves
+  DevBuf<int32_t> leaf_cnt, leaf_fill, leaf_istart, tile_start;
+  // items
+  DevBuf<int32_t> item_q, item_leaf, item_row, item_cnt, fb_q, fb_leaf;
+  DevBuf<double> item_d2;
+  DevBuf<float> item_bound;
+  DevBuf<uint64_t> cand;
+  DevBuf<int64_t> ctl;
+  std::vector<int64_t> h_ctl;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+}  // namespace leafi
+
+struct leafi_index {
+  int device = 0;
+  bool built = false;
+  int64_t n = 0;
+  int m = 0;
+  int S = 0;
+  int N = 0;
+  int64_t rows = 0;     // padded rows
+  int max_chunks = 1;   // chunks of the largest leaf
+  // leaf store (device)
+  leafi::DevBuf<float> x32, xn16, boxes, leaf_eps;
+  leafi::DevBuf<uint16_t> x16;
+  leafi::DevBuf<int64_t> rowid, leaf_off;
+  leafi::DevBuf<int32_t> leaf_n;
+  // host copies
+  std::vector<int64_t> h_leaf_off, h_leaf_n, h_members;
+  std::vector<float> h_boxes;
+  leafi::Filters filt;
+  leafi::Calibration cal;
+  leafi::Workspace ws;
+  int num_cus = 256;
+  ~leafi_index();
+};

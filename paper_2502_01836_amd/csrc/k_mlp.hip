@@ -1,0 +1,355 @@
+// Learned-filter kernels: batched MLP inference d^f = w2 . ReLU(W1 q + b1) + b2
+// for every (query, filter) pair, and plain SGD training of every filter
+// (one work-group per filter, the whole epoch loop on the device).
+//
+// Packed filter layout (P = h*m + 2h + 1 floats): W1 input-major (element
+// (i, j) = input i, hidden unit j at i*h + j), b1 [h], w2 [h], b2.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace leafi {
+
+namespace {
+
+// Inference tile: 64 queries x 256 hidden units per work-group; a thread owns
+// 4 consecutive hidden units for 16 queries (64 FP32 accumulators).  The
+// query tile is staged in LDS, transposed, 64 inputs at a time.
+__global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, int F, int m, int h,
+                                                   const float *__restrict__ x, int64_t nq, float *out) {
+  __shared__ float xs[64][64 + 4];
+  const int f = blockIdx.x;
+  const int64_t q0 = static_cast<int64_t>(blockIdx.y) * 64;
+  const int tid = threadIdx.x;
+  const int jg = tid & 63, qg = tid >> 6;
+  const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
+  const float *W1 = w + f * P;
+  const float *b1 = W1 + static_cast<int64_t>(h) * m;
+  const float *w2 = b1 + h;
+  const float b2 = w2[h];
+  float part[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) part[v] = 0.0f;
+  for (int jb = 0; jb < h; jb += 256) {
+    const int j0 = jb + 4 * jg;
+    const bool jok = j0 < h;
+    float acc[4][16];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[u][v] = 0.0f;
+    for (int ib = 0; ib < m; ib += 64) {
+      __syncthreads();
+      for (int e = tid; e < 64 * 64; e += 256) {
+        int qq = e >> 6, i = e & 63;
+        float v = 0.0f;
+        if (q0 + qq < nq && ib + i < m) v = x[(q0 + qq) * m + ib + i];
+        xs[i][qq] = v;
+      }
+      __syncthreads();
+      if (jok) {
+        const int ilim = m - ib < 64 ? m - ib : 64;
+        for (int i = 0; i < ilim; ++i) {
+          // a filter's packed stride is odd, so these four stay scalar loads
+          const float *wr = W1 + static_cast<int64_t>(ib + i) * h + j0;
+          float wu[4] = {wr[0], wr[1], wr[2], wr[3]};
+#pragma unroll
+          for (int v4 = 0; v4 < 4; ++v4) {
+            float4 xv = *reinterpret_cast<const float4 *>(&xs[i][16 * qg + 4 * v4]);
+            float xq[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) acc[u][4 * v4 + c] = fmaf(wu[u], xq[c], acc[u][4 * v4 + c]);
+          }
+        }
+      }
+    }
+    if (jok) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        float bb = b1[j0 + u], ww = w2[j0 + u];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) part[v] = fmaf(ww, fmaxf(acc[u][v] + bb, 0.0f), part[v]);
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) part[v] = wave_sum(part[v]);
+  if (jg == 0) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      int64_t q = q0 + 16 * qg + v;
+      if (q < nq) out[q * F + f] = part[v] + b2;
+    }
+  }
+}
+
+constexpr int kTB = 64;  // training mini-batch capacity (columns of the LDS batch)
+
+struct StepLds {
+  float *xb;    // [m][kTB] batch, transposed
+  float *red;   // [4][kTB] per-wave partial sums
+  float *yh;    // [kTB] predictions
+  float *gy;    // [kTB] dLoss/dyhat
+  float *yt;    // [kTB] targets
+};
+
+// Forward pass of one batch (columns 0..nb-1 of the LDS batch): z for hidden
+// unit j = threadIdx.x, predictions into s.yh.  Returns nothing; z stays in
+// the caller's registers.
+__device__ inline void batch_forward(const float *W1, const float *b1, const float *w2, float b2, int m, int h,
+                                     int nb, const StepLds &s, float (&z)[kTB]) {
+  const int j = threadIdx.x;
+  const int lane = j & (kWave - 1), wv = j / kWave;
+#pragma unroll
+  for (int c = 0; c < kTB; ++c) z[c] = 0.0f;
+  if (j < h) {
+    float bj = b1[j];
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) z[c] = bj;
+    for (int i = 0; i < m; ++i) {
+      float wij = W1[static_cast<int64_t>(i) * h + j];
+      const float4 *xr = reinterpret_cast<const float4 *>(s.xb + i * kTB);
+#pragma unroll
+      for (int c4 = 0; c4 < kTB / 4; ++c4) {
+        float4 xv = xr[c4];
+        z[4 * c4 + 0] = fmaf(wij, xv.x, z[4 * c4 + 0]);
+        z[4 * c4 + 1] = fmaf(wij, xv.y, z[4 * c4 + 1]);
+        z[4 * c4 + 2] = fmaf(wij, xv.z, z[4 * c4 + 2]);
+        z[4 * c4 + 3] = fmaf(wij, xv.w, z[4 * c4 + 3]);
+      }
+    }
+  }
+  float w2j = j < h ? w2[j] : 0.0f;
+#pragma unroll
+  for (int c = 0; c < kTB; ++c) {
+    float p = wave_sum(w2j * fmaxf(z[c], 0.0f));
+    if (lane == 0) s.red[wv * kTB + c] = p;
+  }
+  __syncthreads();
+  if (j < kTB) {
+    float acc = b2;
+    for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) acc += s.red[w * kTB + j];
+    s.yh[j] = j < nb ? acc : 0.0f;
+  }
+  __syncthreads();
+}
+
+// Gradient step on the batch whose forward pass left z in registers and
+// predictions in s.yh; targets in s.yt.  Returns the batch loss (thread 0).
+__device__ inline float batch_sgd(float *W1, float *b1, float *w2, float *b2p, int m, int h, int nb, float lr,
+                                  const StepLds &s, const float (&z)[kTB]) {
+  const int j = threadIdx.x;
+  if (j < kTB) s.gy[j] = j < nb ? 2.0f * (s.yh[j] - s.yt[j]) / nb : 0.0f;
+  __syncthreads();
+  float loss = 0.0f;
+  if (j == 0) {
+    float gs = 0.0f;
+    for (int c = 0; c < nb; ++c) {
+      float r = s.yh[c] - s.yt[c];
+      loss += r * r;
+      gs += s.gy[c];
+    }
+    loss /= nb;
+    *b2p -= lr * gs;
+  }
+  if (j < h) {
+    float w2j = w2[j];
+    float gw2 = 0.0f, gb1 = 0.0f;
+    float delta[kTB];
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) {
+      float g = s.gy[c];
+      gw2 = fmaf(g, fmaxf(z[c], 0.0f), gw2);
+      delta[c] = z[c] > 0.0f ? g * w2j : 0.0f;
+      gb1 += delta[c];
+    }
+    for (int i = 0; i < m; ++i) {
+      const float4 *xr = reinterpret_cast<const float4 *>(s.xb + i * kTB);
+      float gw = 0.0f;
+#pragma unroll
+      for (int c4 = 0; c4 < kTB / 4; ++c4) {
+        float4 xv = xr[c4];
+        gw = fmaf(delta[4 * c4 + 0], xv.x, gw);
+        gw = fmaf(delta[4 * c4 + 1], xv.y, gw);
+        gw = fmaf(delta[4 * c4 + 2], xv.z, gw);
+        gw = fmaf(delta[4 * c4 + 3], xv.w, gw);
+      }
+      W1[static_cast<int64_t>(i) * h + j] -= lr * gw;
+    }
+    w2[j] = w2j - lr * gw2;
+    b1[j] -= lr * gb1;
+  }
+  __syncthreads();
+  return loss;
+}
+
+__device__ inline StepLds carve(float *base, int m) {
+  StepLds s;
+  s.xb = base;
+  s.red = s.xb + m * kTB;
+  s.yh = s.red + 4 * kTB;
+  s.gy = s.yh + kTB;
+  s.yt = s.gy + kTB;
+  return s;
+}
+
+// Load examples ex[0..nb) (query indices into xq) into the LDS batch.
+__device__ inline void load_batch(const float *xq, int m, const int32_t *qidx, const float *y, int nb,
+                                  const StepLds &s) {
+  for (int e = threadIdx.x; e < kTB * m; e += blockDim.x) {
+    int c = e / m, i = e - (e / m) * m;
+    s.xb[i * kTB + c] = c < nb ? xq[static_cast<int64_t>(qidx[c]) * m + i] : 0.0f;
+  }
+  for (int c = threadIdx.x; c < kTB; c += blockDim.x) s.yt[c] = c < nb ? y[c] : 0.0f;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_mlp_sgd_step(float *w, int F, int m, int h, const float *x, const float *y,
+                                                      int batch, float lr, float *loss_out) {
+  extern __shared__ float lds[];
+  StepLds s = carve(lds, m);
+  const int f = blockIdx.x;
+  const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
+  float *W1 = w + f * P;
+  float *b1 = W1 + static_cast<int64_t>(h) * m;
+  float *w2 = b1 + h;
+  for (int e = threadIdx.x; e < kTB * m; e += blockDim.x) {
+    int c = e / m, i = e - (e / m) * m;
+    s.xb[i * kTB + c] = c < batch ? x[(static_cast<int64_t>(f) * batch + c) * m + i] : 0.0f;
+  }
+  for (int c = threadIdx.x; c < kTB; c += blockDim.x) s.yt[c] = c < batch ? y[static_cast<int64_t>(f) * batch + c] : 0.0f;
+  __syncthreads();
+  float z[kTB];
+  batch_forward(W1, b1, w2, w2[h], m, h, batch, s, z);
+  float loss = batch_sgd(W1, b1, w2, w2 + h, m, h, batch, lr, s, z);
+  if (threadIdx.x == 0 && loss_out) loss_out[f] = loss;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_train(TrainArgs a) {
+  extern __shared__ float lds[];
+  StepLds s = carve(lds, a.m);
+  int32_t *perm = reinterpret_cast<int32_t *>(s.yt + kTB);
+  int32_t *bq = perm + a.n_train;   // [kTB] query indices of the current batch
+  float *by = reinterpret_cast<float *>(bq + kTB);  // [kTB]
+  __shared__ float vsum;
+  __shared__ int stop;
+  __shared__ float b2s;  // output bias, kept in LDS while training
+  const int f = blockIdx.x;
+  const int m = a.m, h = a.h;
+  const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
+  float *W1 = a.w + f * P;
+  float *b1 = W1 + static_cast<int64_t>(h) * m;
+  float *w2 = b1 + h;
+  float *b2 = w2 + h;
+  float *wb = a.w_best + f * P;
+  const int32_t *exq = a.ex_q + static_cast<int64_t>(f) * a.n_ex;
+  const float *exy = a.ex_y + static_cast<int64_t>(f) * a.n_ex;
+  const int n_val = a.n_ex - a.n_train;
+  // output bias starts at the mean training target
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int e = 0; e < a.n_train; ++e) acc += exy[e];
+    b2s = static_cast<float>(acc / (a.n_train > 0 ? a.n_train : 1));
+    wb[P - 1] = b2s;
+  }
+  for (int e = threadIdx.x; e < a.n_train; e += blockDim.x) perm[e] = e;
+  for (int64_t e = threadIdx.x; e < P - 1; e += blockDim.x) wb[e] = W1[e];
+  __syncthreads();
+  float best = __builtin_inff();
+  float lr = a.lr0;
+  int bad = 0, epoch = 0;
+  float z[kTB];
+  for (; epoch < a.max_epochs; ++epoch) {
+    if (threadIdx.x == 0) {  // Fisher-Yates shuffle with a counter-based generator
+      for (int e = a.n_train - 1; e > 0; --e) {
+        uint64_t r = mix64(a.seed ^ mix64((static_cast<uint64_t>(f) << 40) ^ (static_cast<uint64_t>(epoch) << 20) ^ e));
+        int o = static_cast<int>(r % static_cast<uint64_t>(e + 1));
+        int tmp = perm[e];
+        perm[e] = perm[o];
+        perm[o] = tmp;
+      }
+    }
+    __syncthreads();
+    for (int s0 = 0; s0 < a.n_train; s0 += a.batch) {
+      int nb = a.n_train - s0 < a.batch ? a.n_train - s0 : a.batch;
+      for (int c = threadIdx.x; c < nb; c += blockDim.x) {
+        bq[c] = exq[perm[s0 + c]];
+        by[c] = exy[perm[s0 + c]];
+      }
+      __syncthreads();
+      load_batch(a.xq, m, bq, by, nb, s);
+      batch_forward(W1, b1, w2, b2s, m, h, nb, s, z);
+      batch_sgd(W1, b1, w2, &b2s, m, h, nb, lr, s, z);
+    }
+    // validation error
+    if (threadIdx.x == 0) vsum = 0.0f;
+    __syncthreads();
+    for (int s0 = 0; s0 < n_val; s0 += kTB) {
+      int nb = n_val - s0 < kTB ? n_val - s0 : kTB;
+      load_batch(a.xq, m, exq + a.n_train + s0, exy + a.n_train + s0, nb, s);
+      batch_forward(W1, b1, w2, b2s, m, h, nb, s, z);
+      if (threadIdx.x == 0)
+        for (int c = 0; c < nb; ++c) {
+          float r = s.yh[c] - s.yt[c];
+          vsum += r * r;
+        }
+      __syncthreads();
+    }
+    float vm = n_val > 0 ? vsum / n_val : 0.0f;
+    bool improved = vm < best * (1.0f - 1e-4f);
+    if (improved) {
+      best = vm;
+      bad = 0;
+      for (int64_t e = threadIdx.x; e < P - 1; e += blockDim.x) wb[e] = W1[e];
+      if (threadIdx.x == 0) wb[P - 1] = b2s;
+    } else if (++bad >= a.patience) {
+      lr *= 0.1f;
+      bad = 0;
+    }
+    if (threadIdx.x == 0) stop = (lr < a.lr_min * (1.0f - 1e-3f)) || !(vm == vm);
+    __syncthreads();
+    if (stop) {
+      ++epoch;
+      break;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < P - 1; e += blockDim.x) W1[e] = wb[e];
+  if (threadIdx.x == 0) {
+    *b2 = wb[P - 1];
+    a.val_mse[f] = best;
+    a.epochs_run[f] = epoch;
+  }
+}
+
+}  // namespace
+
+void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, hipStream_t st) {
+  if (nq <= 0 || F <= 0) return;
+  dim3 grid(F, static_cast<unsigned>(ceil_div(nq, 64)));
+  hipLaunchKernelGGL(k_mlp_infer, grid, dim3(256), 0, st, w, F, m, h, x, nq, out);
+  LAUNCH_OK("mlp_infer");
+}
+
+static size_t step_lds(int m) { return static_cast<size_t>(m) * kTB * 4 + (4 + 3) * kTB * 4; }
+
+void launch_mlp_sgd_step(float *w, int F, int m, int h, const float *x, const float *y, int batch, float lr,
+                         float *loss, hipStream_t st) {
+  size_t lds = step_lds(m);
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_sgd_step),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(k_mlp_sgd_step, dim3(F), dim3(256), lds, st, w, F, m, h, x, y, batch, lr, loss);
+  LAUNCH_OK("mlp_sgd_step");
+}
+
+void launch_mlp_train(const TrainArgs &a, hipStream_t st) {
+  size_t lds = step_lds(a.m) + static_cast<size_t>(a.n_train) * 4 + kTB * 8;
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_train),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(k_mlp_train, dim3(a.F), dim3(256), lds, st, a);
+  LAUNCH_OK("mlp_train");
+}
+
+}  // namespace leafi

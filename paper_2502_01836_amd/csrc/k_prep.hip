@@ -1,0 +1,283 @@
+// Ingest and query-preparation kernels: z-normalisation with FP64 statistics,
+// segment summaries, the leaf-store pack, summary lower bounds and visit order.
+//
+// Layouts: series/queries are row-major [rows, m]; one wavefront handles one
+// row (lanes stride over t), four rows per 256-thread work-group.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace leafi {
+
+namespace {
+
+constexpr int kRowsPerBlock = 4;  // wavefronts (rows) per work-group
+constexpr int kMaxM = 1024;
+
+// FP64 mean and population std of one row (wave-cooperative).
+__device__ inline void row_moments(const float *r, int m, int lane, double &mu, double &sd) {
+  double s = 0.0;
+  for (int t = lane; t < m; t += kWave) s += static_cast<double>(r[t]);
+  s = wave_sum(s);
+  mu = s / m;
+  double v = 0.0;
+  for (int t = lane; t < m; t += kWave) {
+    double d = static_cast<double>(r[t]) - mu;
+    v += d * d;
+  }
+  v = wave_sum(v);
+  sd = sqrt(v / m);
+}
+
+__device__ __forceinline__ float normalise(float x, double mu, double sd) {
+  return sd < 1e-8 ? 0.0f : static_cast<float>((static_cast<double>(x) - mu) / sd);
+}
+
+// Per-segment mean and population std of the normalised values held in
+// LDS (seg s covers [floor(s m / S), floor((s+1) m / S))), lane s does segment s.
+__device__ inline void segment_moments(const float *z, int m, int S, int s, float &smu, float &ssd) {
+  int a = (s * m) / S, b = ((s + 1) * m) / S;
+  double acc = 0.0;
+  for (int t = a; t < b; ++t) acc += static_cast<double>(z[t]);
+  double mu = acc / (b - a);
+  double v = 0.0;
+  for (int t = a; t < b; ++t) {
+    double d = static_cast<double>(z[t]) - mu;
+    v += d * d;
+  }
+  smu = static_cast<float>(mu);
+  ssd = static_cast<float>(sqrt(v / (b - a)));
+}
+
+__global__ void __launch_bounds__(256) k_series_stats(const float *__restrict__ raw, int64_t n, int m, int S,
+                                                      double *mean, double *sdv, float *seg_mu, float *seg_sd) {
+  __shared__ float zs[kRowsPerBlock][kMaxM];
+  int lane = threadIdx.x & (kWave - 1);
+  int w = threadIdx.x / kWave;
+  int64_t row = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + w;
+  if (row >= n) return;  // whole wavefront leaves together (no block barrier below)
+  const float *r = raw + row * m;
+  double mu, sd;
+  row_moments(r, m, lane, mu, sd);
+  for (int t = lane; t < m; t += kWave) zs[w][t] = normalise(r[t], mu, sd);
+  wave_lds_sync();
+  if (lane == 0) {
+    mean[row] = mu;
+    sdv[row] = sd;
+  }
+  for (int s = lane; s < S; s += kWave) {
+    float a, b;
+    segment_moments(zs[w], m, S, s, a, b);
+    seg_mu[row * S + s] = a;
+    seg_sd[row * S + s] = b;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_pack(const float *__restrict__ raw, const int64_t *__restrict__ src_of_row,
+                                              const int32_t *__restrict__ leaf_of_row, int64_t rows, int m,
+                                              const double *__restrict__ mean, const double *__restrict__ sdv,
+                                              float *x32, uint16_t *x16, float *xn16, int64_t *rowid,
+                                              float *leaf_eps) {
+  int lane = threadIdx.x & (kWave - 1);
+  int64_t row = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + threadIdx.x / kWave;
+  if (row >= rows) return;
+  int64_t src = src_of_row[row];
+  float *o32 = x32 + row * m;
+  uint16_t *o16 = x16 + row * m;
+  if (src < 0) {
+    for (int t = lane; t < m; t += kWave) {
+      o32[t] = 0.0f;
+      o16[t] = 0;
+    }
+    if (lane == 0) {
+      xn16[row] = __builtin_inff();
+      rowid[row] = -1;
+    }
+    return;
+  }
+  const float *r = raw + src * m;
+  double mu = mean[src], sd = sdv[src];
+  float nrm = 0.0f, err = 0.0f;
+  for (int t = lane; t < m; t += kWave) {
+    float z = normalise(r[t], mu, sd);
+    uint16_t b = f32_to_bf16(z);
+    float zb = bf16_to_f32(b);
+    o32[t] = z;
+    o16[t] = b;
+    nrm = fmaf(zb, zb, nrm);
+    float e = z - zb;
+    err = fmaf(e, e, err);
+  }
+  nrm = wave_sum(nrm);
+  err = wave_sum(err);
+  if (lane == 0) {
+    xn16[row] = nrm;
+    rowid[row] = src;
+    // non-negative floats order like their bit patterns
+    float e = sqrtf(err) * (1.0f + 1e-5f);
+    atomicMax(reinterpret_cast<unsigned int *>(leaf_eps + leaf_of_row[row]), f2u(e));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_znorm(const float *x, int64_t n, int m, float *out) {
+  int lane = threadIdx.x & (kWave - 1);
+  int64_t row = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + threadIdx.x / kWave;
+  if (row >= n) return;
+  const float *r = x + row * m;
+  double mu, sd;
+  row_moments(r, m, lane, mu, sd);
+  // every lane has read its elements before any lane writes (out may alias x)
+  float vals[kMaxM / kWave];
+  int c = 0;
+  for (int t = lane; t < m; t += kWave) vals[c++] = normalise(r[t], mu, sd);
+  c = 0;
+  for (int t = lane; t < m; t += kWave) out[row * m + t] = vals[c++];
+}
+
+__global__ void __launch_bounds__(256) k_qprep(const float *__restrict__ raw, int64_t nq, int m, int S, float *q32,
+                                               uint16_t *q16, float *qn16, float *qeps, float *qstat) {
+  __shared__ float zs[kRowsPerBlock][kMaxM];
+  int lane = threadIdx.x & (kWave - 1);
+  int w = threadIdx.x / kWave;
+  int64_t row = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + w;
+  if (row >= nq) return;
+  const float *r = raw + row * m;
+  double mu, sd;
+  row_moments(r, m, lane, mu, sd);
+  float nrm = 0.0f, err = 0.0f;
+  for (int t = lane; t < m; t += kWave) {
+    float z = normalise(r[t], mu, sd);
+    uint16_t b = f32_to_bf16(z);
+    float zb = bf16_to_f32(b);
+    zs[w][t] = z;
+    q32[row * m + t] = z;
+    q16[row * m + t] = b;
+    nrm = fmaf(zb, zb, nrm);
+    float e = z - zb;
+    err = fmaf(e, e, err);
+  }
+  nrm = wave_sum(nrm);
+  err = wave_sum(err);
+  if (lane == 0) {
+    qn16[row] = nrm;
+    qeps[row] = sqrtf(err) * (1.0f + 1e-5f);
+  }
+  wave_lds_sync();
+  for (int s = lane; s < S; s += kWave) {
+    float a, b;
+    segment_moments(zs[w], m, S, s, a, b);
+    qstat[(row * S + s) * 2 + 0] = a;
+    qstat[(row * S + s) * 2 + 1] = b;
+  }
+}
+
+// d^lb(q, L)^2 = sum_s l_s [gap(mu_q, [mu_lo, mu_hi])^2 + gap(sd_q, [sd_lo, sd_hi])^2].
+__global__ void __launch_bounds__(256) k_lb(const float *__restrict__ qstat, int64_t nq,
+                                            const float *__restrict__ boxes, int N, int S, int m, float *lb) {
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= nq * N) return;
+  int64_t q = idx / N;
+  int L = static_cast<int>(idx - q * N);
+  const float *qs = qstat + q * S * 2;
+  const float *bx = boxes + static_cast<int64_t>(L) * S * 4;
+  float acc = 0.0f;
+  for (int s = 0; s < S; ++s) {
+    float len = static_cast<float>(((s + 1) * m) / S - (s * m) / S);
+    float mq = qs[2 * s], sq = qs[2 * s + 1];
+    float gm = fmaxf(fmaxf(bx[4 * s] - mq, mq - bx[4 * s + 1]), 0.0f);
+    float gs = fmaxf(fmaxf(bx[4 * s + 2] - sq, sq - bx[4 * s + 3]), 0.0f);
+    acc += len * (gm * gm + gs * gs);
+  }
+  lb[idx] = sqrtf(acc);
+}
+
+// One work-group per query: bitonic sort of (lb bits, leaf id) keys in LDS.
+__global__ void __launch_bounds__(256) k_order(const float *__restrict__ lb, int N, int P, int32_t *order) {
+  extern __shared__ uint64_t keys[];
+  int64_t q = blockIdx.x;
+  for (int i = threadIdx.x; i < P; i += blockDim.x)
+    keys[i] = i < N ? make_key(lb[q * N + i], static_cast<uint32_t>(i)) : kKeyMax;
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (P >> 1); i += blockDim.x) {
+        int lo = 2 * i - (i & (stride - 1));
+        int hi = lo + stride;
+        bool up = (lo & size) == 0;
+        uint64_t x = keys[lo], y = keys[hi];
+        if ((x > y) == up) {
+          keys[lo] = y;
+          keys[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < N; i += blockDim.x) order[q * N + i] = static_cast<int32_t>(key_row(keys[i]));
+}
+
+__global__ void __launch_bounds__(256) k_make_queries(const float *__restrict__ x32, const int64_t *__restrict__ rows,
+                                                      const float *__restrict__ sigma, int64_t nq, int m,
+                                                      uint64_t seed, float *out) {
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= nq * m) return;
+  int64_t j = idx / m;
+  int t = static_cast<int>(idx - j * m);
+  uint64_t base = mix64(seed ^ mix64(static_cast<uint64_t>(j) * 0x100000001b3ull + t));
+  double u1 = u01(mix64(base + 1)), u2 = u01(mix64(base + 2));
+  double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);  // Box-Muller
+  out[idx] = static_cast<float>(x32[rows[j] * m + t] + sigma[j] * g);
+}
+
+}  // namespace
+
+void launch_series_stats(const float *raw, int64_t n, int m, int S, double *mean, double *sd, float *seg_mu,
+                         float *seg_sd, hipStream_t st) {
+  int64_t blocks = ceil_div(n, kRowsPerBlock);
+  hipLaunchKernelGGL(k_series_stats, dim3(blocks), dim3(256), 0, st, raw, n, m, S, mean, sd, seg_mu, seg_sd);
+  LAUNCH_OK("series_stats");
+}
+
+void launch_pack(const float *raw, const int64_t *src_of_row, const int32_t *leaf_of_row, int64_t rows, int m,
+                 const double *mean, const double *sd, float *x32, uint16_t *x16, float *xn16, int64_t *rowid,
+                 float *leaf_eps, hipStream_t st) {
+  int64_t blocks = ceil_div(rows, kRowsPerBlock);
+  hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, st, raw, src_of_row, leaf_of_row, rows, m, mean, sd, x32,
+                     x16, xn16, rowid, leaf_eps);
+  LAUNCH_OK("pack");
+}
+
+void launch_znorm(const float *x, int64_t n, int m, float *out, hipStream_t st) {
+  int64_t blocks = ceil_div(n, kRowsPerBlock);
+  hipLaunchKernelGGL(k_znorm, dim3(blocks), dim3(256), 0, st, x, n, m, out);
+  LAUNCH_OK("znorm");
+}
+
+void launch_qprep(const float *raw, int64_t nq, int m, int S, float *q32, uint16_t *q16, float *qn16, float *qeps,
+                  float *qstat, hipStream_t st) {
+  int64_t blocks = ceil_div(nq, kRowsPerBlock);
+  hipLaunchKernelGGL(k_qprep, dim3(blocks), dim3(256), 0, st, raw, nq, m, S, q32, q16, qn16, qeps, qstat);
+  LAUNCH_OK("qprep");
+}
+
+void launch_lb(const float *qstat, int64_t nq, const float *boxes, int N, int S, int m, float *lb, hipStream_t st) {
+  int64_t total = nq * N;
+  hipLaunchKernelGGL(k_lb, dim3(ceil_div(total, 256)), dim3(256), 0, st, qstat, nq, boxes, N, S, m, lb);
+  LAUNCH_OK("lb");
+}
+
+void launch_order(const float *lb, int64_t nq, int N, int32_t *order, hipStream_t st) {
+  int P = pow2_at_least(N < 2 ? 2 : N);
+  size_t lds = static_cast<size_t>(P) * sizeof(uint64_t);
+  hipLaunchKernelGGL(k_order, dim3(nq), dim3(256), lds, st, lb, N, P, order);
+  LAUNCH_OK("order");
+}
+
+void launch_make_queries(const float *x32, const int64_t *rows, const float *sigma, int64_t nq, int m,
+                         uint64_t seed, float *out, hipStream_t st) {
+  int64_t total = nq * m;
+  hipLaunchKernelGGL(k_make_queries, dim3(ceil_div(total, 256)), dim3(256), 0, st, x32, rows, sigma, nq, m, seed,
+                     out);
+  LAUNCH_OK("make_queries");
+}
+
+}  // namespace leafi

@@ -1,0 +1,321 @@
+// Round machinery of the batched search (Algorithm 2 run for many queries at
+// once, a few leaves per query per round): the prune cascade that emits the
+// round's (query, leaf) items, the items' CSR-by-leaf layout and scan tiles,
+// the per-query merge into the running top-k with the best-so-far tau, and
+// the final output.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace leafi {
+
+namespace {
+
+// Algorithm 2's cascade for one query: walk the visit order from the cursor,
+// prune a leaf when d^lb > tau or (it has a filter and d^f - o > tau), and
+// emit up to `want` surviving leaves.  All decisions of the round use the tau
+// from before the round.  Visit order is by ascending d^lb, so the first leaf
+// the bound prunes ends the walk.
+__global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float *__restrict__ lb,
+                                                  const int32_t *__restrict__ order, const float *__restrict__ dfilt,
+                                                  int F, const int32_t *__restrict__ filt_of_leaf,
+                                                  const float *__restrict__ offsets, const int32_t *__restrict__ leaf_n,
+                                                  int want, RoundBufs b) {
+  int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int pos = b.cursor[q];
+  int cnt = 0;
+  int64_t lbp = 0, fp = 0, series = 0;
+  if (pos < N) {
+    float tau = b.tau[q];
+    float tau_lb = tau * (1.0f + kLbSlack);
+    int pair = b.pair[q];
+    const float *lbq = lb + q * N;
+    const int32_t *oq = order + q * N;
+    while (pos < N && (want == 0 || cnt < want)) {
+      int L = oq[pos];
+      ++pos;
+      if (lbq[L] > tau_lb) {
+        lbp += N - pos + 1;
+        pos = N;
+        break;
+      }
+      int f = filt_of_leaf ? filt_of_leaf[L] : -1;
+      if (f >= 0 && pair >= 0) {
+        float dF = dfilt[q * F + f] - offsets[static_cast<int64_t>(pair) * F + f];
+        if (dF > tau) {
+          ++fp;
+          continue;
+        }
+      }
+      b.qitem_leaf[q * N + cnt] = L;
+      ++cnt;
+      series += leaf_n[L];
+      atomicAdd(b.leaf_cnt + L, 1);
+    }
+    b.cursor[q] = pos;
+  }
+  b.qitem_cnt[q] = cnt;
+  if (lbp) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlLbPruned), static_cast<unsigned long long>(lbp));
+  if (fp) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFPruned), static_cast<unsigned long long>(fp));
+  if (cnt) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlScanned), static_cast<unsigned long long>(cnt));
+    atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlSeries), static_cast<unsigned long long>(series));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_emit_fallback(int64_t n_fb, int N, RoundBufs b) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n_fb) return;
+  int q = b.fb_q[i];
+  int L = b.fb_leaf[i];
+  int r = atomicAdd(b.qitem_cnt + q, 1);
+  b.qitem_leaf[static_cast<int64_t>(q) * N + r] = L;
+  atomicAdd(b.leaf_cnt + L, 1);
+}
+
+// Exclusive scans over leaves: item starts and tile starts (one work-group).
+__global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__restrict__ leaf_off, int mq,
+                                                    RoundBufs b) {
+  __shared__ int64_t part_i[1024];
+  __shared__ int64_t part_t[1024];
+  int tid = threadIdx.x;
+  int per = (N + 1023) / 1024;
+  int l0 = tid * per, l1 = min(N, l0 + per);
+  int64_t si = 0, stl = 0;
+  for (int L = l0; L < l1; ++L) {
+    int c = b.leaf_cnt[L];
+    int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + kChunkRows - 1) / kChunkRows;
+    si += c;
+    stl += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
+  }
+  part_i[tid] = si;
+  part_t[tid] = stl;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the 1024 partial sums
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t ai = tid >= o ? part_i[tid - o] : 0;
+    int64_t at = tid >= o ? part_t[tid - o] : 0;
+    __syncthreads();
+    part_i[tid] += ai;
+    part_t[tid] += at;
+    __syncthreads();
+  }
+  int64_t ri = part_i[tid] - si, rt = part_t[tid] - stl;
+  for (int L = l0; L < l1; ++L) {
+    int c = b.leaf_cnt[L];
+    int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + kChunkRows - 1) / kChunkRows;
+    b.leaf_istart[L] = static_cast<int32_t>(ri);
+    b.tile_start[L] = static_cast<int32_t>(rt);
+    b.leaf_fill[L] = 0;
+    ri += c;
+    rt += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
+  }
+  if (tid == 1023) {
+    b.leaf_istart[N] = static_cast<int32_t>(part_i[1023]);
+    b.tile_start[N] = static_cast<int32_t>(part_t[1023]);
+    b.ctl[kCtlItems] = part_i[1023];
+    b.ctl[kCtlTiles] = part_t[1023];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_scatter(int64_t nq, int N, RoundBufs b) {
+  int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int n = b.qitem_cnt[q];
+  for (int r = 0; r < n; ++r) {
+    int L = b.qitem_leaf[q * N + r];
+    int slot = b.leaf_istart[L] + atomicAdd(b.leaf_fill + L, 1);
+    b.item_q[slot] = static_cast<int32_t>(q);
+    b.item_leaf[slot] = L;
+    b.qitem_idx[q * N + r] = slot;
+  }
+}
+
+// One wavefront per query: merge the round's item results into the running
+// top-k (sorted by (FP64 distance, row)), refresh tau and, in a regular
+// round, queue every item whose certificate bound does not exceed the new tau
+// for an exact FP32 rescan.
+__global__ void __launch_bounds__(64) k_query_merge(int64_t nq, int N, int kmax, int KM, int check_cert,
+                                                    int dedupe, RoundBufs b) {
+  extern __shared__ unsigned char smem_raw[];
+  volatile double *vals = reinterpret_cast<volatile double *>(smem_raw);
+  volatile uint32_t *tags = reinterpret_cast<volatile uint32_t *>(smem_raw + sizeof(double) * 2 * KM);
+  int lane = threadIdx.x;
+  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    int n_it = b.qitem_cnt[q];
+    if (n_it > 0) {
+      int k = b.kq[q];
+      int have = b.res_cnt[q];
+      for (int i = lane; i < KM; i += kWave) {
+        vals[i] = i < have ? b.res_d2[q * kmax + i] : __builtin_inf();
+        tags[i] = i < have ? static_cast<uint32_t>(b.res_row[q * kmax + i]) : 0xffffffffu;
+      }
+      for (int it = 0; it < n_it; ++it) {
+        int idx = b.qitem_idx[q * N + it];
+        int c = b.item_cnt[idx];
+        for (int i = lane; i < KM; i += kWave) {
+          vals[KM + i] = i < c ? b.item_d2[static_cast<int64_t>(idx) * kmax + i] : __builtin_inf();
+          tags[KM + i] = i < c ? static_cast<uint32_t>(b.item_row[static_cast<int64_t>(idx) * kmax + i]) : 0xffffffffu;
+        }
+        wave_lds_sync();
+        wave_sort_dbl_tag(vals, tags, 2 * KM, lane);
+        if (dedupe && lane == 0) {
+          int w = 0;
+          for (int r = 0; r < 2 * KM; ++r) {
+            if (r > 0 && tags[r] != 0xffffffffu && tags[r] == tags[w - 1]) continue;
+            vals[w] = vals[r];
+            tags[w] = tags[r];
+            ++w;
+          }
+          for (int r = w; r < 2 * KM; ++r) {
+            vals[r] = __builtin_inf();
+            tags[r] = 0xffffffffu;
+          }
+        }
+        wave_lds_sync();
+      }
+      int cnt = 0;
+      for (int i = 0; i < k; ++i) cnt += tags[i] != 0xffffffffu ? 1 : 0;
+      for (int i = lane; i < k; i += kWave) {
+        b.res_d2[q * kmax + i] = vals[i];
+        b.res_row[q * kmax + i] = static_cast<int32_t>(tags[i]);
+      }
+      float tau = __builtin_inff();
+      if (cnt == k) {
+        double d = sqrt(vals[k - 1]);
+        tau = static_cast<float>(d);
+        if (static_cast<double>(tau) < d) tau = nextafterf(tau, __builtin_inff());
+      }
+      if (lane == 0) {
+        b.res_cnt[q] = cnt;
+        b.tau[q] = tau;
+      }
+      if (check_cert) {
+        for (int it = lane; it < n_it; it += kWave) {
+          int idx = b.qitem_idx[q * N + it];
+          if (!(b.item_bound[idx] > tau)) {
+            unsigned long long slot =
+                atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFallback), 1ull);
+            b.fb_q[slot] = static_cast<int32_t>(q);
+            b.fb_leaf[slot] = b.item_leaf[idx];
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+    if (check_cert && lane == 0 && b.cursor[q] < N)
+      atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlActive), 1ull);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_finalize(int64_t nq, int kmax, const int64_t *__restrict__ rowid,
+                                                  RoundBufs b, int64_t *ids, float *dists) {
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= nq * kmax) return;
+  int64_t q = idx / kmax;
+  int i = static_cast<int>(idx - q * kmax);
+  if (i < b.res_cnt[q]) {
+    ids[idx] = rowid[b.res_row[idx]];
+    dists[idx] = static_cast<float>(sqrt(b.res_d2[idx]));
+  } else {
+    ids[idx] = -1;
+    dists[idx] = __builtin_inff();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_items_to_leaf_knn(int64_t n_items, int N, int k, int kmax,
+                                                           const int64_t *__restrict__ rowid, RoundBufs b, float *d,
+                                                           int64_t *ids) {
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n_items * k) return;
+  int64_t it = idx / k;
+  int i = static_cast<int>(idx - it * k);
+  int64_t q = b.item_q[it];
+  int L = b.item_leaf[it];
+  int64_t o = (q * N + L) * k + i;
+  if (i < b.item_cnt[it]) {
+    d[o] = static_cast<float>(sqrt(b.item_d2[it * kmax + i]));
+    ids[o] = rowid[b.item_row[it * kmax + i]];
+  } else {
+    d[o] = __builtin_inff();
+    ids[o] = -1;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_select_pairs(int64_t nq, const int32_t *__restrict__ k_dev,
+                                                      const float *__restrict__ t_dev, int n_pairs,
+                                                      const int32_t *__restrict__ pair_k,
+                                                      const float *__restrict__ pair_t, int kmax, int32_t *pair,
+                                                      int32_t *kq) {
+  int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int k = min(max(k_dev[q], 1), kmax);
+  float t = t_dev[q];
+  int p = -1;
+  if (t < 1.0f)
+    for (int i = 0; i < n_pairs; ++i)
+      if (pair_k[i] == k && pair_t[i] == t) {
+        p = i;
+        break;
+      }
+  pair[q] = p;
+  kq[q] = k;
+}
+
+}  // namespace
+
+void launch_worklist(int64_t nq, int N, const float *lb, const int32_t *order, const float *dfilt, int F,
+                     const int32_t *filt_of_leaf, const float *offsets, const int32_t *leaf_n, int want,
+                     RoundBufs b, hipStream_t st) {
+  hipLaunchKernelGGL(k_worklist, dim3(ceil_div(nq, 256)), dim3(256), 0, st, nq, N, lb, order, dfilt, F, filt_of_leaf,
+                     offsets, leaf_n, want, b);
+  LAUNCH_OK("worklist");
+}
+
+void launch_emit_fallback(int64_t n_fb, int N, RoundBufs b, hipStream_t st) {
+  if (n_fb <= 0) return;
+  hipLaunchKernelGGL(k_emit_fallback, dim3(ceil_div(n_fb, 256)), dim3(256), 0, st, n_fb, N, b);
+  LAUNCH_OK("emit_fallback");
+}
+
+void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, RoundBufs b, hipStream_t st) {
+  hipLaunchKernelGGL(k_leaf_scan, dim3(1), dim3(1024), 0, st, N, leaf_off, mq, b);
+  LAUNCH_OK("leaf_scan");
+}
+
+void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter, dim3(ceil_div(nq, 256)), dim3(256), 0, st, nq, N, b);
+  LAUNCH_OK("scatter");
+}
+
+void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st) {
+  int KM = pow2_at_least(kmax < 2 ? 2 : kmax);
+  size_t lds = static_cast<size_t>(2 * KM) * (sizeof(double) + sizeof(uint32_t));
+  int grid = static_cast<int>(nq < 65536 ? nq : 65536);
+  hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(64), lds, st, nq, N, kmax, KM, check_cert ? 1 : 0,
+                     dedupe ? 1 : 0, b);
+  LAUNCH_OK("query_merge");
+}
+
+void launch_finalize(int64_t nq, int kmax, const int64_t *rowid, RoundBufs b, int64_t *ids, float *dists,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(ceil_div(nq * kmax, 256)), dim3(256), 0, st, nq, kmax, rowid, b, ids, dists);
+  LAUNCH_OK("finalize");
+}
+
+void launch_items_to_leaf_knn(int64_t n_items, int N, int k, int kmax, const int64_t *rowid, RoundBufs b, float *d,
+                              int64_t *ids, hipStream_t st) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(k_items_to_leaf_knn, dim3(ceil_div(n_items * k, 256)), dim3(256), 0, st, n_items, N, k, kmax,
+                     rowid, b, d, ids);
+  LAUNCH_OK("items_to_leaf_knn");
+}
+
+void launch_select_pairs(int64_t nq, const int32_t *k_dev, const float *t_dev, int n_pairs, const int32_t *pair_k,
+                         const float *pair_t, int kmax, int32_t *pair, int32_t *kq, hipStream_t st) {
+  hipLaunchKernelGGL(k_select_pairs, dim3(ceil_div(nq, 256)), dim3(256), 0, st, nq, k_dev, t_dev, n_pairs, pair_k,
+                     pair_t, kmax, pair, kq);
+  LAUNCH_OK("select_pairs");
+}
+
+}  // namespace leafi

@@ -1,0 +1,455 @@
+// Leaf-scan kernels (SearchNode of Algorithm 2 for many (query, leaf) items at
+// once) and the per-item candidate rerank.
+//
+// A scan tile is (leaf L, group of up to MQ queries that all search L this
+// round, chunk of kChunkRows rows of L).  The persistent grid walks the tiles;
+// per tile it streams the chunk's rows once for all the group's queries and
+// keeps, per query, the kprime best (squared distance, row) keys.
+//
+// BF16 form: the squared distance of the bf16-rounded vectors is
+// ||q~||^2 + ||x~||^2 - 2 q~.x~ with q~.x~ on v_mfma_f32_16x16x32_bf16 (data
+// rows are the A operand, 16 rows per MFMA; queries the B operand, 16 per
+// MFMA; FP32 accumulation).  Every lane loads 16 contiguous bytes of its row
+// per K step, so the four lanes of a row read 64 contiguous bytes.
+//
+// FP32 form: direct difference sum_t (q_t - x_t)^2, 16 lanes per row, each
+// lane summing m/16 contiguous elements, then a fixed 16-lane tree.
+//
+// Candidate keeping (both forms): per query an LDS list with a threshold; a
+// key below the threshold is appended with an LDS atomic; when a list could
+// overflow in the next 64 rows it is sorted (bitonic, one wavefront) and cut
+// to kprime, which also tightens the threshold.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace leafi {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+struct TileInfo {
+  int L, g, c, C;
+  int64_t r0, r1, real_end;
+  int p0, nqt;
+};
+
+__device__ inline TileInfo decode_tile(int t, const StoreView &s, const RoundBufs &b, int mq) {
+  // leaf L with tile_start[L] <= t < tile_start[L + 1]
+  int lo = 0, hi = s.N;  // invariant: tile_start[lo] <= t < tile_start[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (b.tile_start[mid] <= t) lo = mid; else hi = mid;
+  }
+  TileInfo ti;
+  ti.L = lo;
+  int64_t off0 = s.leaf_off[lo], off1 = s.leaf_off[lo + 1];
+  ti.C = static_cast<int>((off1 - off0 + kChunkRows - 1) / kChunkRows);
+  int local = t - b.tile_start[lo];
+  ti.g = local / ti.C;
+  ti.c = local - ti.g * ti.C;
+  ti.r0 = off0 + static_cast<int64_t>(ti.c) * kChunkRows;
+  ti.r1 = ti.r0 + kChunkRows < off1 ? ti.r0 + kChunkRows : off1;
+  ti.real_end = off0 + s.leaf_n[lo];
+  ti.p0 = b.leaf_istart[lo] + ti.g * mq;
+  int left = b.leaf_istart[lo + 1] - ti.p0;
+  ti.nqt = left < mq ? left : mq;
+  return ti;
+}
+
+// Sort list j and keep its kprime best; refresh the threshold.
+__device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int j, int cap, int kprime, int lane) {
+  volatile uint64_t *lst = keys + static_cast<int64_t>(j) * cap;
+  int c = cnt[j];
+  int P = pow2_at_least(c < 2 ? 2 : c);
+  for (int i = c + lane; i < P; i += kWave) lst[i] = kKeyMax;
+  wave_lds_sync();
+  wave_sort_u64(lst, P, lane);
+  int keep = c < kprime ? c : kprime;
+  if (lane == 0) {
+    cnt[j] = keep;
+    thr[j] = keep == kprime ? lst[kprime - 1] : kKeyMax;
+  }
+  wave_lds_sync();
+}
+
+__device__ inline void append_key(uint64_t *keys, int *cnt, const uint64_t *thr, int j, int cap, uint64_t key) {
+  if (key < thr[j]) {
+    int slot = atomicAdd(cnt + j, 1);
+    keys[static_cast<int64_t>(j) * cap + slot] = key;
+  }
+}
+
+__device__ inline void finish_tile(uint64_t *keys, int *cnt, uint64_t *thr, int t, int mq, int nqt, int cap,
+                                   int kprime, int wave, int nwaves, int lane, uint64_t *cand) {
+  for (int j = wave; j < mq; j += nwaves) {
+    uint64_t *out = cand + (static_cast<int64_t>(t) * mq + j) * kprime;
+    if (j < nqt) {
+      compact_list(keys, cnt, thr, j, cap, kprime, lane);
+      const volatile uint64_t *lst = keys + static_cast<int64_t>(j) * cap;
+      for (int i = lane; i < kprime; i += kWave) out[i] = lst[i];
+    } else {
+      for (int i = lane; i < kprime; i += kWave) out[i] = kKeyMax;
+    }
+  }
+}
+
+template <int KS, int QB>
+__global__ void __launch_bounds__(256) k_scan_bf16(StoreView s, QueryView qv, RoundBufs b, int kprime, int cap,
+                                                   uint64_t *cand) {
+  constexpr int MQ = 16 * QB;
+  constexpr int kWaves = 4;
+  extern __shared__ uint64_t smem[];
+  uint64_t *keys = smem;
+  uint64_t *thr = keys + MQ * cap;
+  int *cnt = reinterpret_cast<int *>(thr + MQ);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int m = s.m;
+  const int n_tiles = static_cast<int>(b.ctl[kCtlTiles]);
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    TileInfo ti = decode_tile(t, s, b, MQ);
+    if (threadIdx.x < MQ) {
+      cnt[threadIdx.x] = 0;
+      thr[threadIdx.x] = kKeyMax;
+    }
+    // B operand: this lane's query column and k-chunk, all K steps
+    bf16x8 qreg[QB][KS];
+    float qn[QB];
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      int j = 16 * qb + (lane & 15);
+      if (j < ti.nqt) {
+        int64_t qi = b.item_q[ti.p0 + j];
+        const uint16_t *qp = qv.q16 + qi * m + 8 * (lane >> 4);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) qreg[qb][k] = *reinterpret_cast<const bf16x8 *>(qp + 32 * k);
+        qn[qb] = qv.qn16[qi];
+      } else {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) qreg[qb][k] = bf16x8{};
+        qn[qb] = 0.0f;
+      }
+    }
+    __syncthreads();
+    for (int64_t base = ti.r0; base < ti.r1; base += 64) {
+      const uint16_t *ap = s.x16 + (base + 16 * wave + (lane & 15)) * m + 8 * (lane >> 4);
+      bf16x8 a[KS];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) a[k] = *reinterpret_cast<const bf16x8 *>(ap + 32 * k);
+      floatx4 acc[QB];
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) acc[qb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < KS; ++k)
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb)
+          acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k], qreg[qb][k], acc[qb], 0, 0, 0);
+      // epilogue: lane holds rows rowc..rowc+3 for query column (lane & 15)
+      int64_t rowc = base + 16 * wave + 4 * (lane >> 4);
+      float4 xn = *reinterpret_cast<const float4 *>(s.xn16 + rowc);
+      float xr[4] = {xn.x, xn.y, xn.z, xn.w};
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) {
+        int j = 16 * qb + (lane & 15);
+        if (j < ti.nqt) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            int64_t row = rowc + r;
+            if (row < ti.real_end) {
+              float d2 = fmaxf(qn[qb] + xr[r] - 2.0f * acc[qb][r], 0.0f);
+              append_key(keys, cnt, thr, j, cap, make_key(d2, static_cast<uint32_t>(row)));
+            }
+          }
+        }
+      }
+      __syncthreads();
+      for (int j = wave; j < ti.nqt; j += kWaves)
+        if (cnt[j] > cap - 64) compact_list(keys, cnt, thr, j, cap, kprime, lane);
+      __syncthreads();
+    }
+    finish_tile(keys, cnt, thr, t, MQ, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
+    __syncthreads();
+  }
+}
+
+template <int EPL>
+__global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
+                                                   int cap, uint64_t *cand) {
+  constexpr int kWaves = 4;
+  extern __shared__ uint64_t smem[];
+  uint64_t *keys = smem;
+  uint64_t *thr = keys + mq * cap;
+  int *cnt = reinterpret_cast<int *>(thr + mq);
+  float *qs = reinterpret_cast<float *>(cnt + mq);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int sub = lane & 15, rsel = lane >> 4;
+  const int m = s.m;  // == 16 * EPL
+  const int n_tiles = static_cast<int>(b.ctl[kCtlTiles]);
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    TileInfo ti = decode_tile(t, s, b, mq);
+    if (threadIdx.x < mq) {
+      cnt[threadIdx.x] = 0;
+      thr[threadIdx.x] = kKeyMax;
+    }
+    for (int e = threadIdx.x; e < ti.nqt * m; e += blockDim.x) {
+      int j = e / m;
+      qs[e] = qv.q32[static_cast<int64_t>(b.item_q[ti.p0 + j]) * m + (e - j * m)];
+    }
+    __syncthreads();
+    for (int64_t base = ti.r0; base < ti.r1; base += 64) {
+      float x[4][EPL];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const float *xp = s.x32 + (base + 16 * wave + 4 * st + rsel) * m + sub * EPL;
+#pragma unroll
+        for (int e = 0; e < EPL; e += 2) {
+          float2 v = *reinterpret_cast<const float2 *>(xp + e);
+          x[st][e] = v.x;
+          x[st][e + 1] = v.y;
+        }
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        int64_t row = base + 16 * wave + 4 * st + rsel;
+        for (int j = 0; j < ti.nqt; ++j) {
+          const float *qp = qs + j * m + sub * EPL;
+          float p = 0.0f;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            float d = qp[e] - x[st][e];
+            p = fmaf(d, d, p);
+          }
+          p += __shfl_xor(p, 8, 16);
+          p += __shfl_xor(p, 4, 16);
+          p += __shfl_xor(p, 2, 16);
+          p += __shfl_xor(p, 1, 16);
+          if (sub == 0 && row < ti.real_end) append_key(keys, cnt, thr, j, cap, make_key(p, static_cast<uint32_t>(row)));
+        }
+      }
+      __syncthreads();
+      for (int j = wave; j < ti.nqt; j += kWaves)
+        if (cnt[j] > cap - 64) compact_list(keys, cnt, thr, j, cap, kprime, lane);
+      __syncthreads();
+    }
+    finish_tile(keys, cnt, thr, t, mq, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
+    __syncthreads();
+  }
+}
+
+// One wavefront per item.  LDS: merged keys [P], then per candidate the fp32
+// key, FP64 distance and row.
+__global__ void __launch_bounds__(64) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
+                                                    int kmax, int bf16, int PB, const uint64_t *__restrict__ cand) {
+  extern __shared__ uint64_t smem[];
+  volatile uint64_t *buf = smem;                                                 // [PB]
+  volatile uint64_t *k32 = smem + PB;                                            // [PK]
+  const int PK = pow2_at_least(kprime < 2 ? 2 : kprime);
+  volatile double *d64 = reinterpret_cast<volatile double *>(smem + PB + PK);   // [PK]
+  volatile uint32_t *r64 = reinterpret_cast<volatile uint32_t *>(d64 + PK);      // [PK]
+  const int lane = threadIdx.x;
+  const int m = s.m;
+  const int n_items = static_cast<int>(b.ctl[kCtlItems]);
+  // error constants (see the certificate below)
+  const double u = 1.0 / 16777216.0;  // 2^-24
+  const float delta32 = static_cast<float>(2.0 * (m + 4) * u);
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    int L = b.item_leaf[item];
+    int64_t q = b.item_q[item];
+    int k = b.kq[q];
+    int pos = item - b.leaf_istart[L];
+    int g = pos / mq, j = pos - (pos / mq) * mq;
+    int C = static_cast<int>((s.leaf_off[L + 1] - s.leaf_off[L] + kChunkRows - 1) / kChunkRows);
+    int n = C * kprime;
+    int P = pow2_at_least(n < 2 ? 2 : n);
+    int64_t tile0 = b.tile_start[L] + static_cast<int64_t>(g) * C;
+    for (int e = lane; e < P; e += kWave) {
+      uint64_t v = kKeyMax;
+      if (e < n) {
+        int c = e / kprime;
+        v = cand[((tile0 + c) * mq + j) * kprime + (e - c * kprime)];
+      }
+      buf[e] = v;
+    }
+    wave_lds_sync();
+    wave_sort_u64(buf, P, lane);
+    uint64_t kth = buf[kprime - 1];
+    // number of real candidates among the first kprime
+    int nc = 0;
+    for (int e = 0; e < kprime; ++e) nc += buf[e] != kKeyMax ? 1 : 0;
+    // FP32 direct-difference rerank
+    const float *qp = qv.q32 + q * m;
+    for (int e = 0; e < PK; ++e) {
+      if (e < nc) {
+        uint32_t row = key_row(buf[e]);
+        const float *xp = s.x32 + static_cast<int64_t>(row) * m;
+        float p = 0.0f;
+        for (int t = lane; t < m; t += kWave) {
+          float d = qp[t] - xp[t];
+          p = fmaf(d, d, p);
+        }
+        p = wave_sum(p);
+        if (lane == 0) k32[e] = make_key(p, row);
+      } else if (lane == 0) {
+        k32[e] = kKeyMax;
+      }
+    }
+    wave_lds_sync();
+    wave_sort_u64(k32, PK, lane);
+    // FP64 for every candidate within the FP32 error band of the k-th
+    float band = __builtin_inff();
+    if (nc >= k) band = key_d2(k32[k - 1]) * (1.0f + 2.0f * delta32);
+    int nb = 0;
+    for (int e = 0; e < nc; ++e) nb += key_d2(k32[e]) <= band ? 1 : 0;
+    for (int e = 0; e < PK; ++e) {
+      if (e < nb) {
+        uint32_t row = key_row(k32[e]);
+        const float *xp = s.x32 + static_cast<int64_t>(row) * m;
+        double p = 0.0;
+        for (int t = lane; t < m; t += kWave) {
+          double d = static_cast<double>(qp[t]) - static_cast<double>(xp[t]);
+          p = fma(d, d, p);
+        }
+        p = wave_sum(p);
+        if (lane == 0) {
+          d64[e] = p;
+          r64[e] = row;
+        }
+      } else if (lane == 0) {
+        d64[e] = __builtin_inf();
+        r64[e] = 0xffffffffu;
+      }
+    }
+    wave_lds_sync();
+    wave_sort_dbl_tag(d64, r64, PK, lane);
+    int keep = nb < k ? nb : k;
+    for (int i = lane; i < keep; i += kWave) {
+      b.item_d2[static_cast<int64_t>(item) * kmax + i] = d64[i];
+      b.item_row[static_cast<int64_t>(item) * kmax + i] = static_cast<int32_t>(r64[i]);
+    }
+    // Certificate: every row of the item outside the candidate list has a
+    // scan key >= kth.  BF16: the computed value is within delta16 of the
+    // exact squared distance of the bf16 vectors, and rounding moved q and x
+    // by at most qeps and leaf_eps, so d(q, x) >= sqrt(kth - delta16) - eps.
+    // FP32: the direct-difference value is within a relative delta32.
+    if (lane == 0) {
+      float bound = __builtin_inff();
+      if (kth != kKeyMax) {
+        float kd = key_d2(kth);
+        if (bf16) {
+          double qn = qv.qn16[q];
+          double x2 = 1.02 * m;
+          double delta16 = (m + 3) * 2.0 * u * (qn + x2 + 2.0 * sqrt(qn * x2));
+          double v = static_cast<double>(kd) - delta16;
+          bound = static_cast<float>((v > 0.0 ? sqrt(v) : 0.0) - qv.qeps[q] - s.leaf_eps[L]);
+        } else {
+          bound = static_cast<float>(sqrt(static_cast<double>(kd) * (1.0 - delta32)));
+        }
+      }
+      b.item_cnt[item] = keep;
+      b.item_bound[item] = bound;
+    }
+    wave_lds_sync();
+  }
+}
+
+template <int KS, int QB>
+void scan_bf16_inst(StoreView s, QueryView q, RoundBufs b, int kprime, int cap, uint64_t *cand, int grid,
+                    hipStream_t st) {
+  constexpr int MQ = 16 * QB;
+  size_t lds = static_cast<size_t>(MQ) * cap * 8 + MQ * 8 + MQ * 4;
+  auto kern = k_scan_bf16<KS, QB>;
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, s, q, b, kprime, cap, cand);
+  LAUNCH_OK("scan_bf16");
+}
+
+template <int QB>
+void scan_bf16_ks(int ks, StoreView s, QueryView q, RoundBufs b, int kprime, int cap, uint64_t *cand, int grid,
+                  hipStream_t st) {
+  switch (ks) {
+    case 1: scan_bf16_inst<1, QB>(s, q, b, kprime, cap, cand, grid, st); break;
+    case 2: scan_bf16_inst<2, QB>(s, q, b, kprime, cap, cand, grid, st); break;
+    case 3: scan_bf16_inst<3, QB>(s, q, b, kprime, cap, cand, grid, st); break;
+    case 4: scan_bf16_inst<4, QB>(s, q, b, kprime, cap, cand, grid, st); break;
+    case 5: scan_bf16_inst<5, QB>(s, q, b, kprime, cap, cand, grid, st); break;
+    case 6: scan_bf16_inst<6, QB>(s, q, b, kprime, cap, cand, grid, st); break;
+    case 7: scan_bf16_inst<7, QB>(s, q, b, kprime, cap, cand, grid, st); break;
+    case 8: scan_bf16_inst<8, QB>(s, q, b, kprime, cap, cand, grid, st); break;
+    default: fail(LEAFI_EINVAL, "bf16 scan supports m <= 256");
+  }
+}
+
+template <int EPL>
+void scan_fp32_inst(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int cap, uint64_t *cand, int grid,
+                    hipStream_t st) {
+  size_t lds = static_cast<size_t>(mq) * cap * 8 + mq * 8 + mq * 4 + static_cast<size_t>(mq) * s.m * 4;
+  auto kern = k_scan_fp32<EPL>;
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, s, q, b, mq, kprime, cap, cand);
+  LAUNCH_OK("scan_fp32");
+}
+
+}  // namespace
+
+// Candidate-list geometry for a given kprime: (queries per tile, list capacity).
+void scan_geometry(int kprime, int *mq, int *cap) {
+  int kc = pow2_at_least(kprime < 4 ? 4 : kprime);
+  if (kc <= 32) { *mq = 32; *cap = 128; }
+  else if (kc <= 64) { *mq = 16; *cap = 256; }
+  else if (kc <= 128) { *mq = 16; *cap = 256; }
+  else { *mq = 16; *cap = 512; }
+}
+
+void launch_scan_bf16(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
+                      hipStream_t st) {
+  int mq2, cap;
+  scan_geometry(kprime, &mq2, &cap);
+  if (mq != mq2) fail(LEAFI_EINTERNAL, "scan_bf16: tile geometry mismatch");
+  int ks = s.m / 32;
+  if (mq == 32) scan_bf16_ks<2>(ks, s, q, b, kprime, cap, cand, grid, st);
+  else scan_bf16_ks<1>(ks, s, q, b, kprime, cap, cand, grid, st);
+}
+
+void launch_scan_fp32(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
+                      hipStream_t st) {
+  int mq2, cap;
+  scan_geometry(kprime, &mq2, &cap);
+  if (mq > mq2) fail(LEAFI_EINTERNAL, "scan_fp32: tile geometry mismatch");
+  switch (s.m / 16) {
+    case 2: scan_fp32_inst<2>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    case 4: scan_fp32_inst<4>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    case 6: scan_fp32_inst<6>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    case 8: scan_fp32_inst<8>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    case 10: scan_fp32_inst<10>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    case 12: scan_fp32_inst<12>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    case 14: scan_fp32_inst<14>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    case 16: scan_fp32_inst<16>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    case 24: scan_fp32_inst<24>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    case 32: scan_fp32_inst<32>(s, q, b, mq, kprime, cap, cand, grid, st); break;
+    default: fail(LEAFI_EINVAL, "fp32 scan supports m in {32,64,...,256,384,512}");
+  }
+}
+
+int rerank_lds_bytes(int max_chunks, int kprime, int *PB) {
+  int n = max_chunks * kprime;
+  *PB = pow2_at_least(n < 2 ? 2 : n);
+  int PK = pow2_at_least(kprime < 2 ? 2 : kprime);
+  return (*PB + PK) * 8 + PK * 8 + PK * 4;
+}
+
+void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int kmax, bool bf16,
+                        const uint64_t *cand, int grid, int max_chunks, hipStream_t st) {
+  int PB;
+  size_t lds = static_cast<size_t>(rerank_lds_bytes(max_chunks, kprime, &PB));
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_item_rerank),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(k_item_rerank, dim3(grid), dim3(64), lds, st, s, q, b, mq, kprime, kmax, bf16 ? 1 : 0, PB, cand);
+  LAUNCH_OK("item_rerank");
+}
+
+}  // namespace leafi

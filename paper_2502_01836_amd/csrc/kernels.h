@@ -1,0 +1,183 @@
+// Launch wrappers for the gfx950 kernels of libleafi.  Every wrapper enqueues
+// on `st` and checks the launch; sizes are validated by the caller.
+#pragma once
+
+#include "common.h"
+
+namespace leafi {
+
+// ---- ingest and query preparation (k_prep.hip) ---------------------------
+
+// Per series: mean and population std in FP64 (sd < 1e-8 marks a constant
+// series), and per-segment mean/std of the stored fp32 normalised values.
+void launch_series_stats(const float *raw, int64_t n, int m, int S, double *mean, double *sd, float *seg_mu,
+                         float *seg_sd, hipStream_t st);
+
+// Build the leaf store: output row r takes raw series src_of_row[r] (-1 =
+// padding) and writes the normalised fp32 row, its bf16 copy, ||x~||^2, the
+// original id, and raises leaf_eps[leaf_of_row[r]] to ||x - x~||.
+void launch_pack(const float *raw, const int64_t *src_of_row, const int32_t *leaf_of_row, int64_t rows, int m,
+                 const double *mean, const double *sd, float *x32, uint16_t *x16, float *xn16, int64_t *rowid,
+                 float *leaf_eps, hipStream_t st);
+
+// Plain z-normalisation (out may alias x).
+void launch_znorm(const float *x, int64_t n, int m, float *out, hipStream_t st);
+
+// Query preparation: normalised fp32 and bf16 rows, ||q~||^2, ||q - q~||, and
+// per-segment (mean, std) pairs qstat [nq, S, 2].
+void launch_qprep(const float *raw, int64_t nq, int m, int S, float *q32, uint16_t *q16, float *qn16, float *qeps,
+                  float *qstat, hipStream_t st);
+
+// Summary lower bounds lb [nq, N].
+void launch_lb(const float *qstat, int64_t nq, const float *boxes, int N, int S, int m, float *lb, hipStream_t st);
+
+// Visit order: per query, leaves sorted by (lb, leaf id).
+void launch_order(const float *lb, int64_t nq, int N, int32_t *order, hipStream_t st);
+
+// Training queries: q_j = x32[row_j] + sigma_j * N(0, 1) noise from a
+// counter-based generator keyed by (seed, j, t).
+void launch_make_queries(const float *x32, const int64_t *rows, const float *sigma, int64_t nq, int m,
+                         uint64_t seed, float *out, hipStream_t st);
+
+// ---- round machinery (k_rounds.hip) ---------------------------------------
+
+struct RoundBufs {
+  // per query
+  int32_t *cursor;      // next position in the visit order
+  float *tau;           // k-th best distance so far (+inf until k results)
+  int32_t *kq;          // k of each query
+  int32_t *pair;        // calibrated (k, target) row of the offset table, -1 = filters off
+  int32_t *res_cnt;     // results held
+  double *res_d2;       // [nq, kmax] squared FP64 distances, sorted
+  int32_t *res_row;     // [nq, kmax] leaf-store rows
+  int32_t *qitem_cnt;   // items emitted this round
+  int32_t *qitem_leaf;  // [nq, N] leaves emitted this round
+  int32_t *qitem_idx;   // [nq, N] their item slots
+  // per leaf
+  int32_t *leaf_cnt;    // [N] items per leaf this round
+  int32_t *leaf_fill;   // [N]
+  int32_t *leaf_istart; // [N + 1]
+  int32_t *tile_start;  // [N + 1]
+  // per item
+  int32_t *item_q;
+  int32_t *item_leaf;
+  double *item_d2;      // [items, kmax]
+  int32_t *item_row;    // [items, kmax]
+  int32_t *item_cnt;
+  float *item_bound;    // lower bound on any row of the item that is not a candidate
+  // fallback list of (query, leaf) pairs
+  int32_t *fb_q;
+  int32_t *fb_leaf;
+  // control: see Ctl
+  int64_t *ctl;
+};
+
+enum Ctl : int {
+  kCtlItems = 0,      // items this round
+  kCtlTiles = 1,      // scan tiles this round
+  kCtlActive = 2,     // queries with leaves left
+  kCtlFallback = 3,   // uncertified items queued for an exact rescan
+  kCtlLbPruned = 4,
+  kCtlFPruned = 5,
+  kCtlSeries = 6,     // real series in scanned items
+  kCtlScanned = 7,    // items (leaves) scanned, excluding rescans
+  kCtlCount = 8
+};
+
+struct StoreView {
+  const float *x32;
+  const uint16_t *x16;
+  const float *xn16;
+  const int64_t *leaf_off;  // padded row offsets [N + 1]
+  const int32_t *leaf_n;    // real rows per leaf
+  const float *leaf_eps;
+  int m;
+  int N;
+};
+
+struct QueryView {
+  const float *q32;
+  const uint16_t *q16;
+  const float *qn16;
+  const float *qeps;
+};
+
+// Emit this round's (query, leaf) pairs from the visit order (Algorithm 2's
+// prune cascade).  want = leaves per query this round (0 = all survivors).
+void launch_worklist(int64_t nq, int N, const float *lb, const int32_t *order, const float *dfilt, int F,
+                     const int32_t *filt_of_leaf, const float *offsets, const int32_t *leaf_n, int want,
+                     RoundBufs b, hipStream_t st);
+
+// Emit pairs from the fallback list instead.
+void launch_emit_fallback(int64_t n_fb, int N, RoundBufs b, hipStream_t st);
+
+// Items CSR by leaf and tile ranges (single work-group).
+void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, RoundBufs b, hipStream_t st);
+
+// Place each query's emitted leaves into item slots.
+void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st);
+
+// Leaf scan over all tiles; keeps the kprime best (key = dist^2 bits, row)
+// per (tile, query slot) in cand.
+void launch_scan_bf16(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
+                      hipStream_t st);
+void launch_scan_fp32(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
+                      hipStream_t st);
+
+// Per item: merge its tiles' candidates, rerank in FP32 (FP64 for the band
+// around the k-th), write the item's top-k and its certificate bound.
+void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int kmax, bool bf16,
+                        const uint64_t *cand, int grid, int max_chunks, hipStream_t st);
+
+// Candidate-list geometry for kprime kept keys: queries per tile and list capacity.
+void scan_geometry(int kprime, int *mq, int *cap);
+
+// Per query: merge the round's items into the running top-k, update tau,
+// queue uncertified items (check_cert) and count active queries.
+void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st);
+
+// Final outputs: ids (original series ids) and Euclidean distances.
+void launch_finalize(int64_t nq, int kmax, const int64_t *rowid, RoundBufs b, int64_t *ids, float *dists,
+                     hipStream_t st);
+
+// Per-leaf top-k for all (query, leaf) items (all-pairs mode): copies item
+// results into d [nq, N, k] / ids [nq, N, k].
+void launch_items_to_leaf_knn(int64_t n_items, int N, int k, int kmax, const int64_t *rowid, RoundBufs b,
+                              float *d, int64_t *ids, hipStream_t st);
+
+// ---- learned filters (k_mlp.hip) -------------------------------------------
+
+// d^f for every (query, filter): out [nq, F].
+void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, hipStream_t st);
+
+// Per-query offset row lookup for (k, target) pairs.
+// k is clamped to [1, kmax].
+void launch_select_pairs(int64_t nq, const int32_t *k_dev, const float *t_dev, int n_pairs, const int32_t *pair_k,
+                         const float *pair_t, int kmax, int32_t *pair, int32_t *kq, hipStream_t st);
+
+struct TrainArgs {
+  float *w;              // [F, P] weights (updated)
+  float *w_best;         // [F, P] best-validation copy
+  const float *xq;       // query pool [*, m] (normalised)
+  const int32_t *ex_q;   // [F, n_ex] query index of each example
+  const float *ex_y;     // [F, n_ex] target
+  int n_train;           // first n_train examples of each filter train
+  int n_ex;              // remaining n_ex - n_train validate
+  int F, m, h;
+  int batch;
+  int max_epochs;
+  int patience;
+  float lr0, lr_min;
+  uint64_t seed;
+  float *val_mse;        // [F] best validation MSE
+  int32_t *epochs_run;   // [F]
+};
+
+// Full SGD training, one work-group per filter.
+void launch_mlp_train(const TrainArgs &a, hipStream_t st);
+
+// One SGD step per filter on explicit batches.
+void launch_mlp_sgd_step(float *w, int F, int m, int h, const float *x, const float *y, int batch, float lr,
+                         float *loss, hipStream_t st);
+
+}  // namespace leafi

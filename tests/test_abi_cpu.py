@@ -1,0 +1,83 @@
+"""The C-ABI library loads and exports every entry point its header declares;
+argument validation works without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "leafi.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(leafi_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2502_01836_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2502_01836_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    from paper_2502_01836_amd import _lib
+    names = _declared()
+    assert len(names) >= 20
+    bound = {n for n, _, _ in _lib.SIGNATURES}
+    for n in names:
+        assert hasattr(lib, n), f"{n} not exported"
+        assert n in bound, f"{n} has no ctypes signature"
+
+
+def test_version_and_defaults(lib):
+    from paper_2502_01836_amd import _lib
+    assert lib.leafi_version().decode().startswith("leafi")
+    o = _lib.TrainOpts()
+    lib.leafi_default_train_opts(ctypes.byref(o))
+    assert (o.n_global, o.n_local, o.max_epochs, o.batch, o.patience) == (1500, 500, 1000, 64, 10)
+    assert abs(o.lr0 - 0.01) < 1e-9 and abs(o.a - 2.0) < 1e-9 and o.th_override < 0
+    s = _lib.SearchOpts()
+    lib.leafi_default_search_opts(ctypes.byref(s))
+    assert s.k_max == 1 and s.scan == 0 and s.n_schedule == 2 and list(s.schedule[:2]) == [1, 0]
+
+
+def test_struct_sizes_match_header_layout():
+    from paper_2502_01836_amd import _lib
+    assert ctypes.sizeof(_lib.BuildOpts) == 16
+    assert ctypes.sizeof(_lib.SearchOpts) == 4 * 4 + 8 * 4 + 4 + 3 * 4
+    assert ctypes.sizeof(_lib.SearchStats) == 5 * 8 + 2 * 4 + 3 * 8
+    assert ctypes.sizeof(_lib.Info) == 8 + 6 * 4 + 8 + 8
+
+
+def test_null_handles_are_rejected_without_touching_the_gpu(lib):
+    from paper_2502_01836_amd import _lib
+    info = _lib.Info()
+    assert lib.leafi_get_info(None, ctypes.byref(info)) == -1
+    assert lib.leafi_export_boxes(None, None) == -1
+    assert "NULL" in lib.leafi_last_error().decode()
+    o = _lib.SearchOpts()
+    lib.leafi_default_search_opts(ctypes.byref(o))
+    assert lib.leafi_search_knn(None, None, 0, None, None, ctypes.byref(o), None, None, None, None) == -1
+    assert lib.leafi_create(None) == -1
+    # sizes are validated before any device work
+    assert lib.leafi_znorm(None, -1, 8, None, None) == -1
+    assert lib.leafi_mlp_infer(None, 1, 8, 3, None, 1, None, None) == -1   # hidden not a multiple of 4
+    assert lib.leafi_mlp_sgd_step(None, 1, 8, 4, None, None, 65, 0.1, None, None) == -1  # batch > 64
+    lib.leafi_destroy(None)
+
+
+def test_python_binding_fails_loudly_without_library(tmp_path):
+    from paper_2502_01836_amd import _lib
+    saved = _lib._lib
+    _lib._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="not built"):
+            _lib.load(str(tmp_path / "missing.so"))
+    finally:
+        _lib._lib = saved
