@@ -87,8 +87,11 @@ __device__ inline void finish_tile(uint64_t *keys, int *cnt, uint64_t *thr, int 
     uint64_t *out = cand + (static_cast<int64_t>(t) * mq + j) * kprime;
     if (j < nqt) {
       compact_list(keys, cnt, thr, j, cap, kprime, lane);
+      // only the first cnt[j] entries are candidates; the list may hold fewer
+      // than kprime (a chunk with few real rows) and LDS beyond them is stale
       const volatile uint64_t *lst = keys + static_cast<int64_t>(j) * cap;
-      for (int i = lane; i < kprime; i += kWave) out[i] = lst[i];
+      const int keep = cnt[j];
+      for (int i = lane; i < kprime; i += kWave) out[i] = i < keep ? lst[i] : kKeyMax;
     } else {
       for (int i = lane; i < kprime; i += kWave) out[i] = kKeyMax;
     }
