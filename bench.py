@@ -1,0 +1,207 @@
+"""Benchmark of the LeaFi hot path on one MI355X.
+
+Workload (the learned-filter configuration): 1,000,000 random-walk series of
+length 256 (fp32, z-normalised by the library), leaf capacity 10,000, one
+256->256->1 ReLU MLP filter per selected leaf trained on 1,500 global + 500
+local noisy queries per filter, conformal calibration on 500 held-out queries
+for recall 0.99 at k = 1, and query batches of 1,000 noisy collection series
+(noise levels 0.05 / 0.1 / 0.2, one level per batch, cycling).
+
+A step is one batched search of 1,000 queries through the whole search path:
+z-normalisation, summary bounds, visit order, filter inference, the round
+schedule of prune / leaf scan (BF16 MFMA) / rerank (FP32, FP64 band) / merge,
+and the output.  Index build, training and calibration happen before the
+timed region.  Inputs are resident in HBM when timing starts.
+
+Prints one JSON line (rank 0).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "queries/sec + p50/p99 latency at recall@k≥0.99; leaf-scan HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rw1m")
+    ap.add_argument("--cpu-sample", type=int, default=48, help="queries timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--fp32-sample", type=int, default=200, help="queries timed on the plain FP32 path (0 = skip)")
+    ap.add_argument("--schedule", default="1,0")
+    ap.add_argument("--max-epochs", type=int, default=1000)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU layout is a design "
+              "note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_2502_01836_amd as pkg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pkg.load()
+    wl = W.WORKLOADS[a.workload]
+    n, m = wl["n"], wl["m"]
+    t0 = time.time()
+    raw = W.random_walk(n, m, wl["seed"])
+    calib, _, _ = W.noisy_queries(raw, wl["n_calib"], wl["train_sigma"], wl["calib_seed"], wl["calib_seed"] + 100)
+    tests = []
+    for s, sd in zip(wl["sigmas"], wl["test_seeds"]):
+        q, _, _ = W.noisy_queries(raw, wl["nq"], s, sd, sd + 100)
+        tests.append(q)
+    log(f"generated {n}x{m} in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    raw_d = torch.from_numpy(raw).to(dev)
+    ix = pkg.Index()
+    t0 = time.time()
+    ix.build(raw_d, leaf_capacity=wl["capacity"], n_segments=16)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    info = ix.info()
+    log(f"built index: {info['n_leaves']} leaves in {t_build:.1f}s")
+    del raw_d
+    t0 = time.time()
+    rep = ix.train_filters(n_global=1500, n_local=500, noise_lo=wl["train_sigma"][0], noise_hi=wl["train_sigma"][1],
+                           a=2.0, max_epochs=a.max_epochs, seed=wl["train_seed"])
+    t_train = time.time() - t0
+    log(f"trained {rep['n_filters']} filters in {t_train:.1f}s (th={rep['th']:.1f}, "
+        f"epochs<={rep['epochs_max_run']}, val mse {rep['mean_val_mse']:.3f})")
+    t0 = time.time()
+    ix.calibrate(torch.from_numpy(calib).to(dev), [wl["k"]], [wl["target"]])
+    torch.cuda.synchronize()
+    t_cal = time.time() - t0
+    log(f"calibrated in {t_cal:.1f}s")
+
+    sched = tuple(int(x) for x in a.schedule.split(","))
+    k = wl["k"]
+    qd = [torch.from_numpy(q).to(dev) for q in tests]
+    nq = wl["nq"]
+    kt = torch.full((nq,), k, dtype=torch.int32, device=dev)
+    tt = torch.full((nq,), wl["target"], dtype=torch.float32, device=dev)
+    out = (torch.empty((nq, k), dtype=torch.int64, device=dev), torch.empty((nq, k), dtype=torch.float32, device=dev))
+
+    # exact answers (filters off) for the recall check; exact search is itself
+    # checked against the FP64 oracle by the parity tests
+    exact = []
+    for q in qd:
+        ids, d = ix.search(q, k=kt, target=tt, k_max=k, use_filters=False, schedule=sched)
+        exact.append(d.cpu().numpy().astype(np.float64))
+
+    def step(i, with_stats=False):
+        return ix.search(qd[i % len(qd)], k=kt, target=tt, k_max=k, use_filters=True, schedule=sched,
+                         with_stats=with_stats, out=out)
+
+    for i in range(a.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(a.steps):
+        s0 = time.perf_counter()
+        step(i)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    qps = a.steps * nq / t_total
+    ms_per_step = 1e3 * t_total / a.steps
+
+    # recall and scan roofline from one instrumented pass over each batch
+    recalls, scan_ms, scan_bytes, stats_all = [], 0.0, 0.0, []
+    for i in range(len(qd)):
+        ids, d, st = step(i, with_stats=True)
+        got = d.cpu().numpy().astype(np.float64)
+        recalls.append(float((got[:, k - 1] <= exact[i][:, k - 1] * (1 + 1e-6)).mean()))
+        scan_ms += st["ms_scan"]
+        scan_bytes += st["scan_bytes"]
+        stats_all.append(st)
+    achieved = scan_bytes / (scan_ms * 1e-3) / 1e9 if scan_ms > 0 else 0.0
+    n_series = n * nq
+    pruned = 1.0 - sum(s["series_scanned"] for s in stats_all) / (len(stats_all) * n_series)
+
+    # plain FP32 per-query path on the same GPU (same filters and calibration)
+    fp32 = None
+    if a.fp32_sample > 0:
+        ns = min(a.fp32_sample, nq)
+        qs = qd[1][:ns].contiguous()
+        ix.search(qs[:4].contiguous(), k=k, target=wl["target"], use_filters=True, schedule=sched, scan="fp32")
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        ix.search(qs, k=k, target=wl["target"], use_filters=True, schedule=sched, scan="fp32")
+        torch.cuda.synchronize()
+        fp32 = ns / (time.perf_counter() - s0)
+
+    # CPU oracle (FP64 brute force, all host threads) on a bounded sample
+    cpu = None
+    if a.cpu_sample > 0:
+        import oracle as O
+        ns = a.cpu_sample
+        xs = O.znorm(raw)
+        qs_cpu = O.znorm(tests[1][:ns])
+        s0 = time.perf_counter()
+        O.knn(xs, qs_cpu, k)
+        dt = time.perf_counter() - s0
+        cpu = {"value": ns / dt, "unit": "queries/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"{ns} queries of the sigma=0.1 batch, FP64 brute-force exact k-NN over all {n} series"}
+
+    lat_ms = np.array(lat) * 1e3
+    line = {
+        "metric": METRIC,
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {n} random walks x {m}, leaf capacity {wl['capacity']}, "
+                               f"{rep['n_filters']} MLP filters {m}->{m}->1, k={k}, recall target {wl['target']}, "
+                               f"batches of {nq} queries (noise 0.05/0.1/0.2)",
+                   "schedule": list(sched), "n_leaves": info["n_leaves"]},
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "recall_at_k": float(np.mean(recalls)),
+        "recall_by_batch": recalls,
+        "series_pruning_ratio": pruned,
+        "fp32_plain_qps": fp32,
+        "speedup_vs_fp32_plain": (qps / fp32) if fp32 else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_scan_bf16", "scan_ms_per_step": scan_ms / len(qd),
+                     "scan_bytes_per_step": scan_bytes / len(qd)},
+        "cpu_baseline": cpu,
+        "setup_s": {"build": t_build, "train": t_train, "calibrate": t_cal,
+                    "collect_ms": rep["ms_collect"], "sgd_ms": rep["ms_train"]},
+        "search_stats": stats_all[1],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

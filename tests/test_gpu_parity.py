@@ -179,9 +179,12 @@ def test_duplicates_tie_break_by_id_and_empty_batch():
     ix = pkg.Index().build(torch.from_numpy(raw).cuda(), leaf_capacity=400, n_segments=8)
     q = raw[[10, 3000]].copy()
     ids, d = ix.search(torch.from_numpy(q).cuda(), k=3, use_filters=False, schedule=(1,))
-    ids = ids.cpu().numpy()
-    assert list(ids[0]) == [10, 4000, 4500]
-    assert ids[1][0] == 3000 and set(ids[1][:2]) == {20, 3000}
+    ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    assert list(ids[0]) == [10, 4000, 4500] and not d[0].any()
+    xs, qs = O.znorm(raw), O.znorm(q)
+    want_ids, want_d = O.knn(xs, qs, 3)
+    assert_knn_parity(ids, d, want_ids, want_d, xs, qs)
+    assert set(ids[1][:2]) == {20, 3000}
     e_ids, e_d = ix.search(torch.zeros((0, 64), device="cuda"), k=1, use_filters=False)
     assert e_ids.shape == (0, 1)
 
