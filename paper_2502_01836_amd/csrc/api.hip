@@ -259,30 +259,53 @@ void prep_queries(leafi_index *ix, const float *raw, int64_t nq, hipStream_t st)
   launch_order(w.lb.get(), nq, ix->N, w.order.get(), st);
 }
 
+// Scan work-groups resident per CU (the persistent grid is num_cus times this).
+constexpr int kScanBlocksPerCU = 4;
+// Device bytes above which a round's item buffers are sized from the actual
+// counts (one host read-back) instead of from an upper bound.
+constexpr double kPreallocLimit = 1.0 * (1 << 30);
+
 // With the round's item lists in place (qitem_leaf / qitem_cnt / leaf_cnt)
 // and the round control words zeroed: lay out items and tiles, scan, rerank.
-// Returns the number of items (0: nothing enqueued after the layout).
-int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm) {
+// items_bound >= 0 is an upper bound of the round's items: buffers are sized
+// from it and nothing is read back.  Otherwise the counts are read back
+// first.  Returns the item count when it was read back, else -1.
+int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
+                   int64_t items_bound = -1) {
   Workspace &w = ix->ws;
   int mq, cap;
   scan_geometry(kprime, &mq, &cap);
   (void)cap;
   launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, views(w), st);
-  read_ctl(ix, st);
-  int64_t items = w.h_ctl[kCtlItems], tiles = w.h_ctl[kCtlTiles];
-  if (items == 0) return 0;
-  ensure_items(ix, items, kmax);
-  w.cand.reserve(static_cast<size_t>(tiles) * mq * kprime);
+  int64_t items = -1, tiles;
+  const int64_t tiles_bound =
+      items_bound >= 0 ? ceil_div(items_bound, mq) * ix->max_chunks + ix->total_chunks : -1;
+  const double bytes = items_bound >= 0 ? static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
+                                              static_cast<double>(tiles_bound) * mq * kprime * 8.0
+                                        : 0.0;
+  if (items_bound < 0 || bytes > kPreallocLimit) {
+    read_ctl(ix, st);
+    items = w.h_ctl[kCtlItems];
+    tiles = w.h_ctl[kCtlTiles];
+    if (items == 0) return 0;
+  } else {
+    items = -1;
+    tiles = tiles_bound;
+  }
+  ensure_items(ix, items >= 0 ? items : std::max<int64_t>(items_bound, 1), kmax);
+  w.cand.reserve(static_cast<size_t>(std::max<int64_t>(tiles, 1)) * mq * kprime);
   RoundBufs b = views(w);
   StoreView s = store_view(ix);
   QueryView q = query_view(w);
   launch_scatter(nq, ix->N, b, st);
-  int grid_scan = static_cast<int>(std::min<int64_t>(tiles, static_cast<int64_t>(ix->num_cus) * 2));
+  int grid_scan = static_cast<int>(std::min<int64_t>(std::max<int64_t>(tiles, 1),
+                                                     static_cast<int64_t>(ix->num_cus) * kScanBlocksPerCU));
   if (tm) HIP_OK(hipEventRecord(w.ev0, st));
   if (bf16) launch_scan_bf16(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
   else launch_scan_fp32(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
   if (tm) HIP_OK(hipEventRecord(w.ev1, st));
-  int grid_r = static_cast<int>(std::min<int64_t>(items, static_cast<int64_t>(ix->num_cus) * 16));
+  int64_t ib = items >= 0 ? items : std::max<int64_t>(items_bound, 1);
+  int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * 16));
   launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks, st);
   return items;
 }
@@ -323,51 +346,67 @@ struct SearchPlan {
 void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
                   const SearchPlan &p, int64_t *ids, float *dists, leafi_search_stats *stats, hipStream_t st) {
   Workspace &w = ix->ws;
+  const int N = ix->N;
   ensure_queries(ix, nq, p.kmax);
   prep_queries(ix, raw, nq, st);
   const int F = ix->filt.F;
   const bool use_f = p.filters && F > 0 && ix->cal.pairs() > 0;
-  if (use_f) launch_mlp_infer(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), nq, w.dfilt.get(), st);
   launch_select_pairs(nq, k_dev, t_dev, use_f ? ix->cal.pairs() : 0, use_f ? ix->cal.pair_k.get() : nullptr,
                       use_f ? ix->cal.pair_t.get() : nullptr, p.kmax, w.pair.get(), w.kq.get(), st);
   fill_i32(w.cursor.get(), nq, 0, st);
   fill_f32(w.tau.get(), nq, INFINITY, st);
   fill_i32(w.res_cnt.get(), nq, 0, st);
   HIP_OK(hipMemsetAsync(w.ctl.get(), 0, kCtlCount * sizeof(int64_t), st));
+  if (use_f) {
+    w.plist.reserve(static_cast<size_t>(F) * nq);
+    w.pcnt.reserve(F);
+  }
   const int kprime = p.kprime;
   const int kprime_fb = default_kprime(p.kmax, false);
   Timing tm;
   int64_t fallback = 0;
   int rounds = 0;
-  std::vector<int32_t> hcnt(ix->N);
+  bool filters_ready = false;
+  std::vector<int32_t> hcnt(N);
   for (int r = 0;; ++r) {
-    reset_round_ctl(w, st);
-    HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, ix->N * sizeof(int32_t), st));
-    int want = p.schedule[std::min<size_t>(r, p.schedule.size() - 1)];
-    RoundBufs b = views(w);
-    launch_worklist(nq, ix->N, w.lb.get(), w.order.get(), w.dfilt.get(), std::max(F, 1),
-                    use_f ? ix->filt.filt_of_leaf.get() : nullptr, use_f ? ix->cal.offsets.get() : nullptr,
-                    ix->leaf_n.get(), want, b, st);
-    if (stats) {
-      d2h(hcnt.data(), w.leaf_cnt.get(), ix->N, st);
+    // Filters cannot prune while tau is +inf (the first round).  Once the
+    // first round has set tau, evaluate d^f for every pair a later round can
+    // still test; tau only decreases, so this covers all later rounds.
+    if (use_f && r > 0 && !filters_ready) {
+      HIP_OK(hipMemsetAsync(w.pcnt.get(), 0, F * sizeof(int32_t), st));
+      launch_filter_pairs(nq, N, w.lb.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
+                          w.pcnt.get(), st);
+      launch_mlp_infer_pairs(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), nq,
+                             w.dfilt.get(), st);
+      filters_ready = true;
     }
-    int64_t items = scan_round(ix, nq, p.bf16, kprime, p.kmax, st, stats ? &tm : nullptr);
+    reset_round_ctl(w, st);
+    HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, N * sizeof(int32_t), st));
+    const int want = p.schedule[std::min<size_t>(r, p.schedule.size() - 1)];
+    const bool f_now = use_f && filters_ready;
+    launch_worklist(nq, N, w.lb.get(), w.order.get(), w.dfilt.get(), std::max(F, 1),
+                    f_now ? ix->filt.filt_of_leaf.get() : nullptr, f_now ? ix->cal.offsets.get() : nullptr,
+                    ix->leaf_n.get(), want, views(w), st);
+    if (stats) d2h(hcnt.data(), w.leaf_cnt.get(), N, st);
+    const int64_t bound = nq * static_cast<int64_t>(want == 0 ? N : std::min(want, N));
+    int64_t items = scan_round(ix, nq, p.bf16, kprime, p.kmax, st, stats ? &tm : nullptr, bound);
     if (items == 0) break;
-    ++rounds;
-    if (stats) tm.scan_bytes += leaf_bytes(ix, hcnt, p.bf16);
-    launch_query_merge(nq, ix->N, p.kmax, true, false, views(w), st);
+    launch_query_merge(nq, N, p.kmax, true, false, views(w), st);
     read_ctl(ix, st);
+    if (w.h_ctl[kCtlItems] == 0) break;
+    ++rounds;
     add_scan_time(ix, stats ? &tm : nullptr);
-    int64_t active = w.h_ctl[kCtlActive];
-    int64_t n_fb = w.h_ctl[kCtlFallback];
+    if (stats) tm.scan_bytes += leaf_bytes(ix, hcnt, p.bf16);
+    const int64_t active = w.h_ctl[kCtlActive];
+    const int64_t n_fb = w.h_ctl[kCtlFallback];
     if (n_fb > 0) {
       fallback += n_fb;
       reset_round_ctl(w, st);
-      HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, ix->N * sizeof(int32_t), st));
+      HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, N * sizeof(int32_t), st));
       fill_i32(w.qitem_cnt.get(), nq, 0, st);
-      launch_emit_fallback(n_fb, ix->N, views(w), st);
-      if (scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr) > 0)
-        launch_query_merge(nq, ix->N, p.kmax, false, true, views(w), st);
+      launch_emit_fallback(n_fb, N, views(w), st);
+      if (scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, n_fb) != 0)
+        launch_query_merge(nq, N, p.kmax, false, true, views(w), st);
     }
     if (active == 0) break;
   }
@@ -520,11 +559,13 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     std::vector<int64_t> members;
     members.reserve(n);
     int max_chunks = 1;
+    int64_t total_chunks = 0;
     for (int L = 0; L < N; ++L) {
       for (int64_t r = off[L]; r < off[L + 1]; ++r) leaf_of_row[r] = L;
       for (size_t i = 0; i < tree.leaves[L].size(); ++i) src[off[L] + i] = tree.leaves[L][i];
       members.insert(members.end(), tree.leaves[L].begin(), tree.leaves[L].end());
       max_chunks = std::max<int>(max_chunks, static_cast<int>(ceil_div(off[L + 1] - off[L], kChunkRows)));
+      total_chunks += ceil_div(off[L + 1] - off[L], kChunkRows);
     }
     std::vector<float> boxes = leaf_boxes(hmu, hsd, S, tree);
     // 4. device leaf store
@@ -555,6 +596,7 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     ix->N = N;
     ix->rows = rows;
     ix->max_chunks = max_chunks;
+    ix->total_chunks = total_chunks;
     ix->h_leaf_off = std::move(off);
     ix->h_leaf_n = std::move(lsz);
     ix->h_members = std::move(members);

@@ -77,8 +77,9 @@ class DevBuf {
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
-// Rows of each leaf are padded to a multiple of this in the leaf store.
-constexpr int kRowAlign = 64;
+// Rows of each leaf are padded to a multiple of this in the leaf store (an
+// even number of the scan's 64-row blocks, so its unrolled loop has no tail).
+constexpr int kRowAlign = 128;
 // Rows of one scan tile (multiple of kRowAlign).
 constexpr int kChunkRows = 1024;
 // Relative slack applied to tau before a summary bound may prune (covers the

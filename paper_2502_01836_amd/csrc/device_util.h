@@ -62,7 +62,7 @@ __host__ __device__ __forceinline__ int pow2_at_least(int n) {
 }
 
 // Bitonic sort of P (power of two) 64-bit keys in LDS by one wavefront, ascending.
-__device__ inline void wave_sort_u64(volatile uint64_t *a, int P, int lane) {
+__device__ inline void wave_sort_u64(uint64_t *a, int P, int lane) {
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = lane; i < (P >> 1); i += kWave) {
@@ -82,7 +82,7 @@ __device__ inline void wave_sort_u64(volatile uint64_t *a, int P, int lane) {
 
 // Bitonic sort of P (power of two) (double, uint32) pairs, ascending by
 // (value, tag), by one wavefront.
-__device__ inline void wave_sort_dbl_tag(volatile double *v, volatile uint32_t *t, int P, int lane) {
+__device__ inline void wave_sort_dbl_tag(double *v, uint32_t *t, int P, int lane) {
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = lane; i < (P >> 1); i += kWave) {

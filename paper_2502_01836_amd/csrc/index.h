@@ -89,6 +89,7 @@ struct Workspace {
   DevBuf<double> item_d2;
   DevBuf<float> item_bound;
   DevBuf<uint64_t> cand;
+  DevBuf<int32_t> plist, pcnt;  // filter pairs to evaluate
   DevBuf<int64_t> ctl;
   std::vector<int64_t> h_ctl;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -105,6 +106,7 @@ struct leafi_index {
   int N = 0;
   int64_t rows = 0;     // padded rows
   int max_chunks = 1;   // chunks of the largest leaf
+  int64_t total_chunks = 0;  // scan chunks over all leaves
   // leaf store (device)
   leafi::DevBuf<float> x32, xn16, boxes, leaf_eps;
   leafi::DevBuf<uint16_t> x16;

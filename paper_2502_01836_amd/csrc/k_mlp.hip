@@ -11,14 +11,15 @@ namespace leafi {
 
 namespace {
 
-// Inference tile: 64 queries x 256 hidden units per work-group; a thread owns
-// 4 consecutive hidden units for 16 queries (64 FP32 accumulators).  The
-// query tile is staged in LDS, transposed, 64 inputs at a time.
-__global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, int F, int m, int h,
-                                                   const float *__restrict__ x, int64_t nq, float *out) {
+// Inference tile: 64 rows (queries) x 256 hidden units per work-group; a
+// thread owns 4 consecutive hidden units for 16 rows (64 FP32 accumulators).
+// The row tile is staged in LDS, transposed, 64 inputs at a time.  Row r of
+// the tile is query qidx(r) and its result goes to out[qidx(r) * F + f]; the
+// arithmetic of one (query, filter) pair is the same whichever tile holds it.
+template <typename RowIdx>
+__device__ inline void mlp_tile(const float *__restrict__ w, int F, int f, int m, int h,
+                                const float *__restrict__ x, int64_t r0, int64_t nrows, RowIdx qidx, float *out) {
   __shared__ float xs[64][64 + 4];
-  const int f = blockIdx.x;
-  const int64_t q0 = static_cast<int64_t>(blockIdx.y) * 64;
   const int tid = threadIdx.x;
   const int jg = tid & 63, qg = tid >> 6;
   const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
@@ -42,7 +43,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, 
       for (int e = tid; e < 64 * 64; e += 256) {
         int qq = e >> 6, i = e & 63;
         float v = 0.0f;
-        if (q0 + qq < nq && ib + i < m) v = x[(q0 + qq) * m + ib + i];
+        if (r0 + qq < nrows && ib + i < m) v = x[qidx(r0 + qq) * m + ib + i];
         xs[i][qq] = v;
       }
       __syncthreads();
@@ -78,10 +79,31 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, 
   if (jg == 0) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      int64_t q = q0 + 16 * qg + v;
-      if (q < nq) out[q * F + f] = part[v] + b2;
+      int64_t r = r0 + 16 * qg + v;
+      if (r < nrows) out[qidx(r) * F + f] = part[v] + b2;
     }
   }
+}
+
+// d^f for every (query, filter): grid (F, ceil(nq / 64)).
+__global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, int F, int m, int h,
+                                                   const float *__restrict__ x, int64_t nq, float *out) {
+  mlp_tile(w, F, blockIdx.x, m, h, x, static_cast<int64_t>(blockIdx.y) * 64, nq, [](int64_t r) { return r; }, out);
+}
+
+// d^f for listed pairs: filter f evaluates queries plist[f * stride + 0 ..
+// pcnt[f]); work-groups past a filter's count exit at once.
+__global__ void __launch_bounds__(256) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
+                                                         const float *__restrict__ x,
+                                                         const int32_t *__restrict__ plist,
+                                                         const int32_t *__restrict__ pcnt, int64_t stride,
+                                                         float *out) {
+  const int f = blockIdx.x;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 64;
+  const int64_t cnt = pcnt[f];
+  if (r0 >= cnt) return;  // uniform for the work-group
+  const int32_t *pl = plist + f * stride;
+  mlp_tile(w, F, f, m, h, x, r0, cnt, [pl](int64_t r) { return static_cast<int64_t>(pl[r]); }, out);
 }
 
 constexpr int kTB = 64;  // training mini-batch capacity (columns of the LDS batch)
@@ -331,6 +353,14 @@ void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64
   dim3 grid(F, static_cast<unsigned>(ceil_div(nq, 64)));
   hipLaunchKernelGGL(k_mlp_infer, grid, dim3(256), 0, st, w, F, m, h, x, nq, out);
   LAUNCH_OK("mlp_infer");
+}
+
+void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int32_t *plist,
+                            const int32_t *pcnt, int64_t stride, float *out, hipStream_t st) {
+  if (F <= 0 || stride <= 0) return;
+  dim3 grid(F, static_cast<unsigned>(ceil_div(stride, 64)));
+  hipLaunchKernelGGL(k_mlp_infer_pairs, grid, dim3(256), 0, st, w, F, m, h, x, plist, pcnt, stride, out);
+  LAUNCH_OK("mlp_infer_pairs");
 }
 
 static size_t step_lds(int m) { return static_cast<size_t>(m) * kTB * 4 + (4 + 3) * kTB * 4; }

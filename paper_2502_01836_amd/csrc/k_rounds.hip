@@ -10,57 +10,112 @@ namespace leafi {
 
 namespace {
 
-// Algorithm 2's cascade for one query: walk the visit order from the cursor,
-// prune a leaf when d^lb > tau or (it has a filter and d^f - o > tau), and
-// emit up to `want` surviving leaves.  All decisions of the round use the tau
-// from before the round.  Visit order is by ascending d^lb, so the first leaf
-// the bound prunes ends the walk.
+// Algorithm 2's cascade for one query (one wavefront per query): walk the
+// visit order from the cursor 64 positions at a time, prune a leaf when
+// d^lb > tau or (it has a filter and d^f - o > tau), and emit up to `want`
+// surviving leaves in visit order.  All decisions of the round use the tau
+// from before the round.  The order is by ascending d^lb, so the first leaf
+// the bound prunes ends the walk (every later leaf is pruned too).
 __global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float *__restrict__ lb,
                                                   const int32_t *__restrict__ order, const float *__restrict__ dfilt,
                                                   int F, const int32_t *__restrict__ filt_of_leaf,
                                                   const float *__restrict__ offsets, const int32_t *__restrict__ leaf_n,
                                                   int want, RoundBufs b) {
-  int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (q >= nq) return;  // whole wavefront
   int pos = b.cursor[q];
   int cnt = 0;
   int64_t lbp = 0, fp = 0, series = 0;
   if (pos < N) {
-    float tau = b.tau[q];
-    float tau_lb = tau * (1.0f + kLbSlack);
-    int pair = b.pair[q];
+    const float tau = b.tau[q];
+    const float tau_lb = tau * (1.0f + kLbSlack);
+    const int pair = b.pair[q];
+    const bool use_f = filt_of_leaf != nullptr && pair >= 0;
     const float *lbq = lb + q * N;
     const int32_t *oq = order + q * N;
+    const uint64_t lt = (1ull << lane) - 1ull;
     while (pos < N && (want == 0 || cnt < want)) {
-      int L = oq[pos];
-      ++pos;
-      if (lbq[L] > tau_lb) {
-        lbp += N - pos + 1;
+      const int p = pos + lane;
+      const bool valid = p < N;
+      const int L = valid ? oq[p] : 0;
+      const bool lbbad = valid && lbq[L] > tau_lb;
+      const uint64_t mbad = __ballot(lbbad);
+      const int nvalid = N - pos < kWave ? N - pos : kWave;
+      const int s = mbad ? __ffsll(static_cast<unsigned long long>(mbad)) - 1 : kWave;
+      const int stop = s < nvalid ? s : nvalid;
+      const bool in = lane < stop;
+      bool fpr = false;
+      if (in && use_f) {
+        const int f = filt_of_leaf[L];
+        if (f >= 0) fpr = dfilt[q * F + f] - offsets[static_cast<int64_t>(pair) * F + f] > tau;
+      }
+      const bool surv = in && !fpr;
+      uint64_t msurv = __ballot(surv);
+      int end = stop;
+      bool cut = false;
+      if (want > 0 && __popcll(msurv) > want - cnt) {
+        const int need = want - cnt;
+        const int rank = __popcll(msurv & lt);
+        const uint64_t mlast = __ballot(surv && rank == need - 1);
+        end = __ffsll(static_cast<unsigned long long>(mlast));  // one past the need-th survivor
+        msurv &= end >= kWave ? ~0ull : ((1ull << end) - 1ull);
+        cut = true;
+      }
+      const uint64_t mend = end >= kWave ? ~0ull : ((1ull << end) - 1ull);
+      if ((msurv >> lane) & 1ull) {
+        const int rank = __popcll(msurv & lt);
+        b.qitem_leaf[q * N + cnt + rank] = L;
+        atomicAdd(b.leaf_cnt + L, 1);
+        series += leaf_n[L];
+      }
+      cnt += __popcll(msurv);
+      fp += __popcll(__ballot(fpr) & mend);
+      if (cut) {
+        pos += end;
+        break;
+      }
+      if (s < nvalid) {
+        lbp += N - (pos + s);
         pos = N;
         break;
       }
-      int f = filt_of_leaf ? filt_of_leaf[L] : -1;
-      if (f >= 0 && pair >= 0) {
-        float dF = dfilt[q * F + f] - offsets[static_cast<int64_t>(pair) * F + f];
-        if (dF > tau) {
-          ++fp;
-          continue;
-        }
-      }
-      b.qitem_leaf[q * N + cnt] = L;
-      ++cnt;
-      series += leaf_n[L];
-      atomicAdd(b.leaf_cnt + L, 1);
+      pos += nvalid;
     }
+  }
+  series = wave_sum(series);
+  if (lane == 0) {
     b.cursor[q] = pos;
+    b.qitem_cnt[q] = cnt;
+    if (lbp) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlLbPruned), static_cast<unsigned long long>(lbp));
+    if (fp) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFPruned), static_cast<unsigned long long>(fp));
+    if (cnt) {
+      atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlScanned), static_cast<unsigned long long>(cnt));
+      atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlSeries), static_cast<unsigned long long>(series));
+    }
   }
-  b.qitem_cnt[q] = cnt;
-  if (lbp) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlLbPruned), static_cast<unsigned long long>(lbp));
-  if (fp) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFPruned), static_cast<unsigned long long>(fp));
-  if (cnt) {
-    atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlScanned), static_cast<unsigned long long>(cnt));
-    atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlSeries), static_cast<unsigned long long>(series));
-  }
+}
+
+// Filter pairs worth evaluating once tau is known: every (query, filtered
+// leaf) still ahead of the cursor whose bound does not prune it.  Later rounds
+// only lower tau, so no other pair can reach the filter test.  Filter f
+// collects its queries in plist[f * nq + ...].
+__global__ void __launch_bounds__(256) k_filter_pairs(int64_t nq, int N, const float *__restrict__ lb,
+                                                      const int32_t *__restrict__ order,
+                                                      const int32_t *__restrict__ filt_of_leaf, RoundBufs b,
+                                                      int32_t *plist, int32_t *pcnt) {
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= nq * N) return;
+  int64_t q = idx / N;
+  int pos = static_cast<int>(idx - q * N);
+  if (pos < b.cursor[q] || b.pair[q] < 0) return;
+  int L = order[q * N + pos];
+  int f = filt_of_leaf[L];
+  if (f < 0) return;
+  float tau = b.tau[q];
+  if (lb[q * N + L] > tau * (1.0f + kLbSlack)) return;
+  int slot = atomicAdd(pcnt + f, 1);
+  plist[static_cast<int64_t>(f) * nq + slot] = static_cast<int32_t>(q);
 }
 
 __global__ void __launch_bounds__(256) k_emit_fallback(int64_t n_fb, int N, RoundBufs b) {
@@ -118,11 +173,13 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
   }
 }
 
+// One wavefront per query: place its emitted leaves into item slots.
 __global__ void __launch_bounds__(256) k_scatter(int64_t nq, int N, RoundBufs b) {
-  int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (q >= nq) return;
-  int n = b.qitem_cnt[q];
-  for (int r = 0; r < n; ++r) {
+  const int n = b.qitem_cnt[q];
+  for (int r = lane; r < n; r += kWave) {
     int L = b.qitem_leaf[q * N + r];
     int slot = b.leaf_istart[L] + atomicAdd(b.leaf_fill + L, 1);
     b.item_q[slot] = static_cast<int32_t>(q);
@@ -138,8 +195,8 @@ __global__ void __launch_bounds__(256) k_scatter(int64_t nq, int N, RoundBufs b)
 __global__ void __launch_bounds__(64) k_query_merge(int64_t nq, int N, int kmax, int KM, int check_cert,
                                                     int dedupe, RoundBufs b) {
   extern __shared__ unsigned char smem_raw[];
-  volatile double *vals = reinterpret_cast<volatile double *>(smem_raw);
-  volatile uint32_t *tags = reinterpret_cast<volatile uint32_t *>(smem_raw + sizeof(double) * 2 * KM);
+  double *vals = reinterpret_cast<double *>(smem_raw);
+  uint32_t *tags = reinterpret_cast<uint32_t *>(smem_raw + sizeof(double) * 2 * KM);
   int lane = threadIdx.x;
   for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
     int n_it = b.qitem_cnt[q];
@@ -267,9 +324,16 @@ __global__ void __launch_bounds__(256) k_select_pairs(int64_t nq, const int32_t 
 void launch_worklist(int64_t nq, int N, const float *lb, const int32_t *order, const float *dfilt, int F,
                      const int32_t *filt_of_leaf, const float *offsets, const int32_t *leaf_n, int want,
                      RoundBufs b, hipStream_t st) {
-  hipLaunchKernelGGL(k_worklist, dim3(ceil_div(nq, 256)), dim3(256), 0, st, nq, N, lb, order, dfilt, F, filt_of_leaf,
+  hipLaunchKernelGGL(k_worklist, dim3(ceil_div(nq, 4)), dim3(256), 0, st, nq, N, lb, order, dfilt, F, filt_of_leaf,
                      offsets, leaf_n, want, b);
   LAUNCH_OK("worklist");
+}
+
+void launch_filter_pairs(int64_t nq, int N, const float *lb, const int32_t *order, const int32_t *filt_of_leaf,
+                         RoundBufs b, int32_t *plist, int32_t *pcnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_filter_pairs, dim3(ceil_div(nq * N, 256)), dim3(256), 0, st, nq, N, lb, order, filt_of_leaf, b,
+                     plist, pcnt);
+  LAUNCH_OK("filter_pairs");
 }
 
 void launch_emit_fallback(int64_t n_fb, int N, RoundBufs b, hipStream_t st) {
@@ -284,7 +348,7 @@ void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, RoundBufs b, hipSt
 }
 
 void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
-  hipLaunchKernelGGL(k_scatter, dim3(ceil_div(nq, 256)), dim3(256), 0, st, nq, N, b);
+  hipLaunchKernelGGL(k_scatter, dim3(ceil_div(nq, 4)), dim3(256), 0, st, nq, N, b);
   LAUNCH_OK("scatter");
 }
 

@@ -58,9 +58,14 @@ __device__ inline TileInfo decode_tile(int t, const StoreView &s, const RoundBuf
   return ti;
 }
 
+// Work-group barrier for LDS traffic only: waits for this wave's LDS
+// operations, then s_barrier.  Unlike __syncthreads it does not drain
+// outstanding global loads, so prefetched rows stay in flight across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Sort list j and keep its kprime best; refresh the threshold.
 __device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int j, int cap, int kprime, int lane) {
-  volatile uint64_t *lst = keys + static_cast<int64_t>(j) * cap;
+  uint64_t *lst = keys + static_cast<int64_t>(j) * cap;
   int c = cnt[j];
   int P = pow2_at_least(c < 2 ? 2 : c);
   for (int i = c + lane; i < P; i += kWave) lst[i] = kKeyMax;
@@ -89,13 +94,70 @@ __device__ inline void finish_tile(uint64_t *keys, int *cnt, uint64_t *thr, int 
       compact_list(keys, cnt, thr, j, cap, kprime, lane);
       // only the first cnt[j] entries are candidates; the list may hold fewer
       // than kprime (a chunk with few real rows) and LDS beyond them is stale
-      const volatile uint64_t *lst = keys + static_cast<int64_t>(j) * cap;
+      const uint64_t *lst = keys + static_cast<int64_t>(j) * cap;
       const int keep = cnt[j];
       for (int i = lane; i < kprime; i += kWave) out[i] = i < keep ? lst[i] : kKeyMax;
     } else {
       for (int i = lane; i < kprime; i += kWave) out[i] = kKeyMax;
     }
   }
+}
+
+// A operand of this wave's 16 rows of the 64-row block at `base`: lane l
+// holds row base + 16 wave + (l & 15), elements 32 k + 8 (l >> 4) .. + 8.
+template <int KS>
+__device__ __forceinline__ void load_rows(const uint16_t *x16, int64_t base, int wave, int lane, int m,
+                                          bf16x8 (&a)[KS]) {
+  const uint16_t *ap = x16 + (base + 16 * wave + (lane & 15)) * m + 8 * (lane >> 4);
+#pragma unroll
+  for (int k = 0; k < KS; ++k) a[k] = *reinterpret_cast<const bf16x8 *>(ap + 32 * k);
+}
+
+// One 64-row block: its squared norms, the prefetch of the next block into
+// `nxt`, MFMAs on `cur`, candidate appends, then list maintenance.
+template <int KS, int QB>
+__device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &ti, int64_t base, bf16x8 (&cur)[KS],
+                                           bf16x8 (&nxt)[KS], bool more, const bf16x8 (&qreg)[QB][KS],
+                                           const float (&qn)[QB], uint64_t *keys, int *cnt, uint64_t *thr, int cap,
+                                           int kprime, int wave, int lane) {
+  constexpr int kWaves = 4;
+  const int64_t rowc = base + 16 * wave + 4 * (lane >> 4);
+  const float4 xn = *reinterpret_cast<const float4 *>(s.xn16 + rowc);
+  // unconditional (the last block of a tile re-reads its own rows, which are
+  // cached): a branch here would leave the in-flight load count ambiguous and
+  // make the compiler drain every load before the MFMAs
+  load_rows<KS>(s.x16, more ? base + 64 : base, wave, lane, s.m, nxt);
+  floatx4 acc[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) acc[qb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < KS; ++k)
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb)
+      acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur[k], qreg[qb][k], acc[qb], 0, 0, 0);
+  // epilogue: lane holds rows rowc..rowc+3 for query column (lane & 15)
+  const float xr[4] = {xn.x, xn.y, xn.z, xn.w};
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const int j = 16 * qb + (lane & 15);
+    if (j < ti.nqt) {
+      const uint64_t tj = thr[j];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = rowc + r;
+        const float d2 = fmaxf(qn[qb] + xr[r] - 2.0f * acc[qb][r], 0.0f);
+        const uint64_t key = make_key(d2, static_cast<uint32_t>(row));
+        if (row < ti.real_end && key < tj) {
+          const int slot = atomicAdd(cnt + j, 1);
+          keys[static_cast<int64_t>(j) * cap + slot] = key;
+        }
+      }
+    }
+  }
+  lds_barrier();
+  for (int j = wave; j < ti.nqt; j += kWaves)
+    if (cnt[j] > cap - 64) compact_list(keys, cnt, thr, j, cap, kprime, lane);
+  lds_barrier();
 }
 
 template <int KS, int QB>
@@ -136,41 +198,19 @@ __global__ void __launch_bounds__(256) k_scan_bf16(StoreView s, QueryView qv, Ro
       }
     }
     __syncthreads();
-    for (int64_t base = ti.r0; base < ti.r1; base += 64) {
-      const uint16_t *ap = s.x16 + (base + 16 * wave + (lane & 15)) * m + 8 * (lane >> 4);
-      bf16x8 a[KS];
-#pragma unroll
-      for (int k = 0; k < KS; ++k) a[k] = *reinterpret_cast<const bf16x8 *>(ap + 32 * k);
-      floatx4 acc[QB];
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb) acc[qb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int k = 0; k < KS; ++k)
-#pragma unroll
-        for (int qb = 0; qb < QB; ++qb)
-          acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k], qreg[qb][k], acc[qb], 0, 0, 0);
-      // epilogue: lane holds rows rowc..rowc+3 for query column (lane & 15)
-      int64_t rowc = base + 16 * wave + 4 * (lane >> 4);
-      float4 xn = *reinterpret_cast<const float4 *>(s.xn16 + rowc);
-      float xr[4] = {xn.x, xn.y, xn.z, xn.w};
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb) {
-        int j = 16 * qb + (lane & 15);
-        if (j < ti.nqt) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            int64_t row = rowc + r;
-            if (row < ti.real_end) {
-              float d2 = fmaxf(qn[qb] + xr[r] - 2.0f * acc[qb][r], 0.0f);
-              append_key(keys, cnt, thr, j, cap, make_key(d2, static_cast<uint32_t>(row)));
-            }
-          }
-        }
-      }
-      __syncthreads();
-      for (int j = wave; j < ti.nqt; j += kWaves)
-        if (cnt[j] > cap - 64) compact_list(keys, cnt, thr, j, cap, kprime, lane);
-      __syncthreads();
+    // The A operand of the wave's 16 rows in the next 64-row block is loaded
+    // while the current block is processed (ping-pong registers, no copies),
+    // so one block of global loads is always in flight; the barriers wait on
+    // LDS only.  Loads are issued in the order they are consumed because the
+    // hardware's load counter retires in order.
+    // Chunks hold an even number of 64-row blocks (leaves are padded to 128
+    // rows), so both halves of the unrolled body always run.
+    bf16x8 a0[KS], a1[KS];
+    load_rows<KS>(s.x16, ti.r0, wave, lane, m, a0);
+    for (int64_t base = ti.r0; base < ti.r1; base += 128) {
+      scan_block<KS, QB>(s, ti, base, a0, a1, true, qreg, qn, keys, cnt, thr, cap, kprime, wave, lane);
+      scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qreg, qn, keys, cnt, thr, cap, kprime, wave,
+                         lane);
     }
     finish_tile(keys, cnt, thr, t, MQ, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
     __syncthreads();
@@ -247,11 +287,11 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
 __global__ void __launch_bounds__(64) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
                                                     int kmax, int bf16, int PB, const uint64_t *__restrict__ cand) {
   extern __shared__ uint64_t smem[];
-  volatile uint64_t *buf = smem;                                                 // [PB]
-  volatile uint64_t *k32 = smem + PB;                                            // [PK]
+  uint64_t *buf = smem;                                                 // [PB]
+  uint64_t *k32 = smem + PB;                                            // [PK]
   const int PK = pow2_at_least(kprime < 2 ? 2 : kprime);
-  volatile double *d64 = reinterpret_cast<volatile double *>(smem + PB + PK);   // [PK]
-  volatile uint32_t *r64 = reinterpret_cast<volatile uint32_t *>(d64 + PK);      // [PK]
+  double *d64 = reinterpret_cast<double *>(smem + PB + PK);   // [PK]
+  uint32_t *r64 = reinterpret_cast<uint32_t *>(d64 + PK);      // [PK]
   const int lane = threadIdx.x;
   const int m = s.m;
   const int n_items = static_cast<int>(b.ctl[kCtlItems]);

@@ -108,6 +108,11 @@ void launch_worklist(int64_t nq, int N, const float *lb, const int32_t *order, c
                      const int32_t *filt_of_leaf, const float *offsets, const int32_t *leaf_n, int want,
                      RoundBufs b, hipStream_t st);
 
+// (query, filter) pairs whose filter test a later round can reach, grouped
+// by filter into plist [F, nq] with counts pcnt [F] (zeroed by the caller).
+void launch_filter_pairs(int64_t nq, int N, const float *lb, const int32_t *order, const int32_t *filt_of_leaf,
+                         RoundBufs b, int32_t *plist, int32_t *pcnt, hipStream_t st);
+
 // Emit pairs from the fallback list instead.
 void launch_emit_fallback(int64_t n_fb, int N, RoundBufs b, hipStream_t st);
 
@@ -149,6 +154,10 @@ void launch_items_to_leaf_knn(int64_t n_items, int N, int k, int kmax, const int
 
 // d^f for every (query, filter): out [nq, F].
 void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, hipStream_t st);
+
+// d^f for listed pairs only (filter f: queries plist[f * stride + 0 .. pcnt[f])).
+void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int32_t *plist,
+                            const int32_t *pcnt, int64_t stride, float *out, hipStream_t st);
 
 // Per-query offset row lookup for (k, target) pairs.
 // k is clamped to [1, kmax].
