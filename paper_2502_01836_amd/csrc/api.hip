@@ -259,8 +259,9 @@ void prep_queries(leafi_index *ix, const float *raw, int64_t nq, hipStream_t st)
   launch_order(w.lb.get(), nq, ix->N, w.order.get(), st);
 }
 
-// Scan work-groups resident per CU (the persistent grid is num_cus times this).
-constexpr int kScanBlocksPerCU = 4;
+// Upper bound of scan work-groups per CU; the launch clamps the persistent
+// grid to what can be resident at once.
+constexpr int kScanBlocksPerCU = 8;
 // Device bytes above which a round's item buffers are sized from the actual
 // counts (one host read-back) instead of from an upper bound.
 constexpr double kPreallocLimit = 1.0 * (1 << 30);

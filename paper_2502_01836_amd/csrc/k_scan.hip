@@ -117,7 +117,7 @@ __device__ __forceinline__ void load_rows(const uint16_t *x16, int64_t base, int
 // `nxt`, MFMAs on `cur`, candidate appends, then list maintenance.
 template <int KS, int QB>
 __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &ti, int64_t base, bf16x8 (&cur)[KS],
-                                           bf16x8 (&nxt)[KS], bool more, const bf16x8 (&qreg)[QB][KS],
+                                           bf16x8 (&nxt)[KS], bool more, const uint16_t *qs, int qstride,
                                            const float (&qn)[QB], uint64_t *keys, int *cnt, uint64_t *thr, int cap,
                                            int kprime, int wave, int lane) {
   constexpr int kWaves = 4;
@@ -130,11 +130,15 @@ __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &t
   floatx4 acc[QB];
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) acc[qb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  // B operand from LDS: lane l reads query 16 qb + (l & 15), same k-chunk as A
+  const uint16_t *qb0 = qs + (lane & 15) * qstride + 8 * (lane >> 4);
 #pragma unroll
   for (int k = 0; k < KS; ++k)
 #pragma unroll
-    for (int qb = 0; qb < QB; ++qb)
-      acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur[k], qreg[qb][k], acc[qb], 0, 0, 0);
+    for (int qb = 0; qb < QB; ++qb) {
+      const bf16x8 bq = *reinterpret_cast<const bf16x8 *>(qb0 + 16 * qb * qstride + 32 * k);
+      acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur[k], bq, acc[qb], 0, 0, 0);
+    }
   // epilogue: lane holds rows rowc..rowc+3 for query column (lane & 15)
   const float xr[4] = {xn.x, xn.y, xn.z, xn.w};
 #pragma unroll
@@ -169,6 +173,7 @@ __global__ void __launch_bounds__(256) k_scan_bf16(StoreView s, QueryView qv, Ro
   uint64_t *keys = smem;
   uint64_t *thr = keys + MQ * cap;
   int *cnt = reinterpret_cast<int *>(thr + MQ);
+  uint16_t *qs = reinterpret_cast<uint16_t *>(cnt + MQ);  // [MQ][m + 8], 16-byte aligned
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int m = s.m;
@@ -180,22 +185,20 @@ __global__ void __launch_bounds__(256) k_scan_bf16(StoreView s, QueryView qv, Ro
       thr[threadIdx.x] = kKeyMax;
     }
     // B operand: this lane's query column and k-chunk, all K steps
-    bf16x8 qreg[QB][KS];
+    // The group's bf16 queries go to LDS (row stride m + 8 elements, so the 16
+    // rows one MFMA reads start in different banks); they are the B operand.
+    const int qstride = m + 8;
+    for (int e = threadIdx.x; e < MQ * (m / 8); e += blockDim.x) {
+      const int j = e / (m / 8), c = e - j * (m / 8);
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (j < ti.nqt) v = *reinterpret_cast<const uint4 *>(qv.q16 + static_cast<int64_t>(b.item_q[ti.p0 + j]) * m + 8 * c);
+      *reinterpret_cast<uint4 *>(qs + j * qstride + 8 * c) = v;
+    }
     float qn[QB];
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-      int j = 16 * qb + (lane & 15);
-      if (j < ti.nqt) {
-        int64_t qi = b.item_q[ti.p0 + j];
-        const uint16_t *qp = qv.q16 + qi * m + 8 * (lane >> 4);
-#pragma unroll
-        for (int k = 0; k < KS; ++k) qreg[qb][k] = *reinterpret_cast<const bf16x8 *>(qp + 32 * k);
-        qn[qb] = qv.qn16[qi];
-      } else {
-#pragma unroll
-        for (int k = 0; k < KS; ++k) qreg[qb][k] = bf16x8{};
-        qn[qb] = 0.0f;
-      }
+      const int j = 16 * qb + (lane & 15);
+      qn[qb] = j < ti.nqt ? qv.qn16[b.item_q[ti.p0 + j]] : 0.0f;
     }
     __syncthreads();
     // The A operand of the wave's 16 rows in the next 64-row block is loaded
@@ -208,9 +211,9 @@ __global__ void __launch_bounds__(256) k_scan_bf16(StoreView s, QueryView qv, Ro
     bf16x8 a0[KS], a1[KS];
     load_rows<KS>(s.x16, ti.r0, wave, lane, m, a0);
     for (int64_t base = ti.r0; base < ti.r1; base += 128) {
-      scan_block<KS, QB>(s, ti, base, a0, a1, true, qreg, qn, keys, cnt, thr, cap, kprime, wave, lane);
-      scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qreg, qn, keys, cnt, thr, cap, kprime, wave,
-                         lane);
+      scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kprime, wave, lane);
+      scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qs, qstride, qn, keys, cnt, thr, cap, kprime,
+                         wave, lane);
     }
     finish_tile(keys, cnt, thr, t, MQ, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
     __syncthreads();
@@ -398,14 +401,32 @@ __global__ void __launch_bounds__(64) k_item_rerank(StoreView s, QueryView qv, R
   }
 }
 
+// Work-groups that can be resident at once for `kern` with `lds` bytes of
+// LDS, capped at `want`.  A persistent grid larger than this would leave a
+// tail of work-groups that only start after the first ones have finished.
+template <typename K>
+int resident_grid(K kern, size_t lds, int want) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  int per_cu = 0;
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), 256, lds));
+  int g = cus * (per_cu > 0 ? per_cu : 1);
+  return want < g ? (want > 0 ? want : 1) : g;
+}
+
 template <int KS, int QB>
 void scan_bf16_inst(StoreView s, QueryView q, RoundBufs b, int kprime, int cap, uint64_t *cand, int grid,
                     hipStream_t st) {
   constexpr int MQ = 16 * QB;
-  size_t lds = static_cast<size_t>(MQ) * cap * 8 + MQ * 8 + MQ * 4;
+  size_t lds = static_cast<size_t>(MQ) * cap * 8 + MQ * 8 + MQ * 4 + static_cast<size_t>(MQ) * (32 * KS + 8) * 2;
   auto kern = k_scan_bf16<KS, QB>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  grid = resident_grid(kern, lds, grid);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, s, q, b, kprime, cap, cand);
   LAUNCH_OK("scan_bf16");
 }
@@ -433,6 +454,7 @@ void scan_fp32_inst(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, i
   auto kern = k_scan_fp32<EPL>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  grid = resident_grid(kern, lds, grid);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, s, q, b, mq, kprime, cap, cand);
   LAUNCH_OK("scan_fp32");
 }
