@@ -133,14 +133,17 @@ __global__ void __launch_bounds__(256) k_znorm(const float *x, int64_t n, int m,
   for (int t = lane; t < m; t += kWave) out[row * m + t] = vals[c++];
 }
 
+// Raw row i is written to output row slots[i] (i when slots is null).
 __global__ void __launch_bounds__(256) k_qprep(const float *__restrict__ raw, int64_t nq, int m, int S, float *q32,
-                                               uint16_t *q16, float *qn16, float *qeps, float *qstat) {
+                                               uint16_t *q16, float *qn16, float *qeps, float *qstat,
+                                               const int32_t *__restrict__ slots) {
   __shared__ float zs[kRowsPerBlock][kMaxM];
   int lane = threadIdx.x & (kWave - 1);
   int w = threadIdx.x / kWave;
-  int64_t row = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + w;
-  if (row >= nq) return;
-  const float *r = raw + row * m;
+  int64_t i = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + w;
+  if (i >= nq) return;
+  const float *r = raw + i * m;
+  const int64_t row = slots ? slots[i] : i;
   double mu, sd;
   row_moments(r, m, lane, mu, sd);
   float nrm = 0.0f, err = 0.0f;
@@ -172,11 +175,13 @@ __global__ void __launch_bounds__(256) k_qprep(const float *__restrict__ raw, in
 
 // d^lb(q, L)^2 = sum_s l_s [gap(mu_q, [mu_lo, mu_hi])^2 + gap(sd_q, [sd_lo, sd_hi])^2].
 __global__ void __launch_bounds__(256) k_lb(const float *__restrict__ qstat, int64_t nq,
-                                            const float *__restrict__ boxes, int N, int S, int m, float *lb) {
+                                            const float *__restrict__ boxes, int N, int S, int m, float *lb,
+                                            const int32_t *__restrict__ slots) {
   int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= nq * N) return;
-  int64_t q = idx / N;
-  int L = static_cast<int>(idx - q * N);
+  int64_t i = idx / N;
+  int L = static_cast<int>(idx - i * N);
+  const int64_t q = slots ? slots[i] : i;
   const float *qs = qstat + q * S * 2;
   const float *bx = boxes + static_cast<int64_t>(L) * S * 4;
   float acc = 0.0f;
@@ -187,13 +192,14 @@ __global__ void __launch_bounds__(256) k_lb(const float *__restrict__ qstat, int
     float gs = fmaxf(fmaxf(bx[4 * s + 2] - sq, sq - bx[4 * s + 3]), 0.0f);
     acc += len * (gm * gm + gs * gs);
   }
-  lb[idx] = sqrtf(acc);
+  lb[q * N + L] = sqrtf(acc);
 }
 
 // One work-group per query: bitonic sort of (lb bits, leaf id) keys in LDS.
-__global__ void __launch_bounds__(256) k_order(const float *__restrict__ lb, int N, int P, int32_t *order) {
+__global__ void __launch_bounds__(256) k_order(const float *__restrict__ lb, int N, int P, int32_t *order,
+                                               const int32_t *__restrict__ slots) {
   extern __shared__ uint64_t keys[];
-  int64_t q = blockIdx.x;
+  const int64_t q = slots ? slots[blockIdx.x] : static_cast<int64_t>(blockIdx.x);
   for (int i = threadIdx.x; i < P; i += blockDim.x)
     keys[i] = i < N ? make_key(lb[q * N + i], static_cast<uint32_t>(i)) : kKeyMax;
   __syncthreads();
@@ -253,22 +259,23 @@ void launch_znorm(const float *x, int64_t n, int m, float *out, hipStream_t st) 
 }
 
 void launch_qprep(const float *raw, int64_t nq, int m, int S, float *q32, uint16_t *q16, float *qn16, float *qeps,
-                  float *qstat, hipStream_t st) {
+                  float *qstat, hipStream_t st, const int32_t *slots) {
   int64_t blocks = ceil_div(nq, kRowsPerBlock);
-  hipLaunchKernelGGL(k_qprep, dim3(blocks), dim3(256), 0, st, raw, nq, m, S, q32, q16, qn16, qeps, qstat);
+  hipLaunchKernelGGL(k_qprep, dim3(blocks), dim3(256), 0, st, raw, nq, m, S, q32, q16, qn16, qeps, qstat, slots);
   LAUNCH_OK("qprep");
 }
 
-void launch_lb(const float *qstat, int64_t nq, const float *boxes, int N, int S, int m, float *lb, hipStream_t st) {
+void launch_lb(const float *qstat, int64_t nq, const float *boxes, int N, int S, int m, float *lb, hipStream_t st,
+               const int32_t *slots) {
   int64_t total = nq * N;
-  hipLaunchKernelGGL(k_lb, dim3(ceil_div(total, 256)), dim3(256), 0, st, qstat, nq, boxes, N, S, m, lb);
+  hipLaunchKernelGGL(k_lb, dim3(ceil_div(total, 256)), dim3(256), 0, st, qstat, nq, boxes, N, S, m, lb, slots);
   LAUNCH_OK("lb");
 }
 
-void launch_order(const float *lb, int64_t nq, int N, int32_t *order, hipStream_t st) {
+void launch_order(const float *lb, int64_t nq, int N, int32_t *order, hipStream_t st, const int32_t *slots) {
   int P = pow2_at_least(N < 2 ? 2 : N);
   size_t lds = static_cast<size_t>(P) * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_order, dim3(nq), dim3(256), lds, st, lb, N, P, order);
+  hipLaunchKernelGGL(k_order, dim3(nq), dim3(256), lds, st, lb, N, P, order, slots);
   LAUNCH_OK("order");
 }
 

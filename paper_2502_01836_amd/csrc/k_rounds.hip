@@ -20,11 +20,17 @@ __global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float
                                                   const int32_t *__restrict__ order, const float *__restrict__ dfilt,
                                                   int F, const int32_t *__restrict__ filt_of_leaf,
                                                   const float *__restrict__ offsets, const int32_t *__restrict__ leaf_n,
-                                                  int want, RoundBufs b) {
+                                                  int want, Schedule sched, int32_t *qround, RoundBufs b) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (q >= nq) return;  // whole wavefront
   int pos = b.cursor[q];
+  if (qround && pos < N) {
+    // serving: each query follows its own schedule from its own round count
+    const int r = qround[q];
+    want = sched.r[r < sched.n ? r : sched.n - 1];
+    if (lane == 0) qround[q] = r + 1;
+  }
   int cnt = 0;
   int64_t lbp = 0, fp = 0, series = 0;
   if (pos < N) {
@@ -103,11 +109,13 @@ __global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float
 __global__ void __launch_bounds__(256) k_filter_pairs(int64_t nq, int N, const float *__restrict__ lb,
                                                       const int32_t *__restrict__ order,
                                                       const int32_t *__restrict__ filt_of_leaf, RoundBufs b,
-                                                      int32_t *plist, int32_t *pcnt) {
+                                                      const int32_t *__restrict__ qround, int32_t *plist,
+                                                      int32_t *pcnt) {
   int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= nq * N) return;
   int64_t q = idx / N;
   int pos = static_cast<int>(idx - q * N);
+  if (qround && qround[q] != 1) return;  // serving: only queries that just finished their first round
   if (pos < b.cursor[q] || b.pair[q] < 0) return;
   int L = order[q * N + pos];
   int f = filt_of_leaf[L];
@@ -303,11 +311,12 @@ __global__ void __launch_bounds__(256) k_select_pairs(int64_t nq, const int32_t 
                                                       const float *__restrict__ t_dev, int n_pairs,
                                                       const int32_t *__restrict__ pair_k,
                                                       const float *__restrict__ pair_t, int kmax, int32_t *pair,
-                                                      int32_t *kq) {
-  int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
-  int k = min(max(k_dev[q], 1), kmax);
-  float t = t_dev[q];
+                                                      int32_t *kq, const int32_t *__restrict__ slots) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const int64_t q = slots ? slots[i] : i;
+  int k = min(max(k_dev[i], 1), kmax);
+  float t = t_dev[i];
   int p = -1;
   if (t < 1.0f)
     for (int i = 0; i < n_pairs; ++i)
@@ -319,20 +328,46 @@ __global__ void __launch_bounds__(256) k_select_pairs(int64_t nq, const int32_t 
   kq[q] = k;
 }
 
+// Serving: retire every active slot whose search has ended (cursor past the
+// last leaf): copy its ids and distances to the compact done list.
+__global__ void __launch_bounds__(256) k_collect_done(int64_t n_slots, int N, int kmax,
+                                                      const int64_t *__restrict__ rowid, RoundBufs b, int32_t *state,
+                                                      int32_t *done_slot, int64_t *done_ids, float *done_d,
+                                                      int32_t *n_done) {
+  int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n_slots || state[q] != 1 || b.cursor[q] < N) return;
+  state[q] = 2;
+  int j = atomicAdd(n_done, 1);
+  done_slot[j] = static_cast<int32_t>(q);
+  int c = b.res_cnt[q];
+  for (int i = 0; i < kmax; ++i) {
+    int64_t o = static_cast<int64_t>(j) * kmax + i;
+    if (i < c) {
+      done_ids[o] = rowid[b.res_row[q * kmax + i]];
+      done_d[o] = static_cast<float>(sqrt(b.res_d2[q * kmax + i]));
+    } else {
+      done_ids[o] = -1;
+      done_d[o] = __builtin_inff();
+    }
+  }
+}
+
 }  // namespace
 
 void launch_worklist(int64_t nq, int N, const float *lb, const int32_t *order, const float *dfilt, int F,
                      const int32_t *filt_of_leaf, const float *offsets, const int32_t *leaf_n, int want,
-                     RoundBufs b, hipStream_t st) {
+                     RoundBufs b, hipStream_t st, const Schedule *sched, int32_t *qround) {
+  Schedule sc{};
+  if (sched) sc = *sched;
   hipLaunchKernelGGL(k_worklist, dim3(ceil_div(nq, 4)), dim3(256), 0, st, nq, N, lb, order, dfilt, F, filt_of_leaf,
-                     offsets, leaf_n, want, b);
+                     offsets, leaf_n, want, sc, qround, b);
   LAUNCH_OK("worklist");
 }
 
 void launch_filter_pairs(int64_t nq, int N, const float *lb, const int32_t *order, const int32_t *filt_of_leaf,
-                         RoundBufs b, int32_t *plist, int32_t *pcnt, hipStream_t st) {
+                         RoundBufs b, int32_t *plist, int32_t *pcnt, hipStream_t st, const int32_t *qround) {
   hipLaunchKernelGGL(k_filter_pairs, dim3(ceil_div(nq * N, 256)), dim3(256), 0, st, nq, N, lb, order, filt_of_leaf, b,
-                     plist, pcnt);
+                     qround, plist, pcnt);
   LAUNCH_OK("filter_pairs");
 }
 
@@ -376,10 +411,21 @@ void launch_items_to_leaf_knn(int64_t n_items, int N, int k, int kmax, const int
 }
 
 void launch_select_pairs(int64_t nq, const int32_t *k_dev, const float *t_dev, int n_pairs, const int32_t *pair_k,
-                         const float *pair_t, int kmax, int32_t *pair, int32_t *kq, hipStream_t st) {
+                         const float *pair_t, int kmax, int32_t *pair, int32_t *kq, hipStream_t st,
+                         const int32_t *slots) {
   hipLaunchKernelGGL(k_select_pairs, dim3(ceil_div(nq, 256)), dim3(256), 0, st, nq, k_dev, t_dev, n_pairs, pair_k,
-                     pair_t, kmax, pair, kq);
+                     pair_t, kmax, pair, kq, slots);
   LAUNCH_OK("select_pairs");
 }
 
+}  // namespace leafi
+
+namespace leafi {
+void launch_collect_done(int64_t n_slots, int N, int kmax, const int64_t *rowid, RoundBufs b, int32_t *state,
+                         int32_t *done_slot, int64_t *done_ids, float *done_d, int32_t *n_done, hipStream_t st) {
+  if (n_slots <= 0) return;
+  hipLaunchKernelGGL(k_collect_done, dim3(ceil_div(n_slots, 256)), dim3(256), 0, st, n_slots, N, kmax, rowid, b,
+                     state, done_slot, done_ids, done_d, n_done);
+  LAUNCH_OK("collect_done");
+}
 }  // namespace leafi

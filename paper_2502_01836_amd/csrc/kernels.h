@@ -24,15 +24,18 @@ void launch_pack(const float *raw, const int64_t *src_of_row, const int32_t *lea
 void launch_znorm(const float *x, int64_t n, int m, float *out, hipStream_t st);
 
 // Query preparation: normalised fp32 and bf16 rows, ||q~||^2, ||q - q~||, and
-// per-segment (mean, std) pairs qstat [nq, S, 2].
+// per-segment (mean, std) pairs qstat [., S, 2].  With `slots`, raw row i
+// goes to output row slots[i] (the serving engine's per-query slots).
 void launch_qprep(const float *raw, int64_t nq, int m, int S, float *q32, uint16_t *q16, float *qn16, float *qeps,
-                  float *qstat, hipStream_t st);
+                  float *qstat, hipStream_t st, const int32_t *slots = nullptr);
 
-// Summary lower bounds lb [nq, N].
-void launch_lb(const float *qstat, int64_t nq, const float *boxes, int N, int S, int m, float *lb, hipStream_t st);
+// Summary lower bounds lb [., N] for rows i (or slots[i]).
+void launch_lb(const float *qstat, int64_t nq, const float *boxes, int N, int S, int m, float *lb, hipStream_t st,
+               const int32_t *slots = nullptr);
 
 // Visit order: per query, leaves sorted by (lb, leaf id).
-void launch_order(const float *lb, int64_t nq, int N, int32_t *order, hipStream_t st);
+void launch_order(const float *lb, int64_t nq, int N, int32_t *order, hipStream_t st,
+                  const int32_t *slots = nullptr);
 
 // Training queries: q_j = x32[row_j] + sigma_j * N(0, 1) noise from a
 // counter-based generator keyed by (seed, j, t).
@@ -102,16 +105,29 @@ struct QueryView {
   const float *qeps;
 };
 
+// Round schedule: leaves per query in round r = r_[min(r, n - 1)] (0 = all survivors).
+struct Schedule {
+  int n;
+  int r[8];
+};
+
 // Emit this round's (query, leaf) pairs from the visit order (Algorithm 2's
-// prune cascade).  want = leaves per query this round (0 = all survivors).
+// prune cascade).  want = leaves per query this round (0 = all survivors);
+// with qround (serving), each query instead takes sched.r at its own round
+// count, which the kernel advances.
 void launch_worklist(int64_t nq, int N, const float *lb, const int32_t *order, const float *dfilt, int F,
                      const int32_t *filt_of_leaf, const float *offsets, const int32_t *leaf_n, int want,
-                     RoundBufs b, hipStream_t st);
+                     RoundBufs b, hipStream_t st, const Schedule *sched = nullptr, int32_t *qround = nullptr);
 
 // (query, filter) pairs whose filter test a later round can reach, grouped
 // by filter into plist [F, nq] with counts pcnt [F] (zeroed by the caller).
 void launch_filter_pairs(int64_t nq, int N, const float *lb, const int32_t *order, const int32_t *filt_of_leaf,
-                         RoundBufs b, int32_t *plist, int32_t *pcnt, hipStream_t st);
+                         RoundBufs b, int32_t *plist, int32_t *pcnt, hipStream_t st,
+                         const int32_t *qround = nullptr);
+
+// Serving: retire finished active slots (state 1 -> 2) into a compact done list.
+void launch_collect_done(int64_t n_slots, int N, int kmax, const int64_t *rowid, RoundBufs b, int32_t *state,
+                         int32_t *done_slot, int64_t *done_ids, float *done_d, int32_t *n_done, hipStream_t st);
 
 // Emit pairs from the fallback list instead.
 void launch_emit_fallback(int64_t n_fb, int N, RoundBufs b, hipStream_t st);
@@ -162,7 +178,8 @@ void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x,
 // Per-query offset row lookup for (k, target) pairs.
 // k is clamped to [1, kmax].
 void launch_select_pairs(int64_t nq, const int32_t *k_dev, const float *t_dev, int n_pairs, const int32_t *pair_k,
-                         const float *pair_t, int kmax, int32_t *pair, int32_t *kq, hipStream_t st);
+                         const float *pair_t, int kmax, int32_t *pair, int32_t *kq, hipStream_t st,
+                         const int32_t *slots = nullptr);
 
 struct TrainArgs {
   float *w;              // [F, P] weights (updated)
