@@ -258,6 +258,76 @@ int leafi_search_knn(leafi_index *index, const float *queries_dev, int64_t nq, c
                      float *dists_dev, leafi_search_stats *stats, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Serving: continuous batching of k-NN requests (Algorithm 2 for a stream of
+ * queries with mixed k and recall targets)
+ *
+ * A server keeps the index, filters and offsets resident and runs engine
+ * rounds on its own HIP stream from a worker thread.  Every admitted request
+ * owns a slot of per-query device state; a round prepares the requests
+ * admitted since the previous round, advances every active request by one
+ * round of its own schedule (requests are grouped by surviving leaf across
+ * the whole mix for the leaf scan) and retires finished requests, freeing
+ * their slots.  A request's result does not depend on which other requests
+ * shared its rounds.  Admission is by memory: the number of slots is
+ * max_slots, or fewer if mem_budget cannot hold that many slots' state.
+ * While a server exists, its index must not be used by any other call.
+ * ---------------------------------------------------------------------- */
+
+typedef struct leafi_server leafi_server;
+
+typedef struct {
+  int32_t max_slots;      /* requests on the GPU at once (0 = as many as mem_budget holds) */
+  int32_t k_max;          /* largest k of any request, 1..256 (k is clamped to it) */
+  int32_t scan;           /* LEAFI_SCAN_BF16 or LEAFI_SCAN_FP32 */
+  int32_t use_filters;
+  int32_t n_schedule;     /* per-request round schedule, as in leafi_search_opts */
+  int32_t schedule[8];
+  int32_t queue_capacity; /* requests waiting for a slot before submit returns LEAFI_EAGAIN */
+  int64_t mem_budget;     /* device bytes for per-slot state (0 = unlimited) */
+  int32_t reserved[4];
+} leafi_server_opts;
+
+typedef struct {
+  int64_t completed;      /* requests finished during the replay */
+  int64_t rounds;         /* engine rounds run during the replay */
+  double wall_s;          /* first arrival to last completion */
+  double mean_active;     /* mean requests per round */
+  int32_t max_active;
+  int32_t reserved;
+} leafi_server_report;
+
+/* Defaults: 1024 slots, k_max 1, BF16 scan, filters on, schedule {1, 0},
+ * queue capacity 2^20, mem_budget 4 GiB. */
+void leafi_default_server_opts(leafi_server_opts *opts);
+
+/* Start a server on a built index (calibrated if it should use filters). */
+int leafi_server_create(leafi_index *index, const leafi_server_opts *opts, leafi_server **out);
+
+/* Stop the worker after it has finished every submitted request; release all. */
+void leafi_server_destroy(leafi_server *server);
+
+/* Number of slots the server admitted (after the memory budget). */
+int leafi_server_info(const leafi_server *server, int32_t *max_slots);
+
+/* Queue one raw query (query_host [m]) with its k and recall target; returns
+ * a ticket.  LEAFI_EAGAIN when queue_capacity requests are already waiting. */
+int leafi_server_submit(leafi_server *server, const float *query_host, int32_t k, float target, uint64_t *ticket);
+
+/* done = 1 once the request has finished; then ids_host / dists_host [k_max]
+ * (either may be NULL) receive its result, latency_ms (nullable) the time from
+ * submission to completion, and the ticket is released. */
+int leafi_server_poll(leafi_server *server, uint64_t ticket, int64_t *ids_host, float *dists_host,
+                      double *latency_ms, int32_t *done);
+
+/* Replay an arrival trace: query i (queries_host [n, m]) is submitted at
+ * arrival_s[i] seconds after the call starts (a full queue delays it); waits
+ * for every result.  Outputs ids_host / dists_host [n, k_max] and latency_ms
+ * [n] (scheduled arrival to completion).  `report` may be NULL. */
+int leafi_server_replay(leafi_server *server, const float *queries_host, int64_t n, const double *arrival_s,
+                        const int32_t *ks, const float *targets, int64_t *ids_host, float *dists_host,
+                        double *latency_ms, leafi_server_report *report);
+
+/* ------------------------------------------------------------------------
  * Building blocks, exposed for checking and for callers that compose them
  * ---------------------------------------------------------------------- */
 

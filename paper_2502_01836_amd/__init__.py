@@ -13,7 +13,7 @@ import numpy as np
 from . import _lib
 from ._lib import LeafiError, check, load, struct_dict
 
-__all__ = ["Index", "LeafiError", "load", "znorm", "mlp_infer", "mlp_sgd_step", "version"]
+__all__ = ["Index", "Server", "LeafiError", "load", "znorm", "mlp_infer", "mlp_sgd_step", "version"]
 
 
 def _torch():
@@ -197,6 +197,85 @@ class Index:
         check(load().leafi_leaf_knn(self._h, _dev(queries, torch.float32, "queries"), nq, k,
                                     _dev(d, torch.float32, "d"), _dev(ids, torch.int64, "ids"), _stream()))
         return d, ids
+
+
+class Server:
+    """Continuous-batching request server over a built (and calibrated) Index.
+
+    The index must not be used by other calls while the server exists.
+    Queries are host arrays (numpy fp32 [m] or [n, m]).
+    """
+
+    def __init__(self, index: Index, k_max: int = 1, max_slots: int = 1024, scan: str = "bf16",
+                 use_filters: bool = True, schedule=(1, 0), queue_capacity: int = 1 << 20,
+                 mem_budget: int = 4 << 30):
+        lib = load()
+        o = _lib.ServerOpts()
+        lib.leafi_default_server_opts(ctypes.byref(o))
+        o.max_slots = max_slots
+        o.k_max = k_max
+        o.scan = {"bf16": _lib.LEAFI_SCAN_BF16, "fp32": _lib.LEAFI_SCAN_FP32}[scan]
+        o.use_filters = 1 if use_filters else 0
+        o.n_schedule = len(schedule)
+        for i, v in enumerate(schedule):
+            o.schedule[i] = v
+        o.queue_capacity = queue_capacity
+        o.mem_budget = mem_budget
+        h = ctypes.c_void_p()
+        check(lib.leafi_server_create(index._h, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._index = index  # keeps the index alive
+        self.k_max = k_max
+        self.m = index.info()["m"]
+
+    @property
+    def slots(self) -> int:
+        n = ctypes.c_int32()
+        check(load().leafi_server_info(self._h, ctypes.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().leafi_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, query, k: int = 1, target: float = 1.0) -> int:
+        q = np.ascontiguousarray(query, dtype=np.float32)
+        t = ctypes.c_uint64()
+        check(load().leafi_server_submit(self._h, q.ctypes.data_as(ctypes.c_void_p), k, target, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """Returns None while running, else (ids [k_max], dists [k_max], latency_ms)."""
+        ids = np.empty(self.k_max, dtype=np.int64)
+        d = np.empty(self.k_max, dtype=np.float32)
+        lat = ctypes.c_double()
+        done = ctypes.c_int32()
+        check(load().leafi_server_poll(self._h, ticket, ids.ctypes.data_as(ctypes.c_void_p),
+                                       d.ctypes.data_as(ctypes.c_void_p), ctypes.byref(lat), ctypes.byref(done)))
+        return (ids, d, lat.value) if done.value else None
+
+    def replay(self, queries, arrival_s, ks, targets):
+        q = np.ascontiguousarray(queries, dtype=np.float32)
+        n = q.shape[0]
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        k = np.ascontiguousarray(np.broadcast_to(ks, (n,)), dtype=np.int32)
+        t = np.ascontiguousarray(np.broadcast_to(targets, (n,)), dtype=np.float32)
+        ids = np.empty((n, self.k_max), dtype=np.int64)
+        d = np.empty((n, self.k_max), dtype=np.float32)
+        lat = np.empty(n, dtype=np.float64)
+        rep = _lib.ServerReport()
+        P = ctypes.c_void_p
+        check(load().leafi_server_replay(self._h, q.ctypes.data_as(P), n, arr.ctypes.data_as(P),
+                                         k.ctypes.data_as(P), t.ctypes.data_as(P), ids.ctypes.data_as(P),
+                                         d.ctypes.data_as(P), lat.ctypes.data_as(P), ctypes.byref(rep)))
+        return ids, d, lat, struct_dict(rep)
 
 
 def znorm(x):

@@ -68,6 +68,17 @@ class SearchStats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_scan", ctypes.c_double), ("scan_bytes", ctypes.c_double)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("k_max", ctypes.c_int32), ("scan", ctypes.c_int32),
+                ("use_filters", ctypes.c_int32), ("n_schedule", ctypes.c_int32), ("schedule", ctypes.c_int32 * 8),
+                ("queue_capacity", ctypes.c_int32), ("mem_budget", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4)]
+
+
+class ServerReport(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("rounds", ctypes.c_int64), ("wall_s", ctypes.c_double),
+                ("mean_active", ctypes.c_double), ("max_active", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 def struct_dict(s) -> dict:
     out = {}
     for name, _ in s._fields_:
@@ -102,6 +113,14 @@ SIGNATURES = [
     ("leafi_default_search_opts", None, [ctypes.POINTER(SearchOpts)]),
     ("leafi_search_knn", ctypes.c_int, [P, P, I64, P, P, ctypes.POINTER(SearchOpts), P, P,
                                         ctypes.POINTER(SearchStats), P]),
+    ("leafi_default_server_opts", None, [ctypes.POINTER(ServerOpts)]),
+    ("leafi_server_create", ctypes.c_int, [P, ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]),
+    ("leafi_server_destroy", None, [P]),
+    ("leafi_server_info", ctypes.c_int, [P, ctypes.POINTER(I32)]),
+    ("leafi_server_submit", ctypes.c_int, [P, P, I32, F32, ctypes.POINTER(ctypes.c_uint64)]),
+    ("leafi_server_poll", ctypes.c_int, [P, ctypes.c_uint64, P, P, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(I32)]),
+    ("leafi_server_replay", ctypes.c_int, [P, P, I64, P, P, P, P, P, P, ctypes.POINTER(ServerReport)]),
     ("leafi_znorm", ctypes.c_int, [P, I64, I32, P, P]),
     ("leafi_lower_bounds", ctypes.c_int, [P, P, I64, P, P]),
     ("leafi_mlp_infer", ctypes.c_int, [P, I32, I32, I32, P, I64, P, P]),

@@ -9,7 +9,7 @@
 #include <random>
 #include <string>
 
-#include "index.h"
+#include "engine.h"
 
 using namespace leafi;
 
@@ -18,44 +18,13 @@ leafi_index::~leafi_index() {
   if (ws.ev1) (void)hipEventDestroy(ws.ev1);
 }
 
-namespace {
+namespace leafi {
 
 thread_local std::string g_last_error;
-
-template <typename Fn>
-int guarded(Fn &&fn) {
-  try {
-    fn();
-    return LEAFI_OK;
-  } catch (const Error &e) {
-    g_last_error = e.what();
-    return e.code;
-  } catch (const std::bad_alloc &) {
-    g_last_error = "host allocation failed";
-    return LEAFI_ENOMEM;
-  } catch (const std::exception &e) {
-    g_last_error = e.what();
-    return LEAFI_EINTERNAL;
-  } catch (...) {
-    g_last_error = "unknown failure";
-    return LEAFI_EINTERNAL;
-  }
-}
-
-inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 void require_built(const leafi_index *ix) {
   if (!ix) fail(LEAFI_EINVAL, "index handle is NULL");
   if (!ix->built) fail(LEAFI_ESTATE, "index not built (call leafi_build_index first)");
-}
-
-template <typename T>
-void h2d(T *dst, const T *src, size_t n, hipStream_t st) {
-  if (n) HIP_OK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, st));
-}
-template <typename T>
-void d2h(T *dst, const T *src, size_t n, hipStream_t st) {
-  if (n) HIP_OK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, st));
 }
 
 // ---- small kernels of the orchestration --------------------------------------
@@ -246,11 +215,6 @@ void reset_round_ctl(Workspace &w, hipStream_t st) {
   HIP_OK(hipMemsetAsync(w.ctl.get(), 0, 4 * sizeof(int64_t), st));
 }
 
-struct Timing {
-  double scan_ms = 0.0;
-  double scan_bytes = 0.0;
-};
-
 // Prepare nq raw queries: normalised copies, lower bounds and visit order.
 void prep_queries(leafi_index *ix, const float *raw, int64_t nq, hipStream_t st) {
   Workspace &w = ix->ws;
@@ -272,7 +236,7 @@ constexpr double kPreallocLimit = 1.0 * (1 << 30);
 // from it and nothing is read back.  Otherwise the counts are read back
 // first.  Returns the item count when it was read back, else -1.
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
-                   int64_t items_bound = -1) {
+                   int64_t items_bound) {
   Workspace &w = ix->ws;
   int mq, cap;
   scan_geometry(kprime, &mq, &cap);
@@ -490,7 +454,7 @@ void check_queries(const leafi_index *ix, const float *q, int64_t nq) {
   (void)ix;
 }
 
-}  // namespace
+}  // namespace leafi
 
 // =============================================================================
 // C ABI

@@ -1,0 +1,70 @@
+// Host orchestration helpers shared by the C ABI entry points (api.hip) and
+// the serving engine (serve.hip).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "index.h"
+
+namespace leafi {
+
+extern thread_local std::string g_last_error;
+
+// Run fn, turning exceptions into LEAFI_E* codes and the thread's message.
+template <typename Fn>
+int guarded(Fn &&fn) {
+  try {
+    fn();
+    return LEAFI_OK;
+  } catch (const Error &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return LEAFI_ENOMEM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return LEAFI_EINTERNAL;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return LEAFI_EINTERNAL;
+  }
+}
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <typename T>
+void h2d(T *dst, const T *src, size_t n, hipStream_t st) {
+  if (n) HIP_OK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, st));
+}
+template <typename T>
+void d2h(T *dst, const T *src, size_t n, hipStream_t st) {
+  if (n) HIP_OK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, st));
+}
+
+struct Timing {
+  double scan_ms = 0.0;
+  double scan_bytes = 0.0;
+};
+
+void require_built(const leafi_index *ix);
+void fill_f32(float *p, int64_t n, float v, hipStream_t st);
+void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+RoundBufs views(Workspace &w);
+StoreView store_view(const leafi_index *ix);
+QueryView query_view(Workspace &w);
+// Grow the per-query workspace for nq queries of up to kmax results.
+void ensure_queries(leafi_index *ix, int64_t nq, int kmax);
+void ensure_items(leafi_index *ix, int64_t items, int kmax);
+// Copy the control words to the host (synchronises the stream).
+void read_ctl(leafi_index *ix, hipStream_t st);
+// Zero the per-round control words (items, tiles, active, fallback).
+void reset_round_ctl(Workspace &w, hipStream_t st);
+// Lay out the round's items, scan and rerank them (see api.hip).
+int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
+                   int64_t items_bound = -1);
+void add_scan_time(leafi_index *ix, Timing *tm);
+int default_kprime(int kmax, bool bf16);
+
+}  // namespace leafi
