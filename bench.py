@@ -47,6 +47,11 @@ def main():
     ap.add_argument("--fp32-sample", type=int, default=200, help="queries timed on the plain FP32 path (0 = skip)")
     ap.add_argument("--schedule", default="1,0")
     ap.add_argument("--max-epochs", type=int, default=1000)
+    ap.add_argument("--serve-rates", default="50000,100000,200000,400000",
+                    help="offered request rates (per second) of the serving leg; empty = skip")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB device copy first (reference for hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU layout is a design "
@@ -71,7 +76,13 @@ def main():
     log(f"generated {n}x{m} in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
+    if a.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     raw_d = torch.from_numpy(raw).to(dev)
     ix = pkg.Index()
     t0 = time.time()
@@ -88,7 +99,10 @@ def main():
     log(f"trained {rep['n_filters']} filters in {t_train:.1f}s (th={rep['th']:.1f}, "
         f"epochs<={rep['epochs_max_run']}, val mse {rep['mean_val_mse']:.3f})")
     t0 = time.time()
-    ix.calibrate(torch.from_numpy(calib).to(dev), [wl["k"]], [wl["target"]])
+    # the measured configuration is (k = 1, target 0.99); the serving leg also
+    # uses k = 10 and targets 0.90 / 0.95
+    serve_ks, serve_targets = [1, 10], [0.90, 0.95, 0.99]
+    ix.calibrate(torch.from_numpy(calib).to(dev), serve_ks, serve_targets)
     torch.cuda.synchronize()
     t_cal = time.time() - t0
     log(f"calibrated in {t_cal:.1f}s")
@@ -166,6 +180,45 @@ def main():
         cpu = {"value": ns / dt, "unit": "queries/s", "cores": O.num_threads(), "kind": "oracle",
                "sample": f"{ns} queries of the sigma=0.1 batch, FP64 brute-force exact k-NN over all {n} series"}
 
+    # serving leg: Poisson arrivals of single requests with mixed k and targets
+    serving = []
+    rates = [float(r) for r in a.serve_rates.split(",") if r.strip()]
+    if rates:
+        pool = np.concatenate(tests)                       # 3,000 distinct queries
+        pool_d = torch.from_numpy(pool).to(dev)
+        kmax_s = max(serve_ks)
+        ex_ids, ex_d = ix.search(pool_d, k=kmax_s, k_max=kmax_s, use_filters=False, schedule=sched)
+        ex_d = ex_d.cpu().numpy().astype(np.float64)
+        del pool_d
+        sv = pkg.Server(ix, k_max=kmax_s, max_slots=4096, schedule=sched)
+        try:
+            rng = np.random.default_rng(5003)
+            for lam in rates:
+                nreq = int(min(lam * a.serve_seconds, 200_000))
+                pick = rng.integers(0, len(pool), nreq)
+                ks_r = rng.choice(serve_ks, nreq).astype(np.int32)
+                tg_r = rng.choice(serve_targets, nreq).astype(np.float32)
+                arr = np.cumsum(rng.exponential(1.0 / lam, nreq))
+                ids_r, d_r, lat_r, rep_r = sv.replay(pool[pick], arr, ks_r, tg_r)
+                rec = {}
+                for kk in serve_ks:
+                    for tt in serve_targets:
+                        sel = (ks_r == kk) & (tg_r == np.float32(tt))
+                        if sel.any():
+                            kth = ex_d[pick[sel], kk - 1]
+                            got = d_r[sel, :kk].astype(np.float64)
+                            hits = (got <= kth[:, None] * (1 + 1e-6)).sum(1) / kk
+                            rec[f"k{kk}_t{tt:.2f}"] = float(hits.mean())
+                serving.append({"offered_qps": lam, "requests": nreq,
+                                "achieved_qps": nreq / rep_r["wall_s"],
+                                "p50_ms": float(np.percentile(lat_r, 50)), "p99_ms": float(np.percentile(lat_r, 99)),
+                                "mean_active": rep_r["mean_active"], "max_active": rep_r["max_active"],
+                                "rounds": rep_r["rounds"], "recall": rec})
+                log(f"serving {lam:.0f}/s: {serving[-1]['achieved_qps']:.0f}/s p50 {serving[-1]['p50_ms']:.2f} ms "
+                    f"p99 {serving[-1]['p99_ms']:.2f} ms, mean active {rep_r['mean_active']:.0f}")
+        finally:
+            sv.close()
+
     lat_ms = np.array(lat) * 1e3
     line = {
         "metric": METRIC,
@@ -196,6 +249,7 @@ def main():
                      "kernel": "k_scan_bf16", "scan_ms_per_step": scan_ms / len(qd),
                      "scan_bytes_per_step": scan_bytes / len(qd)},
         "cpu_baseline": cpu,
+        "serving": serving,
         "setup_s": {"build": t_build, "train": t_train, "calibrate": t_cal,
                     "collect_ms": rep["ms_collect"], "sgd_ms": rep["ms_train"]},
         "search_stats": stats_all[1],
