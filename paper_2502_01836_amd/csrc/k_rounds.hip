@@ -200,13 +200,15 @@ __global__ void __launch_bounds__(256) k_scatter(int64_t nq, int N, RoundBufs b)
 // top-k (sorted by (FP64 distance, row)), refresh tau and, in a regular
 // round, queue every item whose certificate bound does not exceed the new tau
 // for an exact FP32 rescan.
-__global__ void __launch_bounds__(64) k_query_merge(int64_t nq, int N, int kmax, int KM, int check_cert,
-                                                    int dedupe, RoundBufs b) {
+__global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int KM, int check_cert,
+                                                     int dedupe, RoundBufs b) {
   extern __shared__ unsigned char smem_raw[];
-  double *vals = reinterpret_cast<double *>(smem_raw);
-  uint32_t *tags = reinterpret_cast<uint32_t *>(smem_raw + sizeof(double) * 2 * KM);
-  int lane = threadIdx.x;
-  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+  // four wavefronts per work-group, each with its own LDS slice and query
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  unsigned char *mine = smem_raw + static_cast<size_t>(wave) * 2 * KM * (sizeof(double) + sizeof(uint32_t));
+  double *vals = reinterpret_cast<double *>(mine);
+  uint32_t *tags = reinterpret_cast<uint32_t *>(mine + sizeof(double) * 2 * KM);
+  for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
     int n_it = b.qitem_cnt[q];
     if (n_it > 0) {
       int k = b.kq[q];
@@ -389,9 +391,10 @@ void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
 
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st) {
   int KM = pow2_at_least(kmax < 2 ? 2 : kmax);
-  size_t lds = static_cast<size_t>(2 * KM) * (sizeof(double) + sizeof(uint32_t));
-  int grid = static_cast<int>(nq < 65536 ? nq : 65536);
-  hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(64), lds, st, nq, N, kmax, KM, check_cert ? 1 : 0,
+  size_t lds = 4 * static_cast<size_t>(2 * KM) * (sizeof(double) + sizeof(uint32_t));
+  int64_t blocks = ceil_div(nq, 4);
+  int grid = static_cast<int>(blocks < 65536 ? blocks : 65536);
+  hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, KM, check_cert ? 1 : 0,
                      dedupe ? 1 : 0, b);
   LAUNCH_OK("query_merge");
 }

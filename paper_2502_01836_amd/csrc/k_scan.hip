@@ -287,21 +287,24 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
 
 // One wavefront per item.  LDS: merged keys [P], then per candidate the fp32
 // key, FP64 distance and row.
-__global__ void __launch_bounds__(64) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
-                                                    int kmax, int bf16, int PB, const uint64_t *__restrict__ cand) {
+__global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
+                                                     int kmax, int bf16, int PB, int slice_u64,
+                                                     const uint64_t *__restrict__ cand) {
   extern __shared__ uint64_t smem[];
-  uint64_t *buf = smem;                                                 // [PB]
-  uint64_t *k32 = smem + PB;                                            // [PK]
+  // blockDim / 64 wavefronts per work-group, one item each, own LDS slice
+  const int wave = threadIdx.x / kWave, wpb = blockDim.x / kWave;
+  uint64_t *buf = smem + static_cast<size_t>(wave) * slice_u64;        // [PB]
+  uint64_t *k32 = buf + PB;                                             // [PK]
   const int PK = pow2_at_least(kprime < 2 ? 2 : kprime);
-  double *d64 = reinterpret_cast<double *>(smem + PB + PK);   // [PK]
-  uint32_t *r64 = reinterpret_cast<uint32_t *>(d64 + PK);      // [PK]
-  const int lane = threadIdx.x;
+  double *d64 = reinterpret_cast<double *>(buf + PB + PK);             // [PK]
+  uint32_t *r64 = reinterpret_cast<uint32_t *>(d64 + PK);              // [PK]
+  const int lane = threadIdx.x & (kWave - 1);
   const int m = s.m;
   const int n_items = static_cast<int>(b.ctl[kCtlItems]);
   // error constants (see the certificate below)
   const double u = 1.0 / 16777216.0;  // 2^-24
   const float delta32 = static_cast<float>(2.0 * (m + 4) * u);
-  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+  for (int item = blockIdx.x * wpb + wave; item < n_items; item += gridDim.x * wpb) {
     int L = b.item_leaf[item];
     int64_t q = b.item_q[item];
     int k = b.kq[q];
@@ -510,10 +513,14 @@ int rerank_lds_bytes(int max_chunks, int kprime, int *PB) {
 void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int kmax, bool bf16,
                         const uint64_t *cand, int grid, int max_chunks, hipStream_t st) {
   int PB;
-  size_t lds = static_cast<size_t>(rerank_lds_bytes(max_chunks, kprime, &PB));
+  const size_t slice = round_up(rerank_lds_bytes(max_chunks, kprime, &PB), 16);
+  const int wpb = slice * 4 <= 65536 ? 4 : 1;
+  const size_t lds = slice * wpb;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_item_rerank),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  hipLaunchKernelGGL(k_item_rerank, dim3(grid), dim3(64), lds, st, s, q, b, mq, kprime, kmax, bf16 ? 1 : 0, PB, cand);
+  const int blocks = (grid + wpb - 1) / wpb;
+  hipLaunchKernelGGL(k_item_rerank, dim3(blocks), dim3(64 * wpb), lds, st, s, q, b, mq, kprime, kmax, bf16 ? 1 : 0, PB,
+                     static_cast<int>(slice / 8), cand);
   LAUNCH_OK("item_rerank");
 }
 
