@@ -87,7 +87,9 @@ typedef struct {
  * grouped leaf by leaf in fp32 and in a bf16 copy, with per-leaf summaries
  * (per segment the min/max of the members' mean and std).  Any previous
  * index, filters and calibration in the handle are discarded.
- * Limits: 1 <= n < 2^31, 8 <= m <= 1024, m a multiple of 8.
+ * Limits: 1 <= n < 2^31; 32 <= m <= 512, m a multiple of 32.  The BF16
+ * scan needs m <= 256, the FP32 scan m <= 256 or m in {384, 512}; a search
+ * with a scan that does not support m fails with LEAFI_EINVAL.
  */
 int leafi_build_index(leafi_index *index, const float *series_dev, int64_t n, int32_t m,
                       const leafi_build_opts *opts, void *stream);
