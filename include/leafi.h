@@ -229,8 +229,12 @@ typedef struct {
                               repeats; 0 = every leaf that survives.  {1} is the
                               paper's sequential loop. */
   int32_t kprime;          /* BF16 candidates kept per (query, leaf); 0 = 4k */
-  int32_t reserved[3];
+  int32_t flags;           /* LEAFI_SEARCH_* bits below; 0 = automatic */
+  int32_t reserved[2];
 } leafi_search_opts;
+
+#define LEAFI_SEARCH_NO_GRAPH 1     /* planned sequence as plain launches, never captured */
+#define LEAFI_SEARCH_HOST_ROUNDS 2  /* host-driven rounds (counts read back every round) */
 
 void leafi_default_search_opts(leafi_search_opts *opts);
 
@@ -240,10 +244,12 @@ typedef struct {
   int64_t leaves_filter_pruned;
   int64_t series_scanned;   /* real series in scanned leaves */
   int64_t fallback_items;   /* (query, leaf) pairs re-scanned exactly in FP32 */
-  int32_t rounds;
-  int32_t reserved;
+  int32_t rounds;           /* regular rounds that scanned at least one leaf */
+  int32_t path;             /* how the batch ran: 0 host-driven rounds (counts read back
+                               every round), 1 planned launch sequence, 2 replay of a
+                               captured graph, 3 captured in this call and replayed */
   double ms_total;
-  double ms_scan;           /* time in the leaf-scan kernels */
+  double ms_scan;           /* time in the BF16 leaf-scan kernels (HIP events on the stream) */
   double scan_bytes;        /* unique leaf-store bytes the scan kernels had to read */
 } leafi_search_stats;
 
@@ -253,7 +259,16 @@ typedef struct {
  * target; a query whose (k, target) pair is not calibrated, or whose target is
  * >= 1, runs without filters (exact).  Outputs ids_dev [nq, k_max] (int64) and
  * dists_dev [nq, k_max] (fp32); slots beyond a query's k hold id -1 and +inf.
- * `stats` (host) may be NULL.
+ * `stats` (host) may be NULL; when given, the call synchronises the stream.
+ *
+ * Execution: with the BF16 scan and a schedule that contains a 0 (so every
+ * query ends within that many rounds), the batch runs as a fixed launch
+ * sequence that reads nothing back (buffers sized from the per-round upper
+ * bound nq * min(R, n_leaves), if that fits 8 GiB).  The second call with the
+ * same shape, options and buffer addresses captures that sequence in a HIP
+ * graph, and later identical calls replay it (the graph reads the current
+ * contents of the caller's buffers).  Other cases run host-driven rounds.
+ * Results are identical on every path.
  */
 int leafi_search_knn(leafi_index *index, const float *queries_dev, int64_t nq, const int32_t *k_dev,
                      const float *target_dev, const leafi_search_opts *opts, int64_t *ids_dev,

@@ -12,6 +12,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import LeafiError, check, load, struct_dict
+from ._lib import LEAFI_SEARCH_HOST_ROUNDS as SEARCH_HOST_ROUNDS
+from ._lib import LEAFI_SEARCH_NO_GRAPH as SEARCH_NO_GRAPH
 
 __all__ = ["Index", "Server", "LeafiError", "load", "znorm", "mlp_infer", "mlp_sgd_step", "version"]
 
@@ -147,7 +149,7 @@ class Index:
 
     # -------------------------------------------------------------- search
     def search(self, queries, k=1, target=1.0, k_max=None, scan: str = "bf16", use_filters: bool = True,
-               schedule=(1, 0), kprime: int = 0, with_stats: bool = False, out=None):
+               schedule=(1, 0), kprime: int = 0, with_stats: bool = False, out=None, flags: int = 0):
         torch = _torch()
         nq = queries.shape[0]
         dev = queries.device
@@ -165,6 +167,7 @@ class Index:
         for i, s in enumerate(schedule):
             o.schedule[i] = s
         o.kprime = kprime
+        o.flags = flags
         if out is None:
             ids = torch.empty((nq, k_max), dtype=torch.int64, device=dev)
             dists = torch.empty((nq, k_max), dtype=torch.float32, device=dev)

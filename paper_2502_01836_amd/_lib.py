@@ -18,6 +18,8 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "ESTATE", -4: "EHIP", -5: "EAGAIN", -6
 
 LEAFI_SCAN_BF16 = 0
 LEAFI_SCAN_FP32 = 1
+LEAFI_SEARCH_NO_GRAPH = 1
+LEAFI_SEARCH_HOST_ROUNDS = 2
 LEAFI_CALIB_STEP = 0
 LEAFI_CALIB_STEFFEN = 1
 LEAFI_CALIB_NO_CORRECTION = 2
@@ -58,13 +60,13 @@ class TrainReport(ctypes.Structure):
 class SearchOpts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("scan", ctypes.c_int32), ("use_filters", ctypes.c_int32),
                 ("n_schedule", ctypes.c_int32), ("schedule", ctypes.c_int32 * 8), ("kprime", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class SearchStats(ctypes.Structure):
     _fields_ = [("leaves_scanned", ctypes.c_int64), ("leaves_lb_pruned", ctypes.c_int64),
                 ("leaves_filter_pruned", ctypes.c_int64), ("series_scanned", ctypes.c_int64),
-                ("fallback_items", ctypes.c_int64), ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fallback_items", ctypes.c_int64), ("rounds", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("ms_total", ctypes.c_double), ("ms_scan", ctypes.c_double), ("scan_bytes", ctypes.c_double)]
 
 

@@ -16,6 +16,9 @@ using namespace leafi;
 leafi_index::~leafi_index() {
   if (ws.ev0) (void)hipEventDestroy(ws.ev0);
   if (ws.ev1) (void)hipEventDestroy(ws.ev1);
+  for (hipEvent_t e : ws.sev) (void)hipEventDestroy(e);
+  ws.graphs.clear();
+  if (ws.graphs.cap) (void)hipStreamDestroy(ws.graphs.cap);
 }
 
 namespace leafi {
@@ -209,10 +212,14 @@ void read_ctl(leafi_index *ix, hipStream_t st) {
   HIP_OK(hipStreamSynchronize(st));
 }
 
-// Zero the per-round control words (items, tiles, active, fallback); the
-// statistics words keep accumulating.
-void reset_round_ctl(Workspace &w, hipStream_t st) {
-  HIP_OK(hipMemsetAsync(w.ctl.get(), 0, 4 * sizeof(int64_t), st));
+// Zero the per-round control words (items, tiles, active, fallback) and the
+// per-leaf item counts; the statistics words keep accumulating.
+void reset_round(leafi_index *ix, hipStream_t st) { launch_round_reset(views(ix->ws), 4, ix->N, 0, st); }
+
+// Before a fallback pass: zero the per-leaf and per-query item counts.  The
+// fallback count itself stays: the emit kernel reads it.
+void reset_for_fallback(leafi_index *ix, int64_t nq, hipStream_t st) {
+  launch_round_reset(views(ix->ws), 0, ix->N, nq, st);
 }
 
 // Prepare nq raw queries: normalised copies, lower bounds and visit order.
@@ -229,33 +236,53 @@ constexpr int kScanBlocksPerCU = 8;
 // Device bytes above which a round's item buffers are sized from the actual
 // counts (one host read-back) instead of from an upper bound.
 constexpr double kPreallocLimit = 1.0 * (1 << 30);
+// Upper bound of the bound-sized round buffers of a planned search (no host
+// read-back at all; see search_planned).
+constexpr double kPlannedLimit = 8.0 * (1 << 30);
 
 // With the round's item lists in place (qitem_leaf / qitem_cnt / leaf_cnt)
 // and the round control words zeroed: lay out items and tiles, scan, rerank.
 // items_bound >= 0 is an upper bound of the round's items: buffers are sized
 // from it and nothing is read back.  Otherwise the counts are read back
 // first.  Returns the item count when it was read back, else -1.
+int64_t tiles_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, int mq) {
+  // every leaf has at most nq items, and at most items_bound in all
+  const int64_t a = ceil_div(items_bound, mq) * ix->max_chunks + ix->total_chunks;
+  const int64_t b = ceil_div(nq, mq) * ix->total_chunks;
+  return std::min(a, b);
+}
+
+double round_bytes_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, int kprime, int kmax) {
+  int mq, cap;
+  scan_geometry(kprime, &mq, &cap);
+  return static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
+         static_cast<double>(tiles_bound(ix, nq, items_bound, mq)) * mq * kprime * 8.0;
+}
+
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
-                   int64_t items_bound) {
+                   int64_t items_bound, const RoundOpts *ro) {
   Workspace &w = ix->ws;
+  RoundOpts def;
+  if (!ro) ro = &def;
   int mq, cap;
   scan_geometry(kprime, &mq, &cap);
   (void)cap;
-  launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, views(w), st);
+  launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, views(w), st);
   int64_t items = -1, tiles;
-  const int64_t tiles_bound =
-      items_bound >= 0 ? ceil_div(items_bound, mq) * ix->max_chunks + ix->total_chunks : -1;
+  const int64_t tb = items_bound >= 0 ? tiles_bound(ix, nq, items_bound, mq) : -1;
   const double bytes = items_bound >= 0 ? static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
-                                              static_cast<double>(tiles_bound) * mq * kprime * 8.0
+                                              static_cast<double>(tb) * mq * kprime * 8.0
                                         : 0.0;
-  if (items_bound < 0 || bytes > kPreallocLimit) {
+  if (!ro->may_read && (items_bound < 0 || bytes > kPlannedLimit))
+    fail(LEAFI_EINTERNAL, "scan_round: planned round exceeds its preallocation bound");
+  if (ro->may_read && (items_bound < 0 || bytes > kPreallocLimit)) {
     read_ctl(ix, st);
     items = w.h_ctl[kCtlItems];
     tiles = w.h_ctl[kCtlTiles];
     if (items == 0) return 0;
   } else {
     items = -1;
-    tiles = tiles_bound;
+    tiles = tb;
   }
   ensure_items(ix, items >= 0 ? items : std::max<int64_t>(items_bound, 1), kmax);
   w.cand.reserve(static_cast<size_t>(std::max<int64_t>(tiles, 1)) * mq * kprime);
@@ -265,10 +292,12 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   launch_scatter(nq, ix->N, b, st);
   int grid_scan = static_cast<int>(std::min<int64_t>(std::max<int64_t>(tiles, 1),
                                                      static_cast<int64_t>(ix->num_cus) * kScanBlocksPerCU));
-  if (tm) HIP_OK(hipEventRecord(w.ev0, st));
+  hipEvent_t e0 = ro->ev_begin ? ro->ev_begin : (tm ? w.ev0 : nullptr);
+  hipEvent_t e1 = ro->ev_end ? ro->ev_end : (tm ? w.ev1 : nullptr);
+  if (e0) HIP_OK(hipEventRecord(e0, st));
   if (bf16) launch_scan_bf16(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
   else launch_scan_fp32(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
-  if (tm) HIP_OK(hipEventRecord(w.ev1, st));
+  if (e1) HIP_OK(hipEventRecord(e1, st));
   int64_t ib = items >= 0 ? items : std::max<int64_t>(items_bound, 1);
   int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * 16));
   launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks, st);
@@ -290,14 +319,8 @@ int default_kprime(int kmax, bool bf16) {
   return std::min(kp, 256);
 }
 
-// Unique leaf-store bytes one scan pass reads for the given leaves.
-double leaf_bytes(const leafi_index *ix, const std::vector<int32_t> &cnt, bool bf16) {
-  double per_row = bf16 ? 2.0 * ix->m + 4.0 : 4.0 * ix->m;
-  double tot = 0.0;
-  for (int L = 0; L < ix->N; ++L)
-    if (cnt[L] > 0) tot += static_cast<double>(ix->h_leaf_off[L + 1] - ix->h_leaf_off[L]) * per_row;
-  return tot;
-}
+// Bytes of one leaf-store row as the scan of that precision reads it.
+int64_t scan_row_bytes(const leafi_index *ix, bool bf16) { return bf16 ? 2LL * ix->m + 4 : 4LL * ix->m; }
 
 struct SearchPlan {
   int kmax = 1;
@@ -305,70 +328,109 @@ struct SearchPlan {
   bool filters = false;
   std::vector<int> schedule{1};
   int kprime = 4;
+  bool graph = true;  // planned batches may be captured and replayed
 };
 
-// Batched search of nq raw queries (Algorithm 2 in rounds).
+// Per-batch initialisation in one launch: cursor 0, tau +inf, no results, no
+// items, zero leaf counts, filter-pair counts and control words.
+__global__ void k_batch_init(int64_t nq, int N, int F, RoundBufs b, int32_t *pcnt) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < nq) {
+    b.cursor[i] = 0;
+    b.tau[i] = __builtin_inff();
+    b.res_cnt[i] = 0;
+    b.qitem_cnt[i] = 0;
+  }
+  if (i < N) b.leaf_cnt[i] = 0;
+  if (pcnt && i < F) pcnt[i] = 0;
+  if (i < kCtlCount) b.ctl[i] = 0;
+}
+
+// Queries, lower bounds, visit order, (k, target) pair, batch state.
+void begin_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
+                 const SearchPlan &p, bool use_f, hipStream_t st) {
+  Workspace &w = ix->ws;
+  prep_queries(ix, raw, nq, st);
+  launch_select_pairs(nq, k_dev, t_dev, use_f ? ix->cal.pairs() : 0, use_f ? ix->cal.pair_k.get() : nullptr,
+                      use_f ? ix->cal.pair_t.get() : nullptr, p.kmax, w.pair.get(), w.kq.get(), st);
+  const int F = ix->filt.F;
+  const int64_t n = std::max<int64_t>(std::max<int64_t>(nq, ix->N), std::max<int64_t>(F, kCtlCount));
+  hipLaunchKernelGGL(k_batch_init, dim3(static_cast<int>(ceil_div(n, 256))), dim3(256), 0, st, nq, ix->N, F,
+                     views(w), use_f ? w.pcnt.get() : nullptr);
+  LAUNCH_OK("batch_init");
+}
+
+// After the first round has set tau: d^f for every (query, filtered leaf)
+// pair a later round can still test.  tau only decreases, so this covers all
+// later rounds (filter-pair counts were zeroed by begin_batch).
+void eval_filters(leafi_index *ix, int64_t nq, hipStream_t st) {
+  Workspace &w = ix->ws;
+  const int F = ix->filt.F;
+  launch_filter_pairs(nq, ix->N, w.lb.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
+                      w.pcnt.get(), st);
+  launch_mlp_infer_pairs(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), nq,
+                         w.dfilt.get(), st);
+}
+
+void launch_round_worklist(leafi_index *ix, int64_t nq, int want, bool f_now, hipStream_t st) {
+  Workspace &w = ix->ws;
+  const int F = ix->filt.F;
+  launch_worklist(nq, ix->N, w.lb.get(), w.order.get(), w.dfilt.get(), std::max(F, 1),
+                  f_now ? ix->filt.filt_of_leaf.get() : nullptr, f_now ? ix->cal.offsets.get() : nullptr,
+                  ix->leaf_n.get(), want, views(w), st);
+}
+
+void stats_from_ctl(const leafi_index *ix, leafi_search_stats *stats) {
+  const std::vector<int64_t> &c = ix->ws.h_ctl;
+  stats->leaves_scanned += c[kCtlScanned];
+  stats->leaves_lb_pruned += c[kCtlLbPruned];
+  stats->leaves_filter_pruned += c[kCtlFPruned];
+  stats->series_scanned += c[kCtlSeries];
+  stats->fallback_items += c[kCtlFbTotal];
+  stats->rounds += static_cast<int32_t>(c[kCtlRounds]);
+  stats->scan_bytes += static_cast<double>(c[kCtlScanBytes]);
+}
+
+// Batched search of nq raw queries (Algorithm 2 in rounds), host-driven: the
+// counts of every round are read back, which sizes the buffers from actual
+// counts and ends the loop as soon as no query has leaves left.  Serves any
+// schedule, including open-ended ones such as the paper's one leaf per round.
 void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
                   const SearchPlan &p, int64_t *ids, float *dists, leafi_search_stats *stats, hipStream_t st) {
   Workspace &w = ix->ws;
   const int N = ix->N;
   ensure_queries(ix, nq, p.kmax);
-  prep_queries(ix, raw, nq, st);
   const int F = ix->filt.F;
   const bool use_f = p.filters && F > 0 && ix->cal.pairs() > 0;
-  launch_select_pairs(nq, k_dev, t_dev, use_f ? ix->cal.pairs() : 0, use_f ? ix->cal.pair_k.get() : nullptr,
-                      use_f ? ix->cal.pair_t.get() : nullptr, p.kmax, w.pair.get(), w.kq.get(), st);
-  fill_i32(w.cursor.get(), nq, 0, st);
-  fill_f32(w.tau.get(), nq, INFINITY, st);
-  fill_i32(w.res_cnt.get(), nq, 0, st);
-  HIP_OK(hipMemsetAsync(w.ctl.get(), 0, kCtlCount * sizeof(int64_t), st));
   if (use_f) {
     w.plist.reserve(static_cast<size_t>(F) * nq);
     w.pcnt.reserve(F);
   }
-  const int kprime = p.kprime;
+  begin_batch(ix, raw, nq, k_dev, t_dev, p, use_f, st);
   const int kprime_fb = default_kprime(p.kmax, false);
   Timing tm;
-  int64_t fallback = 0;
-  int rounds = 0;
+  RoundOpts ro;
+  ro.row_bytes = scan_row_bytes(ix, p.bf16);
   bool filters_ready = false;
-  std::vector<int32_t> hcnt(N);
   for (int r = 0;; ++r) {
-    // Filters cannot prune while tau is +inf (the first round).  Once the
-    // first round has set tau, evaluate d^f for every pair a later round can
-    // still test; tau only decreases, so this covers all later rounds.
     if (use_f && r > 0 && !filters_ready) {
-      HIP_OK(hipMemsetAsync(w.pcnt.get(), 0, F * sizeof(int32_t), st));
-      launch_filter_pairs(nq, N, w.lb.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
-                          w.pcnt.get(), st);
-      launch_mlp_infer_pairs(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), nq,
-                             w.dfilt.get(), st);
+      eval_filters(ix, nq, st);
       filters_ready = true;
     }
-    reset_round_ctl(w, st);
-    HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, N * sizeof(int32_t), st));
+    if (r > 0) reset_round(ix, st);
     const int want = p.schedule[std::min<size_t>(r, p.schedule.size() - 1)];
-    const bool f_now = use_f && filters_ready;
-    launch_worklist(nq, N, w.lb.get(), w.order.get(), w.dfilt.get(), std::max(F, 1),
-                    f_now ? ix->filt.filt_of_leaf.get() : nullptr, f_now ? ix->cal.offsets.get() : nullptr,
-                    ix->leaf_n.get(), want, views(w), st);
-    if (stats) d2h(hcnt.data(), w.leaf_cnt.get(), N, st);
+    launch_round_worklist(ix, nq, want, use_f && filters_ready, st);
     const int64_t bound = nq * static_cast<int64_t>(want == 0 ? N : std::min(want, N));
-    int64_t items = scan_round(ix, nq, p.bf16, kprime, p.kmax, st, stats ? &tm : nullptr, bound);
+    int64_t items = scan_round(ix, nq, p.bf16, p.kprime, p.kmax, st, stats ? &tm : nullptr, bound, &ro);
     if (items == 0) break;
     launch_query_merge(nq, N, p.kmax, true, false, views(w), st);
     read_ctl(ix, st);
     if (w.h_ctl[kCtlItems] == 0) break;
-    ++rounds;
     add_scan_time(ix, stats ? &tm : nullptr);
-    if (stats) tm.scan_bytes += leaf_bytes(ix, hcnt, p.bf16);
     const int64_t active = w.h_ctl[kCtlActive];
     const int64_t n_fb = w.h_ctl[kCtlFallback];
     if (n_fb > 0) {
-      fallback += n_fb;
-      reset_round_ctl(w, st);
-      HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, N * sizeof(int32_t), st));
-      fill_i32(w.qitem_cnt.get(), nq, 0, st);
+      reset_for_fallback(ix, nq, st);
       launch_emit_fallback(n_fb, N, views(w), st);
       if (scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, n_fb) != 0)
         launch_query_merge(nq, N, p.kmax, false, true, views(w), st);
@@ -378,14 +440,232 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
   launch_finalize(nq, p.kmax, ix->rowid.get(), views(w), ids, dists, st);
   if (stats) {
     read_ctl(ix, st);
-    stats->leaves_scanned += w.h_ctl[kCtlScanned];
-    stats->leaves_lb_pruned += w.h_ctl[kCtlLbPruned];
-    stats->leaves_filter_pruned += w.h_ctl[kCtlFPruned];
-    stats->series_scanned += w.h_ctl[kCtlSeries];
-    stats->fallback_items += fallback;
-    stats->rounds += rounds;
+    stats_from_ctl(ix, stats);
     stats->ms_scan += tm.scan_ms;
-    stats->scan_bytes += tm.scan_bytes;
+    stats->path = 0;
+  }
+}
+
+// Regular rounds of a schedule that ends in 0 (every survivor): the round
+// with the first 0 takes all remaining leaves of every query, so the batch
+// has at most that many rounds.  0 if the schedule is open-ended.
+int planned_rounds(const SearchPlan &p) {
+  for (size_t r = 0; r < p.schedule.size(); ++r)
+    if (p.schedule[r] == 0) return static_cast<int>(r) + 1;
+  return 0;
+}
+
+int64_t planned_bound(const leafi_index *ix, int64_t nq, const SearchPlan &p, int r) {
+  const int want = p.schedule[r];
+  return nq * static_cast<int64_t>(want == 0 ? ix->N : std::min(want, ix->N));
+}
+
+// Whether a batch can run as a planned sequence: a bounded number of rounds
+// whose bound-sized buffers fit the planned limit.
+bool can_plan(const leafi_index *ix, int64_t nq, const SearchPlan &p) {
+  const int R = planned_rounds(p);
+  if (R == 0 || R > kMaxPlannedRounds || !p.bf16) return false;
+  const int kprime_fb = default_kprime(p.kmax, false);
+  for (int r = 0; r < R; ++r) {
+    const int64_t bnd = planned_bound(ix, nq, p, r);
+    if (round_bytes_bound(ix, nq, bnd, p.kprime, p.kmax) > kPlannedLimit) return false;
+    if (round_bytes_bound(ix, nq, bnd, kprime_fb, p.kmax) > kPlannedLimit) return false;
+  }
+  return true;
+}
+
+// Reserve every buffer a planned sequence touches at its bound, so that
+// enqueueing it allocates nothing (a requirement of graph capture).
+void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_f) {
+  Workspace &w = ix->ws;
+  ensure_queries(ix, nq, p.kmax);
+  const int F = ix->filt.F;
+  if (use_f) {
+    w.plist.reserve(static_cast<size_t>(F) * nq);
+    w.pcnt.reserve(F);
+  }
+  const int kprime_fb = default_kprime(p.kmax, false);
+  int64_t items = 1;
+  size_t cand = 1;
+  for (int r = 0; r < planned_rounds(p); ++r) {
+    const int64_t bnd = planned_bound(ix, nq, p, r);
+    items = std::max(items, bnd);
+    for (int kp : {p.kprime, kprime_fb}) {
+      int mq, cap;
+      scan_geometry(kp, &mq, &cap);
+      cand = std::max(cand, static_cast<size_t>(std::max<int64_t>(tiles_bound(ix, nq, bnd, mq), 1)) * mq * kp);
+    }
+  }
+  ensure_items(ix, items, p.kmax);
+  w.cand.reserve(cand);
+  if (w.sev.empty()) {
+    w.sev.resize(2 * kMaxPlannedRounds);
+    for (auto &e : w.sev) HIP_OK(hipEventCreate(&e));
+  }
+}
+
+// The whole batch as a fixed launch sequence with no host read-back: each
+// round is the prune cascade, scan, rerank and merge, then an exact rescan
+// pass of the uncertified items whose size is read on the device (empty
+// passes exit at once).  With `timed`, per-round events bracket the scan.
+void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
+                     const SearchPlan &p, bool use_f, int64_t *ids, float *dists, bool timed, hipStream_t st) {
+  Workspace &w = ix->ws;
+  const int N = ix->N;
+  const int kprime_fb = default_kprime(p.kmax, false);
+  begin_batch(ix, raw, nq, k_dev, t_dev, p, use_f, st);
+  const int R = planned_rounds(p);
+  for (int r = 0; r < R; ++r) {
+    if (use_f && r == 1) eval_filters(ix, nq, st);
+    if (r > 0) reset_round(ix, st);
+    launch_round_worklist(ix, nq, p.schedule[r], use_f && r > 0, st);
+    const int64_t bnd = planned_bound(ix, nq, p, r);
+    RoundOpts ro;
+    ro.may_read = false;
+    ro.row_bytes = scan_row_bytes(ix, true);
+    if (timed) {
+      ro.ev_begin = w.sev[2 * r];
+      ro.ev_end = w.sev[2 * r + 1];
+    }
+    scan_round(ix, nq, true, p.kprime, p.kmax, st, nullptr, bnd, &ro);
+    launch_query_merge(nq, N, p.kmax, true, false, views(w), st);
+    RoundOpts rf;
+    rf.may_read = false;
+    reset_for_fallback(ix, nq, st);
+    launch_emit_fallback(bnd, N, views(w), st);
+    scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bnd, &rf);
+    launch_query_merge(nq, N, p.kmax, false, true, views(w), st);
+  }
+  launch_finalize(nq, p.kmax, ix->rowid.get(), views(w), ids, dists, st);
+}
+
+// Identity of a planned sequence: every value and device address baked into
+// its launches.  A graph is replayed only for an identical key.
+std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev,
+                               const float *t_dev, const SearchPlan &p, bool use_f, const int64_t *ids,
+                               const float *dists, bool timed) {
+  Workspace &w = ix->ws;
+  std::vector<uint64_t> k;
+  auto put = [&](const void *ptr, size_t bytes) {
+    const size_t n0 = k.size();
+    k.resize(n0 + (bytes + 7) / 8, 0);
+    std::memcpy(k.data() + n0, ptr, bytes);
+  };
+  auto ptr = [&](const void *q) { k.push_back(reinterpret_cast<uintptr_t>(q)); };
+  RoundBufs b = views(w);
+  QueryView q = query_view(w);
+  StoreView s = store_view(ix);
+  put(&b, sizeof b);
+  put(&q, sizeof q);
+  put(&s, sizeof s);
+  for (int64_t v : {nq, static_cast<int64_t>(p.kmax), static_cast<int64_t>(p.kprime), static_cast<int64_t>(use_f),
+                    static_cast<int64_t>(timed), static_cast<int64_t>(ix->N), static_cast<int64_t>(ix->m),
+                    static_cast<int64_t>(ix->S), static_cast<int64_t>(ix->filt.F), static_cast<int64_t>(ix->filt.h),
+                    static_cast<int64_t>(ix->cal.pairs()), static_cast<int64_t>(ix->max_chunks), ix->total_chunks})
+    k.push_back(static_cast<uint64_t>(v));
+  for (int r : p.schedule) k.push_back(static_cast<uint64_t>(r));
+  for (const void *a : {static_cast<const void *>(raw), static_cast<const void *>(k_dev),
+                        static_cast<const void *>(t_dev), static_cast<const void *>(ids),
+                        static_cast<const void *>(dists), static_cast<const void *>(w.cand.get()),
+                        static_cast<const void *>(w.plist.get()), static_cast<const void *>(w.pcnt.get()),
+                        static_cast<const void *>(w.dfilt.get()), static_cast<const void *>(w.lb.get()),
+                        static_cast<const void *>(w.order.get()), static_cast<const void *>(w.qstat.get()),
+                        static_cast<const void *>(ix->boxes.get()), static_cast<const void *>(ix->rowid.get()),
+                        static_cast<const void *>(ix->filt.w.get()), static_cast<const void *>(ix->filt.filt_of_leaf.get()),
+                        static_cast<const void *>(ix->cal.offsets.get()), static_cast<const void *>(ix->cal.pair_k.get()),
+                        static_cast<const void *>(ix->cal.pair_t.get())})
+    ptr(a);
+  if (timed)
+    for (hipEvent_t e : w.sev) ptr(e);
+  return k;
+}
+
+// Capture the planned sequence into an executable graph; nullptr (and the
+// cache disabled for this kind, with the reason kept) if capture fails.
+hipGraphExec_t capture_planned(leafi_index *ix, const std::vector<uint64_t> &key, const float *raw, int64_t nq,
+                               const int32_t *k_dev, const float *t_dev, const SearchPlan &p, bool use_f,
+                               int64_t *ids, float *dists, bool timed) {
+  GraphCache &g = ix->ws.graphs;
+  if (!g.cap) HIP_OK(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIP_OK(hipStreamBeginCapture(g.cap, hipStreamCaptureModeRelaxed));
+  try {
+    enqueue_planned(ix, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed, g.cap);
+  } catch (const Error &e) {
+    (void)hipStreamEndCapture(g.cap, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    (timed ? g.off_timed : g.off) = true;
+    g.why = e.what();
+    return nullptr;
+  }
+  hipError_t e1 = hipStreamEndCapture(g.cap, &graph);
+  hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) : e1;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) {
+    (void)hipGetLastError();
+    (timed ? g.off_timed : g.off) = true;
+    g.why = std::string("graph capture: ") + hipGetErrorString(e2);
+    return nullptr;
+  }
+  // nothing may have been reallocated while capturing
+  if (plan_key(ix, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed) != key) {
+    (void)hipGraphExecDestroy(exec);
+    return nullptr;
+  }
+  return exec;
+}
+
+// Planned batch search.  The first batch of a given shape runs the sequence
+// as ordinary launches; from the second identical batch on it is captured
+// once into a graph and replayed (up to kGraphCacheSize shapes are kept).
+void search_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
+                    const SearchPlan &p, int64_t *ids, float *dists, leafi_search_stats *stats, hipStream_t st) {
+  Workspace &w = ix->ws;
+  const bool use_f = p.filters && ix->filt.F > 0 && ix->cal.pairs() > 0;
+  const bool timed = stats != nullptr;
+  prepare_planned(ix, nq, p, use_f);
+  GraphCache &g = w.graphs;
+  const std::vector<uint64_t> key = plan_key(ix, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed);
+  hipGraphExec_t exec = nullptr;
+  int path = 1;
+  ++g.tick;
+  for (auto &e : g.entries)
+    if (e.key == key) {
+      exec = e.exec;
+      e.last_use = g.tick;
+      path = 2;
+    }
+  const bool allowed = !(timed ? g.off_timed : g.off);
+  if (!exec && allowed && p.graph && g.pending == key) {
+    exec = capture_planned(ix, key, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed);
+    if (exec) {
+      if (g.entries.size() >= static_cast<size_t>(kGraphCacheSize)) {
+        auto old = std::min_element(g.entries.begin(), g.entries.end(),
+                                    [](const GraphEntry &a, const GraphEntry &b) { return a.last_use < b.last_use; });
+        (void)hipGraphExecDestroy(old->exec);
+        g.entries.erase(old);
+      }
+      g.entries.push_back(GraphEntry{key, exec, g.tick});
+      path = 3;
+    }
+  }
+  if (exec) {
+    HIP_OK(hipGraphLaunch(exec, st));
+  } else {
+    g.pending = key;
+    enqueue_planned(ix, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed, st);
+  }
+  if (stats) {
+    read_ctl(ix, st);
+    stats_from_ctl(ix, stats);
+    for (int r = 0; r < planned_rounds(p); ++r) {
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, w.sev[2 * r], w.sev[2 * r + 1]));
+      stats->ms_scan += ms;
+    }
+    stats->path = path;
   }
 }
 
@@ -410,9 +690,7 @@ void allpairs_items(leafi_index *ix, int64_t nq, int k, hipStream_t st, Consume 
   int64_t n_fb = w.h_ctl[kCtlFallback];
   if (n_fallback) *n_fallback = n_fb;
   if (n_fb > 0) {
-    reset_round_ctl(w, st);
-    HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, ix->N * sizeof(int32_t), st));
-    fill_i32(w.qitem_cnt.get(), nq, 0, st);
+    reset_for_fallback(ix, nq, st);
     launch_emit_fallback(n_fb, ix->N, views(w), st);
     int64_t it2 = scan_round(ix, nq, false, default_kprime(k, false), k, st, nullptr);
     if (it2 > 0) consume(it2);
@@ -426,8 +704,7 @@ void lists_all_leaves(leafi_index *ix, int64_t nq, DevBuf<int32_t> &tmp, hipStre
   for (int L = 0; L < ix->N; ++L) all[L] = L;
   tmp.reserve(ix->N);
   h2d(tmp.get(), all.data(), all.size(), st);
-  reset_round_ctl(w, st);
-  HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, ix->N * sizeof(int32_t), st));
+  reset_round(ix, st);
   hipLaunchKernelGGL(k_fill_allpairs, dim3(ceil_div(nq * ix->N, 256)), dim3(256), 0, st, w.qitem_leaf.get(),
                      w.qitem_cnt.get(), w.leaf_cnt.get(), nq, ix->N, tmp.get(), ix->N);
   LAUNCH_OK("fill_allpairs");
@@ -805,8 +1082,7 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     h2d(dloff.get(), loff.data(), loff.size(), st);
     h2d(dlst.get(), lst.data(), lst.size(), st);
     fill_i32(w.kq.get(), nqt, 1, st);
-    reset_round_ctl(w, st);
-    HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, N * sizeof(int32_t), st));
+    reset_round(ix, st);
     hipLaunchKernelGGL(k_fill_lists, dim3(ceil_div(nqt, 256)), dim3(256), 0, st, w.qitem_leaf.get(),
                        w.qitem_cnt.get(), w.leaf_cnt.get(), nqt, N, dloff.get(), dlst.get());
     LAUNCH_OK("fill_lists");
@@ -1011,6 +1287,7 @@ int leafi_search_knn(leafi_index *ix, const float *queries, int64_t nq, const in
     LEAFI_CHECK_ARG(o->n_schedule >= 1 && o->n_schedule <= 8, "n_schedule must be in [1, 8]");
     for (int i = 0; i < o->n_schedule; ++i) LEAFI_CHECK_ARG(o->schedule[i] >= 0, "schedule entries must be >= 0");
     LEAFI_CHECK_ARG(o->kprime >= 0 && o->kprime <= 256, "kprime must be in [0, 256]");
+    LEAFI_CHECK_ARG((o->flags & ~(LEAFI_SEARCH_NO_GRAPH | LEAFI_SEARCH_HOST_ROUNDS)) == 0, "unknown search flags");
     LEAFI_CHECK_ARG(o->scan != LEAFI_SCAN_BF16 || ix->m <= 256, "the bf16 scan supports m <= 256");
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (nq == 0) return;
@@ -1023,7 +1300,10 @@ int leafi_search_knn(leafi_index *ix, const float *queries, int64_t nq, const in
     p.schedule.assign(o->schedule, o->schedule + o->n_schedule);
     p.kprime = o->kprime > 0 ? std::max<int>(o->kprime, p.kmax) : default_kprime(p.kmax, p.bf16);
     auto t0 = std::chrono::steady_clock::now();
-    if (p.bf16) {
+    p.graph = (o->flags & LEAFI_SEARCH_NO_GRAPH) == 0;
+    if (p.bf16 && (o->flags & LEAFI_SEARCH_HOST_ROUNDS) == 0 && can_plan(ix, nq, p)) {
+      search_planned(ix, queries, nq, k_dev, t_dev, p, ids, dists, stats, st);
+    } else if (p.bf16) {
       search_batch(ix, queries, nq, k_dev, t_dev, p, ids, dists, stats, st);
     } else {
       // plain form: one query at a time

@@ -59,11 +59,21 @@ void ensure_queries(leafi_index *ix, int64_t nq, int kmax);
 void ensure_items(leafi_index *ix, int64_t items, int kmax);
 // Copy the control words to the host (synchronises the stream).
 void read_ctl(leafi_index *ix, hipStream_t st);
-// Zero the per-round control words (items, tiles, active, fallback).
-void reset_round_ctl(Workspace &w, hipStream_t st);
+// Zero the per-round control words (items, tiles, active, fallback) and the
+// per-leaf item counts.
+void reset_round(leafi_index *ix, hipStream_t st);
+// Zero the per-leaf and per-query item counts before a fallback pass.
+void reset_for_fallback(leafi_index *ix, int64_t nq, hipStream_t st);
+
+struct RoundOpts {
+  bool may_read = true;         // false: never read counts back (planned / captured sequences)
+  int64_t row_bytes = 0;        // > 0: account the round's unique leaf bytes in ctl[kCtlScanBytes]
+  hipEvent_t ev_begin = nullptr;  // recorded around the scan kernel when set
+  hipEvent_t ev_end = nullptr;
+};
 // Lay out the round's items, scan and rerank them (see api.hip).
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
-                   int64_t items_bound = -1);
+                   int64_t items_bound = -1, const RoundOpts *ro = nullptr);
 void add_scan_time(leafi_index *ix, Timing *tm);
 int default_kprime(int kmax, bool bf16);
 

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -76,6 +77,33 @@ struct Calibration {
 };
 
 // Scratch buffers of one search / all-pairs pass, grown on demand.
+// Planned batch searches have at most this many regular rounds.
+constexpr int kMaxPlannedRounds = 8;
+// Executable graphs kept per index (least recently used evicted).
+constexpr int kGraphCacheSize = 8;
+
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
+// Captured planned searches, keyed by everything baked into their launches.
+struct GraphCache {
+  std::vector<GraphEntry> entries;
+  std::vector<uint64_t> pending;  // key of the last uncaptured planned batch
+  hipStream_t cap = nullptr;      // capture stream (default priority)
+  bool off = false, off_timed = false;  // capture failed once: do not retry
+  std::string why;
+  uint64_t tick = 0;
+  void clear() {
+    for (auto &e : entries)
+      if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    entries.clear();
+    pending.clear();
+  }
+};
+
 struct Workspace {
   // queries
   DevBuf<float> q32, qn16, qeps, qstat, lb, dfilt, tau;
@@ -93,6 +121,8 @@ struct Workspace {
   DevBuf<int64_t> ctl;
   std::vector<int64_t> h_ctl;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> sev;  // per planned round: scan begin / end
+  GraphCache graphs;
 };
 
 }  // namespace leafi

@@ -3,6 +3,8 @@
 // round's (query, leaf) items, the items' CSR-by-leaf layout and scan tiles,
 // the per-query merge into the running top-k with the best-so-far tau, and
 // the final output.
+#include <algorithm>
+
 #include "device_util.h"
 #include "kernels.h"
 
@@ -126,31 +128,46 @@ __global__ void __launch_bounds__(256) k_filter_pairs(int64_t nq, int N, const f
   plist[static_cast<int64_t>(f) * nq + slot] = static_cast<int32_t>(q);
 }
 
-__global__ void __launch_bounds__(256) k_emit_fallback(int64_t n_fb, int N, RoundBufs b) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n_fb) return;
-  int q = b.fb_q[i];
-  int L = b.fb_leaf[i];
-  int r = atomicAdd(b.qitem_cnt + q, 1);
-  b.qitem_leaf[static_cast<int64_t>(q) * N + r] = L;
-  atomicAdd(b.leaf_cnt + L, 1);
+__global__ void __launch_bounds__(256) k_emit_fallback(int N, RoundBufs b) {
+  const int64_t n_fb = b.ctl[kCtlFallback];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n_fb > 0)
+    atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFbTotal), static_cast<unsigned long long>(n_fb));
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_fb;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int q = b.fb_q[i];
+    int L = b.fb_leaf[i];
+    int r = atomicAdd(b.qitem_cnt + q, 1);
+    b.qitem_leaf[static_cast<int64_t>(q) * N + r] = L;
+    atomicAdd(b.leaf_cnt + L, 1);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_round_reset(RoundBufs b, int n_ctl, int N, int64_t nq) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n_ctl) b.ctl[i] = 0;
+  if (i < N) b.leaf_cnt[i] = 0;
+  if (i < nq) b.qitem_cnt[i] = 0;
 }
 
 // Exclusive scans over leaves: item starts and tile starts (one work-group).
 __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__restrict__ leaf_off, int mq,
-                                                    RoundBufs b) {
+                                                    int64_t row_bytes, RoundBufs b) {
   __shared__ int64_t part_i[1024];
   __shared__ int64_t part_t[1024];
   int tid = threadIdx.x;
   int per = (N + 1023) / 1024;
   int l0 = tid * per, l1 = min(N, l0 + per);
-  int64_t si = 0, stl = 0;
+  int64_t si = 0, stl = 0, rows = 0;
   for (int L = l0; L < l1; ++L) {
     int c = b.leaf_cnt[L];
     int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + kChunkRows - 1) / kChunkRows;
     si += c;
     stl += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
+    if (c > 0) rows += leaf_off[L + 1] - leaf_off[L];
   }
+  if (row_bytes > 0 && rows > 0)
+    atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlScanBytes),
+              static_cast<unsigned long long>(rows * row_bytes));
   part_i[tid] = si;
   part_t[tid] = stl;
   __syncthreads();
@@ -178,6 +195,7 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
     b.tile_start[N] = static_cast<int32_t>(part_t[1023]);
     b.ctl[kCtlItems] = part_i[1023];
     b.ctl[kCtlTiles] = part_t[1023];
+    if (row_bytes > 0 && part_i[1023] > 0) b.ctl[kCtlRounds] += 1;
   }
 }
 
@@ -373,14 +391,22 @@ void launch_filter_pairs(int64_t nq, int N, const float *lb, const int32_t *orde
   LAUNCH_OK("filter_pairs");
 }
 
-void launch_emit_fallback(int64_t n_fb, int N, RoundBufs b, hipStream_t st) {
-  if (n_fb <= 0) return;
-  hipLaunchKernelGGL(k_emit_fallback, dim3(ceil_div(n_fb, 256)), dim3(256), 0, st, n_fb, N, b);
+void launch_emit_fallback(int64_t bound, int N, RoundBufs b, hipStream_t st) {
+  if (bound <= 0) return;
+  const int64_t blocks = ceil_div(bound, 256);
+  hipLaunchKernelGGL(k_emit_fallback, dim3(static_cast<int>(blocks < 1024 ? blocks : 1024)), dim3(256), 0, st, N, b);
   LAUNCH_OK("emit_fallback");
 }
 
-void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, RoundBufs b, hipStream_t st) {
-  hipLaunchKernelGGL(k_leaf_scan, dim3(1), dim3(1024), 0, st, N, leaf_off, mq, b);
+void launch_round_reset(RoundBufs b, int n_ctl, int N, int64_t nq, hipStream_t st) {
+  const int64_t n = std::max<int64_t>(std::max<int64_t>(n_ctl, N), nq);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_round_reset, dim3(static_cast<int>(ceil_div(n, 256))), dim3(256), 0, st, b, n_ctl, N, nq);
+  LAUNCH_OK("round_reset");
+}
+
+void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b, hipStream_t st) {
+  hipLaunchKernelGGL(k_leaf_scan, dim3(1), dim3(1024), 0, st, N, leaf_off, mq, row_bytes, b);
   LAUNCH_OK("leaf_scan");
 }
 

@@ -84,7 +84,10 @@ enum Ctl : int {
   kCtlFPruned = 5,
   kCtlSeries = 6,     // real series in scanned items
   kCtlScanned = 7,    // items (leaves) scanned, excluding rescans
-  kCtlCount = 8
+  kCtlFbTotal = 8,    // uncertified items rescanned, over the batch
+  kCtlScanBytes = 9,  // unique leaf-store bytes the regular rounds read
+  kCtlRounds = 10,    // regular rounds with at least one item
+  kCtlCount = 12
 };
 
 struct StoreView {
@@ -129,11 +132,19 @@ void launch_filter_pairs(int64_t nq, int N, const float *lb, const int32_t *orde
 void launch_collect_done(int64_t n_slots, int N, int kmax, const int64_t *rowid, RoundBufs b, int32_t *state,
                          int32_t *done_slot, int64_t *done_ids, float *done_d, int32_t *n_done, hipStream_t st);
 
-// Emit pairs from the fallback list instead.
-void launch_emit_fallback(int64_t n_fb, int N, RoundBufs b, hipStream_t st);
+// Emit pairs from the fallback list instead.  The count is read on the device
+// (ctl[kCtlFallback]); `bound` >= that count sizes the grid.
+void launch_emit_fallback(int64_t bound, int N, RoundBufs b, hipStream_t st);
 
-// Items CSR by leaf and tile ranges (single work-group).
-void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, RoundBufs b, hipStream_t st);
+// Items CSR by leaf and tile ranges (single work-group).  row_bytes > 0 adds
+// the padded rows of every leaf with items times row_bytes to
+// ctl[kCtlScanBytes] and counts a round in ctl[kCtlRounds] if it has items.
+void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b, hipStream_t st);
+
+// Zero the first n_ctl control words, leaf_cnt[0..N) and qitem_cnt[0..nq)
+// (either count may be 0) in one launch.  A kernel, not a memset, so that the
+// sequence can be captured in a graph.
+void launch_round_reset(RoundBufs b, int n_ctl, int N, int64_t nq, hipStream_t st);
 
 // Place each query's emitted leaves into item slots.
 void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st);

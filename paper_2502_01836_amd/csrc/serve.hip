@@ -144,14 +144,13 @@ void leafi_server::engine_round(int n_new, int &n_active) {
   const int F = ix->filt.F;
   if (use_f) {
     // slots that finished their first round get the filter pairs a later round can test
-    HIP_OK(hipMemsetAsync(w.pcnt.get(), 0, F * sizeof(int32_t), st));
+    fill_i32(w.pcnt.get(), F, 0, st);
     launch_filter_pairs(slots, N, w.lb.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
                         w.pcnt.get(), st, qround.get());
     launch_mlp_infer_pairs(ix->filt.w.get(), F, m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), slots,
                            w.dfilt.get(), st);
   }
-  reset_round_ctl(w, st);
-  HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, N * sizeof(int32_t), st));
+  reset_round(ix, st);
   launch_worklist(slots, N, w.lb.get(), w.order.get(), w.dfilt.get(), std::max(F, 1),
                   use_f ? ix->filt.filt_of_leaf.get() : nullptr, use_f ? ix->cal.offsets.get() : nullptr,
                   ix->leaf_n.get(), 0, views(w), st, &sched, qround.get());
@@ -163,9 +162,7 @@ void leafi_server::engine_round(int n_new, int &n_active) {
   read_ctl(ix, st);
   const int64_t n_fb = w.h_ctl[kCtlFallback];
   if (n_fb > 0) {
-    reset_round_ctl(w, st);
-    HIP_OK(hipMemsetAsync(w.leaf_cnt.get(), 0, N * sizeof(int32_t), st));
-    fill_i32(w.qitem_cnt.get(), slots, 0, st);
+    reset_for_fallback(ix, slots, st);
     launch_emit_fallback(n_fb, N, views(w), st);
     if (scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, n_fb) != 0)
       launch_query_merge(slots, N, kmax, false, true, views(w), st);

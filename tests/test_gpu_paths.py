@@ -1,0 +1,124 @@
+"""The three ways a batch runs (host-driven rounds, the planned launch
+sequence, a captured HIP graph) give bit-identical results and statistics,
+and a replayed graph reads the current contents of the caller's buffers.
+
+Every replay is checked against an eager search, with the program's own eager
+work and synchronisations between replays.  Parity of the shared result with
+the FP64 oracle is checked on the replayed output as well.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+COUNTS = ("leaves_scanned", "leaves_lb_pruned", "leaves_filter_pruned", "series_scanned", "fallback_items",
+          "rounds", "scan_bytes")
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_01836_amd as pkg
+    pkg.load()
+    raw = W.random_walk(24000, 128, seed=611)
+    ix = pkg.Index().build(torch.from_numpy(raw).cuda(), leaf_capacity=800, n_segments=16)
+    N = ix.info()["n_leaves"]
+    h = 32
+    w = W.mlp_weights(N, 128, h, seed=612, out_bias=4.0)
+    offs = np.random.default_rng(613).uniform(0.0, 3.5, N).astype(np.float32)
+    ix.set_filters(np.arange(N, dtype=np.int32), torch.from_numpy(w).cuda(), h)
+    ix.set_offsets([1, 10], [0.9], np.stack([offs, offs]))
+    nq = 300
+    q = [W.noisy_queries(raw, nq, (0.05, 0.3), 614 + i, 714 + i)[0] for i in range(3)]
+    rng = np.random.default_rng(615)
+    ks = rng.choice([1, 10], nq).astype(np.int32)
+    ts = rng.choice([0.9, 1.0], nq).astype(np.float32)
+    # k and target stay in the same device buffers: a graph is replayed only
+    # for the buffer addresses it was captured with
+    kd, td = torch.from_numpy(ks).cuda(), torch.from_numpy(ts).cuda()
+    return dict(pkg=pkg, raw=raw, ix=ix, w=w, h=h, offs=offs, q=q, ks=ks, ts=ts, kd=kd, td=td, N=N)
+
+
+def _search(env, qd, flags, out=None, stats=True):
+    r = env["ix"].search(qd, k=env["kd"], target=env["td"], k_max=10, schedule=(1, 0), with_stats=stats, out=out, flags=flags)
+    torch.cuda.synchronize()
+    return r
+
+
+def test_paths_are_bit_identical(env):
+    pkg = env["pkg"]
+    qd = torch.from_numpy(env["q"][0]).cuda()
+    i0, d0, s0 = _search(env, qd, pkg.SEARCH_HOST_ROUNDS)
+    assert s0["path"] == 0
+    i1, d1, s1 = _search(env, qd, pkg.SEARCH_NO_GRAPH)
+    assert s1["path"] == 1
+    out = (torch.empty_like(i0), torch.empty_like(d0))
+    paths = []
+    for rep in range(4):
+        out[0].fill_(-7)
+        out[1].fill_(-7.0)
+        i2, d2, s2 = _search(env, qd, 0, out=out)
+        paths.append(s2["path"])
+        assert torch.equal(i2, i0) and torch.equal(d2, d0), rep
+        for c in COUNTS:
+            assert s2[c] == s0[c] == s1[c], (c, s0[c], s1[c], s2[c])
+        assert s2["ms_scan"] > 0.0
+    assert torch.equal(i1, i0) and torch.equal(d1, d0)
+    assert 3 in paths and paths[-1] == 2, paths
+
+
+def test_graph_replay_reads_current_buffers(env):
+    pkg = env["pkg"]
+    qd = torch.from_numpy(env["q"][0]).cuda()
+    out = (torch.empty((len(env["ks"]), 10), dtype=torch.int64, device="cuda"),
+           torch.empty((len(env["ks"]), 10), dtype=torch.float32, device="cuda"))
+    for _ in range(3):  # make sure this shape is captured
+        _search(env, qd, 0, out=out, stats=False)
+    seen = []
+    for rep in range(6):
+        src = env["q"][rep % 3]
+        qd.copy_(torch.from_numpy(src).cuda())          # same buffer, new contents
+        ids, d = _search(env, qd, 0, out=out, stats=False)
+        got = (ids.clone(), d.clone())
+        # eager work in between: a host-driven search of the same queries on other buffers
+        e_ids, e_d, st = _search(env, torch.from_numpy(src).cuda(), pkg.SEARCH_HOST_ROUNDS)
+        assert st["path"] == 0
+        assert torch.equal(got[0], e_ids) and torch.equal(got[1], e_d), rep
+        seen.append(got[0].cpu().numpy())
+    assert not np.array_equal(seen[0], seen[1])  # the batches really differ
+
+
+def test_replayed_result_matches_oracle(env):
+    qd = torch.from_numpy(env["q"][1]).cuda()
+    out = (torch.empty((len(env["ks"]), 10), dtype=torch.int64, device="cuda"),
+           torch.empty((len(env["ks"]), 10), dtype=torch.float32, device="cuda"))
+    for _ in range(3):
+        ids, d, st = _search(env, qd, 0, out=out)
+    assert st["path"] == 2
+    ids, d = ids.cpu().numpy(), d.cpu().numpy().astype(np.float64)
+    xs, qs = O.znorm(env["raw"]), O.znorm(env["q"][1])
+    mu, sd = O.segment_stats(xs, 16)
+    t = O.build_tree(mu, sd, 128, 800, "median")
+    lb = O.lower_bound(*O.query_stats(qs, 16), O.leaf_boxes(mu, sd, t), 128)
+    order = O.visit_order(lb)
+    ld, li = O.leaf_knn(xs, t.leaves, qs, 10)
+    df = np.stack([O.mlp_forward(env["w"][f], qs, 128, env["h"]) for f in range(env["N"])], 1)
+    has = np.ones(env["N"], dtype=bool)
+    for k in (1, 10):
+        for tgt in (0.9, 1.0):
+            sel = np.nonzero((env["ks"] == k) & (env["ts"] == tgt))[0]
+            offs = env["offs"] if tgt < 1.0 else np.full(env["N"], np.inf)
+            r = O.leafi_search(lb[sel], order[sel], ld[sel], li[sel], k, has, df[sel] - offs[None], (1, 0))
+            fin = np.isfinite(r.dist)
+            assert np.all(np.abs(d[sel, :k][fin] - r.dist[fin]) <= 1e-4 * r.dist[fin])
+            for a, b in zip(*np.nonzero(ids[sel, :k] != r.ids)):
+                x = xs[ids[sel][a, b]].astype(np.float64)
+                dg = np.sqrt(((x - qs[sel[a]]) ** 2).sum())
+                assert abs(dg - r.dist[a, b]) <= 3e-5 * r.dist[a, b]
+            assert (ids[sel, k:] == -1).all()
