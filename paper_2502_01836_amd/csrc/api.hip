@@ -638,7 +638,8 @@ void search_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t
       path = 2;
     }
   const bool allowed = !(timed ? g.off_timed : g.off);
-  if (!exec && allowed && p.graph && g.pending == key) {
+  const bool seen = std::find(g.pending.begin(), g.pending.end(), key) != g.pending.end();
+  if (!exec && allowed && p.graph && seen) {
     exec = capture_planned(ix, key, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed);
     if (exec) {
       if (g.entries.size() >= static_cast<size_t>(kGraphCacheSize)) {
@@ -654,7 +655,10 @@ void search_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t
   if (exec) {
     HIP_OK(hipGraphLaunch(exec, st));
   } else {
-    g.pending = key;
+    if (!seen) {
+      if (g.pending.size() >= static_cast<size_t>(kGraphCacheSize)) g.pending.erase(g.pending.begin());
+      g.pending.push_back(key);
+    }
     enqueue_planned(ix, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed, st);
   }
   if (stats) {

@@ -91,7 +91,7 @@ struct GraphEntry {
 // Captured planned searches, keyed by everything baked into their launches.
 struct GraphCache {
   std::vector<GraphEntry> entries;
-  std::vector<uint64_t> pending;  // key of the last uncaptured planned batch
+  std::vector<std::vector<uint64_t>> pending;  // keys of recent uncaptured planned batches
   hipStream_t cap = nullptr;      // capture stream (default priority)
   bool off = false, off_timed = false;  // capture failed once: do not retry
   std::string why;

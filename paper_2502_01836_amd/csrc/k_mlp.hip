@@ -11,84 +11,105 @@ namespace leafi {
 
 namespace {
 
-// Inference tile: 64 rows (queries) x 256 hidden units per work-group; a
-// thread owns 4 consecutive hidden units for 16 rows (64 FP32 accumulators).
-// The row tile is staged in LDS, transposed, 64 inputs at a time.  Row r of
-// the tile is query qidx(r) and its result goes to out[qidx(r) * F + f]; the
-// arithmetic of one (query, filter) pair is the same whichever tile holds it.
+// Inference tile: 16 queries x all hidden units per work-group, on FP32
+// matrix cores (v_mfma_f32_16x16x4_f32: A = W1^T, 16 hidden units x 4 inputs;
+// B = 4 inputs x the 16 queries; FP32 accumulation).  Each of the 4
+// wavefronts owns 64 hidden units of every 256-unit chunk (four 16 x 16
+// accumulator tiles).  The queries are staged in LDS (row stride m + 4, so
+// the B reads of one instruction hit distinct banks).  The output layer is
+// summed per lane over its hidden units, then across the 4 lanes sharing a
+// query and across the wavefronts in a fixed order, so the result of a
+// (query, filter) pair does not depend on which tile or batch holds it.
+constexpr int kMlpQ = 16;
+
+size_t mlp_infer_lds(int m) { return (static_cast<size_t>(kMlpQ) * (m + 4) + 4 * kMlpQ) * sizeof(float); }
+
 template <typename RowIdx>
 __device__ inline void mlp_tile(const float *__restrict__ w, int F, int f, int m, int h,
-                                const float *__restrict__ x, int64_t r0, int64_t nrows, RowIdx qidx, float *out) {
-  __shared__ float xs[64][64 + 4];
-  const int tid = threadIdx.x;
-  const int jg = tid & 63, qg = tid >> 6;
+                                const float *__restrict__ x, int64_t r0, int64_t nrows, RowIdx qidx, float *out,
+                                float *xs) {
+  typedef float floatx4 __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int S = m + 4;
+  float *red = xs + kMlpQ * S;
   const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
   const float *W1 = w + f * P;
   const float *b1 = W1 + static_cast<int64_t>(h) * m;
   const float *w2 = b1 + h;
   const float b2 = w2[h];
-  float part[16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) part[v] = 0.0f;
+  __syncthreads();  // the previous tile's readers of xs / red are done
+  for (int e = tid; e < kMlpQ * m; e += blockDim.x) {
+    const int q = e / m, i = e - q * m;
+    xs[q * S + i] = r0 + q < nrows ? x[qidx(r0 + q) * m + i] : 0.0f;
+  }
+  __syncthreads();
+  const int c = lane & 15, kq = lane >> 4;
+  float part = 0.0f;
   for (int jb = 0; jb < h; jb += 256) {
-    const int j0 = jb + 4 * jg;
-    const bool jok = j0 < h;
-    float acc[4][16];
+    const int jw = jb + 64 * wave;  // this wavefront's first hidden unit
+    if (jw >= h) continue;          // uniform across the wavefront
+    floatx4 acc[4];
+    bool ok[4];
+    int col[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[u][v] = 0.0f;
-    for (int ib = 0; ib < m; ib += 64) {
-      __syncthreads();
-      for (int e = tid; e < 64 * 64; e += 256) {
-        int qq = e >> 6, i = e & 63;
-        float v = 0.0f;
-        if (r0 + qq < nrows && ib + i < m) v = x[qidx(r0 + qq) * m + ib + i];
-        xs[i][qq] = v;
-      }
-      __syncthreads();
-      if (jok) {
-        const int ilim = m - ib < 64 ? m - ib : 64;
-        for (int i = 0; i < ilim; ++i) {
-          // a filter's packed stride is odd, so these four stay scalar loads
-          const float *wr = W1 + static_cast<int64_t>(ib + i) * h + j0;
-          float wu[4] = {wr[0], wr[1], wr[2], wr[3]};
-#pragma unroll
-          for (int v4 = 0; v4 < 4; ++v4) {
-            float4 xv = *reinterpret_cast<const float4 *>(&xs[i][16 * qg + 4 * v4]);
-            float xq[4] = {xv.x, xv.y, xv.z, xv.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int c = 0; c < 4; ++c) acc[u][4 * v4 + c] = fmaf(wu[u], xq[c], acc[u][4 * v4 + c]);
-          }
-        }
-      }
+    for (int t = 0; t < 4; ++t) {
+      acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+      col[t] = jw + 16 * t + c;
+      ok[t] = col[t] < h;
+      if (!ok[t]) col[t] = 0;
     }
-    if (jok) {
+    const float *xq = xs + c * S + kq;
+    const float *wk = W1 + static_cast<int64_t>(kq) * h;
+    int i0 = 0;
+    // 16 inputs per step: all operand loads first, then the 16 products
+    for (; i0 + 16 <= m; i0 += 16) {
+      float av[4][4], bv[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        float bb = b1[j0 + u], ww = w2[j0 + u];
+        bv[u] = xq[i0 + 4 * u];
+        const float *wr = wk + static_cast<int64_t>(i0 + 4 * u) * h;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) part[v] = fmaf(ww, fmaxf(acc[u][v] + bb, 0.0f), part[v]);
+        for (int t = 0; t < 4; ++t) av[u][t] = ok[t] ? wr[col[t]] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][t], bv[u], acc[t], 0, 0, 0);
+    }
+    for (; i0 < m; i0 += 4) {
+      const float bv = xq[i0];
+      const float *wr = wk + static_cast<int64_t>(i0) * h;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float av = ok[t] ? wr[col[t]] : 0.0f;
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
       }
     }
+    // lane holds hidden units jw + 16 t + 4 kq + r of query c
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jw + 16 * t + 4 * kq + r;
+        if (j < h) part = fmaf(w2[j], fmaxf(acc[t][r] + b1[j], 0.0f), part);
+      }
   }
-#pragma unroll
-  for (int v = 0; v < 16; ++v) part[v] = wave_sum(part[v]);
-  if (jg == 0) {
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      int64_t r = r0 + 16 * qg + v;
-      if (r < nrows) out[qidx(r) * F + f] = part[v] + b2;
-    }
+  part += __shfl_xor(part, 16);
+  part += __shfl_xor(part, 32);
+  if (lane < 16) red[wave * 16 + lane] = part;
+  __syncthreads();
+  if (tid < kMlpQ) {
+    const int64_t r = r0 + tid;
+    if (r < nrows) out[qidx(r) * F + f] = ((red[tid] + red[16 + tid]) + (red[32 + tid] + red[48 + tid])) + b2;
   }
 }
 
-// d^f for every (query, filter): grid (F, ceil(nq / 64)).
+// d^f for every (query, filter): grid (F, tiles), 16 queries per tile.
 __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, int F, int m, int h,
                                                    const float *__restrict__ x, int64_t nq, float *out) {
-  mlp_tile(w, F, blockIdx.x, m, h, x, static_cast<int64_t>(blockIdx.y) * 64, nq, [](int64_t r) { return r; }, out);
+  extern __shared__ float xs[];
+  for (int64_t r0 = static_cast<int64_t>(blockIdx.y) * kMlpQ; r0 < nq; r0 += static_cast<int64_t>(gridDim.y) * kMlpQ)
+    mlp_tile(w, F, blockIdx.x, m, h, x, r0, nq, [](int64_t r) { return r; }, out, xs);
 }
 
 // d^f for listed pairs: filter f evaluates queries plist[f * stride + 0 ..
@@ -98,12 +119,12 @@ __global__ void __launch_bounds__(256) k_mlp_infer_pairs(const float *__restrict
                                                          const int32_t *__restrict__ plist,
                                                          const int32_t *__restrict__ pcnt, int64_t stride,
                                                          float *out) {
+  extern __shared__ float xs[];
   const int f = blockIdx.x;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 64;
   const int64_t cnt = pcnt[f];
-  if (r0 >= cnt) return;  // uniform for the work-group
   const int32_t *pl = plist + f * stride;
-  mlp_tile(w, F, f, m, h, x, r0, cnt, [pl](int64_t r) { return static_cast<int64_t>(pl[r]); }, out);
+  for (int64_t r0 = static_cast<int64_t>(blockIdx.y) * kMlpQ; r0 < cnt; r0 += static_cast<int64_t>(gridDim.y) * kMlpQ)
+    mlp_tile(w, F, f, m, h, x, r0, cnt, [pl](int64_t r) { return static_cast<int64_t>(pl[r]); }, out, xs);
 }
 
 constexpr int kTB = 64;  // training mini-batch capacity (columns of the LDS batch)
@@ -350,16 +371,24 @@ __global__ void __launch_bounds__(256) k_mlp_train(TrainArgs a) {
 
 void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, hipStream_t st) {
   if (nq <= 0 || F <= 0) return;
-  dim3 grid(F, static_cast<unsigned>(ceil_div(nq, 64)));
-  hipLaunchKernelGGL(k_mlp_infer, grid, dim3(256), 0, st, w, F, m, h, x, nq, out);
+  const int64_t tiles = ceil_div(nq, kMlpQ);
+  dim3 grid(F, static_cast<unsigned>(tiles < 65535 ? tiles : 65535));
+  const size_t lds = mlp_infer_lds(m);
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(k_mlp_infer, grid, dim3(256), lds, st, w, F, m, h, x, nq, out);
   LAUNCH_OK("mlp_infer");
 }
 
 void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int32_t *plist,
                             const int32_t *pcnt, int64_t stride, float *out, hipStream_t st) {
   if (F <= 0 || stride <= 0) return;
-  dim3 grid(F, static_cast<unsigned>(ceil_div(stride, 64)));
-  hipLaunchKernelGGL(k_mlp_infer_pairs, grid, dim3(256), 0, st, w, F, m, h, x, plist, pcnt, stride, out);
+  const int64_t tiles = ceil_div(stride, kMlpQ);
+  dim3 grid(F, static_cast<unsigned>(tiles < 65535 ? tiles : 65535));
+  const size_t lds = mlp_infer_lds(m);
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer_pairs),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(k_mlp_infer_pairs, grid, dim3(256), lds, st, w, F, m, h, x, plist, pcnt, stride, out);
   LAUNCH_OK("mlp_infer_pairs");
 }
 

@@ -109,9 +109,14 @@ def test_admission_under_tiny_memory_budget(served):
     pkg, ix = s["pkg"], s["ix"]
     with pytest.raises(pkg.LeafiError, match="admits no query"):
         pkg.Server(ix, k_max=5, max_slots=0, mem_budget=1000)
-    sv = pkg.Server(ix, k_max=5, max_slots=0, mem_budget=300_000)
+    # slots = floor(budget / per-slot bytes): linear in the budget
+    big = pkg.Server(ix, k_max=5, max_slots=0, mem_budget=300_000)
+    s_big = big.slots
+    big.close()
+    sv = pkg.Server(ix, k_max=5, max_slots=0, mem_budget=30_000)
     try:
         assert 1 <= sv.slots <= 8
+        assert 10 * sv.slots <= s_big <= 10 * (sv.slots + 1)
         n = 40
         ids, d, lat, rep = sv.replay(s["q"][:n], s["arrivals"][:n] * 0.0, s["ks"][:n], s["targets"][:n])
         assert rep["completed"] == n and rep["max_active"] <= sv.slots
