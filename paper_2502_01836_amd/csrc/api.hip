@@ -129,6 +129,7 @@ RoundBufs views(Workspace &w) {
   b.item_bound = w.item_bound.get();
   b.fb_q = w.fb_q.get();
   b.fb_leaf = w.fb_leaf.get();
+  b.chunk = kChunkRows;
   b.ctl = w.ctl.get();
   return b;
 }
@@ -185,8 +186,9 @@ void ensure_queries(leafi_index *ix, int64_t nq, int kmax) {
   w.ctl.reserve(kCtlCount);
   if (w.h_ctl.size() < static_cast<size_t>(kCtlCount)) w.h_ctl.resize(kCtlCount);
   if (!w.ev0) {
-    HIP_OK(hipEventCreate(&w.ev0));
-    HIP_OK(hipEventCreate(&w.ev1));
+    // timing-only events: no system-scope fence (no cache write-back) around the kernels they bracket
+    HIP_OK(hipEventCreateWithFlags(&w.ev0, hipEventDisableSystemFence));
+    HIP_OK(hipEventCreateWithFlags(&w.ev1, hipEventDisableSystemFence));
   }
 }
 
@@ -245,18 +247,35 @@ constexpr double kPlannedLimit = 8.0 * (1 << 30);
 // items_bound >= 0 is an upper bound of the round's items: buffers are sized
 // from it and nothing is read back.  Otherwise the counts are read back
 // first.  Returns the item count when it was read back, else -1.
-int64_t tiles_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, int mq) {
+// Rows per scan tile for a pass: the preferred size, doubled while the
+// per-item merge of the chunk candidate lists (chunks x kprime keys) would
+// exceed kMaxRerankKeys.
+constexpr int kMaxRerankKeys = 4096;
+constexpr int kFp32ChunkRows = 128;  // the FP32 scan streams 4 m bytes per row: finer tiles
+int pick_chunk(const leafi_index *ix, int kprime, int pref) {
+  int chunk = pref;
+  while (chunk < (kRowAlign << (kChunkSizes - 1)) &&
+         static_cast<int64_t>(ix->max_chunks_for(chunk)) * kprime > kMaxRerankKeys)
+    chunk *= 2;
+  return chunk;
+}
+int pass_chunk(const leafi_index *ix, bool bf16, int kprime) {
+  return pick_chunk(ix, kprime, bf16 ? kChunkRows : kFp32ChunkRows);
+}
+
+int64_t tiles_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, int mq, int chunk) {
   // every leaf has at most nq items, and at most items_bound in all
-  const int64_t a = ceil_div(items_bound, mq) * ix->max_chunks + ix->total_chunks;
-  const int64_t b = ceil_div(nq, mq) * ix->total_chunks;
+  const int64_t a = ceil_div(items_bound, mq) * ix->max_chunks_for(chunk) + ix->total_chunks_for(chunk);
+  const int64_t b = ceil_div(nq, mq) * ix->total_chunks_for(chunk);
   return std::min(a, b);
 }
 
-double round_bytes_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, int kprime, int kmax) {
+double round_bytes_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, bool bf16, int kprime, int kmax) {
   int mq, cap;
   scan_geometry(kprime, &mq, &cap);
+  const int chunk = pass_chunk(ix, bf16, kprime);
   return static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
-         static_cast<double>(tiles_bound(ix, nq, items_bound, mq)) * mq * kprime * 8.0;
+         static_cast<double>(tiles_bound(ix, nq, items_bound, mq, chunk)) * mq * kprime * 8.0;
 }
 
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
@@ -267,9 +286,12 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   int mq, cap;
   scan_geometry(kprime, &mq, &cap);
   (void)cap;
-  launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, views(w), st);
+  const int chunk = pass_chunk(ix, bf16, kprime);
+  RoundBufs b0 = views(w);
+  b0.chunk = chunk;
+  launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b0, st);
   int64_t items = -1, tiles;
-  const int64_t tb = items_bound >= 0 ? tiles_bound(ix, nq, items_bound, mq) : -1;
+  const int64_t tb = items_bound >= 0 ? tiles_bound(ix, nq, items_bound, mq, chunk) : -1;
   const double bytes = items_bound >= 0 ? static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
                                               static_cast<double>(tb) * mq * kprime * 8.0
                                         : 0.0;
@@ -287,6 +309,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   ensure_items(ix, items >= 0 ? items : std::max<int64_t>(items_bound, 1), kmax);
   w.cand.reserve(static_cast<size_t>(std::max<int64_t>(tiles, 1)) * mq * kprime);
   RoundBufs b = views(w);
+  b.chunk = chunk;
   StoreView s = store_view(ix);
   QueryView q = query_view(w);
   launch_scatter(nq, ix->N, b, st);
@@ -300,7 +323,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   if (e1) HIP_OK(hipEventRecord(e1, st));
   int64_t ib = items >= 0 ? items : std::max<int64_t>(items_bound, 1);
   int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * 16));
-  launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks, st);
+  launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks_for(chunk), st);
   return items;
 }
 
@@ -369,7 +392,7 @@ void eval_filters(leafi_index *ix, int64_t nq, hipStream_t st) {
   launch_filter_pairs(nq, ix->N, w.lb.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
                       w.pcnt.get(), st);
   launch_mlp_infer_pairs(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), nq,
-                         w.dfilt.get(), st);
+                         w.ptile.get(), w.dfilt.get(), st);
 }
 
 void launch_round_worklist(leafi_index *ix, int64_t nq, int want, bool f_now, hipStream_t st) {
@@ -405,6 +428,7 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
   if (use_f) {
     w.plist.reserve(static_cast<size_t>(F) * nq);
     w.pcnt.reserve(F);
+    w.ptile.reserve(F + 1);
   }
   begin_batch(ix, raw, nq, k_dev, t_dev, p, use_f, st);
   const int kprime_fb = default_kprime(p.kmax, false);
@@ -468,8 +492,8 @@ bool can_plan(const leafi_index *ix, int64_t nq, const SearchPlan &p) {
   const int kprime_fb = default_kprime(p.kmax, false);
   for (int r = 0; r < R; ++r) {
     const int64_t bnd = planned_bound(ix, nq, p, r);
-    if (round_bytes_bound(ix, nq, bnd, p.kprime, p.kmax) > kPlannedLimit) return false;
-    if (round_bytes_bound(ix, nq, bnd, kprime_fb, p.kmax) > kPlannedLimit) return false;
+    if (round_bytes_bound(ix, nq, bnd, true, p.kprime, p.kmax) > kPlannedLimit) return false;
+    if (round_bytes_bound(ix, nq, bnd, false, kprime_fb, p.kmax) > kPlannedLimit) return false;
   }
   return true;
 }
@@ -483,6 +507,7 @@ void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_
   if (use_f) {
     w.plist.reserve(static_cast<size_t>(F) * nq);
     w.pcnt.reserve(F);
+    w.ptile.reserve(F + 1);
   }
   const int kprime_fb = default_kprime(p.kmax, false);
   int64_t items = 1;
@@ -490,17 +515,19 @@ void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_
   for (int r = 0; r < planned_rounds(p); ++r) {
     const int64_t bnd = planned_bound(ix, nq, p, r);
     items = std::max(items, bnd);
-    for (int kp : {p.kprime, kprime_fb}) {
+    for (bool bf : {true, false}) {
+      const int kp = bf ? p.kprime : kprime_fb;
       int mq, cap;
       scan_geometry(kp, &mq, &cap);
-      cand = std::max(cand, static_cast<size_t>(std::max<int64_t>(tiles_bound(ix, nq, bnd, mq), 1)) * mq * kp);
+      const int chunk = pass_chunk(ix, bf, kp);
+      cand = std::max(cand, static_cast<size_t>(std::max<int64_t>(tiles_bound(ix, nq, bnd, mq, chunk), 1)) * mq * kp);
     }
   }
   ensure_items(ix, items, p.kmax);
   w.cand.reserve(cand);
   if (w.sev.empty()) {
     w.sev.resize(2 * kMaxPlannedRounds);
-    for (auto &e : w.sev) HIP_OK(hipEventCreate(&e));
+    for (auto &e : w.sev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
 }
 
@@ -561,7 +588,7 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
   for (int64_t v : {nq, static_cast<int64_t>(p.kmax), static_cast<int64_t>(p.kprime), static_cast<int64_t>(use_f),
                     static_cast<int64_t>(timed), static_cast<int64_t>(ix->N), static_cast<int64_t>(ix->m),
                     static_cast<int64_t>(ix->S), static_cast<int64_t>(ix->filt.F), static_cast<int64_t>(ix->filt.h),
-                    static_cast<int64_t>(ix->cal.pairs()), static_cast<int64_t>(ix->max_chunks), ix->total_chunks})
+                    static_cast<int64_t>(ix->cal.pairs()), ix->rows})
     k.push_back(static_cast<uint64_t>(v));
   for (int r : p.schedule) k.push_back(static_cast<uint64_t>(r));
   for (const void *a : {static_cast<const void *>(raw), static_cast<const void *>(k_dev),
@@ -573,7 +600,7 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
                         static_cast<const void *>(ix->boxes.get()), static_cast<const void *>(ix->rowid.get()),
                         static_cast<const void *>(ix->filt.w.get()), static_cast<const void *>(ix->filt.filt_of_leaf.get()),
                         static_cast<const void *>(ix->cal.offsets.get()), static_cast<const void *>(ix->cal.pair_k.get()),
-                        static_cast<const void *>(ix->cal.pair_t.get())})
+                        static_cast<const void *>(ix->cal.pair_t.get()), static_cast<const void *>(w.ptile.get())})
     ptr(a);
   if (timed)
     for (hipEvent_t e : w.sev) ptr(e);
@@ -804,14 +831,21 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     std::vector<int32_t> leaf_of_row(rows);
     std::vector<int64_t> members;
     members.reserve(n);
-    int max_chunks = 1;
-    int64_t total_chunks = 0;
     for (int L = 0; L < N; ++L) {
       for (int64_t r = off[L]; r < off[L + 1]; ++r) leaf_of_row[r] = L;
       for (size_t i = 0; i < tree.leaves[L].size(); ++i) src[off[L] + i] = tree.leaves[L][i];
       members.insert(members.end(), tree.leaves[L].begin(), tree.leaves[L].end());
-      max_chunks = std::max<int>(max_chunks, static_cast<int>(ceil_div(off[L + 1] - off[L], kChunkRows)));
-      total_chunks += ceil_div(off[L + 1] - off[L], kChunkRows);
+    }
+    int max_chunks[kChunkSizes];
+    int64_t total_chunks[kChunkSizes];
+    for (int j = 0; j < kChunkSizes; ++j) {
+      max_chunks[j] = 1;
+      total_chunks[j] = 0;
+      for (int L = 0; L < N; ++L) {
+        const int64_t c = ceil_div(off[L + 1] - off[L], static_cast<int64_t>(kRowAlign) << j);
+        max_chunks[j] = std::max<int>(max_chunks[j], static_cast<int>(c));
+        total_chunks[j] += c;
+      }
     }
     std::vector<float> boxes = leaf_boxes(hmu, hsd, S, tree);
     // 4. device leaf store
@@ -841,8 +875,10 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     ix->S = S;
     ix->N = N;
     ix->rows = rows;
-    ix->max_chunks = max_chunks;
-    ix->total_chunks = total_chunks;
+    for (int j = 0; j < kChunkSizes; ++j) {
+      ix->chunks_max[j] = max_chunks[j];
+      ix->chunks_total[j] = total_chunks[j];
+    }
     ix->h_leaf_off = std::move(off);
     ix->h_leaf_n = std::move(lsz);
     ix->h_members = std::move(members);

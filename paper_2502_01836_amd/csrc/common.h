@@ -80,8 +80,15 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // Rows of each leaf are padded to a multiple of this in the leaf store (an
 // even number of the scan's 64-row blocks, so its unrolled loop has no tail).
 constexpr int kRowAlign = 128;
-// Rows of one scan tile (multiple of kRowAlign).
+// Rows of one scan tile of the BF16 scan (multiple of kRowAlign); passes may
+// use any of the kChunkSizes sizes kRowAlign << j.
 constexpr int kChunkRows = 1024;
+constexpr int kChunkSizes = 6;  // 128 .. 4096 rows
+inline int chunk_log(int chunk) {
+  int j = 0;
+  while ((kRowAlign << j) < chunk && j < kChunkSizes - 1) ++j;
+  return j;
+}
 // Relative slack applied to tau before a summary bound may prune (covers the
 // fp32 evaluation of the bound).
 constexpr float kLbSlack = 1e-5f;

@@ -118,6 +118,7 @@ struct Workspace {
   DevBuf<float> item_bound;
   DevBuf<uint64_t> cand;
   DevBuf<int32_t> plist, pcnt;  // filter pairs to evaluate
+  DevBuf<int32_t> ptile;        // prefix of the filters' 16-query inference tiles [F + 1]
   DevBuf<int64_t> ctl;
   std::vector<int64_t> h_ctl;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -135,8 +136,11 @@ struct leafi_index {
   int S = 0;
   int N = 0;
   int64_t rows = 0;     // padded rows
-  int max_chunks = 1;   // chunks of the largest leaf
-  int64_t total_chunks = 0;  // scan chunks over all leaves
+  // per scan chunk size kRowAlign << j: chunks of the largest leaf, and over all leaves
+  int chunks_max[leafi::kChunkSizes] = {};
+  int64_t chunks_total[leafi::kChunkSizes] = {};
+  int max_chunks_for(int chunk) const { return chunks_max[leafi::chunk_log(chunk)]; }
+  int64_t total_chunks_for(int chunk) const { return chunks_total[leafi::chunk_log(chunk)]; }
   // leaf store (device)
   leafi::DevBuf<float> x32, xn16, boxes, leaf_eps;
   leafi::DevBuf<uint16_t> x16;

@@ -4,6 +4,8 @@
 //
 // Packed filter layout (P = h*m + 2h + 1 floats): W1 input-major (element
 // (i, j) = input i, hidden unit j at i*h + j), b1 [h], w2 [h], b2.
+#include <algorithm>
+
 #include "device_util.h"
 #include "kernels.h"
 
@@ -112,19 +114,54 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, 
     mlp_tile(w, F, blockIdx.x, m, h, x, r0, nq, [](int64_t r) { return r; }, out, xs);
 }
 
+// Exclusive prefix of the filters' tile counts ceil(pcnt[f] / 16) (one
+// work-group; tile_prefix[F] = total).
+__global__ void __launch_bounds__(1024) k_mlp_tiles(int F, const int32_t *__restrict__ pcnt, int32_t *tile_prefix) {
+  __shared__ int32_t part[1024];
+  const int tid = threadIdx.x;
+  const int per = (F + 1023) / 1024;
+  const int f0 = tid * per, f1 = min(F, f0 + per);
+  int sum = 0;
+  for (int f = f0; f < f1; ++f) sum += (pcnt[f] + kMlpQ - 1) / kMlpQ;
+  part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - sum;
+  for (int f = f0; f < f1; ++f) {
+    tile_prefix[f] = run;
+    run += (pcnt[f] + kMlpQ - 1) / kMlpQ;
+  }
+  if (tid == 1023) tile_prefix[F] = part[1023];
+}
+
 // d^f for listed pairs: filter f evaluates queries plist[f * stride + 0 ..
-// pcnt[f]); work-groups past a filter's count exit at once.
+// pcnt[f]).  A persistent grid walks the non-empty tiles of all filters.
 __global__ void __launch_bounds__(256) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
                                                          const float *__restrict__ x,
                                                          const int32_t *__restrict__ plist,
                                                          const int32_t *__restrict__ pcnt, int64_t stride,
-                                                         float *out) {
+                                                         const int32_t *__restrict__ tile_prefix, float *out) {
   extern __shared__ float xs[];
-  const int f = blockIdx.x;
-  const int64_t cnt = pcnt[f];
-  const int32_t *pl = plist + f * stride;
-  for (int64_t r0 = static_cast<int64_t>(blockIdx.y) * kMlpQ; r0 < cnt; r0 += static_cast<int64_t>(gridDim.y) * kMlpQ)
-    mlp_tile(w, F, f, m, h, x, r0, cnt, [pl](int64_t r) { return static_cast<int64_t>(pl[r]); }, out, xs);
+  const int total = tile_prefix[F];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    // filter of tile t: the last f with tile_prefix[f] <= t
+    int lo = 0, hi = F - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_prefix[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const int f = lo;
+    const int64_t r0 = static_cast<int64_t>(t - tile_prefix[f]) * kMlpQ;
+    const int32_t *pl = plist + f * stride;
+    mlp_tile(w, F, f, m, h, x, r0, static_cast<int64_t>(pcnt[f]), [pl](int64_t r) { return static_cast<int64_t>(pl[r]); },
+             out, xs);
+  }
 }
 
 constexpr int kTB = 64;  // training mini-batch capacity (columns of the LDS batch)
@@ -381,14 +418,24 @@ void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64
 }
 
 void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int32_t *plist,
-                            const int32_t *pcnt, int64_t stride, float *out, hipStream_t st) {
+                            const int32_t *pcnt, int64_t stride, int32_t *tile_prefix, float *out, hipStream_t st) {
   if (F <= 0 || stride <= 0) return;
-  const int64_t tiles = ceil_div(stride, kMlpQ);
-  dim3 grid(F, static_cast<unsigned>(tiles < 65535 ? tiles : 65535));
+  hipLaunchKernelGGL(k_mlp_tiles, dim3(1), dim3(1024), 0, st, F, pcnt, tile_prefix);
+  LAUNCH_OK("mlp_tiles");
+  // persistent grid: a few work-groups per CU, never more than the tiles can be
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  const int64_t tiles_bound = static_cast<int64_t>(F) * ceil_div(stride, kMlpQ);
+  const int grid = static_cast<int>(std::min<int64_t>(tiles_bound, static_cast<int64_t>(cus) * 4));
   const size_t lds = mlp_infer_lds(m);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer_pairs),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  hipLaunchKernelGGL(k_mlp_infer_pairs, grid, dim3(256), lds, st, w, F, m, h, x, plist, pcnt, stride, out);
+  hipLaunchKernelGGL(k_mlp_infer_pairs, dim3(grid), dim3(256), lds, st, w, F, m, h, x, plist, pcnt, stride,
+                     tile_prefix, out);
   LAUNCH_OK("mlp_infer_pairs");
 }
 

@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
   int64_t si = 0, stl = 0, rows = 0;
   for (int L = l0; L < l1; ++L) {
     int c = b.leaf_cnt[L];
-    int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + kChunkRows - 1) / kChunkRows;
+    int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + b.chunk - 1) / b.chunk;
     si += c;
     stl += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
     if (c > 0) rows += leaf_off[L + 1] - leaf_off[L];
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
   int64_t ri = part_i[tid] - si, rt = part_t[tid] - stl;
   for (int L = l0; L < l1; ++L) {
     int c = b.leaf_cnt[L];
-    int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + kChunkRows - 1) / kChunkRows;
+    int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + b.chunk - 1) / b.chunk;
     b.leaf_istart[L] = static_cast<int32_t>(ri);
     b.tile_start[L] = static_cast<int32_t>(rt);
     b.leaf_fill[L] = 0;
@@ -217,15 +217,20 @@ __global__ void __launch_bounds__(256) k_scatter(int64_t nq, int N, RoundBufs b)
 // One wavefront per query: merge the round's item results into the running
 // top-k (sorted by (FP64 distance, row)), refresh tau and, in a regular
 // round, queue every item whose certificate bound does not exceed the new tau
-// for an exact FP32 rescan.
-__global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int KM, int check_cert,
+// for an exact FP32 rescan.  The running top-k and as many items as fit the
+// wavefront's LDS slice of C entries (KM slots per item) are gathered at once
+// and sorted together, so a query with many items needs few passes.  With
+// `dedupe`, a row met twice (a rescan of a leaf already merged) is kept once.
+__global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int KM, int C, int check_cert,
                                                      int dedupe, RoundBufs b) {
   extern __shared__ unsigned char smem_raw[];
   // four wavefronts per work-group, each with its own LDS slice and query
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  unsigned char *mine = smem_raw + static_cast<size_t>(wave) * 2 * KM * (sizeof(double) + sizeof(uint32_t));
+  unsigned char *mine = smem_raw + static_cast<size_t>(wave) * C * (sizeof(double) + sizeof(uint32_t));
   double *vals = reinterpret_cast<double *>(mine);
-  uint32_t *tags = reinterpret_cast<uint32_t *>(mine + sizeof(double) * 2 * KM);
+  uint32_t *tags = reinterpret_cast<uint32_t *>(mine + sizeof(double) * C);
+  const int per = (C - KM) / KM;  // items per pass
+  const uint64_t lt = (1ull << lane) - 1ull;
   for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
     int n_it = b.qitem_cnt[q];
     if (n_it > 0) {
@@ -235,26 +240,52 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
         vals[i] = i < have ? b.res_d2[q * kmax + i] : __builtin_inf();
         tags[i] = i < have ? static_cast<uint32_t>(b.res_row[q * kmax + i]) : 0xffffffffu;
       }
-      for (int it = 0; it < n_it; ++it) {
-        int idx = b.qitem_idx[q * N + it];
-        int c = b.item_cnt[idx];
-        for (int i = lane; i < KM; i += kWave) {
-          vals[KM + i] = i < c ? b.item_d2[static_cast<int64_t>(idx) * kmax + i] : __builtin_inf();
-          tags[KM + i] = i < c ? static_cast<uint32_t>(b.item_row[static_cast<int64_t>(idx) * kmax + i]) : 0xffffffffu;
+      for (int it0 = 0; it0 < n_it; it0 += per) {
+        const int nb = n_it - it0 < per ? n_it - it0 : per;
+        const int n = pow2_at_least(KM * (nb + 1));
+        for (int e = lane; e < n - KM; e += kWave) {
+          const int j = e / KM, i = e - j * KM;
+          double v = __builtin_inf();
+          uint32_t t = 0xffffffffu;
+          if (j < nb) {
+            const int idx = b.qitem_idx[q * N + it0 + j];
+            if (i < b.item_cnt[idx]) {
+              v = b.item_d2[static_cast<int64_t>(idx) * kmax + i];
+              t = static_cast<uint32_t>(b.item_row[static_cast<int64_t>(idx) * kmax + i]);
+            }
+          }
+          vals[KM + e] = v;
+          tags[KM + e] = t;
         }
         wave_lds_sync();
-        wave_sort_dbl_tag(vals, tags, 2 * KM, lane);
-        if (dedupe && lane == 0) {
-          int w = 0;
-          for (int r = 0; r < 2 * KM; ++r) {
-            if (r > 0 && tags[r] != 0xffffffffu && tags[r] == tags[w - 1]) continue;
-            vals[w] = vals[r];
-            tags[w] = tags[r];
-            ++w;
+        wave_sort_dbl_tag(vals, tags, n, lane);
+        if (dedupe) {
+          // equal rows carry equal distances, so copies are adjacent: keep
+          // the first of each run, compacted in order into the first slots
+          int written = 0;
+          for (int r0 = 0; r0 < n && written < KM; r0 += kWave) {
+            const int r = r0 + lane;
+            double v = 0.0;
+            uint32_t t = 0xffffffffu;
+            bool keep = false;
+            if (r < n) {
+              v = vals[r];
+              t = tags[r];
+              keep = !(r > 0 && t != 0xffffffffu && t == tags[r - 1]);
+            }
+            const uint64_t mk = __ballot(keep);
+            wave_lds_sync();
+            const int pos = written + __popcll(mk & lt);
+            if (keep && pos < KM) {
+              vals[pos] = v;
+              tags[pos] = t;
+            }
+            written += __popcll(mk);
+            wave_lds_sync();
           }
-          for (int r = w; r < 2 * KM; ++r) {
-            vals[r] = __builtin_inf();
-            tags[r] = 0xffffffffu;
+          for (int i = written + lane; i < KM; i += kWave) {
+            vals[i] = __builtin_inf();
+            tags[i] = 0xffffffffu;
           }
         }
         wave_lds_sync();
@@ -416,11 +447,16 @@ void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
 }
 
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st) {
-  int KM = pow2_at_least(kmax < 2 ? 2 : kmax);
-  size_t lds = 4 * static_cast<size_t>(2 * KM) * (sizeof(double) + sizeof(uint32_t));
+  const int KM = pow2_at_least(kmax < 2 ? 2 : kmax);
+  // LDS slice per wavefront: the running top-k plus up to 255 items' lists
+  // (at most 256 entries unless 2 KM alone is larger)
+  const int C = std::max(2 * KM, std::min(pow2_at_least(KM * (N + 1)), 256));
+  size_t lds = 4 * static_cast<size_t>(C) * (sizeof(double) + sizeof(uint32_t));
   int64_t blocks = ceil_div(nq, 4);
   int grid = static_cast<int>(blocks < 65536 ? blocks : 65536);
-  hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, KM, check_cert ? 1 : 0,
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_merge),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, KM, C, check_cert ? 1 : 0,
                      dedupe ? 1 : 0, b);
   LAUNCH_OK("query_merge");
 }

@@ -35,6 +35,18 @@ struct TileInfo {
   int p0, nqt;
 };
 
+// Work-groups are dispatched to the 8 XCDs round-robin (work-group i runs
+// on XCD i mod 8).  With a grid that is a multiple of 8, renumber them so
+// that each XCD takes a contiguous range of tiles per pass of the persistent
+// loop: neighbouring tiles (other query groups of the same rows) then share
+// an L2.
+constexpr int kXcds = 8;
+__device__ inline int xcd_block() {
+  const int per = gridDim.x / kXcds;
+  if (per * kXcds != static_cast<int>(gridDim.x)) return blockIdx.x;
+  return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
 __device__ inline TileInfo decode_tile(int t, const StoreView &s, const RoundBufs &b, int mq) {
   // leaf L with tile_start[L] <= t < tile_start[L + 1]
   int lo = 0, hi = s.N;  // invariant: tile_start[lo] <= t < tile_start[hi]
@@ -45,12 +57,13 @@ __device__ inline TileInfo decode_tile(int t, const StoreView &s, const RoundBuf
   TileInfo ti;
   ti.L = lo;
   int64_t off0 = s.leaf_off[lo], off1 = s.leaf_off[lo + 1];
-  ti.C = static_cast<int>((off1 - off0 + kChunkRows - 1) / kChunkRows);
-  int local = t - b.tile_start[lo];
-  ti.g = local / ti.C;
-  ti.c = local - ti.g * ti.C;
-  ti.r0 = off0 + static_cast<int64_t>(ti.c) * kChunkRows;
-  ti.r1 = ti.r0 + kChunkRows < off1 ? ti.r0 + kChunkRows : off1;
+  ti.C = static_cast<int>((off1 - off0 + b.chunk - 1) / b.chunk);
+  const int G = (b.leaf_istart[lo + 1] - b.leaf_istart[lo] + mq - 1) / mq;
+  int local = t - b.tile_start[lo];  // chunk-major: local = c * G + g (see tile_of)
+  ti.c = local / G;
+  ti.g = local - ti.c * G;
+  ti.r0 = off0 + static_cast<int64_t>(ti.c) * b.chunk;
+  ti.r1 = ti.r0 + b.chunk < off1 ? ti.r0 + b.chunk : off1;
   ti.real_end = off0 + s.leaf_n[lo];
   ti.p0 = b.leaf_istart[lo] + ti.g * mq;
   int left = b.leaf_istart[lo + 1] - ti.p0;
@@ -178,7 +191,7 @@ __global__ void __launch_bounds__(256) k_scan_bf16(StoreView s, QueryView qv, Ro
   const int wave = threadIdx.x / kWave;
   const int m = s.m;
   const int n_tiles = static_cast<int>(b.ctl[kCtlTiles]);
-  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  for (int t = xcd_block(); t < n_tiles; t += gridDim.x) {
     TileInfo ti = decode_tile(t, s, b, MQ);
     if (threadIdx.x < MQ) {
       cnt[threadIdx.x] = 0;
@@ -234,7 +247,7 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
   const int sub = lane & 15, rsel = lane >> 4;
   const int m = s.m;  // == 16 * EPL
   const int n_tiles = static_cast<int>(b.ctl[kCtlTiles]);
-  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  for (int t = xcd_block(); t < n_tiles; t += gridDim.x) {
     TileInfo ti = decode_tile(t, s, b, mq);
     if (threadIdx.x < mq) {
       cnt[threadIdx.x] = 0;
@@ -310,15 +323,15 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
     int k = b.kq[q];
     int pos = item - b.leaf_istart[L];
     int g = pos / mq, j = pos - (pos / mq) * mq;
-    int C = static_cast<int>((s.leaf_off[L + 1] - s.leaf_off[L] + kChunkRows - 1) / kChunkRows);
+    int C = static_cast<int>((s.leaf_off[L + 1] - s.leaf_off[L] + b.chunk - 1) / b.chunk);
+    const int G = (b.leaf_istart[L + 1] - b.leaf_istart[L] + mq - 1) / mq;
     int n = C * kprime;
     int P = pow2_at_least(n < 2 ? 2 : n);
-    int64_t tile0 = b.tile_start[L] + static_cast<int64_t>(g) * C;
     for (int e = lane; e < P; e += kWave) {
       uint64_t v = kKeyMax;
       if (e < n) {
         int c = e / kprime;
-        v = cand[((tile0 + c) * mq + j) * kprime + (e - c * kprime)];
+        v = cand[(tile_of(b.tile_start, L, g, c, G) * mq + j) * kprime + (e - c * kprime)];
       }
       buf[e] = v;
     }
@@ -418,7 +431,8 @@ int resident_grid(K kern, size_t lds, int want) {
   int per_cu = 0;
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), 256, lds));
   int g = cus * (per_cu > 0 ? per_cu : 1);
-  return want < g ? (want > 0 ? want : 1) : g;
+  g = want < g ? (want > 0 ? want : 1) : g;
+  return g >= kXcds ? g / kXcds * kXcds : g;  // a multiple of the XCD count (see xcd_block)
 }
 
 template <int KS, int QB>

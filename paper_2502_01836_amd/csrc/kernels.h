@@ -73,7 +73,16 @@ struct RoundBufs {
   int32_t *fb_leaf;
   // control: see Ctl
   int64_t *ctl;
+  // rows per scan tile of the pass in flight (a multiple of kRowAlign)
+  int32_t chunk;
 };
+
+// Tile of item group g (queries g*mq ..) and row chunk c of leaf L: chunk-major
+// (the groups of one chunk are consecutive tiles, so work-groups that read
+// the same rows run side by side on one XCD and share its L2).
+__host__ __device__ inline int64_t tile_of(const int32_t *tile_start, int L, int g, int c, int G) {
+  return static_cast<int64_t>(tile_start[L]) + static_cast<int64_t>(c) * G + g;
+}
 
 enum Ctl : int {
   kCtlItems = 0,      // items this round
@@ -183,8 +192,10 @@ void launch_items_to_leaf_knn(int64_t n_items, int N, int k, int kmax, const int
 void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, hipStream_t st);
 
 // d^f for listed pairs only (filter f: queries plist[f * stride + 0 .. pcnt[f])).
+// tile_prefix [F + 1] is scratch: a first launch lays out the non-empty
+// 16-query tiles of all filters, a persistent grid then walks them.
 void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int32_t *plist,
-                            const int32_t *pcnt, int64_t stride, float *out, hipStream_t st);
+                            const int32_t *pcnt, int64_t stride, int32_t *tile_prefix, float *out, hipStream_t st);
 
 // Per-query offset row lookup for (k, target) pairs.
 // k is clamped to [1, kmax].

@@ -148,7 +148,7 @@ void leafi_server::engine_round(int n_new, int &n_active) {
     launch_filter_pairs(slots, N, w.lb.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
                         w.pcnt.get(), st, qround.get());
     launch_mlp_infer_pairs(ix->filt.w.get(), F, m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), slots,
-                           w.dfilt.get(), st);
+                           w.ptile.get(), w.dfilt.get(), st);
   }
   reset_round(ix, st);
   launch_worklist(slots, N, w.lb.get(), w.order.get(), w.dfilt.get(), std::max(F, 1),
@@ -316,7 +316,7 @@ int leafi_server_create(leafi_index *ix, const leafi_server_opts *o, leafi_serve
     // of a round's item and candidate buffers
     const double N = ix->N, m = ix->m, F = std::max(ix->filt.F, 1), k = o->k_max;
     const double per_slot = m * 10.0 + ix->S * 8.0 + N * 16.0 + F * 8.0 + k * 12.0 + 64.0 +
-                            N * (k * 12.0 + 32.0) + N * ix->max_chunks * 4.0 * sv->kprime * 8.0 / 16.0;
+                            N * (k * 12.0 + 32.0) + N * ix->max_chunks_for(kChunkRows) * 4.0 * sv->kprime * 8.0 / 16.0;
     int by_mem = o->mem_budget > 0 ? static_cast<int>(static_cast<double>(o->mem_budget) / per_slot) : (1 << 30);
     int slots = o->max_slots > 0 ? std::min(o->max_slots, by_mem) : by_mem;
     LEAFI_CHECK_ARG(slots >= 1, "memory budget admits no query");
@@ -327,6 +327,7 @@ int leafi_server_create(leafi_index *ix, const leafi_server_opts *o, leafi_serve
     if (sv->use_f) {
       w.plist.reserve(static_cast<size_t>(ix->filt.F) * slots);
       w.pcnt.reserve(ix->filt.F);
+      w.ptile.reserve(ix->filt.F + 1);
     }
     sv->state.alloc(slots);
     sv->qround.alloc(slots);
