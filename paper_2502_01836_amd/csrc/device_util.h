@@ -47,6 +47,16 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, kWave);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
 // Orders LDS traffic of one wavefront between stages of a cooperative
 // algorithm (lanes read what other lanes wrote in the previous stage).
 __device__ __forceinline__ void wave_lds_sync() {

@@ -41,10 +41,12 @@ struct TileInfo {
 // loop: neighbouring tiles (other query groups of the same rows) then share
 // an L2.
 constexpr int kXcds = 8;
-__device__ inline int xcd_block() {
-  const int per = gridDim.x / kXcds;
-  if (per * kXcds != static_cast<int>(gridDim.x)) return blockIdx.x;
-  return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+constexpr int kXcdRun = 4;  // consecutive tiles kept on one XCD
+// j-th tile (j = 0, 1, ...) of the work-groups of XCD x: runs of kXcdRun
+// consecutive tiles, dealt to the XCDs in turn, so every XCD gets an equal
+// share of the tiles (to within one run) wherever the tile count ends.
+__device__ inline int64_t xcd_tile(int64_t j, int x) {
+  return ((j / kXcdRun) * kXcds + x) * kXcdRun + j % kXcdRun;
 }
 
 __device__ inline TileInfo decode_tile(int t, const StoreView &s, const RoundBufs &b, int mq) {
@@ -191,7 +193,15 @@ __global__ void __launch_bounds__(256) k_scan_bf16(StoreView s, QueryView qv, Ro
   const int wave = threadIdx.x / kWave;
   const int m = s.m;
   const int n_tiles = static_cast<int>(b.ctl[kCtlTiles]);
-  for (int t = xcd_block(); t < n_tiles; t += gridDim.x) {
+  // work-group i runs on XCD i % 8; with a grid that is a multiple of 8 it
+  // takes the tiles xcd_tile(i / 8 + p * gridDim.x / 8, i % 8), p = 0, 1, ...
+  const bool by_xcd = gridDim.x % kXcds == 0;
+  const int x = blockIdx.x % kXcds, per = gridDim.x / kXcds;
+  for (int64_t j = by_xcd ? blockIdx.x / kXcds : blockIdx.x;; j += by_xcd ? per : gridDim.x) {
+    const int64_t tt = by_xcd ? xcd_tile(j, x) : j;
+    if (by_xcd ? (j / kXcdRun) * kXcds * kXcdRun >= n_tiles : tt >= n_tiles) break;
+    if (tt >= n_tiles) continue;
+    const int t = static_cast<int>(tt);
     TileInfo ti = decode_tile(t, s, b, MQ);
     if (threadIdx.x < MQ) {
       cnt[threadIdx.x] = 0;
@@ -247,7 +257,15 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
   const int sub = lane & 15, rsel = lane >> 4;
   const int m = s.m;  // == 16 * EPL
   const int n_tiles = static_cast<int>(b.ctl[kCtlTiles]);
-  for (int t = xcd_block(); t < n_tiles; t += gridDim.x) {
+  // work-group i runs on XCD i % 8; with a grid that is a multiple of 8 it
+  // takes the tiles xcd_tile(i / 8 + p * gridDim.x / 8, i % 8), p = 0, 1, ...
+  const bool by_xcd = gridDim.x % kXcds == 0;
+  const int x = blockIdx.x % kXcds, per = gridDim.x / kXcds;
+  for (int64_t j = by_xcd ? blockIdx.x / kXcds : blockIdx.x;; j += by_xcd ? per : gridDim.x) {
+    const int64_t tt = by_xcd ? xcd_tile(j, x) : j;
+    if (by_xcd ? (j / kXcdRun) * kXcds * kXcdRun >= n_tiles : tt >= n_tiles) break;
+    if (tt >= n_tiles) continue;
+    const int t = static_cast<int>(tt);
     TileInfo ti = decode_tile(t, s, b, mq);
     if (threadIdx.x < mq) {
       cnt[threadIdx.x] = 0;
@@ -298,6 +316,11 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
   }
 }
 
+// Selection instead of a full sort when at most kSelectMax of at most
+// 64 * kSelectPerLane chunk candidates are wanted.
+constexpr int kSelectMax = 16;
+constexpr int kSelectPerLane = 16;
+
 // One wavefront per item.  LDS: merged keys [P], then per candidate the fp32
 // key, FP64 distance and row.
 __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
@@ -326,17 +349,50 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
     int C = static_cast<int>((s.leaf_off[L + 1] - s.leaf_off[L] + b.chunk - 1) / b.chunk);
     const int G = (b.leaf_istart[L + 1] - b.leaf_istart[L] + mq - 1) / mq;
     int n = C * kprime;
-    int P = pow2_at_least(n < 2 ? 2 : n);
-    for (int e = lane; e < P; e += kWave) {
-      uint64_t v = kKeyMax;
-      if (e < n) {
-        int c = e / kprime;
-        v = cand[(tile_of(b.tile_start, L, g, c, G) * mq + j) * kprime + (e - c * kprime)];
+    if (kprime <= kSelectMax && n <= kWave * kSelectPerLane) {
+      // few keys wanted from many: kprime rounds of a wavefront minimum over
+      // the keys above the previous one (keys are unique), held in registers
+      uint64_t mine[kSelectPerLane];
+#pragma unroll
+      for (int u = 0; u < kSelectPerLane; ++u) {
+        const int e = lane + u * kWave;
+        uint64_t v = kKeyMax;
+        if (e < n) {
+          const int c = e / kprime;
+          v = cand[(tile_of(b.tile_start, L, g, c, G) * mq + j) * kprime + (e - c * kprime)];
+        }
+        mine[u] = v;
       }
-      buf[e] = v;
+      uint64_t prev = 0;
+      bool first = true;
+      for (int r = 0; r < kprime; ++r) {
+        uint64_t lo = kKeyMax;
+#pragma unroll
+        for (int u = 0; u < kSelectPerLane; ++u)
+          if ((first || mine[u] > prev) && mine[u] < lo) lo = mine[u];
+        lo = wave_min(lo);
+        if (lane == 0) buf[r] = lo;
+        prev = lo;
+        first = false;
+        if (lo == kKeyMax) {  // no keys left: the rest stay empty
+          for (int e = r + 1 + lane; e < kprime; e += kWave) buf[e] = kKeyMax;
+          break;
+        }
+      }
+      wave_lds_sync();
+    } else {
+      int P = pow2_at_least(n < 2 ? 2 : n);
+      for (int e = lane; e < P; e += kWave) {
+        uint64_t v = kKeyMax;
+        if (e < n) {
+          int c = e / kprime;
+          v = cand[(tile_of(b.tile_start, L, g, c, G) * mq + j) * kprime + (e - c * kprime)];
+        }
+        buf[e] = v;
+      }
+      wave_lds_sync();
+      wave_sort_u64(buf, P, lane);
     }
-    wave_lds_sync();
-    wave_sort_u64(buf, P, lane);
     uint64_t kth = buf[kprime - 1];
     // number of real candidates among the first kprime
     int nc = 0;
@@ -432,7 +488,7 @@ int resident_grid(K kern, size_t lds, int want) {
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), 256, lds));
   int g = cus * (per_cu > 0 ? per_cu : 1);
   g = want < g ? (want > 0 ? want : 1) : g;
-  return g >= kXcds ? g / kXcds * kXcds : g;  // a multiple of the XCD count (see xcd_block)
+  return g >= kXcds ? g / kXcds * kXcds : g;  // a multiple of the XCD count (see xcd_tile)
 }
 
 template <int KS, int QB>
