@@ -168,6 +168,8 @@ void ensure_queries(leafi_index *ix, int64_t nq, int kmax) {
   w.qstat.reserve(nq * S * 2);
   w.lb.reserve(nq * N);
   w.order.reserve(nq * N);
+  w.lbs.reserve(nq * N);
+  w.dfo.reserve(nq * N);
   w.dfilt.reserve(nq * F);
   w.tau.reserve(nq);
   w.cursor.reserve(nq);
@@ -229,7 +231,7 @@ void prep_queries(leafi_index *ix, const float *raw, int64_t nq, hipStream_t st)
   Workspace &w = ix->ws;
   launch_qprep(raw, nq, ix->m, ix->S, w.q32.get(), w.q16.get(), w.qn16.get(), w.qeps.get(), w.qstat.get(), st);
   launch_lb(w.qstat.get(), nq, ix->boxes.get(), ix->N, ix->S, ix->m, w.lb.get(), st);
-  launch_order(w.lb.get(), nq, ix->N, w.order.get(), st);
+  launch_order(w.lb.get(), nq, ix->N, w.order.get(), w.lbs.get(), st);
 }
 
 // Upper bound of scan work-groups per CU; the launch clamps the persistent
@@ -389,18 +391,17 @@ void begin_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k
 void eval_filters(leafi_index *ix, int64_t nq, hipStream_t st) {
   Workspace &w = ix->ws;
   const int F = ix->filt.F;
-  launch_filter_pairs(nq, ix->N, w.lb.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
-                      w.pcnt.get(), st);
-  launch_mlp_infer_pairs(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), nq,
-                         w.ptile.get(), w.dfilt.get(), st);
+  launch_filter_pairs(nq, ix->N, w.lbs.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
+                      w.pcnt.get(), w.dfo.get(), st);
+  launch_mlp_infer_pairs(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), nq, ix->N,
+                         w.pair.get(), ix->cal.offsets.get(), w.ptile.get(), w.dfo.get(), st);
 }
 
 void launch_round_worklist(leafi_index *ix, int64_t nq, int want, bool f_now, hipStream_t st) {
   Workspace &w = ix->ws;
   const int F = ix->filt.F;
-  launch_worklist(nq, ix->N, w.lb.get(), w.order.get(), w.dfilt.get(), std::max(F, 1),
-                  f_now ? ix->filt.filt_of_leaf.get() : nullptr, f_now ? ix->cal.offsets.get() : nullptr,
-                  ix->leaf_n.get(), want, views(w), st);
+  launch_worklist(nq, ix->N, w.lbs.get(), w.order.get(), f_now ? w.dfo.get() : nullptr, ix->leaf_n.get(), want,
+                  views(w), st);
 }
 
 void stats_from_ctl(const leafi_index *ix, leafi_search_stats *stats) {
@@ -595,7 +596,7 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
                         static_cast<const void *>(t_dev), static_cast<const void *>(ids),
                         static_cast<const void *>(dists), static_cast<const void *>(w.cand.get()),
                         static_cast<const void *>(w.plist.get()), static_cast<const void *>(w.pcnt.get()),
-                        static_cast<const void *>(w.dfilt.get()), static_cast<const void *>(w.lb.get()),
+                        static_cast<const void *>(w.dfo.get()), static_cast<const void *>(w.lbs.get()),
                         static_cast<const void *>(w.order.get()), static_cast<const void *>(w.qstat.get()),
                         static_cast<const void *>(ix->boxes.get()), static_cast<const void *>(ix->rowid.get()),
                         static_cast<const void *>(ix->filt.w.get()), static_cast<const void *>(ix->filt.filt_of_leaf.get()),

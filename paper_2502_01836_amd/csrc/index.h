@@ -117,7 +117,9 @@ struct Workspace {
   DevBuf<double> item_d2;
   DevBuf<float> item_bound;
   DevBuf<uint64_t> cand;
-  DevBuf<int32_t> plist, pcnt;  // filter pairs to evaluate
+  DevBuf<int64_t> plist;        // filter pairs to evaluate (q * N + visit position)
+  DevBuf<int32_t> pcnt;
+  DevBuf<float> lbs, dfo;       // [nq, N] in visit order: summary bound, filter pruning value
   DevBuf<int32_t> ptile;        // prefix of the filters' 16-query inference tiles [F + 1]
   DevBuf<int64_t> ctl;
   std::vector<int64_t> h_ctl;

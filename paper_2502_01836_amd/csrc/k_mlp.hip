@@ -26,10 +26,9 @@ constexpr int kMlpQ = 16;
 
 size_t mlp_infer_lds(int m) { return (static_cast<size_t>(kMlpQ) * (m + 4) + 4 * kMlpQ) * sizeof(float); }
 
-template <typename RowIdx>
-__device__ inline void mlp_tile(const float *__restrict__ w, int F, int f, int m, int h,
-                                const float *__restrict__ x, int64_t r0, int64_t nrows, RowIdx qidx, float *out,
-                                float *xs) {
+template <typename RowIdx, typename Out>
+__device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h, const float *__restrict__ x,
+                                int64_t r0, int64_t nrows, RowIdx qidx, Out out, float *xs) {
   typedef float floatx4 __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int S = m + 4;
@@ -102,7 +101,7 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int F, int f, int m
   __syncthreads();
   if (tid < kMlpQ) {
     const int64_t r = r0 + tid;
-    if (r < nrows) out[qidx(r) * F + f] = ((red[tid] + red[16 + tid]) + (red[32 + tid] + red[48 + tid])) + b2;
+    if (r < nrows) out(r, ((red[tid] + red[16 + tid]) + (red[32 + tid] + red[48 + tid])) + b2);
   }
 }
 
@@ -110,8 +109,9 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int F, int f, int m
 __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, int F, int m, int h,
                                                    const float *__restrict__ x, int64_t nq, float *out) {
   extern __shared__ float xs[];
+  const int f = blockIdx.x;
   for (int64_t r0 = static_cast<int64_t>(blockIdx.y) * kMlpQ; r0 < nq; r0 += static_cast<int64_t>(gridDim.y) * kMlpQ)
-    mlp_tile(w, F, blockIdx.x, m, h, x, r0, nq, [](int64_t r) { return r; }, out, xs);
+    mlp_tile(w, f, m, h, x, r0, nq, [](int64_t r) { return r; }, [=](int64_t r, float v) { out[r * F + f] = v; }, xs);
 }
 
 // Exclusive prefix of the filters' tile counts ceil(pcnt[f] / 16) (one
@@ -139,13 +139,17 @@ __global__ void __launch_bounds__(1024) k_mlp_tiles(int F, const int32_t *__rest
   if (tid == 1023) tile_prefix[F] = part[1023];
 }
 
-// d^f for listed pairs: filter f evaluates queries plist[f * stride + 0 ..
-// pcnt[f]).  A persistent grid walks the non-empty tiles of all filters.
+// Pruning values for listed pairs: filter f evaluates the entries
+// plist[f * stride + 0 .. pcnt[f]) (q * N + visit position) and writes
+// d^f - o for the query's calibrated (k, target) row.  A persistent grid
+// walks the non-empty tiles of all filters.
 __global__ void __launch_bounds__(256) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
                                                          const float *__restrict__ x,
-                                                         const int32_t *__restrict__ plist,
-                                                         const int32_t *__restrict__ pcnt, int64_t stride,
-                                                         const int32_t *__restrict__ tile_prefix, float *out) {
+                                                         const int64_t *__restrict__ plist,
+                                                         const int32_t *__restrict__ pcnt, int64_t stride, int N,
+                                                         const int32_t *__restrict__ pair,
+                                                         const float *__restrict__ offsets,
+                                                         const int32_t *__restrict__ tile_prefix, float *dfo) {
   extern __shared__ float xs[];
   const int total = tile_prefix[F];
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
@@ -158,9 +162,14 @@ __global__ void __launch_bounds__(256) k_mlp_infer_pairs(const float *__restrict
     }
     const int f = lo;
     const int64_t r0 = static_cast<int64_t>(t - tile_prefix[f]) * kMlpQ;
-    const int32_t *pl = plist + f * stride;
-    mlp_tile(w, F, f, m, h, x, r0, static_cast<int64_t>(pcnt[f]), [pl](int64_t r) { return static_cast<int64_t>(pl[r]); },
-             out, xs);
+    const int64_t *pl = plist + f * stride;
+    mlp_tile(
+        w, f, m, h, x, r0, static_cast<int64_t>(pcnt[f]), [=](int64_t r) { return pl[r] / N; },
+        [=](int64_t r, float v) {
+          const int64_t e = pl[r];
+          dfo[e] = v - offsets[static_cast<int64_t>(pair[e / N]) * F + f];
+        },
+        xs);
   }
 }
 
@@ -417,8 +426,9 @@ void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64
   LAUNCH_OK("mlp_infer");
 }
 
-void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int32_t *plist,
-                            const int32_t *pcnt, int64_t stride, int32_t *tile_prefix, float *out, hipStream_t st) {
+void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int64_t *plist,
+                            const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets,
+                            int32_t *tile_prefix, float *dfo, hipStream_t st) {
   if (F <= 0 || stride <= 0) return;
   hipLaunchKernelGGL(k_mlp_tiles, dim3(1), dim3(1024), 0, st, F, pcnt, tile_prefix);
   LAUNCH_OK("mlp_tiles");
@@ -434,8 +444,8 @@ void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x,
   const size_t lds = mlp_infer_lds(m);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer_pairs),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  hipLaunchKernelGGL(k_mlp_infer_pairs, dim3(grid), dim3(256), lds, st, w, F, m, h, x, plist, pcnt, stride,
-                     tile_prefix, out);
+  hipLaunchKernelGGL(k_mlp_infer_pairs, dim3(grid), dim3(256), lds, st, w, F, m, h, x, plist, pcnt, stride, N, pair,
+                     offsets, tile_prefix, dfo);
   LAUNCH_OK("mlp_infer_pairs");
 }
 

@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(256) k_lb(const float *__restrict__ qstat, int
 
 // One work-group per query: bitonic sort of (lb bits, leaf id) keys in LDS.
 __global__ void __launch_bounds__(256) k_order(const float *__restrict__ lb, int N, int P, int32_t *order,
-                                               const int32_t *__restrict__ slots) {
+                                               float *lbs, const int32_t *__restrict__ slots) {
   extern __shared__ uint64_t keys[];
   const int64_t q = slots ? slots[blockIdx.x] : static_cast<int64_t>(blockIdx.x);
   for (int i = threadIdx.x; i < P; i += blockDim.x)
@@ -218,7 +218,10 @@ __global__ void __launch_bounds__(256) k_order(const float *__restrict__ lb, int
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < N; i += blockDim.x) order[q * N + i] = static_cast<int32_t>(key_row(keys[i]));
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    order[q * N + i] = static_cast<int32_t>(key_row(keys[i]));
+    lbs[q * N + i] = key_d2(keys[i]);  // the bound itself, in visit order
+  }
 }
 
 __global__ void __launch_bounds__(256) k_make_queries(const float *__restrict__ x32, const int64_t *__restrict__ rows,
@@ -272,10 +275,11 @@ void launch_lb(const float *qstat, int64_t nq, const float *boxes, int N, int S,
   LAUNCH_OK("lb");
 }
 
-void launch_order(const float *lb, int64_t nq, int N, int32_t *order, hipStream_t st, const int32_t *slots) {
+void launch_order(const float *lb, int64_t nq, int N, int32_t *order, float *lbs, hipStream_t st,
+                  const int32_t *slots) {
   int P = pow2_at_least(N < 2 ? 2 : N);
   size_t lds = static_cast<size_t>(P) * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_order, dim3(nq), dim3(256), lds, st, lb, N, P, order, slots);
+  hipLaunchKernelGGL(k_order, dim3(nq), dim3(256), lds, st, lb, N, P, order, lbs, slots);
   LAUNCH_OK("order");
 }
 

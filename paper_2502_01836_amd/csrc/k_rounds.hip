@@ -18,11 +18,10 @@ namespace {
 // surviving leaves in visit order.  All decisions of the round use the tau
 // from before the round.  The order is by ascending d^lb, so the first leaf
 // the bound prunes ends the walk (every later leaf is pruned too).
-__global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float *__restrict__ lb,
-                                                  const int32_t *__restrict__ order, const float *__restrict__ dfilt,
-                                                  int F, const int32_t *__restrict__ filt_of_leaf,
-                                                  const float *__restrict__ offsets, const int32_t *__restrict__ leaf_n,
-                                                  int want, Schedule sched, int32_t *qround, RoundBufs b) {
+__global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float *__restrict__ lbs,
+                                                  const int32_t *__restrict__ order, const float *__restrict__ dfo,
+                                                  const int32_t *__restrict__ leaf_n, int want, Schedule sched,
+                                                  int32_t *qround, RoundBufs b) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (q >= nq) return;  // whole wavefront
@@ -38,26 +37,24 @@ __global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float
   if (pos < N) {
     const float tau = b.tau[q];
     const float tau_lb = tau * (1.0f + kLbSlack);
-    const int pair = b.pair[q];
-    const bool use_f = filt_of_leaf != nullptr && pair >= 0;
-    const float *lbq = lb + q * N;
+    const bool use_f = dfo != nullptr && b.pair[q] >= 0;
+    const float *lbq = lbs + q * N;
+    const float *fq = use_f ? dfo + q * N : nullptr;
     const int32_t *oq = order + q * N;
     const uint64_t lt = (1ull << lane) - 1ull;
     while (pos < N && (want == 0 || cnt < want)) {
       const int p = pos + lane;
       const bool valid = p < N;
+      // three independent coalesced loads per position: leaf, bound, filter value
       const int L = valid ? oq[p] : 0;
-      const bool lbbad = valid && lbq[L] > tau_lb;
+      const bool lbbad = valid && lbq[p] > tau_lb;
+      const float fv = valid && use_f ? fq[p] : -__builtin_inff();
       const uint64_t mbad = __ballot(lbbad);
       const int nvalid = N - pos < kWave ? N - pos : kWave;
       const int s = mbad ? __ffsll(static_cast<unsigned long long>(mbad)) - 1 : kWave;
       const int stop = s < nvalid ? s : nvalid;
       const bool in = lane < stop;
-      bool fpr = false;
-      if (in && use_f) {
-        const int f = filt_of_leaf[L];
-        if (f >= 0) fpr = dfilt[q * F + f] - offsets[static_cast<int64_t>(pair) * F + f] > tau;
-      }
+      const bool fpr = in && fv > tau;
       const bool surv = in && !fpr;
       uint64_t msurv = __ballot(surv);
       int end = stop;
@@ -104,28 +101,30 @@ __global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float
   }
 }
 
-// Filter pairs worth evaluating once tau is known: every (query, filtered
-// leaf) still ahead of the cursor whose bound does not prune it.  Later rounds
-// only lower tau, so no other pair can reach the filter test.  Filter f
-// collects its queries in plist[f * nq + ...].
-__global__ void __launch_bounds__(256) k_filter_pairs(int64_t nq, int N, const float *__restrict__ lb,
+// Filter pairs worth evaluating once tau is known: every (query, visit
+// position) ahead of the cursor whose leaf has a filter and whose bound does
+// not prune it.  Later rounds only lower tau, so no other pair can reach the
+// filter test.  Filter f collects its entries q * N + position in
+// plist[f * nq + ...]; every other position ahead of the cursor gets
+// dfo = -inf.
+__global__ void __launch_bounds__(256) k_filter_pairs(int64_t nq, int N, const float *__restrict__ lbs,
                                                       const int32_t *__restrict__ order,
                                                       const int32_t *__restrict__ filt_of_leaf, RoundBufs b,
-                                                      const int32_t *__restrict__ qround, int32_t *plist,
-                                                      int32_t *pcnt) {
+                                                      const int32_t *__restrict__ qround, int64_t *plist,
+                                                      int32_t *pcnt, float *dfo) {
   int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= nq * N) return;
   int64_t q = idx / N;
   int pos = static_cast<int>(idx - q * N);
   if (qround && qround[q] != 1) return;  // serving: only queries that just finished their first round
   if (pos < b.cursor[q] || b.pair[q] < 0) return;
-  int L = order[q * N + pos];
-  int f = filt_of_leaf[L];
-  if (f < 0) return;
-  float tau = b.tau[q];
-  if (lb[q * N + L] > tau * (1.0f + kLbSlack)) return;
+  const int f = filt_of_leaf[order[idx]];
+  if (f < 0 || lbs[idx] > b.tau[q] * (1.0f + kLbSlack)) {
+    dfo[idx] = -__builtin_inff();
+    return;
+  }
   int slot = atomicAdd(pcnt + f, 1);
-  plist[static_cast<int64_t>(f) * nq + slot] = static_cast<int32_t>(q);
+  plist[static_cast<int64_t>(f) * nq + slot] = idx;
 }
 
 __global__ void __launch_bounds__(256) k_emit_fallback(int N, RoundBufs b) {
@@ -405,20 +404,21 @@ __global__ void __launch_bounds__(256) k_collect_done(int64_t n_slots, int N, in
 
 }  // namespace
 
-void launch_worklist(int64_t nq, int N, const float *lb, const int32_t *order, const float *dfilt, int F,
-                     const int32_t *filt_of_leaf, const float *offsets, const int32_t *leaf_n, int want,
-                     RoundBufs b, hipStream_t st, const Schedule *sched, int32_t *qround) {
+void launch_worklist(int64_t nq, int N, const float *lbs, const int32_t *order, const float *dfo,
+                     const int32_t *leaf_n, int want, RoundBufs b, hipStream_t st, const Schedule *sched,
+                     int32_t *qround) {
   Schedule sc{};
   if (sched) sc = *sched;
-  hipLaunchKernelGGL(k_worklist, dim3(ceil_div(nq, 4)), dim3(256), 0, st, nq, N, lb, order, dfilt, F, filt_of_leaf,
-                     offsets, leaf_n, want, sc, qround, b);
+  hipLaunchKernelGGL(k_worklist, dim3(ceil_div(nq, 4)), dim3(256), 0, st, nq, N, lbs, order, dfo, leaf_n, want, sc,
+                     qround, b);
   LAUNCH_OK("worklist");
 }
 
-void launch_filter_pairs(int64_t nq, int N, const float *lb, const int32_t *order, const int32_t *filt_of_leaf,
-                         RoundBufs b, int32_t *plist, int32_t *pcnt, hipStream_t st, const int32_t *qround) {
-  hipLaunchKernelGGL(k_filter_pairs, dim3(ceil_div(nq * N, 256)), dim3(256), 0, st, nq, N, lb, order, filt_of_leaf, b,
-                     qround, plist, pcnt);
+void launch_filter_pairs(int64_t nq, int N, const float *lbs, const int32_t *order, const int32_t *filt_of_leaf,
+                         RoundBufs b, int64_t *plist, int32_t *pcnt, float *dfo, hipStream_t st,
+                         const int32_t *qround) {
+  hipLaunchKernelGGL(k_filter_pairs, dim3(ceil_div(nq * N, 256)), dim3(256), 0, st, nq, N, lbs, order, filt_of_leaf,
+                     b, qround, plist, pcnt, dfo);
   LAUNCH_OK("filter_pairs");
 }
 

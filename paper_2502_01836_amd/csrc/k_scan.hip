@@ -128,22 +128,20 @@ __device__ __forceinline__ void load_rows(const uint16_t *x16, int64_t base, int
   for (int k = 0; k < KS; ++k) a[k] = *reinterpret_cast<const bf16x8 *>(ap + 32 * k);
 }
 
-// One 64-row block: its squared norms, the prefetch of block `pf` into
-// `nxt`, MFMAs on `cur`, candidate appends (none if the block is past the
-// tile, `valid` false) and list maintenance.  No branch depends on `valid`,
-// so the compiler can track the loads in flight across blocks.
+// One 64-row block: its squared norms, the prefetch of the next block into
+// `nxt`, MFMAs on `cur`, candidate appends, then list maintenance.
 template <int KS, int QB>
 __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &ti, int64_t base, bf16x8 (&cur)[KS],
-                                           bf16x8 (&nxt)[KS], int64_t pf, bool valid, const uint16_t *qs,
-                                           int qstride, const float (&qn)[QB], uint64_t *keys, int *cnt,
-                                           uint64_t *thr, int cap, int kprime, int wave, int lane) {
+                                           bf16x8 (&nxt)[KS], bool more, const uint16_t *qs, int qstride,
+                                           const float (&qn)[QB], uint64_t *keys, int *cnt, uint64_t *thr, int cap,
+                                           int kprime, int wave, int lane) {
   constexpr int kWaves = 4;
   const int64_t rowc = base + 16 * wave + 4 * (lane >> 4);
-  const float4 xn = *reinterpret_cast<const float4 *>(s.xn16 + (valid ? rowc : pf));
-  // unconditional (past the end of the tile it re-reads the tile's last
-  // block, which is cached): a branch here would leave the in-flight load
-  // count ambiguous and make the compiler drain every load before the MFMAs
-  load_rows<KS>(s.x16, pf, wave, lane, s.m, nxt);
+  const float4 xn = *reinterpret_cast<const float4 *>(s.xn16 + rowc);
+  // unconditional (the last block of a tile re-reads its own rows, which are
+  // cached): a branch here would leave the in-flight load count ambiguous and
+  // make the compiler drain every load before the MFMAs
+  load_rows<KS>(s.x16, more ? base + 64 : base, wave, lane, s.m, nxt);
   floatx4 acc[QB];
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) acc[qb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -168,7 +166,7 @@ __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &t
         const int64_t row = rowc + r;
         const float d2 = fmaxf(qn[qb] + xr[r] - 2.0f * acc[qb][r], 0.0f);
         const uint64_t key = make_key(d2, static_cast<uint32_t>(row));
-        if (valid && row < ti.real_end && key < tj) {
+        if (row < ti.real_end && key < tj) {
           const int slot = atomicAdd(cnt + j, 1);
           keys[static_cast<int64_t>(j) * cap + slot] = key;
         }
@@ -226,23 +224,19 @@ __global__ void __launch_bounds__(256, 3) k_scan_bf16(StoreView s, QueryView qv,
       qn[qb] = j < ti.nqt ? qv.qn16[b.item_q[ti.p0 + j]] : 0.0f;
     }
     __syncthreads();
-    // The A operand of the wave's 16 rows is loaded two 64-row blocks ahead of
-    // its use (three register buffers in rotation, no copies), so two blocks
-    // of global loads are always in flight; the barriers wait on LDS only.
-    // Loads are issued in the order they are consumed because the hardware's
-    // load counter retires in order.  Prefetches past the tile re-read its
-    // last block, and blocks past the tile only prefetch.
-    bf16x8 a0[KS], a1[KS], a2[KS];
-    const int64_t last = ti.r1 - 64;
+    // The A operand of the wave's 16 rows in the next 64-row block is loaded
+    // while the current block is processed (ping-pong registers, no copies),
+    // so one block of global loads is always in flight; the barriers wait on
+    // LDS only.  Loads are issued in the order they are consumed because the
+    // hardware's load counter retires in order.
+    // Chunks hold an even number of 64-row blocks (leaves are padded to 128
+    // rows), so both halves of the unrolled body always run.
+    bf16x8 a0[KS], a1[KS];
     load_rows<KS>(s.x16, ti.r0, wave, lane, m, a0);
-    load_rows<KS>(s.x16, ti.r0 + 64 < last ? ti.r0 + 64 : last, wave, lane, m, a1);
-    for (int64_t base = ti.r0; base < ti.r1; base += 192) {
-      scan_block<KS, QB>(s, ti, base, a0, a2, base + 128 < last ? base + 128 : last, true, qs, qstride, qn, keys,
-                         cnt, thr, cap, kprime, wave, lane);
-      scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 192 < last ? base + 192 : last, base + 64 < ti.r1, qs,
-                         qstride, qn, keys, cnt, thr, cap, kprime, wave, lane);
-      scan_block<KS, QB>(s, ti, base + 128, a2, a1, base + 256 < last ? base + 256 : last, base + 128 < ti.r1, qs,
-                         qstride, qn, keys, cnt, thr, cap, kprime, wave, lane);
+    for (int64_t base = ti.r0; base < ti.r1; base += 128) {
+      scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kprime, wave, lane);
+      scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qs, qstride, qn, keys, cnt, thr, cap, kprime,
+                         wave, lane);
     }
     finish_tile(keys, cnt, thr, t, MQ, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
     __syncthreads();

@@ -33,8 +33,9 @@ void launch_qprep(const float *raw, int64_t nq, int m, int S, float *q32, uint16
 void launch_lb(const float *qstat, int64_t nq, const float *boxes, int N, int S, int m, float *lb, hipStream_t st,
                const int32_t *slots = nullptr);
 
-// Visit order: per query, leaves sorted by (lb, leaf id).
-void launch_order(const float *lb, int64_t nq, int N, int32_t *order, hipStream_t st,
+// Visit order: per query, leaves sorted by (lb, leaf id); lbs receives the
+// bounds in that order.
+void launch_order(const float *lb, int64_t nq, int N, int32_t *order, float *lbs, hipStream_t st,
                   const int32_t *slots = nullptr);
 
 // Training queries: q_j = x32[row_j] + sigma_j * N(0, 1) noise from a
@@ -127,14 +128,18 @@ struct Schedule {
 // prune cascade).  want = leaves per query this round (0 = all survivors);
 // with qround (serving), each query instead takes sched.r at its own round
 // count, which the kernel advances.
-void launch_worklist(int64_t nq, int N, const float *lb, const int32_t *order, const float *dfilt, int F,
-                     const int32_t *filt_of_leaf, const float *offsets, const int32_t *leaf_n, int want,
-                     RoundBufs b, hipStream_t st, const Schedule *sched = nullptr, int32_t *qround = nullptr);
+// lbs and dfo are [nq, N] in visit order: the summary bound and (filters
+// active) the filter's pruning value d^f - o, -inf where no filter applies.
+void launch_worklist(int64_t nq, int N, const float *lbs, const int32_t *order, const float *dfo,
+                     const int32_t *leaf_n, int want, RoundBufs b, hipStream_t st, const Schedule *sched = nullptr,
+                     int32_t *qround = nullptr);
 
-// (query, filter) pairs whose filter test a later round can reach, grouped
-// by filter into plist [F, nq] with counts pcnt [F] (zeroed by the caller).
-void launch_filter_pairs(int64_t nq, int N, const float *lb, const int32_t *order, const int32_t *filt_of_leaf,
-                         RoundBufs b, int32_t *plist, int32_t *pcnt, hipStream_t st,
+// (query, visit position) pairs whose filter test a later round can reach,
+// grouped by filter into plist [F, nq] (entries q * N + position) with counts
+// pcnt [F] (zeroed by the caller).  Every other position ahead of the cursor
+// gets dfo = -inf (never pruned by a filter).
+void launch_filter_pairs(int64_t nq, int N, const float *lbs, const int32_t *order, const int32_t *filt_of_leaf,
+                         RoundBufs b, int64_t *plist, int32_t *pcnt, float *dfo, hipStream_t st,
                          const int32_t *qround = nullptr);
 
 // Serving: retire finished active slots (state 1 -> 2) into a compact done list.
@@ -191,11 +196,14 @@ void launch_items_to_leaf_knn(int64_t n_items, int N, int k, int kmax, const int
 // d^f for every (query, filter): out [nq, F].
 void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, hipStream_t st);
 
-// d^f for listed pairs only (filter f: queries plist[f * stride + 0 .. pcnt[f])).
-// tile_prefix [F + 1] is scratch: a first launch lays out the non-empty
-// 16-query tiles of all filters, a persistent grid then walks them.
-void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int32_t *plist,
-                            const int32_t *pcnt, int64_t stride, int32_t *tile_prefix, float *out, hipStream_t st);
+// Pruning values for listed pairs only: filter f evaluates the entries
+// plist[f * stride + 0 .. pcnt[f]) (q * N + visit position) and writes
+// dfo[entry] = d^f(x[q]) - offsets[pair[q] * F + f].  tile_prefix [F + 1] is
+// scratch: a first launch lays out the non-empty 16-query tiles of all
+// filters, a persistent grid then walks them.
+void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int64_t *plist,
+                            const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets,
+                            int32_t *tile_prefix, float *dfo, hipStream_t st);
 
 // Per-query offset row lookup for (k, target) pairs.
 // k is clamped to [1, kmax].

@@ -132,7 +132,7 @@ void leafi_server::engine_round(int n_new, int &n_active) {
     launch_qprep(new_raw.get(), n_new, m, ix->S, w.q32.get(), w.q16.get(), w.qn16.get(), w.qeps.get(), w.qstat.get(),
                  st, new_slots.get());
     launch_lb(w.qstat.get(), n_new, ix->boxes.get(), N, ix->S, m, w.lb.get(), st, new_slots.get());
-    launch_order(w.lb.get(), n_new, N, w.order.get(), st, new_slots.get());
+    launch_order(w.lb.get(), n_new, N, w.order.get(), w.lbs.get(), st, new_slots.get());
     launch_select_pairs(n_new, new_k.get(), new_t.get(), use_f ? ix->cal.pairs() : 0,
                         use_f ? ix->cal.pair_k.get() : nullptr, use_f ? ix->cal.pair_t.get() : nullptr, kmax,
                         w.pair.get(), w.kq.get(), st, new_slots.get());
@@ -145,15 +145,14 @@ void leafi_server::engine_round(int n_new, int &n_active) {
   if (use_f) {
     // slots that finished their first round get the filter pairs a later round can test
     fill_i32(w.pcnt.get(), F, 0, st);
-    launch_filter_pairs(slots, N, w.lb.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
-                        w.pcnt.get(), st, qround.get());
-    launch_mlp_infer_pairs(ix->filt.w.get(), F, m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), slots,
-                           w.ptile.get(), w.dfilt.get(), st);
+    launch_filter_pairs(slots, N, w.lbs.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
+                        w.pcnt.get(), w.dfo.get(), st, qround.get());
+    launch_mlp_infer_pairs(ix->filt.w.get(), F, m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), slots, N,
+                           w.pair.get(), ix->cal.offsets.get(), w.ptile.get(), w.dfo.get(), st);
   }
   reset_round(ix, st);
-  launch_worklist(slots, N, w.lb.get(), w.order.get(), w.dfilt.get(), std::max(F, 1),
-                  use_f ? ix->filt.filt_of_leaf.get() : nullptr, use_f ? ix->cal.offsets.get() : nullptr,
-                  ix->leaf_n.get(), 0, views(w), st, &sched, qround.get());
+  launch_worklist(slots, N, w.lbs.get(), w.order.get(), use_f ? w.dfo.get() : nullptr, ix->leaf_n.get(), 0, views(w),
+                  st, &sched, qround.get());
   int maxwant = 0;
   for (int i = 0; i < sched.n; ++i) maxwant = sched.r[i] == 0 ? N : std::max(maxwant, sched.r[i]);
   const int64_t bound = static_cast<int64_t>(slots) * std::min(maxwant, N);
