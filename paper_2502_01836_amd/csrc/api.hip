@@ -218,7 +218,9 @@ void read_ctl(leafi_index *ix, hipStream_t st) {
 
 // Zero the per-round control words (items, tiles, active, fallback) and the
 // per-leaf item counts; the statistics words keep accumulating.
-void reset_round(leafi_index *ix, hipStream_t st) { launch_round_reset(views(ix->ws), 4, ix->N, 0, st); }
+void reset_round(leafi_index *ix, hipStream_t st) {
+  launch_round_reset(views(ix->ws), kCtlRoundWords, ix->N, 0, st);
+}
 
 // Before a fallback pass: zero the per-leaf and per-query item counts.  The
 // fallback count itself stays: the emit kernel reads it.
@@ -543,9 +545,10 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
   const int kprime_fb = default_kprime(p.kmax, false);
   begin_batch(ix, raw, nq, k_dev, t_dev, p, use_f, st);
   const int R = planned_rounds(p);
+  // No reset launches: the prune cascade zeroes the round's control words and
+  // every merge leaves the per-leaf and per-query item counts at zero.
   for (int r = 0; r < R; ++r) {
     if (use_f && r == 1) eval_filters(ix, nq, st);
-    if (r > 0) reset_round(ix, st);
     launch_round_worklist(ix, nq, p.schedule[r], use_f && r > 0, st);
     const int64_t bnd = planned_bound(ix, nq, p, r);
     RoundOpts ro;
@@ -559,7 +562,6 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     launch_query_merge(nq, N, p.kmax, true, false, views(w), st);
     RoundOpts rf;
     rf.may_read = false;
-    reset_for_fallback(ix, nq, st);
     launch_emit_fallback(bnd, N, views(w), st);
     scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bnd, &rf);
     launch_query_merge(nq, N, p.kmax, false, true, views(w), st);

@@ -57,6 +57,38 @@ __device__ __forceinline__ T wave_min(T v) {
   return v;
 }
 
+// Exclusive prefix sum over a work-group of NT threads (NT / 64 <= 64
+// wavefronts): wavefront scans by shuffles, then one scan of the wavefront
+// totals.  `sh` holds NT / 64 values of LDS; `total` receives the sum.  Every
+// thread of the work-group must call it.
+template <int NT, typename T>
+__device__ inline T block_scan_excl(T v, T *sh, T &total) {
+  static_assert(NT % 64 == 0 && NT / 64 <= 64, "work-group size");
+  constexpr int kW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();  // sh may still be read by a previous call
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    T t = lane < kW ? sh[lane] : T(0);
+#pragma unroll
+    for (int o = 1; o < kW; o <<= 1) {
+      const T y = __shfl_up(t, o, 64);
+      if (lane >= o) t += y;
+    }
+    if (lane < kW) sh[lane] = t;
+  }
+  __syncthreads();
+  total = sh[kW - 1];
+  return (wave > 0 ? sh[wave - 1] : T(0)) + x - v;
+}
+
 // Orders LDS traffic of one wavefront between stages of a cooperative
 // algorithm (lanes read what other lanes wrote in the previous stage).
 __device__ __forceinline__ void wave_lds_sync() {

@@ -117,26 +117,19 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, 
 // Exclusive prefix of the filters' tile counts ceil(pcnt[f] / 16) (one
 // work-group; tile_prefix[F] = total).
 __global__ void __launch_bounds__(1024) k_mlp_tiles(int F, const int32_t *__restrict__ pcnt, int32_t *tile_prefix) {
-  __shared__ int32_t part[1024];
+  __shared__ int32_t sh[16];
   const int tid = threadIdx.x;
   const int per = (F + 1023) / 1024;
-  const int f0 = tid * per, f1 = min(F, f0 + per);
+  const int f0 = min(F, tid * per), f1 = min(F, f0 + per);
   int sum = 0;
   for (int f = f0; f < f1; ++f) sum += (pcnt[f] + kMlpQ - 1) / kMlpQ;
-  part[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int v = tid >= o ? part[tid - o] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int run = part[tid] - sum;
+  int total;
+  int run = block_scan_excl<1024>(sum, sh, total);
   for (int f = f0; f < f1; ++f) {
     tile_prefix[f] = run;
     run += (pcnt[f] + kMlpQ - 1) / kMlpQ;
   }
-  if (tid == 1023) tile_prefix[F] = part[1023];
+  if (tid == 0) tile_prefix[F] = total;
 }
 
 // Pruning values for listed pairs: filter f evaluates the entries

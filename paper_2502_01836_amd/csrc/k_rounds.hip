@@ -18,13 +18,21 @@ namespace {
 // surviving leaves in visit order.  All decisions of the round use the tau
 // from before the round.  The order is by ascending d^lb, so the first leaf
 // the bound prunes ends the walk (every later leaf is pruned too).
-__global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float *__restrict__ lbs,
-                                                  const int32_t *__restrict__ order, const float *__restrict__ dfo,
-                                                  const int32_t *__restrict__ leaf_n, int want, Schedule sched,
-                                                  int32_t *qround, RoundBufs b) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (q >= nq) return;  // whole wavefront
+constexpr int kListWaves = 16;  // queries (wavefronts) per work-group of the prune cascade
+
+__global__ void __launch_bounds__(64 * kListWaves) k_worklist(int64_t nq, int N, const float *__restrict__ lbs,
+                                                             const int32_t *__restrict__ order,
+                                                             const float *__restrict__ dfo,
+                                                             const int32_t *__restrict__ leaf_n, int want,
+                                                             Schedule sched, int32_t *qround, RoundBufs b) {
+  __shared__ int64_t stat[4][kListWaves];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  // the round's control words start from zero (nothing reads them during this kernel)
+  if (blockIdx.x == 0 && threadIdx.x < kCtlRoundWords) b.ctl[threadIdx.x] = 0;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kListWaves + wave;
+  int cnt = 0;
+  int64_t lbp = 0, fp = 0, series = 0;
+  if (q < nq) {
   int pos = b.cursor[q];
   if (qround && pos < N) {
     // serving: each query follows its own schedule from its own round count
@@ -32,8 +40,6 @@ __global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float
     want = sched.r[r < sched.n ? r : sched.n - 1];
     if (lane == 0) qround[q] = r + 1;
   }
-  int cnt = 0;
-  int64_t lbp = 0, fp = 0, series = 0;
   if (pos < N) {
     const float tau = b.tau[q];
     const float tau_lb = tau * (1.0f + kLbSlack);
@@ -92,12 +98,22 @@ __global__ void __launch_bounds__(256) k_worklist(int64_t nq, int N, const float
   if (lane == 0) {
     b.cursor[q] = pos;
     b.qitem_cnt[q] = cnt;
-    if (lbp) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlLbPruned), static_cast<unsigned long long>(lbp));
-    if (fp) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFPruned), static_cast<unsigned long long>(fp));
-    if (cnt) {
-      atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlScanned), static_cast<unsigned long long>(cnt));
-      atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlSeries), static_cast<unsigned long long>(series));
-    }
+  }
+  }  // q < nq
+  // one atomic per counter and work-group
+  if (lane == 0) {
+    stat[0][wave] = lbp;
+    stat[1][wave] = fp;
+    stat[2][wave] = cnt;
+    stat[3][wave] = series;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    int64_t v = 0;
+    for (int w = 0; w < kListWaves; ++w) v += stat[threadIdx.x][w];
+    const int word = threadIdx.x == 0 ? kCtlLbPruned : threadIdx.x == 1 ? kCtlFPruned
+                   : threadIdx.x == 2 ? kCtlScanned : kCtlSeries;
+    if (v) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + word), static_cast<unsigned long long>(v));
   }
 }
 
@@ -151,11 +167,10 @@ __global__ void __launch_bounds__(256) k_round_reset(RoundBufs b, int n_ctl, int
 // Exclusive scans over leaves: item starts and tile starts (one work-group).
 __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__restrict__ leaf_off, int mq,
                                                     int64_t row_bytes, RoundBufs b) {
-  __shared__ int64_t part_i[1024];
-  __shared__ int64_t part_t[1024];
-  int tid = threadIdx.x;
-  int per = (N + 1023) / 1024;
-  int l0 = tid * per, l1 = min(N, l0 + per);
+  __shared__ int64_t sh[16];
+  const int tid = threadIdx.x;
+  const int per = (N + 1023) / 1024;
+  const int l0 = min(N, tid * per), l1 = min(N, l0 + per);
   int64_t si = 0, stl = 0, rows = 0;
   for (int L = l0; L < l1; ++L) {
     int c = b.leaf_cnt[L];
@@ -164,22 +179,10 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
     stl += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
     if (c > 0) rows += leaf_off[L + 1] - leaf_off[L];
   }
-  if (row_bytes > 0 && rows > 0)
-    atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlScanBytes),
-              static_cast<unsigned long long>(rows * row_bytes));
-  part_i[tid] = si;
-  part_t[tid] = stl;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over the 1024 partial sums
-  for (int o = 1; o < 1024; o <<= 1) {
-    int64_t ai = tid >= o ? part_i[tid - o] : 0;
-    int64_t at = tid >= o ? part_t[tid - o] : 0;
-    __syncthreads();
-    part_i[tid] += ai;
-    part_t[tid] += at;
-    __syncthreads();
-  }
-  int64_t ri = part_i[tid] - si, rt = part_t[tid] - stl;
+  int64_t tot_i, tot_t, tot_r;
+  int64_t ri = block_scan_excl<1024>(si, sh, tot_i);
+  int64_t rt = block_scan_excl<1024>(stl, sh, tot_t);
+  block_scan_excl<1024>(rows, sh, tot_r);
   for (int L = l0; L < l1; ++L) {
     int c = b.leaf_cnt[L];
     int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + b.chunk - 1) / b.chunk;
@@ -189,12 +192,15 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
     ri += c;
     rt += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
   }
-  if (tid == 1023) {
-    b.leaf_istart[N] = static_cast<int32_t>(part_i[1023]);
-    b.tile_start[N] = static_cast<int32_t>(part_t[1023]);
-    b.ctl[kCtlItems] = part_i[1023];
-    b.ctl[kCtlTiles] = part_t[1023];
-    if (row_bytes > 0 && part_i[1023] > 0) b.ctl[kCtlRounds] += 1;
+  if (tid == 0) {
+    b.leaf_istart[N] = static_cast<int32_t>(tot_i);
+    b.tile_start[N] = static_cast<int32_t>(tot_t);
+    b.ctl[kCtlItems] = tot_i;
+    b.ctl[kCtlTiles] = tot_t;
+    if (row_bytes > 0 && tot_i > 0) {
+      b.ctl[kCtlScanBytes] += tot_r * row_bytes;
+      b.ctl[kCtlRounds] += 1;
+    }
   }
 }
 
@@ -230,6 +236,13 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
   uint32_t *tags = reinterpret_cast<uint32_t *>(mine + sizeof(double) * C);
   const int per = (C - KM) / KM;  // items per pass
   const uint64_t lt = (1ull << lane) - 1ull;
+  __shared__ int active_sh[4];
+  // the per-leaf item counts are not needed past this point: leave them zero
+  // for the next pass (rescan or round)
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b.leaf_cnt[i] = 0;
+  int active = 0;
   for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
     int n_it = b.qitem_cnt[q];
     if (n_it > 0) {
@@ -317,9 +330,16 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
         }
       }
       wave_lds_sync();
+      if (lane == 0) b.qitem_cnt[q] = 0;  // read by nothing else: zero for a rescan pass
     }
-    if (check_cert && lane == 0 && b.cursor[q] < N)
-      atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlActive), 1ull);
+    if (check_cert && b.cursor[q] < N) ++active;
+  }
+  // one atomic per work-group for the count of queries with leaves left
+  if (lane == 0) active_sh[wave] = active;
+  __syncthreads();
+  if (check_cert && threadIdx.x == 0) {
+    const int a = active_sh[0] + active_sh[1] + active_sh[2] + active_sh[3];
+    if (a) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlActive), static_cast<unsigned long long>(a));
   }
 }
 
@@ -409,8 +429,8 @@ void launch_worklist(int64_t nq, int N, const float *lbs, const int32_t *order, 
                      int32_t *qround) {
   Schedule sc{};
   if (sched) sc = *sched;
-  hipLaunchKernelGGL(k_worklist, dim3(ceil_div(nq, 4)), dim3(256), 0, st, nq, N, lbs, order, dfo, leaf_n, want, sc,
-                     qround, b);
+  hipLaunchKernelGGL(k_worklist, dim3(ceil_div(std::max<int64_t>(nq, 1), kListWaves)), dim3(64 * kListWaves), 0, st,
+                     nq, N, lbs, order, dfo, leaf_n, want, sc, qround, b);
   LAUNCH_OK("worklist");
 }
 

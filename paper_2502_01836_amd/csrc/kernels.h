@@ -85,19 +85,23 @@ __host__ __device__ inline int64_t tile_of(const int32_t *tile_start, int L, int
   return static_cast<int64_t>(tile_start[L]) + static_cast<int64_t>(c) * G + g;
 }
 
+// Control words: each on its own 128-byte line (kCtlStride int64 apart), so
+// that atomics on different counters do not serialise on one L2 line.
+constexpr int kCtlStride = 16;
 enum Ctl : int {
-  kCtlItems = 0,      // items this round
-  kCtlTiles = 1,      // scan tiles this round
-  kCtlActive = 2,     // queries with leaves left
-  kCtlFallback = 3,   // uncertified items queued for an exact rescan
-  kCtlLbPruned = 4,
-  kCtlFPruned = 5,
-  kCtlSeries = 6,     // real series in scanned items
-  kCtlScanned = 7,    // items (leaves) scanned, excluding rescans
-  kCtlFbTotal = 8,    // uncertified items rescanned, over the batch
-  kCtlScanBytes = 9,  // unique leaf-store bytes the regular rounds read
-  kCtlRounds = 10,    // regular rounds with at least one item
-  kCtlCount = 12
+  kCtlItems = 0 * kCtlStride,       // items this round
+  kCtlTiles = 1 * kCtlStride,       // scan tiles this round
+  kCtlActive = 2 * kCtlStride,      // queries with leaves left
+  kCtlFallback = 3 * kCtlStride,    // uncertified items queued for an exact rescan
+  kCtlLbPruned = 4 * kCtlStride,
+  kCtlFPruned = 5 * kCtlStride,
+  kCtlSeries = 6 * kCtlStride,      // real series in scanned items
+  kCtlScanned = 7 * kCtlStride,     // items (leaves) scanned, excluding rescans
+  kCtlFbTotal = 8 * kCtlStride,     // uncertified items rescanned, over the batch
+  kCtlScanBytes = 9 * kCtlStride,   // unique leaf-store bytes the regular rounds read
+  kCtlRounds = 10 * kCtlStride,     // regular rounds with at least one item
+  kCtlCount = 11 * kCtlStride,
+  kCtlRoundWords = kCtlFallback + 1  // words a round starts from zero (items .. fallback)
 };
 
 struct StoreView {
