@@ -124,6 +124,12 @@ def main():
         ids, d = ix.search(q, k=kt, target=tt, k_max=k, use_filters=False, schedule=sched)
         exact.append(d.cpu().numpy().astype(np.float64))
 
+    # scan tile shape: timed on the sigma = 0.1 batch, fastest kept
+    t0 = time.time()
+    tune = ix.autotune(qd[1], k=kt, target=tt, k_max=k, use_filters=True, schedule=sched, repeats=5)
+    log(f"tuned scan tiles in {time.time() - t0:.1f}s: {tune['chosen']} of "
+        f"{[(c['chunk_rows'], c['queries_per_tile'], round(c['ms'], 3)) for c in tune['candidates']]}")
+
     def step(i, with_stats=False):
         return ix.search(qd[i % len(qd)], k=kt, target=tt, k_max=k, use_filters=True, schedule=sched,
                          with_stats=with_stats, out=out)
@@ -276,6 +282,7 @@ def main():
                      "scan_bytes_per_step": t_scan_bytes / (a.steps if ts else len(qd)),
                      "measured_in": "timed steps" if ts else "one extra pass per batch"},
         "search_path": sorted(paths),
+        "scan_tiling": tune,
         "cpu_baseline": cpu,
         "serving": serving,
         "setup_s": {"build": t_build, "train": t_train, "calibrate": t_cal,

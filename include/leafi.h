@@ -275,6 +275,40 @@ int leafi_search_knn(leafi_index *index, const float *queries_dev, int64_t nq, c
                      float *dists_dev, leafi_search_stats *stats, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Scan tiling auto-tuner (no counterpart in the paper: it picks the BF16 leaf
+ * scan's tile shape for this GPU and workload)
+ * ---------------------------------------------------------------------- */
+
+#define LEAFI_TUNE_MAX 16
+
+typedef struct {
+  int32_t n_candidates;                 /* tile shapes timed */
+  int32_t chosen;                       /* index of the fastest, now in use */
+  int32_t chunk_rows[LEAFI_TUNE_MAX];   /* leaf rows per scan tile */
+  int32_t queries_per_tile[LEAFI_TUNE_MAX];
+  double ms[LEAFI_TUNE_MAX];            /* median time of one search of the sample batch */
+} leafi_tune_report;
+
+/*
+ * Time the sample batch (queries_dev [nq, m], k_dev, target_dev and opts as
+ * for leafi_search_knn, BF16 scan) once per candidate tile shape -- rows per
+ * tile in {512, 1024, 2048} and, when at most 32 candidates are kept per
+ * (query, leaf), 16 or 32 queries per tile -- `repeats` times each after one
+ * warm-up, and keep the shape with the smallest median for all later searches
+ * of this index.  Results of every search are identical under every shape.
+ * The stream is synchronised.  `report` (host) may be NULL.
+ */
+int leafi_autotune(leafi_index *index, const float *queries_dev, int64_t nq, const int32_t *k_dev,
+                   const float *target_dev, const leafi_search_opts *opts, int32_t repeats,
+                   leafi_tune_report *report, void *stream);
+
+/* Set the BF16 scan's tile shape directly (what leafi_autotune chooses):
+ * chunk_rows in {128, 256, ..., 4096}; queries_per_tile 16 or 32 (used when
+ * at most 32 candidates are kept per (query, leaf), else 16).  The default is
+ * 1024 rows and 32 queries.  Results do not depend on the shape. */
+int leafi_set_tiling(leafi_index *index, int32_t chunk_rows, int32_t queries_per_tile);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of k-NN requests (Algorithm 2 for a stream of
  * queries with mixed k and recall targets)
  *

@@ -183,6 +183,39 @@ class Index:
             return ids, dists, struct_dict(st)
         return ids, dists
 
+    def autotune(self, queries, k=1, target=1.0, k_max=None, use_filters: bool = True, schedule=(1, 0),
+                 kprime: int = 0, repeats: int = 5):
+        """Time the BF16 scan's tile shapes on this sample batch and keep the
+        fastest for later searches; returns the tuner's report."""
+        torch = _torch()
+        nq = queries.shape[0]
+        dev = queries.device
+        kt = k if isinstance(k, torch.Tensor) else torch.full((nq,), int(k), dtype=torch.int32, device=dev)
+        tt = target if isinstance(target, torch.Tensor) else torch.full((nq,), float(target), dtype=torch.float32,
+                                                                         device=dev)
+        if k_max is None:
+            k_max = int(k) if not isinstance(k, torch.Tensor) else int(kt.max().item())
+        o = _lib.SearchOpts()
+        load().leafi_default_search_opts(ctypes.byref(o))
+        o.k_max = k_max
+        o.use_filters = 1 if use_filters else 0
+        o.n_schedule = len(schedule)
+        for i, s_ in enumerate(schedule):
+            o.schedule[i] = s_
+        o.kprime = kprime
+        rep = _lib.TuneReport()
+        check(load().leafi_autotune(self._h, _dev(queries, torch.float32, "queries"), nq, _dev(kt, torch.int32, "k"),
+                                    _dev(tt, torch.float32, "target"), ctypes.byref(o), repeats, ctypes.byref(rep),
+                                    _stream()))
+        n = rep.n_candidates
+        return {"candidates": [{"chunk_rows": rep.chunk_rows[i], "queries_per_tile": rep.queries_per_tile[i],
+                                "ms": rep.ms[i]} for i in range(n)],
+                "chosen": {"chunk_rows": rep.chunk_rows[rep.chosen], "queries_per_tile": rep.queries_per_tile[rep.chosen],
+                           "ms": rep.ms[rep.chosen]}}
+
+    def set_tiling(self, chunk_rows: int = 1024, queries_per_tile: int = 32):
+        check(load().leafi_set_tiling(self._h, chunk_rows, queries_per_tile))
+
     def lower_bounds(self, queries):
         torch = _torch()
         nq = queries.shape[0]

@@ -70,6 +70,15 @@ class SearchStats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_scan", ctypes.c_double), ("scan_bytes", ctypes.c_double)]
 
 
+LEAFI_TUNE_MAX = 16
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int32), ("chosen", ctypes.c_int32),
+                ("chunk_rows", ctypes.c_int32 * LEAFI_TUNE_MAX), ("queries_per_tile", ctypes.c_int32 * LEAFI_TUNE_MAX),
+                ("ms", ctypes.c_double * LEAFI_TUNE_MAX)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("k_max", ctypes.c_int32), ("scan", ctypes.c_int32),
                 ("use_filters", ctypes.c_int32), ("n_schedule", ctypes.c_int32), ("schedule", ctypes.c_int32 * 8),
@@ -115,6 +124,8 @@ SIGNATURES = [
     ("leafi_default_search_opts", None, [ctypes.POINTER(SearchOpts)]),
     ("leafi_search_knn", ctypes.c_int, [P, P, I64, P, P, ctypes.POINTER(SearchOpts), P, P,
                                         ctypes.POINTER(SearchStats), P]),
+    ("leafi_autotune", ctypes.c_int, [P, P, I64, P, P, ctypes.POINTER(SearchOpts), I32, ctypes.POINTER(TuneReport), P]),
+    ("leafi_set_tiling", ctypes.c_int, [P, I32, I32]),
     ("leafi_default_server_opts", None, [ctypes.POINTER(ServerOpts)]),
     ("leafi_server_create", ctypes.c_int, [P, ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]),
     ("leafi_server_destroy", None, [P]),

@@ -264,7 +264,10 @@ int pick_chunk(const leafi_index *ix, int kprime, int pref) {
   return chunk;
 }
 int pass_chunk(const leafi_index *ix, bool bf16, int kprime) {
-  return pick_chunk(ix, kprime, bf16 ? kChunkRows : kFp32ChunkRows);
+  return pick_chunk(ix, kprime, bf16 ? ix->tune_chunk : kFp32ChunkRows);
+}
+void pass_geometry(const leafi_index *ix, bool bf16, int kprime, int *mq, int *cap) {
+  scan_geometry(kprime, mq, cap, bf16 ? ix->tune_mq : 32);
 }
 
 int64_t tiles_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, int mq, int chunk) {
@@ -276,7 +279,7 @@ int64_t tiles_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, int 
 
 double round_bytes_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, bool bf16, int kprime, int kmax) {
   int mq, cap;
-  scan_geometry(kprime, &mq, &cap);
+  pass_geometry(ix, bf16, kprime, &mq, &cap);
   const int chunk = pass_chunk(ix, bf16, kprime);
   return static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
          static_cast<double>(tiles_bound(ix, nq, items_bound, mq, chunk)) * mq * kprime * 8.0;
@@ -288,7 +291,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   RoundOpts def;
   if (!ro) ro = &def;
   int mq, cap;
-  scan_geometry(kprime, &mq, &cap);
+  pass_geometry(ix, bf16, kprime, &mq, &cap);
   (void)cap;
   const int chunk = pass_chunk(ix, bf16, kprime);
   RoundBufs b0 = views(w);
@@ -521,7 +524,7 @@ void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_
     for (bool bf : {true, false}) {
       const int kp = bf ? p.kprime : kprime_fb;
       int mq, cap;
-      scan_geometry(kp, &mq, &cap);
+      pass_geometry(ix, bf, kp, &mq, &cap);
       const int chunk = pass_chunk(ix, bf, kp);
       cand = std::max(cand, static_cast<size_t>(std::max<int64_t>(tiles_bound(ix, nq, bnd, mq, chunk), 1)) * mq * kp);
     }
@@ -591,7 +594,8 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
   for (int64_t v : {nq, static_cast<int64_t>(p.kmax), static_cast<int64_t>(p.kprime), static_cast<int64_t>(use_f),
                     static_cast<int64_t>(timed), static_cast<int64_t>(ix->N), static_cast<int64_t>(ix->m),
                     static_cast<int64_t>(ix->S), static_cast<int64_t>(ix->filt.F), static_cast<int64_t>(ix->filt.h),
-                    static_cast<int64_t>(ix->cal.pairs()), ix->rows})
+                    static_cast<int64_t>(ix->cal.pairs()), ix->rows,
+                    static_cast<int64_t>(ix->tune_chunk), static_cast<int64_t>(ix->tune_mq)})
     k.push_back(static_cast<uint64_t>(v));
   for (int r : p.schedule) k.push_back(static_cast<uint64_t>(r));
   for (const void *a : {static_cast<const void *>(raw), static_cast<const void *>(k_dev),
@@ -1318,32 +1322,39 @@ void leafi_default_search_opts(leafi_search_opts *o) {
   o->kprime = 0;
 }
 
+namespace leafi {
+SearchPlan make_plan(const leafi_index *ix, const leafi_search_opts *o) {
+  LEAFI_CHECK_ARG(o != nullptr, "opts is NULL");
+  LEAFI_CHECK_ARG(o->k_max >= 1 && o->k_max <= 256, "k_max must be in [1, 256]");
+  LEAFI_CHECK_ARG(o->scan == LEAFI_SCAN_BF16 || o->scan == LEAFI_SCAN_FP32, "unknown scan kind");
+  LEAFI_CHECK_ARG(o->n_schedule >= 1 && o->n_schedule <= 8, "n_schedule must be in [1, 8]");
+  for (int i = 0; i < o->n_schedule; ++i) LEAFI_CHECK_ARG(o->schedule[i] >= 0, "schedule entries must be >= 0");
+  LEAFI_CHECK_ARG(o->kprime >= 0 && o->kprime <= 256, "kprime must be in [0, 256]");
+  LEAFI_CHECK_ARG((o->flags & ~(LEAFI_SEARCH_NO_GRAPH | LEAFI_SEARCH_HOST_ROUNDS)) == 0, "unknown search flags");
+  LEAFI_CHECK_ARG(o->scan != LEAFI_SCAN_BF16 || ix->m <= 256, "the bf16 scan supports m <= 256");
+  SearchPlan p;
+  p.kmax = o->k_max;
+  p.bf16 = o->scan == LEAFI_SCAN_BF16;
+  p.filters = o->use_filters != 0;
+  p.schedule.assign(o->schedule, o->schedule + o->n_schedule);
+  p.kprime = o->kprime > 0 ? std::max<int>(o->kprime, p.kmax) : default_kprime(p.kmax, p.bf16);
+  p.graph = (o->flags & LEAFI_SEARCH_NO_GRAPH) == 0;
+  return p;
+}
+}  // namespace leafi
+
 int leafi_search_knn(leafi_index *ix, const float *queries, int64_t nq, const int32_t *k_dev, const float *t_dev,
                      const leafi_search_opts *o, int64_t *ids, float *dists, leafi_search_stats *stats,
                      void *stream) {
   return guarded([&] {
     require_built(ix);
-    LEAFI_CHECK_ARG(o != nullptr, "opts is NULL");
     check_queries(ix, queries, nq);
-    LEAFI_CHECK_ARG(o->k_max >= 1 && o->k_max <= 256, "k_max must be in [1, 256]");
-    LEAFI_CHECK_ARG(o->scan == LEAFI_SCAN_BF16 || o->scan == LEAFI_SCAN_FP32, "unknown scan kind");
-    LEAFI_CHECK_ARG(o->n_schedule >= 1 && o->n_schedule <= 8, "n_schedule must be in [1, 8]");
-    for (int i = 0; i < o->n_schedule; ++i) LEAFI_CHECK_ARG(o->schedule[i] >= 0, "schedule entries must be >= 0");
-    LEAFI_CHECK_ARG(o->kprime >= 0 && o->kprime <= 256, "kprime must be in [0, 256]");
-    LEAFI_CHECK_ARG((o->flags & ~(LEAFI_SEARCH_NO_GRAPH | LEAFI_SEARCH_HOST_ROUNDS)) == 0, "unknown search flags");
-    LEAFI_CHECK_ARG(o->scan != LEAFI_SCAN_BF16 || ix->m <= 256, "the bf16 scan supports m <= 256");
+    SearchPlan p = make_plan(ix, o);
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (nq == 0) return;
     LEAFI_CHECK_ARG(k_dev && t_dev && ids && dists, "NULL k, target or output pointer");
     hipStream_t st = as_stream(stream);
-    SearchPlan p;
-    p.kmax = o->k_max;
-    p.bf16 = o->scan == LEAFI_SCAN_BF16;
-    p.filters = o->use_filters != 0;
-    p.schedule.assign(o->schedule, o->schedule + o->n_schedule);
-    p.kprime = o->kprime > 0 ? std::max<int>(o->kprime, p.kmax) : default_kprime(p.kmax, p.bf16);
     auto t0 = std::chrono::steady_clock::now();
-    p.graph = (o->flags & LEAFI_SEARCH_NO_GRAPH) == 0;
     if (p.bf16 && (o->flags & LEAFI_SEARCH_HOST_ROUNDS) == 0 && can_plan(ix, nq, p)) {
       search_planned(ix, queries, nq, k_dev, t_dev, p, ids, dists, stats, st);
     } else if (p.bf16) {
@@ -1357,6 +1368,84 @@ int leafi_search_knn(leafi_index *ix, const float *queries, int64_t nq, const in
     if (stats) {
       HIP_OK(hipStreamSynchronize(st));
       stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  });
+}
+
+int leafi_set_tiling(leafi_index *ix, int32_t chunk_rows, int32_t queries_per_tile) {
+  return guarded([&] {
+    require_built(ix);
+    bool ok = false;
+    for (int j = 0; j < kChunkSizes; ++j) ok = ok || chunk_rows == (kRowAlign << j);
+    LEAFI_CHECK_ARG(ok, "chunk_rows must be 128 << j, j = 0 .. 5");
+    LEAFI_CHECK_ARG(queries_per_tile == 16 || queries_per_tile == 32, "queries_per_tile must be 16 or 32");
+    ix->tune_chunk = chunk_rows;
+    ix->tune_mq = queries_per_tile;
+  });
+}
+
+int leafi_autotune(leafi_index *ix, const float *queries, int64_t nq, const int32_t *k_dev, const float *t_dev,
+                   const leafi_search_opts *o, int32_t repeats, leafi_tune_report *report, void *stream) {
+  return guarded([&] {
+    require_built(ix);
+    check_queries(ix, queries, nq);
+    LEAFI_CHECK_ARG(nq > 0 && k_dev && t_dev, "empty sample or NULL k / target");
+    LEAFI_CHECK_ARG(repeats >= 1 && repeats <= 100, "repeats must be in [1, 100]");
+    SearchPlan p = make_plan(ix, o);
+    LEAFI_CHECK_ARG(p.bf16, "the tuner tunes the BF16 scan");
+    p.graph = false;
+    hipStream_t st = as_stream(stream);
+    DevBuf<int64_t> ids(static_cast<size_t>(nq) * p.kmax);
+    DevBuf<float> dists(static_cast<size_t>(nq) * p.kmax);
+    const bool small = p.kprime <= 32;  // candidate lists of at most 32 keys
+    std::vector<std::pair<int, int>> cand;  // (chunk rows, queries per tile)
+    for (int chunk : {512, 1024, 2048})
+      for (int mq : {32, 16})
+        if (small || mq == 16) cand.emplace_back(chunk, mq);
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    HIP_OK(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+    std::vector<double> med(cand.size());
+    const int old_chunk = ix->tune_chunk, old_mq = ix->tune_mq;
+    try {
+      for (size_t c = 0; c < cand.size(); ++c) {
+        ix->tune_chunk = cand[c].first;
+        ix->tune_mq = cand[c].second;
+        std::vector<double> t;
+        for (int r = 0; r <= repeats; ++r) {
+          HIP_OK(hipEventRecord(e0, st));
+          if (can_plan(ix, nq, p)) search_planned(ix, queries, nq, k_dev, t_dev, p, ids.get(), dists.get(), nullptr, st);
+          else search_batch(ix, queries, nq, k_dev, t_dev, p, ids.get(), dists.get(), nullptr, st);
+          HIP_OK(hipEventRecord(e1, st));
+          HIP_OK(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+          if (r > 0) t.push_back(ms);  // the first run is the warm-up
+        }
+        std::sort(t.begin(), t.end());
+        med[c] = t[t.size() / 2];
+      }
+    } catch (...) {
+      ix->tune_chunk = old_chunk;
+      ix->tune_mq = old_mq;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const size_t best = static_cast<size_t>(std::min_element(med.begin(), med.end()) - med.begin());
+    ix->tune_chunk = cand[best].first;
+    ix->tune_mq = cand[best].second;
+    if (report) {
+      std::memset(report, 0, sizeof(*report));
+      report->n_candidates = static_cast<int32_t>(cand.size());
+      report->chosen = static_cast<int32_t>(best);
+      for (size_t c = 0; c < cand.size() && c < LEAFI_TUNE_MAX; ++c) {
+        report->chunk_rows[c] = cand[c].first;
+        report->queries_per_tile[c] = cand[c].second;
+        report->ms[c] = med[c];
+      }
     }
   });
 }

@@ -155,5 +155,9 @@ struct leafi_index {
   leafi::Calibration cal;
   leafi::Workspace ws;
   int num_cus = 256;
+  // BF16 scan tiling (set by leafi_autotune): rows per tile, and queries per
+  // tile when at most 32 candidates are kept
+  int tune_chunk = leafi::kChunkRows;
+  int tune_mq = 32;
   ~leafi_index();
 };

@@ -535,9 +535,9 @@ void scan_fp32_inst(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, i
 }  // namespace
 
 // Candidate-list geometry for a given kprime: (queries per tile, list capacity).
-void scan_geometry(int kprime, int *mq, int *cap) {
+void scan_geometry(int kprime, int *mq, int *cap, int mq_small) {
   int kc = pow2_at_least(kprime < 4 ? 4 : kprime);
-  if (kc <= 32) { *mq = 32; *cap = 128; }
+  if (kc <= 32) { *mq = mq_small == 16 ? 16 : 32; *cap = 128; }
   else if (kc <= 64) { *mq = 16; *cap = 256; }
   else if (kc <= 128) { *mq = 16; *cap = 256; }
   else { *mq = 16; *cap = 512; }
@@ -546,7 +546,7 @@ void scan_geometry(int kprime, int *mq, int *cap) {
 void launch_scan_bf16(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
                       hipStream_t st) {
   int mq2, cap;
-  scan_geometry(kprime, &mq2, &cap);
+  scan_geometry(kprime, &mq2, &cap, mq);
   if (mq != mq2) fail(LEAFI_EINTERNAL, "scan_bf16: tile geometry mismatch");
   int ks = s.m / 32;
   if (mq == 32) scan_bf16_ks<2>(ks, s, q, b, kprime, cap, cand, grid, st);

@@ -179,8 +179,9 @@ void launch_scan_fp32(StoreView s, QueryView q, RoundBufs b, int mq, int kprime,
 void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int kmax, bool bf16,
                         const uint64_t *cand, int grid, int max_chunks, hipStream_t st);
 
-// Candidate-list geometry for kprime kept keys: queries per tile and list capacity.
-void scan_geometry(int kprime, int *mq, int *cap);
+// Candidate-list geometry for kprime kept keys: queries per tile and list
+// capacity.  For kprime <= 32 the queries per tile are mq_small (16 or 32).
+void scan_geometry(int kprime, int *mq, int *cap, int mq_small = 32);
 
 // Per query: merge the round's items into the running top-k, update tau,
 // queue uncertified items (check_cert) and count active queries.
