@@ -242,9 +242,7 @@ constexpr int kScanBlocksPerCU = 8;
 // Device bytes above which a round's item buffers are sized from the actual
 // counts (one host read-back) instead of from an upper bound.
 constexpr double kPreallocLimit = 1.0 * (1 << 30);
-// Upper bound of the bound-sized round buffers of a planned search (no host
-// read-back at all; see search_planned).
-constexpr double kPlannedLimit = 8.0 * (1 << 30);
+
 
 // With the round's item lists in place (qitem_leaf / qitem_cnt / leaf_cnt)
 // and the round control words zeroed: lay out items and tiles, scan, rerank.

@@ -75,6 +75,10 @@ struct RoundOpts {
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
                    int64_t items_bound = -1, const RoundOpts *ro = nullptr);
 void add_scan_time(leafi_index *ix, Timing *tm);
+// Upper bound of the bound-sized buffers of a round that reads nothing back.
+constexpr double kPlannedLimit = 8.0 * (1 << 30);
+// Device bytes a scan pass of items_bound items needs (items and candidate lists).
+double round_bytes_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, bool bf16, int kprime, int kmax);
 int default_kprime(int kmax, bool bf16);
 
 }  // namespace leafi

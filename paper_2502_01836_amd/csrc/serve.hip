@@ -68,15 +68,21 @@ struct Request {
 template <typename T>
 struct Pinned {
   T *p = nullptr;
+  T *dev = nullptr;  // device address of a mapped allocation
   size_t n = 0;
-  void alloc(size_t c) {
+  void alloc(size_t c, bool mapped = false) {
     release();
-    if (c) HIP_OK(hipHostMalloc(reinterpret_cast<void **>(&p), c * sizeof(T), hipHostMallocDefault));
+    if (c) {
+      HIP_OK(hipHostMalloc(reinterpret_cast<void **>(&p), c * sizeof(T),
+                           mapped ? hipHostMallocMapped : hipHostMallocDefault));
+      if (mapped) HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void **>(&dev), p, 0));
+    }
     n = c;
   }
   void release() {
     if (p) (void)hipHostFree(p);
     p = nullptr;
+    dev = nullptr;
     n = 0;
   }
   ~Pinned() { release(); }
@@ -104,12 +110,15 @@ struct leafi_server {
   std::thread worker;
   std::string worker_error;
   // device state beyond the index workspace
-  DevBuf<int32_t> state, qround, new_slots, new_k, done_slot, n_done;
-  DevBuf<float> new_t, new_raw, done_d;
-  DevBuf<int64_t> done_ids;
-  Pinned<float> h_raw, h_t, h_done_d;
-  Pinned<int32_t> h_slots, h_k, h_done_slot, h_ndone;
+  DevBuf<int32_t> state, qround, new_slots, new_k, n_done;
+  DevBuf<float> new_t, new_raw;
+  Pinned<float> h_raw, h_t;
+  Pinned<int32_t> h_slots, h_k;
+  // finished requests, written by the GPU straight into mapped host memory
+  Pinned<float> h_done_d;
+  Pinned<int32_t> h_done_slot, h_ndone;
   Pinned<int64_t> h_done_ids;
+  bool device_rounds = false;  // the rescan pass runs unconditionally, sized by the round bound
   // statistics
   int64_t rounds = 0, completed = 0;
   double active_sum = 0.0;
@@ -117,6 +126,12 @@ struct leafi_server {
 
   void run();
   void engine_round(int n_new, int &n_active);
+  // items one round can hold: every slot's largest schedule step
+  int64_t round_bound() const {
+    int maxwant = 0;
+    for (int i = 0; i < sched.n; ++i) maxwant = sched.r[i] == 0 ? ix->N : std::max(maxwant, sched.r[i]);
+    return static_cast<int64_t>(slots) * std::min(maxwant, ix->N);
+  }
   ~leafi_server();
 };
 
@@ -153,31 +168,35 @@ void leafi_server::engine_round(int n_new, int &n_active) {
   reset_round(ix, st);
   launch_worklist(slots, N, w.lbs.get(), w.order.get(), use_f ? w.dfo.get() : nullptr, ix->leaf_n.get(), 0, views(w),
                   st, &sched, qround.get());
-  int maxwant = 0;
-  for (int i = 0; i < sched.n; ++i) maxwant = sched.r[i] == 0 ? N : std::max(maxwant, sched.r[i]);
-  const int64_t bound = static_cast<int64_t>(slots) * std::min(maxwant, N);
-  if (scan_round(ix, slots, bf16, kprime, kmax, st, nullptr, bound) != 0)
+  const int64_t bound = round_bound();
+  RoundOpts ro;
+  ro.may_read = !device_rounds;
+  if (scan_round(ix, slots, bf16, kprime, kmax, st, nullptr, bound, &ro) != 0)
     launch_query_merge(slots, N, kmax, true, false, views(w), st);
-  read_ctl(ix, st);
-  const int64_t n_fb = w.h_ctl[kCtlFallback];
-  if (n_fb > 0) {
-    reset_for_fallback(ix, slots, st);
-    launch_emit_fallback(n_fb, N, views(w), st);
-    if (scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, n_fb) != 0)
-      launch_query_merge(slots, N, kmax, false, true, views(w), st);
+  if (device_rounds) {
+    // exact rescan of the uncertified items, sized on the device (an empty
+    // pass exits at once): no read-back inside the round
+    launch_emit_fallback(bound, N, views(w), st);
+    scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, bound, &ro);
+    launch_query_merge(slots, N, kmax, false, true, views(w), st);
+  } else {
+    read_ctl(ix, st);
+    const int64_t n_fb = w.h_ctl[kCtlFallback];
+    if (n_fb > 0) {
+      reset_for_fallback(ix, slots, st);
+      launch_emit_fallback(n_fb, N, views(w), st);
+      if (scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, n_fb) != 0)
+        launch_query_merge(slots, N, kmax, false, true, views(w), st);
+    }
   }
-  HIP_OK(hipMemsetAsync(n_done.get(), 0, sizeof(int32_t), st));
-  launch_collect_done(slots, N, kmax, ix->rowid.get(), views(w), state.get(), done_slot.get(), done_ids.get(),
-                      done_d.get(), n_done.get(), st);
+  // finished requests go straight to mapped host memory (plain stores; the
+  // count is a device atomic, copied back): one synchronisation per round
+  fill_i32(n_done.get(), 1, 0, st);
+  launch_collect_done(slots, N, kmax, ix->rowid.get(), views(w), state.get(), h_done_slot.dev, h_done_ids.dev,
+                      h_done_d.dev, n_done.get(), st);
   d2h(h_ndone.p, n_done.get(), 1, st);
   HIP_OK(hipStreamSynchronize(st));
   const int nd = h_ndone.p[0];
-  if (nd > 0) {
-    d2h(h_done_slot.p, done_slot.get(), nd, st);
-    d2h(h_done_ids.p, done_ids.get(), static_cast<size_t>(nd) * kmax, st);
-    d2h(h_done_d.p, done_d.get(), static_cast<size_t>(nd) * kmax, st);
-    HIP_OK(hipStreamSynchronize(st));
-  }
   const double t = now_s();
   {
     std::lock_guard<std::mutex> lk(mu);
@@ -334,18 +353,23 @@ int leafi_server_create(leafi_index *ix, const leafi_server_opts *o, leafi_serve
     sv->new_k.alloc(slots);
     sv->new_t.alloc(slots);
     sv->new_raw.alloc(static_cast<size_t>(slots) * ix->m);
-    sv->done_slot.alloc(slots);
-    sv->n_done.alloc(1);
-    sv->done_ids.alloc(static_cast<size_t>(slots) * o->k_max);
-    sv->done_d.alloc(static_cast<size_t>(slots) * o->k_max);
+    {
+      // the rescan pass can run without read-back if both passes' buffers fit
+      const int64_t bnd = sv->round_bound();
+      const bool bf = o->scan == LEAFI_SCAN_BF16;
+      sv->device_rounds =
+          round_bytes_bound(ix, slots, bnd, bf, sv->kprime, o->k_max) <= kPlannedLimit &&
+          round_bytes_bound(ix, slots, bnd, false, default_kprime(o->k_max, false), o->k_max) <= kPlannedLimit;
+    }
     sv->h_raw.alloc(static_cast<size_t>(slots) * ix->m);
     sv->h_slots.alloc(slots);
     sv->h_k.alloc(slots);
     sv->h_t.alloc(slots);
-    sv->h_done_slot.alloc(slots);
+    sv->h_done_slot.alloc(slots, true);
     sv->h_ndone.alloc(1);
-    sv->h_done_ids.alloc(static_cast<size_t>(slots) * o->k_max);
-    sv->h_done_d.alloc(static_cast<size_t>(slots) * o->k_max);
+    sv->n_done.alloc(1);
+    sv->h_done_ids.alloc(static_cast<size_t>(slots) * o->k_max, true);
+    sv->h_done_d.alloc(static_cast<size_t>(slots) * o->k_max, true);
     HIP_OK(hipStreamCreate(&sv->st));
     hipLaunchKernelGGL(k_slot_reset_all, dim3(ceil_div(slots, 256)), dim3(256), 0, sv->st, static_cast<int64_t>(slots),
                        ix->N, views(w), sv->state.get(), sv->qround.get());
