@@ -87,9 +87,10 @@ typedef struct {
  * grouped leaf by leaf in fp32 and in a bf16 copy, with per-leaf summaries
  * (per segment the min/max of the members' mean and std).  Any previous
  * index, filters and calibration in the handle are discarded.
- * Limits: 1 <= n < 2^31; 32 <= m <= 512, m a multiple of 32.  The BF16
- * scan needs m <= 256, the FP32 scan m <= 256 or m in {384, 512}; a search
- * with a scan that does not support m fails with LEAFI_EINVAL.
+ * Limits: 1 <= n < 2^31; at most 16384 leaves; 32 <= m <= 512, m a
+ * multiple of 32.  The BF16 scan needs m <= 256, the FP32 scan m <= 256 or
+ * m in {384, 512}; a search with a scan that does not support m fails with
+ * LEAFI_EINVAL.
  */
 int leafi_build_index(leafi_index *index, const float *series_dev, int64_t n, int32_t m,
                       const leafi_build_opts *opts, void *stream);

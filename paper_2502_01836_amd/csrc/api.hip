@@ -824,7 +824,7 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     // 2. tree
     TreeResult tree = build_tree(hmu, hsd, n, S, m, opts->leaf_capacity, opts->split_rule);
     const int N = static_cast<int>(tree.leaves.size());
-    LEAFI_CHECK_ARG(N <= 8192, "more than 8192 leaves; raise leaf_capacity");
+    LEAFI_CHECK_ARG(N <= 16384, "more than 16384 leaves; raise leaf_capacity");
     // 3. padded leaf-contiguous layout
     std::vector<int64_t> off(N + 1, 0), lsz(N);
     for (int L = 0; L < N; ++L) {

@@ -278,7 +278,9 @@ void launch_lb(const float *qstat, int64_t nq, const float *boxes, int N, int S,
 void launch_order(const float *lb, int64_t nq, int N, int32_t *order, float *lbs, hipStream_t st,
                   const int32_t *slots) {
   int P = pow2_at_least(N < 2 ? 2 : N);
-  size_t lds = static_cast<size_t>(P) * sizeof(uint64_t);
+  size_t lds = static_cast<size_t>(P) * sizeof(uint64_t);  // <= 128 KiB for N <= 16384
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_order),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   hipLaunchKernelGGL(k_order, dim3(nq), dim3(256), lds, st, lb, N, P, order, lbs, slots);
   LAUNCH_OK("order");
 }

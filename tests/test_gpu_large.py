@@ -1,0 +1,111 @@
+"""Parity at the two larger configurations, on outputs the FP64 oracle can
+compute one query at a time.
+
+* 10,000,000 random walks of length 256 (precision case): batches of 1,024
+  queries, k = 10, BF16 scan with FP32 rerank; per-query error against FP64
+  brute force over all 10M series.
+* 25,000,000 Gaussian-mixture series of length 96 split at range midpoints
+  (ragged leaves): 4,096 queries with k = 1, 10, 50 in one batch.
+
+Each builds its collection once (about a minute of host time each).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_01836_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def _say(msg):
+    print(f"[large] {msg}", file=sys.stderr, flush=True)
+
+
+def _check(ids, d, want_ids, want_d, xs, qs):
+    """ids equal except near-ties, distances within 1e-4 relative; returns the
+    largest relative distance error per query."""
+    fin = np.isfinite(want_d)
+    assert np.array_equal(np.isfinite(d), fin)
+    rel = np.where(fin, np.abs(d - want_d) / np.maximum(want_d, 1e-6), 0.0)
+    assert rel.max() <= 1e-4, rel.max()
+    for a, b in zip(*np.nonzero((ids != want_ids) & fin)):
+        x = xs[ids[a, b]].astype(np.float64)
+        dg = np.sqrt(((x - qs[a].astype(np.float64)) ** 2).sum())
+        assert abs(dg - want_d[a, b]) <= 3e-5 * want_d[a, b], (a, b)
+    return rel.max(axis=1)
+
+
+def test_precision_10m_k10():
+    pkg = _pkg()
+    wl = W.WORKLOADS["rw10m"]
+    raw = W.random_walk(wl["n"], wl["m"], wl["seed"])
+    _say("generated 10M x 256")
+    ix = pkg.Index().build(torch.from_numpy(raw).cuda(), leaf_capacity=wl["capacity"], n_segments=16)
+    torch.cuda.synchronize()
+    _say(f"built {ix.info()['n_leaves']} leaves")
+    parts = [W.noisy_queries(raw, n, s, wl["test_seed"] + i, wl["test_seed"] + 100 + i)[0]
+             for i, (n, s) in enumerate(zip((342, 341, 341), wl["sigmas"]))]
+    q = np.concatenate(parts)
+    qd = torch.from_numpy(q).cuda()
+    out = (torch.empty((len(q), 10), dtype=torch.int64, device="cuda"),
+           torch.empty((len(q), 10), dtype=torch.float32, device="cuda"))
+    res = []
+    for _ in range(3):  # planned launches, then captured, then replayed
+        ids, d, st = ix.search(qd, k=10, use_filters=False, schedule=(1, 0), with_stats=True, out=out)
+        res.append((ids.clone(), d.clone(), st))
+    assert torch.equal(res[0][0], res[2][0]) and torch.equal(res[0][1], res[2][1])
+    st = res[2][2]
+    _say(f"search stats {st}")
+    assert st["fallback_items"] <= 0.02 * st["leaves_scanned"] + 1
+    ids, d = res[2][0].cpu().numpy(), res[2][1].cpu().numpy().astype(np.float64)
+    xs = O.znorm(raw)
+    del raw
+    rows = np.random.default_rng(11).choice(len(q), 16, replace=False)
+    qs = O.znorm(q[rows])
+    want_ids, want_d = O.knn(xs, qs, 10)
+    err = _check(ids[rows], d[rows], want_ids, want_d, xs, qs)
+    _say(f"per-query max relative distance error vs FP64: {np.array2string(err, precision=2)}")
+
+
+def test_ragged_25m_k_mix():
+    pkg = _pkg()
+    wl = W.WORKLOADS["gm25m"]
+    raw = W.gaussian_mixture(wl["n"], wl["m"], wl["n_comp"], wl["spread"], wl["seed_means"], wl["seed_members"])
+    _say("generated 25M x 96")
+    ix = pkg.Index().build(torch.from_numpy(raw).cuda(), leaf_capacity=wl["capacity"], n_segments=16,
+                           split_rule="midpoint")
+    torch.cuda.synchronize()
+    off, _ = ix.leaves()
+    sizes = np.diff(off)
+    _say(f"built {len(sizes)} leaves, sizes {sizes.min()} .. {sizes.max()}")
+    assert sizes.max() <= wl["capacity"] and sizes.min() < wl["capacity"] // 4  # ragged
+    q, _, _ = W.noisy_queries(raw, wl["nq"], wl["sigma"], wl["q_seed"], wl["q_seed"] + 100)
+    ks = np.array([wl["ks"][i % 3] for i in range(wl["nq"])], dtype=np.int32)
+    qd, kd = torch.from_numpy(q).cuda(), torch.from_numpy(ks).cuda()
+    ids, d, st = ix.search(qd, k=kd, k_max=50, use_filters=False, schedule=(1, 0), with_stats=True)
+    _say(f"search stats {st}")
+    assert st["fallback_items"] <= 0.02 * st["leaves_scanned"] + 1
+    ids, d = ids.cpu().numpy(), d.cpu().numpy().astype(np.float64)
+    xs = O.znorm(raw)
+    del raw
+    rows = np.random.default_rng(12).choice(len(q), 24, replace=False)
+    qs = O.znorm(q[rows])
+    want_ids, want_d = O.knn(xs, qs, 50)
+    for k in wl["ks"]:
+        sel = ks[rows] == k
+        if sel.any():
+            _check(ids[rows][sel, :k], d[rows][sel, :k], want_ids[sel, :k], want_d[sel, :k], xs, qs[sel])
+            assert (ids[rows][sel, k:] == -1).all()
