@@ -22,7 +22,8 @@ namespace {
 // summed per lane over its hidden units, then across the 4 lanes sharing a
 // query and across the wavefronts in a fixed order, so the result of a
 // (query, filter) pair does not depend on which tile or batch holds it.
-constexpr int kMlpQ = 16;
+constexpr int kMlpQ = 32;             // queries per tile
+constexpr int kMlpQB = kMlpQ / 16;    // 16-query column blocks per tile
 
 size_t mlp_infer_lds(int m) { return (static_cast<size_t>(kMlpQ) * (m + 4) + 4 * kMlpQ) * sizeof(float); }
 
@@ -45,16 +46,19 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
   }
   __syncthreads();
   const int c = lane & 15, kq = lane >> 4;
-  float part = 0.0f;
+  float part[kMlpQB];
+#pragma unroll
+  for (int qb = 0; qb < kMlpQB; ++qb) part[qb] = 0.0f;
   for (int jb = 0; jb < h; jb += 256) {
     const int jw = jb + 64 * wave;  // this wavefront's first hidden unit
     if (jw >= h) continue;          // uniform across the wavefront
-    floatx4 acc[4];
+    floatx4 acc[4][kMlpQB];
     bool ok[4];
     int col[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int qb = 0; qb < kMlpQB; ++qb) acc[t][qb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
       col[t] = jw + 16 * t + c;
       ok[t] = col[t] < h;
       if (!ok[t]) col[t] = 0;
@@ -62,12 +66,14 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
     const float *xq = xs + c * S + kq;
     const float *wk = W1 + static_cast<int64_t>(kq) * h;
     int i0 = 0;
-    // 16 inputs per step: all operand loads first, then the 16 products
+    // 16 inputs per step: all operand loads first, then the products; each
+    // A value (a W1 element) serves both 16-query column blocks
     for (; i0 + 16 <= m; i0 += 16) {
-      float av[4][4], bv[4];
+      float av[4][4], bv[4][kMlpQB];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        bv[u] = xq[i0 + 4 * u];
+#pragma unroll
+        for (int qb = 0; qb < kMlpQB; ++qb) bv[u][qb] = xq[16 * qb * S + i0 + 4 * u];
         const float *wr = wk + static_cast<int64_t>(i0 + 4 * u) * h;
 #pragma unroll
         for (int t = 0; t < 4; ++t) av[u][t] = ok[t] ? wr[col[t]] : 0.0f;
@@ -75,33 +81,45 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][t], bv[u], acc[t], 0, 0, 0);
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int qb = 0; qb < kMlpQB; ++qb)
+            acc[t][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][t], bv[u][qb], acc[t][qb], 0, 0, 0);
     }
     for (; i0 < m; i0 += 4) {
-      const float bv = xq[i0];
       const float *wr = wk + static_cast<int64_t>(i0) * h;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const float av = ok[t] ? wr[col[t]] : 0.0f;
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+#pragma unroll
+        for (int qb = 0; qb < kMlpQB; ++qb)
+          acc[t][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xq[16 * qb * S + i0], acc[t][qb], 0, 0, 0);
       }
     }
-    // lane holds hidden units jw + 16 t + 4 kq + r of query c
+    // lane holds hidden units jw + 16 t + 4 kq + r of queries c + 16 qb
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int j = jw + 16 * t + 4 * kq + r;
-        if (j < h) part = fmaf(w2[j], fmaxf(acc[t][r] + b1[j], 0.0f), part);
+        if (j < h) {
+          const float wj = w2[j], bj = b1[j];
+#pragma unroll
+          for (int qb = 0; qb < kMlpQB; ++qb) part[qb] = fmaf(wj, fmaxf(acc[t][qb][r] + bj, 0.0f), part[qb]);
+        }
       }
   }
-  part += __shfl_xor(part, 16);
-  part += __shfl_xor(part, 32);
-  if (lane < 16) red[wave * 16 + lane] = part;
+#pragma unroll
+  for (int qb = 0; qb < kMlpQB; ++qb) {
+    part[qb] += __shfl_xor(part[qb], 16);
+    part[qb] += __shfl_xor(part[qb], 32);
+    if (lane < 16) red[wave * kMlpQ + 16 * qb + lane] = part[qb];
+  }
   __syncthreads();
   if (tid < kMlpQ) {
     const int64_t r = r0 + tid;
-    if (r < nrows) out(r, ((red[tid] + red[16 + tid]) + (red[32 + tid] + red[48 + tid])) + b2);
+    if (r < nrows)
+      out(r, ((red[tid] + red[kMlpQ + tid]) + (red[2 * kMlpQ + tid] + red[3 * kMlpQ + tid])) + b2);
   }
 }
 

@@ -397,22 +397,33 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
     // number of real candidates among the first kprime
     int nc = 0;
     for (int e = 0; e < kprime; ++e) nc += buf[e] != kKeyMax ? 1 : 0;
-    // FP32 direct-difference rerank
+    // FP32 direct-difference rerank: CB candidates at a time, G lanes each
+    // (all their rows are in flight together), 4 consecutive elements per lane
     const float *qp = qv.q32 + q * m;
-    for (int e = 0; e < PK; ++e) {
+    const int CB = PK < 8 ? PK : 8, GL = kWave / CB;
+    const int sub = lane & (GL - 1), cb = lane / GL;
+    for (int e0 = 0; e0 < PK; e0 += CB) {
+      const int e = e0 + cb;
+      float p = 0.0f;
+      uint32_t row = 0;
       if (e < nc) {
-        uint32_t row = key_row(buf[e]);
+        row = key_row(buf[e]);
         const float *xp = s.x32 + static_cast<int64_t>(row) * m;
-        float p = 0.0f;
-        for (int t = lane; t < m; t += kWave) {
-          float d = qp[t] - xp[t];
+        for (int t = 4 * sub; t < m; t += 4 * GL) {
+          const float4 a = *reinterpret_cast<const float4 *>(qp + t);
+          const float4 x = *reinterpret_cast<const float4 *>(xp + t);
+          float d = a.x - x.x;
+          p = fmaf(d, d, p);
+          d = a.y - x.y;
+          p = fmaf(d, d, p);
+          d = a.z - x.z;
+          p = fmaf(d, d, p);
+          d = a.w - x.w;
           p = fmaf(d, d, p);
         }
-        p = wave_sum(p);
-        if (lane == 0) k32[e] = make_key(p, row);
-      } else if (lane == 0) {
-        k32[e] = kKeyMax;
       }
+      for (int o = GL >> 1; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
+      if (sub == 0) k32[e] = e < nc ? make_key(p, row) : kKeyMax;
     }
     wave_lds_sync();
     wave_sort_u64(k32, PK, lane);
@@ -421,23 +432,30 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
     if (nc >= k) band = key_d2(k32[k - 1]) * (1.0f + 2.0f * delta32);
     int nb = 0;
     for (int e = 0; e < nc; ++e) nb += key_d2(k32[e]) <= band ? 1 : 0;
-    for (int e = 0; e < PK; ++e) {
+    for (int e0 = 0; e0 < PK; e0 += CB) {
+      const int e = e0 + cb;
+      double p = 0.0;
+      uint32_t row = 0xffffffffu;
       if (e < nb) {
-        uint32_t row = key_row(k32[e]);
+        row = key_row(k32[e]);
         const float *xp = s.x32 + static_cast<int64_t>(row) * m;
-        double p = 0.0;
-        for (int t = lane; t < m; t += kWave) {
-          double d = static_cast<double>(qp[t]) - static_cast<double>(xp[t]);
+        for (int t = 4 * sub; t < m; t += 4 * GL) {
+          const float4 a = *reinterpret_cast<const float4 *>(qp + t);
+          const float4 x = *reinterpret_cast<const float4 *>(xp + t);
+          double d = static_cast<double>(a.x) - static_cast<double>(x.x);
+          p = fma(d, d, p);
+          d = static_cast<double>(a.y) - static_cast<double>(x.y);
+          p = fma(d, d, p);
+          d = static_cast<double>(a.z) - static_cast<double>(x.z);
+          p = fma(d, d, p);
+          d = static_cast<double>(a.w) - static_cast<double>(x.w);
           p = fma(d, d, p);
         }
-        p = wave_sum(p);
-        if (lane == 0) {
-          d64[e] = p;
-          r64[e] = row;
-        }
-      } else if (lane == 0) {
-        d64[e] = __builtin_inf();
-        r64[e] = 0xffffffffu;
+      }
+      for (int o = GL >> 1; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
+      if (sub == 0) {
+        d64[e] = e < nb ? p : __builtin_inf();
+        r64[e] = row;
       }
     }
     wave_lds_sync();
