@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--timed-stats", type=int, default=1,
                     help="1: every timed step returns its scan-kernel time (HIP events); 0: no per-step statistics")
+    ap.add_argument("--search-flags", type=int, default=0,
+                    help="leafi_search_opts.flags for the timed steps (1: no graph, 2: host-driven rounds)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for hardware byte counters)")
     a = ap.parse_args()
@@ -132,7 +134,7 @@ def main():
 
     def step(i, with_stats=False):
         return ix.search(qd[i % len(qd)], k=kt, target=tt, k_max=k, use_filters=True, schedule=sched,
-                         with_stats=with_stats, out=out)
+                         with_stats=with_stats, out=out, flags=a.search_flags)
 
     # setup: a batch shape runs as plain launches on its first call and is
     # captured into a HIP graph on its second; prime all three batches

@@ -359,33 +359,15 @@ struct SearchPlan {
   bool graph = true;  // planned batches may be captured and replayed
 };
 
-// Per-batch initialisation in one launch: cursor 0, tau +inf, no results, no
-// items, zero leaf counts, filter-pair counts and control words.
-__global__ void k_batch_init(int64_t nq, int N, int F, RoundBufs b, int32_t *pcnt) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < nq) {
-    b.cursor[i] = 0;
-    b.tau[i] = __builtin_inff();
-    b.res_cnt[i] = 0;
-    b.qitem_cnt[i] = 0;
-  }
-  if (i < N) b.leaf_cnt[i] = 0;
-  if (pcnt && i < F) pcnt[i] = 0;
-  if (i < kCtlCount) b.ctl[i] = 0;
-}
-
 // Queries, lower bounds, visit order, (k, target) pair, batch state.
 void begin_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
                  const SearchPlan &p, bool use_f, hipStream_t st) {
   Workspace &w = ix->ws;
-  prep_queries(ix, raw, nq, st);
-  launch_select_pairs(nq, k_dev, t_dev, use_f ? ix->cal.pairs() : 0, use_f ? ix->cal.pair_k.get() : nullptr,
-                      use_f ? ix->cal.pair_t.get() : nullptr, p.kmax, w.pair.get(), w.kq.get(), st);
-  const int F = ix->filt.F;
-  const int64_t n = std::max<int64_t>(std::max<int64_t>(nq, ix->N), std::max<int64_t>(F, kCtlCount));
-  hipLaunchKernelGGL(k_batch_init, dim3(static_cast<int>(ceil_div(n, 256))), dim3(256), 0, st, nq, ix->N, F,
-                     views(w), use_f ? w.pcnt.get() : nullptr);
-  LAUNCH_OK("batch_init");
+  launch_query_setup(raw, nq, ix->m, ix->S, ix->boxes.get(), ix->N, w.q32.get(), w.q16.get(), w.qn16.get(),
+                     w.qeps.get(), w.qstat.get(), w.lb.get(),
+                     w.order.get(), w.lbs.get(), k_dev, t_dev, use_f ? ix->cal.pairs() : 0,
+                     use_f ? ix->cal.pair_k.get() : nullptr, use_f ? ix->cal.pair_t.get() : nullptr, p.kmax,
+                     views(w), ix->filt.F, use_f ? w.pcnt.get() : nullptr, st);
 }
 
 // After the first round has set tau: d^f for every (query, filtered leaf)
@@ -565,9 +547,11 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     rf.may_read = false;
     launch_emit_fallback(bnd, N, views(w), st);
     scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bnd, &rf);
-    launch_query_merge(nq, N, p.kmax, false, true, views(w), st);
+    // the last merge of the batch also writes the output rows
+    const bool last = r == R - 1;
+    launch_query_merge(nq, N, p.kmax, false, true, views(w), st, last ? ix->rowid.get() : nullptr,
+                       last ? ids : nullptr, last ? dists : nullptr);
   }
-  launch_finalize(nq, p.kmax, ix->rowid.get(), views(w), ids, dists, st);
 }
 
 // Identity of a planned sequence: every value and device address baked into

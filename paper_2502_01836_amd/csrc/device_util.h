@@ -89,6 +89,34 @@ __device__ inline T block_scan_excl(T v, T *sh, T &total) {
   return (wave > 0 ? sh[wave - 1] : T(0)) + x - v;
 }
 
+// Summary lower bound of one (query, leaf): per segment s of length l_s,
+// l_s [gap(mu_q, [mu_lo, mu_hi])^2 + gap(sd_q, [sd_lo, sd_hi])^2], summed in
+// segment order; qs = (mu, sd) per segment, bx = (mu lo, mu hi, sd lo, sd hi).
+__device__ __forceinline__ float summary_lb(const float *qs, const float *bx, int S, int m) {
+  float acc = 0.0f;
+  for (int s = 0; s < S; ++s) {
+    float len = static_cast<float>(((s + 1) * m) / S - (s * m) / S);
+    float mq = qs[2 * s], sq = qs[2 * s + 1];
+    float gm = fmaxf(fmaxf(bx[4 * s] - mq, mq - bx[4 * s + 1]), 0.0f);
+    float gs = fmaxf(fmaxf(bx[4 * s + 2] - sq, sq - bx[4 * s + 3]), 0.0f);
+    acc += len * (gm * gm + gs * gs);
+  }
+  return sqrtf(acc);
+}
+
+// Calibrated (k, target) row of a query: -1 (filters off) for a target >= 1
+// or a pair that was not calibrated.  k is clamped to [1, kmax].
+__device__ __forceinline__ int select_pair_of(int k, float t, int n_pairs, const int32_t *pair_k, const float *pair_t) {
+  int p = -1;
+  if (t < 1.0f)
+    for (int i = 0; i < n_pairs; ++i)
+      if (pair_k[i] == k && pair_t[i] == t) {
+        p = i;
+        break;
+      }
+  return p;
+}
+
 // Orders LDS traffic of one wavefront between stages of a cooperative
 // algorithm (lanes read what other lanes wrote in the previous stage).
 __device__ __forceinline__ void wave_lds_sync() {

@@ -182,27 +182,11 @@ __global__ void __launch_bounds__(256) k_lb(const float *__restrict__ qstat, int
   int64_t i = idx / N;
   int L = static_cast<int>(idx - i * N);
   const int64_t q = slots ? slots[i] : i;
-  const float *qs = qstat + q * S * 2;
-  const float *bx = boxes + static_cast<int64_t>(L) * S * 4;
-  float acc = 0.0f;
-  for (int s = 0; s < S; ++s) {
-    float len = static_cast<float>(((s + 1) * m) / S - (s * m) / S);
-    float mq = qs[2 * s], sq = qs[2 * s + 1];
-    float gm = fmaxf(fmaxf(bx[4 * s] - mq, mq - bx[4 * s + 1]), 0.0f);
-    float gs = fmaxf(fmaxf(bx[4 * s + 2] - sq, sq - bx[4 * s + 3]), 0.0f);
-    acc += len * (gm * gm + gs * gs);
-  }
-  lb[q * N + L] = sqrtf(acc);
+  lb[q * N + L] = summary_lb(qstat + q * S * 2, boxes + static_cast<int64_t>(L) * S * 4, S, m);
 }
 
-// One work-group per query: bitonic sort of (lb bits, leaf id) keys in LDS.
-__global__ void __launch_bounds__(256) k_order(const float *__restrict__ lb, int N, int P, int32_t *order,
-                                               float *lbs, const int32_t *__restrict__ slots) {
-  extern __shared__ uint64_t keys[];
-  const int64_t q = slots ? slots[blockIdx.x] : static_cast<int64_t>(blockIdx.x);
-  for (int i = threadIdx.x; i < P; i += blockDim.x)
-    keys[i] = i < N ? make_key(lb[q * N + i], static_cast<uint32_t>(i)) : kKeyMax;
-  __syncthreads();
+// Work-group bitonic sort of P keys in LDS (P a power of two).
+__device__ inline void block_sort_u64(uint64_t *keys, int P) {
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = threadIdx.x; i < (P >> 1); i += blockDim.x) {
@@ -218,6 +202,99 @@ __global__ void __launch_bounds__(256) k_order(const float *__restrict__ lb, int
       __syncthreads();
     }
   }
+}
+
+// Everything a query needs before its first round, one work-group per query:
+// z-normalisation (fp32 and bf16 copies, norms, rounding error), segment
+// statistics, the summary bound of every leaf, the visit order (bitonic sort
+// of (bound, leaf id)), the calibrated (k, target) row and the search state.
+// The same arithmetic as the separate kernels (k_qprep, k_lb, k_order,
+// select_pair_of).  Work-group 0 also zeroes the batch's control words, leaf
+// counts and filter-pair counts.
+__global__ void __launch_bounds__(256) k_query_setup(const float *__restrict__ raw, int m, int S,
+                                                     const float *__restrict__ boxes, int N, int P, float *q32,
+                                                     uint16_t *q16, float *qn16, float *qeps, float *qstat, float *lb, int32_t *order, float *lbs,
+                                                     const int32_t *__restrict__ k_dev, const float *__restrict__ t_dev,
+                                                     int n_pairs, const int32_t *__restrict__ pair_k,
+                                                     const float *__restrict__ pair_t, int kmax, RoundBufs b,
+                                                     int F, int32_t *pcnt) {
+  extern __shared__ uint64_t keys[];                    // [P]
+  float *zs = reinterpret_cast<float *>(keys + P);       // [m]
+  float *st = zs + m;                                    // [S][2]
+  const int64_t q = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < kCtlCount; i += blockDim.x) b.ctl[i] = 0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) b.leaf_cnt[i] = 0;
+    if (pcnt)
+      for (int i = threadIdx.x; i < F; i += blockDim.x) pcnt[i] = 0;
+  }
+  if (w == 0) {
+    const float *r = raw + q * m;
+    double mu, sd;
+    row_moments(r, m, lane, mu, sd);
+    float nrm = 0.0f, err = 0.0f;
+    for (int t = lane; t < m; t += kWave) {
+      float z = normalise(r[t], mu, sd);
+      uint16_t bb = f32_to_bf16(z);
+      float zb = bf16_to_f32(bb);
+      zs[t] = z;
+      q32[q * m + t] = z;
+      q16[q * m + t] = bb;
+      nrm = fmaf(zb, zb, nrm);
+      float e = z - zb;
+      err = fmaf(e, e, err);
+    }
+    nrm = wave_sum(nrm);
+    err = wave_sum(err);
+    if (lane == 0) {
+      qn16[q] = nrm;
+      qeps[q] = sqrtf(err) * (1.0f + 1e-5f);
+      const int k = min(max(k_dev[q], 1), kmax);
+      b.pair[q] = select_pair_of(k, t_dev[q], n_pairs, pair_k, pair_t);
+      b.kq[q] = k;
+      b.cursor[q] = 0;
+      b.tau[q] = __builtin_inff();
+      b.res_cnt[q] = 0;
+      b.qitem_cnt[q] = 0;
+    }
+    wave_lds_sync();
+    for (int s = lane; s < S; s += kWave) {
+      float a, c;
+      segment_moments(zs, m, S, s, a, c);
+      st[2 * s] = a;
+      st[2 * s + 1] = c;
+      qstat[(q * S + s) * 2 + 0] = a;
+      qstat[(q * S + s) * 2 + 1] = c;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    uint64_t key = kKeyMax;
+    if (i < N) {
+      const float v = summary_lb(st, boxes + static_cast<int64_t>(i) * S * 4, S, m);
+      lb[q * N + i] = v;
+      key = make_key(v, static_cast<uint32_t>(i));
+    }
+    keys[i] = key;
+  }
+  __syncthreads();
+  block_sort_u64(keys, P);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    order[q * N + i] = static_cast<int32_t>(key_row(keys[i]));
+    lbs[q * N + i] = key_d2(keys[i]);
+  }
+}
+
+// One work-group per query: bitonic sort of (lb bits, leaf id) keys in LDS.
+__global__ void __launch_bounds__(256) k_order(const float *__restrict__ lb, int N, int P, int32_t *order,
+                                               float *lbs, const int32_t *__restrict__ slots) {
+  extern __shared__ uint64_t keys[];
+  const int64_t q = slots ? slots[blockIdx.x] : static_cast<int64_t>(blockIdx.x);
+  for (int i = threadIdx.x; i < P; i += blockDim.x)
+    keys[i] = i < N ? make_key(lb[q * N + i], static_cast<uint32_t>(i)) : kKeyMax;
+  __syncthreads();
+  block_sort_u64(keys, P);
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     order[q * N + i] = static_cast<int32_t>(key_row(keys[i]));
     lbs[q * N + i] = key_d2(keys[i]);  // the bound itself, in visit order
@@ -283,6 +360,20 @@ void launch_order(const float *lb, int64_t nq, int N, int32_t *order, float *lbs
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   hipLaunchKernelGGL(k_order, dim3(nq), dim3(256), lds, st, lb, N, P, order, lbs, slots);
   LAUNCH_OK("order");
+}
+
+void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float *boxes, int N, float *q32,
+                        uint16_t *q16, float *qn16, float *qeps, float *qstat, float *lb, int32_t *order, float *lbs, const int32_t *k_dev, const float *t_dev,
+                        int n_pairs, const int32_t *pair_k, const float *pair_t, int kmax, RoundBufs b, int F,
+                        int32_t *pcnt, hipStream_t st) {
+  if (nq <= 0) return;
+  const int P = pow2_at_least(N < 2 ? 2 : N);
+  const size_t lds = static_cast<size_t>(P) * sizeof(uint64_t) + (static_cast<size_t>(m) + 2 * S) * sizeof(float);
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_setup),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(k_query_setup, dim3(static_cast<unsigned>(nq)), dim3(256), lds, st, raw, m, S, boxes, N, P, q32,
+                     q16, qn16, qeps, qstat, lb, order, lbs, k_dev, t_dev, n_pairs, pair_k, pair_t, kmax, b, F, pcnt);
+  LAUNCH_OK("query_setup");
 }
 
 void launch_make_queries(const float *x32, const int64_t *rows, const float *sigma, int64_t nq, int m,

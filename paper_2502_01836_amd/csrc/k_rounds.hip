@@ -227,7 +227,8 @@ __global__ void __launch_bounds__(256) k_scatter(int64_t nq, int N, RoundBufs b)
 // and sorted together, so a query with many items needs few passes.  With
 // `dedupe`, a row met twice (a rescan of a leaf already merged) is kept once.
 __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int KM, int C, int check_cert,
-                                                     int dedupe, RoundBufs b) {
+                                                     int dedupe, RoundBufs b, const int64_t *__restrict__ rowid,
+                                                     int64_t *out_ids, float *out_d) {
   extern __shared__ unsigned char smem_raw[];
   // four wavefronts per work-group, each with its own LDS slice and query
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -329,8 +330,22 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
           }
         }
       }
+      if (out_ids) {  // the batch's last merge: write the query's output row
+        for (int i = lane; i < kmax; i += kWave) {
+          const bool hit = i < cnt;
+          out_ids[q * kmax + i] = hit ? rowid[tags[i]] : -1;
+          out_d[q * kmax + i] = hit ? static_cast<float>(sqrt(vals[i])) : __builtin_inff();
+        }
+      }
       wave_lds_sync();
       if (lane == 0) b.qitem_cnt[q] = 0;  // read by nothing else: zero for a rescan pass
+    } else if (out_ids) {
+      const int cnt = b.res_cnt[q];
+      for (int i = lane; i < kmax; i += kWave) {
+        const bool hit = i < cnt;
+        out_ids[q * kmax + i] = hit ? rowid[b.res_row[q * kmax + i]] : -1;
+        out_d[q * kmax + i] = hit ? static_cast<float>(sqrt(b.res_d2[q * kmax + i])) : __builtin_inff();
+      }
     }
     if (check_cert && b.cursor[q] < N) ++active;
   }
@@ -385,16 +400,8 @@ __global__ void __launch_bounds__(256) k_select_pairs(int64_t nq, const int32_t 
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nq) return;
   const int64_t q = slots ? slots[i] : i;
-  int k = min(max(k_dev[i], 1), kmax);
-  float t = t_dev[i];
-  int p = -1;
-  if (t < 1.0f)
-    for (int i = 0; i < n_pairs; ++i)
-      if (pair_k[i] == k && pair_t[i] == t) {
-        p = i;
-        break;
-      }
-  pair[q] = p;
+  const int k = min(max(k_dev[i], 1), kmax);
+  pair[q] = select_pair_of(k, t_dev[i], n_pairs, pair_k, pair_t);
   kq[q] = k;
 }
 
@@ -466,7 +473,8 @@ void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
   LAUNCH_OK("scatter");
 }
 
-void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st) {
+void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
+                        const int64_t *rowid, int64_t *ids, float *dists) {
   const int KM = pow2_at_least(kmax < 2 ? 2 : kmax);
   // LDS slice per wavefront: the running top-k plus up to 255 items' lists
   // (at most 256 entries unless 2 KM alone is larger)
@@ -477,7 +485,7 @@ void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedup
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_merge),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, KM, C, check_cert ? 1 : 0,
-                     dedupe ? 1 : 0, b);
+                     dedupe ? 1 : 0, b, rowid, ids, dists);
   LAUNCH_OK("query_merge");
 }
 

@@ -122,6 +122,16 @@ struct QueryView {
   const float *qeps;
 };
 
+// All of a batch's per-query preparation in one launch (one work-group per
+// query): the results of launch_qprep, launch_lb, launch_order and
+// launch_select_pairs plus the search state (cursor 0, tau +inf, no results,
+// no items); work-group 0 zeroes the control words, leaf counts and (pcnt
+// non-null) F filter-pair counts.
+void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float *boxes, int N, float *q32,
+                        uint16_t *q16, float *qn16, float *qeps, float *qstat, float *lb, int32_t *order, float *lbs, const int32_t *k_dev, const float *t_dev,
+                        int n_pairs, const int32_t *pair_k, const float *pair_t, int kmax, RoundBufs b, int F,
+                        int32_t *pcnt, hipStream_t st);
+
 // Round schedule: leaves per query in round r = r_[min(r, n - 1)] (0 = all survivors).
 struct Schedule {
   int n;
@@ -184,8 +194,11 @@ void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprim
 void scan_geometry(int kprime, int *mq, int *cap, int mq_small = 32);
 
 // Per query: merge the round's items into the running top-k, update tau,
-// queue uncertified items (check_cert) and count active queries.
-void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st);
+// queue uncertified items (check_cert) and count active queries.  With ids
+// non-null (the batch's last merge) also write every query's output row, as
+// launch_finalize does.
+void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
+                        const int64_t *rowid = nullptr, int64_t *ids = nullptr, float *dists = nullptr);
 
 // Final outputs: ids (original series ids) and Euclidean distances.
 void launch_finalize(int64_t nq, int kmax, const int64_t *rowid, RoundBufs b, int64_t *ids, float *dists,
