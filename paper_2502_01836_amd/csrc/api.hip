@@ -319,7 +319,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   QueryView q = query_view(w);
   launch_scatter(nq, ix->N, b, st);
   int grid_scan = static_cast<int>(std::min<int64_t>(std::max<int64_t>(tiles, 1),
-                                                     static_cast<int64_t>(ix->num_cus) * kScanBlocksPerCU));
+                                                     static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : kScanBlocksPerCU)));
   hipEvent_t e0 = ro->ev_begin ? ro->ev_begin : (tm ? w.ev0 : nullptr);
   hipEvent_t e1 = ro->ev_end ? ro->ev_end : (tm ? w.ev1 : nullptr);
   if (e0) HIP_OK(hipEventRecord(e0, st));
@@ -327,7 +327,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   else launch_scan_fp32(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
   if (e1) HIP_OK(hipEventRecord(e1, st));
   int64_t ib = items >= 0 ? items : std::max<int64_t>(items_bound, 1);
-  int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * 16));
+  int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : 16)));
   launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks_for(chunk), st);
   return items;
 }
@@ -545,6 +545,7 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     launch_query_merge(nq, N, p.kmax, true, false, views(w), st);
     RoundOpts rf;
     rf.may_read = false;
+    rf.small = true;
     launch_emit_fallback(bnd, N, views(w), st);
     scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bnd, &rf);
     // the last merge of the batch also writes the output rows

@@ -70,6 +70,7 @@ struct RoundOpts {
   int64_t row_bytes = 0;        // > 0: account the round's unique leaf bytes in ctl[kCtlScanBytes]
   hipEvent_t ev_begin = nullptr;  // recorded around the scan kernel when set
   hipEvent_t ev_end = nullptr;
+  bool small = false;           // a pass expected to hold few items (rescans): small persistent grids
 };
 // Lay out the round's items, scan and rerank them (see api.hip).
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,

@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
 }
 
 // One wavefront per query: place its emitted leaves into item slots.
-__global__ void __launch_bounds__(256) k_scatter(int64_t nq, int N, RoundBufs b) {
+__global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (q >= nq) return;
@@ -451,8 +451,8 @@ void launch_filter_pairs(int64_t nq, int N, const float *lbs, const int32_t *ord
 
 void launch_emit_fallback(int64_t bound, int N, RoundBufs b, hipStream_t st) {
   if (bound <= 0) return;
-  const int64_t blocks = ceil_div(bound, 256);
-  hipLaunchKernelGGL(k_emit_fallback, dim3(static_cast<int>(blocks < 1024 ? blocks : 1024)), dim3(256), 0, st, N, b);
+  const int64_t blocks = ceil_div(bound, 256);  // grid-stride: rescans are few, a small grid launches fast
+  hipLaunchKernelGGL(k_emit_fallback, dim3(static_cast<int>(blocks < 64 ? blocks : 64)), dim3(256), 0, st, N, b);
   LAUNCH_OK("emit_fallback");
 }
 
@@ -469,7 +469,7 @@ void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, int64_t row_bytes,
 }
 
 void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
-  hipLaunchKernelGGL(k_scatter, dim3(ceil_div(nq, 4)), dim3(256), 0, st, nq, N, b);
+  hipLaunchKernelGGL(k_scatter, dim3(ceil_div(nq, 16)), dim3(1024), 0, st, nq, N, b);  // 16 queries per work-group
   LAUNCH_OK("scatter");
 }
 

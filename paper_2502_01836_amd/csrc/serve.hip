@@ -177,7 +177,9 @@ void leafi_server::engine_round(int n_new, int &n_active) {
     // exact rescan of the uncertified items, sized on the device (an empty
     // pass exits at once): no read-back inside the round
     launch_emit_fallback(bound, N, views(w), st);
-    scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, bound, &ro);
+    RoundOpts rf = ro;
+    rf.small = true;
+    scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, bound, &rf);
     launch_query_merge(slots, N, kmax, false, true, views(w), st);
   } else {
     read_ctl(ix, st);
