@@ -440,8 +440,7 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
     const int64_t active = w.h_ctl[kCtlActive];
     const int64_t n_fb = w.h_ctl[kCtlFallback];
     if (n_fb > 0) {
-      reset_for_fallback(ix, nq, st);
-      launch_emit_fallback(n_fb, N, views(w), st);
+      // the merge left each query's rescan list in its item list
       if (scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, n_fb) != 0)
         launch_query_merge(nq, N, p.kmax, false, true, views(w), st);
     }
@@ -546,7 +545,7 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     RoundOpts rf;
     rf.may_read = false;
     rf.small = true;
-    launch_emit_fallback(bnd, N, views(w), st);
+    // rescan pass over the lists the merge left (empty lists: the pass exits at once)
     scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bnd, &rf);
     // the last merge of the batch also writes the output rows
     const bool last = r == R - 1;

@@ -207,6 +207,11 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
 // One wavefront per query: place its emitted leaves into item slots.
 __global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b) {
   const int lane = threadIdx.x & (kWave - 1);
+  // the per-leaf item counts were consumed by the leaf scan: leave them zero
+  // for the next pass (the merge counts rescan items into them)
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b.leaf_cnt[i] = 0;
   const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (q >= nq) return;
   const int n = b.qitem_cnt[q];
@@ -237,13 +242,8 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
   uint32_t *tags = reinterpret_cast<uint32_t *>(mine + sizeof(double) * C);
   const int per = (C - KM) / KM;  // items per pass
   const uint64_t lt = (1ull << lane) - 1ull;
-  __shared__ int active_sh[4];
-  // the per-leaf item counts are not needed past this point: leave them zero
-  // for the next pass (rescan or round)
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    b.leaf_cnt[i] = 0;
-  int active = 0;
+  __shared__ int active_sh[4], fb_sh[4];
+  int active = 0, n_fb = 0;
   for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
     int n_it = b.qitem_cnt[q];
     if (n_it > 0) {
@@ -319,16 +319,27 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
         b.res_cnt[q] = cnt;
         b.tau[q] = tau;
       }
+      // the query's item list becomes its rescan list: every item whose
+      // certificate bound does not exceed the new tau, in item order
+      int nr = 0;
       if (check_cert) {
-        for (int it = lane; it < n_it; it += kWave) {
-          int idx = b.qitem_idx[q * N + it];
-          if (!(b.item_bound[idx] > tau)) {
-            unsigned long long slot =
-                atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFallback), 1ull);
-            b.fb_q[slot] = static_cast<int32_t>(q);
-            b.fb_leaf[slot] = b.item_leaf[idx];
+        for (int it0 = 0; it0 < n_it; it0 += kWave) {
+          const int it = it0 + lane;
+          bool un = false;
+          int L = 0;
+          if (it < n_it) {
+            const int idx = b.qitem_idx[q * N + it];
+            un = !(b.item_bound[idx] > tau);
+            L = b.item_leaf[idx];
           }
+          const uint64_t mu = __ballot(un);
+          if (un) {
+            b.qitem_leaf[q * N + nr + __popcll(mu & lt)] = L;
+            atomicAdd(b.leaf_cnt + L, 1);
+          }
+          nr += __popcll(mu);
         }
+        n_fb += nr;
       }
       if (out_ids) {  // the batch's last merge: write the query's output row
         for (int i = lane; i < kmax; i += kWave) {
@@ -338,7 +349,7 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
         }
       }
       wave_lds_sync();
-      if (lane == 0) b.qitem_cnt[q] = 0;  // read by nothing else: zero for a rescan pass
+      if (lane == 0) b.qitem_cnt[q] = nr;  // the rescan pass's items of this query (usually none)
     } else if (out_ids) {
       const int cnt = b.res_cnt[q];
       for (int i = lane; i < kmax; i += kWave) {
@@ -349,12 +360,21 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
     }
     if (check_cert && b.cursor[q] < N) ++active;
   }
-  // one atomic per work-group for the count of queries with leaves left
-  if (lane == 0) active_sh[wave] = active;
+  // one atomic per work-group for the count of queries with leaves left and
+  // for the rescan items
+  if (lane == 0) {
+    active_sh[wave] = active;
+    fb_sh[wave] = n_fb;
+  }
   __syncthreads();
   if (check_cert && threadIdx.x == 0) {
     const int a = active_sh[0] + active_sh[1] + active_sh[2] + active_sh[3];
+    const int f = fb_sh[0] + fb_sh[1] + fb_sh[2] + fb_sh[3];
     if (a) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlActive), static_cast<unsigned long long>(a));
+    if (f) {
+      atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFallback), static_cast<unsigned long long>(f));
+      atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFbTotal), static_cast<unsigned long long>(f));
+    }
   }
 }
 

@@ -176,7 +176,6 @@ void leafi_server::engine_round(int n_new, int &n_active) {
   if (device_rounds) {
     // exact rescan of the uncertified items, sized on the device (an empty
     // pass exits at once): no read-back inside the round
-    launch_emit_fallback(bound, N, views(w), st);
     RoundOpts rf = ro;
     rf.small = true;
     scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, bound, &rf);
@@ -185,8 +184,6 @@ void leafi_server::engine_round(int n_new, int &n_active) {
     read_ctl(ix, st);
     const int64_t n_fb = w.h_ctl[kCtlFallback];
     if (n_fb > 0) {
-      reset_for_fallback(ix, slots, st);
-      launch_emit_fallback(n_fb, N, views(w), st);
       if (scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, n_fb) != 0)
         launch_query_merge(slots, N, kmax, false, true, views(w), st);
     }
