@@ -53,31 +53,39 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
     const int jw = jb + 64 * wave;  // this wavefront's first hidden unit
     if (jw >= h) continue;          // uniform across the wavefront
     floatx4 acc[4][kMlpQB];
-    bool ok[4];
     int col[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
 #pragma unroll
       for (int qb = 0; qb < kMlpQB; ++qb) acc[t][qb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
       col[t] = jw + 16 * t + c;
-      ok[t] = col[t] < h;
-      if (!ok[t]) col[t] = 0;
+      if (col[t] >= h) col[t] = 0;
     }
     const float *xq = xs + c * S + kq;
     const float *wk = W1 + static_cast<int64_t>(kq) * h;
     int i0 = 0;
-    // 16 inputs per step: all operand loads first, then the products; each
-    // A value (a W1 element) serves both 16-query column blocks
-    for (; i0 + 16 <= m; i0 += 16) {
-      float av[4][4], bv[4][kMlpQB];
+    // 16 inputs per step; the W1 operands of the next step are loaded while
+    // the current step's products run (two register buffers, unconditional
+    // loads: the last prefetch re-reads the current step).  Each A value (a
+    // W1 element) serves both 16-query column blocks.
+    const int steps = m / 16;
+    float av0[4][4], av1[4][4];
+    auto load_a = [&](float (&av)[4][4], int base) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
+        const float *wr = wk + static_cast<int64_t>(base + 4 * u) * h;
 #pragma unroll
-        for (int qb = 0; qb < kMlpQB; ++qb) bv[u][qb] = xq[16 * qb * S + i0 + 4 * u];
-        const float *wr = wk + static_cast<int64_t>(i0 + 4 * u) * h;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) av[u][t] = ok[t] ? wr[col[t]] : 0.0f;
+        // unconditional load: a hidden unit past h reads column 0 instead, and
+        // its output row is skipped in the output layer below
+        for (int t = 0; t < 4; ++t) av[u][t] = wr[col[t]];
       }
+    };
+    auto step = [&](const float (&av)[4][4], int base) {
+      float bv[4][kMlpQB];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int qb = 0; qb < kMlpQB; ++qb) bv[u][qb] = xq[16 * qb * S + base + 4 * u];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -85,12 +93,30 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
 #pragma unroll
           for (int qb = 0; qb < kMlpQB; ++qb)
             acc[t][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][t], bv[u][qb], acc[t][qb], 0, 0, 0);
+    };
+    if (steps > 0) {
+      load_a(av0, 0);
+      int sidx = 0;
+      // scheduling barriers keep the prefetch ahead of the products (the
+      // compiler would otherwise sink the loads to where they are used)
+      for (; sidx + 2 <= steps; sidx += 2) {
+        load_a(av1, 16 * (sidx + 1));
+        __builtin_amdgcn_sched_barrier(0);
+        step(av0, 16 * sidx);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(av0, 16 * (sidx + 2 < steps ? sidx + 2 : sidx + 1));
+        __builtin_amdgcn_sched_barrier(0);
+        step(av1, 16 * (sidx + 1));
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (sidx < steps) step(av0, 16 * sidx);
+      i0 = 16 * steps;
     }
     for (; i0 < m; i0 += 4) {
       const float *wr = wk + static_cast<int64_t>(i0) * h;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const float av = ok[t] ? wr[col[t]] : 0.0f;
+        const float av = wr[col[t]];
 #pragma unroll
         for (int qb = 0; qb < kMlpQB; ++qb)
           acc[t][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xq[16 * qb * S + i0], acc[t][qb], 0, 0, 0);
@@ -124,7 +150,7 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
 }
 
 // d^f for every (query, filter): grid (F, tiles), 16 queries per tile.
-__global__ void __launch_bounds__(256) k_mlp_infer(const float *__restrict__ w, int F, int m, int h,
+__global__ void __launch_bounds__(256, 3) k_mlp_infer(const float *__restrict__ w, int F, int m, int h,
                                                    const float *__restrict__ x, int64_t nq, float *out) {
   extern __shared__ float xs[];
   const int f = blockIdx.x;
@@ -154,7 +180,7 @@ __global__ void __launch_bounds__(1024) k_mlp_tiles(int F, const int32_t *__rest
 // plist[f * stride + 0 .. pcnt[f]) (q * N + visit position) and writes
 // d^f - o for the query's calibrated (k, target) row.  A persistent grid
 // walks the non-empty tiles of all filters.
-__global__ void __launch_bounds__(256) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
+__global__ void __launch_bounds__(256, 3) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
                                                          const float *__restrict__ x,
                                                          const int64_t *__restrict__ plist,
                                                          const int32_t *__restrict__ pcnt, int64_t stride, int N,
