@@ -52,8 +52,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--timed-stats", type=int, default=1,
                     help="1: every timed step returns its scan-kernel time (HIP events); 0: no per-step statistics")
-    ap.add_argument("--search-flags", type=int, default=0,
-                    help="leafi_search_opts.flags for the timed steps (1: no graph, 2: host-driven rounds)")
+    ap.add_argument("--search-flags", type=int, default=1,
+                    help="leafi_search_opts.flags for the timed steps: 1 (default) the planned launch sequence, "
+                         "whose scan dispatches carry their own timing events; 0 captured HIP graphs; "
+                         "2 host-driven rounds")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for hardware byte counters)")
     a = ap.parse_args()
@@ -170,6 +172,21 @@ def main():
     achieved = t_scan_bytes / (t_scan_ms * 1e-3) / 1e9 if t_scan_ms > 0 else 0.0
     log(f"timed {a.steps} steps: {qps:.0f} queries/s, scan {achieved:.0f} GB/s, paths {sorted(paths)}")
 
+    # the same steps replayed as captured HIP graphs, no statistics (after the
+    # timed region; event-record nodes inside a graph distort kernel timing,
+    # so the scan roofline above comes from the planned launches)
+    def gstep(i):
+        return ix.search(qd[i % len(qd)], k=kt, target=tt, k_max=k, use_filters=True, schedule=sched, out=out)
+    for i in range(2 * len(qd)):
+        gstep(i)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for i in range(a.steps):
+        gstep(i)
+        torch.cuda.synchronize()
+    graph_qps = a.steps * nq / (time.perf_counter() - g0)
+    log(f"graph replay: {graph_qps:.0f} queries/s")
+
     # recall and pruning from one more pass over each batch
     recalls, stats_all = [], []
     for i in range(len(qd)):
@@ -284,6 +301,7 @@ def main():
                      "scan_bytes_per_step": t_scan_bytes / (a.steps if ts else len(qd)),
                      "measured_in": "timed steps" if ts else "one extra pass per batch"},
         "search_path": sorted(paths),
+        "graph_replay_qps": graph_qps,
         "scan_tiling": tune,
         "cpu_baseline": cpu,
         "serving": serving,

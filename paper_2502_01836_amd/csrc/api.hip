@@ -322,10 +322,16 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
                                                      static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : kScanBlocksPerCU)));
   hipEvent_t e0 = ro->ev_begin ? ro->ev_begin : (tm ? w.ev0 : nullptr);
   hipEvent_t e1 = ro->ev_end ? ro->ev_end : (tm ? w.ev1 : nullptr);
-  if (e0) HIP_OK(hipEventRecord(e0, st));
-  if (bf16) launch_scan_bf16(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
+  // Outside graph capture the BF16 scan's own dispatch carries the timing
+  // events (start and stop of the kernel itself); under capture they are
+  // separate event-record nodes around it.
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (e0 || e1) HIP_OK(hipStreamIsCapturing(st, &cs));
+  const bool ext = bf16 && cs == hipStreamCaptureStatusNone;
+  if (e0 && !ext) HIP_OK(hipEventRecord(e0, st));
+  if (bf16) launch_scan_bf16(s, q, b, mq, kprime, w.cand.get(), grid_scan, st, ext ? e0 : nullptr, ext ? e1 : nullptr);
   else launch_scan_fp32(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
-  if (e1) HIP_OK(hipEventRecord(e1, st));
+  if (e1 && !ext) HIP_OK(hipEventRecord(e1, st));
   int64_t ib = items >= 0 ? items : std::max<int64_t>(items_bound, 1);
   int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : 16)));
   launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks_for(chunk), st);

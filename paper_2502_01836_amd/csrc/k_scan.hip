@@ -19,6 +19,8 @@
 // key below the threshold is appended with an LDS atomic; when a list could
 // overflow in the next 64 rows it is sorted (bitonic, one wavefront) and cut
 // to kprime, which also tightens the threshold.
+#include <hip/hip_ext.h>
+
 #include "device_util.h"
 #include "kernels.h"
 
@@ -511,29 +513,32 @@ int resident_grid(K kern, size_t lds, int want) {
 
 template <int KS, int QB>
 void scan_bf16_inst(StoreView s, QueryView q, RoundBufs b, int kprime, int cap, uint64_t *cand, int grid,
-                    hipStream_t st) {
+                    hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int MQ = 16 * QB;
   size_t lds = static_cast<size_t>(MQ) * cap * 8 + MQ * 8 + MQ * 4 + static_cast<size_t>(MQ) * (32 * KS + 8) * 2;
   auto kern = k_scan_bf16<KS, QB>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   grid = resident_grid(kern, lds, grid);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, s, q, b, kprime, cap, cand);
+  if (e0 || e1)  // start / stop timestamps of this dispatch itself
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, e0, e1, 0, s, q, b, kprime, cap, cand);
+  else
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, s, q, b, kprime, cap, cand);
   LAUNCH_OK("scan_bf16");
 }
 
 template <int QB>
 void scan_bf16_ks(int ks, StoreView s, QueryView q, RoundBufs b, int kprime, int cap, uint64_t *cand, int grid,
-                  hipStream_t st) {
+                  hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   switch (ks) {
-    case 1: scan_bf16_inst<1, QB>(s, q, b, kprime, cap, cand, grid, st); break;
-    case 2: scan_bf16_inst<2, QB>(s, q, b, kprime, cap, cand, grid, st); break;
-    case 3: scan_bf16_inst<3, QB>(s, q, b, kprime, cap, cand, grid, st); break;
-    case 4: scan_bf16_inst<4, QB>(s, q, b, kprime, cap, cand, grid, st); break;
-    case 5: scan_bf16_inst<5, QB>(s, q, b, kprime, cap, cand, grid, st); break;
-    case 6: scan_bf16_inst<6, QB>(s, q, b, kprime, cap, cand, grid, st); break;
-    case 7: scan_bf16_inst<7, QB>(s, q, b, kprime, cap, cand, grid, st); break;
-    case 8: scan_bf16_inst<8, QB>(s, q, b, kprime, cap, cand, grid, st); break;
+    case 1: scan_bf16_inst<1, QB>(s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    case 2: scan_bf16_inst<2, QB>(s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    case 3: scan_bf16_inst<3, QB>(s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    case 4: scan_bf16_inst<4, QB>(s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    case 5: scan_bf16_inst<5, QB>(s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    case 6: scan_bf16_inst<6, QB>(s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    case 7: scan_bf16_inst<7, QB>(s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    case 8: scan_bf16_inst<8, QB>(s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
     default: fail(LEAFI_EINVAL, "bf16 scan supports m <= 256");
   }
 }
@@ -562,13 +567,13 @@ void scan_geometry(int kprime, int *mq, int *cap, int mq_small) {
 }
 
 void launch_scan_bf16(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
-                      hipStream_t st) {
+                      hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   int mq2, cap;
   scan_geometry(kprime, &mq2, &cap, mq);
   if (mq != mq2) fail(LEAFI_EINTERNAL, "scan_bf16: tile geometry mismatch");
   int ks = s.m / 32;
-  if (mq == 32) scan_bf16_ks<2>(ks, s, q, b, kprime, cap, cand, grid, st);
-  else scan_bf16_ks<1>(ks, s, q, b, kprime, cap, cand, grid, st);
+  if (mq == 32) scan_bf16_ks<2>(ks, s, q, b, kprime, cap, cand, grid, st, e0, e1);
+  else scan_bf16_ks<1>(ks, s, q, b, kprime, cap, cand, grid, st, e0, e1);
 }
 
 void launch_scan_fp32(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,

@@ -180,7 +180,7 @@ void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st);
 // Leaf scan over all tiles; keeps the kprime best (key = dist^2 bits, row)
 // per (tile, query slot) in cand.
 void launch_scan_bf16(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
-                      hipStream_t st);
+                      hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_scan_fp32(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
                       hipStream_t st);
 
