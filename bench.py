@@ -37,6 +37,24 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per scan dispatch from the committed counter summary, if it
+    was taken with the scan source as it is now (else None)."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "paper_2502_01836_amd", "csrc", "k_scan.hip")
+    summ = os.path.join(here, "profiles", "scan_bf16_rw1m_traffic.md")
+    try:
+        text = open(summ).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_", "k_scan_")))
+    if vals.get("k_scan_sha256", "").strip() != digest:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,7 +311,7 @@ def main():
         "fp32_plain_qps": fp32,
         "speedup_vs_fp32_plain": (qps / fp32) if fp32 else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_scan_bf16", "launches": t_scans,
                      "avg_launch_us": 1e3 * t_scan_ms / max(t_scans, 1),
                      "bytes_per_launch": t_scan_bytes / max(t_scans, 1),
