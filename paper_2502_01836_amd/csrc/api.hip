@@ -130,6 +130,7 @@ RoundBufs views(Workspace &w) {
   b.fb_q = w.fb_q.get();
   b.fb_leaf = w.fb_leaf.get();
   b.chunk = kChunkRows;
+  b.use_tau = 0;
   b.ctl = w.ctl.get();
   return b;
 }
@@ -294,6 +295,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   const int chunk = pass_chunk(ix, bf16, kprime);
   RoundBufs b0 = views(w);
   b0.chunk = chunk;
+  b0.use_tau = ro->use_tau ? 1 : 0;
   launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b0, st);
   int64_t items = -1, tiles;
   const int64_t tb = items_bound >= 0 ? tiles_bound(ix, nq, items_bound, mq, chunk) : -1;
@@ -315,6 +317,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   w.cand.reserve(static_cast<size_t>(std::max<int64_t>(tiles, 1)) * mq * kprime);
   RoundBufs b = views(w);
   b.chunk = chunk;
+  b.use_tau = ro->use_tau ? 1 : 0;
   StoreView s = store_view(ix);
   QueryView q = query_view(w);
   launch_scatter(nq, ix->N, b, st);
@@ -427,6 +430,7 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
   Timing tm;
   RoundOpts ro;
   ro.row_bytes = scan_row_bytes(ix, p.bf16);
+  ro.use_tau = true;
   bool filters_ready = false;
   for (int r = 0;; ++r) {
     if (use_f && r > 0 && !filters_ready) {
@@ -541,6 +545,7 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     const int64_t bnd = planned_bound(ix, nq, p, r);
     RoundOpts ro;
     ro.may_read = false;
+    ro.use_tau = true;
     ro.row_bytes = scan_row_bytes(ix, true);
     if (timed) {
       ro.ev_begin = w.sev[2 * r];

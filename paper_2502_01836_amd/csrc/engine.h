@@ -71,6 +71,7 @@ struct RoundOpts {
   hipEvent_t ev_begin = nullptr;  // recorded around the scan kernel when set
   hipEvent_t ev_end = nullptr;
   bool small = false;           // a pass expected to hold few items (rescans): small persistent grids
+  bool use_tau = false;         // a search round: the BF16 scan skips rows provably farther than tau
 };
 // Lay out the round's items, scan and rerank them (see api.hip).
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,

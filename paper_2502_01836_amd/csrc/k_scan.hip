@@ -80,9 +80,36 @@ __device__ inline TileInfo decode_tile(int t, const StoreView &s, const RoundBuf
 // outstanding global loads, so prefetched rows stay in flight across it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Error bound of the BF16 scan's squared distance for a query with bf16
+// norm^2 qn (rows have norm^2 <= 1.02 m): the computed value is within
+// delta16 of the exact squared distance of the bf16 vectors.
+__device__ __forceinline__ double bf16_delta(double qn, int m) {
+  const double u = 1.0 / 16777216.0;  // 2^-24
+  const double x2 = 1.02 * m;
+  return (m + 3) * 2.0 * u * (qn + x2 + 2.0 * sqrt(qn * x2));
+}
+
+// A query's scan threshold from its best-so-far tau: rows whose computed
+// squared distance reaches it are provably farther than tau (1 + 2^-12), so
+// they can neither enter the query's top k nor need a place in its candidate
+// list.  With rounding moving q and x by at most qeps and leps, a row is at
+// least sqrt(d2 - delta16) - qeps - leps away.  +inf while tau is +inf.
+__device__ __forceinline__ float tau_threshold(float tau, double qn, float qeps, float leps, int m) {
+  if (!(tau < __builtin_inff())) return __builtin_inff();
+  const double t = static_cast<double>(tau) * (1.0 + 1.0 / 4096.0) + qeps + leps;
+  const double v = t * t + bf16_delta(qn, m);
+  float T = static_cast<float>(v);
+  if (static_cast<double>(T) < v) T = nextafterf(T, __builtin_inff());
+  return T;
+}
+
+// Candidate list j of a tile occupies keys[j (cap + 1) .. + cap): the one
+// spare entry per list staggers the lists across LDS banks (appends of
+// different queries at equal slots would otherwise hit one bank).
+
 // Sort list j and keep its kprime best; refresh the threshold.
 __device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int j, int cap, int kprime, int lane) {
-  uint64_t *lst = keys + static_cast<int64_t>(j) * cap;
+  uint64_t *lst = keys + static_cast<int64_t>(j) * (cap + 1);
   int c = cnt[j];
   int P = pow2_at_least(c < 2 ? 2 : c);
   for (int i = c + lane; i < P; i += kWave) lst[i] = kKeyMax;
@@ -91,7 +118,7 @@ __device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int
   int keep = c < kprime ? c : kprime;
   if (lane == 0) {
     cnt[j] = keep;
-    thr[j] = keep == kprime ? lst[kprime - 1] : kKeyMax;
+    if (keep == kprime) thr[j] = lst[kprime - 1];  // else the list is not full: keep the threshold
   }
   wave_lds_sync();
 }
@@ -99,7 +126,7 @@ __device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int
 __device__ inline void append_key(uint64_t *keys, int *cnt, const uint64_t *thr, int j, int cap, uint64_t key) {
   if (key < thr[j]) {
     int slot = atomicAdd(cnt + j, 1);
-    keys[static_cast<int64_t>(j) * cap + slot] = key;
+    keys[static_cast<int64_t>(j) * (cap + 1) + slot] = key;
   }
 }
 
@@ -111,7 +138,7 @@ __device__ inline void finish_tile(uint64_t *keys, int *cnt, uint64_t *thr, int 
       compact_list(keys, cnt, thr, j, cap, kprime, lane);
       // only the first cnt[j] entries are candidates; the list may hold fewer
       // than kprime (a chunk with few real rows) and LDS beyond them is stale
-      const uint64_t *lst = keys + static_cast<int64_t>(j) * cap;
+      const uint64_t *lst = keys + static_cast<int64_t>(j) * (cap + 1);
       const int keep = cnt[j];
       for (int i = lane; i < kprime; i += kWave) out[i] = i < keep ? lst[i] : kKeyMax;
     } else {
@@ -170,7 +197,7 @@ __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &t
         const uint64_t key = make_key(d2, static_cast<uint32_t>(row));
         if (row < ti.real_end && key < tj) {
           const int slot = atomicAdd(cnt + j, 1);
-          keys[static_cast<int64_t>(j) * cap + slot] = key;
+          keys[static_cast<int64_t>(j) * (cap + 1) + slot] = key;
         }
       }
     }
@@ -188,7 +215,7 @@ __global__ void __launch_bounds__(256, 3) k_scan_bf16(StoreView s, QueryView qv,
   constexpr int kWaves = 4;
   extern __shared__ uint64_t smem[];
   uint64_t *keys = smem;
-  uint64_t *thr = keys + MQ * cap;
+  uint64_t *thr = keys + MQ * (cap + 1);
   int *cnt = reinterpret_cast<int *>(thr + MQ);
   uint16_t *qs = reinterpret_cast<uint16_t *>(cnt + MQ);  // [MQ][m + 8], 16-byte aligned
   const int lane = threadIdx.x & (kWave - 1);
@@ -206,8 +233,15 @@ __global__ void __launch_bounds__(256, 3) k_scan_bf16(StoreView s, QueryView qv,
     const int t = static_cast<int>(tt);
     TileInfo ti = decode_tile(t, s, b, MQ);
     if (threadIdx.x < MQ) {
-      cnt[threadIdx.x] = 0;
-      thr[threadIdx.x] = kKeyMax;
+      const int j = threadIdx.x;
+      cnt[j] = 0;
+      uint64_t t0 = kKeyMax;
+      if (b.use_tau && j < ti.nqt) {
+        const int64_t qq = b.item_q[ti.p0 + j];
+        const float T = tau_threshold(b.tau[qq], qv.qn16[qq], qv.qeps[qq], s.leaf_eps[ti.L], m);
+        if (T < __builtin_inff()) t0 = make_key(T, 0u);
+      }
+      thr[j] = t0;
     }
     // B operand: this lane's query column and k-chunk, all K steps
     // The group's bf16 queries go to LDS (row stride m + 8 elements, so the 16
@@ -251,7 +285,7 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
   constexpr int kWaves = 4;
   extern __shared__ uint64_t smem[];
   uint64_t *keys = smem;
-  uint64_t *thr = keys + mq * cap;
+  uint64_t *thr = keys + mq * (cap + 1);
   int *cnt = reinterpret_cast<int *>(thr + mq);
   float *qs = reinterpret_cast<float *>(cnt + mq);
   const int lane = threadIdx.x & (kWave - 1);
@@ -472,15 +506,15 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
     // exact squared distance of the bf16 vectors, and rounding moved q and x
     // by at most qeps and leaf_eps, so d(q, x) >= sqrt(kth - delta16) - eps.
     // FP32: the direct-difference value is within a relative delta32.
+    // With a tau threshold T (search rounds), rows at or above T were never
+    // candidates, so the list's own bound is capped by T's.
     if (lane == 0) {
       float bound = __builtin_inff();
-      if (kth != kKeyMax) {
-        float kd = key_d2(kth);
+      float kd = kth != kKeyMax ? key_d2(kth) : __builtin_inff();
+      if (bf16 && b.use_tau) kd = fminf(kd, tau_threshold(b.tau[q], qv.qn16[q], qv.qeps[q], s.leaf_eps[L], m));
+      if (kd < __builtin_inff()) {
         if (bf16) {
-          double qn = qv.qn16[q];
-          double x2 = 1.02 * m;
-          double delta16 = (m + 3) * 2.0 * u * (qn + x2 + 2.0 * sqrt(qn * x2));
-          double v = static_cast<double>(kd) - delta16;
+          double v = static_cast<double>(kd) - bf16_delta(qv.qn16[q], m);
           bound = static_cast<float>((v > 0.0 ? sqrt(v) : 0.0) - qv.qeps[q] - s.leaf_eps[L]);
         } else {
           bound = static_cast<float>(sqrt(static_cast<double>(kd) * (1.0 - delta32)));
@@ -515,7 +549,7 @@ template <int KS, int QB>
 void scan_bf16_inst(StoreView s, QueryView q, RoundBufs b, int kprime, int cap, uint64_t *cand, int grid,
                     hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int MQ = 16 * QB;
-  size_t lds = static_cast<size_t>(MQ) * cap * 8 + MQ * 8 + MQ * 4 + static_cast<size_t>(MQ) * (32 * KS + 8) * 2;
+  size_t lds = static_cast<size_t>(MQ) * (cap + 1) * 8 + MQ * 8 + MQ * 4 + static_cast<size_t>(MQ) * (32 * KS + 8) * 2;
   auto kern = k_scan_bf16<KS, QB>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -546,7 +580,7 @@ void scan_bf16_ks(int ks, StoreView s, QueryView q, RoundBufs b, int kprime, int
 template <int EPL>
 void scan_fp32_inst(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int cap, uint64_t *cand, int grid,
                     hipStream_t st) {
-  size_t lds = static_cast<size_t>(mq) * cap * 8 + mq * 8 + mq * 4 + static_cast<size_t>(mq) * s.m * 4;
+  size_t lds = static_cast<size_t>(mq) * (cap + 1) * 8 + mq * 8 + mq * 4 + static_cast<size_t>(mq) * s.m * 4;
   auto kern = k_scan_fp32<EPL>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));

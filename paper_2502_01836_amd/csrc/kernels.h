@@ -76,6 +76,9 @@ struct RoundBufs {
   int64_t *ctl;
   // rows per scan tile of the pass in flight (a multiple of kRowAlign)
   int32_t chunk;
+  // 1: a search round, whose BF16 scan may skip rows provably farther than
+  // the query's tau; 0: per-item exact top-k (all-pairs passes)
+  int32_t use_tau;
 };
 
 // Tile of item group g (queries g*mq ..) and row chunk c of leaf L: chunk-major

@@ -171,6 +171,7 @@ void leafi_server::engine_round(int n_new, int &n_active) {
   const int64_t bound = round_bound();
   RoundOpts ro;
   ro.may_read = !device_rounds;
+  ro.use_tau = true;
   if (scan_round(ix, slots, bf16, kprime, kmax, st, nullptr, bound, &ro) != 0)
     launch_query_merge(slots, N, kmax, true, false, views(w), st);
   if (device_rounds) {
@@ -178,6 +179,7 @@ void leafi_server::engine_round(int n_new, int &n_active) {
     // pass exits at once): no read-back inside the round
     RoundOpts rf = ro;
     rf.small = true;
+    rf.use_tau = false;
     scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, bound, &rf);
     launch_query_merge(slots, N, kmax, false, true, views(w), st);
   } else {
