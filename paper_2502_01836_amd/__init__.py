@@ -183,6 +183,37 @@ class Index:
             return ids, dists, struct_dict(st)
         return ids, dists
 
+    def searcher(self, queries, k, target, out, k_max: int, use_filters: bool = True, schedule=(1, 0),
+                 kprime: int = 0, flags: int = 0, with_stats: bool = False):
+        """A search bound to fixed device buffers (queries [nq, m] fp32, k [nq]
+        int32, target [nq] fp32, out = (ids [nq, k_max] int64, dists [nq,
+        k_max] fp32)): the arguments are marshalled once, so each call costs
+        one library call.  The buffers' contents may change between calls.
+        Returns a function of no arguments that returns the statistics dict
+        (with_stats) or None."""
+        torch = _torch()
+        nq = queries.shape[0]
+        o = _lib.SearchOpts()
+        load().leafi_default_search_opts(ctypes.byref(o))
+        o.k_max = k_max
+        o.use_filters = 1 if use_filters else 0
+        o.n_schedule = len(schedule)
+        for i, s_ in enumerate(schedule):
+            o.schedule[i] = s_
+        o.kprime = kprime
+        o.flags = flags
+        st = _lib.SearchStats()
+        args = (self._h, _dev(queries, torch.float32, "queries"), nq, _dev(k, torch.int32, "k"),
+                _dev(target, torch.float32, "target"), ctypes.byref(o), _dev(out[0], torch.int64, "ids"),
+                _dev(out[1], torch.float32, "dists"), ctypes.byref(st) if with_stats else None, _stream())
+        fn = load().leafi_search_knn
+        keep = (queries, k, target, out, o, st)  # the buffers stay alive with the closure
+
+        def run():
+            check(fn(*args))
+            return struct_dict(keep[5]) if with_stats else None
+        return run
+
     def autotune(self, queries, k=1, target=1.0, k_max=None, use_filters: bool = True, schedule=(1, 0),
                  kprime: int = 0, repeats: int = 5):
         """Time the BF16 scan's tile shapes on this sample batch and keep the

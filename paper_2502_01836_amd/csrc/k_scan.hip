@@ -21,6 +21,9 @@
 // to kprime, which also tightens the threshold.
 #include <hip/hip_ext.h>
 
+#include <map>
+#include <mutex>
+
 #include "device_util.h"
 #include "kernels.h"
 
@@ -209,7 +212,7 @@ __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &t
 }
 
 template <int KS, int QB>
-__global__ void __launch_bounds__(256, 3) k_scan_bf16(StoreView s, QueryView qv, RoundBufs b, int kprime, int cap,
+__global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv, RoundBufs b, int kprime, int cap,
                                                    uint64_t *cand) {
   constexpr int MQ = 16 * QB;
   constexpr int kWaves = 4;
@@ -530,17 +533,30 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
 // Work-groups that can be resident at once for `kern` with `lds` bytes of
 // LDS, capped at `want`.  A persistent grid larger than this would leave a
 // tail of work-groups that only start after the first ones have finished.
+// The occupancy query is cached per (kernel, LDS bytes): it is asked on every
+// launch and the answer never changes.
 template <typename K>
 int resident_grid(K kern, size_t lds, int want) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, size_t>, int> cache;
   static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
-    HIP_OK(hipGetDevice(&dev));
-    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const void *fn = reinterpret_cast<const void *>(kern);
+  int g = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (cus == 0) {
+      int dev = 0;
+      HIP_OK(hipGetDevice(&dev));
+      HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    auto it = cache.find({fn, lds});
+    if (it == cache.end()) {
+      int per_cu = 0;
+      HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds));
+      it = cache.emplace(std::make_pair(fn, lds), cus * (per_cu > 0 ? per_cu : 1)).first;
+    }
+    g = it->second;
   }
-  int per_cu = 0;
-  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), 256, lds));
-  int g = cus * (per_cu > 0 ? per_cu : 1);
   g = want < g ? (want > 0 ? want : 1) : g;
   return g >= kXcds ? g / kXcds * kXcds : g;  // a multiple of the XCD count (see xcd_tile)
 }
