@@ -89,6 +89,17 @@ __device__ inline T block_scan_excl(T v, T *sh, T &total) {
   return (wave > 0 ? sh[wave - 1] : T(0)) + x - v;
 }
 
+// Leaf store bf16 layout: 16-row panels (row r of the store is row r % 16 of
+// panel r / 16, whose 16 x m block starts at element 16 m (r / 16)).  Within a
+// panel, column t of row rr sits in the 32-column block t / 32 (16 x 32
+// elements, 1 KiB), at ((t % 32) / 8 * 16 + rr) * 8 + t % 8: exactly the
+// order in which a wavefront's 64 lanes take the 16-row x 32-column A operand
+// of one v_mfma_f32_16x16x32_bf16 (lane = 16 g + rr, eight elements each), so
+// one load instruction reads 1 KiB of consecutive memory.
+__host__ __device__ __forceinline__ int panel_index(int rr, int t) {
+  return (t >> 5) * 512 + (((t & 31) >> 3) * 16 + rr) * 8 + (t & 7);
+}
+
 // Summary lower bound of one (query, leaf): per segment s of length l_s,
 // l_s [gap(mu_q, [mu_lo, mu_hi])^2 + gap(sd_q, [sd_lo, sd_hi])^2], summed in
 // segment order; qs = (mu, sd) per segment, bx = (mu lo, mu hi, sd lo, sd hi).

@@ -82,11 +82,13 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ raw, con
   if (row >= rows) return;
   int64_t src = src_of_row[row];
   float *o32 = x32 + row * m;
-  uint16_t *o16 = x16 + row * m;
+  // bf16 copy in 16-row panels (see panel_index)
+  uint16_t *o16 = x16 + (row >> 4) * 16 * m;
+  const int rr = static_cast<int>(row & 15);
   if (src < 0) {
     for (int t = lane; t < m; t += kWave) {
       o32[t] = 0.0f;
-      o16[t] = 0;
+      o16[panel_index(rr, t)] = 0;
     }
     if (lane == 0) {
       xn16[row] = __builtin_inff();
@@ -102,7 +104,7 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ raw, con
     uint16_t b = f32_to_bf16(z);
     float zb = bf16_to_f32(b);
     o32[t] = z;
-    o16[t] = b;
+    o16[panel_index(rr, t)] = b;
     nrm = fmaf(zb, zb, nrm);
     float e = z - zb;
     err = fmaf(e, e, err);

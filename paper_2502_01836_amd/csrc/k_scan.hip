@@ -151,13 +151,15 @@ __device__ inline void finish_tile(uint64_t *keys, int *cnt, uint64_t *thr, int 
 }
 
 // A operand of this wave's 16 rows of the 64-row block at `base`: lane l
-// holds row base + 16 wave + (l & 15), elements 32 k + 8 (l >> 4) .. + 8.
+// holds row base + 16 wave + (l & 15), elements 32 k + 8 (l >> 4) .. + 8.  In
+// the panel layout (panel_index) that is element 512 k + 8 l of the rows'
+// panel: each of the KS loads reads 1 KiB of consecutive memory.
 template <int KS>
 __device__ __forceinline__ void load_rows(const uint16_t *x16, int64_t base, int wave, int lane, int m,
                                           bf16x8 (&a)[KS]) {
-  const uint16_t *ap = x16 + (base + 16 * wave + (lane & 15)) * m + 8 * (lane >> 4);
+  const uint16_t *ap = x16 + (base + 16 * wave) * m + 8 * lane;
 #pragma unroll
-  for (int k = 0; k < KS; ++k) a[k] = *reinterpret_cast<const bf16x8 *>(ap + 32 * k);
+  for (int k = 0; k < KS; ++k) a[k] = *reinterpret_cast<const bf16x8 *>(ap + 512 * k);
 }
 
 // One 64-row block: its squared norms, the prefetch of the next block into
