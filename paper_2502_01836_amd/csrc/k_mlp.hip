@@ -69,8 +69,13 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
     // loads: the last prefetch re-reads the current step).  Each A value (a
     // W1 element) serves both 16-query column blocks.
     const int steps = m / 16;
-    float av0[4][4], av1[4][4];
-    auto load_a = [&](float (&av)[4][4], int base) {
+    // four register buffers in rotation: the W1 operands of step s + 3 are
+    // loaded while step s computes (about four steps of products cover the
+    // load latency; the tile's single wavefront per SIMD has no other work
+    // to hide it behind)
+    float av0[4][4], av1[4][4], av2[4][4], av3[4][4];
+    auto load_a = [&](float (&av)[4][4], int sidx) {
+      const int base = 16 * (sidx < steps ? sidx : steps - 1);  // past the end: re-read the last step
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const float *wr = wk + static_cast<int64_t>(base + 4 * u) * h;
@@ -80,7 +85,8 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
         for (int t = 0; t < 4; ++t) av[u][t] = wr[col[t]];
       }
     };
-    auto step = [&](const float (&av)[4][4], int base) {
+    auto step = [&](const float (&av)[4][4], int sidx) {
+      const int base = 16 * sidx;
       float bv[4][kMlpQB];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -96,20 +102,33 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
     };
     if (steps > 0) {
       load_a(av0, 0);
+      load_a(av1, 1);
+      load_a(av2, 2);
       int sidx = 0;
-      // scheduling barriers keep the prefetch ahead of the products (the
+      // scheduling barriers keep the prefetches ahead of the products (the
       // compiler would otherwise sink the loads to where they are used)
-      for (; sidx + 2 <= steps; sidx += 2) {
-        load_a(av1, 16 * (sidx + 1));
+      for (; sidx + 4 <= steps; sidx += 4) {
+        load_a(av3, sidx + 3);
         __builtin_amdgcn_sched_barrier(0);
-        step(av0, 16 * sidx);
+        step(av0, sidx);
         __builtin_amdgcn_sched_barrier(0);
-        load_a(av0, 16 * (sidx + 2 < steps ? sidx + 2 : sidx + 1));
+        load_a(av0, sidx + 4);
         __builtin_amdgcn_sched_barrier(0);
-        step(av1, 16 * (sidx + 1));
+        step(av1, sidx + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(av1, sidx + 5);
+        __builtin_amdgcn_sched_barrier(0);
+        step(av2, sidx + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(av2, sidx + 6);
+        __builtin_amdgcn_sched_barrier(0);
+        step(av3, sidx + 3);
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (sidx < steps) step(av0, 16 * sidx);
+      // at most three steps left, already in av0, av1, av2
+      if (sidx < steps) step(av0, sidx);
+      if (sidx + 1 < steps) step(av1, sidx + 1);
+      if (sidx + 2 < steps) step(av2, sidx + 2);
       i0 = 16 * steps;
     }
     for (; i0 < m; i0 += 4) {
@@ -150,7 +169,7 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
 }
 
 // d^f for every (query, filter): grid (F, tiles), 16 queries per tile.
-__global__ void __launch_bounds__(256, 3) k_mlp_infer(const float *__restrict__ w, int F, int m, int h,
+__global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ w, int F, int m, int h,
                                                    const float *__restrict__ x, int64_t nq, float *out) {
   extern __shared__ float xs[];
   const int f = blockIdx.x;
@@ -180,7 +199,7 @@ __global__ void __launch_bounds__(1024) k_mlp_tiles(int F, const int32_t *__rest
 // plist[f * stride + 0 .. pcnt[f]) (q * N + visit position) and writes
 // d^f - o for the query's calibrated (k, target) row.  A persistent grid
 // walks the non-empty tiles of all filters.
-__global__ void __launch_bounds__(256, 3) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
+__global__ void __launch_bounds__(256, 2) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
                                                          const float *__restrict__ x,
                                                          const int64_t *__restrict__ plist,
                                                          const int32_t *__restrict__ pcnt, int64_t stride, int N,
