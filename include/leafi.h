@@ -390,7 +390,9 @@ int leafi_znorm(const float *x_dev, int64_t n, int32_t m, float *out_dev, void *
 int leafi_lower_bounds(leafi_index *index, const float *queries_dev, int64_t nq, float *lb_dev, void *stream);
 
 /* Filter predictions for already z-normalised inputs x_dev [nq, m]:
- * out_dev [nq, n_filters] = d^f (before any offset), fp32. */
+ * out_dev [nq, n_filters] = d^f (before any offset), fp32.  m is a multiple
+ * of 4 in [4, 1024], hidden a multiple of 4 in [4, 1024]; x_dev is 16-byte
+ * aligned.  Returns -1 otherwise. */
 int leafi_mlp_infer(const float *weights_dev, int32_t n_filters, int32_t m, int32_t hidden, const float *x_dev,
                     int64_t nq, float *out_dev, void *stream);
 

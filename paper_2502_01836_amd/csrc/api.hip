@@ -1470,10 +1470,11 @@ int leafi_mlp_infer(const float *w, int32_t F, int32_t m, int32_t h, const float
                     void *stream) {
   return guarded([&] {
     LEAFI_CHECK_ARG(F >= 0 && nq >= 0, "bad sizes");
-    LEAFI_CHECK_ARG(m >= 1 && m <= 4096, "m must be in [1, 4096]");
+    LEAFI_CHECK_ARG(m >= 4 && m <= 1024 && m % 4 == 0, "m must be a multiple of 4 in [4, 1024]");
     LEAFI_CHECK_ARG(h >= 4 && h <= 1024 && h % 4 == 0, "hidden must be a multiple of 4 in [4, 1024]");
     if (F == 0 || nq == 0) return;
     LEAFI_CHECK_ARG(w && x && out, "NULL pointer");
+    LEAFI_CHECK_ARG(reinterpret_cast<uintptr_t>(x) % 16 == 0, "x must be 16-byte aligned");
     LEAFI_CHECK_ARG(F <= 65535 && ceil_div(nq, 64) <= 65535, "grid too large; split the call");
     launch_mlp_infer(w, F, m, h, x, nq, out, as_stream(stream));
   });

@@ -24,8 +24,13 @@ namespace {
 // (query, filter) pair does not depend on which tile or batch holds it.
 constexpr int kMlpQ = 32;             // queries per tile
 constexpr int kMlpQB = kMlpQ / 16;    // 16-query column blocks per tile
+constexpr int kMlpXcds = 8;           // XCDs (separate L2 caches) per device
 
-size_t mlp_infer_lds(int m) { return (static_cast<size_t>(kMlpQ) * (m + 4) + 4 * kMlpQ) * sizeof(float); }
+// LDS: the query tile [kMlpQ][m + 4], the per-wavefront output sums
+// [4][kMlpQ], the tile's query rows [kMlpQ] (int64) and 4 ints for the
+// tile search.  (All carved from the dynamic block: a static __shared__
+// variable would move it off its 16-byte alignment.)
+size_t mlp_infer_lds(int m) { return (static_cast<size_t>(kMlpQ) * (m + 4) + 6 * kMlpQ + 4) * sizeof(float); }
 
 template <typename RowIdx, typename Out>
 __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h, const float *__restrict__ x,
@@ -34,15 +39,32 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int S = m + 4;
   float *red = xs + kMlpQ * S;
+  int64_t *qrow = reinterpret_cast<int64_t *>(red + 4 * kMlpQ);
   const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
   const float *W1 = w + f * P;
   const float *b1 = W1 + static_cast<int64_t>(h) * m;
   const float *w2 = b1 + h;
   const float b2 = w2[h];
-  __syncthreads();  // the previous tile's readers of xs / red are done
-  for (int e = tid; e < kMlpQ * m; e += blockDim.x) {
-    const int q = e / m, i = e - q * m;
-    xs[q * S + i] = r0 + q < nrows ? x[qidx(r0 + q) * m + i] : 0.0f;
+  __syncthreads();  // the previous tile's readers of xs / red / qrow are done
+  if (tid < kMlpQ) qrow[tid] = r0 + tid < nrows ? qidx(r0 + tid) : -1;
+  __syncthreads();
+  // wavefront w stages rows w, w + 4, ... with 16-byte loads (m is a
+  // multiple of 4 and x 16-byte aligned, so every row, in x and in the
+  // padded tile, starts 16-byte aligned); all of a lane's loads are in
+  // flight before the first store
+  constexpr int kRowsPerWave = kMlpQ / 4;
+  for (int i4 = lane; 4 * i4 < m; i4 += kWave) {
+    float4 v[kRowsPerWave];
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerWave; ++rr) {
+      const int64_t rq = qrow[wave + 4 * rr];
+      v[rr] = reinterpret_cast<const float4 *>(x + (rq < 0 ? 0 : rq) * m)[i4];
+    }
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerWave; ++rr) {
+      const bool live = qrow[wave + 4 * rr] >= 0;
+      reinterpret_cast<float4 *>(xs + (wave + 4 * rr) * S)[i4] = live ? v[rr] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
   }
   __syncthreads();
   const int c = lane & 15, kq = lane >> 4;
@@ -61,6 +83,18 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
       col[t] = jw + 16 * t + c;
       if (col[t] >= h) col[t] = 0;
     }
+    // output-layer weights of this lane's hidden units, loaded now so their
+    // latency hides under the products (a unit past h reads unit 0; its
+    // term is skipped below)
+    float w2v[4][4], b1v[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jw + 16 * t + 4 * kq + r;
+        w2v[t][r] = w2[j < h ? j : 0];
+        b1v[t][r] = b1[j < h ? j : 0];
+      }
     const float *xq = xs + c * S + kq;
     const float *wk = W1 + static_cast<int64_t>(kq) * h;
     int i0 = 0;
@@ -148,9 +182,9 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
       for (int r = 0; r < 4; ++r) {
         const int j = jw + 16 * t + 4 * kq + r;
         if (j < h) {
-          const float wj = w2[j], bj = b1[j];
 #pragma unroll
-          for (int qb = 0; qb < kMlpQB; ++qb) part[qb] = fmaf(wj, fmaxf(acc[t][qb][r] + bj, 0.0f), part[qb]);
+          for (int qb = 0; qb < kMlpQB; ++qb)
+            part[qb] = fmaf(w2v[t][r], fmaxf(acc[t][qb][r] + b1v[t][r], 0.0f), part[qb]);
         }
       }
   }
@@ -164,7 +198,7 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
   if (tid < kMlpQ) {
     const int64_t r = r0 + tid;
     if (r < nrows)
-      out(r, ((red[tid] + red[kMlpQ + tid]) + (red[2 * kMlpQ + tid] + red[3 * kMlpQ + tid])) + b2);
+      out(r, qrow[tid], ((red[tid] + red[kMlpQ + tid]) + (red[2 * kMlpQ + tid] + red[3 * kMlpQ + tid])) + b2);
   }
 }
 
@@ -174,7 +208,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ 
   extern __shared__ float xs[];
   const int f = blockIdx.x;
   for (int64_t r0 = static_cast<int64_t>(blockIdx.y) * kMlpQ; r0 < nq; r0 += static_cast<int64_t>(gridDim.y) * kMlpQ)
-    mlp_tile(w, f, m, h, x, r0, nq, [](int64_t r) { return r; }, [=](int64_t r, float v) { out[r * F + f] = v; }, xs);
+    mlp_tile(w, f, m, h, x, r0, nq, [](int64_t r) { return r; }, [=](int64_t r, int64_t, float v) { out[r * F + f] = v; }, xs);
 }
 
 // Exclusive prefix of the filters' tile counts ceil(pcnt[f] / 16) (one
@@ -207,24 +241,44 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer_pairs(const float *__restr
                                                          const float *__restrict__ offsets,
                                                          const int32_t *__restrict__ tile_prefix, float *dfo) {
   extern __shared__ float xs[];
+  int &s_lo = reinterpret_cast<int *>(xs + kMlpQ * (m + 4) + 6 * kMlpQ)[0];
+  int &s_f = reinterpret_cast<int *>(xs + kMlpQ * (m + 4) + 6 * kMlpQ)[1];
   const int total = tile_prefix[F];
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    // filter of tile t: the last f with tile_prefix[f] <= t
-    int lo = 0, hi = F - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tile_prefix[mid] <= t) lo = mid;
-      else hi = mid - 1;
+  // filters per bucket of the two-level search (at most 64 for F <= 16384)
+  const int B = (F + blockDim.x - 1) / blockDim.x;
+  // Work-groups are dispatched to the 8 XCDs round-robin (blockIdx % 8), and
+  // each XCD has its own L2.  Tiles are numbered filter by filter, so the
+  // work-groups of XCD x take the contiguous eighth [x T / 8, (x + 1) T / 8)
+  // of the T tiles: a filter's W1 is fetched into one or two L2s instead of
+  // all eight.  (Any grid not a multiple of 8 walks the tiles in plain
+  // stride; either way every tile is taken exactly once.)
+  const bool by_xcd = gridDim.x % kMlpXcds == 0;
+  const int xcd = blockIdx.x % kMlpXcds;
+  const int t_lo = by_xcd ? static_cast<int>(static_cast<int64_t>(total) * xcd / kMlpXcds) : 0;
+  const int t_hi = by_xcd ? static_cast<int>(static_cast<int64_t>(total) * (xcd + 1) / kMlpXcds) : total;
+  const int t_step = by_xcd ? gridDim.x / kMlpXcds : gridDim.x;
+  for (int t = t_lo + (by_xcd ? blockIdx.x / kMlpXcds : blockIdx.x); t < t_hi; t += t_step) {
+    // filter of tile t: the f with tile_prefix[f] <= t < tile_prefix[f + 1]
+    // (tile_prefix is non-decreasing, so exactly one f qualifies).  One
+    // thread per bucket of B filters finds the bucket, then one thread per
+    // filter of that bucket the filter: two dependent loads, not log2 F.
+    __syncthreads();  // the previous tile's readers of s_lo / s_f are done
+    {
+      const int lo = threadIdx.x * B;
+      if (lo < F && tile_prefix[lo] <= t && t < tile_prefix[min(lo + B, F)]) s_lo = lo;
     }
-    const int f = lo;
+    __syncthreads();
+    {
+      const int f = s_lo + static_cast<int>(threadIdx.x);
+      if (static_cast<int>(threadIdx.x) < B && f < F && tile_prefix[f] <= t && t < tile_prefix[f + 1]) s_f = f;
+    }
+    __syncthreads();
+    const int f = __builtin_amdgcn_readfirstlane(s_f);  // uniform: kept in scalar registers
     const int64_t r0 = static_cast<int64_t>(t - tile_prefix[f]) * kMlpQ;
     const int64_t *pl = plist + f * stride;
     mlp_tile(
         w, f, m, h, x, r0, static_cast<int64_t>(pcnt[f]), [=](int64_t r) { return pl[r] / N; },
-        [=](int64_t r, float v) {
-          const int64_t e = pl[r];
-          dfo[e] = v - offsets[static_cast<int64_t>(pair[e / N]) * F + f];
-        },
+        [=](int64_t r, int64_t q, float v) { dfo[pl[r]] = v - offsets[static_cast<int64_t>(pair[q]) * F + f]; },
         xs);
   }
 }
@@ -372,7 +426,8 @@ __global__ void __launch_bounds__(256) k_mlp_sgd_step(float *w, int F, int m, in
 }
 
 __global__ void __launch_bounds__(256) k_mlp_train(TrainArgs a) {
-  extern __shared__ float lds[];
+  // 16-byte aligned after the static variables below (float4 reads)
+  extern __shared__ __align__(16) float lds[];
   StepLds s = carve(lds, a.m);
   int32_t *perm = reinterpret_cast<int32_t *>(s.yt + kTB);
   int32_t *bq = perm + a.n_train;   // [kTB] query indices of the current batch
@@ -496,7 +551,9 @@ void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x,
     HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   }
   const int64_t tiles_bound = static_cast<int64_t>(F) * ceil_div(stride, kMlpQ);
-  const int grid = static_cast<int>(std::min<int64_t>(tiles_bound, static_cast<int64_t>(cus) * 4));
+  // (a multiple of 8 for the per-XCD tile ranges; spare work-groups exit)
+  const int grid = static_cast<int>(
+      ceil_div(std::min<int64_t>(tiles_bound, static_cast<int64_t>(cus) * 4), kMlpXcds) * kMlpXcds);
   const size_t lds = mlp_infer_lds(m);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer_pairs),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));

@@ -54,13 +54,37 @@ __device__ inline int64_t xcd_tile(int64_t j, int x) {
   return ((j / kXcdRun) * kXcds + x) * kXcdRun + j % kXcdRun;
 }
 
-__device__ inline TileInfo decode_tile(int t, const StoreView &s, const RoundBufs &b, int mq) {
-  // leaf L with tile_start[L] <= t < tile_start[L + 1]
-  int lo = 0, hi = s.N;  // invariant: tile_start[lo] <= t < tile_start[hi]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (b.tile_start[mid] <= t) lo = mid; else hi = mid;
-  }
+// Work-group barrier for LDS traffic only: waits for this wave's LDS
+// operations, then s_barrier.  Unlike __syncthreads it does not drain
+// outstanding global loads, so prefetched rows stay in flight across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Leaf of tile t, found by the whole work-group: the L with
+// tile_start[L] <= t < tile_start[L + 1] (tile_start is non-decreasing and
+// tile_start[N] is the tile count, so exactly one L qualifies, and exactly
+// one bucket of B consecutive leaves holds it).  One thread per bucket
+// finds the bucket, then one thread per leaf of the bucket the leaf: two
+// dependent loads where a binary search takes log2 N.  Every thread must
+// call it; sh holds two ints of LDS, free when it is called.  (Kernels
+// carve sh from their dynamic LDS: a static __shared__ variable would move
+// the dynamic block off its 16-byte alignment.)
+__device__ inline int tile_leaf(int t, const int32_t *__restrict__ tile_start, int N, int *sh) {
+  const int B = (N + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * B;
+  if (lo < N && tile_start[lo] <= t && t < tile_start[lo + B < N ? lo + B : N]) sh[0] = lo;
+  lds_barrier();
+  // the value is uniform: readfirstlane keeps it (and all that derives from
+  // it) in scalar registers
+  const int L0 = __builtin_amdgcn_readfirstlane(sh[0]);
+  if (B == 1) return L0;
+  const int L = L0 + static_cast<int>(threadIdx.x);
+  if (static_cast<int>(threadIdx.x) < B && L < N && tile_start[L] <= t && t < tile_start[L + 1]) sh[1] = L;
+  lds_barrier();
+  return __builtin_amdgcn_readfirstlane(sh[1]);
+}
+
+__device__ inline TileInfo decode_tile(int t, const StoreView &s, const RoundBufs &b, int mq, int *sh) {
+  const int lo = tile_leaf(t, b.tile_start, s.N, sh);
   TileInfo ti;
   ti.L = lo;
   int64_t off0 = s.leaf_off[lo], off1 = s.leaf_off[lo + 1];
@@ -77,11 +101,6 @@ __device__ inline TileInfo decode_tile(int t, const StoreView &s, const RoundBuf
   ti.nqt = left < mq ? left : mq;
   return ti;
 }
-
-// Work-group barrier for LDS traffic only: waits for this wave's LDS
-// operations, then s_barrier.  Unlike __syncthreads it does not drain
-// outstanding global loads, so prefetched rows stay in flight across it.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Error bound of the BF16 scan's squared distance for a query with bf16
 // norm^2 qn (rows have norm^2 <= 1.02 m): the computed value is within
@@ -110,10 +129,40 @@ __device__ __forceinline__ float tau_threshold(float tau, double qn, float qeps,
 // spare entry per list staggers the lists across LDS banks (appends of
 // different queries at equal slots would otherwise hit one bank).
 
-// Sort list j and keep its kprime best; refresh the threshold.
+// Up to this many kept keys, a list is cut by selection instead of a sort.
+constexpr int kListSelectMax = 16;
+
+// Keep the kprime best keys of list j, in ascending order at its head, and
+// refresh the threshold.  Few wanted (kprime <= kListSelectMax): kprime
+// rounds of a wavefront minimum over the keys above the previous round's
+// (the keys of one list are distinct: one per row); otherwise a bitonic sort.
 __device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int j, int cap, int kprime, int lane) {
   uint64_t *lst = keys + static_cast<int64_t>(j) * (cap + 1);
   int c = cnt[j];
+  if (kprime <= kListSelectMax) {
+    uint64_t prev = 0, mine = kKeyMax;  // lane r keeps the r-th smallest
+    int keep = 0;
+    for (int r = 0; r < kprime; ++r) {
+      uint64_t lo = kKeyMax;
+      for (int e = lane; e < c; e += kWave) {
+        const uint64_t v = lst[e];
+        if ((r == 0 || v > prev) && v < lo) lo = v;
+      }
+      lo = wave_min(lo);
+      if (lo == kKeyMax) break;  // fewer than kprime keys (uniform)
+      if (lane == r) mine = lo;
+      prev = lo;
+      ++keep;
+    }
+    wave_lds_sync();  // every lane has read the list before its head is rewritten
+    if (lane < keep) lst[lane] = mine;
+    if (lane == 0) {
+      cnt[j] = keep;
+      if (keep == kprime) thr[j] = prev;  // else the list is not full: keep the threshold
+    }
+    wave_lds_sync();
+    return;
+  }
   int P = pow2_at_least(c < 2 ? 2 : c);
   for (int i = c + lane; i < P; i += kWave) lst[i] = kKeyMax;
   wave_lds_sync();
@@ -194,16 +243,24 @@ __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &t
   for (int qb = 0; qb < QB; ++qb) {
     const int j = 16 * qb + (lane & 15);
     if (j < ti.nqt) {
+      // the lane's (up to 4) appends take one LDS atomic: one round trip per
+      // block instead of one per row
       const uint64_t tj = thr[j];
+      uint64_t kk[4];
+      int n = 0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = rowc + r;
         const float d2 = fmaxf(qn[qb] + xr[r] - 2.0f * acc[qb][r], 0.0f);
-        const uint64_t key = make_key(d2, static_cast<uint32_t>(row));
-        if (row < ti.real_end && key < tj) {
-          const int slot = atomicAdd(cnt + j, 1);
-          keys[static_cast<int64_t>(j) * (cap + 1) + slot] = key;
-        }
+        kk[r] = make_key(d2, static_cast<uint32_t>(row));
+        if (!(row < ti.real_end && kk[r] < tj)) kk[r] = kKeyMax;
+        n += kk[r] != kKeyMax;
+      }
+      if (n > 0) {
+        uint64_t *dst = keys + static_cast<int64_t>(j) * (cap + 1) + atomicAdd(cnt + j, n);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (kk[r] != kKeyMax) *dst++ = kk[r];
       }
     }
   }
@@ -223,6 +280,7 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
   uint64_t *thr = keys + MQ * (cap + 1);
   int *cnt = reinterpret_cast<int *>(thr + MQ);
   uint16_t *qs = reinterpret_cast<uint16_t *>(cnt + MQ);  // [MQ][m + 8], 16-byte aligned
+  int *s_leaf = reinterpret_cast<int *>(qs + MQ * (s.m + 8));  // [2], after the tile's queries
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int m = s.m;
@@ -236,7 +294,11 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
     if (by_xcd ? (j / kXcdRun) * kXcds * kXcdRun >= n_tiles : tt >= n_tiles) break;
     if (tt >= n_tiles) continue;
     const int t = static_cast<int>(tt);
-    TileInfo ti = decode_tile(t, s, b, MQ);
+    TileInfo ti = decode_tile(t, s, b, MQ, s_leaf);
+    // The tile's first rows are requested before its queries are staged, so
+    // the two sets of loads are in flight together.
+    bf16x8 a0[KS], a1[KS];
+    load_rows<KS>(s.x16, ti.r0, wave, lane, m, a0);
     if (threadIdx.x < MQ) {
       const int j = threadIdx.x;
       cnt[j] = 0;
@@ -264,7 +326,7 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
       const int j = 16 * qb + (lane & 15);
       qn[qb] = j < ti.nqt ? qv.qn16[b.item_q[ti.p0 + j]] : 0.0f;
     }
-    __syncthreads();
+    lds_barrier();
     // The A operand of the wave's 16 rows in the next 64-row block is loaded
     // while the current block is processed (ping-pong registers, no copies),
     // so one block of global loads is always in flight; the barriers wait on
@@ -272,8 +334,6 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
     // hardware's load counter retires in order.
     // Chunks hold an even number of 64-row blocks (leaves are padded to 128
     // rows), so both halves of the unrolled body always run.
-    bf16x8 a0[KS], a1[KS];
-    load_rows<KS>(s.x16, ti.r0, wave, lane, m, a0);
     for (int64_t base = ti.r0; base < ti.r1; base += 128) {
       scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kprime, wave, lane);
       scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qs, qstride, qn, keys, cnt, thr, cap, kprime,
@@ -293,6 +353,7 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
   uint64_t *thr = keys + mq * (cap + 1);
   int *cnt = reinterpret_cast<int *>(thr + mq);
   float *qs = reinterpret_cast<float *>(cnt + mq);
+  int *s_leaf = reinterpret_cast<int *>(qs + mq * s.m);  // [2], after the tile's queries
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int sub = lane & 15, rsel = lane >> 4;
@@ -307,7 +368,7 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
     if (by_xcd ? (j / kXcdRun) * kXcds * kXcdRun >= n_tiles : tt >= n_tiles) break;
     if (tt >= n_tiles) continue;
     const int t = static_cast<int>(tt);
-    TileInfo ti = decode_tile(t, s, b, mq);
+    TileInfo ti = decode_tile(t, s, b, mq, s_leaf);
     if (threadIdx.x < mq) {
       cnt[threadIdx.x] = 0;
       thr[threadIdx.x] = kKeyMax;
@@ -567,7 +628,8 @@ template <int KS, int QB>
 void scan_bf16_inst(StoreView s, QueryView q, RoundBufs b, int kprime, int cap, uint64_t *cand, int grid,
                     hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int MQ = 16 * QB;
-  size_t lds = static_cast<size_t>(MQ) * (cap + 1) * 8 + MQ * 8 + MQ * 4 + static_cast<size_t>(MQ) * (32 * KS + 8) * 2;
+  size_t lds =
+      static_cast<size_t>(MQ) * (cap + 1) * 8 + MQ * 8 + MQ * 4 + static_cast<size_t>(MQ) * (32 * KS + 8) * 2 + 16;
   auto kern = k_scan_bf16<KS, QB>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -598,7 +660,7 @@ void scan_bf16_ks(int ks, StoreView s, QueryView q, RoundBufs b, int kprime, int
 template <int EPL>
 void scan_fp32_inst(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int cap, uint64_t *cand, int grid,
                     hipStream_t st) {
-  size_t lds = static_cast<size_t>(mq) * (cap + 1) * 8 + mq * 8 + mq * 4 + static_cast<size_t>(mq) * s.m * 4;
+  size_t lds = static_cast<size_t>(mq) * (cap + 1) * 8 + mq * 8 + mq * 4 + static_cast<size_t>(mq) * s.m * 4 + 16;
   auto kern = k_scan_fp32<EPL>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));

@@ -68,6 +68,8 @@ def test_null_handles_are_rejected_without_touching_the_gpu(lib):
     # sizes are validated before any device work
     assert lib.leafi_znorm(None, -1, 8, None, None) == -1
     assert lib.leafi_mlp_infer(None, 1, 8, 3, None, 1, None, None) == -1   # hidden not a multiple of 4
+    assert lib.leafi_mlp_infer(None, 1, 6, 8, None, 1, None, None) == -1   # m not a multiple of 4
+    assert lib.leafi_mlp_infer(None, 1, 2048, 8, None, 1, None, None) == -1  # m above 1024
     assert lib.leafi_mlp_sgd_step(None, 1, 8, 4, None, None, 65, 0.1, None, None) == -1  # batch > 64
     lib.leafi_destroy(None)
 
