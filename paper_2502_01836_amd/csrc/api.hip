@@ -296,7 +296,12 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   RoundBufs b0 = views(w);
   b0.chunk = chunk;
   b0.use_tau = ro->use_tau ? 1 : 0;
-  launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b0, st);
+  // a pass with few items (rescans, a first round of one leaf per query)
+  // and preallocated buffers lays out and places its items in one
+  // single-work-group launch (below, once the buffers are final)
+  constexpr int64_t kFusedItems = 8192;
+  const bool fused = !ro->may_read && (ro->small || (items_bound >= 0 && items_bound <= kFusedItems));
+  if (!fused) launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b0, st);
   int64_t items = -1, tiles;
   const int64_t tb = items_bound >= 0 ? tiles_bound(ix, nq, items_bound, mq, chunk) : -1;
   const double bytes = items_bound >= 0 ? static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
@@ -320,7 +325,8 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   b.use_tau = ro->use_tau ? 1 : 0;
   StoreView s = store_view(ix);
   QueryView q = query_view(w);
-  launch_scatter(nq, ix->N, b, st);
+  if (fused) launch_leaf_scan_scatter(nq, ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b, st);
+  else launch_scatter(nq, ix->N, b, st);
   int grid_scan = static_cast<int>(std::min<int64_t>(std::max<int64_t>(tiles, 1),
                                                      static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : kScanBlocksPerCU)));
   hipEvent_t e0 = ro->ev_begin ? ro->ev_begin : (tm ? w.ev0 : nullptr);

@@ -164,10 +164,10 @@ __global__ void __launch_bounds__(256) k_round_reset(RoundBufs b, int n_ctl, int
   if (i < nq) b.qitem_cnt[i] = 0;
 }
 
-// Exclusive scans over leaves: item starts and tile starts (one work-group).
-__global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__restrict__ leaf_off, int mq,
-                                                    int64_t row_bytes, RoundBufs b) {
-  __shared__ int64_t sh[16];
+// Exclusive scans over leaves: item starts and tile starts (the whole
+// work-group of 1024 threads).
+__device__ inline void leaf_scan_body(int N, const int64_t *__restrict__ leaf_off, int mq, int64_t row_bytes,
+                                      RoundBufs &b, int64_t *sh) {
   const int tid = threadIdx.x;
   const int per = (N + 1023) / 1024;
   const int l0 = min(N, tid * per), l1 = min(N, l0 + per);
@@ -200,6 +200,33 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
     if (row_bytes > 0 && tot_i > 0) {
       b.ctl[kCtlScanBytes] += tot_r * row_bytes;
       b.ctl[kCtlRounds] += 1;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__restrict__ leaf_off, int mq,
+                                                    int64_t row_bytes, RoundBufs b) {
+  __shared__ int64_t sh[16];
+  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh);
+}
+
+// A small pass (the exact rescan of a round's few uncertified items) in one
+// launch instead of two: the leaf scan, then every query's items placed by
+// one thread each (the placement is k_scatter's).
+__global__ void __launch_bounds__(1024) k_leaf_scan_scatter(int64_t nq, int N, const int64_t *__restrict__ leaf_off,
+                                                            int mq, int64_t row_bytes, RoundBufs b) {
+  __shared__ int64_t sh[16];
+  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh);
+  __syncthreads();  // item starts written; the per-leaf counts are consumed
+  for (int i = threadIdx.x; i < N; i += blockDim.x) b.leaf_cnt[i] = 0;
+  for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
+    const int n = b.qitem_cnt[q];
+    for (int r = 0; r < n; ++r) {
+      const int L = b.qitem_leaf[q * N + r];
+      const int slot = b.leaf_istart[L] + atomicAdd(b.leaf_fill + L, 1);
+      b.item_q[slot] = static_cast<int32_t>(q);
+      b.item_leaf[slot] = L;
+      b.qitem_idx[q * N + r] = slot;
     }
   }
 }
@@ -486,6 +513,12 @@ void launch_round_reset(RoundBufs b, int n_ctl, int N, int64_t nq, hipStream_t s
 void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b, hipStream_t st) {
   hipLaunchKernelGGL(k_leaf_scan, dim3(1), dim3(1024), 0, st, N, leaf_off, mq, row_bytes, b);
   LAUNCH_OK("leaf_scan");
+}
+
+void launch_leaf_scan_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_leaf_scan_scatter, dim3(1), dim3(1024), 0, st, nq, N, leaf_off, mq, row_bytes, b);
+  LAUNCH_OK("leaf_scan_scatter");
 }
 
 void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {

@@ -180,6 +180,11 @@ void launch_round_reset(RoundBufs b, int n_ctl, int N, int64_t nq, hipStream_t s
 // Place each query's emitted leaves into item slots.
 void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st);
 
+// launch_leaf_scan then launch_scatter in one single-work-group launch, for
+// passes with few items (its placement loop is serial per query).
+void launch_leaf_scan_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b,
+                              hipStream_t st);
+
 // Leaf scan over all tiles; keeps the kprime best (key = dist^2 bits, row)
 // per (tile, query slot) in cand.
 void launch_scan_bf16(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
