@@ -57,6 +57,39 @@ __device__ __forceinline__ T wave_min(T v) {
   return v;
 }
 
+// DPP move of a 64-bit value (two 32-bit halves); lanes whose source is out
+// of their row or whose row is masked off keep their own value.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(v), static_cast<int>(v), Ctrl, RowMask, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(v >> 32), static_cast<int>(v >> 32), Ctrl, RowMask, 0xf,
+                                             false);
+  return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
+// Minimum of a 64-bit key over the wavefront, returned to every lane, on
+// DPP lane moves (no LDS round trips, unlike shuffles): row_shr 1, 2, 4, 8
+// leave each 16-lane row's minimum in its lane 15, row_bcast 15 and 31 carry
+// it across the rows to lane 63, which is read back.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  uint64_t t;
+  t = dpp_u64<0x111, 0xf>(v);  // row_shr:1
+  v = t < v ? t : v;
+  t = dpp_u64<0x112, 0xf>(v);  // row_shr:2
+  v = t < v ? t : v;
+  t = dpp_u64<0x114, 0xf>(v);  // row_shr:4
+  v = t < v ? t : v;
+  t = dpp_u64<0x118, 0xf>(v);  // row_shr:8
+  v = t < v ? t : v;
+  t = dpp_u64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = t < v ? t : v;
+  t = dpp_u64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  v = t < v ? t : v;
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(v), 63);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), 63);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 // Exclusive prefix sum over a work-group of NT threads (NT / 64 <= 64
 // wavefronts): wavefront scans by shuffles, then one scan of the wavefront
 // totals.  `sh` holds NT / 64 values of LDS; `total` receives the sum.  Every

@@ -148,7 +148,7 @@ __device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int
         const uint64_t v = lst[e];
         if ((r == 0 || v > prev) && v < lo) lo = v;
       }
-      lo = wave_min(lo);
+      lo = wave_min_u64(lo);
       if (lo == kKeyMax) break;  // fewer than kprime keys (uniform)
       if (lane == r) mine = lo;
       prev = lo;
@@ -425,7 +425,7 @@ constexpr int kSelectPerLane = 16;
 
 // One wavefront per item.  LDS: merged keys [P], then per candidate the fp32
 // key, FP64 distance and row.
-__global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
+__global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
                                                      int kmax, int bf16, int PB, int slice_u64,
                                                      const uint64_t *__restrict__ cand) {
   extern __shared__ uint64_t smem[];
@@ -443,27 +443,32 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
   const double u = 1.0 / 16777216.0;  // 2^-24
   const float delta32 = static_cast<float>(2.0 * (m + 4) * u);
   for (int item = blockIdx.x * wpb + wave; item < n_items; item += gridDim.x * wpb) {
-    int L = b.item_leaf[item];
-    int64_t q = b.item_q[item];
-    int k = b.kq[q];
-    int pos = item - b.leaf_istart[L];
-    int g = pos / mq, j = pos - (pos / mq) * mq;
-    int C = static_cast<int>((s.leaf_off[L + 1] - s.leaf_off[L] + b.chunk - 1) / b.chunk);
-    const int G = (b.leaf_istart[L + 1] - b.leaf_istart[L] + mq - 1) / mq;
+    const int L = b.item_leaf[item];
+    const int64_t q = b.item_q[item];
+    // everything else the item needs from memory, requested together
+    const int k = b.kq[q];
+    const int ist0 = b.leaf_istart[L], ist1 = b.leaf_istart[L + 1];
+    const int64_t off0 = s.leaf_off[L], off1 = s.leaf_off[L + 1];
+    const float tau_q = b.tau[q], qn_q = qv.qn16[q], qe_q = qv.qeps[q], le_L = s.leaf_eps[L];
+    const int pos = item - ist0;
+    const int g = pos / mq, j = pos - (pos / mq) * mq;
+    const int C = static_cast<int>((off1 - off0 + b.chunk - 1) / b.chunk);
+    const int G = (ist1 - ist0 + mq - 1) / mq;
     int n = C * kprime;
     if (kprime <= kSelectMax && n <= kWave * kSelectPerLane) {
       // few keys wanted from many: kprime rounds of a wavefront minimum over
       // the keys above the previous one (keys are unique), held in registers
+      // (unconditional loads of clamped entries, so all of a lane's loads
+      // are in flight together; n >= kprime >= 1, so entry 0 exists)
       uint64_t mine[kSelectPerLane];
+      const int64_t t0 = b.tile_start[L];
 #pragma unroll
       for (int u = 0; u < kSelectPerLane; ++u) {
         const int e = lane + u * kWave;
-        uint64_t v = kKeyMax;
-        if (e < n) {
-          const int c = e / kprime;
-          v = cand[(tile_of(b.tile_start, L, g, c, G) * mq + j) * kprime + (e - c * kprime)];
-        }
-        mine[u] = v;
+        const int ec = e < n ? e : 0;
+        const int c = ec / kprime;
+        const uint64_t v = cand[((t0 + static_cast<int64_t>(c) * G + g) * mq + j) * kprime + (ec - c * kprime)];
+        mine[u] = e < n ? v : kKeyMax;
       }
       uint64_t prev = 0;
       bool first = true;
@@ -472,7 +477,7 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
 #pragma unroll
         for (int u = 0; u < kSelectPerLane; ++u)
           if ((first || mine[u] > prev) && mine[u] < lo) lo = mine[u];
-        lo = wave_min(lo);
+        lo = wave_min_u64(lo);
         if (lane == 0) buf[r] = lo;
         prev = lo;
         first = false;
@@ -504,60 +509,130 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
     const float *qp = qv.q32 + q * m;
     const int CB = PK < 8 ? PK : 8, GL = kWave / CB;
     const int sub = lane & (GL - 1), cb = lane / GL;
-    for (int e0 = 0; e0 < PK; e0 += CB) {
-      const int e = e0 + cb;
-      float p = 0.0f;
+    // FP64 for every candidate within the FP32 error band of the k-th
+    float band = __builtin_inff();
+    int nb = 0;
+    if (PK <= 8 && m <= 16 * GL) {
+      // Few candidates (CB == PK): each lane group holds its candidate's row
+      // and the query's matching elements in registers for both passes, so
+      // the rows are read once.  Same sums in the same order as below.
+      constexpr int kHold = 4;
+      const int e = cb;
       uint32_t row = 0;
+      float4 qa[kHold], xa[kHold];
+      float p = 0.0f;
       if (e < nc) {
         row = key_row(buf[e]);
         const float *xp = s.x32 + static_cast<int64_t>(row) * m;
-        for (int t = 4 * sub; t < m; t += 4 * GL) {
-          const float4 a = *reinterpret_cast<const float4 *>(qp + t);
-          const float4 x = *reinterpret_cast<const float4 *>(xp + t);
-          float d = a.x - x.x;
-          p = fmaf(d, d, p);
-          d = a.y - x.y;
-          p = fmaf(d, d, p);
-          d = a.z - x.z;
-          p = fmaf(d, d, p);
-          d = a.w - x.w;
-          p = fmaf(d, d, p);
+#pragma unroll
+        for (int i = 0; i < kHold; ++i) {
+          const int t = 4 * sub + i * 4 * GL;
+          if (t < m) {
+            qa[i] = *reinterpret_cast<const float4 *>(qp + t);
+            xa[i] = *reinterpret_cast<const float4 *>(xp + t);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kHold; ++i) {
+          if (4 * sub + i * 4 * GL < m) {
+            float d = qa[i].x - xa[i].x;
+            p = fmaf(d, d, p);
+            d = qa[i].y - xa[i].y;
+            p = fmaf(d, d, p);
+            d = qa[i].z - xa[i].z;
+            p = fmaf(d, d, p);
+            d = qa[i].w - xa[i].w;
+            p = fmaf(d, d, p);
+          }
         }
       }
       for (int o = GL >> 1; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
       if (sub == 0) k32[e] = e < nc ? make_key(p, row) : kKeyMax;
-    }
-    wave_lds_sync();
-    wave_sort_u64(k32, PK, lane);
-    // FP64 for every candidate within the FP32 error band of the k-th
-    float band = __builtin_inff();
-    if (nc >= k) band = key_d2(k32[k - 1]) * (1.0f + 2.0f * delta32);
-    int nb = 0;
-    for (int e = 0; e < nc; ++e) nb += key_d2(k32[e]) <= band ? 1 : 0;
-    for (int e0 = 0; e0 < PK; e0 += CB) {
-      const int e = e0 + cb;
-      double p = 0.0;
-      uint32_t row = 0xffffffffu;
-      if (e < nb) {
-        row = key_row(k32[e]);
-        const float *xp = s.x32 + static_cast<int64_t>(row) * m;
-        for (int t = 4 * sub; t < m; t += 4 * GL) {
-          const float4 a = *reinterpret_cast<const float4 *>(qp + t);
-          const float4 x = *reinterpret_cast<const float4 *>(xp + t);
-          double d = static_cast<double>(a.x) - static_cast<double>(x.x);
-          p = fma(d, d, p);
-          d = static_cast<double>(a.y) - static_cast<double>(x.y);
-          p = fma(d, d, p);
-          d = static_cast<double>(a.z) - static_cast<double>(x.z);
-          p = fma(d, d, p);
-          d = static_cast<double>(a.w) - static_cast<double>(x.w);
-          p = fma(d, d, p);
+      wave_lds_sync();
+      wave_sort_u64(k32, PK, lane);
+      if (nc >= k) band = key_d2(k32[k - 1]) * (1.0f + 2.0f * delta32);
+      for (int i = 0; i < nc; ++i) nb += key_d2(k32[i]) <= band ? 1 : 0;
+      // the band's members are exactly the candidates whose FP32 value is
+      // within it (every lane of a group holds its candidate's value)
+      const bool inb = e < nc && p <= band;
+      double pd = 0.0;
+      if (inb) {
+#pragma unroll
+        for (int i = 0; i < kHold; ++i) {
+          if (4 * sub + i * 4 * GL < m) {
+            double d = static_cast<double>(qa[i].x) - static_cast<double>(xa[i].x);
+            pd = fma(d, d, pd);
+            d = static_cast<double>(qa[i].y) - static_cast<double>(xa[i].y);
+            pd = fma(d, d, pd);
+            d = static_cast<double>(qa[i].z) - static_cast<double>(xa[i].z);
+            pd = fma(d, d, pd);
+            d = static_cast<double>(qa[i].w) - static_cast<double>(xa[i].w);
+            pd = fma(d, d, pd);
+          }
         }
       }
-      for (int o = GL >> 1; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
+      for (int o = GL >> 1; o > 0; o >>= 1) pd += __shfl_xor(pd, o, kWave);
       if (sub == 0) {
-        d64[e] = e < nb ? p : __builtin_inf();
-        r64[e] = row;
+        d64[e] = inb ? pd : __builtin_inf();
+        r64[e] = inb ? row : 0xffffffffu;
+      }
+    } else {
+      for (int e0 = 0; e0 < PK; e0 += CB) {
+        const int e = e0 + cb;
+        float p = 0.0f;
+        uint32_t row = 0;
+        if (e < nc) {
+          row = key_row(buf[e]);
+          const float *xp = s.x32 + static_cast<int64_t>(row) * m;
+          // unrolled so a lane's loads of the row are in flight together (at
+          // most 8 per lane for m <= 256: GL >= 8)
+#pragma unroll 8
+          for (int t = 4 * sub; t < m; t += 4 * GL) {
+            const float4 a = *reinterpret_cast<const float4 *>(qp + t);
+            const float4 x = *reinterpret_cast<const float4 *>(xp + t);
+            float d = a.x - x.x;
+            p = fmaf(d, d, p);
+            d = a.y - x.y;
+            p = fmaf(d, d, p);
+            d = a.z - x.z;
+            p = fmaf(d, d, p);
+            d = a.w - x.w;
+            p = fmaf(d, d, p);
+          }
+        }
+        for (int o = GL >> 1; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
+        if (sub == 0) k32[e] = e < nc ? make_key(p, row) : kKeyMax;
+      }
+      wave_lds_sync();
+      wave_sort_u64(k32, PK, lane);
+      if (nc >= k) band = key_d2(k32[k - 1]) * (1.0f + 2.0f * delta32);
+      for (int e = 0; e < nc; ++e) nb += key_d2(k32[e]) <= band ? 1 : 0;
+      for (int e0 = 0; e0 < PK; e0 += CB) {
+        const int e = e0 + cb;
+        double p = 0.0;
+        uint32_t row = 0xffffffffu;
+        if (e < nb) {
+          row = key_row(k32[e]);
+          const float *xp = s.x32 + static_cast<int64_t>(row) * m;
+#pragma unroll 8
+          for (int t = 4 * sub; t < m; t += 4 * GL) {
+            const float4 a = *reinterpret_cast<const float4 *>(qp + t);
+            const float4 x = *reinterpret_cast<const float4 *>(xp + t);
+            double d = static_cast<double>(a.x) - static_cast<double>(x.x);
+            p = fma(d, d, p);
+            d = static_cast<double>(a.y) - static_cast<double>(x.y);
+            p = fma(d, d, p);
+            d = static_cast<double>(a.z) - static_cast<double>(x.z);
+            p = fma(d, d, p);
+            d = static_cast<double>(a.w) - static_cast<double>(x.w);
+            p = fma(d, d, p);
+          }
+        }
+        for (int o = GL >> 1; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
+        if (sub == 0) {
+          d64[e] = e < nb ? p : __builtin_inf();
+          r64[e] = row;
+        }
       }
     }
     wave_lds_sync();
@@ -577,11 +652,11 @@ __global__ void __launch_bounds__(256) k_item_rerank(StoreView s, QueryView qv, 
     if (lane == 0) {
       float bound = __builtin_inff();
       float kd = kth != kKeyMax ? key_d2(kth) : __builtin_inff();
-      if (bf16 && b.use_tau) kd = fminf(kd, tau_threshold(b.tau[q], qv.qn16[q], qv.qeps[q], s.leaf_eps[L], m));
+      if (bf16 && b.use_tau) kd = fminf(kd, tau_threshold(tau_q, qn_q, qe_q, le_L, m));
       if (kd < __builtin_inff()) {
         if (bf16) {
-          double v = static_cast<double>(kd) - bf16_delta(qv.qn16[q], m);
-          bound = static_cast<float>((v > 0.0 ? sqrt(v) : 0.0) - qv.qeps[q] - s.leaf_eps[L]);
+          double v = static_cast<double>(kd) - bf16_delta(qn_q, m);
+          bound = static_cast<float>((v > 0.0 ? sqrt(v) : 0.0) - qe_q - le_L);
         } else {
           bound = static_cast<float>(sqrt(static_cast<double>(kd) * (1.0 - delta32)));
         }
