@@ -211,53 +211,13 @@ __device__ __forceinline__ void load_rows(const uint16_t *x16, int64_t base, int
   for (int k = 0; k < KS; ++k) a[k] = *reinterpret_cast<const bf16x8 *>(ap + 512 * k);
 }
 
-__device__ __forceinline__ void cmpx(uint64_t &a, uint64_t &b) {
-  const uint64_t lo = a < b ? a : b;
-  b = a < b ? b : a;
-  a = lo;
-}
-
-// The 4 smallest of the 16 keys that lanes l, l ^ 16, l ^ 32 and l ^ 48 hold
-// (4 each), ascending, in each of those lanes: a sort of each lane's 4, then
-// two merges with the partner lane (the element-wise minimum of one sorted
-// list and the other reversed holds the 4 smallest of both as a bitonic
-// sequence, which two compare-exchange stages sort).
-__device__ inline void column_top4(uint64_t (&v)[4]) {
-  cmpx(v[0], v[1]);
-  cmpx(v[2], v[3]);
-  cmpx(v[0], v[2]);
-  cmpx(v[1], v[3]);
-  cmpx(v[1], v[2]);
-#pragma unroll
-  for (int o = 16; o <= 32; o <<= 1) {
-    uint64_t w[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      w[i] = static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(v[i]), o, kWave));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = w[3 - i] < v[i] ? w[3 - i] : v[i];
-    cmpx(v[0], v[2]);
-    cmpx(v[1], v[3]);
-    cmpx(v[0], v[1]);
-    cmpx(v[2], v[3]);
-  }
-}
-
-// Most candidates kept per list for which a tile's first block can set the
-// thresholds directly (the k'-th smallest key of its 64 rows).
-constexpr int kSeedMax = 4;
-
 // One 64-row block: its squared norms, the prefetch of the next block into
-// `nxt`, MFMAs on `cur`, candidate appends, then list maintenance.  With
-// `seed` (a tile's first block, some list still without a threshold, k' <=
-// kSeedMax), the block's own k'-th smallest key per query first becomes that
-// query's threshold (any k keys of the tile bound its k-th best from above),
-// so the list starts with k' entries instead of 64 and is rarely compacted.
+// `nxt`, MFMAs on `cur`, candidate appends, then list maintenance.
 template <int KS, int QB>
 __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &ti, int64_t base, bf16x8 (&cur)[KS],
                                            bf16x8 (&nxt)[KS], bool more, const uint16_t *qs, int qstride,
                                            const float (&qn)[QB], uint64_t *keys, int *cnt, uint64_t *thr, int cap,
-                                           int kprime, int wave, int lane, bool seed) {
+                                           int kprime, int wave, int lane) {
   constexpr int kWaves = 4;
   const int64_t rowc = base + 16 * wave + 4 * (lane >> 4);
   const float4 xn = *reinterpret_cast<const float4 *>(s.xn16 + rowc);
@@ -279,40 +239,6 @@ __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &t
     }
   // epilogue: lane holds rows rowc..rowc+3 for query column (lane & 15)
   const float xr[4] = {xn.x, xn.y, xn.z, xn.w};
-  if (seed) {
-    // per query, each wavefront's 4 smallest keys of its 16 rows go to the
-    // (still empty) list's first slots, then one thread per query takes the
-    // k'-th smallest of the 64 as its threshold
-#pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-      uint64_t v[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = rowc + r;
-        const float d2 = fmaxf(qn[qb] + xr[r] - 2.0f * acc[qb][r], 0.0f);
-        v[r] = row < ti.real_end ? make_key(d2, static_cast<uint32_t>(row)) : kKeyMax;
-      }
-      column_top4(v);
-      const int j = 16 * qb + (lane & 15);
-      if (lane < 16 && j < ti.nqt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) keys[static_cast<int64_t>(j) * (cap + 1) + 4 * wave + i] = v[i];
-    }
-    lds_barrier();
-    if (static_cast<int>(threadIdx.x) < ti.nqt) {
-      const int j = threadIdx.x;
-      const uint64_t *p = keys + static_cast<int64_t>(j) * (cap + 1);
-      uint64_t t4[kSeedMax] = {kKeyMax, kKeyMax, kKeyMax, kKeyMax};  // ascending
-      for (int e = 0; e < 4 * kWaves; ++e) {
-        uint64_t x = p[e];
-#pragma unroll
-        for (int i = 0; i < kSeedMax; ++i) cmpx(t4[i], x);
-      }
-      const uint64_t kth = t4[kprime - 1];
-      if (kth != kKeyMax && kth + 1 < thr[j]) thr[j] = kth + 1;
-    }
-    lds_barrier();
-  }
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const int j = 16 * qb + (lane & 15);
@@ -361,7 +287,7 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
   uint64_t *thr = keys + MQ * (cap + 1);
   int *cnt = reinterpret_cast<int *>(thr + MQ);
   uint16_t *qs = reinterpret_cast<uint16_t *>(cnt + MQ);  // [MQ][m + 8], 16-byte aligned
-  int *s_leaf = reinterpret_cast<int *>(qs + MQ * (s.m + 8));  // [3], after the tile's queries
+  int *s_leaf = reinterpret_cast<int *>(qs + MQ * (s.m + 8));  // [2], after the tile's queries
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int m = s.m;
@@ -375,7 +301,6 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
     if (by_xcd ? (j / kXcdRun) * kXcds * kXcdRun >= n_tiles : tt >= n_tiles) break;
     if (tt >= n_tiles) continue;
     const int t = static_cast<int>(tt);
-    if (threadIdx.x == 0) s_leaf[2] = 0;  // some list of the tile starts without a threshold
     TileInfo ti = decode_tile(t, s, b, MQ, s_leaf);
     // The tile's first rows are requested before its queries are staged, so
     // the two sets of loads are in flight together.
@@ -391,7 +316,6 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
         if (T < __builtin_inff()) t0 = make_key(T, 0u);
       }
       thr[j] = t0;
-      if (j < ti.nqt && t0 == kKeyMax) s_leaf[2] = 1;
     }
     // B operand: this lane's query column and k-chunk, all K steps
     // The group's bf16 queries go to LDS (row stride m + 8 elements, so the 16
@@ -417,12 +341,10 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
     // hardware's load counter retires in order.
     // Chunks hold an even number of 64-row blocks (leaves are padded to 128
     // rows), so both halves of the unrolled body always run.
-    const bool seed = kprime <= kSeedMax && __builtin_amdgcn_readfirstlane(s_leaf[2]) != 0;
     for (int64_t base = ti.r0; base < ti.r1; base += 128) {
-      scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kprime, wave, lane,
-                         seed && base == ti.r0);
+      scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kprime, wave, lane);
       scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qs, qstride, qn, keys, cnt, thr, cap, kprime,
-                         wave, lane, false);
+                         wave, lane);
     }
     finish_tile(keys, cnt, thr, t, MQ, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
     __syncthreads();
