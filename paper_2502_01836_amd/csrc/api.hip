@@ -301,7 +301,10 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   // single-work-group launch (below, once the buffers are final)
   constexpr int64_t kFusedItems = 8192;
   const bool fused = !ro->may_read && (ro->small || (items_bound >= 0 && items_bound <= kFusedItems));
-  if (!fused) launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b0, st);
+  // otherwise, with up to kLayoutLdsMax leaves, every work-group of the
+  // placement recomputes the leaf scan itself (one launch instead of two)
+  const bool fused_grid = !ro->may_read && !fused && ix->N <= kLayoutLdsMax;
+  if (!fused && !fused_grid) launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b0, st);
   int64_t items = -1, tiles;
   const int64_t tb = items_bound >= 0 ? tiles_bound(ix, nq, items_bound, mq, chunk) : -1;
   const double bytes = items_bound >= 0 ? static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
@@ -326,6 +329,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   StoreView s = store_view(ix);
   QueryView q = query_view(w);
   if (fused) launch_leaf_scan_scatter(nq, ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b, st);
+  else if (fused_grid) launch_layout_scatter(nq, ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b, st);
   else launch_scatter(nq, ix->N, b, st);
   int grid_scan = static_cast<int>(std::min<int64_t>(std::max<int64_t>(tiles, 1),
                                                      static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : kScanBlocksPerCU)));

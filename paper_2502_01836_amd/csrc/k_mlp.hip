@@ -27,10 +27,10 @@ constexpr int kMlpQB = kMlpQ / 16;    // 16-query column blocks per tile
 constexpr int kMlpXcds = 8;           // XCDs (separate L2 caches) per device
 
 // LDS: the query tile [kMlpQ][m + 4], the per-wavefront output sums
-// [4][kMlpQ], the tile's query rows [kMlpQ] (int64) and 4 ints for the
-// tile search.  (All carved from the dynamic block: a static __shared__
+// [4][kMlpQ], the tile's query rows [kMlpQ] (int64) and 8 ints for the
+// tile search and the tile-prefix scan.  (All carved from the dynamic block: a static __shared__
 // variable would move it off its 16-byte alignment.)
-size_t mlp_infer_lds(int m) { return (static_cast<size_t>(kMlpQ) * (m + 4) + 6 * kMlpQ + 4) * sizeof(float); }
+size_t mlp_infer_lds(int m) { return (static_cast<size_t>(kMlpQ) * (m + 4) + 6 * kMlpQ + 8) * sizeof(float); }
 
 template <typename RowIdx, typename Out>
 __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h, const float *__restrict__ x,
@@ -239,10 +239,30 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer_pairs(const float *__restr
                                                          const int32_t *__restrict__ pcnt, int64_t stride, int N,
                                                          const int32_t *__restrict__ pair,
                                                          const float *__restrict__ offsets,
-                                                         const int32_t *__restrict__ tile_prefix, float *dfo) {
+                                                         const int32_t *__restrict__ tile_prefix, float *dfo,
+                                                         int local_prefix) {
   extern __shared__ float xs[];
-  int &s_lo = reinterpret_cast<int *>(xs + kMlpQ * (m + 4) + 6 * kMlpQ)[0];
-  int &s_f = reinterpret_cast<int *>(xs + kMlpQ * (m + 4) + 6 * kMlpQ)[1];
+  int *ints = reinterpret_cast<int *>(xs + kMlpQ * (m + 4) + 6 * kMlpQ);
+  int &s_lo = ints[0];
+  int &s_f = ints[1];
+  // With local_prefix every work-group computes the tile prefix itself (into
+  // LDS, F + 1 entries after 4 scan words): no separate launch for it.
+  if (local_prefix) {
+    int32_t *tp = ints + 8;
+    const int per = (F + blockDim.x - 1) / blockDim.x;
+    const int f0 = min(F, static_cast<int>(threadIdx.x) * per), f1 = min(F, f0 + per);
+    int sum = 0;
+    for (int f = f0; f < f1; ++f) sum += (pcnt[f] + kMlpQ - 1) / kMlpQ;
+    int tot;
+    int run = block_scan_excl<256>(sum, ints + 4, tot);
+    for (int f = f0; f < f1; ++f) {
+      tp[f] = run;
+      run += (pcnt[f] + kMlpQ - 1) / kMlpQ;
+    }
+    if (threadIdx.x == 0) tp[F] = tot;
+    __syncthreads();
+    tile_prefix = tp;
+  }
   const int total = tile_prefix[F];
   // filters per bucket of the two-level search (at most 64 for F <= 16384)
   const int B = (F + blockDim.x - 1) / blockDim.x;
@@ -541,8 +561,14 @@ void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x,
                             const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets,
                             int32_t *tile_prefix, float *dfo, hipStream_t st) {
   if (F <= 0 || stride <= 0) return;
-  hipLaunchKernelGGL(k_mlp_tiles, dim3(1), dim3(1024), 0, st, F, pcnt, tile_prefix);
-  LAUNCH_OK("mlp_tiles");
+  // up to kLocalPrefixMax filters the inference kernel computes the tile
+  // prefix itself (one launch instead of two)
+  constexpr int kLocalPrefixMax = 4096;
+  const bool local = F <= kLocalPrefixMax;
+  if (!local) {
+    hipLaunchKernelGGL(k_mlp_tiles, dim3(1), dim3(1024), 0, st, F, pcnt, tile_prefix);
+    LAUNCH_OK("mlp_tiles");
+  }
   // persistent grid: a few work-groups per CU, never more than the tiles can be
   static int cus = 0;
   if (cus == 0) {
@@ -554,11 +580,11 @@ void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x,
   // (a multiple of 8 for the per-XCD tile ranges; spare work-groups exit)
   const int grid = static_cast<int>(
       ceil_div(std::min<int64_t>(tiles_bound, static_cast<int64_t>(cus) * 4), kMlpXcds) * kMlpXcds);
-  const size_t lds = mlp_infer_lds(m);
+  const size_t lds = mlp_infer_lds(m) + (local ? (static_cast<size_t>(F) + 1 + 4) * sizeof(int32_t) : 0);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer_pairs),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   hipLaunchKernelGGL(k_mlp_infer_pairs, dim3(grid), dim3(256), lds, st, w, F, m, h, x, plist, pcnt, stride, N, pair,
-                     offsets, tile_prefix, dfo);
+                     offsets, tile_prefix, dfo, local ? 1 : 0);
   LAUNCH_OK("mlp_infer_pairs");
 }
 

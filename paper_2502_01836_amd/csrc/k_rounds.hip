@@ -27,8 +27,12 @@ __global__ void __launch_bounds__(64 * kListWaves) k_worklist(int64_t nq, int N,
                                                              Schedule sched, int32_t *qround, RoundBufs b) {
   __shared__ int64_t stat[4][kListWaves];
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  // the round's control words start from zero (nothing reads them during this kernel)
+  // the round's control words start from zero (nothing reads them during
+  // this kernel), and so do the per-leaf fill counters of the placement
   if (blockIdx.x == 0 && threadIdx.x < kCtlRoundWords) b.ctl[threadIdx.x] = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b.leaf_fill[i] = 0;
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kListWaves + wave;
   int cnt = 0;
   int64_t lbp = 0, fp = 0, series = 0;
@@ -165,9 +169,12 @@ __global__ void __launch_bounds__(256) k_round_reset(RoundBufs b, int n_ctl, int
 }
 
 // Exclusive scans over leaves: item starts and tile starts (the whole
-// work-group of 1024 threads).
+// work-group of 1024 threads).  `publish` writes them, the round's control
+// words and (with zero_fill) zeroed per-leaf fill counters to global memory;
+// `ist` (optional, LDS [N]) receives the item starts.
 __device__ inline void leaf_scan_body(int N, const int64_t *__restrict__ leaf_off, int mq, int64_t row_bytes,
-                                      RoundBufs &b, int64_t *sh) {
+                                      RoundBufs &b, int64_t *sh, bool publish = true, bool zero_fill = true,
+                                      int32_t *ist = nullptr) {
   const int tid = threadIdx.x;
   const int per = (N + 1023) / 1024;
   const int l0 = min(N, tid * per), l1 = min(N, l0 + per);
@@ -186,13 +193,16 @@ __device__ inline void leaf_scan_body(int N, const int64_t *__restrict__ leaf_of
   for (int L = l0; L < l1; ++L) {
     int c = b.leaf_cnt[L];
     int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + b.chunk - 1) / b.chunk;
-    b.leaf_istart[L] = static_cast<int32_t>(ri);
-    b.tile_start[L] = static_cast<int32_t>(rt);
-    b.leaf_fill[L] = 0;
+    if (ist) ist[L] = static_cast<int32_t>(ri);
+    if (publish) {
+      b.leaf_istart[L] = static_cast<int32_t>(ri);
+      b.tile_start[L] = static_cast<int32_t>(rt);
+      if (zero_fill) b.leaf_fill[L] = 0;
+    }
     ri += c;
     rt += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
   }
-  if (tid == 0) {
+  if (publish && tid == 0) {
     b.leaf_istart[N] = static_cast<int32_t>(tot_i);
     b.tile_start[N] = static_cast<int32_t>(tot_t);
     b.ctl[kCtlItems] = tot_i;
@@ -228,6 +238,30 @@ __global__ void __launch_bounds__(1024) k_leaf_scan_scatter(int64_t nq, int N, c
       b.item_leaf[slot] = L;
       b.qitem_idx[q * N + r] = slot;
     }
+  }
+}
+
+// The leaf scan and the item placement in one launch for up to
+// kLayoutLdsMax leaves: every work-group computes the item starts itself into
+// LDS (work-group 0 also publishes them), then places its 16 queries' items
+// as k_scatter does.  leaf_fill must be zero on entry (the prune cascade
+// zeroes it); leaf_cnt is left for the rerank to zero.
+__global__ void __launch_bounds__(1024) k_layout_scatter(int64_t nq, int N, const int64_t *__restrict__ leaf_off,
+                                                         int mq, int64_t row_bytes, RoundBufs b) {
+  extern __shared__ int32_t s_ist[];  // [N]
+  __shared__ int64_t sh[16];
+  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, blockIdx.x == 0, false, s_ist);
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (q >= nq) return;
+  const int n = b.qitem_cnt[q];
+  for (int r = lane; r < n; r += kWave) {
+    const int L = b.qitem_leaf[q * N + r];
+    const int slot = s_ist[L] + atomicAdd(b.leaf_fill + L, 1);
+    b.item_q[slot] = static_cast<int32_t>(q);
+    b.item_leaf[slot] = L;
+    b.qitem_idx[q * N + r] = slot;
   }
 }
 
@@ -519,6 +553,14 @@ void launch_leaf_scan_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq
                               hipStream_t st) {
   hipLaunchKernelGGL(k_leaf_scan_scatter, dim3(1), dim3(1024), 0, st, nq, N, leaf_off, mq, row_bytes, b);
   LAUNCH_OK("leaf_scan_scatter");
+}
+
+void launch_layout_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b,
+                           hipStream_t st) {
+  if (N > kLayoutLdsMax) fail(LEAFI_EINTERNAL, "layout_scatter: too many leaves");
+  hipLaunchKernelGGL(k_layout_scatter, dim3(ceil_div(std::max<int64_t>(nq, 1), 16)), dim3(1024),
+                     static_cast<size_t>(N) * sizeof(int32_t), st, nq, N, leaf_off, mq, row_bytes, b);
+  LAUNCH_OK("layout_scatter");
 }
 
 void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {

@@ -452,6 +452,11 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
   const int lane = threadIdx.x & (kWave - 1);
   const int m = s.m;
   const int n_items = static_cast<int>(b.ctl[kCtlItems]);
+  // the round's per-leaf item counts were consumed by its layout: zero them
+  // for the merge, which counts rescan items into them
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < s.N;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b.leaf_cnt[i] = 0;
   // error constants (see the certificate below)
   const double u = 1.0 / 16777216.0;  // 2^-24
   const float delta32 = static_cast<float>(2.0 * (m + 4) * u);

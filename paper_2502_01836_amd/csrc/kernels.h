@@ -180,6 +180,14 @@ void launch_round_reset(RoundBufs b, int n_ctl, int N, int64_t nq, hipStream_t s
 // Place each query's emitted leaves into item slots.
 void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st);
 
+// launch_leaf_scan then launch_scatter in one launch of the scatter's grid
+// (every work-group recomputes the leaf scan into LDS), for N <=
+// kLayoutLdsMax.  leaf_fill must be zero on entry (launch_worklist zeroes it);
+// leaf_cnt is left for launch_item_rerank to zero.
+constexpr int kLayoutLdsMax = 4096;
+void launch_layout_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b,
+                           hipStream_t st);
+
 // launch_leaf_scan then launch_scatter in one single-work-group launch, for
 // passes with few items (its placement loop is serial per query).
 void launch_leaf_scan_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b,
@@ -224,9 +232,10 @@ void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64
 
 // Pruning values for listed pairs only: filter f evaluates the entries
 // plist[f * stride + 0 .. pcnt[f]) (q * N + visit position) and writes
-// dfo[entry] = d^f(x[q]) - offsets[pair[q] * F + f].  tile_prefix [F + 1] is
-// scratch: a first launch lays out the non-empty 16-query tiles of all
-// filters, a persistent grid then walks them.
+// dfo[entry] = d^f(x[q]) - offsets[pair[q] * F + f].  A persistent grid walks
+// the non-empty 32-query tiles of all filters; their prefix over the filters
+// is computed by every work-group itself for F <= 4096, else by a first
+// launch into tile_prefix [F + 1] (scratch).
 void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int64_t *plist,
                             const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets,
                             int32_t *tile_prefix, float *dfo, hipStream_t st);
