@@ -186,10 +186,13 @@ __device__ inline void leaf_scan_body(int N, const int64_t *__restrict__ leaf_of
     stl += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
     if (c > 0) rows += leaf_off[L + 1] - leaf_off[L];
   }
-  int64_t tot_i, tot_t, tot_r;
-  int64_t ri = block_scan_excl<1024>(si, sh, tot_i);
-  int64_t rt = block_scan_excl<1024>(stl, sh, tot_t);
+  // item and tile counts share one scan (each total < 2^31: packed as
+  // items + tiles * 2^32, the low half never carries), rows a second
+  int64_t tot_it, tot_r;
+  const int64_t rit = block_scan_excl<1024>(si + (stl << 32), sh, tot_it);
   block_scan_excl<1024>(rows, sh, tot_r);
+  int64_t ri = rit & 0xffffffffll, rt = rit >> 32;
+  const int64_t tot_i = tot_it & 0xffffffffll, tot_t = tot_it >> 32;
   for (int L = l0; L < l1; ++L) {
     int c = b.leaf_cnt[L];
     int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + b.chunk - 1) / b.chunk;
@@ -224,16 +227,18 @@ __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__rest
 // launch instead of two: the leaf scan, then every query's items placed by
 // one thread each (the placement is k_scatter's).
 __global__ void __launch_bounds__(1024) k_leaf_scan_scatter(int64_t nq, int N, const int64_t *__restrict__ leaf_off,
-                                                            int mq, int64_t row_bytes, RoundBufs b) {
+                                                            int mq, int64_t row_bytes, RoundBufs b, int lds_starts) {
+  extern __shared__ int32_t s_ist[];  // [N] with lds_starts, else unused
   __shared__ int64_t sh[16];
-  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh);
+  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, true, true, lds_starts ? s_ist : nullptr);
   __syncthreads();  // item starts written; the per-leaf counts are consumed
+  const int32_t *ist = lds_starts ? s_ist : b.leaf_istart;
   for (int i = threadIdx.x; i < N; i += blockDim.x) b.leaf_cnt[i] = 0;
   for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
     const int n = b.qitem_cnt[q];
     for (int r = 0; r < n; ++r) {
       const int L = b.qitem_leaf[q * N + r];
-      const int slot = b.leaf_istart[L] + atomicAdd(b.leaf_fill + L, 1);
+      const int slot = ist[L] + atomicAdd(b.leaf_fill + L, 1);
       b.item_q[slot] = static_cast<int32_t>(q);
       b.item_leaf[slot] = L;
       b.qitem_idx[q * N + r] = slot;
@@ -551,7 +556,9 @@ void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, int64_t row_bytes,
 
 void launch_leaf_scan_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_leaf_scan_scatter, dim3(1), dim3(1024), 0, st, nq, N, leaf_off, mq, row_bytes, b);
+  const bool lds = N <= kLayoutLdsMax;  // item starts kept in LDS for the placement
+  hipLaunchKernelGGL(k_leaf_scan_scatter, dim3(1), dim3(1024), lds ? static_cast<size_t>(N) * sizeof(int32_t) : 0, st,
+                     nq, N, leaf_off, mq, row_bytes, b, lds ? 1 : 0);
   LAUNCH_OK("leaf_scan_scatter");
 }
 
