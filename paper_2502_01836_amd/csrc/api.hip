@@ -304,7 +304,9 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   // otherwise, with up to kLayoutLdsMax leaves, every work-group of the
   // placement recomputes the leaf scan itself (one launch instead of two)
   const bool fused_grid = !ro->may_read && !fused && ix->N <= kLayoutLdsMax;
-  if (!fused && !fused_grid) launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b0, st);
+  if (ro->first_leaf && (ro->may_read || ix->N > kLayoutLdsMax))
+    fail(LEAFI_EINTERNAL, "scan_round: first-leaf layout needs a planned round and at most 4096 leaves");
+  if (!ro->first_leaf && !fused && !fused_grid) launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b0, st);
   int64_t items = -1, tiles;
   const int64_t tb = items_bound >= 0 ? tiles_bound(ix, nq, items_bound, mq, chunk) : -1;
   const double bytes = items_bound >= 0 ? static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
@@ -328,7 +330,10 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   b.use_tau = ro->use_tau ? 1 : 0;
   StoreView s = store_view(ix);
   QueryView q = query_view(w);
-  if (fused) launch_leaf_scan_scatter(nq, ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b, st);
+  if (ro->first_leaf)
+    launch_first_round_layout(nq, ix->N, w.order.get(), ix->leaf_off.get(), ix->leaf_n.get(), mq, ro->row_bytes, b,
+                              st);
+  else if (fused) launch_leaf_scan_scatter(nq, ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b, st);
   else if (fused_grid) launch_layout_scatter(nq, ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b, st);
   else launch_scatter(nq, ix->N, b, st);
   int grid_scan = static_cast<int>(std::min<int64_t>(std::max<int64_t>(tiles, 1),
@@ -392,13 +397,30 @@ void begin_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k
 // After the first round has set tau: d^f for every (query, filtered leaf)
 // pair a later round can still test.  tau only decreases, so this covers all
 // later rounds (filter-pair counts were zeroed by begin_batch).
+void infer_filter_pairs(leafi_index *ix, int64_t nq, hipStream_t st) {
+  Workspace &w = ix->ws;
+  launch_mlp_infer_pairs(ix->filt.w.get(), ix->filt.F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(),
+                         nq, ix->N, w.pair.get(), ix->cal.offsets.get(), w.ptile.get(), w.dfo.get(), st);
+}
+
 void eval_filters(leafi_index *ix, int64_t nq, hipStream_t st) {
   Workspace &w = ix->ws;
-  const int F = ix->filt.F;
   launch_filter_pairs(nq, ix->N, w.lbs.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
                       w.pcnt.get(), w.dfo.get(), st);
-  launch_mlp_infer_pairs(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), nq, ix->N,
-                         w.pair.get(), ix->cal.offsets.get(), w.ptile.get(), w.dfo.get(), st);
+  infer_filter_pairs(ix, nq, st);
+}
+
+// The filter-pair selection done by a merge (see launch_query_merge).
+FilterPairArgs filter_pair_args(leafi_index *ix) {
+  Workspace &w = ix->ws;
+  FilterPairArgs fp;
+  fp.lbs = w.lbs.get();
+  fp.order = w.order.get();
+  fp.filt_of_leaf = ix->filt.filt_of_leaf.get();
+  fp.plist = w.plist.get();
+  fp.pcnt = w.pcnt.get();
+  fp.dfo = w.dfo.get();
+  return fp;
 }
 
 void launch_round_worklist(leafi_index *ix, int64_t nq, int want, bool f_now, hipStream_t st) {
@@ -550,11 +572,18 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
   // No reset launches: the prune cascade zeroes the round's control words and
   // every merge leaves the per-leaf and per-query item counts at zero.
   for (int r = 0; r < R; ++r) {
-    if (use_f && r == 1) eval_filters(ix, nq, st);
-    launch_round_worklist(ix, nq, p.schedule[r], use_f && r > 0, st);
+    // the first round's merge selected the filter pairs a later round can
+    // test (from its own new tau); their inference runs once, here
+    if (use_f && r == 1) infer_filter_pairs(ix, nq, st);
+    // a first round of one leaf per query takes each query's first leaf in
+    // its visit order (tau is +inf, no filter is evaluated yet): the layout
+    // emits it, with no prune cascade launch
+    const bool first_leaf = r == 0 && p.schedule[0] == 1 && ix->N <= kLayoutLdsMax;
+    if (!first_leaf) launch_round_worklist(ix, nq, p.schedule[r], use_f && r > 0, st);
     const int64_t bnd = planned_bound(ix, nq, p, r);
     RoundOpts ro;
     ro.may_read = false;
+    ro.first_leaf = first_leaf;
     ro.use_tau = true;
     ro.row_bytes = scan_row_bytes(ix, true);
     if (timed) {
@@ -562,7 +591,11 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
       ro.ev_end = w.sev[2 * r + 1];
     }
     scan_round(ix, nq, true, p.kprime, p.kmax, st, nullptr, bnd, &ro);
-    launch_query_merge(nq, N, p.kmax, true, false, views(w), st);
+    // The filter pairs need only an upper bound of tau (a larger tau selects
+    // a superset, and every pair it adds is pruned by its bound anyway), so
+    // the first round's merge selects them before its rescan pass.
+    launch_query_merge(nq, N, p.kmax, true, false, views(w), st, nullptr, nullptr, nullptr,
+                       use_f && r == 0 && R > 1 ? filter_pair_args(ix) : FilterPairArgs());
     RoundOpts rf;
     rf.may_read = false;
     rf.small = true;

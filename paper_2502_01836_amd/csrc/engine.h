@@ -72,6 +72,8 @@ struct RoundOpts {
   hipEvent_t ev_end = nullptr;
   bool small = false;           // a pass expected to hold few items (rescans): small persistent grids
   bool use_tau = false;         // a search round: the BF16 scan skips rows provably farther than tau
+  bool first_leaf = false;      // the batch's first round of one leaf per query, emitted by the layout
+                                // itself from the visit order (no prune cascade launch; may_read false)
 };
 // Lay out the round's items, scan and rerank them (see api.hip).
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,

@@ -174,13 +174,14 @@ __global__ void __launch_bounds__(256) k_round_reset(RoundBufs b, int n_ctl, int
 // `ist` (optional, LDS [N]) receives the item starts.
 __device__ inline void leaf_scan_body(int N, const int64_t *__restrict__ leaf_off, int mq, int64_t row_bytes,
                                       RoundBufs &b, int64_t *sh, bool publish = true, bool zero_fill = true,
-                                      int32_t *ist = nullptr) {
+                                      int32_t *ist = nullptr, const int32_t *cnt_src = nullptr) {
+  const int32_t *cnt = cnt_src ? cnt_src : b.leaf_cnt;
   const int tid = threadIdx.x;
   const int per = (N + 1023) / 1024;
   const int l0 = min(N, tid * per), l1 = min(N, l0 + per);
   int64_t si = 0, stl = 0, rows = 0;
   for (int L = l0; L < l1; ++L) {
-    int c = b.leaf_cnt[L];
+    int c = cnt[L];
     int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + b.chunk - 1) / b.chunk;
     si += c;
     stl += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
@@ -194,7 +195,7 @@ __device__ inline void leaf_scan_body(int N, const int64_t *__restrict__ leaf_of
   int64_t ri = rit & 0xffffffffll, rt = rit >> 32;
   const int64_t tot_i = tot_it & 0xffffffffll, tot_t = tot_it >> 32;
   for (int L = l0; L < l1; ++L) {
-    int c = b.leaf_cnt[L];
+    int c = cnt[L];
     int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + b.chunk - 1) / b.chunk;
     if (ist) ist[L] = static_cast<int32_t>(ri);
     if (publish) {
@@ -270,6 +271,46 @@ __global__ void __launch_bounds__(1024) k_layout_scatter(int64_t nq, int N, cons
   }
 }
 
+// A first round of one leaf per query (tau is +inf and no filter is
+// evaluated yet, so nothing is pruned and each query's item is the first
+// leaf of its visit order) laid out in one single-work-group launch instead
+// of the prune cascade plus the layout: per-leaf counts in LDS, the leaf
+// scan, the placement, the query's cursor and item list, and the cascade's
+// statistics (leaves scanned, series).  Work-group 0 of the batch's query
+// preparation has zeroed the control words.
+__global__ void __launch_bounds__(1024) k_first_round_layout(int64_t nq, int N, const int32_t *__restrict__ order,
+                                                             const int64_t *__restrict__ leaf_off,
+                                                             const int32_t *__restrict__ leaf_n, int mq,
+                                                             int64_t row_bytes, RoundBufs b) {
+  extern __shared__ int32_t s_lds[];  // [N] counts, then [N] item starts
+  int32_t *s_cnt = s_lds, *s_ist = s_lds + N;
+  __shared__ int64_t sh[16];
+  for (int i = threadIdx.x; i < N; i += blockDim.x) s_cnt[i] = 0;
+  __syncthreads();
+  for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) atomicAdd(s_cnt + order[q * N], 1);
+  __syncthreads();
+  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, true, true, s_ist, s_cnt);
+  // series in the round's items: sum over leaves of count x real rows
+  int64_t series = 0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) series += static_cast<int64_t>(s_cnt[i]) * leaf_n[i];
+  int64_t tot_series;
+  block_scan_excl<1024>(series, sh, tot_series);  // (its barriers also publish the fill zeroing)
+  for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
+    const int L = order[q * N];
+    const int slot = s_ist[L] + atomicAdd(b.leaf_fill + L, 1);
+    b.item_q[slot] = static_cast<int32_t>(q);
+    b.item_leaf[slot] = L;
+    b.qitem_leaf[q * N] = L;
+    b.qitem_idx[q * N] = slot;
+    b.qitem_cnt[q] = 1;
+    b.cursor[q] = 1;
+  }
+  if (threadIdx.x == 0) {
+    b.ctl[kCtlScanned] += nq;
+    b.ctl[kCtlSeries] += tot_series;
+  }
+}
+
 // One wavefront per query: place its emitted leaves into item slots.
 __global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -299,7 +340,7 @@ __global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b
 // `dedupe`, a row met twice (a rescan of a leaf already merged) is kept once.
 __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int KM, int C, int check_cert,
                                                      int dedupe, RoundBufs b, const int64_t *__restrict__ rowid,
-                                                     int64_t *out_ids, float *out_d) {
+                                                     int64_t *out_ids, float *out_d, FilterPairArgs fp) {
   extern __shared__ unsigned char smem_raw[];
   // four wavefronts per work-group, each with its own LDS slice and query
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -312,6 +353,7 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
   int active = 0, n_fb = 0;
   for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
     int n_it = b.qitem_cnt[q];
+    float tau_now = __builtin_inff();  // the query's tau after this merge (filter pairs below)
     if (n_it > 0) {
       int k = b.kq[q];
       int have = b.res_cnt[q];
@@ -385,6 +427,7 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
         b.res_cnt[q] = cnt;
         b.tau[q] = tau;
       }
+      tau_now = tau;
       // the query's item list becomes its rescan list: every item whose
       // certificate bound does not exceed the new tau, in item order
       int nr = 0;
@@ -423,6 +466,19 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
         out_ids[q * kmax + i] = hit ? rowid[b.res_row[q * kmax + i]] : -1;
         out_d[q * kmax + i] = hit ? static_cast<float>(sqrt(b.res_d2[q * kmax + i])) : __builtin_inff();
       }
+    }
+    if (fp.plist) {
+      // the query's filter pairs for the rounds to come (k_filter_pairs'
+      // selection, from the tau just merged)
+      if (n_it <= 0) tau_now = b.tau[q];
+      const int cur = b.cursor[q];
+      if (b.pair[q] >= 0)
+        for (int pos = cur + lane; pos < N; pos += kWave) {
+          const int64_t idx = q * N + pos;
+          const int f = fp.filt_of_leaf[fp.order[idx]];
+          if (f < 0 || fp.lbs[idx] > tau_now * (1.0f + kLbSlack)) fp.dfo[idx] = -__builtin_inff();
+          else fp.plist[static_cast<int64_t>(f) * nq + atomicAdd(fp.pcnt + f, 1)] = idx;
+        }
     }
     if (check_cert && b.cursor[q] < N) ++active;
   }
@@ -554,6 +610,14 @@ void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, int64_t row_bytes,
   LAUNCH_OK("leaf_scan");
 }
 
+void launch_first_round_layout(int64_t nq, int N, const int32_t *order, const int64_t *leaf_off,
+                               const int32_t *leaf_n, int mq, int64_t row_bytes, RoundBufs b, hipStream_t st) {
+  if (N > kLayoutLdsMax) fail(LEAFI_EINTERNAL, "first_round_layout: too many leaves");
+  hipLaunchKernelGGL(k_first_round_layout, dim3(1), dim3(1024), 2 * static_cast<size_t>(N) * sizeof(int32_t), st, nq,
+                     N, order, leaf_off, leaf_n, mq, row_bytes, b);
+  LAUNCH_OK("first_round_layout");
+}
+
 void launch_leaf_scan_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b,
                               hipStream_t st) {
   const bool lds = N <= kLayoutLdsMax;  // item starts kept in LDS for the placement
@@ -576,7 +640,7 @@ void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
 }
 
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
-                        const int64_t *rowid, int64_t *ids, float *dists) {
+                        const int64_t *rowid, int64_t *ids, float *dists, const FilterPairArgs &fp) {
   const int KM = pow2_at_least(kmax < 2 ? 2 : kmax);
   // LDS slice per wavefront: the running top-k plus up to 255 items' lists
   // (at most 256 entries unless 2 KM alone is larger)
@@ -587,7 +651,7 @@ void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedup
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_merge),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, KM, C, check_cert ? 1 : 0,
-                     dedupe ? 1 : 0, b, rowid, ids, dists);
+                     dedupe ? 1 : 0, b, rowid, ids, dists, fp);
   LAUNCH_OK("query_merge");
 }
 

@@ -188,6 +188,13 @@ constexpr int kLayoutLdsMax = 4096;
 void launch_layout_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b,
                            hipStream_t st);
 
+// The first round of a batch when it takes one leaf per query: each query's
+// item is the first leaf of its visit order (nothing can be pruned yet);
+// replaces launch_worklist, launch_leaf_scan and launch_scatter for that
+// round (single work-group, N <= kLayoutLdsMax).
+void launch_first_round_layout(int64_t nq, int N, const int32_t *order, const int64_t *leaf_off,
+                               const int32_t *leaf_n, int mq, int64_t row_bytes, RoundBufs b, hipStream_t st);
+
 // launch_leaf_scan then launch_scatter in one single-work-group launch, for
 // passes with few items (its placement loop is serial per query).
 void launch_leaf_scan_scatter(int64_t nq, int N, const int64_t *leaf_off, int mq, int64_t row_bytes, RoundBufs b,
@@ -213,8 +220,19 @@ void scan_geometry(int kprime, int *mq, int *cap, int mq_small = 32);
 // queue uncertified items (check_cert) and count active queries.  With ids
 // non-null (the batch's last merge) also write every query's output row, as
 // launch_finalize does.
+// With fp.plist non-null the merge also selects each query's filter pairs
+// from its new tau, as launch_filter_pairs does (no separate launch).
+struct FilterPairArgs {
+  const float *lbs = nullptr;
+  const int32_t *order = nullptr;
+  const int32_t *filt_of_leaf = nullptr;
+  int64_t *plist = nullptr;
+  int32_t *pcnt = nullptr;
+  float *dfo = nullptr;
+};
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
-                        const int64_t *rowid = nullptr, int64_t *ids = nullptr, float *dists = nullptr);
+                        const int64_t *rowid = nullptr, int64_t *ids = nullptr, float *dists = nullptr,
+                        const FilterPairArgs &fp = FilterPairArgs());
 
 // Final outputs: ids (original series ids) and Euclidean distances.
 void launch_finalize(int64_t nq, int kmax, const int64_t *rowid, RoundBufs b, int64_t *ids, float *dists,
