@@ -562,6 +562,16 @@ void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_
 // round is the prune cascade, scan, rerank and merge, then an exact rescan
 // pass of the uncertified items whose size is read on the device (empty
 // passes exit at once).  With `timed`, per-round events bracket the scan.
+// Launches saved against that plain sequence (results are the same):
+//  * a first round of one leaf per query takes each query's first leaf in
+//    its visit order (tau is +inf, no filter is evaluated yet): its layout
+//    emits it, with no prune cascade launch;
+//  * the filter pairs need only an upper bound of tau (a larger tau selects
+//    a superset, and every pair it adds is pruned by its bound anyway), so
+//    the first round's merge selects them from its own new tau, and their
+//    inference runs right after it, before the rescan pass;
+//  * each rescan pass's merge (which queues no rescans) then runs every
+//    query's prune cascade for the next round from the final tau.
 void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
                      const SearchPlan &p, bool use_f, int64_t *ids, float *dists, bool timed, hipStream_t st) {
   Workspace &w = ix->ws;
@@ -572,14 +582,8 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
   // No reset launches: the prune cascade zeroes the round's control words and
   // every merge leaves the per-leaf and per-query item counts at zero.
   for (int r = 0; r < R; ++r) {
-    // the first round's merge selected the filter pairs a later round can
-    // test (from its own new tau); their inference runs once, here
-    if (use_f && r == 1) infer_filter_pairs(ix, nq, st);
-    // a first round of one leaf per query takes each query's first leaf in
-    // its visit order (tau is +inf, no filter is evaluated yet): the layout
-    // emits it, with no prune cascade launch
     const bool first_leaf = r == 0 && p.schedule[0] == 1 && ix->N <= kLayoutLdsMax;
-    if (!first_leaf) launch_round_worklist(ix, nq, p.schedule[r], use_f && r > 0, st);
+    if (r == 0 && !first_leaf) launch_round_worklist(ix, nq, p.schedule[r], false, st);
     const int64_t bnd = planned_bound(ix, nq, p, r);
     RoundOpts ro;
     ro.may_read = false;
@@ -591,20 +595,29 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
       ro.ev_end = w.sev[2 * r + 1];
     }
     scan_round(ix, nq, true, p.kprime, p.kmax, st, nullptr, bnd, &ro);
-    // The filter pairs need only an upper bound of tau (a larger tau selects
-    // a superset, and every pair it adds is pruned by its bound anyway), so
-    // the first round's merge selects them before its rescan pass.
+    const bool filters_next = use_f && r == 0 && R > 1;
     launch_query_merge(nq, N, p.kmax, true, false, views(w), st, nullptr, nullptr, nullptr,
-                       use_f && r == 0 && R > 1 ? filter_pair_args(ix) : FilterPairArgs());
+                       filters_next ? filter_pair_args(ix) : FilterPairArgs());
+    if (filters_next) infer_filter_pairs(ix, nq, st);
     RoundOpts rf;
     rf.may_read = false;
     rf.small = true;
     // rescan pass over the lists the merge left (empty lists: the pass exits at once)
     scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bnd, &rf);
-    // the last merge of the batch also writes the output rows
+    // the last merge of the batch also writes the output rows; the others
+    // run the next round's prune cascade
     const bool last = r == R - 1;
+    CascadeArgs cs;
+    if (!last) {
+      cs.enabled = 1;
+      cs.lbs = w.lbs.get();
+      cs.order = w.order.get();
+      cs.dfo = use_f ? w.dfo.get() : nullptr;
+      cs.leaf_n = ix->leaf_n.get();
+      cs.want = p.schedule[r + 1];
+    }
     launch_query_merge(nq, N, p.kmax, false, true, views(w), st, last ? ix->rowid.get() : nullptr,
-                       last ? ids : nullptr, last ? dists : nullptr);
+                       last ? ids : nullptr, last ? dists : nullptr, FilterPairArgs(), cs);
   }
 }
 

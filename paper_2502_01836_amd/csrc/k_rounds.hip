@@ -20,39 +20,28 @@ namespace {
 // the bound prunes ends the walk (every later leaf is pruned too).
 constexpr int kListWaves = 16;  // queries (wavefronts) per work-group of the prune cascade
 
-__global__ void __launch_bounds__(64 * kListWaves) k_worklist(int64_t nq, int N, const float *__restrict__ lbs,
-                                                             const int32_t *__restrict__ order,
-                                                             const float *__restrict__ dfo,
-                                                             const int32_t *__restrict__ leaf_n, int want,
-                                                             Schedule sched, int32_t *qround, RoundBufs b) {
-  __shared__ int64_t stat[4][kListWaves];
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  // the round's control words start from zero (nothing reads them during
-  // this kernel), and so do the per-leaf fill counters of the placement
-  if (blockIdx.x == 0 && threadIdx.x < kCtlRoundWords) b.ctl[threadIdx.x] = 0;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    b.leaf_fill[i] = 0;
-  const int64_t q = static_cast<int64_t>(blockIdx.x) * kListWaves + wave;
-  int cnt = 0;
-  int64_t lbp = 0, fp = 0, series = 0;
-  if (q < nq) {
+struct CascadeCount {
+  int cnt = 0;  // leaves emitted
+  int64_t lbp = 0, fp = 0, series = 0;  // pruned by bound / by filter, real series emitted (lane 0: totals)
+};
+
+// The cascade of query q (one wavefront) from its cursor with the given tau:
+// emits its surviving leaves into qitem_leaf, counts them per leaf and
+// advances its cursor.
+__device__ inline CascadeCount cascade_query(int64_t q, int N, const float *__restrict__ lbs,
+                                             const int32_t *__restrict__ order, const float *__restrict__ dfo,
+                                             const int32_t *__restrict__ leaf_n, int want, float tau, RoundBufs &b,
+                                             int lane) {
+  CascadeCount c;
   int pos = b.cursor[q];
-  if (qround && pos < N) {
-    // serving: each query follows its own schedule from its own round count
-    const int r = qround[q];
-    want = sched.r[r < sched.n ? r : sched.n - 1];
-    if (lane == 0) qround[q] = r + 1;
-  }
   if (pos < N) {
-    const float tau = b.tau[q];
     const float tau_lb = tau * (1.0f + kLbSlack);
     const bool use_f = dfo != nullptr && b.pair[q] >= 0;
     const float *lbq = lbs + q * N;
     const float *fq = use_f ? dfo + q * N : nullptr;
     const int32_t *oq = order + q * N;
     const uint64_t lt = (1ull << lane) - 1ull;
-    while (pos < N && (want == 0 || cnt < want)) {
+    while (pos < N && (want == 0 || c.cnt < want)) {
       const int p = pos + lane;
       const bool valid = p < N;
       // three independent coalesced loads per position: leaf, bound, filter value
@@ -69,8 +58,8 @@ __global__ void __launch_bounds__(64 * kListWaves) k_worklist(int64_t nq, int N,
       uint64_t msurv = __ballot(surv);
       int end = stop;
       bool cut = false;
-      if (want > 0 && __popcll(msurv) > want - cnt) {
-        const int need = want - cnt;
+      if (want > 0 && __popcll(msurv) > want - c.cnt) {
+        const int need = want - c.cnt;
         const int rank = __popcll(msurv & lt);
         const uint64_t mlast = __ballot(surv && rank == need - 1);
         end = __ffsll(static_cast<unsigned long long>(mlast));  // one past the need-th survivor
@@ -80,36 +69,62 @@ __global__ void __launch_bounds__(64 * kListWaves) k_worklist(int64_t nq, int N,
       const uint64_t mend = end >= kWave ? ~0ull : ((1ull << end) - 1ull);
       if ((msurv >> lane) & 1ull) {
         const int rank = __popcll(msurv & lt);
-        b.qitem_leaf[q * N + cnt + rank] = L;
+        b.qitem_leaf[q * N + c.cnt + rank] = L;
         atomicAdd(b.leaf_cnt + L, 1);
-        series += leaf_n[L];
+        c.series += leaf_n[L];
       }
-      cnt += __popcll(msurv);
-      fp += __popcll(__ballot(fpr) & mend);
+      c.cnt += __popcll(msurv);
+      c.fp += __popcll(__ballot(fpr) & mend);
       if (cut) {
         pos += end;
         break;
       }
       if (s < nvalid) {
-        lbp += N - (pos + s);
+        c.lbp += N - (pos + s);
         pos = N;
         break;
       }
       pos += nvalid;
     }
   }
-  series = wave_sum(series);
+  c.series = wave_sum(c.series);
   if (lane == 0) {
     b.cursor[q] = pos;
-    b.qitem_cnt[q] = cnt;
+    b.qitem_cnt[q] = c.cnt;
   }
-  }  // q < nq
+  return c;
+}
+
+__global__ void __launch_bounds__(64 * kListWaves) k_worklist(int64_t nq, int N, const float *__restrict__ lbs,
+                                                             const int32_t *__restrict__ order,
+                                                             const float *__restrict__ dfo,
+                                                             const int32_t *__restrict__ leaf_n, int want,
+                                                             Schedule sched, int32_t *qround, RoundBufs b) {
+  __shared__ int64_t stat[4][kListWaves];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  // the round's control words start from zero (nothing reads them during
+  // this kernel), and so do the per-leaf fill counters of the placement
+  if (blockIdx.x == 0 && threadIdx.x < kCtlRoundWords) b.ctl[threadIdx.x] = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b.leaf_fill[i] = 0;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kListWaves + wave;
+  CascadeCount c;
+  if (q < nq) {
+    if (qround && b.cursor[q] < N) {
+      // serving: each query follows its own schedule from its own round count
+      const int r = qround[q];
+      want = sched.r[r < sched.n ? r : sched.n - 1];
+      if (lane == 0) qround[q] = r + 1;
+    }
+    c = cascade_query(q, N, lbs, order, dfo, leaf_n, want, b.tau[q], b, lane);
+  }
   // one atomic per counter and work-group
   if (lane == 0) {
-    stat[0][wave] = lbp;
-    stat[1][wave] = fp;
-    stat[2][wave] = cnt;
-    stat[3][wave] = series;
+    stat[0][wave] = c.lbp;
+    stat[1][wave] = c.fp;
+    stat[2][wave] = c.cnt;
+    stat[3][wave] = c.series;
   }
   __syncthreads();
   if (threadIdx.x < 4) {
@@ -340,7 +355,8 @@ __global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b
 // `dedupe`, a row met twice (a rescan of a leaf already merged) is kept once.
 __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int KM, int C, int check_cert,
                                                      int dedupe, RoundBufs b, const int64_t *__restrict__ rowid,
-                                                     int64_t *out_ids, float *out_d, FilterPairArgs fp) {
+                                                     int64_t *out_ids, float *out_d, FilterPairArgs fp,
+                                                     CascadeArgs cs) {
   extern __shared__ unsigned char smem_raw[];
   // four wavefronts per work-group, each with its own LDS slice and query
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -350,7 +366,20 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
   const int per = (C - KM) / KM;  // items per pass
   const uint64_t lt = (1ull << lane) - 1ull;
   __shared__ int active_sh[4], fb_sh[4];
+  __shared__ int64_t cas_sh[4][4];  // the fused cascade's statistics per wavefront
   int active = 0, n_fb = 0;
+  CascadeCount cas;
+  if (cs.enabled) {
+    // the next round's control words start from zero (this merge queues no
+    // rescans and counts no active queries) and so do the fill counters
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      b.ctl[kCtlActive] = 0;
+      b.ctl[kCtlFallback] = 0;
+    }
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+      b.leaf_fill[i] = 0;
+  }
   for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
     int n_it = b.qitem_cnt[q];
     float tau_now = __builtin_inff();  // the query's tau after this merge (filter pairs below)
@@ -480,6 +509,15 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
           else fp.plist[static_cast<int64_t>(f) * nq + atomicAdd(fp.pcnt + f, 1)] = idx;
         }
     }
+    if (cs.enabled) {
+      // the next round's cascade for this query, from the tau just merged
+      if (n_it <= 0) tau_now = b.tau[q];
+      const CascadeCount c = cascade_query(q, N, cs.lbs, cs.order, cs.dfo, cs.leaf_n, cs.want, tau_now, b, lane);
+      cas.cnt += c.cnt;
+      cas.lbp += c.lbp;
+      cas.fp += c.fp;
+      cas.series += c.series;
+    }
     if (check_cert && b.cursor[q] < N) ++active;
   }
   // one atomic per work-group for the count of queries with leaves left and
@@ -487,8 +525,18 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
   if (lane == 0) {
     active_sh[wave] = active;
     fb_sh[wave] = n_fb;
+    cas_sh[0][wave] = cas.lbp;
+    cas_sh[1][wave] = cas.fp;
+    cas_sh[2][wave] = cas.cnt;
+    cas_sh[3][wave] = cas.series;
   }
   __syncthreads();
+  if (cs.enabled && threadIdx.x < 4) {
+    const int64_t v = cas_sh[threadIdx.x][0] + cas_sh[threadIdx.x][1] + cas_sh[threadIdx.x][2] + cas_sh[threadIdx.x][3];
+    const int word = threadIdx.x == 0 ? kCtlLbPruned : threadIdx.x == 1 ? kCtlFPruned
+                   : threadIdx.x == 2 ? kCtlScanned : kCtlSeries;
+    if (v) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + word), static_cast<unsigned long long>(v));
+  }
   if (check_cert && threadIdx.x == 0) {
     const int a = active_sh[0] + active_sh[1] + active_sh[2] + active_sh[3];
     const int f = fb_sh[0] + fb_sh[1] + fb_sh[2] + fb_sh[3];
@@ -640,7 +688,9 @@ void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
 }
 
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
-                        const int64_t *rowid, int64_t *ids, float *dists, const FilterPairArgs &fp) {
+                        const int64_t *rowid, int64_t *ids, float *dists, const FilterPairArgs &fp,
+                        const CascadeArgs &cs) {
+  if (cs.enabled && check_cert) fail(LEAFI_EINTERNAL, "query_merge: the fused cascade needs a merge without rescans");
   const int KM = pow2_at_least(kmax < 2 ? 2 : kmax);
   // LDS slice per wavefront: the running top-k plus up to 255 items' lists
   // (at most 256 entries unless 2 KM alone is larger)
@@ -651,7 +701,7 @@ void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedup
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_merge),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, KM, C, check_cert ? 1 : 0,
-                     dedupe ? 1 : 0, b, rowid, ids, dists, fp);
+                     dedupe ? 1 : 0, b, rowid, ids, dists, fp, cs);
   LAUNCH_OK("query_merge");
 }
 

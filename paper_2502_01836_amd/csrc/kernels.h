@@ -230,9 +230,20 @@ struct FilterPairArgs {
   int32_t *pcnt = nullptr;
   float *dfo = nullptr;
 };
+// With cs.enabled the merge then runs each query's prune cascade for the
+// next round from its new tau, as launch_worklist does (no separate launch;
+// only for a merge that queues no rescans, check_cert false).
+struct CascadeArgs {
+  int enabled = 0;
+  const float *lbs = nullptr;
+  const int32_t *order = nullptr;
+  const float *dfo = nullptr;  // null: no filter test
+  const int32_t *leaf_n = nullptr;
+  int want = 0;
+};
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
                         const int64_t *rowid = nullptr, int64_t *ids = nullptr, float *dists = nullptr,
-                        const FilterPairArgs &fp = FilterPairArgs());
+                        const FilterPairArgs &fp = FilterPairArgs(), const CascadeArgs &cs = CascadeArgs());
 
 // Final outputs: ids (original series ids) and Euclidean distances.
 void launch_finalize(int64_t nq, int kmax, const int64_t *rowid, RoundBufs b, int64_t *ids, float *dists,
