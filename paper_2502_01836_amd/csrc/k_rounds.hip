@@ -297,22 +297,25 @@ __global__ void __launch_bounds__(1024) k_first_round_layout(int64_t nq, int N, 
                                                              const int64_t *__restrict__ leaf_off,
                                                              const int32_t *__restrict__ leaf_n, int mq,
                                                              int64_t row_bytes, RoundBufs b) {
-  extern __shared__ int32_t s_lds[];  // [N] counts, then [N] item starts
+  extern __shared__ int32_t s_lds[];  // [N] counts (then fill counters), [N] item starts
   int32_t *s_cnt = s_lds, *s_ist = s_lds + N;
   __shared__ int64_t sh[16];
   for (int i = threadIdx.x; i < N; i += blockDim.x) s_cnt[i] = 0;
   __syncthreads();
   for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) atomicAdd(s_cnt + order[q * N], 1);
   __syncthreads();
-  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, true, true, s_ist, s_cnt);
+  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, true, false, s_ist, s_cnt);
   // series in the round's items: sum over leaves of count x real rows
   int64_t series = 0;
   for (int i = threadIdx.x; i < N; i += blockDim.x) series += static_cast<int64_t>(s_cnt[i]) * leaf_n[i];
   int64_t tot_series;
-  block_scan_excl<1024>(series, sh, tot_series);  // (its barriers also publish the fill zeroing)
+  block_scan_excl<1024>(series, sh, tot_series);
+  // the counts are consumed: they become the LDS fill counters of the placement
+  for (int i = threadIdx.x; i < N; i += blockDim.x) s_cnt[i] = 0;
+  __syncthreads();
   for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
     const int L = order[q * N];
-    const int slot = s_ist[L] + atomicAdd(b.leaf_fill + L, 1);
+    const int slot = s_ist[L] + atomicAdd(s_cnt + L, 1);
     b.item_q[slot] = static_cast<int32_t>(q);
     b.item_leaf[slot] = L;
     b.qitem_leaf[q * N] = L;

@@ -594,6 +594,11 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
         d64[e] = inb ? pd : __builtin_inf();
         r64[e] = inb ? row : 0xffffffffu;
       }
+    } else if (!bf16) {
+      // FP32 scan items: the candidates' keys already hold FP32
+      // direct-difference values (same error bound), ascending
+      for (int e = lane; e < PK; e += kWave) k32[e] = e < nc ? buf[e] : kKeyMax;
+      wave_lds_sync();
     } else {
       for (int e0 = 0; e0 < PK; e0 += CB) {
         const int e = e0 + cb;
@@ -623,6 +628,8 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
       }
       wave_lds_sync();
       wave_sort_u64(k32, PK, lane);
+    }
+    if (!(PK <= 8 && m <= 16 * GL)) {
       if (nc >= k) band = key_d2(k32[k - 1]) * (1.0f + 2.0f * delta32);
       for (int e = 0; e < nc; ++e) nb += key_d2(k32[e]) <= band ? 1 : 0;
       for (int e0 = 0; e0 < PK; e0 += CB) {
