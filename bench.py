@@ -232,6 +232,10 @@ def main():
         achieved = t_scan_bytes / (t_scan_ms * 1e-3) / 1e9 if t_scan_ms > 0 else 0.0
     n_series = n * nq
     pruned = 1.0 - sum(s["series_scanned"] for s in stats_all) / (len(stats_all) * n_series)
+    for s_, st in zip(wl["sigmas"], stats_all):
+        log(f"batch sigma={s_}: leaves scanned {st['leaves_scanned']}, bound-pruned {st['leaves_lb_pruned']}, "
+            f"filter-pruned {st['leaves_filter_pruned']}, filters evaluated {st['filter_evals']}, "
+            f"rescans {st['fallback_items']}")
 
     # plain FP32 per-query path on the same GPU (same filters and calibration)
     fp32 = None

@@ -252,6 +252,7 @@ typedef struct {
   double ms_total;
   double ms_scan;           /* time in the BF16 leaf-scan kernels (HIP events on the stream) */
   double scan_bytes;        /* unique leaf-store bytes the scan kernels had to read */
+  int64_t filter_evals;     /* (query, leaf) pairs whose learned filter was evaluated */
 } leafi_search_stats;
 
 /*

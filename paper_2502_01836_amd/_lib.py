@@ -67,7 +67,8 @@ class SearchStats(ctypes.Structure):
     _fields_ = [("leaves_scanned", ctypes.c_int64), ("leaves_lb_pruned", ctypes.c_int64),
                 ("leaves_filter_pruned", ctypes.c_int64), ("series_scanned", ctypes.c_int64),
                 ("fallback_items", ctypes.c_int64), ("rounds", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("ms_total", ctypes.c_double), ("ms_scan", ctypes.c_double), ("scan_bytes", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("ms_scan", ctypes.c_double), ("scan_bytes", ctypes.c_double),
+                ("filter_evals", ctypes.c_int64)]
 
 
 LEAFI_TUNE_MAX = 16

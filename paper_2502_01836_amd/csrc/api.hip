@@ -423,11 +423,10 @@ FilterPairArgs filter_pair_args(leafi_index *ix) {
   return fp;
 }
 
-void launch_round_worklist(leafi_index *ix, int64_t nq, int want, bool f_now, hipStream_t st) {
+void launch_round_worklist(leafi_index *ix, int64_t nq, int want, bool f_now, hipStream_t st, bool append) {
   Workspace &w = ix->ws;
-  const int F = ix->filt.F;
   launch_worklist(nq, ix->N, w.lbs.get(), w.order.get(), f_now ? w.dfo.get() : nullptr, ix->leaf_n.get(), want,
-                  views(w), st);
+                  views(w), st, nullptr, nullptr, append);
 }
 
 void stats_from_ctl(const leafi_index *ix, leafi_search_stats *stats) {
@@ -439,7 +438,10 @@ void stats_from_ctl(const leafi_index *ix, leafi_search_stats *stats) {
   stats->fallback_items += c[kCtlFbTotal];
   stats->rounds += static_cast<int32_t>(c[kCtlRounds]);
   stats->scan_bytes += static_cast<double>(c[kCtlScanBytes]);
+  stats->filter_evals += c[kCtlFEvals];
 }
+
+int planned_rounds(const SearchPlan &p);
 
 // Batched search of nq raw queries (Algorithm 2 in rounds), host-driven: the
 // counts of every round are read back, which sizes the buffers from actual
@@ -464,29 +466,39 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
   ro.row_bytes = scan_row_bytes(ix, p.bf16);
   ro.use_tau = true;
   bool filters_ready = false;
+  // A schedule that ends in 0 has a known last round: uncertified items of an
+  // earlier round are rescanned by the next round's scan, as the planned
+  // sequence does; otherwise (and after the last round) by an exact FP32 pass
+  // right away.
+  const int R = planned_rounds(p);
+  int64_t deferred = 0;  // rescans the last merge left queued for this round
   for (int r = 0;; ++r) {
     if (use_f && r > 0 && !filters_ready) {
       eval_filters(ix, nq, st);
       filters_ready = true;
     }
-    if (r > 0) reset_round(ix, st);
+    if (r > 0 && deferred == 0) reset_round(ix, st);
     const int want = p.schedule[std::min<size_t>(r, p.schedule.size() - 1)];
-    launch_round_worklist(ix, nq, want, use_f && filters_ready, st);
-    const int64_t bound = nq * static_cast<int64_t>(want == 0 ? N : std::min(want, N));
+    launch_round_worklist(ix, nq, want, use_f && filters_ready, st, deferred > 0);
+    const int64_t bound = nq * static_cast<int64_t>(want == 0 ? N : std::min(want, N)) + deferred;
     int64_t items = scan_round(ix, nq, p.bf16, p.kprime, p.kmax, st, stats ? &tm : nullptr, bound, &ro);
     if (items == 0) break;
-    launch_query_merge(nq, N, p.kmax, true, false, views(w), st);
+    launch_query_merge(nq, N, p.kmax, true, r > 0, views(w), st);
     read_ctl(ix, st);
     if (w.h_ctl[kCtlItems] == 0) break;
     add_scan_time(ix, stats ? &tm : nullptr);
     const int64_t active = w.h_ctl[kCtlActive];
     const int64_t n_fb = w.h_ctl[kCtlFallback];
+    deferred = 0;
     if (n_fb > 0) {
       // the merge left each query's rescan list in its item list
-      if (scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, n_fb) != 0)
+      if (R > 0 && r < R - 1) {
+        deferred = n_fb;
+      } else if (scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, n_fb) != 0) {
         launch_query_merge(nq, N, p.kmax, false, true, views(w), st);
+      }
     }
-    if (active == 0) break;
+    if (active == 0 && deferred == 0) break;
   }
   launch_finalize(nq, p.kmax, ix->rowid.get(), views(w), ids, dists, st);
   if (stats) {
@@ -506,9 +518,12 @@ int planned_rounds(const SearchPlan &p) {
   return 0;
 }
 
+// Items of round r: its own leaves plus the rescans the previous round left
+// (at most that round's items), never more than one per (query, leaf).
 int64_t planned_bound(const leafi_index *ix, int64_t nq, const SearchPlan &p, int r) {
   const int want = p.schedule[r];
-  return nq * static_cast<int64_t>(want == 0 ? ix->N : std::min(want, ix->N));
+  const int64_t own = nq * static_cast<int64_t>(want == 0 ? ix->N : std::min(want, ix->N));
+  return std::min(nq * static_cast<int64_t>(ix->N), own + (r > 0 ? planned_bound(ix, nq, p, r - 1) : 0));
 }
 
 // Whether a batch can run as a planned sequence: a bounded number of rounds
@@ -559,19 +574,19 @@ void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_
 }
 
 // The whole batch as a fixed launch sequence with no host read-back: each
-// round is the prune cascade, scan, rerank and merge, then an exact rescan
-// pass of the uncertified items whose size is read on the device (empty
-// passes exit at once).  With `timed`, per-round events bracket the scan.
-// Launches saved against that plain sequence (results are the same):
+// round is the prune cascade, scan, rerank and merge; the items a merge
+// could not certify are rescanned by the next round's scan (its cascade
+// appends the round's own leaves after them), and after the last round by an
+// exact FP32 pass whose size is read on the device (an empty pass exits at
+// once).  With `timed`, per-round events bracket the scan.  Launches saved
+// against that plain sequence (results are the same):
 //  * a first round of one leaf per query takes each query's first leaf in
 //    its visit order (tau is +inf, no filter is evaluated yet): its layout
 //    emits it, with no prune cascade launch;
 //  * the filter pairs need only an upper bound of tau (a larger tau selects
 //    a superset, and every pair it adds is pruned by its bound anyway), so
 //    the first round's merge selects them from its own new tau, and their
-//    inference runs right after it, before the rescan pass;
-//  * each rescan pass's merge (which queues no rescans) then runs every
-//    query's prune cascade for the next round from the final tau.
+//    inference runs right after it.
 void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
                      const SearchPlan &p, bool use_f, int64_t *ids, float *dists, bool timed, hipStream_t st) {
   Workspace &w = ix->ws;
@@ -580,10 +595,10 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
   begin_batch(ix, raw, nq, k_dev, t_dev, p, use_f, st);
   const int R = planned_rounds(p);
   // No reset launches: the prune cascade zeroes the round's control words and
-  // every merge leaves the per-leaf and per-query item counts at zero.
+  // every merge leaves the per-leaf item counts at its queued rescans.
   for (int r = 0; r < R; ++r) {
     const bool first_leaf = r == 0 && p.schedule[0] == 1 && ix->N <= kLayoutLdsMax;
-    if (r == 0 && !first_leaf) launch_round_worklist(ix, nq, p.schedule[r], false, st);
+    if (r == 0 && !first_leaf) launch_round_worklist(ix, nq, p.schedule[r], false, st, false);
     const int64_t bnd = planned_bound(ix, nq, p, r);
     RoundOpts ro;
     ro.may_read = false;
@@ -595,29 +610,22 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
       ro.ev_end = w.sev[2 * r + 1];
     }
     scan_round(ix, nq, true, p.kprime, p.kmax, st, nullptr, bnd, &ro);
-    const bool filters_next = use_f && r == 0 && R > 1;
-    launch_query_merge(nq, N, p.kmax, true, false, views(w), st, nullptr, nullptr, nullptr,
+    const bool last = r == R - 1;
+    const bool filters_next = use_f && r == 0 && !last;
+    // rounds after the first may rescan a row the previous round merged
+    launch_query_merge(nq, N, p.kmax, true, r > 0, views(w), st, nullptr, nullptr, nullptr,
                        filters_next ? filter_pair_args(ix) : FilterPairArgs());
     if (filters_next) infer_filter_pairs(ix, nq, st);
+    if (!last) {
+      launch_round_worklist(ix, nq, p.schedule[r + 1], use_f, st, true);
+      continue;
+    }
+    // exact rescan pass over the lists the last merge left, then the output rows
     RoundOpts rf;
     rf.may_read = false;
     rf.small = true;
-    // rescan pass over the lists the merge left (empty lists: the pass exits at once)
     scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bnd, &rf);
-    // the last merge of the batch also writes the output rows; the others
-    // run the next round's prune cascade
-    const bool last = r == R - 1;
-    CascadeArgs cs;
-    if (!last) {
-      cs.enabled = 1;
-      cs.lbs = w.lbs.get();
-      cs.order = w.order.get();
-      cs.dfo = use_f ? w.dfo.get() : nullptr;
-      cs.leaf_n = ix->leaf_n.get();
-      cs.want = p.schedule[r + 1];
-    }
-    launch_query_merge(nq, N, p.kmax, false, true, views(w), st, last ? ix->rowid.get() : nullptr,
-                       last ? ids : nullptr, last ? dists : nullptr, FilterPairArgs(), cs);
+    launch_query_merge(nq, N, p.kmax, false, true, views(w), st, ix->rowid.get(), ids, dists);
   }
 }
 

@@ -45,35 +45,41 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
   const float *b1 = W1 + static_cast<int64_t>(h) * m;
   const float *w2 = b1 + h;
   const float b2 = w2[h];
-  __syncthreads();  // the previous tile's readers of xs / red / qrow are done
-  if (tid < kMlpQ) qrow[tid] = r0 + tid < nrows ? qidx(r0 + tid) : -1;
-  __syncthreads();
-  // wavefront w stages rows w, w + 4, ... with 16-byte loads (m is a
-  // multiple of 4 and x 16-byte aligned, so every row, in x and in the
-  // padded tile, starts 16-byte aligned); all of a lane's loads are in
-  // flight before the first store
-  constexpr int kRowsPerWave = kMlpQ / 4;
-  for (int i4 = lane; 4 * i4 < m; i4 += kWave) {
-    float4 v[kRowsPerWave];
-#pragma unroll
-    for (int rr = 0; rr < kRowsPerWave; ++rr) {
-      const int64_t rq = qrow[wave + 4 * rr];
-      v[rr] = reinterpret_cast<const float4 *>(x + (rq < 0 ? 0 : rq) * m)[i4];
-    }
-#pragma unroll
-    for (int rr = 0; rr < kRowsPerWave; ++rr) {
-      const bool live = qrow[wave + 4 * rr] >= 0;
-      reinterpret_cast<float4 *>(xs + (wave + 4 * rr) * S)[i4] = live ? v[rr] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-  }
-  __syncthreads();
   const int c = lane & 15, kq = lane >> 4;
   float part[kMlpQB];
 #pragma unroll
   for (int qb = 0; qb < kMlpQB; ++qb) part[qb] = 0.0f;
+  // The tile's query rows into LDS (every thread, once: called after the
+  // first block's weights are requested, so the two latencies overlap).
+  // Wavefront w stages rows w, w + 4, ... with 16-byte loads (m is a
+  // multiple of 4 and x 16-byte aligned, so every row, in x and in the
+  // padded tile, starts 16-byte aligned); all of a lane's loads are in
+  // flight before the first store.
+  auto stage = [&]() {
+    __syncthreads();  // the previous tile's readers of xs / red / qrow are done
+    if (tid < kMlpQ) qrow[tid] = r0 + tid < nrows ? qidx(r0 + tid) : -1;
+    __syncthreads();
+    constexpr int kRowsPerWave = kMlpQ / 4;
+    for (int i4 = lane; 4 * i4 < m; i4 += kWave) {
+      float4 v[kRowsPerWave];
+#pragma unroll
+      for (int rr = 0; rr < kRowsPerWave; ++rr) {
+        const int64_t rq = qrow[wave + 4 * rr];
+        v[rr] = reinterpret_cast<const float4 *>(x + (rq < 0 ? 0 : rq) * m)[i4];
+      }
+#pragma unroll
+      for (int rr = 0; rr < kRowsPerWave; ++rr) {
+        const bool live = qrow[wave + 4 * rr] >= 0;
+        reinterpret_cast<float4 *>(xs + (wave + 4 * rr) * S)[i4] = live ? v[rr] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+    }
+    __syncthreads();
+  };
   for (int jb = 0; jb < h; jb += 256) {
     const int jw = jb + 64 * wave;  // this wavefront's first hidden unit
-    if (jw >= h) continue;          // uniform across the wavefront
+    // (a wavefront past h still takes part in the staging below; its loads
+    // are clamped into the weights and its products are skipped)
+    const bool live = jw < h;  // uniform across the wavefront
     floatx4 acc[4][kMlpQB];
     int col[4];
 #pragma unroll
@@ -138,6 +144,10 @@ __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h
       load_a(av0, 0);
       load_a(av1, 1);
       load_a(av2, 2);
+    }
+    if (jb == 0) stage();
+    if (!live) continue;  // no work-group barrier below in this iteration
+    if (steps > 0) {
       int sidx = 0;
       // scheduling barriers keep the prefetches ahead of the products (the
       // compiler would otherwise sink the loads to where they are used)

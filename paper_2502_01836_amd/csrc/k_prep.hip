@@ -288,6 +288,135 @@ __global__ void __launch_bounds__(256) k_query_setup(const float *__restrict__ r
   }
 }
 
+// k_query_setup with one wavefront per query (four per work-group) for up to
+// kSetupWaveMaxN leaves: the same arithmetic in the same order (so the same
+// values), with no work-group barrier on a query's path.  The row is read
+// once into registers; the visit order comes from each key's rank among the
+// query's N keys (distinct, since the leaf id breaks ties), written straight
+// to its sorted position.
+constexpr int kSetupWaveMaxN = 256;
+constexpr int kSetupMaxPerLane = 1024 / kWave;  // row values per lane (m <= 1024)
+
+template <int J>  // keys per lane: N <= 64 J
+__device__ inline void rank_and_write(const uint64_t *keys, int N, int lane, int32_t *order_q, float *lbs_q) {
+  uint64_t mk[J];
+  int rk[J];
+#pragma unroll
+  for (int c = 0; c < J; ++c) {
+    const int i = lane + kWave * c;
+    mk[c] = i < N ? keys[i] : kKeyMax;
+    rk[c] = 0;
+  }
+  for (int j = 0; j < N; ++j) {
+    const uint64_t kj = keys[j];
+#pragma unroll
+    for (int c = 0; c < J; ++c) rk[c] += kj < mk[c] ? 1 : 0;
+  }
+#pragma unroll
+  for (int c = 0; c < J; ++c)
+    if (lane + kWave * c < N) {
+      order_q[rk[c]] = static_cast<int32_t>(key_row(mk[c]));
+      lbs_q[rk[c]] = key_d2(mk[c]);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_query_setup_wave(const float *__restrict__ raw, int64_t nq, int m, int S,
+                                                          const float *__restrict__ boxes, int N, int slice64,
+                                                          float *q32, uint16_t *q16, float *qn16, float *qeps,
+                                                          float *qstat, float *lb, int32_t *order, float *lbs,
+                                                          const int32_t *__restrict__ k_dev,
+                                                          const float *__restrict__ t_dev, int n_pairs,
+                                                          const int32_t *__restrict__ pair_k,
+                                                          const float *__restrict__ pair_t, int kmax, RoundBufs b,
+                                                          int F, int32_t *pcnt) {
+  extern __shared__ uint64_t smem[];  // per wavefront: keys [N], zs [m], st [S][2] (floats)
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  uint64_t *keys = smem + static_cast<size_t>(w) * slice64;
+  float *zs = reinterpret_cast<float *>(keys + N);
+  float *st = zs + m;
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < kCtlCount; i += blockDim.x) b.ctl[i] = 0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) b.leaf_cnt[i] = 0;
+    if (pcnt)
+      for (int i = threadIdx.x; i < F; i += blockDim.x) pcnt[i] = 0;
+  }
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + w;
+  if (q >= nq) return;  // no work-group barrier below
+  const float *r = raw + q * m;
+  float rv[kSetupMaxPerLane];
+#pragma unroll
+  for (int c = 0; c < kSetupMaxPerLane; ++c) {
+    const int t = lane + kWave * c;
+    rv[c] = t < m ? r[t] : 0.0f;
+  }
+  // FP64 mean and population std (row_moments' order of operations)
+  double sum = 0.0;
+#pragma unroll
+  for (int c = 0; c < kSetupMaxPerLane; ++c)
+    if (lane + kWave * c < m) sum += static_cast<double>(rv[c]);
+  sum = wave_sum(sum);
+  const double mu = sum / m;
+  double var = 0.0;
+#pragma unroll
+  for (int c = 0; c < kSetupMaxPerLane; ++c)
+    if (lane + kWave * c < m) {
+      const double d = static_cast<double>(rv[c]) - mu;
+      var += d * d;
+    }
+  var = wave_sum(var);
+  const double sd = sqrt(var / m);
+  float nrm = 0.0f, err = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kSetupMaxPerLane; ++c) {
+    const int t = lane + kWave * c;
+    if (t < m) {
+      const float z = normalise(rv[c], mu, sd);
+      const uint16_t bb = f32_to_bf16(z);
+      const float zb = bf16_to_f32(bb);
+      zs[t] = z;
+      q32[q * m + t] = z;
+      q16[q * m + t] = bb;
+      nrm = fmaf(zb, zb, nrm);
+      const float e = z - zb;
+      err = fmaf(e, e, err);
+    }
+  }
+  nrm = wave_sum(nrm);
+  err = wave_sum(err);
+  if (lane == 0) {
+    qn16[q] = nrm;
+    qeps[q] = sqrtf(err) * (1.0f + 1e-5f);
+    const int k = min(max(k_dev[q], 1), kmax);
+    b.pair[q] = select_pair_of(k, t_dev[q], n_pairs, pair_k, pair_t);
+    b.kq[q] = k;
+    b.cursor[q] = 0;
+    b.tau[q] = __builtin_inff();
+    b.res_cnt[q] = 0;
+    b.qitem_cnt[q] = 0;
+  }
+  wave_lds_sync();
+  for (int s = lane; s < S; s += kWave) {
+    float a, c;
+    segment_moments(zs, m, S, s, a, c);
+    st[2 * s] = a;
+    st[2 * s + 1] = c;
+    qstat[(q * S + s) * 2 + 0] = a;
+    qstat[(q * S + s) * 2 + 1] = c;
+  }
+  wave_lds_sync();
+  for (int i = lane; i < N; i += kWave) {
+    const float v = summary_lb(st, boxes + static_cast<int64_t>(i) * S * 4, S, m);
+    lb[q * N + i] = v;
+    keys[i] = make_key(v, static_cast<uint32_t>(i));
+  }
+  wave_lds_sync();
+  int32_t *oq = order + q * N;
+  float *lq = lbs + q * N;
+  if (N <= kWave) rank_and_write<1>(keys, N, lane, oq, lq);
+  else if (N <= 2 * kWave) rank_and_write<2>(keys, N, lane, oq, lq);
+  else rank_and_write<4>(keys, N, lane, oq, lq);
+}
+
 // One work-group per query: bitonic sort of (lb bits, leaf id) keys in LDS.
 __global__ void __launch_bounds__(256) k_order(const float *__restrict__ lb, int N, int P, int32_t *order,
                                                float *lbs, const int32_t *__restrict__ slots) {
@@ -369,6 +498,17 @@ void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float 
                         int n_pairs, const int32_t *pair_k, const float *pair_t, int kmax, RoundBufs b, int F,
                         int32_t *pcnt, hipStream_t st) {
   if (nq <= 0) return;
+  if (N <= kSetupWaveMaxN && m <= kSetupMaxPerLane * kWave) {
+    const int slice64 = N + (m + 2 * S + 1) / 2;  // keys, then zs and st in 8-byte units
+    const size_t lds_w = 4 * static_cast<size_t>(slice64) * sizeof(uint64_t);
+    if (lds_w > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_setup_wave),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_w)));
+    hipLaunchKernelGGL(k_query_setup_wave, dim3(static_cast<unsigned>(ceil_div(nq, 4))), dim3(256), lds_w, st, raw, nq,
+                       m, S, boxes, N, slice64, q32, q16, qn16, qeps, qstat, lb, order, lbs, k_dev, t_dev, n_pairs,
+                       pair_k, pair_t, kmax, b, F, pcnt);
+    LAUNCH_OK("query_setup");
+    return;
+  }
   const int P = pow2_at_least(N < 2 ? 2 : N);
   const size_t lds = static_cast<size_t>(P) * sizeof(uint64_t) + (static_cast<size_t>(m) + 2 * S) * sizeof(float);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_setup),

@@ -26,12 +26,13 @@ struct CascadeCount {
 };
 
 // The cascade of query q (one wavefront) from its cursor with the given tau:
-// emits its surviving leaves into qitem_leaf, counts them per leaf and
+// emits its surviving leaves into qitem_leaf after the `base` entries already
+// queued there (rescans of the previous round), counts them per leaf and
 // advances its cursor.
 __device__ inline CascadeCount cascade_query(int64_t q, int N, const float *__restrict__ lbs,
                                              const int32_t *__restrict__ order, const float *__restrict__ dfo,
                                              const int32_t *__restrict__ leaf_n, int want, float tau, RoundBufs &b,
-                                             int lane) {
+                                             int lane, int base) {
   CascadeCount c;
   int pos = b.cursor[q];
   if (pos < N) {
@@ -69,7 +70,7 @@ __device__ inline CascadeCount cascade_query(int64_t q, int N, const float *__re
       const uint64_t mend = end >= kWave ? ~0ull : ((1ull << end) - 1ull);
       if ((msurv >> lane) & 1ull) {
         const int rank = __popcll(msurv & lt);
-        b.qitem_leaf[q * N + c.cnt + rank] = L;
+        b.qitem_leaf[q * N + base + c.cnt + rank] = L;
         atomicAdd(b.leaf_cnt + L, 1);
         c.series += leaf_n[L];
       }
@@ -90,7 +91,7 @@ __device__ inline CascadeCount cascade_query(int64_t q, int N, const float *__re
   c.series = wave_sum(c.series);
   if (lane == 0) {
     b.cursor[q] = pos;
-    b.qitem_cnt[q] = c.cnt;
+    b.qitem_cnt[q] = base + c.cnt;
   }
   return c;
 }
@@ -99,7 +100,8 @@ __global__ void __launch_bounds__(64 * kListWaves) k_worklist(int64_t nq, int N,
                                                              const int32_t *__restrict__ order,
                                                              const float *__restrict__ dfo,
                                                              const int32_t *__restrict__ leaf_n, int want,
-                                                             Schedule sched, int32_t *qround, RoundBufs b) {
+                                                             Schedule sched, int32_t *qround, RoundBufs b,
+                                                             int append) {
   __shared__ int64_t stat[4][kListWaves];
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   // the round's control words start from zero (nothing reads them during
@@ -117,7 +119,8 @@ __global__ void __launch_bounds__(64 * kListWaves) k_worklist(int64_t nq, int N,
       want = sched.r[r < sched.n ? r : sched.n - 1];
       if (lane == 0) qround[q] = r + 1;
     }
-    c = cascade_query(q, N, lbs, order, dfo, leaf_n, want, b.tau[q], b, lane);
+    // with `append`, the rescans the last merge queued stay first in the list
+    c = cascade_query(q, N, lbs, order, dfo, leaf_n, want, b.tau[q], b, lane, append ? b.qitem_cnt[q] : 0);
   }
   // one atomic per counter and work-group
   if (lane == 0) {
@@ -154,7 +157,12 @@ __global__ void __launch_bounds__(256) k_filter_pairs(int64_t nq, int N, const f
   if (qround && qround[q] != 1) return;  // serving: only queries that just finished their first round
   if (pos < b.cursor[q] || b.pair[q] < 0) return;
   const int f = filt_of_leaf[order[idx]];
-  if (f < 0 || lbs[idx] > b.tau[q] * (1.0f + kLbSlack)) {
+  const bool sel = !(f < 0 || lbs[idx] > b.tau[q] * (1.0f + kLbSlack));
+  // one count per wavefront of the pairs it queues
+  const uint64_t mk = __ballot(sel);
+  if ((threadIdx.x & (kWave - 1)) == __builtin_ctzll(__ballot(1)))
+    atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFEvals), static_cast<unsigned long long>(__popcll(mk)));
+  if (!sel) {
     dfo[idx] = -__builtin_inff();
     return;
   }
@@ -352,14 +360,16 @@ __global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b
 // One wavefront per query: merge the round's item results into the running
 // top-k (sorted by (FP64 distance, row)), refresh tau and, in a regular
 // round, queue every item whose certificate bound does not exceed the new tau
-// for an exact FP32 rescan.  The running top-k and as many items as fit the
+// for a rescan (by the next round's scan, or an exact FP32 pass after the
+// last round).  The running top-k and as many items as fit the
 // wavefront's LDS slice of C entries (KM slots per item) are gathered at once
 // and sorted together, so a query with many items needs few passes.  With
 // `dedupe`, a row met twice (a rescan of a leaf already merged) is kept once.
+constexpr int kMergePreFp = 4;  // visit positions per lane whose filter-pair inputs the merge prefetches
+
 __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int KM, int C, int check_cert,
                                                      int dedupe, RoundBufs b, const int64_t *__restrict__ rowid,
-                                                     int64_t *out_ids, float *out_d, FilterPairArgs fp,
-                                                     CascadeArgs cs) {
+                                                     int64_t *out_ids, float *out_d, FilterPairArgs fp) {
   extern __shared__ unsigned char smem_raw[];
   // four wavefronts per work-group, each with its own LDS slice and query
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -368,30 +378,53 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
   uint32_t *tags = reinterpret_cast<uint32_t *>(mine + sizeof(double) * C);
   const int per = (C - KM) / KM;  // items per pass
   const uint64_t lt = (1ull << lane) - 1ull;
-  __shared__ int active_sh[4], fb_sh[4];
-  __shared__ int64_t cas_sh[4][4];  // the fused cascade's statistics per wavefront
-  int active = 0, n_fb = 0;
-  CascadeCount cas;
-  if (cs.enabled) {
-    // the next round's control words start from zero (this merge queues no
-    // rescans and counts no active queries) and so do the fill counters
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      b.ctl[kCtlActive] = 0;
-      b.ctl[kCtlFallback] = 0;
-    }
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-      b.leaf_fill[i] = 0;
-  }
+  __shared__ int active_sh[4], fb_sh[4], fe_sh[4];
+  int active = 0, n_fb = 0, n_fe = 0;  // n_fe: this lane's queued filter pairs
   for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
-    int n_it = b.qitem_cnt[q];
+    // Loads that do not depend on the merge are issued before it, so that
+    // the query's chain of dependent global loads stays short: the filter-pair
+    // inputs of this lane's visit positions (N <= 64 kMergePreFp) and the
+    // certificate inputs of the query's first 64 items.
+    const int n_it = b.qitem_cnt[q];
+    const int k = b.kq[q];
+    const int have = b.res_cnt[q];
+    const bool pre_fp = fp.plist && N <= kMergePreFp * kWave;
+    int cur = 0, pq = -1;
+    if (fp.plist) {
+      cur = b.cursor[q];
+      pq = b.pair[q];
+    }
+    int pf[kMergePreFp];
+    float pl[kMergePreFp];
+#pragma unroll
+    for (int c = 0; c < kMergePreFp; ++c) {
+      pf[c] = -1;
+      pl[c] = __builtin_inff();
+      const int pos = lane + kWave * c;
+      if (pre_fp && pos < N) {
+        const int64_t idx = q * N + pos;
+        pl[c] = fp.lbs[idx];
+        pf[c] = fp.filt_of_leaf[fp.order[idx]];
+      }
+    }
+    float cb = __builtin_inff();
+    int cl = 0;
+    if (check_cert && lane < n_it) {
+      const int idx = b.qitem_idx[q * N + lane];
+      cb = b.item_bound[idx];
+      cl = b.item_leaf[idx];
+    }
     float tau_now = __builtin_inff();  // the query's tau after this merge (filter pairs below)
     if (n_it > 0) {
-      int k = b.kq[q];
-      int have = b.res_cnt[q];
       for (int i = lane; i < KM; i += kWave) {
-        vals[i] = i < have ? b.res_d2[q * kmax + i] : __builtin_inf();
-        tags[i] = i < have ? static_cast<uint32_t>(b.res_row[q * kmax + i]) : 0xffffffffu;
+        double v = __builtin_inf();
+        uint32_t t = 0xffffffffu;
+        if (i < kmax) {  // loaded unconditionally, kept below `have`
+          v = b.res_d2[q * kmax + i];
+          t = static_cast<uint32_t>(b.res_row[q * kmax + i]);
+        }
+        vals[i] = i < have ? v : __builtin_inf();
+        tags[i] = i < have ? t : 0xffffffffu;
       }
       for (int it0 = 0; it0 < n_it; it0 += per) {
         const int nb = n_it - it0 < per ? n_it - it0 : per;
@@ -400,11 +433,15 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
           const int j = e / KM, i = e - j * KM;
           double v = __builtin_inf();
           uint32_t t = 0xffffffffu;
-          if (j < nb) {
+          if (j < nb && i < kmax) {
+            // the item's count and values in parallel, kept below the count
             const int idx = b.qitem_idx[q * N + it0 + j];
-            if (i < b.item_cnt[idx]) {
-              v = b.item_d2[static_cast<int64_t>(idx) * kmax + i];
-              t = static_cast<uint32_t>(b.item_row[static_cast<int64_t>(idx) * kmax + i]);
+            const int ic = b.item_cnt[idx];
+            const double vv = b.item_d2[static_cast<int64_t>(idx) * kmax + i];
+            const uint32_t tt = static_cast<uint32_t>(b.item_row[static_cast<int64_t>(idx) * kmax + i]);
+            if (i < ic) {
+              v = vv;
+              t = tt;
             }
           }
           vals[KM + e] = v;
@@ -469,9 +506,14 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
           bool un = false;
           int L = 0;
           if (it < n_it) {
-            const int idx = b.qitem_idx[q * N + it];
-            un = !(b.item_bound[idx] > tau);
-            L = b.item_leaf[idx];
+            if (it0 == 0) {
+              un = !(cb > tau);
+              L = cl;
+            } else {
+              const int idx = b.qitem_idx[q * N + it];
+              un = !(b.item_bound[idx] > tau);
+              L = b.item_leaf[idx];
+            }
           }
           const uint64_t mu = __ballot(un);
           if (un) {
@@ -503,42 +545,50 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
       // the query's filter pairs for the rounds to come (k_filter_pairs'
       // selection, from the tau just merged)
       if (n_it <= 0) tau_now = b.tau[q];
-      const int cur = b.cursor[q];
-      if (b.pair[q] >= 0)
-        for (int pos = cur + lane; pos < N; pos += kWave) {
-          const int64_t idx = q * N + pos;
-          const int f = fp.filt_of_leaf[fp.order[idx]];
-          if (f < 0 || fp.lbs[idx] > tau_now * (1.0f + kLbSlack)) fp.dfo[idx] = -__builtin_inff();
-          else fp.plist[static_cast<int64_t>(f) * nq + atomicAdd(fp.pcnt + f, 1)] = idx;
+      if (pq >= 0) {
+        if (pre_fp) {
+#pragma unroll
+          for (int c = 0; c < kMergePreFp; ++c) {
+            const int pos = lane + kWave * c;
+            if (pos >= cur && pos < N) {
+              const int64_t idx = q * N + pos;
+              const int f = pf[c];
+              if (f < 0 || pl[c] > tau_now * (1.0f + kLbSlack)) {
+                fp.dfo[idx] = -__builtin_inff();
+              } else {
+                fp.plist[static_cast<int64_t>(f) * nq + atomicAdd(fp.pcnt + f, 1)] = idx;
+                ++n_fe;
+              }
+            }
+          }
+        } else {
+          for (int pos = cur + lane; pos < N; pos += kWave) {
+            const int64_t idx = q * N + pos;
+            const int f = fp.filt_of_leaf[fp.order[idx]];
+            if (f < 0 || fp.lbs[idx] > tau_now * (1.0f + kLbSlack)) {
+              fp.dfo[idx] = -__builtin_inff();
+            } else {
+              fp.plist[static_cast<int64_t>(f) * nq + atomicAdd(fp.pcnt + f, 1)] = idx;
+              ++n_fe;
+            }
+          }
         }
-    }
-    if (cs.enabled) {
-      // the next round's cascade for this query, from the tau just merged
-      if (n_it <= 0) tau_now = b.tau[q];
-      const CascadeCount c = cascade_query(q, N, cs.lbs, cs.order, cs.dfo, cs.leaf_n, cs.want, tau_now, b, lane);
-      cas.cnt += c.cnt;
-      cas.lbp += c.lbp;
-      cas.fp += c.fp;
-      cas.series += c.series;
+      }
     }
     if (check_cert && b.cursor[q] < N) ++active;
   }
-  // one atomic per work-group for the count of queries with leaves left and
-  // for the rescan items
+  // one atomic per work-group for the count of queries with leaves left, for
+  // the rescan items and for the queued filter pairs
+  if (fp.plist) n_fe = wave_sum(n_fe);
   if (lane == 0) {
+    fe_sh[wave] = n_fe;
     active_sh[wave] = active;
     fb_sh[wave] = n_fb;
-    cas_sh[0][wave] = cas.lbp;
-    cas_sh[1][wave] = cas.fp;
-    cas_sh[2][wave] = cas.cnt;
-    cas_sh[3][wave] = cas.series;
   }
   __syncthreads();
-  if (cs.enabled && threadIdx.x < 4) {
-    const int64_t v = cas_sh[threadIdx.x][0] + cas_sh[threadIdx.x][1] + cas_sh[threadIdx.x][2] + cas_sh[threadIdx.x][3];
-    const int word = threadIdx.x == 0 ? kCtlLbPruned : threadIdx.x == 1 ? kCtlFPruned
-                   : threadIdx.x == 2 ? kCtlScanned : kCtlSeries;
-    if (v) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + word), static_cast<unsigned long long>(v));
+  if (fp.plist && threadIdx.x == 0) {
+    const int e = fe_sh[0] + fe_sh[1] + fe_sh[2] + fe_sh[3];
+    if (e) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFEvals), static_cast<unsigned long long>(e));
   }
   if (check_cert && threadIdx.x == 0) {
     const int a = active_sh[0] + active_sh[1] + active_sh[2] + active_sh[3];
@@ -626,11 +676,11 @@ __global__ void __launch_bounds__(256) k_collect_done(int64_t n_slots, int N, in
 
 void launch_worklist(int64_t nq, int N, const float *lbs, const int32_t *order, const float *dfo,
                      const int32_t *leaf_n, int want, RoundBufs b, hipStream_t st, const Schedule *sched,
-                     int32_t *qround) {
+                     int32_t *qround, bool append) {
   Schedule sc{};
   if (sched) sc = *sched;
   hipLaunchKernelGGL(k_worklist, dim3(ceil_div(std::max<int64_t>(nq, 1), kListWaves)), dim3(64 * kListWaves), 0, st,
-                     nq, N, lbs, order, dfo, leaf_n, want, sc, qround, b);
+                     nq, N, lbs, order, dfo, leaf_n, want, sc, qround, b, append ? 1 : 0);
   LAUNCH_OK("worklist");
 }
 
@@ -691,9 +741,7 @@ void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
 }
 
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
-                        const int64_t *rowid, int64_t *ids, float *dists, const FilterPairArgs &fp,
-                        const CascadeArgs &cs) {
-  if (cs.enabled && check_cert) fail(LEAFI_EINTERNAL, "query_merge: the fused cascade needs a merge without rescans");
+                        const int64_t *rowid, int64_t *ids, float *dists, const FilterPairArgs &fp) {
   const int KM = pow2_at_least(kmax < 2 ? 2 : kmax);
   // LDS slice per wavefront: the running top-k plus up to 255 items' lists
   // (at most 256 entries unless 2 KM alone is larger)
@@ -704,7 +752,7 @@ void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedup
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_merge),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, KM, C, check_cert ? 1 : 0,
-                     dedupe ? 1 : 0, b, rowid, ids, dists, fp, cs);
+                     dedupe ? 1 : 0, b, rowid, ids, dists, fp);
   LAUNCH_OK("query_merge");
 }
 

@@ -103,7 +103,8 @@ enum Ctl : int {
   kCtlFbTotal = 8 * kCtlStride,     // uncertified items rescanned, over the batch
   kCtlScanBytes = 9 * kCtlStride,   // unique leaf-store bytes the regular rounds read
   kCtlRounds = 10 * kCtlStride,     // regular rounds with at least one item
-  kCtlCount = 11 * kCtlStride,
+  kCtlFEvals = 11 * kCtlStride,     // (query, leaf) pairs queued for filter inference
+  kCtlCount = 12 * kCtlStride,
   kCtlRoundWords = kCtlFallback + 1  // words a round starts from zero (items .. fallback)
 };
 
@@ -147,9 +148,12 @@ struct Schedule {
 // count, which the kernel advances.
 // lbs and dfo are [nq, N] in visit order: the summary bound and (filters
 // active) the filter's pruning value d^f - o, -inf where no filter applies.
+// With `append` the emitted leaves follow the rescans the last merge queued
+// in each query's item list (counted in qitem_cnt and leaf_cnt), so this
+// round's scan also rescans them.
 void launch_worklist(int64_t nq, int N, const float *lbs, const int32_t *order, const float *dfo,
                      const int32_t *leaf_n, int want, RoundBufs b, hipStream_t st, const Schedule *sched = nullptr,
-                     int32_t *qround = nullptr);
+                     int32_t *qround = nullptr, bool append = false);
 
 // (query, visit position) pairs whose filter test a later round can reach,
 // grouped by filter into plist [F, nq] (entries q * N + position) with counts
@@ -230,20 +234,9 @@ struct FilterPairArgs {
   int32_t *pcnt = nullptr;
   float *dfo = nullptr;
 };
-// With cs.enabled the merge then runs each query's prune cascade for the
-// next round from its new tau, as launch_worklist does (no separate launch;
-// only for a merge that queues no rescans, check_cert false).
-struct CascadeArgs {
-  int enabled = 0;
-  const float *lbs = nullptr;
-  const int32_t *order = nullptr;
-  const float *dfo = nullptr;  // null: no filter test
-  const int32_t *leaf_n = nullptr;
-  int want = 0;
-};
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
                         const int64_t *rowid = nullptr, int64_t *ids = nullptr, float *dists = nullptr,
-                        const FilterPairArgs &fp = FilterPairArgs(), const CascadeArgs &cs = CascadeArgs());
+                        const FilterPairArgs &fp = FilterPairArgs());
 
 // Final outputs: ids (original series ids) and Euclidean distances.
 void launch_finalize(int64_t nq, int kmax, const int64_t *rowid, RoundBufs b, int64_t *ids, float *dists,

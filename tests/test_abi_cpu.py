@@ -51,7 +51,7 @@ def test_struct_sizes_match_header_layout():
     from paper_2502_01836_amd import _lib
     assert ctypes.sizeof(_lib.BuildOpts) == 16
     assert ctypes.sizeof(_lib.SearchOpts) == 4 * 4 + 8 * 4 + 4 + 3 * 4
-    assert ctypes.sizeof(_lib.SearchStats) == 5 * 8 + 2 * 4 + 3 * 8
+    assert ctypes.sizeof(_lib.SearchStats) == 5 * 8 + 2 * 4 + 3 * 8 + 8
     assert ctypes.sizeof(_lib.Info) == 8 + 6 * 4 + 8 + 8
 
 

@@ -148,6 +148,7 @@ def test_exact_search_matches_bruteforce(rw20k, rw20k_leafknn, scan, schedule, k
         assert st["leaves_scanned"] == int(r.scanned.sum())
         assert st["leaves_lb_pruned"] == int(r.lb_pruned.sum())
     assert st["leaves_filter_pruned"] == 0
+    assert st["filter_evals"] == 0
     if scan == "bf16":
         # the bf16 candidate certificate holds for nearly every (query, leaf) item
         assert st["fallback_items"] <= 0.05 * st["leaves_scanned"] + 1, st
@@ -328,6 +329,10 @@ def test_trained_filters_reach_the_recall_target(rw20k):
     recall = (got_d[:, 0] <= want_d[:, 0] * (1 + 1e-5)).mean()
     assert recall >= 0.9, recall
     assert st["leaves_filter_pruned"] > 0
+    # every filter-pruned leaf had its filter evaluated; an evaluated leaf is
+    # later pruned (by its filter, or by its bound once tau has dropped) or scanned
+    assert st["leaves_filter_pruned"] <= st["filter_evals"]
+    assert st["filter_evals"] <= st["leaves_filter_pruned"] + st["leaves_lb_pruned"] + st["leaves_scanned"]
 
 
 def test_partial_last_chunk_with_large_kprime():
