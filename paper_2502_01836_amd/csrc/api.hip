@@ -387,7 +387,7 @@ struct SearchPlan {
 void begin_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
                  const SearchPlan &p, bool use_f, hipStream_t st) {
   Workspace &w = ix->ws;
-  launch_query_setup(raw, nq, ix->m, ix->S, ix->boxes.get(), ix->N, w.q32.get(), w.q16.get(), w.qn16.get(),
+  launch_query_setup(raw, nq, ix->m, ix->S, ix->boxes.get(), ix->boxes_t.get(), ix->N, w.q32.get(), w.q16.get(), w.qn16.get(),
                      w.qeps.get(), w.qstat.get(), w.lb.get(),
                      w.order.get(), w.lbs.get(), k_dev, t_dev, use_f ? ix->cal.pairs() : 0,
                      use_f ? ix->cal.pair_k.get() : nullptr, use_f ? ix->cal.pair_t.get() : nullptr, p.kmax,
@@ -661,7 +661,8 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
                         static_cast<const void *>(w.plist.get()), static_cast<const void *>(w.pcnt.get()),
                         static_cast<const void *>(w.dfo.get()), static_cast<const void *>(w.lbs.get()),
                         static_cast<const void *>(w.order.get()), static_cast<const void *>(w.qstat.get()),
-                        static_cast<const void *>(ix->boxes.get()), static_cast<const void *>(ix->rowid.get()),
+                        static_cast<const void *>(ix->boxes.get()), static_cast<const void *>(ix->boxes_t.get()),
+                        static_cast<const void *>(ix->rowid.get()),
                         static_cast<const void *>(ix->filt.w.get()), static_cast<const void *>(ix->filt.filt_of_leaf.get()),
                         static_cast<const void *>(ix->cal.offsets.get()), static_cast<const void *>(ix->cal.pair_k.get()),
                         static_cast<const void *>(ix->cal.pair_t.get()), static_cast<const void *>(w.ptile.get())})
@@ -920,6 +921,7 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     ix->leaf_off.alloc(N + 1);
     ix->leaf_n.alloc(N);
     ix->boxes.alloc(boxes.size());
+    ix->boxes_t.alloc(boxes.size());
     ix->leaf_eps.alloc(N);
     DevBuf<int64_t> dsrc(rows);
     DevBuf<int32_t> dleaf(rows);
@@ -933,6 +935,10 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     h2d(ix->leaf_off.get(), off.data(), N + 1, st);
     h2d(ix->leaf_n.get(), ln32.data(), N, st);
     h2d(ix->boxes.get(), boxes.data(), boxes.size(), st);
+    std::vector<float> boxes_t(boxes.size());
+    for (int L = 0; L < N; ++L)
+      for (int j = 0; j < 4 * S; ++j) boxes_t[static_cast<size_t>(j) * N + L] = boxes[(static_cast<size_t>(L) * S) * 4 + j];
+    h2d(ix->boxes_t.get(), boxes_t.data(), boxes_t.size(), st);
     HIP_OK(hipStreamSynchronize(st));
     ix->n = n;
     ix->m = m;
@@ -964,7 +970,7 @@ int leafi_get_info(const leafi_index *ix, leafi_info *out) {
     out->n_calibrated = ix->cal.pairs();
     out->padded_rows = ix->rows;
     out->device_bytes = static_cast<int64_t>(ix->x32.bytes() + ix->x16.bytes() + ix->xn16.bytes() + ix->rowid.bytes() +
-                                             ix->leaf_off.bytes() + ix->leaf_n.bytes() + ix->boxes.bytes() +
+                                             ix->leaf_off.bytes() + ix->leaf_n.bytes() + ix->boxes.bytes() + ix->boxes_t.bytes() +
                                              ix->leaf_eps.bytes() + ix->filt.w.bytes() + ix->cal.offsets.bytes());
   });
 }

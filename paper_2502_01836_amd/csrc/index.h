@@ -145,6 +145,7 @@ struct leafi_index {
   int64_t total_chunks_for(int chunk) const { return chunks_total[leafi::chunk_log(chunk)]; }
   // leaf store (device)
   leafi::DevBuf<float> x32, xn16, boxes, leaf_eps;
+  leafi::DevBuf<float> boxes_t;  // the boxes as [S][4][N]: one value of every leaf, contiguous
   leafi::DevBuf<uint16_t> x16;
   leafi::DevBuf<int64_t> rowid, leaf_off;
   leafi::DevBuf<int32_t> leaf_n;

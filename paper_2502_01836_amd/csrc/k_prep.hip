@@ -297,6 +297,25 @@ __global__ void __launch_bounds__(256) k_query_setup(const float *__restrict__ r
 constexpr int kSetupWaveMaxN = 256;
 constexpr int kSetupMaxPerLane = 1024 / kWave;  // row values per lane (m <= 1024)
 
+// summary_lb of leaf L from the boxes laid out as [S][4][N] (a wavefront's
+// lanes, one leaf each, read consecutive words), with the segment count
+// fixed at compile time: the same operations in the same order, so the same
+// value.
+template <int kS>
+__device__ __forceinline__ float summary_lb_t(const float *qs, const float *__restrict__ bt, int N, int L, int m) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int s = 0; s < kS; ++s) {
+    const float *b = bt + static_cast<int64_t>(4 * s) * N + L;
+    float len = static_cast<float>(((s + 1) * m) / kS - (s * m) / kS);
+    float mq = qs[2 * s], sq = qs[2 * s + 1];
+    float gm = fmaxf(fmaxf(b[0] - mq, mq - b[N]), 0.0f);
+    float gs = fmaxf(fmaxf(b[2 * N] - sq, sq - b[3 * N]), 0.0f);
+    acc += len * (gm * gm + gs * gs);
+  }
+  return sqrtf(acc);
+}
+
 template <int J>  // keys per lane: N <= 64 J
 __device__ inline void rank_and_write(const uint64_t *keys, int N, int lane, int32_t *order_q, float *lbs_q) {
   uint64_t mk[J];
@@ -307,6 +326,7 @@ __device__ inline void rank_and_write(const uint64_t *keys, int N, int lane, int
     mk[c] = i < N ? keys[i] : kKeyMax;
     rk[c] = 0;
   }
+#pragma unroll 8
   for (int j = 0; j < N; ++j) {
     const uint64_t kj = keys[j];
 #pragma unroll
@@ -320,8 +340,23 @@ __device__ inline void rank_and_write(const uint64_t *keys, int N, int lane, int
     }
 }
 
+// The calibrated (k, target) row of a query, found by its whole wavefront
+// (k and t are uniform across it): the first pair that matches, as
+// select_pair_of, with 64 pairs tested per step instead of one.
+__device__ inline int select_pair_wave(int k, float t, int n_pairs, const int32_t *__restrict__ pair_k,
+                                       const float *__restrict__ pair_t, int lane) {
+  if (!(t < 1.0f)) return -1;
+  for (int base = 0; base < n_pairs; base += kWave) {
+    const int i = base + lane;
+    const uint64_t hit = __ballot(i < n_pairs && pair_k[i] == k && pair_t[i] == t);
+    if (hit) return base + __builtin_ctzll(hit);
+  }
+  return -1;
+}
+
 __global__ void __launch_bounds__(256) k_query_setup_wave(const float *__restrict__ raw, int64_t nq, int m, int S,
-                                                          const float *__restrict__ boxes, int N, int slice64,
+                                                          const float *__restrict__ boxes,
+                                                          const float *__restrict__ boxes_t, int N, int slice64,
                                                           float *q32, uint16_t *q16, float *qn16, float *qeps,
                                                           float *qstat, float *lb, int32_t *order, float *lbs,
                                                           const int32_t *__restrict__ k_dev,
@@ -386,13 +421,18 @@ __global__ void __launch_bounds__(256) k_query_setup_wave(const float *__restric
   if (lane == 0) {
     qn16[q] = nrm;
     qeps[q] = sqrtf(err) * (1.0f + 1e-5f);
-    const int k = min(max(k_dev[q], 1), kmax);
-    b.pair[q] = select_pair_of(k, t_dev[q], n_pairs, pair_k, pair_t);
-    b.kq[q] = k;
     b.cursor[q] = 0;
     b.tau[q] = __builtin_inff();
     b.res_cnt[q] = 0;
     b.qitem_cnt[q] = 0;
+  }
+  {
+    const int k = min(max(k_dev[q], 1), kmax);
+    const int pr = select_pair_wave(k, t_dev[q], n_pairs, pair_k, pair_t, lane);
+    if (lane == 0) {
+      b.pair[q] = pr;
+      b.kq[q] = k;
+    }
   }
   wave_lds_sync();
   for (int s = lane; s < S; s += kWave) {
@@ -405,7 +445,8 @@ __global__ void __launch_bounds__(256) k_query_setup_wave(const float *__restric
   }
   wave_lds_sync();
   for (int i = lane; i < N; i += kWave) {
-    const float v = summary_lb(st, boxes + static_cast<int64_t>(i) * S * 4, S, m);
+    const float v = S == 16 ? summary_lb_t<16>(st, boxes_t, N, i, m)
+                            : summary_lb(st, boxes + static_cast<int64_t>(i) * S * 4, S, m);
     lb[q * N + i] = v;
     keys[i] = make_key(v, static_cast<uint32_t>(i));
   }
@@ -493,7 +534,8 @@ void launch_order(const float *lb, int64_t nq, int N, int32_t *order, float *lbs
   LAUNCH_OK("order");
 }
 
-void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float *boxes, int N, float *q32,
+void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float *boxes, const float *boxes_t, int N,
+                        float *q32,
                         uint16_t *q16, float *qn16, float *qeps, float *qstat, float *lb, int32_t *order, float *lbs, const int32_t *k_dev, const float *t_dev,
                         int n_pairs, const int32_t *pair_k, const float *pair_t, int kmax, RoundBufs b, int F,
                         int32_t *pcnt, hipStream_t st) {
@@ -504,7 +546,7 @@ void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float 
     if (lds_w > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_setup_wave),
                                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_w)));
     hipLaunchKernelGGL(k_query_setup_wave, dim3(static_cast<unsigned>(ceil_div(nq, 4))), dim3(256), lds_w, st, raw, nq,
-                       m, S, boxes, N, slice64, q32, q16, qn16, qeps, qstat, lb, order, lbs, k_dev, t_dev, n_pairs,
+                       m, S, boxes, boxes_t, N, slice64, q32, q16, qn16, qeps, qstat, lb, order, lbs, k_dev, t_dev, n_pairs,
                        pair_k, pair_t, kmax, b, F, pcnt);
     LAUNCH_OK("query_setup");
     return;

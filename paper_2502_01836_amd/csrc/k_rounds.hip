@@ -305,24 +305,37 @@ __global__ void __launch_bounds__(1024) k_first_round_layout(int64_t nq, int N, 
                                                              const int64_t *__restrict__ leaf_off,
                                                              const int32_t *__restrict__ leaf_n, int mq,
                                                              int64_t row_bytes, RoundBufs b) {
-  extern __shared__ int32_t s_lds[];  // [N] counts (then fill counters), [N] item starts
+  // [N] counts (then fill counters), [N] item starts, [N + 1] leaf offsets
+  // (int64, 8-byte aligned: 2 N ints before them, N even or padded), [N] leaf sizes
+  extern __shared__ int32_t s_lds[];
   int32_t *s_cnt = s_lds, *s_ist = s_lds + N;
+  int64_t *s_off = reinterpret_cast<int64_t *>(s_lds + 2 * N + (N & 1));
+  int32_t *s_n = reinterpret_cast<int32_t *>(s_off + N + 1);
   __shared__ int64_t sh[16];
-  for (int i = threadIdx.x; i < N; i += blockDim.x) s_cnt[i] = 0;
+  // every global input requested at once: the leaves' offsets and sizes
+  // into LDS and each thread's first query's first leaf into a register
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    s_cnt[i] = 0;
+    s_off[i] = leaf_off[i];
+    s_n[i] = leaf_n[i];
+  }
+  if (threadIdx.x == 0) s_off[N] = leaf_off[N];
+  const int L0 = threadIdx.x < nq ? order[static_cast<int64_t>(threadIdx.x) * N] : 0;
   __syncthreads();
-  for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) atomicAdd(s_cnt + order[q * N], 1);
+  if (threadIdx.x < nq) atomicAdd(s_cnt + L0, 1);
+  for (int64_t q = threadIdx.x + blockDim.x; q < nq; q += blockDim.x) atomicAdd(s_cnt + order[q * N], 1);
   __syncthreads();
-  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, true, false, s_ist, s_cnt);
+  leaf_scan_body(N, s_off, mq, row_bytes, b, sh, true, false, s_ist, s_cnt);
   // series in the round's items: sum over leaves of count x real rows
   int64_t series = 0;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) series += static_cast<int64_t>(s_cnt[i]) * leaf_n[i];
+  for (int i = threadIdx.x; i < N; i += blockDim.x) series += static_cast<int64_t>(s_cnt[i]) * s_n[i];
   int64_t tot_series;
   block_scan_excl<1024>(series, sh, tot_series);
   // the counts are consumed: they become the LDS fill counters of the placement
   for (int i = threadIdx.x; i < N; i += blockDim.x) s_cnt[i] = 0;
   __syncthreads();
   for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
-    const int L = order[q * N];
+    const int L = q == threadIdx.x ? L0 : order[q * N];
     const int slot = s_ist[L] + atomicAdd(s_cnt + L, 1);
     b.item_q[slot] = static_cast<int32_t>(q);
     b.item_leaf[slot] = L;
@@ -714,8 +727,13 @@ void launch_leaf_scan(int N, const int64_t *leaf_off, int mq, int64_t row_bytes,
 void launch_first_round_layout(int64_t nq, int N, const int32_t *order, const int64_t *leaf_off,
                                const int32_t *leaf_n, int mq, int64_t row_bytes, RoundBufs b, hipStream_t st) {
   if (N > kLayoutLdsMax) fail(LEAFI_EINTERNAL, "first_round_layout: too many leaves");
-  hipLaunchKernelGGL(k_first_round_layout, dim3(1), dim3(1024), 2 * static_cast<size_t>(N) * sizeof(int32_t), st, nq,
-                     N, order, leaf_off, leaf_n, mq, row_bytes, b);
+  // counts, starts, (padding,) offsets, sizes: at most 80 KiB for 4,096 leaves
+  const size_t lds = (2 * static_cast<size_t>(N) + (N & 1)) * sizeof(int32_t) +
+                     (static_cast<size_t>(N) + 1) * sizeof(int64_t) + static_cast<size_t>(N) * sizeof(int32_t);
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_first_round_layout),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(k_first_round_layout, dim3(1), dim3(1024), lds, st, nq, N, order, leaf_off, leaf_n, mq,
+                     row_bytes, b);
   LAUNCH_OK("first_round_layout");
 }
 

@@ -130,8 +130,8 @@ struct QueryView {
 // query): the results of launch_qprep, launch_lb, launch_order and
 // launch_select_pairs plus the search state (cursor 0, tau +inf, no results,
 // no items); work-group 0 zeroes the control words, leaf counts and (pcnt
-// non-null) F filter-pair counts.
-void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float *boxes, int N, float *q32,
+// non-null) F filter-pair counts.  boxes_t holds the boxes as [S][4][N].
+void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float *boxes, const float *boxes_t, int N, float *q32,
                         uint16_t *q16, float *qn16, float *qeps, float *qstat, float *lb, int32_t *order, float *lbs, const int32_t *k_dev, const float *t_dev,
                         int n_pairs, const int32_t *pair_k, const float *pair_t, int kmax, RoundBufs b, int F,
                         int32_t *pcnt, hipStream_t st);
