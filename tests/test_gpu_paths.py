@@ -157,3 +157,40 @@ def test_autotune_keeps_results_identical(env):
     env["ix"].set_tiling(1024, 32)
     with pytest.raises(pkg.LeafiError):
         env["ix"].set_tiling(1000, 32)
+
+
+def test_deferred_rescans_agree_and_stay_exact(env):
+    """With k' = k every first-round item fails its certificate (its k'-th
+    candidate is the k-th result itself), so the whole first round is rescanned
+    by the second round's scan, and what fails again by the final FP32 pass.
+    The three paths agree bit for bit, and the answer is the exact k-NN of the
+    FP64 oracle."""
+    pkg = env["pkg"]
+    qd = torch.from_numpy(env["q"][1]).cuda()
+    k = 10
+    # a graph is replayed only for the buffer addresses it was captured with
+    nq = len(env["ks"])
+    kd = torch.full((nq,), k, dtype=torch.int32, device="cuda")
+    td = torch.ones(nq, dtype=torch.float32, device="cuda")
+    out = (torch.empty((nq, k), dtype=torch.int64, device="cuda"),
+           torch.empty((nq, k), dtype=torch.float32, device="cuda"))
+    res = []
+    for flags in (pkg.SEARCH_HOST_ROUNDS, pkg.SEARCH_NO_GRAPH, 0, 0, 0):
+        ids, d, st = env["ix"].search(qd, k=kd, target=td, k_max=k, use_filters=False, schedule=(1, 0), kprime=k,
+                                      with_stats=True, flags=flags, out=out)
+        torch.cuda.synchronize()
+        res.append((ids.clone(), d.clone(), st))
+    assert [r[2]["path"] for r in res][:2] == [0, 1] and res[-1][2]["path"] == 2
+    for ids, d, st in res[1:]:
+        assert torch.equal(ids, res[0][0]) and torch.equal(d, res[0][1])
+        for c in COUNTS:
+            assert st[c] == res[0][2][c], (c, st[c], res[0][2][c])
+    assert res[0][2]["fallback_items"] >= len(env["ks"])  # every first-round item, at least
+    xs, qs = O.znorm(env["raw"]), O.znorm(env["q"][1])
+    want_ids, want_d = O.knn(xs, qs, k)
+    got_ids, got_d = res[-1][0].cpu().numpy(), res[-1][1].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got_d - want_d) <= 1e-5 * want_d)
+    for a, b in zip(*np.nonzero(got_ids != want_ids)):
+        # a different id only where another row is (numerically) as close
+        dg = np.sqrt(((xs[got_ids[a, b]].astype(np.float64) - qs[a]) ** 2).sum())
+        assert abs(dg - want_d[a, b]) <= 1e-5 * want_d[a, b]
