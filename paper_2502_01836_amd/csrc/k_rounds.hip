@@ -254,12 +254,14 @@ __global__ void __launch_bounds__(1024) k_leaf_scan_scatter(int64_t nq, int N, c
                                                             int mq, int64_t row_bytes, RoundBufs b, int lds_starts) {
   extern __shared__ int32_t s_ist[];  // [N] with lds_starts, else unused
   __shared__ int64_t sh[16];
+  // each thread's first query's item count, requested before the leaf scan
+  const int n0 = threadIdx.x < nq ? b.qitem_cnt[threadIdx.x] : 0;
   leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, true, true, lds_starts ? s_ist : nullptr);
   __syncthreads();  // item starts written; the per-leaf counts are consumed
   const int32_t *ist = lds_starts ? s_ist : b.leaf_istart;
   for (int i = threadIdx.x; i < N; i += blockDim.x) b.leaf_cnt[i] = 0;
   for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
-    const int n = b.qitem_cnt[q];
+    const int n = q == threadIdx.x ? n0 : b.qitem_cnt[q];
     for (int r = 0; r < n; ++r) {
       const int L = b.qitem_leaf[q * N + r];
       const int slot = ist[L] + atomicAdd(b.leaf_fill + L, 1);
@@ -279,14 +281,20 @@ __global__ void __launch_bounds__(1024) k_layout_scatter(int64_t nq, int N, cons
                                                          int mq, int64_t row_bytes, RoundBufs b) {
   extern __shared__ int32_t s_ist[];  // [N]
   __shared__ int64_t sh[16];
-  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, blockIdx.x == 0, false, s_ist);
-  __syncthreads();
+  // the wavefront's query's item list is requested before the leaf scan, so
+  // its latency hides under the scan's
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  int n = 0, L0 = 0;
+  if (q < nq) {
+    n = b.qitem_cnt[q];
+    if (lane < n) L0 = b.qitem_leaf[q * N + lane];
+  }
+  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, blockIdx.x == 0, false, s_ist);
+  __syncthreads();
   if (q >= nq) return;
-  const int n = b.qitem_cnt[q];
   for (int r = lane; r < n; r += kWave) {
-    const int L = b.qitem_leaf[q * N + r];
+    const int L = r == lane ? L0 : b.qitem_leaf[q * N + r];
     const int slot = s_ist[L] + atomicAdd(b.leaf_fill + L, 1);
     b.item_q[slot] = static_cast<int32_t>(q);
     b.item_leaf[slot] = L;

@@ -438,6 +438,41 @@ constexpr int kSelectPerLane = 16;
 
 // One wavefront per item.  LDS: merged keys [P], then per candidate the fp32
 // key, FP64 distance and row.
+// The kprime smallest of an item's n chunk-list keys into buf (ascending,
+// kKeyMax past the last real key): kprime rounds of a wavefront minimum over
+// the keys above the previous one (keys are unique), U per lane in registers
+// (unconditional loads of clamped entries, so all of a lane's loads are in
+// flight together; n >= kprime >= 1, so entry 0 exists; n <= 64 U).
+template <int U>
+__device__ inline void select_keys(const uint64_t *__restrict__ cand, int64_t t0, int G, int g, int mq, int j,
+                                   int kprime, int n, int lane, uint64_t *buf) {
+  uint64_t mine[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = lane + u * kWave;
+    const int ec = e < n ? e : 0;
+    const int c = ec / kprime;
+    const uint64_t v = cand[((t0 + static_cast<int64_t>(c) * G + g) * mq + j) * kprime + (ec - c * kprime)];
+    mine[u] = e < n ? v : kKeyMax;
+  }
+  uint64_t prev = 0;
+  bool first = true;
+  for (int r = 0; r < kprime; ++r) {
+    uint64_t lo = kKeyMax;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if ((first || mine[u] > prev) && mine[u] < lo) lo = mine[u];
+    lo = wave_min_u64(lo);
+    if (lane == 0) buf[r] = lo;
+    prev = lo;
+    first = false;
+    if (lo == kKeyMax) {  // no keys left: the rest stay empty
+      for (int e = r + 1 + lane; e < kprime; e += kWave) buf[e] = kKeyMax;
+      break;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
                                                      int kmax, int bf16, int PB, int slice_u64,
                                                      const uint64_t *__restrict__ cand) {
@@ -474,36 +509,12 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
     const int G = (ist1 - ist0 + mq - 1) / mq;
     int n = C * kprime;
     if (kprime <= kSelectMax && n <= kWave * kSelectPerLane) {
-      // few keys wanted from many: kprime rounds of a wavefront minimum over
-      // the keys above the previous one (keys are unique), held in registers
-      // (unconditional loads of clamped entries, so all of a lane's loads
-      // are in flight together; n >= kprime >= 1, so entry 0 exists)
-      uint64_t mine[kSelectPerLane];
+      // few keys wanted from many: kprime rounds of a wavefront minimum, each
+      // lane holding as few registers as n needs
       const int64_t t0 = b.tile_start[L];
-#pragma unroll
-      for (int u = 0; u < kSelectPerLane; ++u) {
-        const int e = lane + u * kWave;
-        const int ec = e < n ? e : 0;
-        const int c = ec / kprime;
-        const uint64_t v = cand[((t0 + static_cast<int64_t>(c) * G + g) * mq + j) * kprime + (ec - c * kprime)];
-        mine[u] = e < n ? v : kKeyMax;
-      }
-      uint64_t prev = 0;
-      bool first = true;
-      for (int r = 0; r < kprime; ++r) {
-        uint64_t lo = kKeyMax;
-#pragma unroll
-        for (int u = 0; u < kSelectPerLane; ++u)
-          if ((first || mine[u] > prev) && mine[u] < lo) lo = mine[u];
-        lo = wave_min_u64(lo);
-        if (lane == 0) buf[r] = lo;
-        prev = lo;
-        first = false;
-        if (lo == kKeyMax) {  // no keys left: the rest stay empty
-          for (int e = r + 1 + lane; e < kprime; e += kWave) buf[e] = kKeyMax;
-          break;
-        }
-      }
+      if (n <= kWave) select_keys<1>(cand, t0, G, g, mq, j, kprime, n, lane, buf);
+      else if (n <= 4 * kWave) select_keys<4>(cand, t0, G, g, mq, j, kprime, n, lane, buf);
+      else select_keys<kSelectPerLane>(cand, t0, G, g, mq, j, kprime, n, lane, buf);
       wave_lds_sync();
     } else {
       int P = pow2_at_least(n < 2 ? 2 : n);
