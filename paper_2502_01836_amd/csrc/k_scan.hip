@@ -142,11 +142,21 @@ __device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int
   if (kprime <= kListSelectMax) {
     uint64_t prev = 0, mine = kKeyMax;  // lane r keeps the r-th smallest
     int keep = 0;
+    // a list of up to 128 keys is read into registers once (two per lane)
+    // instead of once per round
+    const bool regs = c <= 2 * kWave;
+    const uint64_t v0 = regs && lane < c ? lst[lane] : kKeyMax;
+    const uint64_t v1 = regs && lane + kWave < c ? lst[lane + kWave] : kKeyMax;
     for (int r = 0; r < kprime; ++r) {
       uint64_t lo = kKeyMax;
-      for (int e = lane; e < c; e += kWave) {
-        const uint64_t v = lst[e];
-        if ((r == 0 || v > prev) && v < lo) lo = v;
+      if (regs) {
+        if ((r == 0 || v0 > prev) && v0 < lo) lo = v0;
+        if ((r == 0 || v1 > prev) && v1 < lo) lo = v1;
+      } else {
+        for (int e = lane; e < c; e += kWave) {
+          const uint64_t v = lst[e];
+          if ((r == 0 || v > prev) && v < lo) lo = v;
+        }
       }
       lo = wave_min_u64(lo);
       if (lo == kKeyMax) break;  // fewer than kprime keys (uniform)
