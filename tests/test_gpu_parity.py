@@ -134,7 +134,7 @@ def test_leaf_knn_matches_oracle(rw20k, rw20k_leafknn, k):
 # --------------------------------------------------------------------------- exact search
 
 @pytest.mark.parametrize("scan", ["bf16", "fp32"])
-@pytest.mark.parametrize("schedule", [(1,), (1, 0), (3,)])
+@pytest.mark.parametrize("schedule", [(1,), (1, 0), (3,), (2, 0), (1, 2, 0)])
 @pytest.mark.parametrize("k", [1, 10])
 def test_exact_search_matches_bruteforce(rw20k, rw20k_leafknn, scan, schedule, k):
     ix = rw20k["ix"]
