@@ -244,7 +244,10 @@ typedef struct {
   int64_t leaves_lb_pruned;
   int64_t leaves_filter_pruned;
   int64_t series_scanned;   /* real series in scanned leaves */
-  int64_t fallback_items;   /* (query, leaf) pairs re-scanned exactly in FP32 */
+  int64_t fallback_items;   /* (query, leaf) pairs whose candidates could not certify the
+                               top k: rescanned by the next round's scan when the schedule
+                               ends in 0 and has one, else exactly in FP32 (each rescan
+                               counts once) */
   int32_t rounds;           /* regular rounds that scanned at least one leaf */
   int32_t path;             /* how the batch ran: 0 host-driven rounds (counts read back
                                every round), 1 planned launch sequence, 2 replay of a
@@ -266,7 +269,8 @@ typedef struct {
  * Execution: with the BF16 scan and a schedule that contains a 0 (so every
  * query ends within that many rounds), the batch runs as a fixed launch
  * sequence that reads nothing back (buffers sized from the per-round upper
- * bound nq * min(R, n_leaves), if that fits 8 GiB).  The second call with the
+ * bound nq * min(R, n_leaves) plus the previous round's rescans, at most
+ * nq * n_leaves, if that fits 8 GiB).  The second call with the
  * same shape, options and buffer addresses captures that sequence in a HIP
  * graph, and later identical calls replay it (the graph reads the current
  * contents of the caller's buffers).  Other cases run host-driven rounds.
