@@ -23,18 +23,22 @@ namespace {
 // query and across the wavefronts in a fixed order, so the result of a
 // (query, filter) pair does not depend on which tile or batch holds it.
 constexpr int kMlpQ = 32;             // queries per tile
-constexpr int kMlpQB = kMlpQ / 16;    // 16-query column blocks per tile
+constexpr int kMlpQBig = 64;          // queries per tile of a large pair batch (W1 read half as often)
 constexpr int kMlpXcds = 8;           // XCDs (separate L2 caches) per device
 
-// LDS: the query tile [kMlpQ][m + 4], the per-wavefront output sums
-// [4][kMlpQ], the tile's query rows [kMlpQ] (int64) and 8 ints for the
-// tile search and the tile-prefix scan.  (All carved from the dynamic block: a static __shared__
-// variable would move it off its 16-byte alignment.)
-size_t mlp_infer_lds(int m) { return (static_cast<size_t>(kMlpQ) * (m + 4) + 6 * kMlpQ + 8) * sizeof(float); }
+// LDS for tiles of up to Q queries: the query tile [Q][m + 4], the
+// per-wavefront output sums [4][Q], the tile's query rows [Q] (int64) and
+// 8 ints for the tile search and the tile-prefix scan.  (All carved from the
+// dynamic block: a static __shared__ variable would move it off its 16-byte
+// alignment.)
+__host__ __device__ constexpr size_t mlp_tile_floats(int m, int Q) { return static_cast<size_t>(Q) * (m + 4) + 6 * Q; }
+size_t mlp_infer_lds(int m, int Q = kMlpQ) { return (mlp_tile_floats(m, Q) + 8) * sizeof(float); }
 
-template <typename RowIdx, typename Out>
+template <int Q, typename RowIdx, typename Out>
 __device__ inline void mlp_tile(const float *__restrict__ w, int f, int m, int h, const float *__restrict__ x,
                                 int64_t r0, int64_t nrows, RowIdx qidx, Out out, float *xs) {
+  constexpr int kMlpQ = Q;              // queries per tile
+  constexpr int kMlpQB = Q / 16;        // 16-query column blocks per tile
   typedef float floatx4 __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int S = m + 4;
@@ -218,7 +222,8 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ 
   extern __shared__ float xs[];
   const int f = blockIdx.x;
   for (int64_t r0 = static_cast<int64_t>(blockIdx.y) * kMlpQ; r0 < nq; r0 += static_cast<int64_t>(gridDim.y) * kMlpQ)
-    mlp_tile(w, f, m, h, x, r0, nq, [](int64_t r) { return r; }, [=](int64_t r, int64_t, float v) { out[r * F + f] = v; }, xs);
+    mlp_tile<kMlpQ>(w, f, m, h, x, r0, nq, [](int64_t r) { return r; },
+                    [=](int64_t r, int64_t, float v) { out[r * F + f] = v; }, xs);
 }
 
 // Exclusive prefix of the filters' tile counts ceil(pcnt[f] / 16) (one
@@ -239,59 +244,35 @@ __global__ void __launch_bounds__(1024) k_mlp_tiles(int F, const int32_t *__rest
   if (tid == 0) tile_prefix[F] = total;
 }
 
-// Pruning values for listed pairs: filter f evaluates the entries
-// plist[f * stride + 0 .. pcnt[f]) (q * N + visit position) and writes
-// d^f - o for the query's calibrated (k, target) row.  A persistent grid
-// walks the non-empty tiles of all filters.
-__global__ void __launch_bounds__(256, 2) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
-                                                         const float *__restrict__ x,
-                                                         const int64_t *__restrict__ plist,
-                                                         const int32_t *__restrict__ pcnt, int64_t stride, int N,
-                                                         const int32_t *__restrict__ pair,
-                                                         const float *__restrict__ offsets,
-                                                         const int32_t *__restrict__ tile_prefix, float *dfo,
-                                                         int local_prefix) {
-  extern __shared__ float xs[];
-  int *ints = reinterpret_cast<int *>(xs + kMlpQ * (m + 4) + 6 * kMlpQ);
+// The persistent walk over the non-empty tiles of Q queries: tile t belongs
+// to the filter f with tile_prefix[f] <= t < tile_prefix[f + 1].  Work-groups
+// are dispatched to the 8 XCDs round-robin (blockIdx % 8), and each XCD has
+// its own L2.  Tiles are numbered filter by filter, so the work-groups of XCD
+// x take the contiguous eighth [x T / 8, (x + 1) T / 8) of the T tiles: a
+// filter's W1 is fetched into one or two L2s instead of all eight.  (Any grid
+// not a multiple of 8 walks the tiles in plain stride; either way every tile
+// is taken exactly once.)
+template <int Q>
+__device__ inline void infer_pair_tiles(const float *__restrict__ w, int F, int m, int h, const float *__restrict__ x,
+                                        const int64_t *__restrict__ plist, const int32_t *__restrict__ pcnt,
+                                        int64_t stride, int N, const int32_t *__restrict__ pair,
+                                        const float *__restrict__ offsets, const int32_t *tile_prefix, float *dfo,
+                                        float *xs, int *ints) {
   int &s_lo = ints[0];
   int &s_f = ints[1];
-  // With local_prefix every work-group computes the tile prefix itself (into
-  // LDS, F + 1 entries after 4 scan words): no separate launch for it.
-  if (local_prefix) {
-    int32_t *tp = ints + 8;
-    const int per = (F + blockDim.x - 1) / blockDim.x;
-    const int f0 = min(F, static_cast<int>(threadIdx.x) * per), f1 = min(F, f0 + per);
-    int sum = 0;
-    for (int f = f0; f < f1; ++f) sum += (pcnt[f] + kMlpQ - 1) / kMlpQ;
-    int tot;
-    int run = block_scan_excl<256>(sum, ints + 4, tot);
-    for (int f = f0; f < f1; ++f) {
-      tp[f] = run;
-      run += (pcnt[f] + kMlpQ - 1) / kMlpQ;
-    }
-    if (threadIdx.x == 0) tp[F] = tot;
-    __syncthreads();
-    tile_prefix = tp;
-  }
   const int total = tile_prefix[F];
   // filters per bucket of the two-level search (at most 64 for F <= 16384)
   const int B = (F + blockDim.x - 1) / blockDim.x;
-  // Work-groups are dispatched to the 8 XCDs round-robin (blockIdx % 8), and
-  // each XCD has its own L2.  Tiles are numbered filter by filter, so the
-  // work-groups of XCD x take the contiguous eighth [x T / 8, (x + 1) T / 8)
-  // of the T tiles: a filter's W1 is fetched into one or two L2s instead of
-  // all eight.  (Any grid not a multiple of 8 walks the tiles in plain
-  // stride; either way every tile is taken exactly once.)
   const bool by_xcd = gridDim.x % kMlpXcds == 0;
   const int xcd = blockIdx.x % kMlpXcds;
   const int t_lo = by_xcd ? static_cast<int>(static_cast<int64_t>(total) * xcd / kMlpXcds) : 0;
   const int t_hi = by_xcd ? static_cast<int>(static_cast<int64_t>(total) * (xcd + 1) / kMlpXcds) : total;
   const int t_step = by_xcd ? gridDim.x / kMlpXcds : gridDim.x;
   for (int t = t_lo + (by_xcd ? blockIdx.x / kMlpXcds : blockIdx.x); t < t_hi; t += t_step) {
-    // filter of tile t: the f with tile_prefix[f] <= t < tile_prefix[f + 1]
-    // (tile_prefix is non-decreasing, so exactly one f qualifies).  One
-    // thread per bucket of B filters finds the bucket, then one thread per
-    // filter of that bucket the filter: two dependent loads, not log2 F.
+    // filter of tile t (tile_prefix is non-decreasing, so exactly one f
+    // qualifies): one thread per bucket of B filters finds the bucket, then
+    // one thread per filter of that bucket the filter: two dependent loads,
+    // not log2 F
     __syncthreads();  // the previous tile's readers of s_lo / s_f are done
     {
       const int lo = threadIdx.x * B;
@@ -304,13 +285,63 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer_pairs(const float *__restr
     }
     __syncthreads();
     const int f = __builtin_amdgcn_readfirstlane(s_f);  // uniform: kept in scalar registers
-    const int64_t r0 = static_cast<int64_t>(t - tile_prefix[f]) * kMlpQ;
+    const int64_t r0 = static_cast<int64_t>(t - tile_prefix[f]) * Q;
     const int64_t *pl = plist + f * stride;
-    mlp_tile(
+    mlp_tile<Q>(
         w, f, m, h, x, r0, static_cast<int64_t>(pcnt[f]), [=](int64_t r) { return pl[r] / N; },
         [=](int64_t r, int64_t q, float v) { dfo[pl[r]] = v - offsets[static_cast<int64_t>(pair[q]) * F + f]; },
         xs);
   }
+}
+
+// Pruning values for listed pairs: filter f evaluates the entries
+// plist[f * stride + 0 .. pcnt[f]) (q * N + visit position) and writes
+// d^f - o for the query's calibrated (k, target) row.  A persistent grid
+// walks the non-empty tiles of all filters.  With local_prefix every
+// work-group computes the filters' tile prefix itself (into LDS, F + 1
+// entries after 4 scan words: no separate launch for it) and, when the
+// batch has at least big_min tiles of kMlpQ queries, uses tiles of kMlpQBig
+// queries instead (W1 is then read half as often; a small batch keeps the
+// smaller tiles, which spread over more CUs).  The tile size changes no
+// value: every (query, filter) pair is summed in the same order either way.
+__global__ void __launch_bounds__(256, 2) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
+                                                         const float *__restrict__ x,
+                                                         const int64_t *__restrict__ plist,
+                                                         const int32_t *__restrict__ pcnt, int64_t stride, int N,
+                                                         const int32_t *__restrict__ pair,
+                                                         const float *__restrict__ offsets,
+                                                         const int32_t *__restrict__ tile_prefix, float *dfo,
+                                                         int local_prefix, int big_min) {
+  extern __shared__ float xs[];
+  // the tile area is sized for the largest tile this launch may use
+  int *ints = reinterpret_cast<int *>(xs + mlp_tile_floats(m, big_min > 0 ? kMlpQBig : kMlpQ));
+  bool big = false;
+  if (local_prefix) {
+    // tile counts at both sizes in one scan (each total < 2^31: packed as
+    // small + big * 2^32, the low half never carries)
+    int32_t *tp = ints + 12;  // after s_lo, s_f, 2 spare ints and the scan's 4 int64 words
+    const int per = (F + blockDim.x - 1) / blockDim.x;
+    const int f0 = min(F, static_cast<int>(threadIdx.x) * per), f1 = min(F, f0 + per);
+    int64_t sum = 0;
+    for (int f = f0; f < f1; ++f)
+      sum += (pcnt[f] + kMlpQ - 1) / kMlpQ + (static_cast<int64_t>((pcnt[f] + kMlpQBig - 1) / kMlpQBig) << 32);
+    int64_t tot;
+    const int64_t run2 = block_scan_excl<256>(sum, reinterpret_cast<int64_t *>(ints + 4), tot);
+    big = big_min > 0 && (tot & 0xffffffffll) >= big_min;  // uniform
+    const int Q = big ? kMlpQBig : kMlpQ;
+    int run = static_cast<int>(big ? run2 >> 32 : run2 & 0xffffffffll);
+    for (int f = f0; f < f1; ++f) {
+      tp[f] = run;
+      run += (pcnt[f] + Q - 1) / Q;
+    }
+    if (threadIdx.x == 0) tp[F] = static_cast<int>(big ? tot >> 32 : tot & 0xffffffffll);
+    __syncthreads();
+    tile_prefix = tp;
+  }
+  if (big)
+    infer_pair_tiles<kMlpQBig>(w, F, m, h, x, plist, pcnt, stride, N, pair, offsets, tile_prefix, dfo, xs, ints);
+  else
+    infer_pair_tiles<kMlpQ>(w, F, m, h, x, plist, pcnt, stride, N, pair, offsets, tile_prefix, dfo, xs, ints);
 }
 
 constexpr int kTB = 64;  // training mini-batch capacity (columns of the LDS batch)
@@ -590,11 +621,15 @@ void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x,
   // (a multiple of 8 for the per-XCD tile ranges; spare work-groups exit)
   const int grid = static_cast<int>(
       ceil_div(std::min<int64_t>(tiles_bound, static_cast<int64_t>(cus) * 4), kMlpXcds) * kMlpXcds);
-  const size_t lds = mlp_infer_lds(m) + (local ? (static_cast<size_t>(F) + 1 + 4) * sizeof(int32_t) : 0);
+  // with the prefix computed locally, a batch of at least one small tile per
+  // CU runs on the large tiles
+  const int big_min = local ? cus : 0;
+  const size_t lds = mlp_infer_lds(m, local ? kMlpQBig : kMlpQ) +
+                     (local ? (static_cast<size_t>(F) + 1 + 4) * sizeof(int32_t) : 0);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer_pairs),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   hipLaunchKernelGGL(k_mlp_infer_pairs, dim3(grid), dim3(256), lds, st, w, F, m, h, x, plist, pcnt, stride, N, pair,
-                     offsets, tile_prefix, dfo, local ? 1 : 0);
+                     offsets, tile_prefix, dfo, local ? 1 : 0, big_min);
   LAUNCH_OK("mlp_infer_pairs");
 }
 
