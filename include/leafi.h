@@ -53,8 +53,26 @@ typedef struct leafi_index leafi_index;
  * Handle management
  * ---------------------------------------------------------------------- */
 
-/* Create an empty index handle bound to the current HIP device. */
-int leafi_create(leafi_index **out);
+/* Device memory allocator supplied by the caller (e.g. a framework's caching
+ * allocator).  alloc stores a device pointer of at least `bytes` bytes (256-
+ * byte aligned) in *dptr and returns 0, or returns nonzero when it cannot;
+ * free releases a pointer alloc returned.  The library calls free only after
+ * every piece of work it queued on the device has finished (it synchronises
+ * the device first), so a pool may hand the block out again at once. */
+typedef int (*leafi_alloc_fn)(void *ctx, size_t bytes, void **dptr);
+typedef void (*leafi_free_fn)(void *ctx, void *dptr);
+
+/*
+ * Create an empty index handle bound to the current HIP device.  Every
+ * device allocation the handle makes (leaf store, filters, calibration
+ * tables, search workspace, serving state) goes through alloc / free with
+ * `alloc_ctx`, which must stay valid until leafi_destroy returns; with both
+ * NULL the library uses hipMalloc / hipFree.  Giving only one of them is
+ * LEAFI_EINVAL.  A refused allocation makes the call that needed it return
+ * LEAFI_ENOMEM; the handle stays valid (an index build that failed leaves it
+ * unbuilt).
+ */
+int leafi_create(leafi_alloc_fn alloc, leafi_free_fn free_fn, void *alloc_ctx, leafi_index **out);
 
 /* Release the handle and every device allocation it owns.  NULL is a no-op. */
 void leafi_destroy(leafi_index *index);
@@ -140,11 +158,14 @@ typedef struct {
   int32_t batch;         /* SGD mini-batch size */
   int32_t patience;      /* epochs without validation improvement before lr /= 10 */
   uint64_t seed;
+  int32_t keep_examples; /* 1: keep the training queries and targets for leafi_get_examples */
+  int32_t reserved;
 } leafi_train_opts;
 
 /* Fill opts with the defaults listed above (n_global 1500, n_local 500,
  * noise 0.1..0.4, a 2, val 0.2, th measured, budget 8 GiB, h = m, 1000
- * epochs, lr 0.01 -> 1e-5, batch 64, patience 10, seed 1). */
+ * epochs, lr 0.01 -> 1e-5, batch 64, patience 10, seed 1, examples not
+ * kept). */
 void leafi_default_train_opts(leafi_train_opts *opts);
 
 typedef struct {
@@ -167,6 +188,24 @@ typedef struct {
  */
 int leafi_train_filters(leafi_index *index, const leafi_train_opts *opts, leafi_train_report *report,
                         void *stream);
+
+/*
+ * The training set of the last leafi_train_filters call that had
+ * keep_examples = 1 (paper: Algorithm 1 and Section "Training Data
+ * Generation").  The training queries are raw (before z-normalisation): the
+ * n_global global queries first (collection series drawn uniformly, plus
+ * noise), then n_local local queries per filter, filter by filter (series of
+ * the filter's leaf, plus noise).  Per filter f the n_examples examples are
+ * [global training | local | global validation]: example e pairs query
+ * ex_query[f * n_examples + e] with target ex_target[f * n_examples + e] =
+ * d^L(query, leaf of f), the node-wise nearest-neighbour distance.
+ * Outputs (each may be NULL): *n_queries, *n_examples, *n_train (training
+ * examples per filter, the rest validate), queries_dev [n_queries, m] fp32,
+ * ex_query_host [n_filters, n_examples] int32, ex_target_dev [n_filters,
+ * n_examples] fp32.  LEAFI_ESTATE if no training set was kept.
+ */
+int leafi_get_examples(const leafi_index *index, int64_t *n_queries, int32_t *n_examples, int32_t *n_train,
+                       float *queries_dev, int32_t *ex_query_host, float *ex_target_dev, void *stream);
 
 /*
  * Install given filters instead of training them: n_filters filters on the
@@ -236,6 +275,12 @@ typedef struct {
 
 #define LEAFI_SEARCH_NO_GRAPH 1     /* planned sequence as plain launches, never captured */
 #define LEAFI_SEARCH_HOST_ROUNDS 2  /* host-driven rounds (counts read back every round) */
+/* Filter inference tiles: by default a batch with at least one 32-query tile
+ * per compute unit uses 64-query tiles (filter weights read half as often),
+ * else 32-query tiles.  These flags force one size; values never depend on
+ * it (every (query, filter) sum runs in the same order). */
+#define LEAFI_SEARCH_FILTER_TILE_SMALL 4
+#define LEAFI_SEARCH_FILTER_TILE_LARGE 8
 
 void leafi_default_search_opts(leafi_search_opts *opts);
 

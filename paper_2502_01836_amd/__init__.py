@@ -12,10 +12,13 @@ import numpy as np
 
 from . import _lib
 from ._lib import LeafiError, check, load, struct_dict
+from ._lib import LEAFI_SEARCH_FILTER_TILE_LARGE as SEARCH_FILTER_TILE_LARGE
+from ._lib import LEAFI_SEARCH_FILTER_TILE_SMALL as SEARCH_FILTER_TILE_SMALL
 from ._lib import LEAFI_SEARCH_HOST_ROUNDS as SEARCH_HOST_ROUNDS
 from ._lib import LEAFI_SEARCH_NO_GRAPH as SEARCH_NO_GRAPH
 
-__all__ = ["Index", "Server", "LeafiError", "load", "znorm", "mlp_infer", "mlp_sgd_step", "version"]
+__all__ = ["Index", "Server", "TorchAllocator", "LeafiError", "load", "znorm", "mlp_infer", "mlp_sgd_step",
+           "version"]
 
 
 def _torch():
@@ -43,13 +46,62 @@ def version() -> str:
     return load().leafi_version().decode()
 
 
-class Index:
-    """One index handle: leaf store, filters and calibration on the current device."""
+class TorchAllocator:
+    """Device memory for an index handle from torch's caching allocator
+    (leafi_alloc_fn / leafi_free_fn).  `limit` (bytes, optional) makes it
+    refuse any allocation that would take its live total above the limit."""
 
-    def __init__(self):
+    def __init__(self, limit=None):
+        torch = _torch()
+        self.device = torch.cuda.current_device()
+        self.limit = limit
+        self.live = {}
+
+        def alloc(ctx, nbytes, out):
+            try:
+                if self.limit is not None and sum(self.live.values()) + nbytes > self.limit:
+                    return 1
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device)
+            except Exception:
+                return 1
+            self.live[ptr] = int(nbytes)
+            out[0] = ptr
+            return 0
+
+        def free(ctx, ptr):
+            self.live.pop(ptr, None)
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:  # interpreter shutdown: torch may already be gone
+                pass
+
+        # the ctypes callbacks must outlive every handle that uses them
+        self.alloc_fn = _lib.ALLOC_FN(alloc)
+        self.free_fn = _lib.FREE_FN(free)
+
+    @property
+    def live_bytes(self) -> int:
+        return sum(self.live.values())
+
+
+class Index:
+    """One index handle: leaf store, filters and calibration on the current device.
+
+    allocator: "torch" (default: torch's caching allocator owns every device
+    byte of the handle), "hip" (the library's own hipMalloc), or a
+    TorchAllocator instance."""
+
+    def __init__(self, allocator="torch"):
         lib = load()
         h = ctypes.c_void_p()
-        check(lib.leafi_create(ctypes.byref(h)))
+        if allocator == "torch":
+            allocator = TorchAllocator()
+        if allocator == "hip" or allocator is None:
+            self._alloc = None
+            check(lib.leafi_create(_lib.ALLOC_FN(), _lib.FREE_FN(), None, ctypes.byref(h)))
+        else:
+            self._alloc = allocator
+            check(lib.leafi_create(allocator.alloc_fn, allocator.free_fn, None, ctypes.byref(h)))
         self._h = h
         self._m = None
 
@@ -104,6 +156,24 @@ class Index:
         r = _lib.TrainReport()
         check(load().leafi_train_filters(self._h, ctypes.byref(o), ctypes.byref(r), _stream()))
         return struct_dict(r)
+
+    def examples(self):
+        """The kept training set (train_filters(keep_examples=1)): raw queries
+        [nq, m] (device), example queries [F, n_ex] int32 (host), targets
+        [F, n_ex] (device) and the number of training examples per filter."""
+        torch = _torch()
+        nq, nex, ntr = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        lib = load()
+        check(lib.leafi_get_examples(self._h, ctypes.byref(nq), ctypes.byref(nex), ctypes.byref(ntr), None, None,
+                                     None, _stream()))
+        inf = self.info()
+        F, m = inf["n_filters"], inf["m"]
+        q = torch.empty((nq.value, m), dtype=torch.float32, device="cuda")
+        exq = np.zeros((F, nex.value), dtype=np.int32)
+        y = torch.empty((F, nex.value), dtype=torch.float32, device="cuda")
+        check(lib.leafi_get_examples(self._h, None, None, None, ctypes.c_void_p(q.data_ptr()),
+                                     exq.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(y.data_ptr()), _stream()))
+        return q, exq, y, ntr.value
 
     def set_filters(self, leaf_ids, weights, hidden: int):
         torch = _torch()

@@ -20,6 +20,8 @@ LEAFI_SCAN_BF16 = 0
 LEAFI_SCAN_FP32 = 1
 LEAFI_SEARCH_NO_GRAPH = 1
 LEAFI_SEARCH_HOST_ROUNDS = 2
+LEAFI_SEARCH_FILTER_TILE_SMALL = 4
+LEAFI_SEARCH_FILTER_TILE_LARGE = 8
 LEAFI_CALIB_STEP = 0
 LEAFI_CALIB_STEFFEN = 1
 LEAFI_CALIB_NO_CORRECTION = 2
@@ -48,7 +50,8 @@ class TrainOpts(ctypes.Structure):
                 ("noise_hi", ctypes.c_float), ("a", ctypes.c_float), ("val_fraction", ctypes.c_float),
                 ("th_override", ctypes.c_double), ("mem_budget", ctypes.c_int64), ("hidden", ctypes.c_int32),
                 ("max_epochs", ctypes.c_int32), ("lr0", ctypes.c_float), ("lr_min", ctypes.c_float),
-                ("batch", ctypes.c_int32), ("patience", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("batch", ctypes.c_int32), ("patience", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("keep_examples", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class TrainReport(ctypes.Structure):
@@ -101,13 +104,17 @@ def struct_dict(s) -> dict:
     return out
 
 
+# caller-supplied device allocator (leafi_alloc_fn / leafi_free_fn)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p))
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 # (name, restype, argtypes) of every entry point declared in include/leafi.h
 P = ctypes.c_void_p
 I32 = ctypes.c_int32
 I64 = ctypes.c_int64
 F32 = ctypes.c_float
 SIGNATURES = [
-    ("leafi_create", ctypes.c_int, [ctypes.POINTER(P)]),
+    ("leafi_create", ctypes.c_int, [ALLOC_FN, FREE_FN, P, ctypes.POINTER(P)]),
     ("leafi_destroy", None, [P]),
     ("leafi_last_error", ctypes.c_char_p, []),
     ("leafi_version", ctypes.c_char_p, []),
@@ -119,6 +126,8 @@ SIGNATURES = [
     ("leafi_train_filters", ctypes.c_int, [P, ctypes.POINTER(TrainOpts), ctypes.POINTER(TrainReport), P]),
     ("leafi_set_filters", ctypes.c_int, [P, I32, I32, P, P, P]),
     ("leafi_get_filters", ctypes.c_int, [P, P, P, P]),
+    ("leafi_get_examples", ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P,
+                                          P]),
     ("leafi_calibrate", ctypes.c_int, [P, P, I32, P, I32, P, I32, I32, P]),
     ("leafi_get_offsets", ctypes.c_int, [P, P]),
     ("leafi_set_offsets", ctypes.c_int, [P, P, I32, P, I32, P]),

@@ -24,6 +24,43 @@ leafi_index::~leafi_index() {
 namespace leafi {
 
 thread_local std::string g_last_error;
+thread_local const AllocFns *t_alloc = nullptr;
+thread_local Arena *t_arena = nullptr;
+
+void *dev_alloc(size_t bytes, AllocFns *how, bool *from_arena) {
+  *how = AllocFns();
+  *from_arena = false;
+  if (t_arena) {
+    const size_t off = (t_arena->used + 255) & ~static_cast<size_t>(255);
+    if (off > t_arena->cap || bytes > t_arena->cap - off)
+      fail(LEAFI_ENOMEM, "scratch area of " + std::to_string(t_arena->cap) + " bytes exhausted");
+    t_arena->used = off + bytes;
+    *from_arena = true;
+    // a measuring arena (no base) hands out distinct non-null stand-ins
+    return t_arena->base ? t_arena->base + off : reinterpret_cast<char *>(off + 256);
+  }
+  void *p = nullptr;
+  if (t_alloc && t_alloc->alloc) {
+    if (t_alloc->alloc(t_alloc->ctx, bytes, &p) != 0 || p == nullptr)
+      fail(LEAFI_ENOMEM, "the caller's allocator refused " + std::to_string(bytes) + " bytes");
+    *how = *t_alloc;
+    return p;
+  }
+  HIP_OK(hipMalloc(&p, bytes));
+  return p;
+}
+
+void dev_free(void *p, const AllocFns &how, bool from_arena) noexcept {
+  if (from_arena || p == nullptr) return;
+  if (how.alloc) {
+    // like hipFree, wait until no queued work can still touch the block: a
+    // caching pool may hand it out again at once
+    (void)hipDeviceSynchronize();
+    how.free(how.ctx, p);
+    return;
+  }
+  (void)hipFree(p);
+}
 
 void require_built(const leafi_index *ix) {
   if (!ix) fail(LEAFI_EINVAL, "index handle is NULL");
@@ -188,7 +225,7 @@ void ensure_queries(leafi_index *ix, int64_t nq, int kmax) {
   w.tile_start.reserve(N + 1);
   w.ctl.reserve(kCtlCount);
   if (w.h_ctl.size() < static_cast<size_t>(kCtlCount)) w.h_ctl.resize(kCtlCount);
-  if (!w.ev0) {
+  if (!w.ev0 && !t_arena) {
     // timing-only events: no system-scope fence (no cache write-back) around the kernels they bracket
     HIP_OK(hipEventCreateWithFlags(&w.ev0, hipEventDisableSystemFence));
     HIP_OK(hipEventCreateWithFlags(&w.ev1, hipEventDisableSystemFence));
@@ -381,6 +418,7 @@ struct SearchPlan {
   std::vector<int> schedule{1};
   int kprime = 4;
   bool graph = true;  // planned batches may be captured and replayed
+  int ftile = 0;      // filter inference tiles: 0 by batch size, 1 small, 2 large
 };
 
 // Queries, lower bounds, visit order, (k, target) pair, batch state.
@@ -397,17 +435,17 @@ void begin_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k
 // After the first round has set tau: d^f for every (query, filtered leaf)
 // pair a later round can still test.  tau only decreases, so this covers all
 // later rounds (filter-pair counts were zeroed by begin_batch).
-void infer_filter_pairs(leafi_index *ix, int64_t nq, hipStream_t st) {
+void infer_filter_pairs(leafi_index *ix, int64_t nq, int ftile, hipStream_t st) {
   Workspace &w = ix->ws;
   launch_mlp_infer_pairs(ix->filt.w.get(), ix->filt.F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(),
-                         nq, ix->N, w.pair.get(), ix->cal.offsets.get(), w.ptile.get(), w.dfo.get(), st);
+                         nq, ix->N, w.pair.get(), ix->cal.offsets.get(), w.ptile.get(), w.dfo.get(), st, ftile);
 }
 
-void eval_filters(leafi_index *ix, int64_t nq, hipStream_t st) {
+void eval_filters(leafi_index *ix, int64_t nq, int ftile, hipStream_t st) {
   Workspace &w = ix->ws;
   launch_filter_pairs(nq, ix->N, w.lbs.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
                       w.pcnt.get(), w.dfo.get(), st);
-  infer_filter_pairs(ix, nq, st);
+  infer_filter_pairs(ix, nq, ftile, st);
 }
 
 // The filter-pair selection done by a merge (see launch_query_merge).
@@ -474,7 +512,7 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
   int64_t deferred = 0;  // rescans the last merge left queued for this round
   for (int r = 0;; ++r) {
     if (use_f && r > 0 && !filters_ready) {
-      eval_filters(ix, nq, st);
+      eval_filters(ix, nq, p.ftile, st);
       filters_ready = true;
     }
     if (r > 0 && deferred == 0) reset_round(ix, st);
@@ -567,7 +605,7 @@ void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_
   }
   ensure_items(ix, items, p.kmax);
   w.cand.reserve(cand);
-  if (w.sev.empty()) {
+  if (w.sev.empty() && !t_arena) {
     w.sev.resize(2 * kMaxPlannedRounds);
     for (auto &e : w.sev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
@@ -615,7 +653,7 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     // rounds after the first may rescan a row the previous round merged
     launch_query_merge(nq, N, p.kmax, true, r > 0, views(w), st, nullptr, nullptr, nullptr,
                        filters_next ? filter_pair_args(ix) : FilterPairArgs());
-    if (filters_next) infer_filter_pairs(ix, nq, st);
+    if (filters_next) infer_filter_pairs(ix, nq, p.ftile, st);
     if (!last) {
       launch_round_worklist(ix, nq, p.schedule[r + 1], use_f, st, true);
       continue;
@@ -652,7 +690,8 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
                     static_cast<int64_t>(timed), static_cast<int64_t>(ix->N), static_cast<int64_t>(ix->m),
                     static_cast<int64_t>(ix->S), static_cast<int64_t>(ix->filt.F), static_cast<int64_t>(ix->filt.h),
                     static_cast<int64_t>(ix->cal.pairs()), ix->rows,
-                    static_cast<int64_t>(ix->tune_chunk), static_cast<int64_t>(ix->tune_mq)})
+                    static_cast<int64_t>(ix->tune_chunk), static_cast<int64_t>(ix->tune_mq),
+                    static_cast<int64_t>(p.ftile)})
     k.push_back(static_cast<uint64_t>(v));
   for (int r : p.schedule) k.push_back(static_cast<uint64_t>(r));
   for (const void *a : {static_cast<const void *>(raw), static_cast<const void *>(k_dev),
@@ -839,10 +878,14 @@ const char *leafi_last_error(void) { return g_last_error.c_str(); }
 
 const char *leafi_version(void) { return "leafi-gfx950 0.1"; }
 
-int leafi_create(leafi_index **out) {
+int leafi_create(leafi_alloc_fn alloc, leafi_free_fn free_fn, void *alloc_ctx, leafi_index **out) {
   return guarded([&] {
     LEAFI_CHECK_ARG(out != nullptr, "out is NULL");
+    LEAFI_CHECK_ARG((alloc == nullptr) == (free_fn == nullptr), "give both alloc and free, or neither");
     auto *ix = new leafi_index();
+    ix->alloc.alloc = alloc;
+    ix->alloc.free = free_fn;
+    ix->alloc.ctx = alloc_ctx;
     HIP_OK(hipGetDevice(&ix->device));
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device) == hipSuccess && cus > 0)
@@ -856,6 +899,7 @@ void leafi_destroy(leafi_index *index) { delete index; }
 int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m, const leafi_build_opts *opts,
                       void *stream) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     LEAFI_CHECK_ARG(ix != nullptr, "index is NULL");
     LEAFI_CHECK_ARG(series != nullptr, "series is NULL");
     LEAFI_CHECK_ARG(opts != nullptr, "opts is NULL");
@@ -870,6 +914,7 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     // discard previous state
     ix->built = false;
     ix->filt = Filters();
+    ix->examples = Examples();
     ix->cal = Calibration();
     // 1. statistics
     DevBuf<double> mean(n), sd(n);
@@ -1015,6 +1060,7 @@ void leafi_default_train_opts(leafi_train_opts *o) {
 }
 
 static void install_filters(leafi_index *ix, int F, int h, const std::vector<int32_t> &leaves, hipStream_t st) {
+  ix->examples = Examples();
   ix->filt.F = F;
   ix->filt.h = h;
   ix->filt.P = static_cast<int64_t>(h) * ix->m + 2 * h + 1;
@@ -1029,6 +1075,7 @@ static void install_filters(leafi_index *ix, int F, int h, const std::vector<int
 int leafi_set_filters(leafi_index *ix, int32_t F, int32_t hidden, const int32_t *leaf_ids, const float *weights,
                       void *stream) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     require_built(ix);
     LEAFI_CHECK_ARG(F >= 0 && F <= ix->N, "n_filters must be in [0, n_leaves]");
     LEAFI_CHECK_ARG(F == 0 || (leaf_ids && weights), "NULL leaf ids or weights");
@@ -1063,6 +1110,7 @@ int leafi_get_filters(const leafi_index *ix, int32_t *leaf_ids, float *weights, 
 
 int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_report *rep, void *stream) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     require_built(ix);
     LEAFI_CHECK_ARG(o != nullptr, "opts is NULL");
     LEAFI_CHECK_ARG(o->n_global >= 2 && o->n_local >= 0, "need n_global >= 2 and n_local >= 0");
@@ -1170,7 +1218,8 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     launch_make_queries(ix->x32.get(), drows.get(), dsig.get(), nqt, m, o->seed, qraw.get(), st);
     ensure_queries(ix, nqt, 1);
     prep_queries(ix, qraw.get(), nqt, st);
-    qraw.release();
+    if (o->keep_examples) ix->examples.q = std::move(qraw);
+    else qraw.release();
 
     // ---- targets d^L with the leaf scan: global x filtered leaves, local x own leaf
     auto t0 = std::chrono::steady_clock::now();
@@ -1266,15 +1315,41 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
       report.epochs_max_run = std::max(report.epochs_max_run, he[f]);
     }
     report.mean_val_mse = s / F;
+    if (o->keep_examples) {
+      Examples &ex = ix->examples;
+      ex.nq = nqt;
+      ex.n_ex = n_ex;
+      ex.n_train = n_train;
+      ex.ex_q = std::move(exq);
+      ex.ex_y = std::move(ex_y);
+    }
     if (rep) *rep = report;
+  });
+}
+
+int leafi_get_examples(const leafi_index *ix, int64_t *n_queries, int32_t *n_examples, int32_t *n_train,
+                       float *queries, int32_t *ex_query, float *ex_target, void *stream) {
+  return guarded([&] {
+    require_built(ix);
+    const Examples &ex = ix->examples;
+    if (ex.nq == 0) fail(LEAFI_ESTATE, "no training set kept (train with keep_examples = 1)");
+    if (n_queries) *n_queries = ex.nq;
+    if (n_examples) *n_examples = ex.n_ex;
+    if (n_train) *n_train = ex.n_train;
+    if (ex_query) std::copy(ex.ex_q.begin(), ex.ex_q.end(), ex_query);
+    hipStream_t st = as_stream(stream);
+    if (queries) HIP_OK(hipMemcpyAsync(queries, ex.q.get(), ex.q.bytes(), hipMemcpyDeviceToDevice, st));
+    if (ex_target) HIP_OK(hipMemcpyAsync(ex_target, ex.ex_y.get(), ex.ex_y.bytes(), hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
   });
 }
 
 int leafi_calibrate(leafi_index *ix, const float *calib, int32_t nc, const int32_t *ks, int32_t n_ks,
                     const float *targets, int32_t n_targets, int32_t flags, void *stream) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     require_built(ix);
-    LEAFI_CHECK_ARG(ix->filt.F > 0, "no filters (train or set them first)");
+    if (ix->filt.F == 0) fail(LEAFI_ESTATE, "no filters (train or set them first)");
     LEAFI_CHECK_ARG(nc >= 1 && calib != nullptr, "need calibration queries");
     LEAFI_CHECK_ARG(n_ks >= 1 && ks != nullptr && n_targets >= 1 && targets != nullptr, "need ks and targets");
     int kc = 1;
@@ -1348,8 +1423,9 @@ int leafi_get_offsets(const leafi_index *ix, float *offsets) {
 int leafi_set_offsets(leafi_index *ix, const int32_t *ks, int32_t n_ks, const float *targets, int32_t n_targets,
                       const float *offsets) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     require_built(ix);
-    LEAFI_CHECK_ARG(ix->filt.F > 0, "no filters");
+    if (ix->filt.F == 0) fail(LEAFI_ESTATE, "no filters (train or set them first)");
     LEAFI_CHECK_ARG(n_ks >= 1 && n_targets >= 1 && ks && targets && offsets, "bad arguments");
     const int F = ix->filt.F;
     Calibration cal;
@@ -1393,7 +1469,11 @@ SearchPlan make_plan(const leafi_index *ix, const leafi_search_opts *o) {
   LEAFI_CHECK_ARG(o->n_schedule >= 1 && o->n_schedule <= 8, "n_schedule must be in [1, 8]");
   for (int i = 0; i < o->n_schedule; ++i) LEAFI_CHECK_ARG(o->schedule[i] >= 0, "schedule entries must be >= 0");
   LEAFI_CHECK_ARG(o->kprime >= 0 && o->kprime <= 256, "kprime must be in [0, 256]");
-  LEAFI_CHECK_ARG((o->flags & ~(LEAFI_SEARCH_NO_GRAPH | LEAFI_SEARCH_HOST_ROUNDS)) == 0, "unknown search flags");
+  LEAFI_CHECK_ARG((o->flags & ~(LEAFI_SEARCH_NO_GRAPH | LEAFI_SEARCH_HOST_ROUNDS | LEAFI_SEARCH_FILTER_TILE_SMALL |
+                                 LEAFI_SEARCH_FILTER_TILE_LARGE)) == 0,
+                  "unknown search flags");
+  LEAFI_CHECK_ARG((o->flags & LEAFI_SEARCH_FILTER_TILE_SMALL) == 0 || (o->flags & LEAFI_SEARCH_FILTER_TILE_LARGE) == 0,
+                  "FILTER_TILE_SMALL and FILTER_TILE_LARGE exclude each other");
   LEAFI_CHECK_ARG(o->scan != LEAFI_SCAN_BF16 || ix->m <= 256, "the bf16 scan supports m <= 256");
   SearchPlan p;
   p.kmax = o->k_max;
@@ -1402,6 +1482,7 @@ SearchPlan make_plan(const leafi_index *ix, const leafi_search_opts *o) {
   p.schedule.assign(o->schedule, o->schedule + o->n_schedule);
   p.kprime = o->kprime > 0 ? std::max<int>(o->kprime, p.kmax) : default_kprime(p.kmax, p.bf16);
   p.graph = (o->flags & LEAFI_SEARCH_NO_GRAPH) == 0;
+  p.ftile = (o->flags & LEAFI_SEARCH_FILTER_TILE_SMALL) ? 1 : (o->flags & LEAFI_SEARCH_FILTER_TILE_LARGE) ? 2 : 0;
   return p;
 }
 }  // namespace leafi
@@ -1410,6 +1491,7 @@ int leafi_search_knn(leafi_index *ix, const float *queries, int64_t nq, const in
                      const leafi_search_opts *o, int64_t *ids, float *dists, leafi_search_stats *stats,
                      void *stream) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     require_built(ix);
     check_queries(ix, queries, nq);
     SearchPlan p = make_plan(ix, o);
@@ -1450,6 +1532,7 @@ int leafi_set_tiling(leafi_index *ix, int32_t chunk_rows, int32_t queries_per_ti
 int leafi_autotune(leafi_index *ix, const float *queries, int64_t nq, const int32_t *k_dev, const float *t_dev,
                    const leafi_search_opts *o, int32_t repeats, leafi_tune_report *report, void *stream) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     require_built(ix);
     check_queries(ix, queries, nq);
     LEAFI_CHECK_ARG(nq > 0 && k_dev && t_dev, "empty sample or NULL k / target");
@@ -1523,6 +1606,7 @@ int leafi_znorm(const float *x, int64_t n, int32_t m, float *out, void *stream) 
 
 int leafi_lower_bounds(leafi_index *ix, const float *queries, int64_t nq, float *lb, void *stream) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     require_built(ix);
     check_queries(ix, queries, nq);
     if (nq == 0) return;
@@ -1566,6 +1650,7 @@ int leafi_mlp_sgd_step(float *w, int32_t F, int32_t m, int32_t h, const float *x
 int leafi_leaf_knn(leafi_index *ix, const float *queries, int64_t nq, int32_t k, float *d, int64_t *ids,
                    void *stream) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     require_built(ix);
     check_queries(ix, queries, nq);
     LEAFI_CHECK_ARG(k >= 1 && k <= 256, "k must be in [1, 256]");

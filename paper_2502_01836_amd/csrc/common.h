@@ -38,7 +38,49 @@ struct Error : std::runtime_error {
 // Check the launch just enqueued.
 #define LAUNCH_OK(name) HIP_OK(hipGetLastError())
 
-// Owning device allocation (hipMalloc / hipFree).
+// Where device memory comes from.  Allocations of an index handle go through
+// the caller's allocator when leafi_create was given one (else hipMalloc);
+// the no-allocation search carves its buffers out of a fixed device array
+// instead (an arena: nothing is freed, the arena is rewound per call).
+struct AllocFns {
+  leafi_alloc_fn alloc = nullptr;
+  leafi_free_fn free = nullptr;
+  void *ctx = nullptr;
+};
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+// In effect on the calling thread (set by the entry points, see AllocScope).
+extern thread_local const AllocFns *t_alloc;
+extern thread_local Arena *t_arena;
+
+// Allocate bytes of device memory from the thread's arena, the handle's
+// allocator or hipMalloc; `how` records which (for the matching free).
+void *dev_alloc(size_t bytes, AllocFns *how, bool *from_arena);
+// Release memory from dev_alloc (arena memory is never released one by one).
+void dev_free(void *p, const AllocFns &how, bool from_arena) noexcept;
+
+// Makes `fns` the calling thread's allocator until the scope ends.
+struct AllocScope {
+  const AllocFns *prev;
+  explicit AllocScope(const AllocFns *fns) : prev(t_alloc) { t_alloc = fns; }
+  ~AllocScope() { t_alloc = prev; }
+  AllocScope(const AllocScope &) = delete;
+  AllocScope &operator=(const AllocScope &) = delete;
+};
+
+// Makes `a` the calling thread's arena until the scope ends.
+struct ArenaScope {
+  Arena *prev;
+  explicit ArenaScope(Arena *a) : prev(t_arena) { t_arena = a; }
+  ~ArenaScope() { t_arena = prev; }
+  ArenaScope(const ArenaScope &) = delete;
+  ArenaScope &operator=(const ArenaScope &) = delete;
+};
+
+// Owning device allocation (see dev_alloc for where the bytes come from).
 template <typename T>
 class DevBuf {
  public:
@@ -47,21 +89,29 @@ class DevBuf {
   ~DevBuf() { release(); }
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  DevBuf(DevBuf &&o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf(DevBuf &&o) noexcept : p_(o.p_), n_(o.n_), how_(o.how_), arena_(o.arena_) { o.p_ = nullptr; o.n_ = 0; }
   DevBuf &operator=(DevBuf &&o) noexcept {
-    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    if (this != &o) {
+      release();
+      p_ = o.p_;
+      n_ = o.n_;
+      how_ = o.how_;
+      arena_ = o.arena_;
+      o.p_ = nullptr;
+      o.n_ = 0;
+    }
     return *this;
   }
   void alloc(size_t n) {
     release();
     if (n == 0) return;
-    HIP_OK(hipMalloc(reinterpret_cast<void **>(&p_), n * sizeof(T)));
+    p_ = static_cast<T *>(dev_alloc(n * sizeof(T), &how_, &arena_));
     n_ = n;
   }
   // Grow-only reallocation (contents not kept).
   void reserve(size_t n) { if (n > n_) alloc(n); }
   void release() {
-    if (p_) (void)hipFree(p_);
+    if (p_) dev_free(p_, how_, arena_);
     p_ = nullptr;
     n_ = 0;
   }
@@ -72,6 +122,8 @@ class DevBuf {
  private:
   T *p_ = nullptr;
   size_t n_ = 0;
+  AllocFns how_;
+  bool arena_ = false;
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

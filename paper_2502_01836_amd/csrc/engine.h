@@ -11,6 +11,9 @@ namespace leafi {
 
 extern thread_local std::string g_last_error;
 
+// Device allocations made while this is in scope go through the handle's allocator.
+#define INDEX_ALLOC_SCOPE(ix) ::leafi::AllocScope leafi_alloc_scope_((ix) ? &(ix)->alloc : nullptr)
+
 // Run fn, turning exceptions into LEAFI_E* codes and the thread's message.
 template <typename Fn>
 int guarded(Fn &&fn) {

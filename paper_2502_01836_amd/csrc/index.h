@@ -104,6 +104,16 @@ struct GraphCache {
   }
 };
 
+// Training set kept by leafi_train_filters (keep_examples): raw queries and
+// the per-filter example table.
+struct Examples {
+  int64_t nq = 0;
+  int n_ex = 0, n_train = 0;
+  DevBuf<float> q;              // [nq, m] raw
+  std::vector<int32_t> ex_q;    // [F, n_ex] query of each example
+  DevBuf<float> ex_y;           // [F, n_ex] d^L targets
+};
+
 struct Workspace {
   // queries
   DevBuf<float> q32, qn16, qeps, qstat, lb, dfilt, tau;
@@ -131,6 +141,7 @@ struct Workspace {
 }  // namespace leafi
 
 struct leafi_index {
+  leafi::AllocFns alloc;  // the caller's allocator (both NULL: hipMalloc / hipFree)
   int device = 0;
   bool built = false;
   int64_t n = 0;
@@ -153,6 +164,7 @@ struct leafi_index {
   std::vector<int64_t> h_leaf_off, h_leaf_n, h_members;
   std::vector<float> h_boxes;
   leafi::Filters filt;
+  leafi::Examples examples;
   leafi::Calibration cal;
   leafi::Workspace ws;
   int num_cus = 256;

@@ -228,18 +228,19 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const float *__restrict__ 
 
 // Exclusive prefix of the filters' tile counts ceil(pcnt[f] / 16) (one
 // work-group; tile_prefix[F] = total).
-__global__ void __launch_bounds__(1024) k_mlp_tiles(int F, const int32_t *__restrict__ pcnt, int32_t *tile_prefix) {
+__global__ void __launch_bounds__(1024) k_mlp_tiles(int F, const int32_t *__restrict__ pcnt, int32_t *tile_prefix,
+                                                    int Q) {
   __shared__ int32_t sh[16];
   const int tid = threadIdx.x;
   const int per = (F + 1023) / 1024;
   const int f0 = min(F, tid * per), f1 = min(F, f0 + per);
   int sum = 0;
-  for (int f = f0; f < f1; ++f) sum += (pcnt[f] + kMlpQ - 1) / kMlpQ;
+  for (int f = f0; f < f1; ++f) sum += (pcnt[f] + Q - 1) / Q;
   int total;
   int run = block_scan_excl<1024>(sum, sh, total);
   for (int f = f0; f < f1; ++f) {
     tile_prefix[f] = run;
-    run += (pcnt[f] + kMlpQ - 1) / kMlpQ;
+    run += (pcnt[f] + Q - 1) / Q;
   }
   if (tid == 0) tile_prefix[F] = total;
 }
@@ -299,11 +300,14 @@ __device__ inline void infer_pair_tiles(const float *__restrict__ w, int F, int 
 // d^f - o for the query's calibrated (k, target) row.  A persistent grid
 // walks the non-empty tiles of all filters.  With local_prefix every
 // work-group computes the filters' tile prefix itself (into LDS, F + 1
-// entries after 4 scan words: no separate launch for it) and, when the
-// batch has at least big_min tiles of kMlpQ queries, uses tiles of kMlpQBig
-// queries instead (W1 is then read half as often; a small batch keeps the
-// smaller tiles, which spread over more CUs).  The tile size changes no
-// value: every (query, filter) pair is summed in the same order either way.
+// entries after 4 scan words: no separate launch for it) and, when big_fixed
+// is -1 and the batch has at least big_min tiles of kMlpQ queries, uses tiles
+// of kMlpQBig queries instead (W1 is then read half as often; a small batch
+// keeps the smaller tiles, which spread over more CUs).  big_fixed 0 / 1
+// forces the small / large tiles (without local_prefix, tile_prefix must be
+// the prefix at that size).  lds_q is the tile size the LDS block is sized
+// for.  The tile size changes no value: every (query, filter) pair is summed
+// in the same order either way.
 __global__ void __launch_bounds__(256, 2) k_mlp_infer_pairs(const float *__restrict__ w, int F, int m, int h,
                                                          const float *__restrict__ x,
                                                          const int64_t *__restrict__ plist,
@@ -311,11 +315,11 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer_pairs(const float *__restr
                                                          const int32_t *__restrict__ pair,
                                                          const float *__restrict__ offsets,
                                                          const int32_t *__restrict__ tile_prefix, float *dfo,
-                                                         int local_prefix, int big_min) {
+                                                         int local_prefix, int big_min, int big_fixed, int lds_q) {
   extern __shared__ float xs[];
   // the tile area is sized for the largest tile this launch may use
-  int *ints = reinterpret_cast<int *>(xs + mlp_tile_floats(m, big_min > 0 ? kMlpQBig : kMlpQ));
-  bool big = false;
+  int *ints = reinterpret_cast<int *>(xs + mlp_tile_floats(m, lds_q));
+  bool big = big_fixed == 1;
   if (local_prefix) {
     // tile counts at both sizes in one scan (each total < 2^31: packed as
     // small + big * 2^32, the low half never carries)
@@ -327,7 +331,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer_pairs(const float *__restr
       sum += (pcnt[f] + kMlpQ - 1) / kMlpQ + (static_cast<int64_t>((pcnt[f] + kMlpQBig - 1) / kMlpQBig) << 32);
     int64_t tot;
     const int64_t run2 = block_scan_excl<256>(sum, reinterpret_cast<int64_t *>(ints + 4), tot);
-    big = big_min > 0 && (tot & 0xffffffffll) >= big_min;  // uniform
+    if (big_fixed < 0) big = big_min > 0 && (tot & 0xffffffffll) >= big_min;  // uniform
     const int Q = big ? kMlpQBig : kMlpQ;
     int run = static_cast<int>(big ? run2 >> 32 : run2 & 0xffffffffll);
     for (int f = f0; f < f1; ++f) {
@@ -600,14 +604,18 @@ void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64
 
 void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int64_t *plist,
                             const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets,
-                            int32_t *tile_prefix, float *dfo, hipStream_t st) {
+                            int32_t *tile_prefix, float *dfo, hipStream_t st, int tile_mode) {
   if (F <= 0 || stride <= 0) return;
   // up to kLocalPrefixMax filters the inference kernel computes the tile
   // prefix itself (one launch instead of two)
   constexpr int kLocalPrefixMax = 4096;
   const bool local = F <= kLocalPrefixMax;
+  // tile_mode 0: large tiles for a large batch (decided on the device, with
+  // the local prefix only); 1: always small; 2: always large
+  const int big_fixed = tile_mode == 1 ? 0 : tile_mode == 2 ? 1 : (local ? -1 : 0);
   if (!local) {
-    hipLaunchKernelGGL(k_mlp_tiles, dim3(1), dim3(1024), 0, st, F, pcnt, tile_prefix);
+    hipLaunchKernelGGL(k_mlp_tiles, dim3(1), dim3(1024), 0, st, F, pcnt, tile_prefix,
+                       big_fixed == 1 ? kMlpQBig : kMlpQ);
     LAUNCH_OK("mlp_tiles");
   }
   // persistent grid: a few work-groups per CU, never more than the tiles can be
@@ -623,13 +631,13 @@ void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x,
       ceil_div(std::min<int64_t>(tiles_bound, static_cast<int64_t>(cus) * 4), kMlpXcds) * kMlpXcds);
   // with the prefix computed locally, a batch of at least one small tile per
   // CU runs on the large tiles
-  const int big_min = local ? cus : 0;
-  const size_t lds = mlp_infer_lds(m, local ? kMlpQBig : kMlpQ) +
-                     (local ? (static_cast<size_t>(F) + 1 + 4) * sizeof(int32_t) : 0);
+  const int big_min = local && big_fixed < 0 ? cus : 0;
+  const int lds_q = big_fixed == 0 ? kMlpQ : kMlpQBig;
+  const size_t lds = mlp_infer_lds(m, lds_q) + (local ? (static_cast<size_t>(F) + 1 + 4) * sizeof(int32_t) : 0);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer_pairs),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   hipLaunchKernelGGL(k_mlp_infer_pairs, dim3(grid), dim3(256), lds, st, w, F, m, h, x, plist, pcnt, stride, N, pair,
-                     offsets, tile_prefix, dfo, local ? 1 : 0, big_min);
+                     offsets, tile_prefix, dfo, local ? 1 : 0, big_min, big_fixed, lds_q);
   LAUNCH_OK("mlp_infer_pairs");
 }
 

@@ -255,12 +255,14 @@ void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64
 // Pruning values for listed pairs only: filter f evaluates the entries
 // plist[f * stride + 0 .. pcnt[f]) (q * N + visit position) and writes
 // dfo[entry] = d^f(x[q]) - offsets[pair[q] * F + f].  A persistent grid walks
-// the non-empty 32-query tiles of all filters; their prefix over the filters
+// the non-empty query tiles of all filters; their prefix over the filters
 // is computed by every work-group itself for F <= 4096, else by a first
-// launch into tile_prefix [F + 1] (scratch).
+// launch into tile_prefix [F + 1] (scratch).  tile_mode: 0 = 32-query tiles,
+// or 64-query tiles when the batch has at least one 32-query tile per CU
+// (F <= 4096); 1 = always 32; 2 = always 64.  Values never depend on it.
 void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x, const int64_t *plist,
                             const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets,
-                            int32_t *tile_prefix, float *dfo, hipStream_t st);
+                            int32_t *tile_prefix, float *dfo, hipStream_t st, int tile_mode = 0);
 
 // Per-query offset row lookup for (k, target) pairs.
 // k is clamped to [1, kmax].

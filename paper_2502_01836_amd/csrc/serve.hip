@@ -225,6 +225,7 @@ void leafi_server::engine_round(int n_new, int &n_active) {
 
 void leafi_server::run() {
   int rc = guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     HIP_OK(hipSetDevice(ix->device));
     int n_active = 0;
     const int m = ix->m;
@@ -315,6 +316,7 @@ void leafi_default_server_opts(leafi_server_opts *o) {
 
 int leafi_server_create(leafi_index *ix, const leafi_server_opts *o, leafi_server **out) {
   return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
     require_built(ix);
     LEAFI_CHECK_ARG(o != nullptr && out != nullptr, "NULL argument");
     LEAFI_CHECK_ARG(o->k_max >= 1 && o->k_max <= 256, "k_max must be in [1, 256]");

@@ -53,6 +53,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(_lib.SearchOpts) == 4 * 4 + 8 * 4 + 4 + 3 * 4
     assert ctypes.sizeof(_lib.SearchStats) == 5 * 8 + 2 * 4 + 3 * 8 + 8
     assert ctypes.sizeof(_lib.Info) == 8 + 6 * 4 + 8 + 8
+    assert ctypes.sizeof(_lib.TrainOpts) == 6 * 4 + 2 * 8 + 6 * 4 + 8 + 2 * 4
 
 
 def test_null_handles_are_rejected_without_touching_the_gpu(lib):
@@ -64,7 +65,13 @@ def test_null_handles_are_rejected_without_touching_the_gpu(lib):
     o = _lib.SearchOpts()
     lib.leafi_default_search_opts(ctypes.byref(o))
     assert lib.leafi_search_knn(None, None, 0, None, None, ctypes.byref(o), None, None, None, None) == -1
-    assert lib.leafi_create(None) == -1
+    F, A = _lib.FREE_FN, _lib.ALLOC_FN
+    assert lib.leafi_create(A(), F(), None, None) == -1                     # out is NULL
+    h = ctypes.c_void_p()
+    only_alloc = A(lambda ctx, n, out: 1)
+    assert lib.leafi_create(only_alloc, F(), None, ctypes.byref(h)) == -1   # alloc without free
+    assert "both" in lib.leafi_last_error().decode() and not h.value
+    assert lib.leafi_get_examples(None, None, None, None, None, None, None, None) == -1
     # sizes are validated before any device work
     assert lib.leafi_znorm(None, -1, 8, None, None) == -1
     assert lib.leafi_mlp_infer(None, 1, 8, 3, None, 1, None, None) == -1   # hidden not a multiple of 4

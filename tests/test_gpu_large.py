@@ -41,6 +41,8 @@ def _check(ids, d, want_ids, want_d, xs, qs):
     assert np.array_equal(np.isfinite(d), fin)
     rel = np.where(fin, np.abs(d - want_d) / np.maximum(want_d, 1e-6), 0.0)
     assert rel.max() <= 1e-4, rel.max()
+    for row, f in zip(ids, fin):
+        assert len(np.unique(row[f])) == int(f.sum())
     for a, b in zip(*np.nonzero((ids != want_ids) & fin)):
         x = xs[ids[a, b]].astype(np.float64)
         dg = np.sqrt(((x - qs[a].astype(np.float64)) ** 2).sum())

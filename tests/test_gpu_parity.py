@@ -40,6 +40,9 @@ def assert_knn_parity(got_ids, got_d, want_ids, want_d, xs, qs):
     assert np.array_equal(np.isfinite(got_d), fin)
     assert np.all(np.abs(got_d[fin] - want_d[fin]) <= REL_D * np.maximum(want_d[fin], 1e-6))
     assert np.array_equal(got_ids[~fin], want_ids[~fin])
+    # a row never holds the same series twice (a rescanned row merged once)
+    for row, f in zip(got_ids, fin):
+        assert len(np.unique(row[f])) == int(f.sum()), row[f]
     bad = np.argwhere((got_ids != want_ids) & fin)
     for qi, j in bad:
         dg = _exact_d(xs, qs, qi, np.array([got_ids[qi, j]]))[0]
@@ -275,39 +278,75 @@ def _same_offsets(got, want):
     return np.allclose(got[~inf], want[~inf], rtol=1e-5, atol=1e-5)
 
 
-def test_calibration_matches_oracle(rw20k, seeded_filters):
-    pkg = rw20k["pkg"]
-    ix, m = rw20k["ix"], rw20k["m"]
-    sf = seeded_filters
-    ix.set_filters(sf["leaf_ids"], torch.from_numpy(sf["w"]).cuda(), sf["h"])
-    cq, _, _ = W.noisy_queries(rw20k["raw"], 150, (0.05, 0.2), 61, 62)
-    ks, targets = [1, 3], [0.8, 0.9, 0.99]
-    ix.calibrate(torch.from_numpy(cq).cuda(), ks, targets)
-    got = ix.offsets().reshape(len(ks), len(targets), -1)
+def _oracle_calibration_curves(rw20k, sf, cq, ks):
+    """The oracle's Algorithm 4 inputs and curves for calibration queries cq:
+    per k the (offsets [nc + 1, N], recall q [nc + 1]) curve."""
+    m = rw20k["m"]
     cqs = O.znorm(cq)
     qmu, qsd = O.query_stats(cqs, 16)
     lb = O.lower_bound(qmu, qsd, rw20k["boxes"], m)
     order = O.visit_order(lb)
-    ld, li = O.leaf_knn(rw20k["xs"], rw20k["tree"].leaves, cqs, 3)
+    ld, li = O.leaf_knn(rw20k["xs"], rw20k["tree"].leaves, cqs, max(ks))
     N = len(sf["leaf_ids"])
     df = np.stack([O.mlp_forward(sf["w"][f], cqs, m, sf["h"]) for f in range(N)], 1)
     leaf_of = np.empty(len(rw20k["xs"]), dtype=np.int64)
     for L, mem in enumerate(rw20k["tree"].leaves):
         leaf_of[mem] = L
     has = np.ones(N, dtype=bool)
-    mism = 0
-    for a, k in enumerate(ks):
+    curves = {}
+    for k in ks:
         dbsf = O.bsf_before(ld, order, k)
         ids, _ = O.knn(rw20k["xs"], cqs, k)
-        offs, q = O.autotune_curve(df, ld[:, :, 0], dbsf, leaf_of[ids], has)
+        curves[k] = O.autotune_curve(df, ld[:, :, 0], dbsf, leaf_of[ids], has)
+    return curves
+
+
+def test_calibration_matches_oracle(rw20k, seeded_filters):
+    ix = rw20k["ix"]
+    sf = seeded_filters
+    ix.set_filters(sf["leaf_ids"], torch.from_numpy(sf["w"]).cuda(), sf["h"])
+    cq, _, _ = W.noisy_queries(rw20k["raw"], 150, (0.05, 0.2), 61, 62)
+    ks, targets = [1, 3], [0.8, 0.9, 0.99]
+    ix.calibrate(torch.from_numpy(cq).cuda(), ks, targets)
+    got = ix.offsets().reshape(len(ks), len(targets), -1)
+    curves = _oracle_calibration_curves(rw20k, sf, cq, ks)
+    mism = 0
+    for a, k in enumerate(ks):
+        offs, q = curves[k]
         for b, t in enumerate(targets):
-            j, want = O.step_offsets(offs, q, t, len(cqs))
+            j, want = O.step_offsets(offs, q, t, len(cq))
             if not _same_offsets(got[a, b], want):
                 # only a neighbouring sorted position may be chosen (near-tie in the simulated recall)
                 alt = [offs[jj] for jj in (j - 1, j + 1) if 0 <= jj < len(offs)]
                 assert any(_same_offsets(got[a, b], x) for x in alt), (k, t)
                 mism += 1
     assert mism <= 1
+
+
+@pytest.mark.parametrize("corrected", [True, False])
+def test_steffen_calibration_matches_oracle(rw20k, seeded_filters, corrected):
+    """The paper's spline variant of Algorithm 4 (LEAFI_CALIB_STEFFEN): per filter,
+    Steffen's monotone interpolant of offset against simulated recall, against
+    the oracle's steffen_offsets on the same curves (1e-5 relative)."""
+    ix = rw20k["ix"]
+    sf = seeded_filters
+    ix.set_filters(sf["leaf_ids"], torch.from_numpy(sf["w"]).cuda(), sf["h"])
+    cq, _, _ = W.noisy_queries(rw20k["raw"], 150, (0.05, 0.2), 61, 62)
+    ks, targets = [1, 3], [0.5, 0.8, 0.9, 0.97, 0.99]
+    ix.calibrate(torch.from_numpy(cq).cuda(), ks, targets, mapping="steffen", corrected=corrected)
+    got = ix.offsets().reshape(len(ks), len(targets), -1)
+    curves = _oracle_calibration_curves(rw20k, sf, cq, ks)
+    n_interp = 0
+    for a, k in enumerate(ks):
+        offs, q = curves[k]
+        for b, t in enumerate(targets):
+            want = O.steffen_offsets(offs, q, t, len(cq), corrected=corrected)
+            assert np.array_equal(np.isinf(got[a, b]), np.isinf(want)), (k, t)
+            fin = np.isfinite(want)
+            assert np.allclose(got[a, b][fin], want[fin], rtol=1e-5, atol=1e-6), (k, t)
+            # count offsets strictly between two knots (not a knot value itself)
+            n_interp += int(sum(not np.isclose(want[f], offs[:, f]).any() for f in np.flatnonzero(fin)))
+    assert n_interp > 0  # the interpolating branch was exercised
 
 
 def test_trained_filters_reach_the_recall_target(rw20k):

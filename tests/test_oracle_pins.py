@@ -439,6 +439,50 @@ def test_steffen_knots_and_monotone():
         assert seg.min() >= min(y[i], y[i + 1]) - 1e-10 and seg.max() <= max(y[i], y[i + 1]) + 1e-10
 
 
+def test_steffen_offsets_hand_cases():
+    """The offset mapping's own rules, by hand: equal recalls keep the largest
+    offset, a target at or below the first recall takes that offset, a target
+    above the largest finite-offset recall turns the filter off, two knots
+    interpolate linearly, and a filter-less leaf stays +inf."""
+    inf = np.inf
+    # nc = 4 positions + the appended +inf row (recall 1)
+    q = np.array([0.5, 0.5, 0.75, 0.75, 1.0])
+    offs = np.array([[1.0, inf, 1.0],
+                     [2.0, inf, 1.5],
+                     [3.0, inf, 2.0],
+                     [5.0, inf, 4.0],
+                     [inf, inf, inf]])
+    # knots after dedupe: filter 0 (0.5, 2), (0.75, 5); filter 2 (0.5, 1.5), (0.75, 4)
+    got = O.steffen_offsets(offs, q, 0.5, 4, corrected=False)
+    assert got[0] == 2.0 and got[2] == 1.5          # largest offset at the repeated recall, not 1.0
+    assert np.isinf(got[1])                          # no filter on that leaf
+    got = O.steffen_offsets(offs, q, 0.3, 4, corrected=False)
+    assert got[0] == 2.0 and got[2] == 1.5          # below the first recall: first knot
+    got = O.steffen_offsets(offs, q, 0.8, 4, corrected=False)
+    assert np.isinf(got).all()                       # above the largest finite recall: filters off
+    got = O.steffen_offsets(offs, q, 0.625, 4, corrected=False)
+    assert got[0] == pytest.approx(3.5, abs=1e-12)  # 2 + 0.5 * (5 - 2)
+    assert got[2] == pytest.approx(2.75, abs=1e-12)  # 1.5 + 0.5 * (4 - 1.5)
+    got = O.steffen_offsets(offs, q, 0.75, 4, corrected=False)
+    assert got[0] == pytest.approx(5.0, abs=1e-12) and got[2] == pytest.approx(4.0, abs=1e-12)
+
+
+def test_steffen_offsets_collinear_and_corrected_target():
+    """Three collinear knots interpolate linearly (every Steffen slope equals the
+    common secant), and the corrected level ceil((nc + 1) t) / nc is what is
+    looked up."""
+    inf = np.inf
+    q = np.array([0.2, 0.4, 0.6, 1.0])               # nc = 3
+    offs = np.array([[1.0], [2.0], [3.0], [inf]])
+    assert O.steffen_offsets(offs, q, 0.5, 3, corrected=False)[0] == pytest.approx(2.5, abs=1e-12)
+    assert O.steffen_offsets(offs, q, 0.3, 3, corrected=False)[0] == pytest.approx(1.5, abs=1e-12)
+    # corrected: 0.3 -> ceil(1.2) / 3 = 2/3 > 0.6, the filter is switched off
+    assert np.isinf(O.steffen_offsets(offs, q, 0.3, 3, corrected=True)[0])
+    # corrected: 0.1 -> ceil(0.4) / 3 = 1/3, between the first two knots
+    assert O.steffen_offsets(offs, q, 0.1, 3, corrected=True)[0] == pytest.approx(1.0 + (1 / 3 - 0.2) / 0.2,
+                                                                                abs=1e-12)
+
+
 # ---------------------------------------------------------------- leaf selection (Algorithm 3)
 
 def test_select_leaves_cases():
