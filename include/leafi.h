@@ -325,6 +325,32 @@ int leafi_search_knn(leafi_index *index, const float *queries_dev, int64_t nq, c
                      const float *target_dev, const leafi_search_opts *opts, int64_t *ids_dev,
                      float *dists_dev, leafi_search_stats *stats, void *stream);
 
+/*
+ * The same search for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * It allocates nothing: every per-batch buffer is carved from one fixed
+ * device array of LEAFI_NOALLOC_SCRATCH_BYTES per GPU, owned by the library
+ * until the process ends; the caller still passes the inputs and outputs.
+ * Arguments, layouts and results are those of leafi_search_knn (results are
+ * bit-identical to it), with these limits:
+ *   - the batch must run as a planned launch sequence: BF16 scan, a schedule
+ *     containing a 0, neither LEAFI_SEARCH_HOST_ROUNDS nor statistics; it is
+ *     enqueued as plain launches (never captured by the library, no events);
+ *   - its buffers must fit the scratch array: a batch that needs more is
+ *     rejected with LEAFI_EINVAL before anything is enqueued (the message
+ *     states both sizes); fewer queries per call fit.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (each batch's first kernel zeroes the counters and control
+ * words a batch starts from): calls that overlap on one GPU -- from two
+ * threads, or on two streams without ordering between them -- race.  The
+ * array's device address is looked up on the first call on each device.  The
+ * call returns once the work is enqueued on `stream`.
+ */
+#define LEAFI_NOALLOC_SCRATCH_BYTES (256u << 20)
+int leafi_search_knn_noalloc(leafi_index *index, const float *queries_dev, int64_t nq, const int32_t *k_dev,
+                             const float *target_dev, const leafi_search_opts *opts, int64_t *ids_dev,
+                             float *dists_dev, void *stream);
+
 /* ------------------------------------------------------------------------
  * Scan tiling auto-tuner (no counterpart in the paper: it picks the BF16 leaf
  * scan's tile shape for this GPU and workload)

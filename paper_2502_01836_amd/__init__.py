@@ -253,6 +253,29 @@ class Index:
             return ids, dists, struct_dict(st)
         return ids, dists
 
+    def search_noalloc(self, queries, k, target, out, k_max: int, use_filters: bool = True, schedule=(1, 0),
+                       kprime: int = 0, flags: int = 0):
+        """leafi_search_knn_noalloc: the planned batch search with every buffer
+        carved from the library's fixed scratch area (nothing allocated).
+        k [nq] int32, target [nq] fp32 and out = (ids, dists) are device
+        tensors; results are written into out."""
+        torch = _torch()
+        nq = queries.shape[0]
+        o = _lib.SearchOpts()
+        load().leafi_default_search_opts(ctypes.byref(o))
+        o.k_max = k_max
+        o.use_filters = 1 if use_filters else 0
+        o.n_schedule = len(schedule)
+        for i, s_ in enumerate(schedule):
+            o.schedule[i] = s_
+        o.kprime = kprime
+        o.flags = flags
+        check(load().leafi_search_knn_noalloc(self._h, _dev(queries, torch.float32, "queries"), nq,
+                                              _dev(k, torch.int32, "k"), _dev(target, torch.float32, "target"),
+                                              ctypes.byref(o), _dev(out[0], torch.int64, "ids"),
+                                              _dev(out[1], torch.float32, "dists"), _stream()))
+        return out
+
     def searcher(self, queries, k, target, out, k_max: int, use_filters: bool = True, schedule=(1, 0),
                  kprime: int = 0, flags: int = 0, with_stats: bool = False):
         """A search bound to fixed device buffers (queries [nq, m] fp32, k [nq]

@@ -134,6 +134,7 @@ SIGNATURES = [
     ("leafi_default_search_opts", None, [ctypes.POINTER(SearchOpts)]),
     ("leafi_search_knn", ctypes.c_int, [P, P, I64, P, P, ctypes.POINTER(SearchOpts), P, P,
                                         ctypes.POINTER(SearchStats), P]),
+    ("leafi_search_knn_noalloc", ctypes.c_int, [P, P, I64, P, P, ctypes.POINTER(SearchOpts), P, P, P]),
     ("leafi_autotune", ctypes.c_int, [P, P, I64, P, P, ctypes.POINTER(SearchOpts), I32, ctypes.POINTER(TuneReport), P]),
     ("leafi_set_tiling", ctypes.c_int, [P, I32, I32]),
     ("leafi_default_server_opts", None, [ctypes.POINTER(ServerOpts)]),

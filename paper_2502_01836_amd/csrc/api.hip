@@ -411,16 +411,6 @@ int default_kprime(int kmax, bool bf16) {
 // Bytes of one leaf-store row as the scan of that precision reads it.
 int64_t scan_row_bytes(const leafi_index *ix, bool bf16) { return bf16 ? 2LL * ix->m + 4 : 4LL * ix->m; }
 
-struct SearchPlan {
-  int kmax = 1;
-  bool bf16 = true;
-  bool filters = false;
-  std::vector<int> schedule{1};
-  int kprime = 4;
-  bool graph = true;  // planned batches may be captured and replayed
-  int ftile = 0;      // filter inference tiles: 0 by batch size, 1 small, 2 large
-};
-
 // Queries, lower bounds, visit order, (k, target) pair, batch state.
 void begin_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
                  const SearchPlan &p, bool use_f, hipStream_t st) {
@@ -866,6 +856,32 @@ void check_queries(const leafi_index *ix, const float *q, int64_t nq) {
   (void)ix;
 }
 
+}  // namespace leafi
+
+namespace leafi {
+SearchPlan make_plan(const leafi_index *ix, const leafi_search_opts *o) {
+  LEAFI_CHECK_ARG(o != nullptr, "opts is NULL");
+  LEAFI_CHECK_ARG(o->k_max >= 1 && o->k_max <= 256, "k_max must be in [1, 256]");
+  LEAFI_CHECK_ARG(o->scan == LEAFI_SCAN_BF16 || o->scan == LEAFI_SCAN_FP32, "unknown scan kind");
+  LEAFI_CHECK_ARG(o->n_schedule >= 1 && o->n_schedule <= 8, "n_schedule must be in [1, 8]");
+  for (int i = 0; i < o->n_schedule; ++i) LEAFI_CHECK_ARG(o->schedule[i] >= 0, "schedule entries must be >= 0");
+  LEAFI_CHECK_ARG(o->kprime >= 0 && o->kprime <= 256, "kprime must be in [0, 256]");
+  LEAFI_CHECK_ARG((o->flags & ~(LEAFI_SEARCH_NO_GRAPH | LEAFI_SEARCH_HOST_ROUNDS | LEAFI_SEARCH_FILTER_TILE_SMALL |
+                                 LEAFI_SEARCH_FILTER_TILE_LARGE)) == 0,
+                  "unknown search flags");
+  LEAFI_CHECK_ARG((o->flags & LEAFI_SEARCH_FILTER_TILE_SMALL) == 0 || (o->flags & LEAFI_SEARCH_FILTER_TILE_LARGE) == 0,
+                  "FILTER_TILE_SMALL and FILTER_TILE_LARGE exclude each other");
+  LEAFI_CHECK_ARG(o->scan != LEAFI_SCAN_BF16 || ix->m <= 256, "the bf16 scan supports m <= 256");
+  SearchPlan p;
+  p.kmax = o->k_max;
+  p.bf16 = o->scan == LEAFI_SCAN_BF16;
+  p.filters = o->use_filters != 0;
+  p.schedule.assign(o->schedule, o->schedule + o->n_schedule);
+  p.kprime = o->kprime > 0 ? std::max<int>(o->kprime, p.kmax) : default_kprime(p.kmax, p.bf16);
+  p.graph = (o->flags & LEAFI_SEARCH_NO_GRAPH) == 0;
+  p.ftile = (o->flags & LEAFI_SEARCH_FILTER_TILE_SMALL) ? 1 : (o->flags & LEAFI_SEARCH_FILTER_TILE_LARGE) ? 2 : 0;
+  return p;
+}
 }  // namespace leafi
 
 // =============================================================================
@@ -1461,31 +1477,6 @@ void leafi_default_search_opts(leafi_search_opts *o) {
   o->kprime = 0;
 }
 
-namespace leafi {
-SearchPlan make_plan(const leafi_index *ix, const leafi_search_opts *o) {
-  LEAFI_CHECK_ARG(o != nullptr, "opts is NULL");
-  LEAFI_CHECK_ARG(o->k_max >= 1 && o->k_max <= 256, "k_max must be in [1, 256]");
-  LEAFI_CHECK_ARG(o->scan == LEAFI_SCAN_BF16 || o->scan == LEAFI_SCAN_FP32, "unknown scan kind");
-  LEAFI_CHECK_ARG(o->n_schedule >= 1 && o->n_schedule <= 8, "n_schedule must be in [1, 8]");
-  for (int i = 0; i < o->n_schedule; ++i) LEAFI_CHECK_ARG(o->schedule[i] >= 0, "schedule entries must be >= 0");
-  LEAFI_CHECK_ARG(o->kprime >= 0 && o->kprime <= 256, "kprime must be in [0, 256]");
-  LEAFI_CHECK_ARG((o->flags & ~(LEAFI_SEARCH_NO_GRAPH | LEAFI_SEARCH_HOST_ROUNDS | LEAFI_SEARCH_FILTER_TILE_SMALL |
-                                 LEAFI_SEARCH_FILTER_TILE_LARGE)) == 0,
-                  "unknown search flags");
-  LEAFI_CHECK_ARG((o->flags & LEAFI_SEARCH_FILTER_TILE_SMALL) == 0 || (o->flags & LEAFI_SEARCH_FILTER_TILE_LARGE) == 0,
-                  "FILTER_TILE_SMALL and FILTER_TILE_LARGE exclude each other");
-  LEAFI_CHECK_ARG(o->scan != LEAFI_SCAN_BF16 || ix->m <= 256, "the bf16 scan supports m <= 256");
-  SearchPlan p;
-  p.kmax = o->k_max;
-  p.bf16 = o->scan == LEAFI_SCAN_BF16;
-  p.filters = o->use_filters != 0;
-  p.schedule.assign(o->schedule, o->schedule + o->n_schedule);
-  p.kprime = o->kprime > 0 ? std::max<int>(o->kprime, p.kmax) : default_kprime(p.kmax, p.bf16);
-  p.graph = (o->flags & LEAFI_SEARCH_NO_GRAPH) == 0;
-  p.ftile = (o->flags & LEAFI_SEARCH_FILTER_TILE_SMALL) ? 1 : (o->flags & LEAFI_SEARCH_FILTER_TILE_LARGE) ? 2 : 0;
-  return p;
-}
-}  // namespace leafi
 
 int leafi_search_knn(leafi_index *ix, const float *queries, int64_t nq, const int32_t *k_dev, const float *t_dev,
                      const leafi_search_opts *o, int64_t *ids, float *dists, leafi_search_stats *stats,

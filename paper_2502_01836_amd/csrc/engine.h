@@ -88,4 +88,24 @@ constexpr double kPlannedLimit = 8.0 * (1 << 30);
 double round_bytes_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, bool bf16, int kprime, int kmax);
 int default_kprime(int kmax, bool bf16);
 
+// How a batch search runs (from leafi_search_opts).
+struct SearchPlan {
+  int kmax = 1;
+  bool bf16 = true;
+  bool filters = false;
+  std::vector<int> schedule{1};
+  int kprime = 4;
+  bool graph = true;  // planned batches may be captured and replayed
+  int ftile = 0;      // filter inference tiles: 0 by batch size, 1 small, 2 large
+};
+SearchPlan make_plan(const leafi_index *ix, const leafi_search_opts *o);
+void check_queries(const leafi_index *ix, const float *q, int64_t nq);
+// Whether the batch can run as a planned launch sequence (no read-back).
+bool can_plan(const leafi_index *ix, int64_t nq, const SearchPlan &p);
+// Reserve every buffer of a planned batch at its bound (no allocation after).
+void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_f);
+// Enqueue the planned launch sequence of a batch on `st`.
+void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
+                     const SearchPlan &p, bool use_f, int64_t *ids, float *dists, bool timed, hipStream_t st);
+
 }  // namespace leafi
