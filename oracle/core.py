@@ -99,6 +99,28 @@ def knn(data_s: np.ndarray, q_s: np.ndarray, k: int):
     return ids, d
 
 
+def knn_stream(chunks, q_s: np.ndarray, k: int):
+    """Exact k-NN over a collection given in consecutive raw chunks (an iterable
+    of (first row id, raw fp32 rows)): each chunk is z-normalised (znorm) and
+    searched by brute force (knn), and the running k best are kept by (d, id).
+    The same result as knn over the whole normalised collection; for
+    collections too large to hold normalised on the host at once."""
+    q_s = np.ascontiguousarray(q_s, dtype=np.float32)
+    nq = q_s.shape[0]
+    best_d = np.full((nq, k), np.inf)
+    best_i = np.full((nq, k), -1, dtype=np.int64)
+    for lo, raw in chunks:
+        ids, d = knn(znorm(raw), q_s, min(k, len(raw)))
+        cat_d = np.concatenate([best_d, d], axis=1)
+        cat_i = np.concatenate([best_i, ids + lo], axis=1)
+        # (d, id) order; empty slots (+inf, -1) sort last
+        key_i = np.where(cat_i < 0, np.iinfo(np.int64).max, cat_i)
+        o = np.lexsort((key_i, cat_d), axis=1)[:, :k]
+        best_d = np.take_along_axis(cat_d, o, axis=1)
+        best_i = np.take_along_axis(cat_i, o, axis=1)
+    return best_i, best_d
+
+
 def leaf_knn(data_s: np.ndarray, leaves: list, q_s: np.ndarray, k: int):
     """Per-leaf exact k-NN: d [nq, N, k] and ids [nq, N, k]; d[:, L, 0] is d^L(q, L)."""
     order = np.concatenate(leaves).astype(np.int64)

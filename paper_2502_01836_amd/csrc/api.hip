@@ -114,18 +114,19 @@ __global__ void k_item_cert(int64_t n_items, int kmax, RoundBufs b) {
     b.fb_leaf[slot] = b.item_leaf[it];
   }
 }
-// Training examples from items: d^L of (query, filtered leaf).
+// Training examples from items: d^L of (query, filtered leaf); item query
+// indices are relative to the chunk starting at training query q_off.
 __global__ void k_items_to_examples(int64_t n_items, int kmax, RoundBufs b, const int32_t *filt_of_leaf, int n_g,
-                                    int n_gt, int n_l, int n_ex, float *ex_y) {
+                                    int n_gt, int n_l, int n_ex, float *ex_y, int64_t q_off) {
   int64_t it = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (it >= n_items) return;
-  int q = b.item_q[it];
+  int64_t q = b.item_q[it] + q_off;
   int f = filt_of_leaf[b.item_leaf[it]];
   if (f < 0) return;
-  int e;
+  int64_t e;
   if (q < n_gt) e = q;
   else if (q < n_g) e = n_gt + n_l + (q - n_gt);
-  else e = n_gt + (q - n_g - f * n_l);
+  else e = n_gt + (q - n_g - static_cast<int64_t>(f) * n_l);
   ex_y[static_cast<int64_t>(f) * n_ex + e] = static_cast<float>(sqrt(b.item_d2[it * kmax]));
 }
 
@@ -169,6 +170,7 @@ RoundBufs views(Workspace &w) {
   b.chunk = kChunkRows;
   b.use_tau = 0;
   b.ctl = w.ctl.get();
+  b.leaf_n = w.leaf_n;
   return b;
 }
 
@@ -224,6 +226,7 @@ void ensure_queries(leafi_index *ix, int64_t nq, int kmax) {
   w.leaf_istart.reserve(N + 1);
   w.tile_start.reserve(N + 1);
   w.ctl.reserve(kCtlCount);
+  w.leaf_n = ix->leaf_n.get();
   if (w.h_ctl.size() < static_cast<size_t>(kCtlCount)) w.h_ctl.resize(kCtlCount);
   if (!w.ev0 && !t_arena) {
     // timing-only events: no system-scope fence (no cache write-back) around the kernels they bracket
@@ -1232,44 +1235,55 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     h2d(drows.get(), rows.data(), nqt, st);
     h2d(dsig.get(), sig.data(), nqt, st);
     launch_make_queries(ix->x32.get(), drows.get(), dsig.get(), nqt, m, o->seed, qraw.get(), st);
-    ensure_queries(ix, nqt, 1);
-    prep_queries(ix, qraw.get(), nqt, st);
-    if (o->keep_examples) ix->examples.q = std::move(qraw);
-    else qraw.release();
 
-    // ---- targets d^L with the leaf scan: global x filtered leaves, local x own leaf
+    // ---- targets d^L with the leaf scan: global queries x filtered leaves,
+    // local queries x their own leaf.  Queries go in chunks that bound the
+    // round's item buffers (about kChunkItems items) and the per-query
+    // buffers strided by the leaf count; each chunk's normalised queries are
+    // kept as the SGD inputs.
     auto t0 = std::chrono::steady_clock::now();
-    std::vector<int64_t> loff(nqt + 1, 0);
-    std::vector<int32_t> lst;
-    lst.reserve(static_cast<size_t>(n_g) * F + static_cast<size_t>(F) * n_l);
-    for (int j = 0; j < n_g; ++j) {
-      lst.insert(lst.end(), sel.begin(), sel.end());
-      loff[j + 1] = loff[j] + F;
-    }
-    for (int f = 0; f < F; ++f)
-      for (int j = 0; j < n_l; ++j) {
-        int64_t i = n_g + static_cast<int64_t>(f) * n_l + j;
-        lst.push_back(sel[f]);
-        loff[i + 1] = loff[i] + 1;
-      }
-    DevBuf<int64_t> dloff(nqt + 1);
-    DevBuf<int32_t> dlst(lst.size());
-    h2d(dloff.get(), loff.data(), loff.size(), st);
-    h2d(dlst.get(), lst.data(), lst.size(), st);
-    fill_i32(w.kq.get(), nqt, 1, st);
-    reset_round(ix, st);
-    hipLaunchKernelGGL(k_fill_lists, dim3(ceil_div(nqt, 256)), dim3(256), 0, st, w.qitem_leaf.get(),
-                       w.qitem_cnt.get(), w.leaf_cnt.get(), nqt, N, dloff.get(), dlst.get());
-    LAUNCH_OK("fill_lists");
     const int n_ex = n_g + n_l, n_train = n_gt + n_l;
+    DevBuf<float> xq(static_cast<size_t>(nqt) * m);
     DevBuf<float> ex_y(static_cast<size_t>(F) * n_ex);
     Timing tcol;
-    allpairs_items(ix, nqt, 1, st, [&](int64_t items) {
-      hipLaunchKernelGGL(k_items_to_examples, dim3(ceil_div(items, 256)), dim3(256), 0, st, items, 1, views(w),
-                         ix->filt.filt_of_leaf.get(), n_g, n_gt, n_l, n_ex, ex_y.get());
-      LAUNCH_OK("items_to_examples");
-    }, &tcol);
-    HIP_OK(hipStreamSynchronize(st));
+    constexpr int64_t kChunkItems = int64_t(1) << 22;
+    const int64_t per_query_bytes = static_cast<int64_t>(N) * 6 * 4 + static_cast<int64_t>(F) * 4;
+    const int64_t max_chunk = std::max<int64_t>(1, std::min<int64_t>(kChunkItems, (int64_t(3) << 30) / per_query_bytes));
+    auto collect = [&](int64_t q0, int64_t q1) {
+      const int64_t nc = q1 - q0;
+      std::vector<int64_t> loff(nc + 1, 0);
+      std::vector<int32_t> lst;
+      for (int64_t j = q0; j < q1; ++j) {
+        if (j < n_g) lst.insert(lst.end(), sel.begin(), sel.end());
+        else lst.push_back(sel[(j - n_g) / n_l]);
+        loff[j - q0 + 1] = static_cast<int64_t>(lst.size());
+      }
+      ensure_queries(ix, nc, 1);
+      launch_qprep(qraw.get() + q0 * m, nc, m, ix->S, w.q32.get(), w.q16.get(), w.qn16.get(), w.qeps.get(),
+                   w.qstat.get(), st);
+      HIP_OK(hipMemcpyAsync(xq.get() + q0 * m, w.q32.get(), static_cast<size_t>(nc) * m * sizeof(float),
+                            hipMemcpyDeviceToDevice, st));
+      DevBuf<int64_t> dloff(nc + 1);
+      DevBuf<int32_t> dlst(lst.size());
+      h2d(dloff.get(), loff.data(), loff.size(), st);
+      h2d(dlst.get(), lst.data(), lst.size(), st);
+      fill_i32(w.kq.get(), nc, 1, st);
+      reset_round(ix, st);
+      hipLaunchKernelGGL(k_fill_lists, dim3(ceil_div(nc, 256)), dim3(256), 0, st, w.qitem_leaf.get(),
+                         w.qitem_cnt.get(), w.leaf_cnt.get(), nc, N, dloff.get(), dlst.get());
+      LAUNCH_OK("fill_lists");
+      allpairs_items(ix, nc, 1, st, [&](int64_t items) {
+        hipLaunchKernelGGL(k_items_to_examples, dim3(ceil_div(items, 256)), dim3(256), 0, st, items, 1, views(w),
+                           ix->filt.filt_of_leaf.get(), n_g, n_gt, n_l, n_ex, ex_y.get(), q0);
+        LAUNCH_OK("items_to_examples");
+      }, &tcol);
+      HIP_OK(hipStreamSynchronize(st));  // the chunk's lists are freed on return
+    };
+    const int64_t g_chunk = std::max<int64_t>(1, std::min<int64_t>(max_chunk, kChunkItems / F));
+    for (int64_t q0 = 0; q0 < n_g; q0 += g_chunk) collect(q0, std::min<int64_t>(n_g, q0 + g_chunk));
+    for (int64_t q0 = n_g; q0 < nqt; q0 += max_chunk) collect(q0, std::min<int64_t>(nqt, q0 + max_chunk));
+    if (o->keep_examples) ix->examples.q = std::move(qraw);
+    else qraw.release();
     auto t1 = std::chrono::steady_clock::now();
     report.ms_collect = std::chrono::duration<double, std::milli>(t1 - t0).count();
 
@@ -1300,7 +1314,7 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     TrainArgs ta;
     ta.w = ix->filt.w.get();
     ta.w_best = wbest.get();
-    ta.xq = w.q32.get();
+    ta.xq = xq.get();
     ta.ex_q = dexq.get();
     ta.ex_y = ex_y.get();
     ta.n_train = n_train;

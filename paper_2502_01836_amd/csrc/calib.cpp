@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <thread>
 
 #include "index.h"
 
@@ -85,32 +86,54 @@ std::vector<float> calibrate_k(const CalibInput &in, int k, const std::vector<fl
   std::vector<int32_t> filt_of_leaf(N, -1);
   for (int f = 0; f < F; ++f) filt_of_leaf[in.leaf_of_filter[f]] = f;
 
-  // true top-k leaves and d^bsf along each query's visit order
+  // true top-k leaves and d^bsf along each query's visit order: the k best
+  // (distance, id) so far, merged with each leaf's sorted list in turn
+  // (queries split over host threads; each query's result is its own)
   std::vector<int32_t> nbr_leaf(static_cast<size_t>(nc) * k, -1);
   std::vector<double> dbsf(static_cast<size_t>(nc) * N, inf);
-  for (int c = 0; c < nc; ++c) {
-    std::vector<std::pair<double, int64_t>> pool;  // k best (distance, id) so far
-    struct Cand {
-      double d;
-      int64_t id;
-      int32_t leaf;
-    };
-    std::vector<Cand> all;
-    for (int pos = 0; pos < N; ++pos) {
-      int L = in.order[static_cast<size_t>(c) * N + pos];
-      dbsf[static_cast<size_t>(c) * N + L] = static_cast<int>(pool.size()) >= k ? pool[k - 1].first : inf;
-      const double *ld = &in.leaf_d[(static_cast<size_t>(c) * N + L) * K];
-      const int64_t *li = &in.leaf_ids[(static_cast<size_t>(c) * N + L) * K];
-      for (int e = 0; e < k && e < K; ++e) {
-        if (li[e] < 0) break;
-        pool.emplace_back(ld[e], li[e]);
-        all.push_back({ld[e], li[e], L});
+  struct Entry {
+    double d;
+    int64_t id;
+    int32_t leaf;
+    bool operator<(const Entry &o) const { return d < o.d || (d == o.d && id < o.id); }
+  };
+  const unsigned hc = std::thread::hardware_concurrency();
+  const int nthreads = static_cast<int>(std::max(1u, std::min({hc == 0 ? 1u : hc, 16u, static_cast<unsigned>(nc)})));
+  auto per_query = [&](int c0, int c1) {
+    std::vector<Entry> pool, lst, merged;
+    pool.reserve(k);
+    lst.reserve(k);
+    merged.reserve(k);
+    for (int c = c0; c < c1; ++c) {
+      pool.clear();
+      for (int pos = 0; pos < N; ++pos) {
+        const int L = in.order[static_cast<size_t>(c) * N + pos];
+        dbsf[static_cast<size_t>(c) * N + L] = static_cast<int>(pool.size()) >= k ? pool[k - 1].d : inf;
+        const double *ld = &in.leaf_d[(static_cast<size_t>(c) * N + L) * K];
+        const int64_t *li = &in.leaf_ids[(static_cast<size_t>(c) * N + L) * K];
+        lst.clear();
+        for (int e = 0; e < k && e < K; ++e) {
+          if (li[e] < 0) break;
+          lst.push_back({ld[e], li[e], L});
+        }
+        if (!std::is_sorted(lst.begin(), lst.end())) std::sort(lst.begin(), lst.end());
+        merged.clear();
+        size_t a = 0, b = 0;
+        while (static_cast<int>(merged.size()) < k && (a < pool.size() || b < lst.size())) {
+          if (b >= lst.size() || (a < pool.size() && pool[a] < lst[b])) merged.push_back(pool[a++]);
+          else merged.push_back(lst[b++]);
+        }
+        pool.swap(merged);
       }
-      std::sort(pool.begin(), pool.end());
-      if (static_cast<int>(pool.size()) > k) pool.resize(k);
+      for (size_t e = 0; e < pool.size(); ++e) nbr_leaf[static_cast<size_t>(c) * k + e] = pool[e].leaf;
     }
-    std::sort(all.begin(), all.end(), [](const Cand &a, const Cand &b) { return a.d < b.d || (a.d == b.d && a.id < b.id); });
-    for (int e = 0; e < k && e < static_cast<int>(all.size()); ++e) nbr_leaf[static_cast<size_t>(c) * k + e] = all[e].leaf;
+  };
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthreads; ++t)
+      th.emplace_back(per_query, static_cast<int>(static_cast<int64_t>(nc) * t / nthreads),
+                      static_cast<int>(static_cast<int64_t>(nc) * (t + 1) / nthreads));
+    for (auto &x : th) x.join();
   }
 
   // sorted non-conformity scores per filter

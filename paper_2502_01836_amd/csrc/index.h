@@ -133,6 +133,7 @@ struct Workspace {
   DevBuf<int32_t> ptile;        // prefix of the filters' 16-query inference tiles [F + 1]
   DevBuf<int64_t> ctl;
   std::vector<int64_t> h_ctl;
+  const int32_t *leaf_n = nullptr;  // the index's leaf sizes (device), for views()
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> sev;  // per planned round: scan begin / end
   GraphCache graphs;

@@ -208,7 +208,7 @@ __device__ inline void leaf_scan_body(int N, const int64_t *__restrict__ leaf_of
     int64_t chunks = (leaf_off[L + 1] - leaf_off[L] + b.chunk - 1) / b.chunk;
     si += c;
     stl += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
-    if (c > 0) rows += leaf_off[L + 1] - leaf_off[L];
+    if (c > 0) rows += b.leaf_n[L];
   }
   // item and tile counts share one scan (each total < 2^31: packed as
   // items + tiles * 2^32, the low half never carries), rows a second

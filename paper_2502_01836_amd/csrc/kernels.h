@@ -74,6 +74,8 @@ struct RoundBufs {
   int32_t *fb_leaf;
   // control: see Ctl
   int64_t *ctl;
+  // [N] real (unpadded) series per leaf: the algorithmic bytes of a round
+  const int32_t *leaf_n;
   // rows per scan tile of the pass in flight (a multiple of kRowAlign)
   int32_t chunk;
   // 1: a search round, whose BF16 scan may skip rows provably farther than

@@ -9,8 +9,17 @@
 // members with value <= lo + (hi - lo) / 2 go left, with the median rule as
 // fallback when one side would be empty.  Leaves are numbered depth-first,
 // left child first; members stay in ascending id order.
+//
+// Large nodes are processed with several host threads: the member ranges in
+// one pass over each member's contiguous summary row (per-thread partial
+// ranges, combined in thread order), the split column gathered once, and the
+// two children built concurrently.  Every decision is the same as a
+// sequential build: min / max and the selection by (value, id) do not depend
+// on the order of evaluation.
 #include <algorithm>
 #include <cmath>
+#include <future>
+#include <thread>
 
 #include "index.h"
 
@@ -18,77 +27,129 @@ namespace leafi {
 
 namespace {
 
+// Host threads for the tree build (the machine's, at most 16).
+int build_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return static_cast<int>(std::max(1u, std::min(hc == 0 ? 1u : hc, 16u)));
+}
+
+// Run fn(t, lo, hi) over [0, n) split into `parts` contiguous ranges.
+template <typename Fn>
+void parallel_ranges(int64_t n, int parts, Fn fn) {
+  if (parts <= 1 || n < 2) {
+    fn(0, int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < parts; ++t) {
+    const int64_t lo = n * t / parts, hi = n * (t + 1) / parts;
+    th.emplace_back([=] { fn(t, lo, hi); });
+  }
+  for (auto &x : th) x.join();
+}
+
+constexpr int64_t kParallelMin = 1 << 18;  // members below which a node is handled by one thread
+
 struct Builder {
   const std::vector<float> &mu, &sd;
   int S;
   int capacity;
   int rule;
   std::vector<double> seglen;
-  TreeResult out;
+  int threads;
 
-  float stat(int64_t id, int s, int st) const { return st == 0 ? mu[id * S + s] : sd[id * S + s]; }
-
-  void split(std::vector<int64_t> &&ids) {
+  // Leaves of the subtree rooted at the node holding `ids` (ascending), depth-first.
+  std::vector<std::vector<int64_t>> split(std::vector<int64_t> &&ids, int budget) {
+    std::vector<std::vector<int64_t>> leaves;
     if (static_cast<int64_t>(ids.size()) <= capacity) {
-      out.leaves.push_back(std::move(ids));
-      return;
+      leaves.push_back(std::move(ids));
+      return leaves;
     }
+    const int64_t n = static_cast<int64_t>(ids.size());
+    const int parts = n >= kParallelMin ? std::max(1, budget) : 1;
+    // member ranges of every (segment, statistic): per-thread partials
+    std::vector<float> lo(static_cast<size_t>(parts) * 2 * S, INFINITY), hi(static_cast<size_t>(parts) * 2 * S, -INFINITY);
+    parallel_ranges(n, parts, [&](int t, int64_t a, int64_t b) {
+      float *l = &lo[static_cast<size_t>(t) * 2 * S], *h = &hi[static_cast<size_t>(t) * 2 * S];
+      for (int64_t i = a; i < b; ++i) {
+        const float *rm = &mu[ids[i] * S], *rs = &sd[ids[i] * S];
+        for (int s = 0; s < S; ++s) {
+          l[2 * s] = std::min(l[2 * s], rm[s]);
+          h[2 * s] = std::max(h[2 * s], rm[s]);
+          l[2 * s + 1] = std::min(l[2 * s + 1], rs[s]);
+          h[2 * s + 1] = std::max(h[2 * s + 1], rs[s]);
+        }
+      }
+    });
     double best = -1.0;
     int bs = 0, bst = 0;
+    float blo = 0.0f, bhi = 0.0f;
     for (int s = 0; s < S; ++s) {
       for (int st = 0; st < 2; ++st) {
-        float lo = stat(ids[0], s, st), hi = lo;
-        for (int64_t id : ids) {
-          float v = stat(id, s, st);
-          lo = v < lo ? v : lo;
-          hi = v > hi ? v : hi;
+        float l = INFINITY, h = -INFINITY;
+        for (int t = 0; t < parts; ++t) {
+          l = std::min(l, lo[static_cast<size_t>(t) * 2 * S + 2 * s + st]);
+          h = std::max(h, hi[static_cast<size_t>(t) * 2 * S + 2 * s + st]);
         }
-        double d = static_cast<double>(hi) - static_cast<double>(lo);
-        double score = seglen[s] * (d * d);
+        const double d = static_cast<double>(h) - static_cast<double>(l);
+        const double score = seglen[s] * (d * d);
         if (score > best) {
           best = score;
           bs = s;
           bst = st;
+          blo = l;
+          bhi = h;
         }
       }
     }
-    std::vector<char> go_left(ids.size(), 0);
+    // the split column, gathered once
+    const std::vector<float> &src = bst == 0 ? mu : sd;
+    std::vector<float> col(n);
+    parallel_ranges(n, parts, [&](int, int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) col[i] = src[ids[i] * S + bs];
+    });
+    std::vector<char> go_left(n, 0);
     bool done = false;
     if (rule == 1) {
-      double lo = stat(ids[0], bs, bst), hi = lo;
-      for (int64_t id : ids) {
-        double v = stat(id, bs, bst);
-        lo = std::min(lo, v);
-        hi = std::max(hi, v);
-      }
-      double mid = lo + (hi - lo) / 2.0;
-      size_t nl = 0;
-      for (size_t i = 0; i < ids.size(); ++i) {
-        go_left[i] = static_cast<double>(stat(ids[i], bs, bst)) <= mid;
+      const double mid = static_cast<double>(blo) + (static_cast<double>(bhi) - static_cast<double>(blo)) / 2.0;
+      int64_t nl = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        go_left[i] = static_cast<double>(col[i]) <= mid;
         nl += go_left[i];
       }
-      done = nl > 0 && nl < ids.size();
+      done = nl > 0 && nl < n;
     }
     if (!done) {
-      // the ceil(n/2) smallest members by (value, id)
-      std::vector<size_t> idx(ids.size());
-      for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
-      size_t nl = (ids.size() + 1) / 2;
-      auto less = [&](size_t a, size_t b) {
-        float va = stat(ids[a], bs, bst), vb = stat(ids[b], bs, bst);
-        return va < vb || (va == vb && ids[a] < ids[b]);
-      };
+      // the ceil(n/2) smallest members by (value, id); ids ascending, so the
+      // position breaks value ties exactly as the id does
+      std::vector<int64_t> idx(n);
+      for (int64_t i = 0; i < n; ++i) idx[i] = i;
+      const int64_t nl = (n + 1) / 2;
+      auto less = [&](int64_t a, int64_t b) { return col[a] < col[b] || (col[a] == col[b] && a < b); };
       std::nth_element(idx.begin(), idx.begin() + (nl - 1), idx.end(), less);
-      size_t pivot = idx[nl - 1];
-      for (size_t i = 0; i < ids.size(); ++i) go_left[i] = !less(pivot, i);
+      const int64_t pivot = idx[nl - 1];
+      for (int64_t i = 0; i < n; ++i) go_left[i] = !less(pivot, i);
     }
     std::vector<int64_t> left, right;
-    left.reserve(ids.size() / 2 + 1);
-    right.reserve(ids.size() / 2 + 1);
-    for (size_t i = 0; i < ids.size(); ++i) (go_left[i] ? left : right).push_back(ids[i]);
+    left.reserve(n / 2 + 1);
+    right.reserve(n / 2 + 1);
+    for (int64_t i = 0; i < n; ++i) (go_left[i] ? left : right).push_back(ids[i]);
     std::vector<int64_t>().swap(ids);
-    split(std::move(left));
-    split(std::move(right));
+    std::vector<float>().swap(col);
+    std::vector<char>().swap(go_left);
+    if (budget > 1 && n >= kParallelMin) {
+      // the two children concurrently, each with half of the threads
+      const int bl = budget / 2, br = budget - bl;
+      auto fut = std::async(std::launch::async, [&, bl] { return split(std::move(left), bl); });
+      std::vector<std::vector<int64_t>> r = split(std::move(right), br);
+      leaves = fut.get();
+      for (auto &v : r) leaves.push_back(std::move(v));
+    } else {
+      leaves = split(std::move(left), budget);
+      std::vector<std::vector<int64_t>> r = split(std::move(right), budget);
+      for (auto &v : r) leaves.push_back(std::move(v));
+    }
+    return leaves;
   }
 };
 
@@ -96,37 +157,45 @@ struct Builder {
 
 TreeResult build_tree(const std::vector<float> &seg_mu, const std::vector<float> &seg_sd, int64_t n, int S, int m,
                       int capacity, int rule) {
-  Builder b{seg_mu, seg_sd, S, capacity, rule, {}, {}};
+  Builder b{seg_mu, seg_sd, S, capacity, rule, {}, build_threads()};
   b.seglen.resize(S);
   for (int s = 0; s < S; ++s) b.seglen[s] = static_cast<double>(((s + 1) * m) / S - (s * m) / S);
   std::vector<int64_t> all(n);
   for (int64_t i = 0; i < n; ++i) all[i] = i;
-  b.split(std::move(all));
-  return std::move(b.out);
+  TreeResult out;
+  out.leaves = b.split(std::move(all), b.threads);
+  return out;
 }
 
 std::vector<float> leaf_boxes(const std::vector<float> &seg_mu, const std::vector<float> &seg_sd, int S,
                               const TreeResult &t) {
-  size_t N = t.leaves.size();
-  std::vector<float> box(N * S * 4);
-  for (size_t L = 0; L < N; ++L) {
-    const auto &mem = t.leaves[L];
-    for (int s = 0; s < S; ++s) {
-      float mlo = seg_mu[mem[0] * S + s], mhi = mlo, slo = seg_sd[mem[0] * S + s], shi = slo;
-      for (int64_t id : mem) {
-        float a = seg_mu[id * S + s], b = seg_sd[id * S + s];
-        mlo = std::min(mlo, a);
-        mhi = std::max(mhi, a);
-        slo = std::min(slo, b);
-        shi = std::max(shi, b);
+  const int64_t N = static_cast<int64_t>(t.leaves.size());
+  std::vector<float> box(static_cast<size_t>(N) * S * 4);
+  parallel_ranges(N, N >= 64 ? build_threads() : 1, [&](int, int64_t a, int64_t b) {
+    for (int64_t L = a; L < b; ++L) {
+      const auto &mem = t.leaves[L];
+      float *o = &box[static_cast<size_t>(L) * S * 4];
+      for (int s = 0; s < S; ++s) {
+        o[4 * s + 0] = o[4 * s + 2] = INFINITY;
+        o[4 * s + 1] = o[4 * s + 3] = -INFINITY;
       }
-      float *o = &box[(L * S + s) * 4];
-      o[0] = std::nextafter(mlo, -INFINITY);
-      o[1] = std::nextafter(mhi, INFINITY);
-      o[2] = std::nextafter(slo, -INFINITY);
-      o[3] = std::nextafter(shi, INFINITY);
+      for (int64_t id : mem) {
+        const float *rm = &seg_mu[id * S], *rs = &seg_sd[id * S];
+        for (int s = 0; s < S; ++s) {
+          o[4 * s + 0] = std::min(o[4 * s + 0], rm[s]);
+          o[4 * s + 1] = std::max(o[4 * s + 1], rm[s]);
+          o[4 * s + 2] = std::min(o[4 * s + 2], rs[s]);
+          o[4 * s + 3] = std::max(o[4 * s + 3], rs[s]);
+        }
+      }
+      for (int s = 0; s < S; ++s) {
+        o[4 * s + 0] = std::nextafter(o[4 * s + 0], -INFINITY);
+        o[4 * s + 1] = std::nextafter(o[4 * s + 1], INFINITY);
+        o[4 * s + 2] = std::nextafter(o[4 * s + 2], -INFINITY);
+        o[4 * s + 3] = std::nextafter(o[4 * s + 3], INFINITY);
+      }
     }
-  }
+  });
   return box;
 }
 

@@ -69,6 +69,26 @@ def test_knn_matches_stable_argsort_with_planted_ties():
     assert list(ids[1, :2]) == [50, 1200]
 
 
+def test_knn_stream_equals_knn_over_the_whole_collection():
+    """Chunked brute force (for collections too large for the host) = brute force
+    over everything, including ties split across chunks and short chunks."""
+    raw = W.random_walk(2300, 32, seed=17)
+    raw[1500] = raw[40] * 3.0 + 2.0     # exact tie (same z-normalised series) in another chunk
+    raw[2299] = raw[41]
+    q, _, _ = W.noisy_queries(raw, 25, 0.2, 18, 19)
+    q[0] = raw[40]
+    qs = O.znorm(q)
+    want_i, want_d = O.knn(O.znorm(raw), qs, 9)
+    chunks = [(lo, raw[lo:lo + 700]) for lo in range(0, len(raw), 700)]  # last chunk 200 rows
+    got_i, got_d = O.knn_stream(chunks, qs, 9)
+    assert np.array_equal(got_i, want_i) and np.array_equal(got_d, want_d)
+    assert list(got_i[0, :2]) == [40, 1500]
+    # chunks shorter than k
+    got_i, got_d = O.knn_stream([(lo, raw[lo:lo + 5]) for lo in range(0, 40, 5)], qs, 9)
+    w_i, w_d = O.knn(O.znorm(raw[:40]), qs, 9)
+    assert np.array_equal(got_i, w_i) and np.array_equal(got_d, w_d)
+
+
 def test_knn_fewer_series_than_k():
     xs = O.znorm(W.random_walk(5, 16, seed=15))
     ids, d = O.knn(xs, xs[:2], 8)

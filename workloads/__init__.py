@@ -17,6 +17,9 @@ import numpy as np
 
 __all__ = [
     "random_walk",
+    "random_walk_device",
+    "random_walk_device_chunks",
+    "noisy_queries_device",
     "gaussian_mixture",
     "noisy_queries",
     "mlp_weights",
@@ -43,6 +46,59 @@ def random_walk(n: int, m: int, seed: int, chunk: int = 262144) -> np.ndarray:
         np.cumsum(steps, axis=1, out=steps)
         out[lo:hi] = steps
     return out
+
+
+def _chunk_steps(n: int, m: int, seed: int, chunk: int, c: int, device):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed * 1_000_003 + c)
+    lo = c * chunk
+    hi = min(n, lo + chunk)
+    return lo, hi, torch.randn((hi - lo, m), generator=g, device=device, dtype=torch.float32)
+
+
+def random_walk_device(n: int, m: int, seed: int, device="cuda", chunk: int = 1 << 20):
+    """Raw random walks generated on the GPU: x_t = sum_{u<=t} e_u with e ~ N(0, 1)
+    from torch's Philox generator, fp32 [n, m] on `device`.  Chunk c (rows
+    c*chunk ..) draws from its own seed, so any chunk can be regenerated alone
+    (random_walk_device_chunks).  For collections too large to draw on the host
+    in reasonable time; a different recipe from random_walk (NumPy PCG64)."""
+    import torch
+    out = torch.empty((n, m), dtype=torch.float32, device=device)
+    for lo, hi, x in random_walk_device_chunks(n, m, seed, device, chunk):
+        out[lo:hi] = x
+    return out
+
+
+def random_walk_device_chunks(n: int, m: int, seed: int, device="cuda", chunk: int = 1 << 20):
+    """Yields (lo, hi, rows lo..hi of random_walk_device as a device tensor)."""
+    import torch
+    for c in range((n + chunk - 1) // chunk):
+        lo, hi, steps = _chunk_steps(n, m, seed, chunk, c, device)
+        yield lo, hi, torch.cumsum(steps, dim=1)
+
+
+def noisy_queries_device(data, nq: int, sigma, seed: int):
+    """noisy_queries for a device collection: nq distinct rows drawn uniformly
+    (torch's generator, seeded) plus noise of standard deviation sigma *
+    std(row) (population std; sigma a scalar or a (lo, hi) range drawn per
+    query).  Returns (queries fp32 [nq, m] on the device, rows int64 [nq],
+    levels fp64 [nq]) with rows and levels on the host."""
+    import torch
+    n, m = data.shape
+    dev = data.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    rows = torch.randperm(n, generator=g, device=dev)[:nq]
+    if isinstance(sigma, tuple):
+        levels = sigma[0] + (sigma[1] - sigma[0]) * torch.rand((nq,), generator=g, device=dev, dtype=torch.float64)
+    else:
+        levels = torch.full((nq,), float(sigma), dtype=torch.float64, device=dev)
+    base = data[rows].to(torch.float64)
+    scale = base.std(dim=1, unbiased=False) * levels
+    noise = torch.randn((nq, m), generator=g, device=dev, dtype=torch.float64)
+    q = (base + scale[:, None] * noise).to(torch.float32)
+    return q, rows.cpu().numpy(), levels.cpu().numpy()
 
 
 def gaussian_mixture(n: int, m: int, n_comp: int, spread: float, seed_means: int,
@@ -126,6 +182,12 @@ WORKLOADS = {
                   split="median", nq=1_024, k=10, target=0.99, n_calib=500, calib_seed=3004,
                   test_seed=3005, train_seed=3002, sigmas=(0.05, 0.1, 0.2),
                   train_sigma=(0.05, 0.2)),
+    # serving case: 50M random walks generated on the GPU (about 77 GB resident
+    # as fp32 + bf16), leaf capacity 10k, mixed k and recall targets
+    "rw50m": dict(kind="random_walk_device", n=50_000_000, m=256, seed=5001, capacity=10_000,
+                  split="median", n_calib=500, calib_seed=5004, train_seed=5002, train_sigma=(0.05, 0.2),
+                  sigma=0.1, test_seed=5005, ks=(1, 10, 100), targets=(0.90, 0.95, 0.99), mix_seed=5003,
+                  nq=1_024, rates=(2_000, 5_000, 10_000, 20_000)),
     # ragged-leaf case: 25M length-96 Gaussian-mixture series, midpoint splits
     "gm25m": dict(kind="gaussian_mixture", n=25_000_000, m=96, n_comp=1_000, spread=0.3,
                   seed_means=4001, seed_members=4002, capacity=10_000, split="midpoint",
