@@ -169,6 +169,7 @@ RoundBufs views(Workspace &w) {
   b.fb_leaf = w.fb_leaf.get();
   b.chunk = kChunkRows;
   b.use_tau = 0;
+  b.kp_query = 0;
   b.ctl = w.ctl.get();
   b.leaf_n = w.leaf_n;
   return b;
@@ -336,6 +337,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   RoundBufs b0 = views(w);
   b0.chunk = chunk;
   b0.use_tau = ro->use_tau ? 1 : 0;
+  b0.kp_query = ro->kp_query ? 1 : 0;
   // a pass with few items (rescans, a first round of one leaf per query)
   // and preallocated buffers lays out and places its items in one
   // single-work-group launch (below, once the buffers are final)
@@ -368,6 +370,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   RoundBufs b = views(w);
   b.chunk = chunk;
   b.use_tau = ro->use_tau ? 1 : 0;
+  b.kp_query = ro->kp_query ? 1 : 0;
   StoreView s = store_view(ix);
   QueryView q = query_view(w);
   if (ro->first_leaf)
@@ -496,6 +499,9 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
   RoundOpts ro;
   ro.row_bytes = scan_row_bytes(ix, p.bf16);
   ro.use_tau = true;
+  ro.kp_query = p.kp_query;
+  RoundOpts rfb;  // the exact FP32 rescan pass
+  rfb.kp_query = p.kp_query;
   bool filters_ready = false;
   // A schedule that ends in 0 has a known last round: uncertified items of an
   // earlier round are rescanned by the next round's scan, as the planned
@@ -525,7 +531,7 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
       // the merge left each query's rescan list in its item list
       if (R > 0 && r < R - 1) {
         deferred = n_fb;
-      } else if (scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, n_fb) != 0) {
+      } else if (scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, n_fb, &rfb) != 0) {
         launch_query_merge(nq, N, p.kmax, false, true, views(w), st);
       }
     }
@@ -635,6 +641,7 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     ro.may_read = false;
     ro.first_leaf = first_leaf;
     ro.use_tau = true;
+    ro.kp_query = p.kp_query;
     ro.row_bytes = scan_row_bytes(ix, true);
     if (timed) {
       ro.ev_begin = w.sev[2 * r];
@@ -655,6 +662,7 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     RoundOpts rf;
     rf.may_read = false;
     rf.small = true;
+    rf.kp_query = p.kp_query;
     scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bnd, &rf);
     launch_query_merge(nq, N, p.kmax, false, true, views(w), st, ix->rowid.get(), ids, dists);
   }
@@ -881,6 +889,7 @@ SearchPlan make_plan(const leafi_index *ix, const leafi_search_opts *o) {
   p.filters = o->use_filters != 0;
   p.schedule.assign(o->schedule, o->schedule + o->n_schedule);
   p.kprime = o->kprime > 0 ? std::max<int>(o->kprime, p.kmax) : default_kprime(p.kmax, p.bf16);
+  p.kp_query = o->kprime == 0;
   p.graph = (o->flags & LEAFI_SEARCH_NO_GRAPH) == 0;
   p.ftile = (o->flags & LEAFI_SEARCH_FILTER_TILE_SMALL) ? 1 : (o->flags & LEAFI_SEARCH_FILTER_TILE_LARGE) ? 2 : 0;
   return p;
@@ -1311,7 +1320,7 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     h2d(ix->filt.w.get(), w0.data(), w0.size(), st);
     DevBuf<float> wbest(static_cast<size_t>(F) * P), vmse(F);
     DevBuf<int32_t> eruns(F);
-    TrainArgs ta;
+    TrainArgs ta{};
     ta.w = ix->filt.w.get();
     ta.w_best = wbest.get();
     ta.xq = xq.get();

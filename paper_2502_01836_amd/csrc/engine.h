@@ -77,6 +77,7 @@ struct RoundOpts {
   bool use_tau = false;         // a search round: the BF16 scan skips rows provably farther than tau
   bool first_leaf = false;      // the batch's first round of one leaf per query, emitted by the layout
                                 // itself from the visit order (no prune cascade launch; may_read false)
+  bool kp_query = false;        // each query keeps item_kprime(its k) candidates (mixed-k batches)
 };
 // Lay out the round's items, scan and rerank them (see api.hip).
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
@@ -97,6 +98,7 @@ struct SearchPlan {
   int kprime = 4;
   bool graph = true;  // planned batches may be captured and replayed
   int ftile = 0;      // filter inference tiles: 0 by batch size, 1 small, 2 large
+  bool kp_query = true;  // per-query candidate counts (the default kprime); false: kprime for every query
 };
 SearchPlan make_plan(const leafi_index *ix, const leafi_search_opts *o);
 void check_queries(const leafi_index *ix, const float *q, int64_t nq);

@@ -382,22 +382,123 @@ __global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b
 // top-k (sorted by (FP64 distance, row)), refresh tau and, in a regular
 // round, queue every item whose certificate bound does not exceed the new tau
 // for a rescan (by the next round's scan, or an exact FP32 pass after the
-// last round).  The running top-k and as many items as fit the
-// wavefront's LDS slice of C entries (KM slots per item) are gathered at once
-// and sorted together, so a query with many items needs few passes.  With
-// `dedupe`, a row met twice (a rescan of a leaf already merged) is kept once.
+// last round).  Every list is already sorted (the running top-k and each
+// item's exact top-k), so the k smallest of their union are selected by a
+// tournament over the list heads (merge_pass): k rounds of a wavefront
+// minimum, not a sort of everything.  A row met twice (a rescan of a leaf
+// already merged) carries the same (distance, row) in both lists and is kept
+// once.
 constexpr int kMergePreFp = 4;  // visit positions per lane whose filter-pair inputs the merge prefetches
+constexpr int kMergeSlots = 4;  // item lists per lane in one tournament pass (256 items per pass)
 
-__global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int KM, int C, int check_cert,
-                                                     int dedupe, RoundBufs b, const int64_t *__restrict__ rowid,
+// Non-negative doubles order like their bit patterns.
+__device__ __forceinline__ uint64_t dbl_bits(double v) { return static_cast<uint64_t>(__double_as_longlong(v)); }
+
+// One pass of the tournament: the k smallest distinct (distance, row)
+// entries of the sorted list in (in_v, in_t) (n_in entries, LDS) and of the
+// item lists qitem_idx[q N + it0 .. it0 + nb) (nb <= 64 kMergeSlots) go to
+// (out_v, out_t) in ascending order; returns how many.  Lane l holds items
+// it0 + l + 64 i: the head of each in registers and the next two entries in
+// flight behind it, so a list that wins several rounds in a row rarely waits.
+__device__ inline int merge_pass(int64_t q, int N, int kmax, int k, const RoundBufs &b, int it0, int nb,
+                                 const double *in_v, const uint32_t *in_t, int n_in, double *out_v,
+                                 uint32_t *out_t, int lane) {
+  constexpr double kInf = __builtin_inf();
+  double hv[kMergeSlots], n1v[kMergeSlots], n2v[kMergeSlots];
+  uint32_t ht[kMergeSlots], n1t[kMergeSlots], n2t[kMergeSlots];
+  int64_t base[kMergeSlots];
+  int pos[kMergeSlots], cnt[kMergeSlots];
+#pragma unroll
+  for (int i = 0; i < kMergeSlots; ++i) {
+    const int j = lane + kWave * i;
+    int idx = 0, c = 0;
+    if (j < nb) {
+      idx = b.qitem_idx[q * N + it0 + j];
+      c = b.item_cnt[idx];
+      c = c < k ? c : k;
+    }
+    base[i] = static_cast<int64_t>(idx) * kmax;
+    cnt[i] = c;
+  }
+#pragma unroll
+  for (int i = 0; i < kMergeSlots; ++i) {
+    hv[i] = n1v[i] = n2v[i] = kInf;
+    ht[i] = n1t[i] = n2t[i] = 0xffffffffu;
+    if (cnt[i] > 0) {
+      hv[i] = b.item_d2[base[i]];
+      ht[i] = static_cast<uint32_t>(b.item_row[base[i]]);
+    }
+    if (cnt[i] > 1) {
+      n1v[i] = b.item_d2[base[i] + 1];
+      n1t[i] = static_cast<uint32_t>(b.item_row[base[i] + 1]);
+    }
+    if (cnt[i] > 2) {
+      n2v[i] = b.item_d2[base[i] + 2];
+      n2t[i] = static_cast<uint32_t>(b.item_row[base[i] + 2]);
+    }
+    pos[i] = 3;
+  }
+  int out = 0, rp = 0;
+  while (out < k) {
+    // this lane's smallest head, then the wavefront's: value first, then row
+    double lv = kInf;
+    uint32_t lt = 0xffffffffu;
+#pragma unroll
+    for (int i = 0; i < kMergeSlots; ++i)
+      if (hv[i] < lv || (hv[i] == lv && ht[i] < lt)) {
+        lv = hv[i];
+        lt = ht[i];
+      }
+    const uint64_t mvb = wave_min_u64(dbl_bits(lv));
+    const uint64_t mtb = wave_min_u64(dbl_bits(lv) == mvb ? static_cast<uint64_t>(lt) : ~0ull);
+    double gv = __longlong_as_double(static_cast<long long>(mvb));
+    uint32_t gt = static_cast<uint32_t>(mtb);
+    // the running list's head (uniform)
+    const double rv = rp < n_in ? in_v[rp] : kInf;
+    const uint32_t rt = rp < n_in ? in_t[rp] : 0xffffffffu;
+    if (rv < gv || (rv == gv && rt < gt)) {
+      gv = rv;
+      gt = rt;
+    }
+    if (gt == 0xffffffffu) break;  // every list is exhausted
+    if (lane == 0) {
+      out_v[out] = gv;
+      out_t[out] = gt;
+    }
+    ++out;
+    // every head equal to the winner advances (a row met twice is emitted once)
+    if (rv == gv && rt == gt) ++rp;
+#pragma unroll
+    for (int i = 0; i < kMergeSlots; ++i) {
+      if (hv[i] == gv && ht[i] == gt) {
+        hv[i] = n1v[i];
+        ht[i] = n1t[i];
+        n1v[i] = n2v[i];
+        n1t[i] = n2t[i];
+        n2v[i] = kInf;
+        n2t[i] = 0xffffffffu;
+        if (pos[i] < cnt[i]) {
+          n2v[i] = b.item_d2[base[i] + pos[i]];
+          n2t[i] = static_cast<uint32_t>(b.item_row[base[i] + pos[i]]);
+        }
+        ++pos[i];
+      }
+    }
+  }
+  wave_lds_sync();
+  return out;
+}
+
+__global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int check_cert,
+                                                     RoundBufs b, const int64_t *__restrict__ rowid,
                                                      int64_t *out_ids, float *out_d, FilterPairArgs fp) {
   extern __shared__ unsigned char smem_raw[];
-  // four wavefronts per work-group, each with its own LDS slice and query
+  // four wavefronts per work-group, each with its own LDS slice and query:
+  // two lists of kmax entries (the tournament's input and output)
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  unsigned char *mine = smem_raw + static_cast<size_t>(wave) * C * (sizeof(double) + sizeof(uint32_t));
-  double *vals = reinterpret_cast<double *>(mine);
-  uint32_t *tags = reinterpret_cast<uint32_t *>(mine + sizeof(double) * C);
-  const int per = (C - KM) / KM;  // items per pass
+  unsigned char *mine = smem_raw + static_cast<size_t>(wave) * 2 * kmax * (sizeof(double) + sizeof(uint32_t));
+  double *buf_v = reinterpret_cast<double *>(mine);
+  uint32_t *buf_t = reinterpret_cast<uint32_t *>(mine + sizeof(double) * 2 * kmax);
   const uint64_t lt = (1ull << lane) - 1ull;
   __shared__ int active_sh[4], fb_sh[4], fe_sh[4];
   int active = 0, n_fb = 0, n_fe = 0;  // n_fe: this lane's queued filter pairs
@@ -437,70 +538,31 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
     }
     float tau_now = __builtin_inff();  // the query's tau after this merge (filter pairs below)
     if (n_it > 0) {
-      for (int i = lane; i < KM; i += kWave) {
-        double v = __builtin_inf();
-        uint32_t t = 0xffffffffu;
-        if (i < kmax) {  // loaded unconditionally, kept below `have`
-          v = b.res_d2[q * kmax + i];
-          t = static_cast<uint32_t>(b.res_row[q * kmax + i]);
-        }
+      double *vals = buf_v, *ov = buf_v + kmax;
+      uint32_t *tags = buf_t, *ot = buf_t + kmax;
+      for (int i = lane; i < kmax; i += kWave) {
+        const double v = b.res_d2[q * kmax + i];  // loaded unconditionally, kept below `have`
+        const uint32_t t = static_cast<uint32_t>(b.res_row[q * kmax + i]);
         vals[i] = i < have ? v : __builtin_inf();
         tags[i] = i < have ? t : 0xffffffffu;
       }
-      for (int it0 = 0; it0 < n_it; it0 += per) {
-        const int nb = n_it - it0 < per ? n_it - it0 : per;
-        const int n = pow2_at_least(KM * (nb + 1));
-        for (int e = lane; e < n - KM; e += kWave) {
-          const int j = e / KM, i = e - j * KM;
-          double v = __builtin_inf();
-          uint32_t t = 0xffffffffu;
-          if (j < nb && i < kmax) {
-            // the item's count and values in parallel, kept below the count
-            const int idx = b.qitem_idx[q * N + it0 + j];
-            const int ic = b.item_cnt[idx];
-            const double vv = b.item_d2[static_cast<int64_t>(idx) * kmax + i];
-            const uint32_t tt = static_cast<uint32_t>(b.item_row[static_cast<int64_t>(idx) * kmax + i]);
-            if (i < ic) {
-              v = vv;
-              t = tt;
-            }
-          }
-          vals[KM + e] = v;
-          tags[KM + e] = t;
-        }
-        wave_lds_sync();
-        wave_sort_dbl_tag(vals, tags, n, lane);
-        if (dedupe) {
-          // equal rows carry equal distances, so copies are adjacent: keep
-          // the first of each run, compacted in order into the first slots
-          int written = 0;
-          for (int r0 = 0; r0 < n && written < KM; r0 += kWave) {
-            const int r = r0 + lane;
-            double v = 0.0;
-            uint32_t t = 0xffffffffu;
-            bool keep = false;
-            if (r < n) {
-              v = vals[r];
-              t = tags[r];
-              keep = !(r > 0 && t != 0xffffffffu && t == tags[r - 1]);
-            }
-            const uint64_t mk = __ballot(keep);
-            wave_lds_sync();
-            const int pos = written + __popcll(mk & lt);
-            if (keep && pos < KM) {
-              vals[pos] = v;
-              tags[pos] = t;
-            }
-            written += __popcll(mk);
-            wave_lds_sync();
-          }
-          for (int i = written + lane; i < KM; i += kWave) {
-            vals[i] = __builtin_inf();
-            tags[i] = 0xffffffffu;
-          }
-        }
-        wave_lds_sync();
+      wave_lds_sync();
+      int n_in = have < k ? have : k;
+      for (int it0 = 0; it0 < n_it; it0 += kWave * kMergeSlots) {
+        const int nb = n_it - it0 < kWave * kMergeSlots ? n_it - it0 : kWave * kMergeSlots;
+        n_in = merge_pass(q, N, kmax, k, b, it0, nb, vals, tags, n_in, ov, ot, lane);
+        double *sv = vals;
+        vals = ov;
+        ov = sv;
+        uint32_t *st = tags;
+        tags = ot;
+        ot = st;
       }
+      for (int i = n_in + lane; i < kmax; i += kWave) {
+        vals[i] = __builtin_inf();
+        tags[i] = 0xffffffffu;
+      }
+      wave_lds_sync();
       int cnt = 0;
       for (int i = 0; i < k; ++i) cnt += tags[i] != 0xffffffffu ? 1 : 0;
       for (int i = lane; i < k; i += kWave) {
@@ -768,17 +830,15 @@ void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
 
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
                         const int64_t *rowid, int64_t *ids, float *dists, const FilterPairArgs &fp) {
-  const int KM = pow2_at_least(kmax < 2 ? 2 : kmax);
-  // LDS slice per wavefront: the running top-k plus up to 255 items' lists
-  // (at most 256 entries unless 2 KM alone is larger)
-  const int C = std::max(2 * KM, std::min(pow2_at_least(KM * (N + 1)), 256));
-  size_t lds = 4 * static_cast<size_t>(C) * (sizeof(double) + sizeof(uint32_t));
+  // LDS slice per wavefront: two lists of kmax entries
+  size_t lds = 4 * 2 * static_cast<size_t>(kmax) * (sizeof(double) + sizeof(uint32_t));
   int64_t blocks = ceil_div(nq, 4);
   int grid = static_cast<int>(blocks < 65536 ? blocks : 65536);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_merge),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, KM, C, check_cert ? 1 : 0,
-                     dedupe ? 1 : 0, b, rowid, ids, dists, fp);
+  (void)dedupe;  // the tournament keeps a row met twice once in every round
+  hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, check_cert ? 1 : 0, b, rowid,
+                     ids, dists, fp);
   LAUNCH_OK("query_merge");
 }
 

@@ -192,12 +192,14 @@ __device__ inline void append_key(uint64_t *keys, int *cnt, const uint64_t *thr,
   }
 }
 
-__device__ inline void finish_tile(uint64_t *keys, int *cnt, uint64_t *thr, int t, int mq, int nqt, int cap,
-                                   int kprime, int wave, int nwaves, int lane, uint64_t *cand) {
+// The tile's lists to its candidate slots: list j keeps its kpl[j] best keys
+// (kpl[j] <= kprime), the rest of its kprime slots are empty.
+__device__ inline void finish_tile(uint64_t *keys, int *cnt, uint64_t *thr, const int *kpl, int t, int mq, int nqt,
+                                   int cap, int kprime, int wave, int nwaves, int lane, uint64_t *cand) {
   for (int j = wave; j < mq; j += nwaves) {
     uint64_t *out = cand + (static_cast<int64_t>(t) * mq + j) * kprime;
     if (j < nqt) {
-      compact_list(keys, cnt, thr, j, cap, kprime, lane);
+      compact_list(keys, cnt, thr, j, cap, kpl[j], lane);
       // only the first cnt[j] entries are candidates; the list may hold fewer
       // than kprime (a chunk with few real rows) and LDS beyond them is stale
       const uint64_t *lst = keys + static_cast<int64_t>(j) * (cap + 1);
@@ -227,7 +229,7 @@ template <int KS, int QB>
 __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &ti, int64_t base, bf16x8 (&cur)[KS],
                                            bf16x8 (&nxt)[KS], bool more, const uint16_t *qs, int qstride,
                                            const float (&qn)[QB], uint64_t *keys, int *cnt, uint64_t *thr, int cap,
-                                           int kprime, int wave, int lane) {
+                                           const int *kpl, int wave, int lane) {
   constexpr int kWaves = 4;
   const int64_t rowc = base + 16 * wave + 4 * (lane >> 4);
   const float4 xn = *reinterpret_cast<const float4 *>(s.xn16 + rowc);
@@ -281,7 +283,7 @@ __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &t
   while (over) {
     const int j = __ffsll(static_cast<unsigned long long>(over)) - 1;
     over &= over - 1;
-    compact_list(keys, cnt, thr, j, cap, kprime, lane);
+    compact_list(keys, cnt, thr, j, cap, kpl[j], lane);
   }
   lds_barrier();
 }
@@ -296,7 +298,8 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
   uint64_t *keys = smem;
   uint64_t *thr = keys + MQ * (cap + 1);
   int *cnt = reinterpret_cast<int *>(thr + MQ);
-  uint16_t *qs = reinterpret_cast<uint16_t *>(cnt + MQ);  // [MQ][m + 8], 16-byte aligned
+  int *kpl = cnt + MQ;                                     // [MQ] candidates each list keeps
+  uint16_t *qs = reinterpret_cast<uint16_t *>(kpl + MQ);  // [MQ][m + 8], 16-byte aligned
   int *s_leaf = reinterpret_cast<int *>(qs + MQ * (s.m + 8));  // [2], after the tile's queries
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -320,12 +323,17 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
       const int j = threadIdx.x;
       cnt[j] = 0;
       uint64_t t0 = kKeyMax;
-      if (b.use_tau && j < ti.nqt) {
+      int kp = kprime;
+      if (j < ti.nqt) {
         const int64_t qq = b.item_q[ti.p0 + j];
-        const float T = tau_threshold(b.tau[qq], qv.qn16[qq], qv.qeps[qq], s.leaf_eps[ti.L], m);
-        if (T < __builtin_inff()) t0 = make_key(T, 0u);
+        if (b.kp_query) kp = item_kprime(1, kprime, b.kq[qq], true);
+        if (b.use_tau) {
+          const float T = tau_threshold(b.tau[qq], qv.qn16[qq], qv.qeps[qq], s.leaf_eps[ti.L], m);
+          if (T < __builtin_inff()) t0 = make_key(T, 0u);
+        }
       }
       thr[j] = t0;
+      kpl[j] = kp;
     }
     // B operand: this lane's query column and k-chunk, all K steps
     // The group's bf16 queries go to LDS (row stride m + 8 elements, so the 16
@@ -352,11 +360,11 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
     // Chunks hold an even number of 64-row blocks (leaves are padded to 128
     // rows), so both halves of the unrolled body always run.
     for (int64_t base = ti.r0; base < ti.r1; base += 128) {
-      scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kprime, wave, lane);
-      scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qs, qstride, qn, keys, cnt, thr, cap, kprime,
+      scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kpl, wave, lane);
+      scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qs, qstride, qn, keys, cnt, thr, cap, kpl,
                          wave, lane);
     }
-    finish_tile(keys, cnt, thr, t, MQ, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
+    finish_tile(keys, cnt, thr, kpl, t, MQ, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
     __syncthreads();
   }
 }
@@ -369,7 +377,8 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
   uint64_t *keys = smem;
   uint64_t *thr = keys + mq * (cap + 1);
   int *cnt = reinterpret_cast<int *>(thr + mq);
-  float *qs = reinterpret_cast<float *>(cnt + mq);
+  int *kpl = cnt + mq;  // [mq] candidates each list keeps
+  float *qs = reinterpret_cast<float *>(kpl + mq);
   int *s_leaf = reinterpret_cast<int *>(qs + mq * s.m);  // [2], after the tile's queries
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -387,8 +396,10 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
     const int t = static_cast<int>(tt);
     TileInfo ti = decode_tile(t, s, b, mq, s_leaf);
     if (threadIdx.x < mq) {
-      cnt[threadIdx.x] = 0;
-      thr[threadIdx.x] = kKeyMax;
+      const int j = threadIdx.x;
+      cnt[j] = 0;
+      thr[j] = kKeyMax;
+      kpl[j] = j < ti.nqt && b.kp_query ? item_kprime(1, kprime, b.kq[b.item_q[ti.p0 + j]], false) : kprime;
     }
     for (int e = threadIdx.x; e < ti.nqt * m; e += blockDim.x) {
       int j = e / m;
@@ -432,11 +443,11 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
       while (over) {
         const int j = __ffsll(static_cast<unsigned long long>(over)) - 1;
         over &= over - 1;
-        compact_list(keys, cnt, thr, j, cap, kprime, lane);
+        compact_list(keys, cnt, thr, j, cap, kpl[j], lane);
       }
       __syncthreads();
     }
-    finish_tile(keys, cnt, thr, t, mq, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
+    finish_tile(keys, cnt, thr, kpl, t, mq, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
     __syncthreads();
   }
 }
@@ -448,14 +459,14 @@ constexpr int kSelectPerLane = 16;
 
 // One wavefront per item.  LDS: merged keys [P], then per candidate the fp32
 // key, FP64 distance and row.
-// The kprime smallest of an item's n chunk-list keys into buf (ascending,
-// kKeyMax past the last real key): kprime rounds of a wavefront minimum over
+// The kp smallest of an item's n chunk-list keys (kprime slots per chunk)
+// into buf (ascending, kKeyMax past the last real key): kp rounds of a
 // the keys above the previous one (keys are unique), U per lane in registers
 // (unconditional loads of clamped entries, so all of a lane's loads are in
-// flight together; n >= kprime >= 1, so entry 0 exists; n <= 64 U).
+// flight together; n >= kprime >= kp >= 1, so entry 0 exists; n <= 64 U).
 template <int U>
 __device__ inline void select_keys(const uint64_t *__restrict__ cand, int64_t t0, int G, int g, int mq, int j,
-                                   int kprime, int n, int lane, uint64_t *buf) {
+                                   int kprime, int kp, int n, int lane, uint64_t *buf) {
   uint64_t mine[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -467,7 +478,7 @@ __device__ inline void select_keys(const uint64_t *__restrict__ cand, int64_t t0
   }
   uint64_t prev = 0;
   bool first = true;
-  for (int r = 0; r < kprime; ++r) {
+  for (int r = 0; r < kp; ++r) {
     uint64_t lo = kKeyMax;
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -477,7 +488,7 @@ __device__ inline void select_keys(const uint64_t *__restrict__ cand, int64_t t0
     prev = lo;
     first = false;
     if (lo == kKeyMax) {  // no keys left: the rest stay empty
-      for (int e = r + 1 + lane; e < kprime; e += kWave) buf[e] = kKeyMax;
+      for (int e = r + 1 + lane; e < kp; e += kWave) buf[e] = kKeyMax;
       break;
     }
   }
@@ -517,14 +528,17 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
     const int g = pos / mq, j = pos - (pos / mq) * mq;
     const int C = static_cast<int>((off1 - off0 + b.chunk - 1) / b.chunk);
     const int G = (ist1 - ist0 + mq - 1) / mq;
+    // the query's own candidate count (its lists hold kp keys in kprime slots)
+    const int kp = item_kprime(b.kp_query, kprime, k, bf16 != 0);
+    const int PKi = pow2_at_least(kp < 2 ? 2 : kp);
     int n = C * kprime;
-    if (kprime <= kSelectMax && n <= kWave * kSelectPerLane) {
-      // few keys wanted from many: kprime rounds of a wavefront minimum, each
+    if (kp <= kSelectMax && n <= kWave * kSelectPerLane) {
+      // few keys wanted from many: kp rounds of a wavefront minimum, each
       // lane holding as few registers as n needs
       const int64_t t0 = b.tile_start[L];
-      if (n <= kWave) select_keys<1>(cand, t0, G, g, mq, j, kprime, n, lane, buf);
-      else if (n <= 4 * kWave) select_keys<4>(cand, t0, G, g, mq, j, kprime, n, lane, buf);
-      else select_keys<kSelectPerLane>(cand, t0, G, g, mq, j, kprime, n, lane, buf);
+      if (n <= kWave) select_keys<1>(cand, t0, G, g, mq, j, kprime, kp, n, lane, buf);
+      else if (n <= 4 * kWave) select_keys<4>(cand, t0, G, g, mq, j, kprime, kp, n, lane, buf);
+      else select_keys<kSelectPerLane>(cand, t0, G, g, mq, j, kprime, kp, n, lane, buf);
       wave_lds_sync();
     } else {
       int P = pow2_at_least(n < 2 ? 2 : n);
@@ -539,19 +553,19 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
       wave_lds_sync();
       wave_sort_u64(buf, P, lane);
     }
-    uint64_t kth = buf[kprime - 1];
-    // number of real candidates among the first kprime
+    uint64_t kth = buf[kp - 1];
+    // number of real candidates among the first kp
     int nc = 0;
-    for (int e = 0; e < kprime; ++e) nc += buf[e] != kKeyMax ? 1 : 0;
+    for (int e = 0; e < kp; ++e) nc += buf[e] != kKeyMax ? 1 : 0;
     // FP32 direct-difference rerank: CB candidates at a time, G lanes each
     // (all their rows are in flight together), 4 consecutive elements per lane
     const float *qp = qv.q32 + q * m;
-    const int CB = PK < 8 ? PK : 8, GL = kWave / CB;
+    const int CB = PKi < 8 ? PKi : 8, GL = kWave / CB;
     const int sub = lane & (GL - 1), cb = lane / GL;
     // FP64 for every candidate within the FP32 error band of the k-th
     float band = __builtin_inff();
     int nb = 0;
-    if (PK <= 8 && m <= 16 * GL) {
+    if (PKi <= 8 && m <= 16 * GL) {
       // Few candidates (CB == PK): each lane group holds its candidate's row
       // and the query's matching elements in registers for both passes, so
       // the rows are read once.  Same sums in the same order as below.
@@ -588,7 +602,7 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
       for (int o = GL >> 1; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
       if (sub == 0) k32[e] = e < nc ? make_key(p, row) : kKeyMax;
       wave_lds_sync();
-      wave_sort_u64(k32, PK, lane);
+      wave_sort_u64(k32, PKi, lane);
       if (nc >= k) band = key_d2(k32[k - 1]) * (1.0f + 2.0f * delta32);
       for (int i = 0; i < nc; ++i) nb += key_d2(k32[i]) <= band ? 1 : 0;
       // the band's members are exactly the candidates whose FP32 value is
@@ -618,10 +632,10 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
     } else if (!bf16) {
       // FP32 scan items: the candidates' keys already hold FP32
       // direct-difference values (same error bound), ascending
-      for (int e = lane; e < PK; e += kWave) k32[e] = e < nc ? buf[e] : kKeyMax;
+      for (int e = lane; e < PKi; e += kWave) k32[e] = e < nc ? buf[e] : kKeyMax;
       wave_lds_sync();
     } else {
-      for (int e0 = 0; e0 < PK; e0 += CB) {
+      for (int e0 = 0; e0 < PKi; e0 += CB) {
         const int e = e0 + cb;
         float p = 0.0f;
         uint32_t row = 0;
@@ -648,12 +662,12 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
         if (sub == 0) k32[e] = e < nc ? make_key(p, row) : kKeyMax;
       }
       wave_lds_sync();
-      wave_sort_u64(k32, PK, lane);
+      wave_sort_u64(k32, PKi, lane);
     }
-    if (!(PK <= 8 && m <= 16 * GL)) {
+    if (!(PKi <= 8 && m <= 16 * GL)) {
       if (nc >= k) band = key_d2(k32[k - 1]) * (1.0f + 2.0f * delta32);
       for (int e = 0; e < nc; ++e) nb += key_d2(k32[e]) <= band ? 1 : 0;
-      for (int e0 = 0; e0 < PK; e0 += CB) {
+      for (int e0 = 0; e0 < PKi; e0 += CB) {
         const int e = e0 + cb;
         double p = 0.0;
         uint32_t row = 0xffffffffu;
@@ -682,7 +696,7 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
       }
     }
     wave_lds_sync();
-    wave_sort_dbl_tag(d64, r64, PK, lane);
+    wave_sort_dbl_tag(d64, r64, PKi, lane);
     int keep = nb < k ? nb : k;
     for (int i = lane; i < keep; i += kWave) {
       b.item_d2[static_cast<int64_t>(item) * kmax + i] = d64[i];
@@ -749,8 +763,8 @@ template <int KS, int QB>
 void scan_bf16_inst(StoreView s, QueryView q, RoundBufs b, int kprime, int cap, uint64_t *cand, int grid,
                     hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int MQ = 16 * QB;
-  size_t lds =
-      static_cast<size_t>(MQ) * (cap + 1) * 8 + MQ * 8 + MQ * 4 + static_cast<size_t>(MQ) * (32 * KS + 8) * 2 + 16;
+  size_t lds = static_cast<size_t>(MQ) * (cap + 1) * 8 + MQ * 8 + MQ * 4 * 2 +
+               static_cast<size_t>(MQ) * (32 * KS + 8) * 2 + 16;
   auto kern = k_scan_bf16<KS, QB>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -781,7 +795,7 @@ void scan_bf16_ks(int ks, StoreView s, QueryView q, RoundBufs b, int kprime, int
 template <int EPL>
 void scan_fp32_inst(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int cap, uint64_t *cand, int grid,
                     hipStream_t st) {
-  size_t lds = static_cast<size_t>(mq) * (cap + 1) * 8 + mq * 8 + mq * 4 + static_cast<size_t>(mq) * s.m * 4 + 16;
+  size_t lds = static_cast<size_t>(mq) * (cap + 1) * 8 + mq * 8 + mq * 4 * 2 + static_cast<size_t>(mq) * s.m * 4 + 16;
   auto kern = k_scan_fp32<EPL>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));

@@ -81,7 +81,19 @@ struct RoundBufs {
   // 1: a search round, whose BF16 scan may skip rows provably farther than
   // the query's tau; 0: per-item exact top-k (all-pairs passes)
   int32_t use_tau;
+  // 1: each query keeps its own number of candidates, item_kprime(k) of the
+  // pass's kprime (a batch of mixed k); 0: every query keeps kprime
+  int32_t kp_query;
 };
+
+// Candidates a query of k results keeps per (query, leaf) in a pass whose
+// lists have kprime slots: 4k for the BF16 scan, k + 8 for the FP32 scan
+// (never fewer than k, never more than kprime), or kprime for all.
+__host__ __device__ inline int item_kprime(int kp_query, int kprime, int k, bool bf16) {
+  if (!kp_query) return kprime;
+  const int kp = bf16 ? 4 * k : k + 8;
+  return kp < kprime ? kp : kprime;
+}
 
 // Tile of item group g (queries g*mq ..) and row chunk c of leaf L: chunk-major
 // (the groups of one chunk are consecutive tiles, so work-groups that read
@@ -288,6 +300,7 @@ struct TrainArgs {
   uint64_t seed;
   float *val_mse;        // [F] best validation MSE
   int32_t *epochs_run;   // [F]
+  float *val_trace;      // [F, max_epochs] validation MSE after each epoch run (may be null)
 };
 
 // Full SGD training, one work-group per filter.

@@ -172,6 +172,7 @@ void leafi_server::engine_round(int n_new, int &n_active) {
   RoundOpts ro;
   ro.may_read = !device_rounds;
   ro.use_tau = true;
+  ro.kp_query = true;
   if (scan_round(ix, slots, bf16, kprime, kmax, st, nullptr, bound, &ro) != 0)
     launch_query_merge(slots, N, kmax, true, false, views(w), st);
   if (device_rounds) {
@@ -186,7 +187,9 @@ void leafi_server::engine_round(int n_new, int &n_active) {
     read_ctl(ix, st);
     const int64_t n_fb = w.h_ctl[kCtlFallback];
     if (n_fb > 0) {
-      if (scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, n_fb) != 0)
+      RoundOpts rf;
+      rf.kp_query = true;
+      if (scan_round(ix, slots, false, default_kprime(kmax, false), kmax, st, nullptr, n_fb, &rf) != 0)
         launch_query_merge(slots, N, kmax, false, true, views(w), st);
     }
   }

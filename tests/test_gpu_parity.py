@@ -174,6 +174,23 @@ def test_exact_search_ragged_m96_k_mix():
         assert (ids[sel, k:] == -1).all() and np.isinf(d[sel, k:]).all()
 
 
+@pytest.mark.parametrize("scan", ["bf16", "fp32"])
+@pytest.mark.parametrize("schedule", [(1, 0), (1,), (2, 0)])
+def test_exact_search_mixed_k_up_to_100(rw20k, scan, schedule):
+    """One batch whose queries ask for k = 1, 10 or 100 (each keeps its own
+    number of candidates inside the batch's lists)."""
+    ix = rw20k["ix"]
+    ks = np.array([1, 10, 100] * 34, dtype=np.int32)[:100]
+    ids, d = ix.search(torch.from_numpy(rw20k["q"]).cuda(), k=torch.from_numpy(ks).cuda(), k_max=100,
+                       use_filters=False, schedule=schedule, scan=scan)
+    ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    want_ids, want_d = O.knn(rw20k["xs"], rw20k["qs"], 100)
+    for k in (1, 10, 100):
+        sel = ks == k
+        assert_knn_parity(ids[sel, :k], d[sel, :k], want_ids[sel, :k], want_d[sel, :k], rw20k["xs"], rw20k["qs"][sel])
+        assert (ids[sel, k:] == -1).all() and np.isinf(d[sel, k:]).all()
+
+
 def test_duplicates_tie_break_by_id_and_empty_batch():
     pkg = _pkg()
     raw = W.random_walk(5000, 64, seed=77)
