@@ -208,6 +208,15 @@ int leafi_get_examples(const leafi_index *index, int64_t *n_queries, int32_t *n_
                        float *queries_dev, int32_t *ex_query_host, float *ex_target_dev, void *stream);
 
 /*
+ * The schedule of the same kept training run: *max_epochs, epochs_run_host
+ * [n_filters] (epochs each filter trained) and val_mse_host [n_filters,
+ * max_epochs] (validation mean squared error after each epoch, NaN after the
+ * filter's last epoch).  Each may be NULL.  LEAFI_ESTATE if no run was kept.
+ */
+int leafi_get_train_trace(const leafi_index *index, int32_t *max_epochs, int32_t *epochs_run_host,
+                          float *val_mse_host);
+
+/*
  * Install given filters instead of training them: n_filters filters on the
  * leaves leaf_ids_host[n_filters] (distinct), weights_dev [n_filters, P] with
  * P = h*m + 2h + 1 packed as [W1 (input-major: element (i, j) at i*h + j) |

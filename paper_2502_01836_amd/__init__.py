@@ -175,6 +175,19 @@ class Index:
                                      exq.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(y.data_ptr()), _stream()))
         return q, exq, y, ntr.value
 
+    def train_trace(self):
+        """Of the kept training run: (epochs run per filter [F] int32,
+        validation MSE after each epoch [F, max_epochs], NaN past the end)."""
+        me = ctypes.c_int32()
+        lib = load()
+        check(lib.leafi_get_train_trace(self._h, ctypes.byref(me), None, None))
+        F = self.info()["n_filters"]
+        ep = np.zeros(F, dtype=np.int32)
+        tr = np.zeros((F, me.value), dtype=np.float32)
+        check(lib.leafi_get_train_trace(self._h, None, ep.ctypes.data_as(ctypes.c_void_p),
+                                        tr.ctypes.data_as(ctypes.c_void_p)))
+        return ep, tr
+
     def set_filters(self, leaf_ids, weights, hidden: int):
         torch = _torch()
         ids = np.ascontiguousarray(leaf_ids, dtype=np.int32)

@@ -126,6 +126,7 @@ SIGNATURES = [
     ("leafi_train_filters", ctypes.c_int, [P, ctypes.POINTER(TrainOpts), ctypes.POINTER(TrainReport), P]),
     ("leafi_set_filters", ctypes.c_int, [P, I32, I32, P, P, P]),
     ("leafi_get_filters", ctypes.c_int, [P, P, P, P]),
+    ("leafi_get_train_trace", ctypes.c_int, [P, ctypes.POINTER(I32), P, P]),
     ("leafi_get_examples", ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P,
                                           P]),
     ("leafi_calibrate", ctypes.c_int, [P, P, I32, P, I32, P, I32, I32, P]),

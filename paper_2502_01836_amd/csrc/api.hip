@@ -1339,6 +1339,12 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     ta.seed = o->seed;
     ta.val_mse = vmse.get();
     ta.epochs_run = eruns.get();
+    DevBuf<float> vtrace;
+    if (o->keep_examples) {
+      vtrace.alloc(static_cast<size_t>(F) * o->max_epochs);
+      fill_f32(vtrace.get(), static_cast<int64_t>(vtrace.size()), NAN, st);
+      ta.val_trace = vtrace.get();
+    }
     auto t2 = std::chrono::steady_clock::now();
     launch_mlp_train(ta, st);
     std::vector<float> hv(F);
@@ -1361,8 +1367,24 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
       ex.n_train = n_train;
       ex.ex_q = std::move(exq);
       ex.ex_y = std::move(ex_y);
+      ex.max_epochs = o->max_epochs;
+      ex.epochs.assign(he.begin(), he.end());
+      ex.val_trace.resize(vtrace.size());
+      d2h(ex.val_trace.data(), vtrace.get(), vtrace.size(), st);
+      HIP_OK(hipStreamSynchronize(st));
     }
     if (rep) *rep = report;
+  });
+}
+
+int leafi_get_train_trace(const leafi_index *ix, int32_t *max_epochs, int32_t *epochs_run, float *val_mse) {
+  return guarded([&] {
+    require_built(ix);
+    const Examples &ex = ix->examples;
+    if (ex.nq == 0) fail(LEAFI_ESTATE, "no training run kept (train with keep_examples = 1)");
+    if (max_epochs) *max_epochs = ex.max_epochs;
+    if (epochs_run) std::copy(ex.epochs.begin(), ex.epochs.end(), epochs_run);
+    if (val_mse) std::copy(ex.val_trace.begin(), ex.val_trace.end(), val_mse);
   });
 }
 

@@ -112,6 +112,9 @@ struct Examples {
   DevBuf<float> q;              // [nq, m] raw
   std::vector<int32_t> ex_q;    // [F, n_ex] query of each example
   DevBuf<float> ex_y;           // [F, n_ex] d^L targets
+  int max_epochs = 0;
+  std::vector<int32_t> epochs;  // [F] epochs each filter ran
+  std::vector<float> val_trace; // [F, max_epochs] validation MSE after each epoch (NaN after the last)
 };
 
 struct Workspace {

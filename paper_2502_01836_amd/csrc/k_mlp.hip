@@ -589,6 +589,391 @@ __global__ void __launch_bounds__(256) k_mlp_train(TrainArgs a) {
   }
 }
 
+// ---- SGD on FP32 matrix cores ------------------------------------------------
+//
+// One work-group of kTrainWaves wavefronts per filter; wavefront w owns the
+// kTrainHT 16-unit hidden tiles kTrainHT w .. (32 hidden units) and holds
+// that slice of W1 in registers for the whole run (per hidden tile, m / 16
+// input tiles x 4 values per lane), so the weights never travel to memory
+// between steps.  Both products of a step run on v_mfma_f32_16x16x4_f32
+// (16 x 16 output tile, 4 inputs per instruction; A: lane l holds
+// A[l mod 16][l / 16]; B: B[l / 16][l mod 16]; D: lane l, register r holds
+// D[4 (l / 16) + r][l mod 16]):
+//   forward   Z = X W1 (batch x hidden): K step s of input tile ti takes the
+//             inputs 16 ti + 4 q + s (q = lane / 16), so register s of the
+//             wavefront's W1 tile is the B operand; the batch rows come from
+//             LDS as the A operand;
+//   backward  dW1 = X^T Delta (inputs x hidden): Delta = dL/dZ is the forward
+//             output tile itself, so its register s is the B operand of K
+//             step s (batch row 4 q + s of the tile), and the output tile
+//             lands in exactly the layout of the W1 registers, which are
+//             updated in place.
+// The output layer, its gradient and the loss are summed in a fixed order
+// (per lane over its hidden units, then a fixed butterfly over the 16 lanes
+// of a quarter, then the wavefronts in turn), so a run is deterministic.
+constexpr int kTrainWaves = 8;            // wavefronts per filter
+constexpr int kTrainHT = 2;               // 16-unit hidden tiles per wavefront: hidden units <= 256
+constexpr int kTrainThreads = 64 * kTrainWaves;
+constexpr int kTrainB = 64;               // mini-batch capacity: four 16-row tiles
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+struct TrainLds {
+  float *xb;     // [kTrainB][m + 1] the batch rows (odd row stride: the A reads of 16 rows hit 16 banks)
+  float *yt;     // [kTrainB] targets
+  float *gy;     // [kTrainB] dLoss / dyhat
+  float *sq;     // [kTrainB] squared errors
+  float *red;    // [kTrainWaves][kTrainB] per-wavefront output-layer sums
+  float *scal;   // [4]: b2, validation error
+  int ldx;
+};
+
+__device__ inline TrainLds train_lds(float *base, int m) {
+  TrainLds t;
+  t.ldx = m + 1;
+  t.xb = base;
+  t.yt = t.xb + kTrainB * t.ldx;
+  t.gy = t.yt + kTrainB;
+  t.sq = t.gy + kTrainB;
+  t.red = t.sq + kTrainB;
+  t.scal = t.red + kTrainWaves * kTrainB;
+  return t;
+}
+size_t train_lds_floats(int m) { return static_cast<size_t>(kTrainB) * (m + 1) + 3 * kTrainB + kTrainWaves * kTrainB + 4; }
+
+// Hidden unit of this lane in hidden tile i of its wavefront.
+__device__ __forceinline__ int train_unit(int i) {
+  return 16 * (kTrainHT * (threadIdx.x / kWave) + i) + (threadIdx.x & 15);
+}
+
+// The wavefront's W1 slice, b1 and w2 from the packed weights (units >= h: zero).
+template <int MT>
+__device__ inline void train_load(const float *wf, int m, int h, float (&W)[kTrainHT][MT][4], float (&b1r)[kTrainHT],
+                                  float (&w2r)[kTrainHT]) {
+  const int q = (threadIdx.x & (kWave - 1)) >> 4;
+#pragma unroll
+  for (int i = 0; i < kTrainHT; ++i) {
+    const int j = train_unit(i);
+    const bool act = j < h;
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) W[i][ti][r] = act ? wf[static_cast<int64_t>(16 * ti + 4 * q + r) * h + j] : 0.0f;
+    b1r[i] = act ? wf[static_cast<int64_t>(h) * m + j] : 0.0f;
+    w2r[i] = act ? wf[static_cast<int64_t>(h) * m + h + j] : 0.0f;
+  }
+}
+
+// Write the wavefront's W1 slice, b1 and w2 into packed weights (the four
+// quarters of the wavefront hold the same b1 and w2; the first writes them).
+template <int MT>
+__device__ inline void train_store(float *wf, int m, int h, const float (&W)[kTrainHT][MT][4],
+                                   const float (&b1r)[kTrainHT], const float (&w2r)[kTrainHT]) {
+  const int q = (threadIdx.x & (kWave - 1)) >> 4;
+#pragma unroll
+  for (int i = 0; i < kTrainHT; ++i) {
+    const int j = train_unit(i);
+    if (j >= h) continue;
+    // one running address, made opaque after every step: the compiler would
+    // otherwise compute all MT x 4 addresses once and keep them live across
+    // the whole training loop that calls this
+    float *p = wf + static_cast<int64_t>(4 * q) * h + j;
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        *p = W[i][ti][r];
+        p += h;
+        asm volatile("" : "+v"(p));
+      }
+      p += static_cast<int64_t>(12) * h;
+    }
+    if (q == 0) {
+      wf[static_cast<int64_t>(h) * m + j] = b1r[i];
+      wf[static_cast<int64_t>(h) * m + h + j] = w2r[i];
+    }
+  }
+}
+
+// One step on the nb (<= 64) rows staged in LDS (rows nb .. 63 are zero):
+// forward pass and squared errors, and with `update` the plain SGD step of
+// the mean squared error with learning rate lr.  Returns the sum of squared
+// errors (valid in thread 0).  Every thread of the work-group calls it.
+// Hidden units >= h have zero weights, b1 and w2 and are never updated
+// (their Delta is zero), so they add nothing.
+template <int MT, bool update>
+__device__ inline float train_step(float (&W)[kTrainHT][MT][4], float (&b1r)[kTrainHT], float (&w2r)[kTrainHT], int h,
+                                   int nb, float lr, const TrainLds &t) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int q = lane >> 4, col = lane & 15;
+  const bool act = 16 * kTrainHT * wave < h;  // any hidden unit of this wavefront in use
+  constexpr int ldx = 16 * MT + 1;            // t.ldx as a constant: LDS offsets become immediates
+  floatx4_t Z[kTrainHT][4];
+#pragma unroll
+  for (int i = 0; i < kTrainHT; ++i)
+#pragma unroll
+    for (int tb = 0; tb < 4; ++tb) Z[i][tb] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  if (act) {
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) {
+      __builtin_amdgcn_sched_barrier(0);  // one input tile's operands in flight at a time
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb) {
+          const float a = t.xb[(16 * tb + col) * ldx + 16 * ti + 4 * q + s];
+#pragma unroll
+          for (int i = 0; i < kTrainHT; ++i) Z[i][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, W[i][ti][s], Z[i][tb], 0, 0, 0);
+        }
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // output layer: per lane over its hidden units, then over the quarter's 16 lanes
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float p = 0.0f;
+#pragma unroll
+      for (int i = 0; i < kTrainHT; ++i) p = fmaf(w2r[i], fmaxf(Z[i][tb][r] + b1r[i], 0.0f), p);
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
+      if (col == 0) t.red[wave * kTrainB + 16 * tb + 4 * q + r] = p;
+    }
+  __syncthreads();
+  if (threadIdx.x < kTrainB) {
+    const int c = threadIdx.x;
+    float yh = t.scal[0];
+    for (int w = 0; w < kTrainWaves; ++w) yh += t.red[w * kTrainB + c];
+    const float e = c < nb ? yh - t.yt[c] : 0.0f;
+    t.gy[c] = 2.0f * e / static_cast<float>(nb);
+    t.sq[c] = e * e;
+  }
+  __syncthreads();
+  float loss = 0.0f;
+  if (threadIdx.x == 0)
+    for (int c = 0; c < nb; ++c) loss += t.sq[c];
+  if (!update) return loss;
+  // Delta = dL/dZ into the forward tiles; gradients of w2 and b1
+  float gw2[kTrainHT], gb1[kTrainHT];
+#pragma unroll
+  for (int i = 0; i < kTrainHT; ++i) gw2[i] = gb1[i] = 0.0f;
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float g = t.gy[16 * tb + 4 * q + r];
+#pragma unroll
+      for (int i = 0; i < kTrainHT; ++i) {
+        const float z = Z[i][tb][r] + b1r[i];
+        gw2[i] = fmaf(g, fmaxf(z, 0.0f), gw2[i]);
+        const float d = z > 0.0f ? g * w2r[i] : 0.0f;
+        Z[i][tb][r] = d;
+        gb1[i] += d;
+      }
+    }
+#pragma unroll
+  for (int i = 0; i < kTrainHT; ++i) {
+    gw2[i] += __shfl_xor(gw2[i], 16, kWave);
+    gb1[i] += __shfl_xor(gb1[i], 16, kWave);
+    gw2[i] += __shfl_xor(gw2[i], 32, kWave);
+    gb1[i] += __shfl_xor(gb1[i], 32, kWave);
+  }
+  // dW1 = X^T Delta, one 16-input tile at a time, applied at once
+  if (act) {
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) {
+      __builtin_amdgcn_sched_barrier(0);
+      floatx4_t G[kTrainHT];
+#pragma unroll
+      for (int i = 0; i < kTrainHT; ++i) G[i] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float a = t.xb[(16 * tb + 4 * q + s) * ldx + 16 * ti + col];
+#pragma unroll
+          for (int i = 0; i < kTrainHT; ++i) G[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Z[i][tb][s], G[i], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < kTrainHT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) W[i][ti][r] = fmaf(-lr, G[i][r], W[i][ti][r]);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < kTrainHT; ++i) {
+    b1r[i] = fmaf(-lr, gb1[i], b1r[i]);
+    w2r[i] = fmaf(-lr, gw2[i], w2r[i]);
+  }
+  __syncthreads();  // every thread has read b2 and gy
+  if (threadIdx.x == 0) {
+    float gs = 0.0f;
+    for (int c = 0; c < nb; ++c) gs += t.gy[c];
+    t.scal[0] = fmaf(-lr, gs, t.scal[0]);
+  }
+  return loss;
+}
+
+// Stage nb rows into the batch: row c is xq[qidx[c]] (or x + c m without an
+// index), rows nb .. 63 zero; targets likewise.
+__device__ inline void train_stage(const float *xq, const int32_t *qidx, const float *y, int nb, int m,
+                                   const TrainLds &t) {
+  for (int e = threadIdx.x; e < kTrainB * m; e += blockDim.x) {
+    const int c = e / m, i = e - c * m;
+    float v = 0.0f;
+    if (c < nb) v = xq[static_cast<int64_t>(qidx ? qidx[c] : c) * m + i];
+    t.xb[c * t.ldx + i] = v;
+  }
+  for (int c = threadIdx.x; c < kTrainB; c += blockDim.x) t.yt[c] = c < nb ? y[c] : 0.0f;
+  __syncthreads();
+}
+
+template <int MT>
+__global__ void __launch_bounds__(kTrainThreads, 1) k_mlp_sgd_step_mfma(float *w, int m, int h, const float *x,
+                                                                        const float *y, int batch, float lr,
+                                                                        float *loss_out) {
+  extern __shared__ __align__(16) float lds[];
+  const TrainLds t = train_lds(lds, m);
+  const int f = blockIdx.x;
+  const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
+  float *wf = w + f * P;
+  float W[kTrainHT][MT][4], b1r[kTrainHT], w2r[kTrainHT];
+  train_load<MT>(wf, m, h, W, b1r, w2r);
+  if (threadIdx.x == 0) t.scal[0] = wf[P - 1];
+  train_stage(x + static_cast<int64_t>(f) * batch * m, nullptr, y + static_cast<int64_t>(f) * batch, batch, m, t);
+  const float sse = train_step<MT, true>(W, b1r, w2r, h, batch, lr, t);
+  __syncthreads();
+  train_store<MT>(wf, m, h, W, b1r, w2r);
+  if (threadIdx.x == 0) {
+    wf[P - 1] = t.scal[0];
+    if (loss_out) loss_out[f] = sse / static_cast<float>(batch);
+  }
+}
+
+// The whole SGD run of one filter per work-group (same schedule as
+// k_mlp_train: per-epoch shuffle, validation after each epoch, the learning
+// rate divided by 10 after `patience` epochs without a 1e-4 relative
+// improvement, stop below lr_min, best-validation weights kept).
+template <int MT>
+__global__ void __launch_bounds__(kTrainThreads, 1) k_mlp_train_mfma(TrainArgs a) {
+  extern __shared__ __align__(16) float lds[];
+  const int m = a.m, h = a.h;
+  const TrainLds t = train_lds(lds, m);
+  int32_t *perm = reinterpret_cast<int32_t *>(t.scal + 4);  // [n_train]
+  int32_t *bq = perm + a.n_train;                            // [kTrainB]
+  float *by = reinterpret_cast<float *>(bq + kTrainB);       // [kTrainB]
+  __shared__ int stop;
+  const int f = blockIdx.x;
+  const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
+  float *wf = a.w + f * P;
+  float *wb = a.w_best + f * P;
+  const int32_t *exq = a.ex_q + static_cast<int64_t>(f) * a.n_ex;
+  const float *exy = a.ex_y + static_cast<int64_t>(f) * a.n_ex;
+  const int n_val = a.n_ex - a.n_train;
+  float W[kTrainHT][MT][4], b1r[kTrainHT], w2r[kTrainHT];
+  train_load<MT>(wf, m, h, W, b1r, w2r);
+  // output bias starts at the mean training target
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int e = 0; e < a.n_train; ++e) acc += exy[e];
+    t.scal[0] = static_cast<float>(acc / (a.n_train > 0 ? a.n_train : 1));
+    wb[P - 1] = t.scal[0];
+  }
+  for (int e = threadIdx.x; e < a.n_train; e += blockDim.x) perm[e] = e;
+  train_store<MT>(wb, m, h, W, b1r, w2r);
+  __syncthreads();
+  float best = __builtin_inff();
+  float lr = a.lr0;
+  int bad = 0, epoch = 0;
+  for (; epoch < a.max_epochs; ++epoch) {
+    if (threadIdx.x == 0) {  // Fisher-Yates shuffle with a counter-based generator
+      for (int e = a.n_train - 1; e > 0; --e) {
+        uint64_t r = mix64(a.seed ^ mix64((static_cast<uint64_t>(f) << 40) ^ (static_cast<uint64_t>(epoch) << 20) ^ e));
+        int o = static_cast<int>(r % static_cast<uint64_t>(e + 1));
+        int tmp = perm[e];
+        perm[e] = perm[o];
+        perm[o] = tmp;
+      }
+    }
+    __syncthreads();
+    for (int s0 = 0; s0 < a.n_train; s0 += a.batch) {
+      const int nb = a.n_train - s0 < a.batch ? a.n_train - s0 : a.batch;
+      for (int c = threadIdx.x; c < nb; c += blockDim.x) {
+        bq[c] = exq[perm[s0 + c]];
+        by[c] = exy[perm[s0 + c]];
+      }
+      __syncthreads();
+      train_stage(a.xq, bq, by, nb, m, t);
+      train_step<MT, true>(W, b1r, w2r, h, nb, lr, t);
+      __syncthreads();
+    }
+    // validation error (forward passes only)
+    float vsum = 0.0f;
+    for (int s0 = 0; s0 < n_val; s0 += kTrainB) {
+      const int nb = n_val - s0 < kTrainB ? n_val - s0 : kTrainB;
+      train_stage(a.xq, exq + a.n_train + s0, exy + a.n_train + s0, nb, m, t);
+      vsum += train_step<MT, false>(W, b1r, w2r, h, nb, 0.0f, t);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const float vm = n_val > 0 ? vsum / n_val : 0.0f;
+      if (a.val_trace) a.val_trace[static_cast<int64_t>(f) * a.max_epochs + epoch] = vm;
+      t.scal[1] = vm;
+    }
+    __syncthreads();
+    const float vm = t.scal[1];
+    const bool improved = vm < best * (1.0f - 1e-4f);
+    if (improved) {
+      best = vm;
+      bad = 0;
+      train_store<MT>(wb, m, h, W, b1r, w2r);
+      if (threadIdx.x == 0) wb[P - 1] = t.scal[0];
+    } else if (++bad >= a.patience) {
+      lr *= 0.1f;
+      bad = 0;
+    }
+    if (threadIdx.x == 0) stop = (lr < a.lr_min * (1.0f - 1e-3f)) || !(vm == vm);
+    __syncthreads();
+    if (stop) {
+      ++epoch;
+      break;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < P; e += blockDim.x) wf[e] = wb[e];
+  if (threadIdx.x == 0) {
+    a.val_mse[f] = best;
+    a.epochs_run[f] = epoch;
+  }
+}
+
+// Shapes the matrix-core training serves: inputs and hidden units multiples
+// of 16, at most 256 each.
+bool train_mfma_ok(int m, int h) { return m % 16 == 0 && h % 16 == 0 && m <= 256 && h <= 16 * kTrainHT * kTrainWaves; }
+
+template <int MT>
+void launch_train_mfma_mt(const TrainArgs &a, hipStream_t st) {
+  const size_t lds = train_lds_floats(a.m) * 4 + static_cast<size_t>(a.n_train) * 4 + kTrainB * 8;
+  auto kern = k_mlp_train_mfma<MT>;
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(a.F), dim3(kTrainThreads), lds, st, a);
+  LAUNCH_OK("mlp_train_mfma");
+}
+
+template <int MT>
+void launch_sgd_mfma_mt(float *w, int F, int m, int h, const float *x, const float *y, int batch, float lr,
+                        float *loss, hipStream_t st) {
+  const size_t lds = train_lds_floats(m) * 4;
+  auto kern = k_mlp_sgd_step_mfma<MT>;
+  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(F), dim3(kTrainThreads), lds, st, w, m, h, x, y, batch, lr, loss);
+  LAUNCH_OK("mlp_sgd_step_mfma");
+}
+
 }  // namespace
 
 void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, hipStream_t st) {
@@ -645,6 +1030,26 @@ static size_t step_lds(int m) { return static_cast<size_t>(m) * kTB * 4 + (4 + 3
 
 void launch_mlp_sgd_step(float *w, int F, int m, int h, const float *x, const float *y, int batch, float lr,
                          float *loss, hipStream_t st) {
+  if (train_mfma_ok(m, h)) {
+    switch (m / 16) {
+      case 1: launch_sgd_mfma_mt<1>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 2: launch_sgd_mfma_mt<2>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 3: launch_sgd_mfma_mt<3>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 4: launch_sgd_mfma_mt<4>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 5: launch_sgd_mfma_mt<5>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 6: launch_sgd_mfma_mt<6>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 7: launch_sgd_mfma_mt<7>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 8: launch_sgd_mfma_mt<8>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 9: launch_sgd_mfma_mt<9>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 10: launch_sgd_mfma_mt<10>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 11: launch_sgd_mfma_mt<11>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 12: launch_sgd_mfma_mt<12>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 13: launch_sgd_mfma_mt<13>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 14: launch_sgd_mfma_mt<14>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 15: launch_sgd_mfma_mt<15>(w, F, m, h, x, y, batch, lr, loss, st); return;
+      case 16: launch_sgd_mfma_mt<16>(w, F, m, h, x, y, batch, lr, loss, st); return;
+    }
+  }
   size_t lds = step_lds(m);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_sgd_step),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -653,6 +1058,26 @@ void launch_mlp_sgd_step(float *w, int F, int m, int h, const float *x, const fl
 }
 
 void launch_mlp_train(const TrainArgs &a, hipStream_t st) {
+  if (train_mfma_ok(a.m, a.h)) {
+    switch (a.m / 16) {
+      case 1: launch_train_mfma_mt<1>(a, st); return;
+      case 2: launch_train_mfma_mt<2>(a, st); return;
+      case 3: launch_train_mfma_mt<3>(a, st); return;
+      case 4: launch_train_mfma_mt<4>(a, st); return;
+      case 5: launch_train_mfma_mt<5>(a, st); return;
+      case 6: launch_train_mfma_mt<6>(a, st); return;
+      case 7: launch_train_mfma_mt<7>(a, st); return;
+      case 8: launch_train_mfma_mt<8>(a, st); return;
+      case 9: launch_train_mfma_mt<9>(a, st); return;
+      case 10: launch_train_mfma_mt<10>(a, st); return;
+      case 11: launch_train_mfma_mt<11>(a, st); return;
+      case 12: launch_train_mfma_mt<12>(a, st); return;
+      case 13: launch_train_mfma_mt<13>(a, st); return;
+      case 14: launch_train_mfma_mt<14>(a, st); return;
+      case 15: launch_train_mfma_mt<15>(a, st); return;
+      case 16: launch_train_mfma_mt<16>(a, st); return;
+    }
+  }
   size_t lds = step_lds(a.m) + static_cast<size_t>(a.n_train) * 4 + kTB * 8;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_train),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));

@@ -156,3 +156,56 @@ def test_filter_tiles_forced_and_automatic_are_identical_and_match_oracle(rw20k_
     if not r.near_tie.any():
         assert st["leaves_filter_pruned"] == int(r.f_pruned.sum())
         assert st["leaves_scanned"] == int(r.scanned.sum())
+
+
+def test_training_schedule_follows_the_plateau_rule_and_keeps_the_best_weights():
+    """The learning-rate schedule (divide by 10 after `patience` epochs without a
+    1e-4 relative validation improvement, stop below lr_min) re-simulated from
+    the recorded validation losses stops at the recorded epoch for every
+    filter; the kept weights are those of the best epoch: their validation MSE
+    under the FP64 oracle's forward pass equals the smallest recorded loss.  The
+    best loss at each learning-rate drop is non-increasing."""
+    pkg = _pkg()
+    wl = W.WORKLOADS["rw20k"]
+    raw = W.random_walk(wl["n"], wl["m"], wl["seed"])
+    ix = pkg.Index().build(torch.from_numpy(raw).cuda(), leaf_capacity=wl["capacity"], n_segments=16)
+    m = h = 256
+    w = (h * m + 2 * h + 1) * 4.0
+    lr0, lr_min, patience = 0.01, 1e-4, 3
+    rep = ix.train_filters(n_global=200, n_local=60, noise_lo=0.05, noise_hi=0.2, max_epochs=60, th_override=0.0,
+                           mem_budget=int(12 * w), seed=21, keep_examples=1, lr0=lr0, lr_min=lr_min,
+                           patience=patience)
+    F = rep["n_filters"]
+    assert F == 12
+    epochs, trace = ix.train_trace()
+    q, exq, y, n_train = ix.examples()
+    leaves, wts = ix.get_filters()
+    wts = wts.cpu().numpy().astype(np.float64)
+    qs, y = O.znorm(q.cpu().numpy()), y.cpu().numpy().astype(np.float64)
+    stops = 0
+    for f in range(F):
+        n = int(epochs[f])
+        assert 1 <= n <= 60 and np.isfinite(trace[f, :n]).all() and np.isnan(trace[f, n:]).all()
+        best, bad, lr, stop_at, drops = np.inf, 0, lr0, None, []
+        for e in range(n):
+            v = float(trace[f, e])
+            if v < best * (1 - 1e-4):
+                best, bad = v, 0
+            else:
+                bad += 1
+                if bad >= patience:
+                    lr *= 0.1
+                    bad = 0
+                    drops.append(best)
+            if lr < lr_min * (1 - 1e-3):
+                stop_at = e + 1
+                break
+        assert (stop_at or 60) == n, (f, stop_at, n)
+        stops += stop_at is not None
+        assert all(b2 <= b1 for b1, b2 in zip(drops, drops[1:]))
+        # the kept weights: validation MSE in FP64 = the best recorded loss
+        e_val = exq[f, n_train:]
+        pred = O.mlp_forward(wts[f], qs[e_val], m, h)
+        mse = float(np.mean((pred - y[f, n_train:]) ** 2))
+        assert abs(mse - np.nanmin(trace[f])) <= 2e-3 * np.nanmin(trace[f]), (f, mse, np.nanmin(trace[f]))
+    assert stops > 0  # the stopping rule was reached by some filter

@@ -234,9 +234,14 @@ def test_mlp_identity_special_case_on_gpu():
     assert np.allclose(got, np.maximum(x.astype(np.float64), 0).sum(1), rtol=1e-6)
 
 
-def test_sgd_step_matches_fp64_gradient():
+@pytest.mark.parametrize("F,m,h,B", [(3, 32, 32, 17), (2, 96, 96, 64), (2, 256, 256, 64), (3, 64, 48, 33),
+                                     (2, 36, 20, 9)])
+def test_sgd_step_matches_fp64_gradient(F, m, h, B):
+    """One SGD step per filter (the training kernel's step: FP32 matrix cores
+    for inputs and hidden units in multiples of 16 up to 256, a plain FP32
+    kernel otherwise) against the FP64 analytic gradient."""
     pkg = _pkg()
-    F, m, h, B, lr = 3, 32, 32, 17, 0.05
+    lr = 0.05
     w = W.mlp_weights(F, m, h, seed=3)
     rng = np.random.default_rng(4)
     x = rng.standard_normal((F, B, m)).astype(np.float32)
