@@ -211,6 +211,7 @@ void ensure_queries(leafi_index *ix, int64_t nq, int kmax) {
   w.order.reserve(nq * N);
   w.lbs.reserve(nq * N);
   w.dfo.reserve(nq * N);
+  w.qbound.reserve(nq);
   w.dfilt.reserve(nq * F);
   w.tau.reserve(nq);
   w.cursor.reserve(nq);
@@ -394,8 +395,16 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   else launch_scan_fp32(s, q, b, mq, kprime, w.cand.get(), grid_scan, st);
   if (e1 && !ext) HIP_OK(hipEventRecord(e1, st));
   int64_t ib = items >= 0 ? items : std::max<int64_t>(items_bound, 1);
-  int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : 16)));
-  launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks_for(chunk), st);
+  // one wavefront per item, a persistent grid of what is resident at once
+  // (three four-wavefront work-groups per CU)
+  int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : 12)));
+  // a search round's rerank skips candidates that cannot enter their query's top k
+  const bool bound = bf16 && ro->use_tau;
+  if (bound)
+    launch_query_bound(s, q, b, nq, mq, kprime, kmax, ix->max_chunks_for(chunk), ix->leaf_eps_max, w.cand.get(),
+                       w.qbound.get(), st);
+  launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks_for(chunk), st,
+                     bound ? w.qbound.get() : nullptr);
   return items;
 }
 
@@ -692,7 +701,8 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
                     static_cast<int64_t>(ix->S), static_cast<int64_t>(ix->filt.F), static_cast<int64_t>(ix->filt.h),
                     static_cast<int64_t>(ix->cal.pairs()), ix->rows,
                     static_cast<int64_t>(ix->tune_chunk), static_cast<int64_t>(ix->tune_mq),
-                    static_cast<int64_t>(p.ftile)})
+                    static_cast<int64_t>(p.ftile), static_cast<int64_t>(p.kp_query),
+                    static_cast<int64_t>(__builtin_bit_cast(uint32_t, ix->leaf_eps_max))})
     k.push_back(static_cast<uint64_t>(v));
   for (int r : p.schedule) k.push_back(static_cast<uint64_t>(r));
   for (const void *a : {static_cast<const void *>(raw), static_cast<const void *>(k_dev),
@@ -705,7 +715,8 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
                         static_cast<const void *>(ix->rowid.get()),
                         static_cast<const void *>(ix->filt.w.get()), static_cast<const void *>(ix->filt.filt_of_leaf.get()),
                         static_cast<const void *>(ix->cal.offsets.get()), static_cast<const void *>(ix->cal.pair_k.get()),
-                        static_cast<const void *>(ix->cal.pair_t.get()), static_cast<const void *>(w.ptile.get())})
+                        static_cast<const void *>(ix->cal.pair_t.get()), static_cast<const void *>(w.ptile.get()),
+                        static_cast<const void *>(w.qbound.get())})
     ptr(a);
   if (timed)
     for (hipEvent_t e : w.sev) ptr(e);
@@ -1003,6 +1014,12 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     HIP_OK(hipMemsetAsync(ix->leaf_eps.get(), 0, N * sizeof(float), st));
     launch_pack(series, dsrc.get(), dleaf.get(), rows, m, mean.get(), sd.get(), ix->x32.get(), ix->x16.get(),
                 ix->xn16.get(), ix->rowid.get(), ix->leaf_eps.get(), st);
+    {
+      std::vector<float> eps(N);
+      d2h(eps.data(), ix->leaf_eps.get(), N, st);
+      HIP_OK(hipStreamSynchronize(st));
+      ix->leaf_eps_max = *std::max_element(eps.begin(), eps.end());
+    }
     std::vector<int32_t> ln32(N);
     for (int L = 0; L < N; ++L) ln32[L] = static_cast<int32_t>(lsz[L]);
     h2d(ix->leaf_off.get(), off.data(), N + 1, st);

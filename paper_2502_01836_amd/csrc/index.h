@@ -133,6 +133,7 @@ struct Workspace {
   DevBuf<int64_t> plist;        // filter pairs to evaluate (q * N + visit position)
   DevBuf<int32_t> pcnt;
   DevBuf<float> lbs, dfo;       // [nq, N] in visit order: summary bound, filter pruning value
+  DevBuf<float> qbound;         // [nq] a search round's bound on each query's k-th distance (rerank)
   DevBuf<int32_t> ptile;        // prefix of the filters' 16-query inference tiles [F + 1]
   DevBuf<int64_t> ctl;
   std::vector<int64_t> h_ctl;
@@ -160,6 +161,7 @@ struct leafi_index {
   int64_t total_chunks_for(int chunk) const { return chunks_total[leafi::chunk_log(chunk)]; }
   // leaf store (device)
   leafi::DevBuf<float> x32, xn16, boxes, leaf_eps;
+  float leaf_eps_max = 0.0f;  // the largest leaf_eps
   leafi::DevBuf<float> boxes_t;  // the boxes as [S][4][N]: one value of every leaf, contiguous
   leafi::DevBuf<uint16_t> x16;
   leafi::DevBuf<int64_t> rowid, leaf_off;

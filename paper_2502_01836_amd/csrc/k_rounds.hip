@@ -150,24 +150,31 @@ __global__ void __launch_bounds__(256) k_filter_pairs(int64_t nq, int N, const f
                                                       const int32_t *__restrict__ filt_of_leaf, RoundBufs b,
                                                       const int32_t *__restrict__ qround, int64_t *plist,
                                                       int32_t *pcnt, float *dfo) {
-  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= nq * N) return;
-  int64_t q = idx / N;
-  int pos = static_cast<int>(idx - q * N);
-  if (qround && qround[q] != 1) return;  // serving: only queries that just finished their first round
-  if (pos < b.cursor[q] || b.pair[q] < 0) return;
-  const int f = filt_of_leaf[order[idx]];
-  const bool sel = !(f < 0 || lbs[idx] > b.tau[q] * (1.0f + kLbSlack));
-  // one count per wavefront of the pairs it queues
-  const uint64_t mk = __ballot(sel);
-  if ((threadIdx.x & (kWave - 1)) == __builtin_ctzll(__ballot(1)))
-    atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFEvals), static_cast<unsigned long long>(__popcll(mk)));
-  if (!sel) {
-    dfo[idx] = -__builtin_inff();
-    return;
+  __shared__ int fe_sh[4];
+  int n_fe = 0;  // pairs this lane queued (counted once per work-group: a per-wavefront atomic on
+                 // one control word serialised on its cache line)
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < nq * N;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t q = idx / N;
+    const int pos = static_cast<int>(idx - q * N);
+    if (qround && qround[q] != 1) continue;  // serving: only queries that just finished their first round
+    if (pos < b.cursor[q] || b.pair[q] < 0) continue;
+    const int f = filt_of_leaf[order[idx]];
+    if (f < 0 || lbs[idx] > b.tau[q] * (1.0f + kLbSlack)) {
+      dfo[idx] = -__builtin_inff();
+      continue;
+    }
+    const int slot = atomicAdd(pcnt + f, 1);
+    plist[static_cast<int64_t>(f) * nq + slot] = idx;
+    ++n_fe;
   }
-  int slot = atomicAdd(pcnt + f, 1);
-  plist[static_cast<int64_t>(f) * nq + slot] = idx;
+  n_fe = wave_sum(n_fe);
+  if ((threadIdx.x & (kWave - 1)) == 0) fe_sh[threadIdx.x / kWave] = n_fe;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int e = fe_sh[0] + fe_sh[1] + fe_sh[2] + fe_sh[3];
+    if (e) atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlFEvals), static_cast<unsigned long long>(e));
+  }
 }
 
 __global__ void __launch_bounds__(256) k_emit_fallback(int N, RoundBufs b) {
@@ -770,8 +777,10 @@ void launch_worklist(int64_t nq, int N, const float *lbs, const int32_t *order, 
 void launch_filter_pairs(int64_t nq, int N, const float *lbs, const int32_t *order, const int32_t *filt_of_leaf,
                          RoundBufs b, int64_t *plist, int32_t *pcnt, float *dfo, hipStream_t st,
                          const int32_t *qround) {
-  hipLaunchKernelGGL(k_filter_pairs, dim3(ceil_div(nq * N, 256)), dim3(256), 0, st, nq, N, lbs, order, filt_of_leaf,
-                     b, qround, plist, pcnt, dfo);
+  // a grid-stride loop over (query, visit position) with a few work-groups per CU
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>(ceil_div(nq * N, 256), 1), 4096);
+  hipLaunchKernelGGL(k_filter_pairs, dim3(static_cast<int>(blocks)), dim3(256), 0, st, nq, N, lbs, order,
+                     filt_of_leaf, b, qround, plist, pcnt, dfo);
   LAUNCH_OK("filter_pairs");
 }
 

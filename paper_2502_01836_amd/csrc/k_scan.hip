@@ -494,9 +494,117 @@ __device__ inline void select_keys(const uint64_t *__restrict__ cand, int64_t t0
   }
 }
 
+// ---- a query's bound for the rerank --------------------------------------------
+//
+// After a search round's BF16 scan, every candidate list of a query is sorted
+// by key (bf16 squared distance, row).  The k smallest keys over all of them
+// belong to k distinct rows, each no farther than sqrt(key + delta16) + eps_q
+// + eps_L, so the query's k-th exact distance after this round's merge is at
+// most U = sqrt(kth key + delta16) + eps_q + max_L eps_L (and at most its tau
+// before the round).  A candidate whose lower bound sqrt(key - delta16) -
+// eps_q - eps_L exceeds U can never enter the query's top k, so the rerank
+// skips its FP32 and FP64 distances.  The k-th smallest key is found by a
+// tournament over the list heads (k rounds of a wavefront minimum), 64 x
+// kBoundSlots lists per pass; a pass keeps the k smallest so far in LDS for
+// the next.
+constexpr int kBoundSlots = 4;
+
+__device__ inline int bound_pass(int64_t q, int N, int k, int kprime, int mq, int chunk, int cmax, const RoundBufs &b,
+                                 const StoreView &s, const uint64_t *__restrict__ cand, int l0, int nl,
+                                 const uint64_t *in, int n_in, uint64_t *out, int lane) {
+  uint64_t hd[kBoundSlots], n1[kBoundSlots], n2[kBoundSlots];
+  int64_t base[kBoundSlots];
+  int pos[kBoundSlots], cnt[kBoundSlots];
+  const int kp = item_kprime(b.kp_query, kprime, k, true);
+#pragma unroll
+  for (int i = 0; i < kBoundSlots; ++i) {
+    const int lam = l0 + lane + kWave * i;
+    cnt[i] = 0;
+    base[i] = 0;
+    if (lam < l0 + nl) {
+      const int r = lam / cmax, c = lam - r * cmax;
+      const int idx = b.qitem_idx[q * N + r];
+      const int L = b.item_leaf[idx];
+      const int ist0 = b.leaf_istart[L], ist1 = b.leaf_istart[L + 1];
+      const int C = static_cast<int>((s.leaf_off[L + 1] - s.leaf_off[L] + chunk - 1) / chunk);
+      if (c < C) {
+        const int p = idx - ist0, g = p / mq, j = p - g * mq, G = (ist1 - ist0 + mq - 1) / mq;
+        base[i] = (tile_of(b.tile_start, L, g, c, G) * mq + j) * kprime;
+        cnt[i] = kp;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kBoundSlots; ++i) {
+    hd[i] = cnt[i] > 0 ? cand[base[i]] : kKeyMax;
+    n1[i] = cnt[i] > 1 ? cand[base[i] + 1] : kKeyMax;
+    n2[i] = cnt[i] > 2 ? cand[base[i] + 2] : kKeyMax;
+    pos[i] = 3;
+  }
+  int o = 0, rp = 0;
+  while (o < k) {
+    uint64_t lo = kKeyMax;
+#pragma unroll
+    for (int i = 0; i < kBoundSlots; ++i) lo = hd[i] < lo ? hd[i] : lo;
+    uint64_t g = wave_min_u64(lo);
+    const uint64_t rv = rp < n_in ? in[rp] : kKeyMax;
+    g = rv < g ? rv : g;
+    if (g == kKeyMax) break;  // every list is exhausted
+    if (lane == 0) out[o] = g;
+    ++o;
+    if (rv == g) ++rp;
+#pragma unroll
+    for (int i = 0; i < kBoundSlots; ++i) {
+      if (hd[i] == g) {  // the row may sit in two lists (a leaf rescanned): every copy advances
+        hd[i] = n1[i];
+        n1[i] = n2[i];
+        n2[i] = pos[i] < cnt[i] ? cand[base[i] + pos[i]] : kKeyMax;
+        ++pos[i];
+      }
+    }
+  }
+  wave_lds_sync();
+  return o;
+}
+
+__global__ void __launch_bounds__(256) k_query_bound(StoreView s, QueryView qv, RoundBufs b, int64_t nq, int mq,
+                                                     int kprime, int kmax, int cmax, float eps_max,
+                                                     const uint64_t *__restrict__ cand, float *qbound) {
+  extern __shared__ uint64_t bsm[];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  uint64_t *buf0 = bsm + static_cast<size_t>(wave) * 2 * kmax, *buf1 = buf0 + kmax;
+  const int N = s.N, m = s.m;
+  for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
+    const int n_it = b.qitem_cnt[q];
+    const int k = b.kq[q];
+    float U = b.tau[q];
+    if (n_it > 0) {
+      const int nlists = n_it * cmax;
+      uint64_t *in = buf0, *out = buf1;
+      int n_in = 0;
+      for (int l0 = 0; l0 < nlists; l0 += kWave * kBoundSlots) {
+        const int nl = nlists - l0 < kWave * kBoundSlots ? nlists - l0 : kWave * kBoundSlots;
+        n_in = bound_pass(q, N, k, kprime, mq, b.chunk, cmax, b, s, cand, l0, nl, in, n_in, out, lane);
+        uint64_t *t = in;
+        in = out;
+        out = t;
+      }
+      if (n_in >= k) {
+        const double kd = static_cast<double>(key_d2(in[k - 1]));
+        const double v = sqrt(kd + bf16_delta(static_cast<double>(qv.qn16[q]), m)) + qv.qeps[q] + eps_max;
+        float u = static_cast<float>(v);
+        if (static_cast<double>(u) < v) u = nextafterf(u, __builtin_inff());
+        U = u < U ? u : U;
+      }
+    }
+    if (lane == 0) qbound[q] = U;
+  }
+}
+
 __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
                                                      int kmax, int bf16, int PB, int slice_u64,
-                                                     const uint64_t *__restrict__ cand) {
+                                                     const uint64_t *__restrict__ cand,
+                                                     const float *__restrict__ qbound) {
   extern __shared__ uint64_t smem[];
   // blockDim / 64 wavefronts per work-group, one item each, own LDS slice
   const int wave = threadIdx.x / kWave, wpb = blockDim.x / kWave;
@@ -532,6 +640,38 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
     const int kp = item_kprime(b.kp_query, kprime, k, bf16 != 0);
     const int PKi = pow2_at_least(kp < 2 ? 2 : kp);
     int n = C * kprime;
+    if (qbound) {
+      // Each chunk list is sorted, so its first key is its smallest; every
+      // row of the item has a key at least the smallest of them (or was never
+      // a candidate: key >= the tau threshold).  When even that bound exceeds
+      // the query's bound U, no row of the item can enter the query's top k:
+      // the item contributes nothing and is certified by that bound (no sort,
+      // no rerank).
+      const float U = qbound[q];
+      const int64_t t0 = b.tile_start[L];
+      uint64_t h = kKeyMax;
+      for (int c = lane; c < C; c += kWave) {
+        const uint64_t v = cand[((t0 + static_cast<int64_t>(c) * G + g) * mq + j) * kprime];
+        h = v < h ? v : h;
+      }
+      h = wave_min_u64(h);
+      float kd = h != kKeyMax ? key_d2(h) : __builtin_inff();
+      kd = fminf(kd, tau_threshold(tau_q, qn_q, qe_q, le_L, m));
+      double lower = -1.0;
+      if (kd < __builtin_inff()) {
+        const double v = static_cast<double>(kd) - bf16_delta(qn_q, m);
+        lower = (v > 0.0 ? sqrt(v) : 0.0) - qe_q - le_L;
+      }
+      if (lower > static_cast<double>(U)) {  // uniform
+        if (lane == 0) {
+          float lb = static_cast<float>(lower);
+          if (static_cast<double>(lb) > lower) lb = nextafterf(lb, -__builtin_inff());
+          b.item_cnt[item] = 0;
+          b.item_bound[item] = lb;
+        }
+        continue;
+      }
+    }
     if (kp <= kSelectMax && n <= kWave * kSelectPerLane) {
       // few keys wanted from many: kp rounds of a wavefront minimum, each
       // lane holding as few registers as n needs
@@ -557,6 +697,21 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
     // number of real candidates among the first kp
     int nc = 0;
     for (int e = 0; e < kp; ++e) nc += buf[e] != kKeyMax ? 1 : 0;
+    if (qbound) {
+      // search rounds: only candidates that can still enter the query's top k
+      // (lower bound not above the query's bound) are reranked; the keys are
+      // ascending, so they are a prefix
+      const float U = qbound[q];
+      const double dq = bf16_delta(static_cast<double>(qn_q), m);
+      int use = 0;
+      for (int e = 0; e < nc; ++e) {
+        const double v = static_cast<double>(key_d2(buf[e])) - dq;
+        const double lower = (v > 0.0 ? sqrt(v) : 0.0) - qe_q - le_L;
+        if (lower > static_cast<double>(U)) break;
+        ++use;
+      }
+      nc = use;
+    }
     // FP32 direct-difference rerank: CB candidates at a time, G lanes each
     // (all their rows are in flight together), 4 consecutive elements per lane
     const float *qp = qv.q32 + q * m;
@@ -852,8 +1007,18 @@ int rerank_lds_bytes(int max_chunks, int kprime, int *PB) {
   return (*PB + PK) * 8 + PK * 8 + PK * 4;
 }
 
+void launch_query_bound(StoreView s, QueryView q, RoundBufs b, int64_t nq, int mq, int kprime, int kmax, int cmax,
+                        float eps_max, const uint64_t *cand, float *qbound, hipStream_t st) {
+  if (nq <= 0) return;
+  const size_t lds = 4 * 2 * static_cast<size_t>(kmax) * sizeof(uint64_t);
+  const int64_t blocks = ceil_div(nq, 4);
+  hipLaunchKernelGGL(k_query_bound, dim3(static_cast<unsigned>(blocks < 65536 ? blocks : 65536)), dim3(256), lds, st, s,
+                     q, b, nq, mq, kprime, kmax, cmax, eps_max, cand, qbound);
+  LAUNCH_OK("query_bound");
+}
+
 void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int kmax, bool bf16,
-                        const uint64_t *cand, int grid, int max_chunks, hipStream_t st) {
+                        const uint64_t *cand, int grid, int max_chunks, hipStream_t st, const float *qbound) {
   int PB;
   const size_t slice = round_up(rerank_lds_bytes(max_chunks, kprime, &PB), 16);
   const int wpb = slice * 4 <= 65536 ? 4 : 1;
@@ -862,7 +1027,7 @@ void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprim
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   const int blocks = (grid + wpb - 1) / wpb;
   hipLaunchKernelGGL(k_item_rerank, dim3(blocks), dim3(64 * wpb), lds, st, s, q, b, mq, kprime, kmax, bf16 ? 1 : 0, PB,
-                     static_cast<int>(slice / 8), cand);
+                     static_cast<int>(slice / 8), cand, qbound);
   LAUNCH_OK("item_rerank");
 }
 

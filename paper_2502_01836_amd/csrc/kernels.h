@@ -227,8 +227,15 @@ void launch_scan_fp32(StoreView s, QueryView q, RoundBufs b, int mq, int kprime,
 
 // Per item: merge its tiles' candidates, rerank in FP32 (FP64 for the band
 // around the k-th), write the item's top-k and its certificate bound.
+// Per query of a search round after its BF16 scan: qbound[q] = an upper bound
+// of the query's k-th distance after the round (from the k-th smallest key
+// over all its candidate lists, and its tau), for the rerank to skip
+// candidates that cannot enter its top k.  cmax = chunks of the largest leaf;
+// eps_max = the largest leaf rounding radius.
+void launch_query_bound(StoreView s, QueryView q, RoundBufs b, int64_t nq, int mq, int kprime, int kmax, int cmax,
+                        float eps_max, const uint64_t *cand, float *qbound, hipStream_t st);
 void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int kmax, bool bf16,
-                        const uint64_t *cand, int grid, int max_chunks, hipStream_t st);
+                        const uint64_t *cand, int grid, int max_chunks, hipStream_t st, const float *qbound = nullptr);
 
 // Candidate-list geometry for kprime kept keys: queries per tile and list
 // capacity.  For kprime <= 32 the queries per tile are mq_small (16 or 32).

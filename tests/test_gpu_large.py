@@ -3,11 +3,14 @@ compute one query at a time.
 
 * 10,000,000 random walks of length 256 (precision case): batches of 1,024
   queries, k = 10, BF16 scan with FP32 rerank; per-query error against FP64
-  brute force over all 10M series.
+  brute force over all 10M series; filtered search with seeded filters
+  against the oracle's Algorithm 2 at equal schedule.
 * 25,000,000 Gaussian-mixture series of length 96 split at range midpoints
-  (ragged leaves): 4,096 queries with k = 1, 10, 50 in one batch.
+  (ragged leaves): 4,096 queries with k = 1, 10, 50 in one batch; filters
+  with infinite offsets give the exact results.
 
-Each builds its collection once (about a minute of host time each).
+At both sizes the batch's bound-sized buffers exceed the planned-sequence
+limit, so batches run host-driven rounds (statistics path 0).
 """
 import sys
 
@@ -50,14 +53,24 @@ def _check(ids, d, want_ids, want_d, xs, qs):
     return rel.max(axis=1)
 
 
-def test_precision_10m_k10():
+def test_precision_10m_k10_exact_and_filtered():
+    """10M random walks, batches of 1,024 queries at k = 10.  Exact search: 16
+    sampled queries against FP64 brute force over all 10M series, per-query
+    maximum relative distance error printed; the default execution and
+    host-driven rounds give identical results (at this size the batch's
+    bound-sized buffers exceed the planned-sequence limit, so both are
+    host-driven: path 0).  Filtered search with seeded filters on every leaf:
+    the same 16 queries against the oracle's Algorithm 2 at the same schedule
+    (the oracle's own tree, bounds, visit order, per-leaf neighbours and FP64
+    filter outputs)."""
     pkg = _pkg()
     wl = W.WORKLOADS["rw10m"]
     raw = W.random_walk(wl["n"], wl["m"], wl["seed"])
     _say("generated 10M x 256")
     ix = pkg.Index().build(torch.from_numpy(raw).cuda(), leaf_capacity=wl["capacity"], n_segments=16)
     torch.cuda.synchronize()
-    _say(f"built {ix.info()['n_leaves']} leaves")
+    N = ix.info()["n_leaves"]
+    _say(f"built {N} leaves")
     parts = [W.noisy_queries(raw, n, s, wl["test_seed"] + i, wl["test_seed"] + 100 + i)[0]
              for i, (n, s) in enumerate(zip((342, 341, 341), wl["sigmas"]))]
     q = np.concatenate(parts)
@@ -65,14 +78,26 @@ def test_precision_10m_k10():
     out = (torch.empty((len(q), 10), dtype=torch.int64, device="cuda"),
            torch.empty((len(q), 10), dtype=torch.float32, device="cuda"))
     res = []
-    for _ in range(3):  # planned launches, then captured, then replayed
-        ids, d, st = ix.search(qd, k=10, use_filters=False, schedule=(1, 0), with_stats=True, out=out)
+    for flags in (0, 0, pkg.SEARCH_HOST_ROUNDS):
+        ids, d, st = ix.search(qd, k=10, use_filters=False, schedule=(1, 0), with_stats=True, out=out, flags=flags)
         res.append((ids.clone(), d.clone(), st))
-    assert torch.equal(res[0][0], res[2][0]) and torch.equal(res[0][1], res[2][1])
-    st = res[2][2]
-    _say(f"search stats {st}")
+        assert st["path"] == 0, st
+    for r in res[1:]:
+        assert torch.equal(res[0][0], r[0]) and torch.equal(res[0][1], r[1])
+    st = res[0][2]
+    _say(f"exact search stats {st}")
     assert st["fallback_items"] <= 0.02 * st["leaves_scanned"] + 1
-    ids, d = res[2][0].cpu().numpy(), res[2][1].cpu().numpy().astype(np.float64)
+    ids, d = res[0][0].cpu().numpy(), res[0][1].cpu().numpy().astype(np.float64)
+    # filtered search: seeded filters on every leaf, seeded offsets for (k = 10, target 0.99)
+    h = 64
+    wts = W.mlp_weights(N, wl["m"], h, seed=3101, out_bias=8.0)
+    offs = np.random.default_rng(3102).uniform(0.0, 6.0, size=N).astype(np.float32)
+    ix.set_filters(np.arange(N, dtype=np.int32), torch.from_numpy(wts).cuda(), h)
+    ix.set_offsets([10], [0.99], offs[None])
+    fids, fd, fst = ix.search(qd, k=10, target=0.99, use_filters=True, schedule=(1, 0), with_stats=True)
+    _say(f"filtered search stats {fst}")
+    assert fst["leaves_filter_pruned"] > 0
+    fids, fd = fids.cpu().numpy(), fd.cpu().numpy().astype(np.float64)
     xs = O.znorm(raw)
     del raw
     rows = np.random.default_rng(11).choice(len(q), 16, replace=False)
@@ -80,6 +105,20 @@ def test_precision_10m_k10():
     want_ids, want_d = O.knn(xs, qs, 10)
     err = _check(ids[rows], d[rows], want_ids, want_d, xs, qs)
     _say(f"per-query max relative distance error vs FP64: {np.array2string(err, precision=2)}")
+    # the oracle's Algorithm 2 with the same filters, at the same schedule
+    mu, sd = O.segment_stats(xs, 16)
+    tree = O.build_tree(mu, sd, wl["m"], wl["capacity"], "median")
+    off_, mem_ = ix.leaves()
+    assert len(tree.leaves) == N
+    for L in range(N):
+        assert np.array_equal(mem_[off_[L]:off_[L + 1]], tree.leaves[L])
+    qmu, qsd = O.query_stats(qs, 16)
+    lb = O.lower_bound(qmu, qsd, O.leaf_boxes(mu, sd, tree), wl["m"])
+    ld, li = O.leaf_knn(xs, tree.leaves, qs, 10)
+    dF = np.stack([O.mlp_forward(wts[f], qs, wl["m"], h) for f in range(N)], 1) - offs[None].astype(np.float64)
+    r = O.leafi_search(lb, O.visit_order(lb), ld, li, 10, np.ones(N, dtype=bool), dF, (1, 0))
+    assert r.f_pruned.sum() > 0
+    _check(fids[rows], fd[rows], r.ids, r.dist, xs, qs)
 
 
 def test_ragged_25m_k_mix():
@@ -99,8 +138,25 @@ def test_ragged_25m_k_mix():
     qd, kd = torch.from_numpy(q).cuda(), torch.from_numpy(ks).cuda()
     ids, d, st = ix.search(qd, k=kd, k_max=50, use_filters=False, schedule=(1, 0), with_stats=True)
     _say(f"search stats {st}")
+    assert st["path"] == 0
     assert st["fallback_items"] <= 0.02 * st["leaves_scanned"] + 1
+    # seeded filters on every leaf: with infinite offsets they never prune and
+    # the results are the exact ones; finite offsets prune
+    N = len(sizes)
+    wts = W.mlp_weights(N, wl["m"], 32, seed=4101, out_bias=8.0)
+    ix.set_filters(np.arange(N, dtype=np.int32), torch.from_numpy(wts).cuda(), 32)
+    ix.set_offsets([1, 10, 50], [0.99], np.full((3, N), np.inf, dtype=np.float32))
+    i2, d2, st2 = ix.search(qd, k=kd, target=0.99, k_max=50, use_filters=True, schedule=(1, 0), with_stats=True)
+    assert st2["leaves_filter_pruned"] == 0 and st2["filter_evals"] > 0
+    assert torch.equal(i2, ids) and torch.equal(d2, d)
+    ix.set_offsets([1, 10, 50], [0.99], np.zeros((3, N), dtype=np.float32))
+    i3, d3, st3 = ix.search(qd, k=kd, target=0.99, k_max=50, use_filters=True, schedule=(1, 0), with_stats=True)
+    _say(f"filtered search stats {st3}")
+    assert st3["leaves_filter_pruned"] > 0
     ids, d = ids.cpu().numpy(), d.cpu().numpy().astype(np.float64)
+    d3 = d3.cpu().numpy().astype(np.float64)
+    kk = ks[:, None] > np.arange(50)
+    assert np.all(d3[kk] >= d[kk] * (1 - 1e-6))  # a filtered search can only miss neighbours
     xs = O.znorm(raw)
     del raw
     rows = np.random.default_rng(12).choice(len(q), 24, replace=False)
