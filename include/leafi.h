@@ -378,10 +378,9 @@ typedef struct {
 /*
  * Time the sample batch (queries_dev [nq, m], k_dev, target_dev and opts as
  * for leafi_search_knn, BF16 scan) once per candidate tile shape -- rows per
- * tile in {512, 1024, 2048} and, when at most 32 candidates are kept per
- * (query, leaf), 16 or 32 queries per tile -- `repeats` times each after one
- * warm-up, and keep the shape with the smallest median for all later searches
- * of this index.  Results of every search are identical under every shape.
+ * tile in {512, 1024, 2048} times 16, 32, 48 or 64 queries per tile --
+ * `repeats` times each after one warm-up, and keep the shape with the
+ * smallest median for all later searches of this index.  Results of every search are identical under every shape.
  * The stream is synchronised.  `report` (host) may be NULL.
  */
 int leafi_autotune(leafi_index *index, const float *queries_dev, int64_t nq, const int32_t *k_dev,
@@ -389,9 +388,9 @@ int leafi_autotune(leafi_index *index, const float *queries_dev, int64_t nq, con
                    leafi_tune_report *report, void *stream);
 
 /* Set the BF16 scan's tile shape directly (what leafi_autotune chooses):
- * chunk_rows in {128, 256, ..., 4096}; queries_per_tile 16 or 32 (used when
- * at most 32 candidates are kept per (query, leaf), else 16).  The default is
- * 1024 rows and 32 queries.  Results do not depend on the shape. */
+ * chunk_rows in {128, 256, ..., 4096}; queries_per_tile 16, 32, 48 or 64.
+ * The default is 1024 rows and 32 queries.  Results do not depend on the
+ * shape. */
 int leafi_set_tiling(leafi_index *index, int32_t chunk_rows, int32_t queries_per_tile);
 
 /* ------------------------------------------------------------------------

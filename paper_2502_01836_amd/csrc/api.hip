@@ -307,8 +307,8 @@ int pick_chunk(const leafi_index *ix, int kprime, int pref) {
 int pass_chunk(const leafi_index *ix, bool bf16, int kprime) {
   return pick_chunk(ix, kprime, bf16 ? ix->tune_chunk : kFp32ChunkRows);
 }
-void pass_geometry(const leafi_index *ix, bool bf16, int kprime, int *mq, int *cap) {
-  scan_geometry(kprime, mq, cap, bf16 ? ix->tune_mq : 32);
+void pass_geometry(const leafi_index *ix, bool bf16, int kprime, int *mq, int *cap, bool one_leaf) {
+  scan_geometry(bf16, kprime, bf16 ? (one_leaf ? 16 : ix->tune_mq) : 32, ix->m, mq, cap);
 }
 
 int64_t tiles_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, int mq, int chunk) {
@@ -332,7 +332,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   RoundOpts def;
   if (!ro) ro = &def;
   int mq, cap;
-  pass_geometry(ix, bf16, kprime, &mq, &cap);
+  pass_geometry(ix, bf16, kprime, &mq, &cap, ro->one_leaf);
   (void)cap;
   const int chunk = pass_chunk(ix, bf16, kprime);
   RoundBufs b0 = views(w);
@@ -527,6 +527,7 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
     const int want = p.schedule[std::min<size_t>(r, p.schedule.size() - 1)];
     launch_round_worklist(ix, nq, want, use_f && filters_ready, st, deferred > 0);
     const int64_t bound = nq * static_cast<int64_t>(want == 0 ? N : std::min(want, N)) + deferred;
+    ro.one_leaf = r == 0 && want == 1;
     int64_t items = scan_round(ix, nq, p.bf16, p.kprime, p.kmax, st, stats ? &tm : nullptr, bound, &ro);
     if (items == 0) break;
     launch_query_merge(nq, N, p.kmax, true, r > 0, views(w), st);
@@ -606,7 +607,7 @@ void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_
     for (bool bf : {true, false}) {
       const int kp = bf ? p.kprime : kprime_fb;
       int mq, cap;
-      pass_geometry(ix, bf, kp, &mq, &cap);
+      pass_geometry(ix, bf, kp, &mq, &cap, bf && r == 0 && p.schedule[0] == 1);
       const int chunk = pass_chunk(ix, bf, kp);
       cand = std::max(cand, static_cast<size_t>(std::max<int64_t>(tiles_bound(ix, nq, bnd, mq, chunk), 1)) * mq * kp);
     }
@@ -649,6 +650,7 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     RoundOpts ro;
     ro.may_read = false;
     ro.first_leaf = first_leaf;
+    ro.one_leaf = r == 0 && p.schedule[0] == 1;
     ro.use_tau = true;
     ro.kp_query = p.kp_query;
     ro.row_bytes = scan_row_bytes(ix, true);
@@ -1576,7 +1578,9 @@ int leafi_set_tiling(leafi_index *ix, int32_t chunk_rows, int32_t queries_per_ti
     bool ok = false;
     for (int j = 0; j < kChunkSizes; ++j) ok = ok || chunk_rows == (kRowAlign << j);
     LEAFI_CHECK_ARG(ok, "chunk_rows must be 128 << j, j = 0 .. 5");
-    LEAFI_CHECK_ARG(queries_per_tile == 16 || queries_per_tile == 32, "queries_per_tile must be 16 or 32");
+    LEAFI_CHECK_ARG(queries_per_tile == 16 || queries_per_tile == 32 || queries_per_tile == 48 ||
+                        queries_per_tile == 64,
+                    "queries_per_tile must be 16, 32, 48 or 64");
     ix->tune_chunk = chunk_rows;
     ix->tune_mq = queries_per_tile;
   });
@@ -1596,11 +1600,9 @@ int leafi_autotune(leafi_index *ix, const float *queries, int64_t nq, const int3
     hipStream_t st = as_stream(stream);
     DevBuf<int64_t> ids(static_cast<size_t>(nq) * p.kmax);
     DevBuf<float> dists(static_cast<size_t>(nq) * p.kmax);
-    const bool small = p.kprime <= 32;  // candidate lists of at most 32 keys
     std::vector<std::pair<int, int>> cand;  // (chunk rows, queries per tile)
     for (int chunk : {512, 1024, 2048})
-      for (int mq : {32, 16})
-        if (small || mq == 16) cand.emplace_back(chunk, mq);
+      for (int mq : {16, 32, 48, 64}) cand.emplace_back(chunk, mq);
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
     HIP_OK(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));

@@ -90,6 +90,30 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+// Minimum of a 32-bit key over the wavefront, returned to every lane (the
+// same DPP steps as wave_min_u64 on one half).
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  uint32_t t;
+#define LEAFI_DPP32(ctrl, rmask) \
+  static_cast<uint32_t>(__builtin_amdgcn_update_dpp(static_cast<int>(v), static_cast<int>(v), ctrl, rmask, 0xf, false))
+  t = LEAFI_DPP32(0x111, 0xf);  // row_shr:1
+  v = t < v ? t : v;
+  t = LEAFI_DPP32(0x112, 0xf);  // row_shr:2
+  v = t < v ? t : v;
+  t = LEAFI_DPP32(0x114, 0xf);  // row_shr:4
+  v = t < v ? t : v;
+  t = LEAFI_DPP32(0x118, 0xf);  // row_shr:8
+  v = t < v ? t : v;
+  t = LEAFI_DPP32(0x142, 0xa);  // row_bcast:15 into rows 1 and 3
+  v = t < v ? t : v;
+  t = LEAFI_DPP32(0x143, 0xc);  // row_bcast:31 into rows 2 and 3
+  v = t < v ? t : v;
+#undef LEAFI_DPP32
+  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
+}
+__device__ __forceinline__ uint64_t wave_min_key(uint64_t v) { return wave_min_u64(v); }
+__device__ __forceinline__ uint32_t wave_min_key(uint32_t v) { return wave_min_u32(v); }
+
 // Exclusive prefix sum over a work-group of NT threads (NT / 64 <= 64
 // wavefronts): wavefront scans by shuffles, then one scan of the wavefront
 // totals.  `sh` holds NT / 64 values of LDS; `total` receives the sum.  Every
@@ -175,18 +199,60 @@ __host__ __device__ __forceinline__ int pow2_at_least(int n) {
   return p;
 }
 
-// Bitonic sort of P (power of two) 64-bit keys in LDS by one wavefront, ascending.
-__device__ inline void wave_sort_u64(uint64_t *a, int P, int lane) {
+// Bitonic sort of P (power of two) 32- or 64-bit keys in LDS by one
+// wavefront, ascending.
+template <typename K>
+__device__ inline void wave_sort_keys(K *a, int P, int lane) {
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = lane; i < (P >> 1); i += kWave) {
         int lo = 2 * i - (i & (stride - 1));
         int hi = lo + stride;
         bool up = (lo & size) == 0;
-        uint64_t x = a[lo], y = a[hi];
+        const K x = a[lo], y = a[hi];
         if ((x > y) == up) {
           a[lo] = y;
           a[hi] = x;
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
+__device__ inline void wave_sort_u64(uint64_t *a, int P, int lane) { wave_sort_keys(a, P, lane); }
+
+// Sort of the first n keys of a (any n >= 0), ascending, by one wavefront,
+// touching no entry at or past n.  Bitonic network in the form whose every
+// comparator puts the smaller key at the lower index (each merge starts by
+// comparing i with its mirror in the block, then halves): entries past n act
+// as +infinity and such a comparator never moves them, so they are neither
+// read nor written.
+template <typename K>
+__device__ inline void wave_sort_keys_n(K *a, int n, int lane) {
+  const int P = pow2_at_least(n < 2 ? 2 : n);
+  for (int size = 2; size <= P; size <<= 1) {
+    const int half = size >> 1;
+    for (int p = lane; p < (P >> 1); p += kWave) {
+      const int blk = p / half, off = p - blk * half;
+      const int lo = blk * size + off, hi = blk * size + size - 1 - off;
+      if (hi < n) {
+        const K x = a[lo], y = a[hi];
+        if (x > y) {
+          a[lo] = y;
+          a[hi] = x;
+        }
+      }
+    }
+    wave_lds_sync();
+    for (int stride = size >> 2; stride > 0; stride >>= 1) {
+      for (int p = lane; p < (P >> 1); p += kWave) {
+        const int lo = 2 * p - (p & (stride - 1)), hi = lo + stride;
+        if (hi < n) {
+          const K x = a[lo], y = a[hi];
+          if (x > y) {
+            a[lo] = y;
+            a[hi] = x;
+          }
         }
       }
       wave_lds_sync();

@@ -78,6 +78,8 @@ struct RoundOpts {
   bool first_leaf = false;      // the batch's first round of one leaf per query, emitted by the layout
                                 // itself from the visit order (no prune cascade launch; may_read false)
   bool kp_query = false;        // each query keeps item_kprime(its k) candidates (mixed-k batches)
+  bool one_leaf = false;        // at most one leaf per query (a first round of schedule 1): BF16 tiles
+                                // of 16 queries, whatever the tuned size (few queries share a leaf)
 };
 // Lay out the round's items, scan and rerank them (see api.hip).
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
@@ -87,6 +89,8 @@ void add_scan_time(leafi_index *ix, Timing *tm);
 constexpr double kPlannedLimit = 8.0 * (1 << 30);
 // Device bytes a scan pass of items_bound items needs (items and candidate lists).
 double round_bytes_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, bool bf16, int kprime, int kmax);
+// Queries per scan tile and list capacity of a pass (one_leaf: see RoundOpts).
+void pass_geometry(const leafi_index *ix, bool bf16, int kprime, int *mq, int *cap, bool one_leaf = false);
 int default_kprime(int kmax, bool bf16);
 
 // How a batch search runs (from leafi_search_opts).

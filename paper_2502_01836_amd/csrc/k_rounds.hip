@@ -496,16 +496,161 @@ __device__ inline int merge_pass(int64_t q, int N, int kmax, int k, const RoundB
   return out;
 }
 
+// The same pass with the pass's lists staged in LDS first: every entry of
+// the (at most 64 kMergeSlots) lists, each cut to k, is loaded at once (all
+// loads in flight together, not one dependent load per round), so the
+// tournament's rounds read LDS only.  Returns -1, having changed nothing,
+// when the lists hold more than kMergeStage entries in all (the caller then
+// runs merge_pass).  stage_v / stage_t hold kMergeStage entries, soff and
+// sidx 64 kMergeSlots + 1 ints.
+constexpr int kMergeStage = 1024;
+
+// LDS of one merge wavefront: the two kmax-entry lists (16-byte multiple),
+// the staged entries, their slot offsets and item indexes.
+__host__ __device__ inline size_t merge_lists_bytes(int kmax) {
+  return (2 * static_cast<size_t>(kmax) * (sizeof(double) + sizeof(uint32_t)) + 15) / 16 * 16;
+}
+__host__ __device__ inline size_t merge_slice_bytes(int kmax) {
+  const size_t stage = static_cast<size_t>(kMergeStage) * (sizeof(double) + sizeof(uint32_t)) +
+                       (2 * kWave * kMergeSlots + 1) * sizeof(int);
+  return merge_lists_bytes(kmax) + (stage + 15) / 16 * 16;
+}
+
+__device__ inline int merge_pass_staged(int64_t q, int N, int kmax, int k, const RoundBufs &b, int it0, int nb,
+                                        const double *in_v, const uint32_t *in_t, int n_in, double *out_v,
+                                        uint32_t *out_t, int lane, double *stage_v, uint32_t *stage_t, int *soff,
+                                        int *sidx) {
+  constexpr double kInf = __builtin_inf();
+  constexpr int kSlots = kWave * kMergeSlots;
+  int cnt[kMergeSlots], off[kMergeSlots];
+  int total = 0;
+#pragma unroll
+  for (int i = 0; i < kMergeSlots; ++i) {
+    const int j = lane + kWave * i;
+    int idx = 0, c = 0;
+    if (j < nb) {
+      idx = b.qitem_idx[q * N + it0 + j];
+      c = b.item_cnt[idx];
+      c = c < k ? c : k;
+    }
+    // slot 64 i + lane starts after every slot before it
+    int x = c;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(x, o, kWave);
+      if (lane >= o) x += y;
+    }
+    off[i] = total + x - c;
+    total += __shfl(x, kWave - 1, kWave);
+    cnt[i] = c;
+    sidx[j] = idx;
+  }
+  if (total > kMergeStage) {  // uniform
+    wave_lds_sync();
+    return -1;
+  }
+#pragma unroll
+  for (int i = 0; i < kMergeSlots; ++i) soff[lane + kWave * i] = off[i];
+  if (lane == 0) soff[kSlots] = total;
+  wave_lds_sync();
+  // entry e of the staged lists belongs to the last slot s with soff[s] <= e
+  // (slots with no entries share their successor's offset)
+  constexpr int kU = 4;  // entries per lane in flight together
+  for (int e0 = 0; e0 < total; e0 += kWave * kU) {
+    double v[kU];
+    uint32_t t[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + lane + kWave * u;
+      int sl = 0;
+      if (e < total) {
+        int lo = 0, hi = kSlots;  // soff[lo] <= e < soff[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (soff[mid] <= e) lo = mid;
+          else hi = mid;
+        }
+        sl = lo;
+      }
+      const int64_t at = static_cast<int64_t>(sidx[sl]) * kmax + (e < total ? e - soff[sl] : 0);
+      v[u] = b.item_d2[at];
+      t[u] = static_cast<uint32_t>(b.item_row[at]);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + lane + kWave * u;
+      if (e < total) {
+        stage_v[e] = v[u];
+        stage_t[e] = t[u];
+      }
+    }
+  }
+  wave_lds_sync();
+  double hv[kMergeSlots];
+  uint32_t ht[kMergeSlots];
+  int pos[kMergeSlots];
+#pragma unroll
+  for (int i = 0; i < kMergeSlots; ++i) {
+    pos[i] = 0;
+    hv[i] = cnt[i] > 0 ? stage_v[off[i]] : kInf;
+    ht[i] = cnt[i] > 0 ? stage_t[off[i]] : 0xffffffffu;
+  }
+  int out = 0, rp = 0;
+  while (out < k) {
+    double lv = kInf;
+    uint32_t lt = 0xffffffffu;
+#pragma unroll
+    for (int i = 0; i < kMergeSlots; ++i)
+      if (hv[i] < lv || (hv[i] == lv && ht[i] < lt)) {
+        lv = hv[i];
+        lt = ht[i];
+      }
+    const uint64_t mvb = wave_min_u64(dbl_bits(lv));
+    const uint64_t mtb = wave_min_u64(dbl_bits(lv) == mvb ? static_cast<uint64_t>(lt) : ~0ull);
+    double gv = __longlong_as_double(static_cast<long long>(mvb));
+    uint32_t gt = static_cast<uint32_t>(mtb);
+    const double rv = rp < n_in ? in_v[rp] : kInf;
+    const uint32_t rt = rp < n_in ? in_t[rp] : 0xffffffffu;
+    if (rv < gv || (rv == gv && rt < gt)) {
+      gv = rv;
+      gt = rt;
+    }
+    if (gt == 0xffffffffu) break;  // every list is exhausted
+    if (lane == 0) {
+      out_v[out] = gv;
+      out_t[out] = gt;
+    }
+    ++out;
+    if (rv == gv && rt == gt) ++rp;
+#pragma unroll
+    for (int i = 0; i < kMergeSlots; ++i) {
+      if (hv[i] == gv && ht[i] == gt) {
+        ++pos[i];
+        const bool more = pos[i] < cnt[i];
+        hv[i] = more ? stage_v[off[i] + pos[i]] : kInf;
+        ht[i] = more ? stage_t[off[i] + pos[i]] : 0xffffffffu;
+      }
+    }
+  }
+  wave_lds_sync();
+  return out;
+}
+
 __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax, int check_cert,
                                                      RoundBufs b, const int64_t *__restrict__ rowid,
                                                      int64_t *out_ids, float *out_d, FilterPairArgs fp) {
   extern __shared__ unsigned char smem_raw[];
   // four wavefronts per work-group, each with its own LDS slice and query:
-  // two lists of kmax entries (the tournament's input and output)
+  // two lists of kmax entries (the tournament's input and output), then the
+  // staging area of merge_pass_staged
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  unsigned char *mine = smem_raw + static_cast<size_t>(wave) * 2 * kmax * (sizeof(double) + sizeof(uint32_t));
+  unsigned char *mine = smem_raw + static_cast<size_t>(wave) * merge_slice_bytes(kmax);
   double *buf_v = reinterpret_cast<double *>(mine);
   uint32_t *buf_t = reinterpret_cast<uint32_t *>(mine + sizeof(double) * 2 * kmax);
+  double *stage_v = reinterpret_cast<double *>(mine + merge_lists_bytes(kmax));
+  uint32_t *stage_t = reinterpret_cast<uint32_t *>(stage_v + kMergeStage);
+  int *soff = reinterpret_cast<int *>(stage_t + kMergeStage);
+  int *sidx = soff + kWave * kMergeSlots + 1;
   const uint64_t lt = (1ull << lane) - 1ull;
   __shared__ int active_sh[4], fb_sh[4], fe_sh[4];
   int active = 0, n_fb = 0, n_fe = 0;  // n_fe: this lane's queued filter pairs
@@ -557,7 +702,9 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
       int n_in = have < k ? have : k;
       for (int it0 = 0; it0 < n_it; it0 += kWave * kMergeSlots) {
         const int nb = n_it - it0 < kWave * kMergeSlots ? n_it - it0 : kWave * kMergeSlots;
-        n_in = merge_pass(q, N, kmax, k, b, it0, nb, vals, tags, n_in, ov, ot, lane);
+        const int got =
+            merge_pass_staged(q, N, kmax, k, b, it0, nb, vals, tags, n_in, ov, ot, lane, stage_v, stage_t, soff, sidx);
+        n_in = got >= 0 ? got : merge_pass(q, N, kmax, k, b, it0, nb, vals, tags, n_in, ov, ot, lane);
         double *sv = vals;
         vals = ov;
         ov = sv;
@@ -839,8 +986,8 @@ void launch_scatter(int64_t nq, int N, RoundBufs b, hipStream_t st) {
 
 void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedupe, RoundBufs b, hipStream_t st,
                         const int64_t *rowid, int64_t *ids, float *dists, const FilterPairArgs &fp) {
-  // LDS slice per wavefront: two lists of kmax entries
-  size_t lds = 4 * 2 * static_cast<size_t>(kmax) * (sizeof(double) + sizeof(uint32_t));
+  // LDS slice per wavefront: two lists of kmax entries and the staging area
+  size_t lds = 4 * merge_slice_bytes(kmax);
   int64_t blocks = ceil_div(nq, 4);
   int grid = static_cast<int>(blocks < 65536 ? blocks : 65536);
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_merge),

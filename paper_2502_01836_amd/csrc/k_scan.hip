@@ -19,8 +19,16 @@
 // key below the threshold is appended with an LDS atomic; when a list could
 // overflow in the next 64 rows it is sorted (bitonic, one wavefront) and cut
 // to kprime, which also tightens the threshold.
+//
+// The BF16 form keeps 32-bit keys in LDS: the squared distance's float bits
+// with the lowest kDropBits cut off (rounded down, so the value a key stands
+// for is a lower bound of the computed distance), then the row's index within
+// the tile.  Half the LDS of full keys, so twice the queries share one pass
+// over a tile's rows.  The tile's lists are written out as full 64-bit keys
+// (truncated distance, global row); within a tile both orders agree.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -33,6 +41,39 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// 32-bit scan keys (BF16 form): row index within the tile in the low
+// kLocalBits bits (tiles of at most 4096 rows), above it the float bits of
+// the squared distance without its sign bit and its kDropBits lowest bits.
+constexpr int kLocalBits = 12;
+constexpr int kDropBits = kLocalBits - 1;
+constexpr uint32_t kKey32Max = ~0u;
+
+__device__ __forceinline__ uint32_t make_key32(float d2, uint32_t local) {
+  return ((f2u(d2) >> kDropBits) << kLocalBits) | local;
+}
+
+// The smallest 32-bit threshold such that every key at or above it stands
+// for a squared distance >= T (T >= 0 finite): T's truncated bits, plus one
+// step when the truncation dropped anything.
+__device__ __forceinline__ uint32_t key32_ceil(float T) {
+  const uint32_t u = f2u(T);
+  uint32_t h = u >> kDropBits;
+  if ((h << kDropBits) != u) ++h;
+  return h << kLocalBits;
+}
+
+// A tile's LDS key as a candidate key: (truncated squared distance, global row).
+__device__ __forceinline__ uint64_t cand_key(uint32_t k, int64_t r0) {
+  if (k == kKey32Max) return kKeyMax;
+  const float d = u2f((k >> kLocalBits) << kDropBits);
+  return make_key(d, static_cast<uint32_t>(r0 + (k & ((1u << kLocalBits) - 1))));
+}
+__device__ __forceinline__ uint64_t cand_key(uint64_t k, int64_t) { return k; }
+
+// The empty key of either width: all bits set.
+template <typename K>
+constexpr K key_max() { return static_cast<K>(~static_cast<K>(0)); }
 
 struct TileInfo {
   int L, g, c, C;
@@ -136,30 +177,32 @@ constexpr int kListSelectMax = 16;
 // refresh the threshold.  Few wanted (kprime <= kListSelectMax): kprime
 // rounds of a wavefront minimum over the keys above the previous round's
 // (the keys of one list are distinct: one per row); otherwise a bitonic sort.
-__device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int j, int cap, int kprime, int lane) {
-  uint64_t *lst = keys + static_cast<int64_t>(j) * (cap + 1);
+template <typename K>
+__device__ inline void compact_list(K *keys, int *cnt, K *thr, int j, int cap, int kprime, int lane) {
+  constexpr K kMax = key_max<K>();
+  K *lst = keys + static_cast<int64_t>(j) * (cap + 1);
   int c = cnt[j];
   if (kprime <= kListSelectMax) {
-    uint64_t prev = 0, mine = kKeyMax;  // lane r keeps the r-th smallest
+    K prev = 0, mine = kMax;  // lane r keeps the r-th smallest
     int keep = 0;
     // a list of up to 128 keys is read into registers once (two per lane)
     // instead of once per round
     const bool regs = c <= 2 * kWave;
-    const uint64_t v0 = regs && lane < c ? lst[lane] : kKeyMax;
-    const uint64_t v1 = regs && lane + kWave < c ? lst[lane + kWave] : kKeyMax;
+    const K v0 = regs && lane < c ? lst[lane] : kMax;
+    const K v1 = regs && lane + kWave < c ? lst[lane + kWave] : kMax;
     for (int r = 0; r < kprime; ++r) {
-      uint64_t lo = kKeyMax;
+      K lo = kMax;
       if (regs) {
         if ((r == 0 || v0 > prev) && v0 < lo) lo = v0;
         if ((r == 0 || v1 > prev) && v1 < lo) lo = v1;
       } else {
         for (int e = lane; e < c; e += kWave) {
-          const uint64_t v = lst[e];
+          const K v = lst[e];
           if ((r == 0 || v > prev) && v < lo) lo = v;
         }
       }
-      lo = wave_min_u64(lo);
-      if (lo == kKeyMax) break;  // fewer than kprime keys (uniform)
+      lo = wave_min_key(lo);
+      if (lo == kMax) break;  // fewer than kprime keys (uniform)
       if (lane == r) mine = lo;
       prev = lo;
       ++keep;
@@ -173,10 +216,7 @@ __device__ inline void compact_list(uint64_t *keys, int *cnt, uint64_t *thr, int
     wave_lds_sync();
     return;
   }
-  int P = pow2_at_least(c < 2 ? 2 : c);
-  for (int i = c + lane; i < P; i += kWave) lst[i] = kKeyMax;
-  wave_lds_sync();
-  wave_sort_u64(lst, P, lane);
+  wave_sort_keys_n(lst, c, lane);  // in place: the list's capacity need not be a power of two
   int keep = c < kprime ? c : kprime;
   if (lane == 0) {
     cnt[j] = keep;
@@ -193,21 +233,20 @@ __device__ inline void append_key(uint64_t *keys, int *cnt, const uint64_t *thr,
 }
 
 // The tile's lists to its candidate slots: list j keeps its kpl[j] best keys
-// (kpl[j] <= kprime), the rest of its kprime slots are empty.
-__device__ inline void finish_tile(uint64_t *keys, int *cnt, uint64_t *thr, const int *kpl, int t, int mq, int nqt,
-                                   int cap, int kprime, int wave, int nwaves, int lane, uint64_t *cand) {
-  for (int j = wave; j < mq; j += nwaves) {
+// (kpl[j] <= kprime), the rest of its kprime slots are empty.  Slots of lists
+// past the tile's queries (j >= nqt) belong to no item and are never read:
+// they are not written.
+template <typename K>
+__device__ inline void finish_tile(K *keys, int *cnt, K *thr, const int *kpl, int t, int mq, int nqt, int cap,
+                                   int kprime, int64_t r0, int wave, int nwaves, int lane, uint64_t *cand) {
+  for (int j = wave; j < nqt; j += nwaves) {
     uint64_t *out = cand + (static_cast<int64_t>(t) * mq + j) * kprime;
-    if (j < nqt) {
-      compact_list(keys, cnt, thr, j, cap, kpl[j], lane);
-      // only the first cnt[j] entries are candidates; the list may hold fewer
-      // than kprime (a chunk with few real rows) and LDS beyond them is stale
-      const uint64_t *lst = keys + static_cast<int64_t>(j) * (cap + 1);
-      const int keep = cnt[j];
-      for (int i = lane; i < kprime; i += kWave) out[i] = i < keep ? lst[i] : kKeyMax;
-    } else {
-      for (int i = lane; i < kprime; i += kWave) out[i] = kKeyMax;
-    }
+    compact_list(keys, cnt, thr, j, cap, kpl[j], lane);
+    // only the first cnt[j] entries are candidates; the list may hold fewer
+    // than kprime (a chunk with few real rows) and LDS beyond them is stale
+    const K *lst = keys + static_cast<int64_t>(j) * (cap + 1);
+    const int keep = cnt[j];
+    for (int i = lane; i < kprime; i += kWave) out[i] = i < keep ? cand_key(lst[i], r0) : kKeyMax;
   }
 }
 
@@ -228,8 +267,8 @@ __device__ __forceinline__ void load_rows(const uint16_t *x16, int64_t base, int
 template <int KS, int QB>
 __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &ti, int64_t base, bf16x8 (&cur)[KS],
                                            bf16x8 (&nxt)[KS], bool more, const uint16_t *qs, int qstride,
-                                           const float (&qn)[QB], uint64_t *keys, int *cnt, uint64_t *thr, int cap,
-                                           const int *kpl, int wave, int lane) {
+                                           const float (&qn)[QB], uint32_t *keys, int *cnt, uint32_t *thr, int cap,
+                                           const int *kpl, bool check, int room, int wave, int lane) {
   constexpr int kWaves = 4;
   const int64_t rowc = base + 16 * wave + 4 * (lane >> 4);
   const float4 xn = *reinterpret_cast<const float4 *>(s.xn16 + rowc);
@@ -257,29 +296,34 @@ __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &t
     if (j < ti.nqt) {
       // the lane's (up to 4) appends take one LDS atomic: one round trip per
       // block instead of one per row
-      const uint64_t tj = thr[j];
-      uint64_t kk[4];
+      const uint32_t tj = thr[j];
+      uint32_t kk[4];
       int n = 0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = rowc + r;
         const float d2 = fmaxf(qn[qb] + xr[r] - 2.0f * acc[qb][r], 0.0f);
-        kk[r] = make_key(d2, static_cast<uint32_t>(row));
-        if (!(row < ti.real_end && kk[r] < tj)) kk[r] = kKeyMax;
-        n += kk[r] != kKeyMax;
+        kk[r] = make_key32(d2, static_cast<uint32_t>(row - ti.r0));
+        if (!(row < ti.real_end && kk[r] < tj)) kk[r] = kKey32Max;
+        n += kk[r] != kKey32Max;
       }
       if (n > 0) {
-        uint64_t *dst = keys + static_cast<int64_t>(j) * (cap + 1) + atomicAdd(cnt + j, n);
+        uint32_t *dst = keys + static_cast<int64_t>(j) * (cap + 1) + atomicAdd(cnt + j, n);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (kk[r] != kKeyMax) *dst++ = kk[r];
+          if (kk[r] != kKey32Max) *dst++ = kk[r];
       }
     }
   }
+  // Lists are checked after every block, or with room for two blocks of
+  // appends (room = 128) after every second one: between checks the
+  // wavefronts need no barrier at all.
+  if (!check) return;
   lds_barrier();
-  // lists that could overflow in the next block: every count read at once
-  // (one lane per list, MQ <= 64), then this wavefront's lists j = wave mod 4
-  uint64_t over = __ballot(lane < ti.nqt && cnt[lane < ti.nqt ? lane : 0] > cap - 64) & (0x1111111111111111ull << wave);
+  // lists that could overflow before the next check: every count read at
+  // once (one lane per list, MQ <= 64), then this wavefront's lists j = wave mod 4
+  uint64_t over = __ballot(lane < ti.nqt && cnt[lane < ti.nqt ? lane : 0] > cap - room) &
+                  (0x1111111111111111ull << wave);
   while (over) {
     const int j = __ffsll(static_cast<unsigned long long>(over)) - 1;
     over &= over - 1;
@@ -289,14 +333,15 @@ __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &t
 }
 
 template <int KS, int QB>
-__global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv, RoundBufs b, int kprime, int cap,
-                                                   uint64_t *cand) {
+__global__ void __launch_bounds__(256, QB >= 3 ? 2 : 4) k_scan_bf16(StoreView s, QueryView qv, RoundBufs b,
+                                                                   int kprime, int cap, uint64_t *cand) {
   constexpr int MQ = 16 * QB;
   static_assert(MQ <= kWave, "one lane per candidate list");
   constexpr int kWaves = 4;
   extern __shared__ uint64_t smem[];
-  uint64_t *keys = smem;
-  uint64_t *thr = keys + MQ * (cap + 1);
+  // MQ is a multiple of 16, so every array below starts 16-byte aligned
+  uint32_t *keys = reinterpret_cast<uint32_t *>(smem);
+  uint32_t *thr = keys + MQ * (cap + 1);
   int *cnt = reinterpret_cast<int *>(thr + MQ);
   int *kpl = cnt + MQ;                                     // [MQ] candidates each list keeps
   uint16_t *qs = reinterpret_cast<uint16_t *>(kpl + MQ);  // [MQ][m + 8], 16-byte aligned
@@ -322,14 +367,14 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
     if (threadIdx.x < MQ) {
       const int j = threadIdx.x;
       cnt[j] = 0;
-      uint64_t t0 = kKeyMax;
+      uint32_t t0 = kKey32Max;
       int kp = kprime;
       if (j < ti.nqt) {
         const int64_t qq = b.item_q[ti.p0 + j];
         if (b.kp_query) kp = item_kprime(1, kprime, b.kq[qq], true);
         if (b.use_tau) {
           const float T = tau_threshold(b.tau[qq], qv.qn16[qq], qv.qeps[qq], s.leaf_eps[ti.L], m);
-          if (T < __builtin_inff()) t0 = make_key(T, 0u);
+          if (T < __builtin_inff()) t0 = key32_ceil(T);
         }
       }
       thr[j] = t0;
@@ -359,12 +404,17 @@ __global__ void __launch_bounds__(256, 4) k_scan_bf16(StoreView s, QueryView qv,
     // hardware's load counter retires in order.
     // Chunks hold an even number of 64-row blocks (leaves are padded to 128
     // rows), so both halves of the unrolled body always run.
+    // a list cut back to its kpl[j] <= kprime keys has room for two blocks
+    // of appends when the capacity allows (uniform)
+    const bool pair = cap - kprime >= 128;
+    const int room = pair ? 128 : 64;
     for (int64_t base = ti.r0; base < ti.r1; base += 128) {
-      scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kpl, wave, lane);
+      scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kpl, !pair, room, wave,
+                         lane);
       scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qs, qstride, qn, keys, cnt, thr, cap, kpl,
-                         wave, lane);
+                         true, room, wave, lane);
     }
-    finish_tile(keys, cnt, thr, kpl, t, MQ, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
+    finish_tile(keys, cnt, thr, kpl, t, MQ, ti.nqt, cap, kprime, ti.r0, wave, kWaves, lane, cand);
     __syncthreads();
   }
 }
@@ -447,7 +497,7 @@ __global__ void __launch_bounds__(256) k_scan_fp32(StoreView s, QueryView qv, Ro
       }
       __syncthreads();
     }
-    finish_tile(keys, cnt, thr, kpl, t, mq, ti.nqt, cap, kprime, wave, kWaves, lane, cand);
+    finish_tile(keys, cnt, thr, kpl, t, mq, ti.nqt, cap, kprime, ti.r0, wave, kWaves, lane, cand);
     __syncthreads();
   }
 }
@@ -567,14 +617,21 @@ __device__ inline int bound_pass(int64_t q, int N, int k, int kprime, int mq, in
   return o;
 }
 
+// One work-group per query: its four wavefronts take every fourth pass of
+// 64 x kBoundSlots lists each and keep their k smallest keys; wavefront 0
+// then merges the four sorted results (a key held by two of them is one row,
+// counted once) up to the k-th.
 __global__ void __launch_bounds__(256) k_query_bound(StoreView s, QueryView qv, RoundBufs b, int64_t nq, int mq,
                                                      int kprime, int kmax, int cmax, float eps_max,
                                                      const uint64_t *__restrict__ cand, float *qbound) {
   extern __shared__ uint64_t bsm[];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   uint64_t *buf0 = bsm + static_cast<size_t>(wave) * 2 * kmax, *buf1 = buf0 + kmax;
+  int *s_n = reinterpret_cast<int *>(bsm + 8 * static_cast<size_t>(kmax));  // [4] result sizes
+  int *s_res = s_n + 4;                                                     // [4] result offsets
   const int N = s.N, m = s.m;
-  for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
+  constexpr int kPass = kWave * kBoundSlots;
+  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
     const int n_it = b.qitem_cnt[q];
     const int k = b.kq[q];
     float U = b.tau[q];
@@ -582,22 +639,50 @@ __global__ void __launch_bounds__(256) k_query_bound(StoreView s, QueryView qv, 
       const int nlists = n_it * cmax;
       uint64_t *in = buf0, *out = buf1;
       int n_in = 0;
-      for (int l0 = 0; l0 < nlists; l0 += kWave * kBoundSlots) {
-        const int nl = nlists - l0 < kWave * kBoundSlots ? nlists - l0 : kWave * kBoundSlots;
+      for (int l0 = wave * kPass; l0 < nlists; l0 += 4 * kPass) {
+        const int nl = nlists - l0 < kPass ? nlists - l0 : kPass;
         n_in = bound_pass(q, N, k, kprime, mq, b.chunk, cmax, b, s, cand, l0, nl, in, n_in, out, lane);
         uint64_t *t = in;
         in = out;
         out = t;
       }
-      if (n_in >= k) {
-        const double kd = static_cast<double>(key_d2(in[k - 1]));
-        const double v = sqrt(kd + bf16_delta(static_cast<double>(qv.qn16[q]), m)) + qv.qeps[q] + eps_max;
-        float u = static_cast<float>(v);
-        if (static_cast<double>(u) < v) u = nextafterf(u, __builtin_inff());
-        U = u < U ? u : U;
+      if (lane == 0) {
+        s_n[wave] = n_in;
+        s_res[wave] = static_cast<int>(in - bsm);  // offset of this wavefront's result
+      }
+      __syncthreads();
+      if (wave == 0) {
+        // lanes 0..3 walk the four sorted results
+        const int w = lane < 4 ? lane : 0;
+        const uint64_t *res = bsm + s_res[w];
+        const int cnt = lane < 4 ? s_n[w] : 0;
+        int pos = 0;
+        uint64_t hd = cnt > 0 ? res[0] : kKeyMax;
+        uint64_t g = kKeyMax;
+        int o = 0;
+        while (o < k) {
+          g = wave_min_u64(hd);
+          if (g == kKeyMax) break;  // fewer than k keys in all
+          ++o;
+          if (hd == g) {
+            ++pos;
+            hd = pos < cnt ? res[pos] : kKeyMax;
+          }
+        }
+        if (o == k) {
+          // the key's distance was rounded down to its truncation step: the
+          // computed value is at most the step's largest float
+          const float kt = key_d2(g);
+          const double kd = static_cast<double>(kt < __builtin_inff() ? u2f(f2u(kt) | ((1u << kDropBits) - 1)) : kt);
+          const double v = sqrt(kd + bf16_delta(static_cast<double>(qv.qn16[q]), m)) + qv.qeps[q] + eps_max;
+          float u = static_cast<float>(v);
+          if (static_cast<double>(u) < v) u = nextafterf(u, __builtin_inff());
+          U = u < U ? u : U;
+        }
       }
     }
-    if (lane == 0) qbound[q] = U;
+    if (threadIdx.x == 0) qbound[q] = U;
+    __syncthreads();  // LDS is reused by the next query
   }
 }
 
@@ -914,12 +999,20 @@ int resident_grid(K kern, size_t lds, int want) {
   return g >= kXcds ? g / kXcds * kXcds : g;  // a multiple of the XCD count (see xcd_tile)
 }
 
+constexpr int kLdsPerCu = 160 * 1024;
+
+// LDS of a BF16 scan work-group: 32-bit lists, thresholds, counts, per-list
+// candidate counts, the queries (row stride m + 8), two ints.
+size_t scan_bf16_lds(int mq, int cap, int m) {
+  return static_cast<size_t>(mq) * (cap + 1) * 4 + static_cast<size_t>(mq) * 4 * 3 +
+         static_cast<size_t>(mq) * (m + 8) * 2 + 16;
+}
+
 template <int KS, int QB>
 void scan_bf16_inst(StoreView s, QueryView q, RoundBufs b, int kprime, int cap, uint64_t *cand, int grid,
                     hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int MQ = 16 * QB;
-  size_t lds = static_cast<size_t>(MQ) * (cap + 1) * 8 + MQ * 8 + MQ * 4 * 2 +
-               static_cast<size_t>(MQ) * (32 * KS + 8) * 2 + 16;
+  const size_t lds = scan_bf16_lds(MQ, cap, 32 * KS);
   auto kern = k_scan_bf16<KS, QB>;
   if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -961,11 +1054,34 @@ void scan_fp32_inst(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, i
 
 }  // namespace
 
-// Candidate-list geometry for a given kprime: (queries per tile, list capacity).
-void scan_geometry(int kprime, int *mq, int *cap, int mq_small) {
+// Candidate-list geometry for a given kprime: (queries per tile, list
+// capacity).  A list is cut back to its kprime best whenever the next 64 (or
+// 128) rows could overflow it, so the capacity is at least kprime + 64.
+// BF16 (32-bit keys): above that, as large as the LDS allows at the
+// work-groups per CU a tile of mq queries is meant to run with (4, 3 and 2
+// for 16, 32 and 48 queries, fewer when even the minimum does not fit), up
+// to 3 kprime + 64 (128 for kprime <= 16, whose lists are cut by
+// selection): fewer cuts where many rows enter the lists (a first round,
+// with no tau yet).  FP32: 64-bit keys, power-of-two capacities.
+void scan_geometry(bool bf16, int kprime, int mq_pref, int m, int *mq, int *cap) {
+  if (bf16) {
+    const int q = (mq_pref == 16 || mq_pref == 32 || mq_pref == 48 || mq_pref == 64) ? mq_pref : 32;
+    const int kp = std::max(kprime, 4);
+    const int lo = (kp + 15) / 16 * 16 + 64;
+    const int hi = kp <= kListSelectMax ? 128 : (3 * kp + 15) / 16 * 16 + 64;
+    const int want = q <= 16 ? 4 : q <= 32 ? 3 : 2;
+    int fit = 0;
+    for (int wgs = want; wgs >= 1; --wgs) {
+      const int64_t room = static_cast<int64_t>(kLdsPerCu) / wgs - static_cast<int64_t>(scan_bf16_lds(q, 0, m)) + 4 * q;
+      fit = static_cast<int>(room / (4 * q)) - 1;
+      if (fit >= lo) break;
+    }
+    *mq = q;
+    *cap = std::max(lo, std::min(hi, fit));
+    return;
+  }
   int kc = pow2_at_least(kprime < 4 ? 4 : kprime);
-  if (kc <= 32) { *mq = mq_small == 16 ? 16 : 32; *cap = 128; }
-  else if (kc <= 64) { *mq = 16; *cap = 256; }
+  if (kc <= 32) { *mq = mq_pref == 16 ? 16 : 32; *cap = 128; }
   else if (kc <= 128) { *mq = 16; *cap = 256; }
   else { *mq = 16; *cap = 512; }
 }
@@ -973,17 +1089,22 @@ void scan_geometry(int kprime, int *mq, int *cap, int mq_small) {
 void launch_scan_bf16(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
                       hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   int mq2, cap;
-  scan_geometry(kprime, &mq2, &cap, mq);
+  scan_geometry(true, kprime, mq, s.m, &mq2, &cap);
   if (mq != mq2) fail(LEAFI_EINTERNAL, "scan_bf16: tile geometry mismatch");
+  if (b.chunk > (1 << kLocalBits)) fail(LEAFI_EINTERNAL, "scan_bf16: tiles of at most 4096 rows");
   int ks = s.m / 32;
-  if (mq == 32) scan_bf16_ks<2>(ks, s, q, b, kprime, cap, cand, grid, st, e0, e1);
-  else scan_bf16_ks<1>(ks, s, q, b, kprime, cap, cand, grid, st, e0, e1);
+  switch (mq) {
+    case 16: scan_bf16_ks<1>(ks, s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    case 32: scan_bf16_ks<2>(ks, s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    case 48: scan_bf16_ks<3>(ks, s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+    default: scan_bf16_ks<4>(ks, s, q, b, kprime, cap, cand, grid, st, e0, e1); break;
+  }
 }
 
 void launch_scan_fp32(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
                       hipStream_t st) {
   int mq2, cap;
-  scan_geometry(kprime, &mq2, &cap);
+  scan_geometry(false, kprime, 32, s.m, &mq2, &cap);
   if (mq > mq2) fail(LEAFI_EINTERNAL, "scan_fp32: tile geometry mismatch");
   switch (s.m / 16) {
     case 2: scan_fp32_inst<2>(s, q, b, mq, kprime, cap, cand, grid, st); break;
@@ -1010,8 +1131,8 @@ int rerank_lds_bytes(int max_chunks, int kprime, int *PB) {
 void launch_query_bound(StoreView s, QueryView q, RoundBufs b, int64_t nq, int mq, int kprime, int kmax, int cmax,
                         float eps_max, const uint64_t *cand, float *qbound, hipStream_t st) {
   if (nq <= 0) return;
-  const size_t lds = 4 * 2 * static_cast<size_t>(kmax) * sizeof(uint64_t);
-  const int64_t blocks = ceil_div(nq, 4);
+  const size_t lds = 4 * 2 * static_cast<size_t>(kmax) * sizeof(uint64_t) + 8 * sizeof(int);
+  const int64_t blocks = nq;  // one work-group per query
   hipLaunchKernelGGL(k_query_bound, dim3(static_cast<unsigned>(blocks < 65536 ? blocks : 65536)), dim3(256), lds, st, s,
                      q, b, nq, mq, kprime, kmax, cmax, eps_max, cand, qbound);
   LAUNCH_OK("query_bound");

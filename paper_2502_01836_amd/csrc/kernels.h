@@ -238,8 +238,9 @@ void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprim
                         const uint64_t *cand, int grid, int max_chunks, hipStream_t st, const float *qbound = nullptr);
 
 // Candidate-list geometry for kprime kept keys: queries per tile and list
-// capacity.  For kprime <= 32 the queries per tile are mq_small (16 or 32).
-void scan_geometry(int kprime, int *mq, int *cap, int mq_small = 32);
+// capacity.  BF16: mq_pref queries per tile (16, 32, 48 or 64; others mean
+// 32).  FP32: 32 queries per tile when kprime <= 32 and mq_pref != 16, else 16.
+void scan_geometry(bool bf16, int kprime, int mq_pref, int m, int *mq, int *cap);
 
 // Per query: merge the round's items into the running top-k, update tau,
 // queue uncertified items (check_cert) and count active queries.  With ids

@@ -131,32 +131,34 @@ def test_autotune_keeps_results_identical(env):
     qd = torch.from_numpy(env["q"][2]).cuda()
     before = _search(env, qd, pkg.SEARCH_NO_GRAPH)
     rep = env["ix"].autotune(qd, k=env["kd"], target=env["td"], k_max=10, schedule=(1, 0), repeats=2)
-    # k_max = 10 keeps 40 candidates per (query, leaf): only 16-query tiles
-    assert len(rep["candidates"]) == 3
+    # three tile heights times four query counts
+    assert len(rep["candidates"]) == 12
     assert {c["chunk_rows"] for c in rep["candidates"]} == {512, 1024, 2048}
+    assert {c["queries_per_tile"] for c in rep["candidates"]} == {16, 32, 48, 64}
     assert all(c["ms"] > 0 for c in rep["candidates"])
     assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"])
     after = _search(env, qd, pkg.SEARCH_NO_GRAPH)
     assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1])
     for c in ("leaves_scanned", "leaves_filter_pruned", "fallback_items"):
         assert before[2][c] == after[2][c]
-    # k = 1 (4 candidates): both tile heights are tried too
+    # k = 1 (4 candidates): the same shapes
     k1 = torch.ones(len(env["ks"]), dtype=torch.int32, device="cuda")
     ids_a, d_a = env["ix"].search(qd, k=k1, target=env["td"], k_max=1, schedule=(1, 0), flags=pkg.SEARCH_NO_GRAPH)
     rep1 = env["ix"].autotune(qd, k=k1, target=env["td"], k_max=1, schedule=(1, 0), repeats=2)
-    assert len(rep1["candidates"]) == 6
-    assert {c["queries_per_tile"] for c in rep1["candidates"]} == {16, 32}
+    assert len(rep1["candidates"]) == 12
     ids_b, d_b = env["ix"].search(qd, k=k1, target=env["td"], k_max=1, schedule=(1, 0), flags=pkg.SEARCH_NO_GRAPH)
     assert torch.equal(ids_a, ids_b) and torch.equal(d_a, d_b)
     # every shape, set directly, for the mixed-k batch
     for chunk in (128, 512, 2048, 4096):
-        for mq in (16, 32):
+        for mq in (16, 32, 48, 64):
             env["ix"].set_tiling(chunk, mq)
             got = _search(env, qd, pkg.SEARCH_NO_GRAPH)
             assert torch.equal(got[0], before[0]) and torch.equal(got[1], before[1]), (chunk, mq)
     env["ix"].set_tiling(1024, 32)
     with pytest.raises(pkg.LeafiError):
         env["ix"].set_tiling(1000, 32)
+    with pytest.raises(pkg.LeafiError):
+        env["ix"].set_tiling(1024, 24)
 
 
 def test_deferred_rescans_agree_and_stay_exact(env):
