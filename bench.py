@@ -156,6 +156,10 @@ def main():
                     help="offered request rates (per second) of the serving leg; empty = skip")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-mem-gb", type=float, default=32.0, help="serving engine's memory budget for request slots")
+    ap.add_argument("--tiling", default="",
+                    help="BF16 scan tile shape 'rows,queries' to use instead of the tuner's pick")
+    ap.add_argument("--cpu-one-core-rows", type=int, default=4_000_000,
+                    help="collection rows the one-thread oracle sample scans (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for hardware byte counters)")
     a = ap.parse_args()
@@ -232,21 +236,28 @@ def main():
     exact_qps = len(batches) * nq / (time.perf_counter() - s0)
     log(f"exact search (filters off): {exact_qps:.0f} queries/s")
 
-    # scan tile shape: the library's tuner on each batch, smallest summed time kept
+    # scan tile shape: the library's tuner on each batch, smallest summed time
+    # kept (or the shape given on the command line)
     t0 = time.time()
-    tot = {}
-    for q, k_, t_ in zip(batches, kd, td):
-        rep_t = ix.autotune(q, k=k_, target=t_, k_max=k_max, use_filters=True, schedule=sched, repeats=3)
-        for c in rep_t["candidates"]:
-            key = (c["chunk_rows"], c["queries_per_tile"])
-            tot[key] = tot.get(key, 0.0) + c["ms"]
-    best = min(tot, key=tot.get)
-    ix.set_tiling(*best)
-    tune = {"candidates": [{"chunk_rows": c, "queries_per_tile": q_, "ms_sum_of_batches": v}
-                           for (c, q_), v in sorted(tot.items())],
-            "chosen": {"chunk_rows": best[0], "queries_per_tile": best[1], "ms_sum_of_batches": tot[best]}}
-    log(f"tuned scan tiles in {time.time() - t0:.1f}s: {best} of "
-        f"{[(c, q_, round(v, 3)) for (c, q_), v in sorted(tot.items())]}")
+    if a.tiling:
+        best = tuple(int(v) for v in a.tiling.split(","))
+        ix.set_tiling(*best)
+        tune = {"candidates": [], "chosen": {"chunk_rows": best[0], "queries_per_tile": best[1]}, "given": True}
+        log(f"scan tiles set to {best}")
+    else:
+        tot = {}
+        for q, k_, t_ in zip(batches, kd, td):
+            rep_t = ix.autotune(q, k=k_, target=t_, k_max=k_max, use_filters=True, schedule=sched, repeats=3)
+            for c in rep_t["candidates"]:
+                key = (c["chunk_rows"], c["queries_per_tile"])
+                tot[key] = tot.get(key, 0.0) + c["ms"]
+        best = min(tot, key=tot.get)
+        ix.set_tiling(*best)
+        tune = {"candidates": [{"chunk_rows": c, "queries_per_tile": q_, "ms_sum_of_batches": v}
+                               for (c, q_), v in sorted(tot.items())],
+                "chosen": {"chunk_rows": best[0], "queries_per_tile": best[1], "ms_sum_of_batches": tot[best]}}
+        log(f"tuned scan tiles in {time.time() - t0:.1f}s: {best} of "
+            f"{[(c, q_, round(v, 3)) for (c, q_), v in sorted(tot.items())]}")
 
     # bound searches (arguments marshalled once); the timed steps use the
     # library's default execution (a repeated plannable batch shape replays a
@@ -384,6 +395,31 @@ def main():
                          f"(z-normalised chunk by chunk)",
                "cpu_model": cpu_model(), "nproc": os.cpu_count()}
         log(f"CPU oracle: {cpu['value']:.2f} queries/s on {cpu['cores']} threads ({dt:.1f}s)")
+        if a.cpu_one_core_rows > 0:
+            # the same oracle on one thread, over the collection's first rows;
+            # its time scales linearly with the rows scanned, so the rate over
+            # the whole collection is the sample's rate times rows / n
+            rows = min(a.cpu_one_core_rows, n)
+            n1 = min(4, a.cpu_sample)
+            threads = O.num_threads()
+            O.set_num_threads(1)
+            try:
+                gen1 = [0.0]
+
+                def first_rows(gt):
+                    for lo, h in host_chunks(gt):
+                        if lo >= rows:
+                            break
+                        yield lo, h[:rows - lo]
+                s1 = time.perf_counter()
+                O.knn_stream(first_rows(gen1), O.znorm(pool[rs[:n1]]), k_max)
+                dt1 = time.perf_counter() - s1 - gen1[0]
+            finally:
+                O.set_num_threads(threads)
+            cpu["one_core"] = {"value": n1 / dt1 * rows / n, "unit": "queries/s", "cores": 1,
+                               "sample": f"{n1} of those queries over the first {rows} series ({dt1:.1f} s), "
+                                         f"rate scaled by {rows}/{n} to the whole collection"}
+            log(f"CPU oracle on one thread: {cpu['one_core']['value']:.3f} queries/s ({dt1:.1f}s for {rows} rows)")
         g_ids = np.concatenate([g[0] for g in got])[rs]
         g_d = np.concatenate([g[1] for g in got])[rs]
         rec_oracle = {"batched": {}, "served": {}}

@@ -8,4 +8,4 @@ marked "parity unpinned" in their docstring (none at present: the trained
 filter weights are not an oracle output).
 """
 from .core import *  # noqa: F401,F403
-from .core import build_bruteforce, num_threads  # noqa: F401
+from .core import build_bruteforce, num_threads, set_num_threads  # noqa: F401

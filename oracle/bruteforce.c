@@ -212,3 +212,12 @@ int or_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the parallel loops above from now on (n >= 1). */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}

@@ -49,6 +49,7 @@ def _lib():
         lib.or_knn.argtypes = [P, I64, I32, P, I64, I32, P, P]
         lib.or_leaf_knn.argtypes = [P, P, P, I32, I32, P, I64, I32, P, P]
         lib.or_num_threads.restype = ctypes.c_int
+        lib.or_set_num_threads.argtypes = [ctypes.c_int]
         _bf = lib
     return _bf
 
@@ -59,6 +60,11 @@ def _ptr(a: np.ndarray):
 
 def num_threads() -> int:
     return int(_lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Host threads of the C brute force's parallel loops from now on."""
+    _lib().or_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------
