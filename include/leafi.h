@@ -305,7 +305,10 @@ typedef struct {
   int32_t rounds;           /* regular rounds that scanned at least one leaf */
   int32_t path;             /* how the batch ran: 0 host-driven rounds (counts read back
                                every round), 1 planned launch sequence, 2 replay of a
-                               captured graph, 3 captured in this call and replayed */
+                               captured graph, 3 captured in this call and replayed,
+                               4 a planned sequence (or replay) one of whose rounds held more
+                               items than its buffers' capacity, then run again with
+                               host-driven rounds (the counts given are that run's) */
   double ms_total;
   double ms_scan;           /* time in the BF16 leaf-scan kernels (HIP events on the stream) */
   double scan_bytes;        /* unique leaf-store bytes the scan kernels had to read */
@@ -322,13 +325,22 @@ typedef struct {
  *
  * Execution: with the BF16 scan and a schedule that contains a 0 (so every
  * query ends within that many rounds), the batch runs as a fixed launch
- * sequence that reads nothing back (buffers sized from the per-round upper
- * bound nq * min(R, n_leaves) plus the previous round's rescans, at most
- * nq * n_leaves, if that fits 8 GiB).  The second call with the
- * same shape, options and buffer addresses captures that sequence in a HIP
- * graph, and later identical calls replay it (the graph reads the current
- * contents of the caller's buffers).  Other cases run host-driven rounds.
- * Results are identical on every path.
+ * sequence (a planned batch).  Each pass's item buffers are sized from its
+ * upper bound nq * min(R, n_leaves) plus the previous round's rescans (at
+ * most nq * n_leaves) when the bound-sized buffers fit 16 GiB, else from the
+ * largest item count that fits (or the capacity set by
+ * leafi_set_plan_capacity, if smaller).  A batch whose passes all fit their
+ * bounds reads nothing back.  Otherwise each round's layout compares its
+ * item count with the capacity on the device; a round with more items lays
+ * out nothing and raises an overflow word, which the call reads back (one
+ * synchronisation of the stream) before returning; after an overflow the
+ * batch runs again with host-driven rounds (stats->path 4), and later calls
+ * of the same shape, options and buffers run host-driven rounds at once
+ * (path 0).  The second call
+ * with the same shape, options and buffer addresses captures the sequence in
+ * a HIP graph, and later identical calls replay it (the graph reads the
+ * current contents of the caller's buffers).  Other cases run host-driven
+ * rounds.  Results are identical on every path.
  */
 int leafi_search_knn(leafi_index *index, const float *queries_dev, int64_t nq, const int32_t *k_dev,
                      const float *target_dev, const leafi_search_opts *opts, int64_t *ids_dev,
@@ -392,6 +404,13 @@ int leafi_autotune(leafi_index *index, const float *queries_dev, int64_t nq, con
  * The default is 1024 rows and 32 queries.  Results do not depend on the
  * shape. */
 int leafi_set_tiling(leafi_index *index, int32_t chunk_rows, int32_t queries_per_tile);
+
+/* Item capacity of a planned batch's passes (see leafi_search_knn): at most
+ * max_items (query, leaf) items per pass, which bounds the planned batch's
+ * device buffers; 0 (the default) means as many as 16 GiB of buffers hold.
+ * A batch whose round exceeds it still returns exact results (it runs again
+ * with host-driven rounds).  Does not change any result. */
+int leafi_set_plan_capacity(leafi_index *index, int64_t max_items);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of k-NN requests (Algorithm 2 for a stream of

@@ -353,6 +353,10 @@ class Index:
     def set_tiling(self, chunk_rows: int = 1024, queries_per_tile: int = 32):
         check(load().leafi_set_tiling(self._h, chunk_rows, queries_per_tile))
 
+    def set_plan_capacity(self, max_items: int = 0):
+        """Item capacity of a planned batch's passes (0 = what 16 GiB of buffers hold)."""
+        check(load().leafi_set_plan_capacity(self._h, int(max_items)))
+
     def lower_bounds(self, queries):
         torch = _torch()
         nq = queries.shape[0]

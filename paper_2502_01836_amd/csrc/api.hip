@@ -172,6 +172,7 @@ RoundBufs views(Workspace &w) {
   b.kp_query = 0;
   b.ctl = w.ctl.get();
   b.leaf_n = w.leaf_n;
+  b.cap_items = 0;
   return b;
 }
 
@@ -339,6 +340,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   b0.chunk = chunk;
   b0.use_tau = ro->use_tau ? 1 : 0;
   b0.kp_query = ro->kp_query ? 1 : 0;
+  b0.cap_items = ro->cap_items;
   // a pass with few items (rescans, a first round of one leaf per query)
   // and preallocated buffers lays out and places its items in one
   // single-work-group launch (below, once the buffers are final)
@@ -372,6 +374,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   b.chunk = chunk;
   b.use_tau = ro->use_tau ? 1 : 0;
   b.kp_query = ro->kp_query ? 1 : 0;
+  b.cap_items = ro->cap_items;
   StoreView s = store_view(ix);
   QueryView q = query_view(w);
   if (ro->first_leaf)
@@ -573,18 +576,57 @@ int64_t planned_bound(const leafi_index *ix, int64_t nq, const SearchPlan &p, in
   return std::min(nq * static_cast<int64_t>(ix->N), own + (r > 0 ? planned_bound(ix, nq, p, r - 1) : 0));
 }
 
-// Whether a batch can run as a planned sequence: a bounded number of rounds
-// whose bound-sized buffers fit the planned limit.
+// Item capacity of a planned pass (bf16: round r's scan; else the exact
+// rescan pass after round r): its bound, or the largest count whose
+// bound-sized buffers fit the planned limit when the bound's do not, or the
+// index's plan_cap_items when that is smaller.  A pass sized below its bound
+// checks its item count on the device (RoundBufs::cap_items).
+int64_t planned_cap(const leafi_index *ix, int64_t nq, const SearchPlan &p, int r, bool bf16) {
+  const int64_t bnd = planned_bound(ix, nq, p, r);
+  const int kp = bf16 ? p.kprime : default_kprime(p.kmax, false);
+  // one first-leaf round per query is sized with its one-leaf tiles
+  const bool one = bf16 && r == 0 && p.schedule[0] == 1;
+  auto fits = [&](int64_t items) {
+    int mq, cap;
+    pass_geometry(ix, bf16, kp, &mq, &cap, one);
+    const int chunk = pass_chunk(ix, bf16, kp);
+    return static_cast<double>(items) * (p.kmax * 12.0 + 32.0) +
+               static_cast<double>(tiles_bound(ix, nq, items, mq, chunk)) * mq * kp * 8.0 <=
+           kPlannedLimit;
+  };
+  int64_t cap = bnd;
+  if (!fits(cap)) {
+    int64_t lo = 0, hi = bnd;  // fits(lo), !fits(hi)
+    while (hi - lo > 1) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      (fits(mid) ? lo : hi) = mid;
+    }
+    cap = lo;
+  }
+  if (ix->plan_cap_items > 0) cap = std::min(cap, ix->plan_cap_items);
+  return cap;
+}
+
+// Whether any pass of a planned batch is sized below its bound (its results
+// are then valid only if no round overflowed: the host checks, see
+// search_planned).
+bool plan_checked(const leafi_index *ix, int64_t nq, const SearchPlan &p) {
+  const int R = planned_rounds(p);
+  for (int r = 0; r < R; ++r) {
+    const int64_t bnd = planned_bound(ix, nq, p, r);
+    if (planned_cap(ix, nq, p, r, true) < bnd) return true;
+  }
+  return R > 0 && planned_cap(ix, nq, p, R - 1, false) < planned_bound(ix, nq, p, R - 1);
+}
+
+// Whether a batch can run as a planned sequence: a bounded number of rounds,
+// each pass holding at least one item within the planned limit.
 bool can_plan(const leafi_index *ix, int64_t nq, const SearchPlan &p) {
   const int R = planned_rounds(p);
   if (R == 0 || R > kMaxPlannedRounds || !p.bf16) return false;
-  const int kprime_fb = default_kprime(p.kmax, false);
-  for (int r = 0; r < R; ++r) {
-    const int64_t bnd = planned_bound(ix, nq, p, r);
-    if (round_bytes_bound(ix, nq, bnd, true, p.kprime, p.kmax) > kPlannedLimit) return false;
-    if (round_bytes_bound(ix, nq, bnd, false, kprime_fb, p.kmax) > kPlannedLimit) return false;
-  }
-  return true;
+  for (int r = 0; r < R; ++r)
+    if (planned_cap(ix, nq, p, r, true) < 1) return false;
+  return planned_cap(ix, nq, p, R - 1, false) >= 1;
 }
 
 // Reserve every buffer a planned sequence touches at its bound, so that
@@ -601,10 +643,12 @@ void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_
   const int kprime_fb = default_kprime(p.kmax, false);
   int64_t items = 1;
   size_t cand = 1;
-  for (int r = 0; r < planned_rounds(p); ++r) {
-    const int64_t bnd = planned_bound(ix, nq, p, r);
-    items = std::max(items, bnd);
+  const int R = planned_rounds(p);
+  for (int r = 0; r < R; ++r) {
     for (bool bf : {true, false}) {
+      if (!bf && r != R - 1) continue;  // the exact rescan pass follows the last round only
+      const int64_t bnd = planned_cap(ix, nq, p, r, bf);
+      items = std::max(items, bnd);
       const int kp = bf ? p.kprime : kprime_fb;
       int mq, cap;
       pass_geometry(ix, bf, kp, &mq, &cap, bf && r == 0 && p.schedule[0] == 1);
@@ -646,8 +690,9 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
   for (int r = 0; r < R; ++r) {
     const bool first_leaf = r == 0 && p.schedule[0] == 1 && ix->N <= kLayoutLdsMax;
     if (r == 0 && !first_leaf) launch_round_worklist(ix, nq, p.schedule[r], false, st, false);
-    const int64_t bnd = planned_bound(ix, nq, p, r);
+    const int64_t bnd = planned_cap(ix, nq, p, r, true);
     RoundOpts ro;
+    ro.cap_items = bnd < planned_bound(ix, nq, p, r) ? bnd : 0;
     ro.may_read = false;
     ro.first_leaf = first_leaf;
     ro.one_leaf = r == 0 && p.schedule[0] == 1;
@@ -674,7 +719,9 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     rf.may_read = false;
     rf.small = true;
     rf.kp_query = p.kp_query;
-    scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bnd, &rf);
+    const int64_t bfb = planned_cap(ix, nq, p, r, false);
+    rf.cap_items = bfb < planned_bound(ix, nq, p, r) ? bfb : 0;
+    scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bfb, &rf);
     launch_query_merge(nq, N, p.kmax, false, true, views(w), st, ix->rowid.get(), ids, dists);
   }
 }
@@ -703,7 +750,7 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
                     static_cast<int64_t>(ix->S), static_cast<int64_t>(ix->filt.F), static_cast<int64_t>(ix->filt.h),
                     static_cast<int64_t>(ix->cal.pairs()), ix->rows,
                     static_cast<int64_t>(ix->tune_chunk), static_cast<int64_t>(ix->tune_mq),
-                    static_cast<int64_t>(p.ftile), static_cast<int64_t>(p.kp_query),
+                    static_cast<int64_t>(p.ftile), static_cast<int64_t>(p.kp_query), ix->plan_cap_items,
                     static_cast<int64_t>(__builtin_bit_cast(uint32_t, ix->leaf_eps_max))})
     k.push_back(static_cast<uint64_t>(v));
   for (int r : p.schedule) k.push_back(static_cast<uint64_t>(r));
@@ -773,6 +820,11 @@ void search_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t
   prepare_planned(ix, nq, p, use_f);
   GraphCache &g = w.graphs;
   const std::vector<uint64_t> key = plan_key(ix, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed);
+  if (std::find(g.overflowed.begin(), g.overflowed.end(), key) != g.overflowed.end()) {
+    // this shape overflowed its planned capacity before: host-driven rounds
+    search_batch(ix, raw, nq, k_dev, t_dev, p, ids, dists, stats, st);
+    return;
+  }
   hipGraphExec_t exec = nullptr;
   int path = 1;
   ++g.tick;
@@ -806,8 +858,21 @@ void search_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t
     }
     enqueue_planned(ix, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed, st);
   }
-  if (stats) {
+  // A pass sized below its bound: the results stand only if no round held
+  // more items than its buffers (the device laid out nothing from then on);
+  // otherwise the batch runs again with host-driven rounds, whose buffers
+  // follow the actual counts.
+  if (stats || plan_checked(ix, nq, p)) {
     read_ctl(ix, st);
+    if (w.h_ctl[kCtlOverflow] != 0) {
+      if (g.overflowed.size() >= static_cast<size_t>(kGraphCacheSize)) g.overflowed.erase(g.overflowed.begin());
+      g.overflowed.push_back(key);
+      search_batch(ix, raw, nq, k_dev, t_dev, p, ids, dists, stats, st);
+      if (stats) stats->path = 4;
+      return;
+    }
+  }
+  if (stats) {
     stats_from_ctl(ix, stats);
     for (int r = 0; r < planned_rounds(p); ++r) {
       float ms = 0.0f;
@@ -1569,6 +1634,14 @@ int leafi_search_knn(leafi_index *ix, const float *queries, int64_t nq, const in
       HIP_OK(hipStreamSynchronize(st));
       stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
+  });
+}
+
+int leafi_set_plan_capacity(leafi_index *ix, int64_t max_items) {
+  return guarded([&] {
+    require_built(ix);
+    LEAFI_CHECK_ARG(max_items >= 0, "max_items must be >= 0");
+    ix->plan_cap_items = max_items;
   });
 }
 

@@ -80,13 +80,15 @@ struct RoundOpts {
   bool kp_query = false;        // each query keeps item_kprime(its k) candidates (mixed-k batches)
   bool one_leaf = false;        // at most one leaf per query (a first round of schedule 1): BF16 tiles
                                 // of 16 queries, whatever the tuned size (few queries share a leaf)
+  int64_t cap_items = 0;        // > 0: the buffers hold this many items, checked on the device
+                                // (RoundBufs::cap_items); 0: the bound holds every layout
 };
 // Lay out the round's items, scan and rerank them (see api.hip).
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,
                    int64_t items_bound = -1, const RoundOpts *ro = nullptr);
 void add_scan_time(leafi_index *ix, Timing *tm);
 // Upper bound of the bound-sized buffers of a round that reads nothing back.
-constexpr double kPlannedLimit = 8.0 * (1 << 30);
+constexpr double kPlannedLimit = 16.0 * (1 << 30);
 // Device bytes a scan pass of items_bound items needs (items and candidate lists).
 double round_bytes_bound(const leafi_index *ix, int64_t nq, int64_t items_bound, bool bf16, int kprime, int kmax);
 // Queries per scan tile and list capacity of a pass (one_leaf: see RoundOpts).
@@ -108,6 +110,9 @@ SearchPlan make_plan(const leafi_index *ix, const leafi_search_opts *o);
 void check_queries(const leafi_index *ix, const float *q, int64_t nq);
 // Whether the batch can run as a planned launch sequence (no read-back).
 bool can_plan(const leafi_index *ix, int64_t nq, const SearchPlan &p);
+// Whether a planned batch has a pass sized below its bound (its overflow
+// word must be read back before the results are used).
+bool plan_checked(const leafi_index *ix, int64_t nq, const SearchPlan &p);
 // Reserve every buffer of a planned batch at its bound (no allocation after).
 void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_f);
 // Enqueue the planned launch sequence of a batch on `st`.

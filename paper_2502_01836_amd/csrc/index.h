@@ -92,6 +92,9 @@ struct GraphEntry {
 struct GraphCache {
   std::vector<GraphEntry> entries;
   std::vector<std::vector<uint64_t>> pending;  // keys of recent uncaptured planned batches
+  // keys of recent planned batches that overflowed their item capacity: the
+  // same shape runs host-driven rounds right away from then on
+  std::vector<std::vector<uint64_t>> overflowed;
   hipStream_t cap = nullptr;      // capture stream (default priority)
   bool off = false, off_timed = false;  // capture failed once: do not retry
   std::string why;
@@ -101,6 +104,7 @@ struct GraphCache {
       if (e.exec) (void)hipGraphExecDestroy(e.exec);
     entries.clear();
     pending.clear();
+    overflowed.clear();
   }
 };
 
@@ -174,8 +178,11 @@ struct leafi_index {
   leafi::Calibration cal;
   leafi::Workspace ws;
   int num_cus = 256;
-  // BF16 scan tiling (set by leafi_autotune): rows per tile, and queries per
-  // tile when at most 32 candidates are kept
+  // Item capacity of a planned batch's passes (leafi_set_plan_capacity);
+  // 0: as many as the planned buffer limit holds.
+  int64_t plan_cap_items = 0;
+  // BF16 scan tiling (set by leafi_autotune or leafi_set_tiling): rows and
+  // queries per tile
   int tune_chunk = leafi::kChunkRows;
   int tune_mq = 32;
   ~leafi_index();

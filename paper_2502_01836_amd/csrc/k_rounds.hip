@@ -194,6 +194,7 @@ __global__ void __launch_bounds__(256) k_emit_fallback(int N, RoundBufs b) {
 __global__ void __launch_bounds__(256) k_round_reset(RoundBufs b, int n_ctl, int N, int64_t nq) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n_ctl) b.ctl[i] = 0;
+  if (n_ctl > 0 && i == 0) b.ctl[kCtlOverflow] = 0;  // a fresh round of a host-driven or served sequence
   if (i < N) b.leaf_cnt[i] = 0;
   if (i < nq) b.qitem_cnt[i] = 0;
 }
@@ -201,10 +202,16 @@ __global__ void __launch_bounds__(256) k_round_reset(RoundBufs b, int n_ctl, int
 // Exclusive scans over leaves: item starts and tile starts (the whole
 // work-group of 1024 threads).  `publish` writes them, the round's control
 // words and (with zero_fill) zeroed per-leaf fill counters to global memory;
-// `ist` (optional, LDS [N]) receives the item starts.
-__device__ inline void leaf_scan_body(int N, const int64_t *__restrict__ leaf_off, int mq, int64_t row_bytes,
+// `ist` (optional, LDS [N]) receives the item starts.  Returns true when the
+// round must lay out nothing: its items exceed b.cap_items, or an earlier
+// round's did (ctl[kCtlOverflow]); the published item and tile counts are
+// then zero and the overflow word is set.
+__device__ inline bool leaf_scan_body(int N, const int64_t *__restrict__ leaf_off, int mq, int64_t row_bytes,
                                       RoundBufs &b, int64_t *sh, bool publish = true, bool zero_fill = true,
                                       int32_t *ist = nullptr, const int32_t *cnt_src = nullptr) {
+  // read before any work-group of this launch can set it (every one decides
+  // the same from its own counts)
+  const bool earlier = b.ctl[kCtlOverflow] != 0;
   const int32_t *cnt = cnt_src ? cnt_src : b.leaf_cnt;
   const int tid = threadIdx.x;
   const int per = (N + 1023) / 1024;
@@ -236,16 +243,19 @@ __device__ inline void leaf_scan_body(int N, const int64_t *__restrict__ leaf_of
     ri += c;
     rt += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
   }
+  const bool over = earlier || (b.cap_items > 0 && tot_i > b.cap_items);
   if (publish && tid == 0) {
     b.leaf_istart[N] = static_cast<int32_t>(tot_i);
     b.tile_start[N] = static_cast<int32_t>(tot_t);
-    b.ctl[kCtlItems] = tot_i;
-    b.ctl[kCtlTiles] = tot_t;
-    if (row_bytes > 0 && tot_i > 0) {
+    b.ctl[kCtlItems] = over ? 0 : tot_i;
+    b.ctl[kCtlTiles] = over ? 0 : tot_t;
+    if (over) b.ctl[kCtlOverflow] = 1;
+    if (!over && row_bytes > 0 && tot_i > 0) {
       b.ctl[kCtlScanBytes] += tot_r * row_bytes;
       b.ctl[kCtlRounds] += 1;
     }
   }
+  return over;
 }
 
 __global__ void __launch_bounds__(1024) k_leaf_scan(int N, const int64_t *__restrict__ leaf_off, int mq,
@@ -263,10 +273,11 @@ __global__ void __launch_bounds__(1024) k_leaf_scan_scatter(int64_t nq, int N, c
   __shared__ int64_t sh[16];
   // each thread's first query's item count, requested before the leaf scan
   const int n0 = threadIdx.x < nq ? b.qitem_cnt[threadIdx.x] : 0;
-  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, true, true, lds_starts ? s_ist : nullptr);
+  const bool over = leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, true, true, lds_starts ? s_ist : nullptr);
   __syncthreads();  // item starts written; the per-leaf counts are consumed
   const int32_t *ist = lds_starts ? s_ist : b.leaf_istart;
   for (int i = threadIdx.x; i < N; i += blockDim.x) b.leaf_cnt[i] = 0;
+  if (over) return;  // uniform: nothing is placed
   for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
     const int n = q == threadIdx.x ? n0 : b.qitem_cnt[q];
     for (int r = 0; r < n; ++r) {
@@ -297,9 +308,9 @@ __global__ void __launch_bounds__(1024) k_layout_scatter(int64_t nq, int N, cons
     n = b.qitem_cnt[q];
     if (lane < n) L0 = b.qitem_leaf[q * N + lane];
   }
-  leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, blockIdx.x == 0, false, s_ist);
+  const bool over = leaf_scan_body(N, leaf_off, mq, row_bytes, b, sh, blockIdx.x == 0, false, s_ist);
   __syncthreads();
-  if (q >= nq) return;
+  if (q >= nq || over) return;
   for (int r = lane; r < n; r += kWave) {
     const int L = r == lane ? L0 : b.qitem_leaf[q * N + r];
     const int slot = s_ist[L] + atomicAdd(b.leaf_fill + L, 1);
@@ -340,7 +351,8 @@ __global__ void __launch_bounds__(1024) k_first_round_layout(int64_t nq, int N, 
   if (threadIdx.x < nq) atomicAdd(s_cnt + L0, 1);
   for (int64_t q = threadIdx.x + blockDim.x; q < nq; q += blockDim.x) atomicAdd(s_cnt + order[q * N], 1);
   __syncthreads();
-  leaf_scan_body(N, s_off, mq, row_bytes, b, sh, true, false, s_ist, s_cnt);
+  const bool over = leaf_scan_body(N, s_off, mq, row_bytes, b, sh, true, false, s_ist, s_cnt);
+  if (over) return;  // uniform (a planned first round is sized for every query)
   // series in the round's items: sum over leaves of count x real rows
   int64_t series = 0;
   for (int i = threadIdx.x; i < N; i += blockDim.x) series += static_cast<int64_t>(s_cnt[i]) * s_n[i];
@@ -374,7 +386,7 @@ __global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     b.leaf_cnt[i] = 0;
   const int64_t q = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (q >= nq) return;
+  if (q >= nq || b.ctl[kCtlOverflow] != 0) return;  // an overflowed round places nothing
   const int n = b.qitem_cnt[q];
   for (int r = lane; r < n; r += kWave) {
     int L = b.qitem_leaf[q * N + r];
@@ -653,6 +665,8 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
   int *sidx = soff + kWave * kMergeSlots + 1;
   const uint64_t lt = (1ull << lane) - 1ull;
   __shared__ int active_sh[4], fb_sh[4], fe_sh[4];
+  // after a capacity overflow the item lists were never placed: nothing to merge
+  if (b.ctl[kCtlOverflow] != 0) return;
   int active = 0, n_fb = 0, n_fe = 0;  // n_fe: this lane's queued filter pairs
   for (int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + wave; q < nq; q += static_cast<int64_t>(gridDim.x) * 4) {
     // Loads that do not depend on the merge are issued before it, so that

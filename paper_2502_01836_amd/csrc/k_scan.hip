@@ -629,6 +629,8 @@ __global__ void __launch_bounds__(256) k_query_bound(StoreView s, QueryView qv, 
   uint64_t *buf0 = bsm + static_cast<size_t>(wave) * 2 * kmax, *buf1 = buf0 + kmax;
   int *s_n = reinterpret_cast<int *>(bsm + 8 * static_cast<size_t>(kmax));  // [4] result sizes
   int *s_res = s_n + 4;                                                     // [4] result offsets
+  // after a capacity overflow the item lists were never placed
+  if (b.ctl[kCtlOverflow] != 0) return;
   const int N = s.N, m = s.m;
   constexpr int kPass = kWave * kBoundSlots;
   for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {

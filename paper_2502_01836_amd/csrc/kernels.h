@@ -84,6 +84,14 @@ struct RoundBufs {
   // 1: each query keeps its own number of candidates, item_kprime(k) of the
   // pass's kprime (a batch of mixed k); 0: every query keeps kprime
   int32_t kp_query;
+  // > 0: the item buffers hold this many items (a planned round sized below
+  // its worst case).  A layout that finds more sets ctl[kCtlOverflow] and
+  // lays out nothing; from then on every round of the batch is empty and
+  // the kernels that read item lists return at once (the host then runs
+  // the batch again with host-driven rounds).  0: buffers fit every layout.
+  // The overflow word is zeroed at the start of every batch (query setup)
+  // and by every round reset (host-driven and served rounds).
+  int64_t cap_items;
 };
 
 // Candidates a query of k results keeps per (query, leaf) in a pass whose
@@ -118,7 +126,8 @@ enum Ctl : int {
   kCtlScanBytes = 9 * kCtlStride,   // unique leaf-store bytes the regular rounds read
   kCtlRounds = 10 * kCtlStride,     // regular rounds with at least one item
   kCtlFEvals = 11 * kCtlStride,     // (query, leaf) pairs queued for filter inference
-  kCtlCount = 12 * kCtlStride,
+  kCtlOverflow = 12 * kCtlStride,   // nonzero: a round's items exceeded the buffers' capacity (cap_items)
+  kCtlCount = 13 * kCtlStride,
   kCtlRoundWords = kCtlFallback + 1  // words a round starts from zero (items .. fallback)
 };
 

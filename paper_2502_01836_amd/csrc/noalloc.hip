@@ -58,6 +58,9 @@ extern "C" int leafi_search_knn_noalloc(leafi_index *ix, const float *queries, i
     LEAFI_CHECK_ARG(k_dev && t_dev && ids && dists, "NULL k, target or output pointer");
     LEAFI_CHECK_ARG(can_plan(ix, nq, p),
                     "the batch does not run as a planned launch sequence (its schedule needs a 0 within 8 rounds)");
+    LEAFI_CHECK_ARG(!plan_checked(ix, nq, p),
+                    "the batch's worst case exceeds the planned buffer limit (a capacity-checked plan may have to "
+                    "run again with host rounds, which allocate); pass fewer queries per call");
     int dev = -1;
     HIP_OK(hipGetDevice(&dev));
     LEAFI_CHECK_ARG(dev == ix->device, "the current device is not the index's device");

@@ -9,8 +9,12 @@ compute one query at a time.
   (ragged leaves): 4,096 queries with k = 1, 10, 50 in one batch; filters
   with infinite offsets give the exact results.
 
-At both sizes the batch's bound-sized buffers exceed the planned-sequence
-limit, so batches run host-driven rounds (statistics path 0).
+At both sizes the buffers sized for a batch's worst case would exceed the
+planned-sequence limit, so batches run as capacity-checked planned sequences
+(statistics path 1 to 3): each round's item count is checked on the device,
+and a round that overflows its buffers sends the batch to host-driven rounds
+(path 4: forced at 10M by a small capacity; at 25M the exact search's second
+round of 14M items overflows the planned buffers).
 """
 import sys
 
@@ -56,10 +60,10 @@ def _check(ids, d, want_ids, want_d, xs, qs):
 def test_precision_10m_k10_exact_and_filtered():
     """10M random walks, batches of 1,024 queries at k = 10.  Exact search: 16
     sampled queries against FP64 brute force over all 10M series, per-query
-    maximum relative distance error printed; the default execution and
-    host-driven rounds give identical results (at this size the batch's
-    bound-sized buffers exceed the planned-sequence limit, so both are
-    host-driven: path 0).  Filtered search with seeded filters on every leaf:
+    maximum relative distance error printed; the default execution (a
+    capacity-checked planned sequence, then its captured graph), host-driven
+    rounds and a planned sequence forced to overflow (path 4) give identical
+    results.  Filtered search with seeded filters on every leaf:
     the same 16 queries against the oracle's Algorithm 2 at the same schedule
     (the oracle's own tree, bounds, visit order, per-leaf neighbours and FP64
     filter outputs)."""
@@ -77,13 +81,23 @@ def test_precision_10m_k10_exact_and_filtered():
     qd = torch.from_numpy(q).cuda()
     out = (torch.empty((len(q), 10), dtype=torch.int64, device="cuda"),
            torch.empty((len(q), 10), dtype=torch.float32, device="cuda"))
+    # k and target in fixed device buffers: a graph is replayed only for the
+    # buffer addresses it was captured with
+    kd = torch.full((len(q),), 10, dtype=torch.int32, device="cuda")
+    td = torch.ones(len(q), dtype=torch.float32, device="cuda")
     res = []
-    for flags in (0, 0, pkg.SEARCH_HOST_ROUNDS):
-        ids, d, st = ix.search(qd, k=10, use_filters=False, schedule=(1, 0), with_stats=True, out=out, flags=flags)
+    for flags, cap, want in ((0, 0, 1), (0, 0, 3), (0, 0, 2), (pkg.SEARCH_HOST_ROUNDS, 0, 0),
+                             (pkg.SEARCH_NO_GRAPH, len(q) + 1, 4)):
+        ix.set_plan_capacity(cap)
+        ids, d, st = ix.search(qd, k=kd, target=td, k_max=10, use_filters=False, schedule=(1, 0), with_stats=True,
+                               out=out, flags=flags)
         res.append((ids.clone(), d.clone(), st))
-        assert st["path"] == 0, st
+        assert st["path"] == want, (want, st)
+    ix.set_plan_capacity(0)
     for r in res[1:]:
         assert torch.equal(res[0][0], r[0]) and torch.equal(res[0][1], r[1])
+        for c in ("leaves_scanned", "series_scanned", "fallback_items", "rounds", "scan_bytes"):
+            assert r[2][c] == res[0][2][c], c
     st = res[0][2]
     _say(f"exact search stats {st}")
     assert st["fallback_items"] <= 0.02 * st["leaves_scanned"] + 1
@@ -138,7 +152,9 @@ def test_ragged_25m_k_mix():
     qd, kd = torch.from_numpy(q).cuda(), torch.from_numpy(ks).cuda()
     ids, d, st = ix.search(qd, k=kd, k_max=50, use_filters=False, schedule=(1, 0), with_stats=True)
     _say(f"search stats {st}")
-    assert st["path"] == 0
+    # 14M items in the second round: more than the planned buffers hold, so
+    # the planned sequence overflows and the batch runs host-driven rounds
+    assert st["path"] == 4
     assert st["fallback_items"] <= 0.02 * st["leaves_scanned"] + 1
     # seeded filters on every leaf: with infinite offsets they never prune and
     # the results are the exact ones; finite offsets prune

@@ -73,6 +73,72 @@ def test_paths_are_bit_identical(env):
     assert 3 in paths and paths[-1] == 2, paths
 
 
+def test_capacity_checked_plans_fall_back_on_overflow(env):
+    """A planned batch whose item buffers are sized below the worst case
+    (leafi_set_plan_capacity) checks every round's item count on the device.
+    Sized for batch A, A runs planned, then captured and replayed, with the
+    host-driven results.  The replayed graph then meets batch B (noisier
+    queries, far more leaves per query) in the same buffers: its second round
+    overflows, lays out nothing, and the call runs B again with host-driven
+    rounds (path 4); later calls of that shape run host-driven rounds at once
+    (path 0).  With room for the first round only, a planned call overflows
+    as well.  The no-allocation search refuses a capacity-checked plan.  The
+    capacity is forced from the host: every kernel still runs to its end."""
+    pkg = env["pkg"]
+    ix = env["ix"]
+    qa = env["q"][1]
+    qb = W.noisy_queries(env["raw"], len(qa), 1.5, 616, 716)[0]
+    nq = len(qa)
+    ra = _search(env, torch.from_numpy(qa).cuda(), pkg.SEARCH_HOST_ROUNDS)
+    rb = _search(env, torch.from_numpy(qb).cuda(), pkg.SEARCH_HOST_ROUNDS)
+    assert ra[2]["rounds"] == 2
+    # B's second round alone holds more items than all of A's rounds
+    assert rb[2]["leaves_scanned"] - nq > ra[2]["leaves_scanned"] + ra[2]["fallback_items"], (ra[2], rb[2])
+    qd = torch.from_numpy(qa).cuda()
+    out = (torch.empty_like(ra[0]), torch.empty_like(ra[1]))
+    try:
+        ix.set_plan_capacity(ra[2]["leaves_scanned"] + ra[2]["fallback_items"])
+        paths = []
+        for rep in range(3):
+            out[0].fill_(-7)
+            out[1].fill_(-7.0)
+            i1, d1, s1 = _search(env, qd, 0, out=out)
+            paths.append(s1["path"])
+            assert torch.equal(i1, ra[0]) and torch.equal(d1, ra[1]), rep
+            for c in COUNTS:
+                assert s1[c] == ra[2][c], (c, ra[2][c], s1[c])
+        assert paths == [1, 3, 2], paths
+        qd.copy_(torch.from_numpy(qb).cuda())  # same buffer, batch B
+        paths = []
+        for rep in range(3):
+            out[0].fill_(-7)
+            out[1].fill_(-7.0)
+            i2, d2, s2 = _search(env, qd, 0, out=out)
+            paths.append(s2["path"])
+            assert torch.equal(i2, rb[0]) and torch.equal(d2, rb[1]), rep
+            for c in COUNTS:
+                assert s2[c] == rb[2][c], (c, rb[2][c], s2[c])
+        assert paths == [4, 0, 0], paths
+        # room for the first round (one leaf per query) only, a shape of its
+        # own (other output buffers), without statistics: the overflow is
+        # read back all the same
+        ix.set_plan_capacity(nq + 1)
+        out2 = (torch.empty_like(ra[0]), torch.empty_like(ra[1]))
+        qd.copy_(torch.from_numpy(qa).cuda())
+        i3, d3 = _search(env, qd, pkg.SEARCH_NO_GRAPH, out=out2, stats=False)
+        assert torch.equal(i3, ra[0]) and torch.equal(d3, ra[1])
+        with pytest.raises(pkg.LeafiError):
+            ix.search_noalloc(qd, env["kd"], env["td"], out2, k_max=10, schedule=(1, 0))
+        with pytest.raises(pkg.LeafiError):
+            ix.set_plan_capacity(-1)
+        # room again: the overflow word does not linger
+        ix.set_plan_capacity(0)
+        i4, d4, s4 = _search(env, qd, pkg.SEARCH_NO_GRAPH)
+        assert s4["path"] == 1 and torch.equal(i4, ra[0]) and torch.equal(d4, ra[1])
+    finally:
+        ix.set_plan_capacity(0)
+
+
 def test_graph_replay_reads_current_buffers(env):
     pkg = env["pkg"]
     qd = torch.from_numpy(env["q"][0]).cuda()
