@@ -412,6 +412,11 @@ int leafi_set_tiling(leafi_index *index, int32_t chunk_rows, int32_t queries_per
  * with host-driven rounds).  Does not change any result. */
 int leafi_set_plan_capacity(leafi_index *index, int64_t max_items);
 
+/* Why this index stopped capturing planned batches into HIP graphs (the
+ * first capture that failed), or "" while capture works.  The string is
+ * owned by the index and valid until its next search or destroy. */
+const char *leafi_graph_note(const leafi_index *index);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of k-NN requests (Algorithm 2 for a stream of
  * queries with mixed k and recall targets)

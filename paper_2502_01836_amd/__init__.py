@@ -353,6 +353,10 @@ class Index:
     def set_tiling(self, chunk_rows: int = 1024, queries_per_tile: int = 32):
         check(load().leafi_set_tiling(self._h, chunk_rows, queries_per_tile))
 
+    def graph_note(self) -> str:
+        """Why planned batches stopped being captured into graphs ('' while they are)."""
+        return (load().leafi_graph_note(self._h) or b"").decode()
+
     def set_plan_capacity(self, max_items: int = 0):
         """Item capacity of a planned batch's passes (0 = what 16 GiB of buffers hold)."""
         check(load().leafi_set_plan_capacity(self._h, int(max_items)))

@@ -139,6 +139,7 @@ SIGNATURES = [
     ("leafi_autotune", ctypes.c_int, [P, P, I64, P, P, ctypes.POINTER(SearchOpts), I32, ctypes.POINTER(TuneReport), P]),
     ("leafi_set_tiling", ctypes.c_int, [P, I32, I32]),
     ("leafi_set_plan_capacity", ctypes.c_int, [P, I64]),
+    ("leafi_graph_note", ctypes.c_char_p, [P]),
     ("leafi_default_server_opts", None, [ctypes.POINTER(ServerOpts)]),
     ("leafi_server_create", ctypes.c_int, [P, ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]),
     ("leafi_server_destroy", None, [P]),

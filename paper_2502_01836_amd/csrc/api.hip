@@ -2,6 +2,7 @@
 // index build, filter training (Algorithms 1 and 3), auto-tuner fitting
 // (Algorithm 4) and the batched round-based search (Algorithm 2).
 #include <algorithm>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -143,8 +144,22 @@ void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
 
 // ---- workspace ----------------------------------------------------------------
 
+void allow_lds(const void *kernel, size_t lds) {
+  if (lds <= 65536) return;
+  static std::mutex mu;
+  static std::vector<std::pair<const void *, size_t>> set;  // the largest limit set per kernel
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = std::find_if(set.begin(), set.end(), [&](const auto &e) { return e.first == kernel; });
+  if (it != set.end() && it->second >= lds) return;
+  HIP_OK(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  if (it != set.end()) it->second = lds;
+  else set.emplace_back(kernel, lds);
+}
+
 RoundBufs views(Workspace &w) {
+  // zeroed first, padding included: plan_key copies the struct's bytes
   RoundBufs b;
+  std::memset(&b, 0, sizeof b);
   b.cursor = w.cursor.get();
   b.tau = w.tau.get();
   b.kq = w.kq.get();
@@ -173,11 +188,13 @@ RoundBufs views(Workspace &w) {
   b.ctl = w.ctl.get();
   b.leaf_n = w.leaf_n;
   b.cap_items = 0;
+  b.cap_tiles = 0;
   return b;
 }
 
 StoreView store_view(const leafi_index *ix) {
   StoreView s;
+  std::memset(&s, 0, sizeof s);
   s.x32 = ix->x32.get();
   s.x16 = ix->x16.get();
   s.xn16 = ix->xn16.get();
@@ -191,6 +208,7 @@ StoreView store_view(const leafi_index *ix) {
 
 QueryView query_view(Workspace &w) {
   QueryView q;
+  std::memset(&q, 0, sizeof q);
   q.q32 = w.q32.get();
   q.q16 = w.q16.get();
   q.qn16 = w.qn16.get();
@@ -341,6 +359,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   b0.use_tau = ro->use_tau ? 1 : 0;
   b0.kp_query = ro->kp_query ? 1 : 0;
   b0.cap_items = ro->cap_items;
+  b0.cap_tiles = ro->cap_tiles;
   // a pass with few items (rescans, a first round of one leaf per query)
   // and preallocated buffers lays out and places its items in one
   // single-work-group launch (below, once the buffers are final)
@@ -353,11 +372,13 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
     fail(LEAFI_EINTERNAL, "scan_round: first-leaf layout needs a planned round and at most 4096 leaves");
   if (!ro->first_leaf && !fused && !fused_grid) launch_leaf_scan(ix->N, ix->leaf_off.get(), mq, ro->row_bytes, b0, st);
   int64_t items = -1, tiles;
-  const int64_t tb = items_bound >= 0 ? tiles_bound(ix, nq, items_bound, mq, chunk) : -1;
+  const int64_t tb = items_bound < 0        ? -1
+                     : ro->cap_tiles > 0 ? std::min(ro->cap_tiles, tiles_bound(ix, nq, items_bound, mq, chunk))
+                                         : tiles_bound(ix, nq, items_bound, mq, chunk);
   const double bytes = items_bound >= 0 ? static_cast<double>(items_bound) * (kmax * 12.0 + 32.0) +
                                               static_cast<double>(tb) * mq * kprime * 8.0
                                         : 0.0;
-  if (!ro->may_read && (items_bound < 0 || bytes > kPlannedLimit))
+  if (!ro->may_read && (items_bound < 0 || bytes > std::max(kPlannedLimit, 0.4 * ix->dev_mem)))
     fail(LEAFI_EINTERNAL, "scan_round: planned round exceeds its preallocation bound");
   if (ro->may_read && (items_bound < 0 || bytes > kPreallocLimit)) {
     read_ctl(ix, st);
@@ -375,6 +396,7 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   b.use_tau = ro->use_tau ? 1 : 0;
   b.kp_query = ro->kp_query ? 1 : 0;
   b.cap_items = ro->cap_items;
+  b.cap_tiles = ro->cap_tiles;
   StoreView s = store_view(ix);
   QueryView q = query_view(w);
   if (ro->first_leaf)
@@ -493,8 +515,11 @@ int planned_rounds(const SearchPlan &p);
 // counts of every round are read back, which sizes the buffers from actual
 // counts and ends the loop as soon as no query has leaves left.  Serves any
 // schedule, including open-ended ones such as the paper's one leaf per round.
+// max_items (optional, two entries) receives the largest item and tile
+// counts of a round's BF16 scan.
 void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k_dev, const float *t_dev,
-                  const SearchPlan &p, int64_t *ids, float *dists, leafi_search_stats *stats, hipStream_t st) {
+                  const SearchPlan &p, int64_t *ids, float *dists, leafi_search_stats *stats, hipStream_t st,
+                  int64_t *max_items = nullptr) {
   Workspace &w = ix->ws;
   const int N = ix->N;
   ensure_queries(ix, nq, p.kmax);
@@ -536,6 +561,10 @@ void search_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *
     launch_query_merge(nq, N, p.kmax, true, r > 0, views(w), st);
     read_ctl(ix, st);
     if (w.h_ctl[kCtlItems] == 0) break;
+    if (max_items) {
+      max_items[0] = std::max(max_items[0], w.h_ctl[kCtlItems]);
+      max_items[1] = std::max(max_items[1], w.h_ctl[kCtlTiles]);
+    }
     add_scan_time(ix, stats ? &tm : nullptr);
     const int64_t active = w.h_ctl[kCtlActive];
     const int64_t n_fb = w.h_ctl[kCtlFallback];
@@ -576,35 +605,59 @@ int64_t planned_bound(const leafi_index *ix, int64_t nq, const SearchPlan &p, in
   return std::min(nq * static_cast<int64_t>(ix->N), own + (r > 0 ? planned_bound(ix, nq, p, r - 1) : 0));
 }
 
-// Item capacity of a planned pass (bf16: round r's scan; else the exact
-// rescan pass after round r): its bound, or the largest count whose
-// bound-sized buffers fit the planned limit when the bound's do not, or the
-// index's plan_cap_items when that is smaller.  A pass sized below its bound
-// checks its item count on the device (RoundBufs::cap_items).
-int64_t planned_cap(const leafi_index *ix, int64_t nq, const SearchPlan &p, int r, bool bf16) {
+// Capacity of a planned pass (bf16: round r's scan; else the exact rescan
+// pass after round r): items and scan tiles.  Its bound, with tiles from
+// tiles_bound, when buffers of that size fit the planned limit.  Else the
+// largest item count whose bound-sized buffers fit the limit; or, for a
+// round's scan after a planned batch of this index overflowed, a quarter
+// more items and tiles than the largest round its host-driven rerun met
+// (plan_items_seen, plan_tiles_seen), as long as those buffers fit 40 % of
+// the device's memory; never more items than the index's plan_cap_items when
+// that is set.  A pass below its bound checks both counts on the device
+// (RoundBufs::cap_items, cap_tiles).
+PassCap planned_cap(const leafi_index *ix, int64_t nq, const SearchPlan &p, int r, bool bf16) {
   const int64_t bnd = planned_bound(ix, nq, p, r);
   const int kp = bf16 ? p.kprime : default_kprime(p.kmax, false);
   // one first-leaf round per query is sized with its one-leaf tiles
   const bool one = bf16 && r == 0 && p.schedule[0] == 1;
-  auto fits = [&](int64_t items) {
-    int mq, cap;
-    pass_geometry(ix, bf16, kp, &mq, &cap, one);
-    const int chunk = pass_chunk(ix, bf16, kp);
-    return static_cast<double>(items) * (p.kmax * 12.0 + 32.0) +
-               static_cast<double>(tiles_bound(ix, nq, items, mq, chunk)) * mq * kp * 8.0 <=
-           kPlannedLimit;
+  int mq, lcap;
+  pass_geometry(ix, bf16, kp, &mq, &lcap, one);
+  const int chunk = pass_chunk(ix, bf16, kp);
+  auto bytes = [&](int64_t items, int64_t tiles) {
+    return static_cast<double>(items) * (p.kmax * 12.0 + 32.0) + static_cast<double>(tiles) * mq * kp * 8.0;
   };
-  int64_t cap = bnd;
-  if (!fits(cap)) {
+  auto tb = [&](int64_t items) { return tiles_bound(ix, nq, items, mq, chunk); };
+  PassCap c{bnd, tb(bnd), false};
+  if (bytes(c.items, c.tiles) > kPlannedLimit) {
     int64_t lo = 0, hi = bnd;  // fits(lo), !fits(hi)
     while (hi - lo > 1) {
       const int64_t mid = lo + (hi - lo) / 2;
-      (fits(mid) ? lo : hi) = mid;
+      (bytes(mid, tb(mid)) <= kPlannedLimit ? lo : hi) = mid;
     }
-    cap = lo;
+    c = PassCap{lo, tb(lo), true};
+    if (bf16 && ix->plan_items_seen > 0) {
+      const int64_t it = std::min(bnd, ix->plan_items_seen + ix->plan_items_seen / 4);
+      const int64_t tl = std::min(tb(it), ix->plan_tiles_seen + ix->plan_tiles_seen / 4);
+      if (it > c.items && bytes(it, tl) <= 0.4 * ix->dev_mem) c = PassCap{it, tl, true};
+    }
   }
-  if (ix->plan_cap_items > 0) cap = std::min(cap, ix->plan_cap_items);
-  return cap;
+  if (ix->plan_cap_items > 0 && ix->plan_cap_items < c.items)
+    c = PassCap{ix->plan_cap_items, std::min(c.tiles, tb(ix->plan_cap_items)), true};
+  c.checked = c.items < bnd || c.tiles < tb(bnd);
+  return c;
+}
+
+// Every pass's capacity of a planned batch (the rounds' scans, then the rescan pass).
+std::vector<int64_t> plan_caps(const leafi_index *ix, int64_t nq, const SearchPlan &p) {
+  std::vector<int64_t> v;
+  const int R = planned_rounds(p);
+  for (int r = 0; r <= R; ++r) {
+    if (R == 0) break;
+    const PassCap c = r < R ? planned_cap(ix, nq, p, r, true) : planned_cap(ix, nq, p, R - 1, false);
+    v.push_back(c.items);
+    v.push_back(c.tiles);
+  }
+  return v;
 }
 
 // Whether any pass of a planned batch is sized below its bound (its results
@@ -612,11 +665,9 @@ int64_t planned_cap(const leafi_index *ix, int64_t nq, const SearchPlan &p, int 
 // search_planned).
 bool plan_checked(const leafi_index *ix, int64_t nq, const SearchPlan &p) {
   const int R = planned_rounds(p);
-  for (int r = 0; r < R; ++r) {
-    const int64_t bnd = planned_bound(ix, nq, p, r);
-    if (planned_cap(ix, nq, p, r, true) < bnd) return true;
-  }
-  return R > 0 && planned_cap(ix, nq, p, R - 1, false) < planned_bound(ix, nq, p, R - 1);
+  for (int r = 0; r < R; ++r)
+    if (planned_cap(ix, nq, p, r, true).checked) return true;
+  return R > 0 && planned_cap(ix, nq, p, R - 1, false).checked;
 }
 
 // Whether a batch can run as a planned sequence: a bounded number of rounds,
@@ -625,8 +676,8 @@ bool can_plan(const leafi_index *ix, int64_t nq, const SearchPlan &p) {
   const int R = planned_rounds(p);
   if (R == 0 || R > kMaxPlannedRounds || !p.bf16) return false;
   for (int r = 0; r < R; ++r)
-    if (planned_cap(ix, nq, p, r, true) < 1) return false;
-  return planned_cap(ix, nq, p, R - 1, false) >= 1;
+    if (planned_cap(ix, nq, p, r, true).items < 1) return false;
+  return planned_cap(ix, nq, p, R - 1, false).items >= 1;
 }
 
 // Reserve every buffer a planned sequence touches at its bound, so that
@@ -647,13 +698,12 @@ void prepare_planned(leafi_index *ix, int64_t nq, const SearchPlan &p, bool use_
   for (int r = 0; r < R; ++r) {
     for (bool bf : {true, false}) {
       if (!bf && r != R - 1) continue;  // the exact rescan pass follows the last round only
-      const int64_t bnd = planned_cap(ix, nq, p, r, bf);
-      items = std::max(items, bnd);
+      const PassCap c = planned_cap(ix, nq, p, r, bf);
+      items = std::max(items, c.items);
       const int kp = bf ? p.kprime : kprime_fb;
       int mq, cap;
       pass_geometry(ix, bf, kp, &mq, &cap, bf && r == 0 && p.schedule[0] == 1);
-      const int chunk = pass_chunk(ix, bf, kp);
-      cand = std::max(cand, static_cast<size_t>(std::max<int64_t>(tiles_bound(ix, nq, bnd, mq, chunk), 1)) * mq * kp);
+      cand = std::max(cand, static_cast<size_t>(std::max<int64_t>(c.tiles, 1)) * mq * kp);
     }
   }
   ensure_items(ix, items, p.kmax);
@@ -690,9 +740,11 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
   for (int r = 0; r < R; ++r) {
     const bool first_leaf = r == 0 && p.schedule[0] == 1 && ix->N <= kLayoutLdsMax;
     if (r == 0 && !first_leaf) launch_round_worklist(ix, nq, p.schedule[r], false, st, false);
-    const int64_t bnd = planned_cap(ix, nq, p, r, true);
+    const PassCap pc = planned_cap(ix, nq, p, r, true);
+    const int64_t bnd = pc.items;
     RoundOpts ro;
-    ro.cap_items = bnd < planned_bound(ix, nq, p, r) ? bnd : 0;
+    ro.cap_items = pc.checked ? pc.items : 0;
+    ro.cap_tiles = pc.checked ? pc.tiles : 0;
     ro.may_read = false;
     ro.first_leaf = first_leaf;
     ro.one_leaf = r == 0 && p.schedule[0] == 1;
@@ -719,9 +771,10 @@ void enqueue_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_
     rf.may_read = false;
     rf.small = true;
     rf.kp_query = p.kp_query;
-    const int64_t bfb = planned_cap(ix, nq, p, r, false);
-    rf.cap_items = bfb < planned_bound(ix, nq, p, r) ? bfb : 0;
-    scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, bfb, &rf);
+    const PassCap fc = planned_cap(ix, nq, p, r, false);
+    rf.cap_items = fc.checked ? fc.items : 0;
+    rf.cap_tiles = fc.checked ? fc.tiles : 0;
+    scan_round(ix, nq, false, kprime_fb, p.kmax, st, nullptr, fc.items, &rf);
     launch_query_merge(nq, N, p.kmax, false, true, views(w), st, ix->rowid.get(), ids, dists);
   }
 }
@@ -751,6 +804,7 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
                     static_cast<int64_t>(ix->cal.pairs()), ix->rows,
                     static_cast<int64_t>(ix->tune_chunk), static_cast<int64_t>(ix->tune_mq),
                     static_cast<int64_t>(p.ftile), static_cast<int64_t>(p.kp_query), ix->plan_cap_items,
+                    ix->plan_items_seen, ix->plan_tiles_seen,
                     static_cast<int64_t>(__builtin_bit_cast(uint32_t, ix->leaf_eps_max))})
     k.push_back(static_cast<uint64_t>(v));
   for (int r : p.schedule) k.push_back(static_cast<uint64_t>(r));
@@ -865,10 +919,21 @@ void search_planned(leafi_index *ix, const float *raw, int64_t nq, const int32_t
   if (stats || plan_checked(ix, nq, p)) {
     read_ctl(ix, st);
     if (w.h_ctl[kCtlOverflow] != 0) {
-      if (g.overflowed.size() >= static_cast<size_t>(kGraphCacheSize)) g.overflowed.erase(g.overflowed.begin());
-      g.overflowed.push_back(key);
-      search_batch(ix, raw, nq, k_dev, t_dev, p, ids, dists, stats, st);
+      // The host-driven run records its largest round; later planned
+      // batches of this index are sized for a quarter more (a new shape
+      // key).  Where that does not grow any pass's capacity (a set
+      // capacity, or the memory limit), the shape runs host-driven rounds at
+      // once from now on.
+      const std::vector<int64_t> before = plan_caps(ix, nq, p);
+      int64_t seen[2] = {0, 0};
+      search_batch(ix, raw, nq, k_dev, t_dev, p, ids, dists, stats, st, seen);
       if (stats) stats->path = 4;
+      ix->plan_items_seen = std::max(ix->plan_items_seen, seen[0]);
+      ix->plan_tiles_seen = std::max(ix->plan_tiles_seen, seen[1]);
+      if (plan_caps(ix, nq, p) == before) {
+        if (g.overflowed.size() >= static_cast<size_t>(kGraphCacheSize)) g.overflowed.erase(g.overflowed.begin());
+        g.overflowed.push_back(plan_key(ix, raw, nq, k_dev, t_dev, p, use_f, ids, dists, timed));
+      }
       return;
     }
   }
@@ -996,6 +1061,8 @@ int leafi_create(leafi_alloc_fn alloc, leafi_free_fn free_fn, void *alloc_ctx, l
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device) == hipSuccess && cus > 0)
       ix->num_cus = cus;
+    size_t mem = 0;
+    if (hipDeviceTotalMem(&mem, ix->device) == hipSuccess && mem > 0) ix->dev_mem = static_cast<double>(mem);
     *out = ix;
   });
 }
@@ -1635,6 +1702,11 @@ int leafi_search_knn(leafi_index *ix, const float *queries, int64_t nq, const in
       stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
   });
+}
+
+const char *leafi_graph_note(const leafi_index *ix) {
+  if (!ix) return "";
+  return ix->ws.graphs.why.c_str();
 }
 
 int leafi_set_plan_capacity(leafi_index *ix, int64_t max_items) {

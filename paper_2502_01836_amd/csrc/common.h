@@ -38,6 +38,12 @@ struct Error : std::runtime_error {
 // Check the launch just enqueued.
 #define LAUNCH_OK(name) HIP_OK(hipGetLastError())
 
+// A kernel that may be launched with more than 64 KiB of dynamic LDS: its
+// limit is raised to `lds` when a launch needs more than any before it, and
+// otherwise left alone (so a sequence being captured into a graph, which
+// repeats launches made eagerly before, makes no such call).
+void allow_lds(const void *kernel, size_t lds);
+
 // Where device memory comes from.  Allocations of an index handle go through
 // the caller's allocator when leafi_create was given one (else hipMalloc);
 // the no-allocation search carves its buffers out of a fixed device array

@@ -80,8 +80,16 @@ struct RoundOpts {
   bool kp_query = false;        // each query keeps item_kprime(its k) candidates (mixed-k batches)
   bool one_leaf = false;        // at most one leaf per query (a first round of schedule 1): BF16 tiles
                                 // of 16 queries, whatever the tuned size (few queries share a leaf)
-  int64_t cap_items = 0;        // > 0: the buffers hold this many items, checked on the device
-                                // (RoundBufs::cap_items); 0: the bound holds every layout
+  int64_t cap_items = 0;        // > 0: the buffers hold this many items and cap_tiles scan tiles,
+  int64_t cap_tiles = 0;        // checked on the device (RoundBufs::cap_items); 0: the bound holds
+                                // every layout
+};
+
+// Capacity of one pass of a planned batch (see planned_cap in api.hip).
+struct PassCap {
+  int64_t items = 0;
+  int64_t tiles = 0;
+  bool checked = false;  // below the pass's bound: the layout checks its counts on the device
 };
 // Lay out the round's items, scan and rerank them (see api.hip).
 int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax, hipStream_t st, Timing *tm,

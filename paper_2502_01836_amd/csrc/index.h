@@ -181,6 +181,11 @@ struct leafi_index {
   // Item capacity of a planned batch's passes (leafi_set_plan_capacity);
   // 0: as many as the planned buffer limit holds.
   int64_t plan_cap_items = 0;
+  // The largest round item and tile counts a planned batch that overflowed
+  // met (in its host-driven rerun): later planned batches are sized for them.
+  int64_t plan_items_seen = 0;
+  int64_t plan_tiles_seen = 0;
+  double dev_mem = 0.0;  // the device's memory (bytes)
   // BF16 scan tiling (set by leafi_autotune or leafi_set_tiling): rows and
   // queries per tile
   int tune_chunk = leafi::kChunkRows;

@@ -957,8 +957,7 @@ template <int MT>
 void launch_train_mfma_mt(const TrainArgs &a, hipStream_t st) {
   const size_t lds = train_lds_floats(a.m) * 4 + static_cast<size_t>(a.n_train) * 4 + kTrainB * 8;
   auto kern = k_mlp_train_mfma<MT>;
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(kern), lds);
   hipLaunchKernelGGL(kern, dim3(a.F), dim3(kTrainThreads), lds, st, a);
   LAUNCH_OK("mlp_train_mfma");
 }
@@ -968,8 +967,7 @@ void launch_sgd_mfma_mt(float *w, int F, int m, int h, const float *x, const flo
                         float *loss, hipStream_t st) {
   const size_t lds = train_lds_floats(m) * 4;
   auto kern = k_mlp_sgd_step_mfma<MT>;
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(kern), lds);
   hipLaunchKernelGGL(kern, dim3(F), dim3(kTrainThreads), lds, st, w, m, h, x, y, batch, lr, loss);
   LAUNCH_OK("mlp_sgd_step_mfma");
 }
@@ -981,8 +979,7 @@ void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64
   const int64_t tiles = ceil_div(nq, kMlpQ);
   dim3 grid(F, static_cast<unsigned>(tiles < 65535 ? tiles : 65535));
   const size_t lds = mlp_infer_lds(m);
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(k_mlp_infer), lds);
   hipLaunchKernelGGL(k_mlp_infer, grid, dim3(256), lds, st, w, F, m, h, x, nq, out);
   LAUNCH_OK("mlp_infer");
 }
@@ -1019,8 +1016,7 @@ void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x,
   const int big_min = local && big_fixed < 0 ? cus : 0;
   const int lds_q = big_fixed == 0 ? kMlpQ : kMlpQBig;
   const size_t lds = mlp_infer_lds(m, lds_q) + (local ? (static_cast<size_t>(F) + 1 + 4) * sizeof(int32_t) : 0);
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_infer_pairs),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(k_mlp_infer_pairs), lds);
   hipLaunchKernelGGL(k_mlp_infer_pairs, dim3(grid), dim3(256), lds, st, w, F, m, h, x, plist, pcnt, stride, N, pair,
                      offsets, tile_prefix, dfo, local ? 1 : 0, big_min, big_fixed, lds_q);
   LAUNCH_OK("mlp_infer_pairs");
@@ -1051,8 +1047,7 @@ void launch_mlp_sgd_step(float *w, int F, int m, int h, const float *x, const fl
     }
   }
   size_t lds = step_lds(m);
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_sgd_step),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(k_mlp_sgd_step), lds);
   hipLaunchKernelGGL(k_mlp_sgd_step, dim3(F), dim3(256), lds, st, w, F, m, h, x, y, batch, lr, loss);
   LAUNCH_OK("mlp_sgd_step");
 }
@@ -1079,8 +1074,7 @@ void launch_mlp_train(const TrainArgs &a, hipStream_t st) {
     }
   }
   size_t lds = step_lds(a.m) + static_cast<size_t>(a.n_train) * 4 + kTB * 8;
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_train),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(k_mlp_train), lds);
   hipLaunchKernelGGL(k_mlp_train, dim3(a.F), dim3(256), lds, st, a);
   LAUNCH_OK("mlp_train");
 }

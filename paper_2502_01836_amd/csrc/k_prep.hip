@@ -528,8 +528,7 @@ void launch_order(const float *lb, int64_t nq, int N, int32_t *order, float *lbs
                   const int32_t *slots) {
   int P = pow2_at_least(N < 2 ? 2 : N);
   size_t lds = static_cast<size_t>(P) * sizeof(uint64_t);  // <= 128 KiB for N <= 16384
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_order),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(k_order), lds);
   hipLaunchKernelGGL(k_order, dim3(nq), dim3(256), lds, st, lb, N, P, order, lbs, slots);
   LAUNCH_OK("order");
 }
@@ -543,8 +542,7 @@ void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float 
   if (N <= kSetupWaveMaxN && m <= kSetupMaxPerLane * kWave) {
     const int slice64 = N + (m + 2 * S + 1) / 2;  // keys, then zs and st in 8-byte units
     const size_t lds_w = 4 * static_cast<size_t>(slice64) * sizeof(uint64_t);
-    if (lds_w > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_setup_wave),
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_w)));
+    allow_lds(reinterpret_cast<const void *>(k_query_setup_wave), lds_w);
     hipLaunchKernelGGL(k_query_setup_wave, dim3(static_cast<unsigned>(ceil_div(nq, 4))), dim3(256), lds_w, st, raw, nq,
                        m, S, boxes, boxes_t, N, slice64, q32, q16, qn16, qeps, qstat, lb, order, lbs, k_dev, t_dev, n_pairs,
                        pair_k, pair_t, kmax, b, F, pcnt);
@@ -553,8 +551,7 @@ void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float 
   }
   const int P = pow2_at_least(N < 2 ? 2 : N);
   const size_t lds = static_cast<size_t>(P) * sizeof(uint64_t) + (static_cast<size_t>(m) + 2 * S) * sizeof(float);
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_setup),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(k_query_setup), lds);
   hipLaunchKernelGGL(k_query_setup, dim3(static_cast<unsigned>(nq)), dim3(256), lds, st, raw, m, S, boxes, N, P, q32,
                      q16, qn16, qeps, qstat, lb, order, lbs, k_dev, t_dev, n_pairs, pair_k, pair_t, kmax, b, F, pcnt);
   LAUNCH_OK("query_setup");

@@ -203,9 +203,9 @@ __global__ void __launch_bounds__(256) k_round_reset(RoundBufs b, int n_ctl, int
 // work-group of 1024 threads).  `publish` writes them, the round's control
 // words and (with zero_fill) zeroed per-leaf fill counters to global memory;
 // `ist` (optional, LDS [N]) receives the item starts.  Returns true when the
-// round must lay out nothing: its items exceed b.cap_items, or an earlier
-// round's did (ctl[kCtlOverflow]); the published item and tile counts are
-// then zero and the overflow word is set.
+// round must lay out nothing: its items or tiles exceed b.cap_items or
+// b.cap_tiles, or an earlier round's did (ctl[kCtlOverflow]); the published
+// item and tile counts are then zero and the overflow word is set.
 __device__ inline bool leaf_scan_body(int N, const int64_t *__restrict__ leaf_off, int mq, int64_t row_bytes,
                                       RoundBufs &b, int64_t *sh, bool publish = true, bool zero_fill = true,
                                       int32_t *ist = nullptr, const int32_t *cnt_src = nullptr) {
@@ -243,7 +243,7 @@ __device__ inline bool leaf_scan_body(int N, const int64_t *__restrict__ leaf_of
     ri += c;
     rt += static_cast<int64_t>((c + mq - 1) / mq) * chunks;
   }
-  const bool over = earlier || (b.cap_items > 0 && tot_i > b.cap_items);
+  const bool over = earlier || (b.cap_items > 0 && tot_i > b.cap_items) || (b.cap_tiles > 0 && tot_t > b.cap_tiles);
   if (publish && tid == 0) {
     b.leaf_istart[N] = static_cast<int32_t>(tot_i);
     b.tile_start[N] = static_cast<int32_t>(tot_t);
@@ -970,8 +970,7 @@ void launch_first_round_layout(int64_t nq, int N, const int32_t *order, const in
   // counts, starts, (padding,) offsets, sizes: at most 80 KiB for 4,096 leaves
   const size_t lds = (2 * static_cast<size_t>(N) + (N & 1)) * sizeof(int32_t) +
                      (static_cast<size_t>(N) + 1) * sizeof(int64_t) + static_cast<size_t>(N) * sizeof(int32_t);
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_first_round_layout),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(k_first_round_layout), lds);
   hipLaunchKernelGGL(k_first_round_layout, dim3(1), dim3(1024), lds, st, nq, N, order, leaf_off, leaf_n, mq,
                      row_bytes, b);
   LAUNCH_OK("first_round_layout");
@@ -1004,8 +1003,7 @@ void launch_query_merge(int64_t nq, int N, int kmax, bool check_cert, bool dedup
   size_t lds = 4 * merge_slice_bytes(kmax);
   int64_t blocks = ceil_div(nq, 4);
   int grid = static_cast<int>(blocks < 65536 ? blocks : 65536);
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_query_merge),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(k_query_merge), lds);
   (void)dedupe;  // the tournament keeps a row met twice once in every round
   hipLaunchKernelGGL(k_query_merge, dim3(grid), dim3(256), lds, st, nq, N, kmax, check_cert ? 1 : 0, b, rowid,
                      ids, dists, fp);

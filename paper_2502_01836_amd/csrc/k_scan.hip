@@ -1016,8 +1016,7 @@ void scan_bf16_inst(StoreView s, QueryView q, RoundBufs b, int kprime, int cap, 
   constexpr int MQ = 16 * QB;
   const size_t lds = scan_bf16_lds(MQ, cap, 32 * KS);
   auto kern = k_scan_bf16<KS, QB>;
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(kern), lds);
   grid = resident_grid(kern, lds, grid);
   if (e0 || e1)  // start / stop timestamps of this dispatch itself
     hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, e0, e1, 0, s, q, b, kprime, cap, cand);
@@ -1047,8 +1046,7 @@ void scan_fp32_inst(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, i
                     hipStream_t st) {
   size_t lds = static_cast<size_t>(mq) * (cap + 1) * 8 + mq * 8 + mq * 4 * 2 + static_cast<size_t>(mq) * s.m * 4 + 16;
   auto kern = k_scan_fp32<EPL>;
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(kern), lds);
   grid = resident_grid(kern, lds, grid);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, s, q, b, mq, kprime, cap, cand);
   LAUNCH_OK("scan_fp32");
@@ -1146,8 +1144,7 @@ void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprim
   const size_t slice = round_up(rerank_lds_bytes(max_chunks, kprime, &PB), 16);
   const int wpb = slice * 4 <= 65536 ? 4 : 1;
   const size_t lds = slice * wpb;
-  if (lds > 65536) HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_item_rerank),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  allow_lds(reinterpret_cast<const void *>(k_item_rerank), lds);
   const int blocks = (grid + wpb - 1) / wpb;
   hipLaunchKernelGGL(k_item_rerank, dim3(blocks), dim3(64 * wpb), lds, st, s, q, b, mq, kprime, kmax, bf16 ? 1 : 0, PB,
                      static_cast<int>(slice / 8), cand, qbound);

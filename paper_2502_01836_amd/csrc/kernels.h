@@ -90,8 +90,10 @@ struct RoundBufs {
   // the kernels that read item lists return at once (the host then runs
   // the batch again with host-driven rounds).  0: buffers fit every layout.
   // The overflow word is zeroed at the start of every batch (query setup)
-  // and by every round reset (host-driven and served rounds).
+  // and by every round reset (host-driven and served rounds).  cap_tiles
+  // (> 0) bounds the round's scan tiles the same way.
   int64_t cap_items;
+  int64_t cap_tiles;
 };
 
 // Candidates a query of k results keeps per (query, leaf) in a pass whose

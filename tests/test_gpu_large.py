@@ -14,7 +14,9 @@ planned-sequence limit, so batches run as capacity-checked planned sequences
 (statistics path 1 to 3): each round's item count is checked on the device,
 and a round that overflows its buffers sends the batch to host-driven rounds
 (path 4: forced at 10M by a small capacity; at 25M the exact search's second
-round of 14M items overflows the planned buffers).
+round of 14M items overflows the planned buffers of the default limit, and
+the next batches of that shape are planned for the size the rerun met, then
+captured and replayed).
 """
 import sys
 
@@ -92,7 +94,7 @@ def test_precision_10m_k10_exact_and_filtered():
         ids, d, st = ix.search(qd, k=kd, target=td, k_max=10, use_filters=False, schedule=(1, 0), with_stats=True,
                                out=out, flags=flags)
         res.append((ids.clone(), d.clone(), st))
-        assert st["path"] == want, (want, st)
+        assert st["path"] == want, (want, st, ix.graph_note())
     ix.set_plan_capacity(0)
     for r in res[1:]:
         assert torch.equal(res[0][0], r[0]) and torch.equal(res[0][1], r[1])
@@ -150,11 +152,26 @@ def test_ragged_25m_k_mix():
     q, _, _ = W.noisy_queries(raw, wl["nq"], wl["sigma"], wl["q_seed"], wl["q_seed"] + 100)
     ks = np.array([wl["ks"][i % 3] for i in range(wl["nq"])], dtype=np.int32)
     qd, kd = torch.from_numpy(q).cuda(), torch.from_numpy(ks).cuda()
-    ids, d, st = ix.search(qd, k=kd, k_max=50, use_filters=False, schedule=(1, 0), with_stats=True)
-    _say(f"search stats {st}")
-    # 14M items in the second round: more than the planned buffers hold, so
-    # the planned sequence overflows and the batch runs host-driven rounds
-    assert st["path"] == 4
+    td = torch.ones(len(q), dtype=torch.float32, device="cuda")
+    out = (torch.empty((len(q), 50), dtype=torch.int64, device="cuda"),
+           torch.empty((len(q), 50), dtype=torch.float32, device="cuda"))
+    # The second round holds 14M items, more than the planned buffers of the
+    # 16 GiB limit: the first planned batch overflows and runs again with
+    # host-driven rounds (path 4), which record the round's size; the next
+    # batch of that shape is planned for it (path 1), then captured (3) and
+    # replayed (2), all with the same results.
+    res = []
+    for want in (4, 1, 3, 2):
+        i_, d_, st = ix.search(qd, k=kd, target=td, k_max=50, use_filters=False, schedule=(1, 0), with_stats=True,
+                               out=out)
+        _say(f"search stats {st}")
+        assert st["path"] == want, (want, st, ix.graph_note())
+        res.append((i_.clone(), d_.clone(), st))
+    for r in res[1:]:
+        assert torch.equal(r[0], res[0][0]) and torch.equal(r[1], res[0][1])
+        for c in ("leaves_scanned", "series_scanned", "fallback_items", "rounds", "scan_bytes"):
+            assert r[2][c] == res[0][2][c], c
+    ids, d, st = res[0]
     assert st["fallback_items"] <= 0.02 * st["leaves_scanned"] + 1
     # seeded filters on every leaf: with infinite offsets they never prune and
     # the results are the exact ones; finite offsets prune

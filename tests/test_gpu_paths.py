@@ -71,6 +71,7 @@ def test_paths_are_bit_identical(env):
         assert s2["ms_scan"] > 0.0
     assert torch.equal(i1, i0) and torch.equal(d1, d0)
     assert 3 in paths and paths[-1] == 2, paths
+    assert env["ix"].graph_note() == ""
 
 
 def test_capacity_checked_plans_fall_back_on_overflow(env):
