@@ -307,6 +307,121 @@ def visit_order(lb: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# iSAX backbone (Section "Preliminaries": SAX quantises each PAA value with
+# discrete symbols, and iSAX compares words of different cardinalities, which
+# makes them indexable in a prefix tree; Section "Evaluation Setup": MESSI,
+# the in-memory iSAX index, is the paper's second backbone)
+# ---------------------------------------------------------------------------
+
+ISAX_MAX_BITS = 8  # symbols of up to 8 bits (cardinality 256) per segment
+
+
+def isax_breakpoints(bits: int = ISAX_MAX_BITS) -> np.ndarray:
+    """SAX breakpoints of cardinality 2^bits: the N(0, 1) quantiles
+    Phi^-1(j / 2^bits), j = 1 .. 2^bits - 1, in FP64, kept as fp32 (reading:
+    the PAA values they are compared with are stored as fp32).  Breakpoints of
+    a smaller cardinality are a subset: those with j a multiple of
+    2^(bits - b)."""
+    from scipy.special import ndtri
+    j = np.arange(1, 2 ** bits, dtype=np.float64)
+    return ndtri(j / 2.0 ** bits).astype(np.float32)
+
+
+def sax_symbols(mu: np.ndarray, bits: int = ISAX_MAX_BITS) -> np.ndarray:
+    """SAX symbol of each PAA value (the segment means, fp32) at cardinality
+    2^bits: the number of breakpoints <= the value (a value equal to a
+    breakpoint takes the upper interval).  Symbols at b < bits bits are these
+    shifted right by bits - b.  Returns int32, same shape as mu."""
+    bp = isax_breakpoints(bits)
+    return np.searchsorted(bp, np.asarray(mu, dtype=np.float32), side="right").astype(np.int32)
+
+
+def build_isax_tree(mu: np.ndarray, m: int, capacity: int, max_bits: int = ISAX_MAX_BITS) -> Tree:
+    """iSAX tree over the segment means (PAA), split until every leaf holds <=
+    capacity series (or its members cannot be told apart at max_bits bits).
+
+    Reading of the MESSI backbone (the paper names it, the iSAX papers define
+    it): the root's children are the words of one bit per segment (each PAA
+    value above or below 0), taken in ascending order of the word read with
+    segment 0 as its highest bit.  A node over capacity takes one more bit of
+    one segment: the segment (below max_bits) whose next bit divides the
+    members most evenly, smallest |n0 - n1|, ties by the lowest segment.  If
+    both halves are non-empty they become its children (the 0 half first);
+    otherwise the node keeps all members with the refined symbol and tries
+    again.  Leaves are numbered depth-first; members stay ascending by id.
+    Each leaf records its bits and its symbol (at those bits) per segment in
+    tree.isax[leaf] = (bits [S], symbol [S])."""
+    n, S = mu.shape
+    sym8 = sax_symbols(mu, max_bits).astype(np.int64)
+    tree = Tree(root=Node(members=np.arange(n, dtype=np.int64)), S=S, m=m)
+    tree.isax = []
+    first = sym8 >> (max_bits - 1)
+    words = np.zeros(n, dtype=np.int64)
+    for s in range(S):
+        words = (words << 1) | first[:, s]
+    order = np.lexsort((np.arange(n), words))        # by word, then id
+    uw, starts = np.unique(words[order], return_index=True)
+    bounds = list(starts) + [n]
+
+    def visit(ids, bits, sym):
+        while len(ids) > capacity:
+            elig = [s for s in range(S) if bits[s] < max_bits]
+            if not elig:
+                break                                  # identical at max_bits in every segment
+            best, best_s, best_nb = None, -1, None
+            for s in elig:
+                nb = (sym8[ids, s] >> (max_bits - 1 - bits[s])) & 1
+                n1 = int(nb.sum())
+                d = abs(len(ids) - 2 * n1)
+                if best is None or d < best:
+                    best, best_s, best_nb = d, s, nb
+            s = best_s
+            bits = bits.copy()
+            bits[s] += 1
+            zero, one = ids[best_nb == 0], ids[best_nb == 1]
+            if len(zero) and len(one):
+                sz, so = sym.copy(), sym.copy()
+                sz[s] = 2 * sym[s]
+                so[s] = 2 * sym[s] + 1
+                visit(zero, bits, sz)
+                visit(one, bits, so)
+                return
+            sym = sym.copy()
+            sym[s] = 2 * sym[s] + (0 if len(zero) else 1)
+        tree.isax.append((bits.copy(), sym.copy()))
+        tree.leaves.append(ids)
+
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        ids = np.sort(order[a:b])
+        visit(ids, np.ones(S, dtype=np.int64), first[ids[0]].copy())
+    return tree
+
+
+def isax_boxes(tree: Tree, max_bits: int = ISAX_MAX_BITS) -> np.ndarray:
+    """Leaf summaries of an iSAX tree in the box form the lower bound takes:
+    per segment the SAX interval of the leaf's symbol, [beta_c, beta_(c+1)]
+    at its cardinality (-inf / +inf at the ends), widened outward by one fp32
+    ulp (so it holds the exact segment mean of every member, not only the
+    stored fp32 one), and the deviation unconstrained, [0, +inf].  With it the
+    bound is MINDIST(PAA(q), iSAX word): the segment-weighted squared gaps
+    between the query's segment means and the intervals."""
+    bp = isax_breakpoints(max_bits)
+    S = tree.S
+    out = np.empty((len(tree.leaves), S, 4), dtype=np.float32)
+    for L, (bits, sym) in enumerate(tree.isax):
+        for s in range(S):
+            step = 1 << (max_bits - int(bits[s]))
+            c = int(sym[s])
+            lo = bp[c * step - 1] if c > 0 else np.float32(-np.inf)
+            hi = bp[(c + 1) * step - 1] if c + 1 < (1 << int(bits[s])) else np.float32(np.inf)
+            out[L, s, 0] = np.nextafter(np.float32(lo), np.float32(-np.inf))
+            out[L, s, 1] = np.nextafter(np.float32(hi), np.float32(np.inf))
+            out[L, s, 2] = 0.0
+            out[L, s, 3] = np.inf
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Learned filter: one-hidden-layer MLP (Section "Evaluation Setup", LeaFi
 # instantiation: hidden width equal to the series length, ReLU)
 # ---------------------------------------------------------------------------

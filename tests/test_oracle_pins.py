@@ -521,3 +521,105 @@ def test_recall_at_k_hand_cases():
     assert O.recall_at_k(np.array([[4, 5, 6]]), np.array([[1.0, 2.0, 3.0]]), true_d)[0] == 1.0
     assert O.recall_at_k(np.array([[4, 5, 6]]), np.array([[1.0, 2.0, 3.5]]), true_d)[0] == pytest.approx(2 / 3)
     assert O.recall_at_k(np.array([[4, -1, -1]]), np.array([[1.0, np.inf, np.inf]]), true_d)[0] == pytest.approx(1 / 3)
+
+
+# ---------------------------------------------------------------- iSAX backbone (MESSI)
+
+def _phi(x: float) -> float:
+    """Standard normal CDF from the complementary error function (math.erfc),
+    independent of the quantile routine the breakpoints come from."""
+    return 0.5 * math.erfc(-x / math.sqrt(2.0))
+
+
+def test_isax_breakpoints_closed_forms_and_nesting():
+    assert list(O.isax_breakpoints(1)) == [0.0]
+    b2 = O.isax_breakpoints(2).astype(np.float64)
+    # Phi^-1(3/4) = 0.6744897501960817 (textbook quartile of N(0, 1))
+    assert np.allclose(b2, [-0.6744897501960817, 0.0, 0.6744897501960817], rtol=0, atol=1e-7)
+    b8 = O.isax_breakpoints(8)
+    assert len(b8) == 255 and np.all(np.diff(b8) > 0)
+    assert np.array_equal(b8, -b8[::-1])               # symmetric about 0
+    for j, v in enumerate(b8.astype(np.float64), start=1):
+        # within the fp32 rounding of the quantile: |Phi(v) - j/256| <= density * |v| * 2^-23
+        dens = math.exp(-v * v / 2) / math.sqrt(2 * math.pi)
+        assert abs(_phi(v) - j / 256.0) <= dens * max(abs(v), 1e-30) * 2.0 ** -23 + 1e-15, j
+    for b in range(1, 8):
+        bb = O.isax_breakpoints(b)
+        assert np.array_equal(bb, b8[(np.arange(1, 2 ** b) << (8 - b)) - 1]), b
+
+
+def test_sax_symbols_hand_cases_and_prefixes():
+    b8 = O.isax_breakpoints(8)
+    v = np.array([-10.0, 10.0, 0.0, -1e-7, b8[10], np.nextafter(b8[10], np.float32(-np.inf))], dtype=np.float32)
+    assert list(O.sax_symbols(v)) == [0, 255, 128, 127, 11, 10]
+    rng = np.random.default_rng(5)
+    mu = rng.standard_normal((500, 4)).astype(np.float32)
+    s8 = O.sax_symbols(mu)
+    for b in range(1, 8):
+        assert np.array_equal(s8 >> (8 - b), O.sax_symbols(mu, b)), b
+
+
+def test_isax_tree_partition_words_and_sizes():
+    raw = W.random_walk(8000, 64, seed=33)
+    xs = O.znorm(raw)
+    mu, _ = O.segment_stats(xs, 16)
+    cap = 60
+    t = O.build_isax_tree(mu, 64, cap)
+    allids = np.sort(np.concatenate(t.leaves))
+    assert np.array_equal(allids, np.arange(len(xs)))
+    s8 = O.sax_symbols(mu)
+    words = []
+    for L, ids in enumerate(t.leaves):
+        bits, sym = t.isax[L]
+        assert np.all(np.diff(ids) > 0)
+        assert np.all(bits >= 1) and np.all(bits <= 8)
+        # every member's symbols start with the leaf's word
+        assert np.array_equal(s8[ids] >> (8 - bits)[None, :], np.broadcast_to(sym, (len(ids), 16)))
+        if len(ids) > cap:
+            assert np.all(bits == 8) and np.all(s8[ids] == s8[ids[0]])
+        words.append(int("".join(str(int(x)) for x in (sym >> (bits - 1))), 2))
+    # depth-first order: root words never decrease along the leaves
+    assert all(a <= b for a, b in zip(words, words[1:]))
+    assert len(t.leaves) > 100
+
+
+def test_isax_lower_bound_hand_case():
+    # m = 4, two segments of length 2; the leaf holds one series whose
+    # segment means are 0.3 and -1.2, at one bit per segment: [0, +inf) and
+    # (-inf, 0).  Query means 0.5 (inside) and 0.4 (0.4 above the interval).
+    t = O.Tree(root=O.Node(members=np.array([0])), S=2, m=4)
+    t.leaves = [np.array([0])]
+    mu = np.array([[0.3, -1.2]], dtype=np.float32)
+    t.isax = [(np.array([1, 1]), O.sax_symbols(mu, 1)[0])]
+    box = O.isax_boxes(t)
+    lb = O.lower_bound(np.array([[0.5, 0.4]]), np.array([[3.0, 0.0]]), box, 4)
+    # 2 * (0^2 + gap^2) with gap = 0.4 - (0 widened by one ulp)
+    assert lb[0, 0] == pytest.approx(math.sqrt(2 * 0.4 ** 2), rel=1e-6)
+
+
+@pytest.fixture(scope="module")
+def isax_index():
+    raw = W.random_walk(6000, 64, seed=37)
+    xs = O.znorm(raw)
+    mu, _ = O.segment_stats(xs, 16)
+    t = O.build_isax_tree(mu, 64, 50)
+    q = O.znorm(W.noisy_queries(raw, 30, (0.05, 0.3), 9, 10)[0])
+    qmu, qsd = O.query_stats(q, 16)
+    lb = O.lower_bound(qmu, qsd, O.isax_boxes(t), 64)
+    ld, li = O.leaf_knn(xs, t.leaves, q, 5)
+    return dict(xs=xs, t=t, q=q, lb=lb, ld=ld, li=li)
+
+
+def test_isax_lower_bound_never_exceeds_node_distance(isax_index):
+    s = isax_index
+    assert np.all(s["lb"] <= s["ld"][:, :, 0] * (1 + 1e-12) + 1e-12)
+
+
+@pytest.mark.parametrize("schedule", [(1,), (1, 0)])
+def test_plain_isax_tree_search_is_exact(isax_index, schedule):
+    s = isax_index
+    r = O.leafi_search(s["lb"], O.visit_order(s["lb"]), s["ld"], s["li"], 5, schedule=schedule)
+    ids, d = O.knn(s["xs"], s["q"], 5)
+    assert np.array_equal(r.ids, ids)
+    assert np.allclose(r.dist, d, rtol=1e-12)
+    assert r.lb_pruned.sum() > 0
