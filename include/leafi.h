@@ -92,18 +92,27 @@ const char *leafi_version(void);
 typedef struct {
   int32_t leaf_capacity; /* split nodes holding more series than this (>= 1) */
   int32_t n_segments;    /* S: equal segments of the node summaries, 1..64, <= m */
-  int32_t split_rule;    /* 0 = median split, 1 = midpoint of the range */
+  int32_t split_rule;    /* 0 = median split, 1 = midpoint of the range, 2 = iSAX (the MESSI
+                            backbone; n_segments <= 32) */
   int32_t reserved;
 } leafi_build_opts;
 
 /*
  * Build the index over n raw fp32 series of length m (series_dev [n, m]).
- * Steps: z-normalisation, per-segment mean/std summaries, a binary tree
- * split until every leaf holds <= leaf_capacity series (a node splits on the
- * segment statistic with the largest seg_len * range^2, at the median or the
- * range midpoint), then a device-resident leaf store: the normalised series
- * grouped leaf by leaf in fp32 and in a bf16 copy, with per-leaf summaries
- * (per segment the min/max of the members' mean and std).  Any previous
+ * Steps: z-normalisation, per-segment mean/std summaries, a tree split until
+ * every leaf holds <= leaf_capacity series, then a device-resident leaf
+ * store: the normalised series grouped leaf by leaf in fp32 and in a bf16
+ * copy, with per-leaf summaries.  Split rules 0 and 1 (DSTree-style binary
+ * tree): a node splits on the segment statistic with the largest
+ * seg_len * range^2, at the median or the range midpoint; summaries are per
+ * segment the min/max of the members' mean and std.  Split rule 2 (iSAX, the
+ * MESSI backbone of Section "Evaluation Setup"): each segment mean becomes a
+ * SAX symbol of up to 8 bits (breakpoints at the N(0, 1) quantiles j / 256);
+ * the root's children are the words of one bit per segment, and a node over
+ * capacity takes the next bit of the segment that divides its members most
+ * evenly (a node whose members agree in all 8 bits of every segment stays
+ * whole); summaries are each leaf's SAX intervals (the lower bound is then
+ * MINDIST(PAA(q), iSAX word)).  Any previous
  * index, filters and calibration in the handle are discarded.
  * Limits: 1 <= n < 2^31; at most 16384 leaves; 32 <= m <= 512, m a
  * multiple of 32.  The BF16 scan needs m <= 256, the FP32 scan m <= 256 or

@@ -120,7 +120,7 @@ class Index:
     def build(self, series, leaf_capacity: int, n_segments: int = 16, split_rule: str = "median"):
         torch = _torch()
         n, m = series.shape
-        o = _lib.BuildOpts(leaf_capacity, n_segments, {"median": 0, "midpoint": 1}[split_rule], 0)
+        o = _lib.BuildOpts(leaf_capacity, n_segments, {"median": 0, "midpoint": 1, "isax": 2}[split_rule], 0)
         check(load().leafi_build_index(self._h, _dev(series, torch.float32, "series"), n, m, ctypes.byref(o),
                                        _stream()))
         self._m = m

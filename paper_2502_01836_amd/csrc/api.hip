@@ -1081,7 +1081,8 @@ int leafi_build_index(leafi_index *ix, const float *series, int64_t n, int32_t m
     LEAFI_CHECK_ARG(opts->leaf_capacity >= 1, "leaf_capacity must be >= 1");
     LEAFI_CHECK_ARG(opts->n_segments >= 1 && opts->n_segments <= 64 && opts->n_segments <= m,
                     "n_segments must be in [1, min(64, m)]");
-    LEAFI_CHECK_ARG(opts->split_rule == 0 || opts->split_rule == 1, "split_rule must be 0 or 1");
+    LEAFI_CHECK_ARG(opts->split_rule >= 0 && opts->split_rule <= 2, "split_rule must be 0, 1 or 2");
+    LEAFI_CHECK_ARG(opts->split_rule != 2 || opts->n_segments <= 32, "the iSAX tree takes at most 32 segments");
     hipStream_t st = as_stream(stream);
     const int S = opts->n_segments;
     // discard previous state

@@ -15,14 +15,27 @@ namespace leafi {
 
 struct TreeResult {
   std::vector<std::vector<int64_t>> leaves;  // member ids per leaf (ascending), depth-first order
+  // iSAX trees only: per leaf and segment the symbol's bits and the symbol
+  // at those bits, [N, S] each (empty for the binary trees)
+  std::vector<uint8_t> isax_bits, isax_sym;
 };
 
 // Split until every leaf holds <= capacity series.  seg_mu / seg_sd are
-// [n, S] fp32 summaries; rule 0 = median, 1 = range midpoint.
+// [n, S] fp32 summaries; rule 0 = median, 1 = range midpoint, 2 = iSAX
+// (build_isax_tree; S <= 32).
 TreeResult build_tree(const std::vector<float> &seg_mu, const std::vector<float> &seg_sd, int64_t n, int S, int m,
                       int capacity, int rule);
 
-// Per-leaf boxes [N, S, 4] (mu lo, mu hi, sd lo, sd hi), widened by one fp32 ulp.
+// iSAX symbols of up to this many bits per segment.
+constexpr int kIsaxMaxBits = 8;
+// SAX breakpoints of cardinality 2^bits as fp32: the N(0, 1) quantiles j / 2^bits.
+std::vector<float> isax_breakpoints(int bits);
+// The iSAX tree over the segment means (see tree.cpp).
+TreeResult build_isax_tree(const std::vector<float> &seg_mu, int64_t n, int S, int capacity);
+
+// Per-leaf boxes [N, S, 4] (mu lo, mu hi, sd lo, sd hi), widened by one fp32
+// ulp: the members' ranges, or for an iSAX tree each leaf's SAX intervals
+// (the deviation unconstrained).
 std::vector<float> leaf_boxes(const std::vector<float> &seg_mu, const std::vector<float> &seg_sd, int S,
                               const TreeResult &t);
 

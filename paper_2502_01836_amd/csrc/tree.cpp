@@ -157,6 +157,7 @@ struct Builder {
 
 TreeResult build_tree(const std::vector<float> &seg_mu, const std::vector<float> &seg_sd, int64_t n, int S, int m,
                       int capacity, int rule) {
+  if (rule == 2) return build_isax_tree(seg_mu, n, S, capacity);
   Builder b{seg_mu, seg_sd, S, capacity, rule, {}, build_threads()};
   b.seglen.resize(S);
   for (int s = 0; s < S; ++s) b.seglen[s] = static_cast<double>(((s + 1) * m) / S - (s * m) / S);
@@ -167,10 +168,163 @@ TreeResult build_tree(const std::vector<float> &seg_mu, const std::vector<float>
   return out;
 }
 
+// ---- iSAX backbone -------------------------------------------------------------
+//
+// The MESSI backbone (Section "Evaluation Setup"; SAX and iSAX as Section
+// "Preliminaries" describes them): each segment mean (PAA value) becomes a
+// symbol, the number of N(0, 1) quantile breakpoints at or below it; a
+// symbol of b bits is the 8-bit one shifted right by 8 - b, because the
+// breakpoints of cardinality 2^b are every 2^(8-b)-th of cardinality 256.
+// The root's children are the words of one bit per segment, in ascending
+// order with segment 0 as the highest bit; a node over capacity takes the
+// next bit of the segment whose bit divides its members most evenly (ties:
+// lowest segment), and splits in two when both halves are non-empty (else it
+// keeps its members with the refined symbol and tries again); leaves are
+// numbered depth-first, the 0 half first.
+
+namespace {
+
+// Standard normal CDF from the complementary error function.
+double norm_cdf(double x) { return 0.5 * std::erfc(-x / std::sqrt(2.0)); }
+
+// Phi^-1(p) for 0 < p < 1: bisection on the CDF over [-40, 40] (80 halvings
+// leave an interval below the spacing of doubles there), then two Newton
+// steps on Phi(x) - p.
+double norm_quantile(double p) {
+  double lo = -40.0, hi = 40.0;
+  for (int i = 0; i < 80; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    (norm_cdf(mid) < p ? lo : hi) = mid;
+  }
+  double x = 0.5 * (lo + hi);
+  for (int i = 0; i < 2; ++i) {
+    const double dens = std::exp(-0.5 * x * x) / 2.5066282746310002;  // sqrt(2 pi)
+    if (dens > 0.0) x -= (norm_cdf(x) - p) / dens;
+  }
+  return x;
+}
+
+}  // namespace
+
+std::vector<float> isax_breakpoints(int bits) {
+  const int c = 1 << bits;
+  std::vector<float> bp(c - 1);
+  for (int j = 1; j < c; ++j) {
+    // the middle one is exactly 0 (p = 1/2); the rest from the lower tail,
+    // where the CDF keeps its relative accuracy, mirrored for the upper half
+    const int jj = j > c / 2 ? c - j : j;
+    const double x = jj * 2 == c ? 0.0 : norm_quantile(static_cast<double>(jj) / c);
+    bp[j - 1] = static_cast<float>(j > c / 2 ? -x : x);
+  }
+  return bp;
+}
+
+TreeResult build_isax_tree(const std::vector<float> &seg_mu, int64_t n, int S, int capacity) {
+  const std::vector<float> bp = isax_breakpoints(kIsaxMaxBits);
+  // 8-bit symbols of every (series, segment)
+  std::vector<uint8_t> sym8(static_cast<size_t>(n) * S);
+  parallel_ranges(n, n >= kParallelMin ? build_threads() : 1, [&](int, int64_t a, int64_t b) {
+    for (int64_t i = a * S; i < b * S; ++i)
+      sym8[i] = static_cast<uint8_t>(std::upper_bound(bp.begin(), bp.end(), seg_mu[i]) - bp.begin());
+  });
+  // root children: ids grouped by their one-bit word, ascending words, ids ascending within
+  std::vector<uint64_t> word(n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t w = 0;
+    for (int s = 0; s < S; ++s) w = (w << 1) | (sym8[i * S + s] >> (kIsaxMaxBits - 1));
+    word[i] = w;
+  }
+  std::vector<int64_t> idx(n);
+  for (int64_t i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return word[a] < word[b]; });
+  TreeResult out;
+  std::vector<uint8_t> bits(S), sym(S);
+  // depth-first, 0 half first: an explicit stack of (members, bits, symbols)
+  struct Task {
+    std::vector<int64_t> ids;
+    std::vector<uint8_t> bits, sym;
+  };
+  auto run = [&](Task root) {
+    std::vector<Task> stack;
+    stack.push_back(std::move(root));
+    while (!stack.empty()) {
+      Task t = std::move(stack.back());
+      stack.pop_back();
+      bool split = false;
+      while (static_cast<int64_t>(t.ids.size()) > capacity) {
+        int best_s = -1;
+        int64_t best = -1, best_n1 = 0;
+        const int64_t nn = static_cast<int64_t>(t.ids.size());
+        for (int s = 0; s < S; ++s) {
+          if (t.bits[s] >= kIsaxMaxBits) continue;
+          const int shift = kIsaxMaxBits - 1 - t.bits[s];
+          int64_t n1 = 0;
+          for (int64_t id : t.ids) n1 += (sym8[id * S + s] >> shift) & 1;
+          const int64_t d = nn > 2 * n1 ? nn - 2 * n1 : 2 * n1 - nn;
+          if (best < 0 || d < best) {
+            best = d;
+            best_s = s;
+            best_n1 = n1;
+          }
+        }
+        if (best_s < 0) break;  // identical at 8 bits in every segment: an oversized leaf
+        const int s = best_s, shift = kIsaxMaxBits - 1 - t.bits[s];
+        t.bits[s] = static_cast<uint8_t>(t.bits[s] + 1);
+        if (best_n1 > 0 && best_n1 < nn) {
+          Task zero{{}, t.bits, t.sym}, one{{}, t.bits, t.sym};
+          zero.sym[s] = static_cast<uint8_t>(2 * t.sym[s]);
+          one.sym[s] = static_cast<uint8_t>(2 * t.sym[s] + 1);
+          zero.ids.reserve(nn - best_n1);
+          one.ids.reserve(best_n1);
+          for (int64_t id : t.ids) (((sym8[id * S + s] >> shift) & 1) ? one : zero).ids.push_back(id);
+          stack.push_back(std::move(one));   // popped after the zero half
+          stack.push_back(std::move(zero));
+          split = true;
+          break;
+        }
+        t.sym[s] = static_cast<uint8_t>(2 * t.sym[s] + (best_n1 > 0 ? 1 : 0));
+      }
+      if (split) continue;
+      out.leaves.push_back(std::move(t.ids));
+      out.isax_bits.insert(out.isax_bits.end(), t.bits.begin(), t.bits.end());
+      out.isax_sym.insert(out.isax_sym.end(), t.sym.begin(), t.sym.end());
+    }
+  };
+  for (int64_t a = 0; a < n;) {
+    int64_t b = a;
+    while (b < n && word[idx[b]] == word[idx[a]]) ++b;
+    Task t;
+    t.ids.assign(idx.begin() + a, idx.begin() + b);
+    t.bits.assign(S, 1);
+    t.sym.resize(S);
+    for (int s = 0; s < S; ++s) t.sym[s] = static_cast<uint8_t>(sym8[t.ids[0] * S + s] >> (kIsaxMaxBits - 1));
+    run(std::move(t));
+    a = b;
+  }
+  return out;
+}
+
 std::vector<float> leaf_boxes(const std::vector<float> &seg_mu, const std::vector<float> &seg_sd, int S,
                               const TreeResult &t) {
   const int64_t N = static_cast<int64_t>(t.leaves.size());
   std::vector<float> box(static_cast<size_t>(N) * S * 4);
+  if (!t.isax_bits.empty()) {
+    // each leaf's SAX interval per segment, widened by one ulp; any deviation
+    const std::vector<float> bp = isax_breakpoints(kIsaxMaxBits);
+    for (int64_t L = 0; L < N; ++L)
+      for (int s = 0; s < S; ++s) {
+        const int b = t.isax_bits[L * S + s], c = t.isax_sym[L * S + s];
+        const int step = 1 << (kIsaxMaxBits - b);
+        const float lo = c > 0 ? bp[c * step - 1] : -INFINITY;
+        const float hi = c + 1 < (1 << b) ? bp[(c + 1) * step - 1] : INFINITY;
+        float *o = &box[(static_cast<size_t>(L) * S + s) * 4];
+        o[0] = std::nextafter(lo, -INFINITY);
+        o[1] = std::nextafter(hi, INFINITY);
+        o[2] = 0.0f;
+        o[3] = INFINITY;
+      }
+    return box;
+  }
   parallel_ranges(N, N >= 64 ? build_threads() : 1, [&](int, int64_t a, int64_t b) {
     for (int64_t L = a; L < b; ++L) {
       const auto &mem = t.leaves[L];

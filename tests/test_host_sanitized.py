@@ -74,6 +74,21 @@ def test_tree_and_boxes_match_oracle(harness, kind):
     assert np.array_equal(boxes, O.leaf_boxes(mu, sd, want))
 
 
+@pytest.mark.parametrize("n,m,cap", [(20000, 64, 100), (12000, 256, 40)])
+def test_isax_tree_and_boxes_match_oracle(harness, n, m, cap):
+    """The iSAX (MESSI) tree: partition, depth-first order and each leaf's
+    SAX-interval box equal the oracle's (the library computes its own
+    breakpoints from the normal CDF; the oracle takes scipy's quantiles)."""
+    xs = O.znorm(W.random_walk(n, m, 1201))
+    mu, sd = O.segment_stats(xs, 16)
+    leaves, boxes = _tree(harness, mu, sd, m, cap, 2)
+    want = O.build_isax_tree(mu, m, cap)
+    assert len(leaves) == len(want.leaves)
+    for got, w in zip(leaves, want.leaves):
+        assert np.array_equal(got, w)
+    assert np.array_equal(boxes, O.isax_boxes(want))
+
+
 def test_tree_with_heavy_ties_matches_oracle(harness):
     """Quantised statistics (many equal values): the median split's (value, id)
     order decides; a capacity of 1 splits down to single series."""
