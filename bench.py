@@ -193,7 +193,8 @@ def main():
 
     ix = pkg.Index()
     t0 = time.time()
-    ix.build(raw_d, leaf_capacity=wl["capacity"], n_segments=16)
+    ix.build(raw_d, leaf_capacity=wl["capacity"], n_segments=wl.get("segments", 16),
+             split_rule=wl.get("split", "median"))
     torch.cuda.synchronize()
     t_build = time.time() - t0
     info = ix.info()
@@ -457,7 +458,9 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": f"{a.workload}: {n} random walks x {m}, leaf capacity {wl['capacity']}, "
+        "config": {"workload": f"{a.workload}: {n} random walks x {m}, "
+                               f"{'iSAX tree of ' + str(wl['segments']) + ' segments, ' if wl.get('split') == 'isax' else ''}"
+                               f"leaf capacity {wl['capacity']}, "
                                f"{info['n_leaves']} leaves, {rep['n_filters']} MLP filters {m}->{m}->1; batches of "
                                f"{nq} queries ({sig_desc}), each with k in {list(ks)} and recall target in "
                                f"{list(targets)}",

@@ -17,6 +17,7 @@
 // sequential build: min / max and the selection by (value, id) do not depend
 // on the order of evaluation.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <future>
 #include <thread>
@@ -235,16 +236,22 @@ TreeResult build_isax_tree(const std::vector<float> &seg_mu, int64_t n, int S, i
     word[i] = w;
   }
   std::vector<int64_t> idx(n);
-  for (int64_t i = 0; i < n; ++i) idx[i] = i;
-  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return word[a] < word[b]; });
-  TreeResult out;
-  std::vector<uint8_t> bits(S), sym(S);
+  if (S <= 20) {
+    // counting sort over the 2^S words (ids stay ascending within a word)
+    std::vector<int64_t> start((size_t(1) << S) + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++start[word[i] + 1];
+    for (size_t w = 1; w < start.size(); ++w) start[w] += start[w - 1];
+    for (int64_t i = 0; i < n; ++i) idx[start[word[i]]++] = i;
+  } else {
+    for (int64_t i = 0; i < n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return word[a] < word[b]; });
+  }
   // depth-first, 0 half first: an explicit stack of (members, bits, symbols)
   struct Task {
     std::vector<int64_t> ids;
     std::vector<uint8_t> bits, sym;
   };
-  auto run = [&](Task root) {
+  auto run = [&](Task root, TreeResult &out) {
     std::vector<Task> stack;
     stack.push_back(std::move(root));
     while (!stack.empty()) {
@@ -290,16 +297,33 @@ TreeResult build_isax_tree(const std::vector<float> &seg_mu, int64_t n, int S, i
       out.isax_sym.insert(out.isax_sym.end(), t.sym.begin(), t.sym.end());
     }
   };
+  // the root's children, each built on its own by the host threads, then
+  // their leaves concatenated in word order
+  std::vector<std::pair<int64_t, int64_t>> groups;
   for (int64_t a = 0; a < n;) {
     int64_t b = a;
     while (b < n && word[idx[b]] == word[idx[a]]) ++b;
-    Task t;
-    t.ids.assign(idx.begin() + a, idx.begin() + b);
-    t.bits.assign(S, 1);
-    t.sym.resize(S);
-    for (int s = 0; s < S; ++s) t.sym[s] = static_cast<uint8_t>(sym8[t.ids[0] * S + s] >> (kIsaxMaxBits - 1));
-    run(std::move(t));
+    groups.emplace_back(a, b);
     a = b;
+  }
+  std::vector<TreeResult> part(groups.size());
+  std::atomic<size_t> next{0};
+  const int threads = n >= kParallelMin ? build_threads() : 1;
+  parallel_ranges(threads, threads, [&](int, int64_t, int64_t) {
+    for (size_t g = next++; g < groups.size(); g = next++) {
+      Task t;
+      t.ids.assign(idx.begin() + groups[g].first, idx.begin() + groups[g].second);
+      t.bits.assign(S, 1);
+      t.sym.resize(S);
+      for (int s = 0; s < S; ++s) t.sym[s] = static_cast<uint8_t>(sym8[t.ids[0] * S + s] >> (kIsaxMaxBits - 1));
+      run(std::move(t), part[g]);
+    }
+  });
+  TreeResult out;
+  for (auto &p : part) {
+    for (auto &l : p.leaves) out.leaves.push_back(std::move(l));
+    out.isax_bits.insert(out.isax_bits.end(), p.isax_bits.begin(), p.isax_bits.end());
+    out.isax_sym.insert(out.isax_sym.end(), p.isax_sym.begin(), p.isax_sym.end());
   }
   return out;
 }

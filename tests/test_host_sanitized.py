@@ -74,7 +74,7 @@ def test_tree_and_boxes_match_oracle(harness, kind):
     assert np.array_equal(boxes, O.leaf_boxes(mu, sd, want))
 
 
-@pytest.mark.parametrize("n,m,cap", [(20000, 64, 100), (12000, 256, 40)])
+@pytest.mark.parametrize("n,m,cap", [(20000, 64, 100), (12000, 256, 40), (300000, 64, 200)])
 def test_isax_tree_and_boxes_match_oracle(harness, n, m, cap):
     """The iSAX (MESSI) tree: partition, depth-first order and each leaf's
     SAX-interval box equal the oracle's (the library computes its own

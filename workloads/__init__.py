@@ -188,6 +188,11 @@ WORKLOADS = {
                   split="median", n_calib=500, calib_seed=5004, train_seed=5002, train_sigma=(0.05, 0.2),
                   sigma=0.1, test_seed=5005, ks=(1, 10, 100), targets=(0.90, 0.95, 0.99), mix_seed=5003,
                   nq=1_024, rates=(2_000, 5_000, 10_000, 20_000)),
+    # the same collection and queries in an iSAX (MESSI) tree: 8 segments, 8-bit symbols
+    "rw50m_isax": dict(kind="random_walk_device", n=50_000_000, m=256, seed=5001, capacity=10_000,
+                       split="isax", segments=8, n_calib=500, calib_seed=5004, train_seed=5002,
+                       train_sigma=(0.05, 0.2), sigma=0.1, test_seed=5005, ks=(1, 10, 100),
+                       targets=(0.90, 0.95, 0.99), mix_seed=5003, nq=1_024, rates=(2_000, 5_000, 10_000, 20_000)),
     # ragged-leaf case: 25M length-96 Gaussian-mixture series, midpoint splits
     "gm25m": dict(kind="gaussian_mixture", n=25_000_000, m=96, n_comp=1_000, spread=0.3,
                   seed_means=4001, seed_members=4002, capacity=10_000, split="midpoint",
