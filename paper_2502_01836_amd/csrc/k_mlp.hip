@@ -949,6 +949,164 @@ __global__ void __launch_bounds__(kTrainThreads, 1) k_mlp_train_mfma(TrainArgs a
   }
 }
 
+// ---- inference with the weights held in registers ---------------------------
+//
+// For the shapes the matrix-core training serves: a persistent grid of
+// work-groups of kTrainWaves wavefronts, each taking whole filters.  A
+// filter's W1 slice is read once into registers in the training layout
+// (train_load), then its rows -- every query, or the filter's listed (query,
+// leaf) pairs -- pass through LDS up to 64 at a time: the forward product on
+// v_mfma_f32_16x16x4_f32 exactly as in training (16-row blocks past the
+// batch's rows skipped), ReLU and the output layer summed per lane over its
+// hidden units, over the 16 lanes of a quarter, then b2 plus the wavefronts
+// in turn.  Every row's value is computed the same way whichever rows share
+// its batch, so the dense and the listed forms give the same d^f.
+template <int MT>
+__device__ inline void infer_batch(const float (&W)[kTrainHT][MT][4], const float (&b1r)[kTrainHT],
+                                   const float (&w2r)[kTrainHT], int h, int nrb, const TrainLds &t) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int q = lane >> 4, col = lane & 15;
+  const bool act = 16 * kTrainHT * wave < h;
+  constexpr int ldx = 16 * MT + 1;
+  floatx4_t Z[kTrainHT][4];
+#pragma unroll
+  for (int i = 0; i < kTrainHT; ++i)
+#pragma unroll
+    for (int tb = 0; tb < 4; ++tb) Z[i][tb] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  if (act) {
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb) {
+          if (tb < nrb) {  // uniform
+            const float a = t.xb[(16 * tb + col) * ldx + 16 * ti + 4 * q + s];
+#pragma unroll
+            for (int i = 0; i < kTrainHT; ++i)
+              Z[i][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, W[i][ti][s], Z[i][tb], 0, 0, 0);
+          }
+        }
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) {
+    if (tb >= nrb) break;  // uniform
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float p = 0.0f;
+#pragma unroll
+      for (int i = 0; i < kTrainHT; ++i) p = fmaf(w2r[i], fmaxf(Z[i][tb][r] + b1r[i], 0.0f), p);
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) p += __shfl_xor(p, o, kWave);
+      if (col == 0) t.red[wave * kTrainB + 16 * tb + 4 * q + r] = p;
+    }
+  }
+}
+
+// The wavefront's W1 slice, b1 and w2 as train_load reads them, through one
+// running address made opaque after every step (the compiler would otherwise
+// compute all MT x 4 x kTrainHT 64-bit addresses before the first load).
+template <int MT>
+__device__ inline void infer_load(const float *wf, int m, int h, float (&W)[kTrainHT][MT][4], float (&b1r)[kTrainHT],
+                                  float (&w2r)[kTrainHT]) {
+  const int q = (threadIdx.x & (kWave - 1)) >> 4;
+#pragma unroll
+  for (int i = 0; i < kTrainHT; ++i) {
+    const int j = train_unit(i);
+    const bool act = j < h;
+    const float *p = wf + static_cast<int64_t>(4 * q) * h + (act ? j : 0);
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float v = *p;
+        W[i][ti][r] = act ? v : 0.0f;
+        p += h;
+        asm volatile("" : "+v"(p));
+      }
+      p += static_cast<int64_t>(12) * h;
+    }
+    b1r[i] = act ? wf[static_cast<int64_t>(h) * m + j] : 0.0f;
+    w2r[i] = act ? wf[static_cast<int64_t>(h) * m + h + j] : 0.0f;
+  }
+}
+
+// Dense form (plist NULL): out[r F + f] = d^f of query r for r < nq.  Listed
+// form: for the pcnt[f] entries e = plist[f stride + i] (e = q N + visit
+// position), dfo[e] = d^f - offsets[pair[q] F + f].  rows_cap (32 or 64)
+// rows per batch.
+template <int MT>
+__global__ void __launch_bounds__(kTrainThreads, 1) k_mlp_infer_ws(const float *__restrict__ w, int F, int m, int h,
+                                                                   const float *__restrict__ x, int64_t nq, float *out,
+                                                                   const int64_t *__restrict__ plist,
+                                                                   const int32_t *__restrict__ pcnt, int64_t stride,
+                                                                   int N, const int32_t *__restrict__ pair,
+                                                                   const float *__restrict__ offsets, float *dfo,
+                                                                   int rows_cap) {
+  extern __shared__ __align__(16) float lds[];
+  const TrainLds t = train_lds(lds, m);
+  int64_t *rowq = reinterpret_cast<int64_t *>(t.scal + 4);  // [kTrainB] query row of each batch row
+  int64_t *rent = rowq + kTrainB;                           // [kTrainB] its list entry
+  const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
+  const int m4 = m / 4;
+  for (int f = blockIdx.x; f < F; f += gridDim.x) {
+    const int64_t n = plist ? static_cast<int64_t>(pcnt[f]) : nq;
+    if (n <= 0) continue;  // uniform
+    const float *wf = w + f * P;
+    float W[kTrainHT][MT][4], b1r[kTrainHT], w2r[kTrainHT];
+    infer_load<MT>(wf, m, h, W, b1r, w2r);
+    const float b2 = wf[P - 1];
+    for (int64_t r0 = 0; r0 < n; r0 += rows_cap) {
+      const int nr = static_cast<int>(n - r0 < rows_cap ? n - r0 : rows_cap);
+      if (threadIdx.x < kTrainB) {
+        const int c = threadIdx.x;
+        int64_t qr = -1, e = -1;
+        if (c < nr) {
+          if (plist) {
+            e = plist[f * stride + r0 + c];
+            qr = e / N;
+          } else {
+            qr = r0 + c;
+          }
+        }
+        rowq[c] = qr;
+        rent[c] = e;
+      }
+      __syncthreads();
+      // the batch's rows (16-byte loads; rows past nr in the last 16-row block are zero)
+      const int rows16 = (nr + 15) / 16 * 16;
+      for (int e4 = threadIdx.x; e4 < rows16 * m4; e4 += blockDim.x) {
+        const int c = e4 / m4, i4 = e4 - c * m4;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (c < nr) v = reinterpret_cast<const float4 *>(x + rowq[c] * m)[i4];
+        float *d = t.xb + c * t.ldx + 4 * i4;
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+      }
+      __syncthreads();
+      infer_batch<MT>(W, b1r, w2r, h, rows16 / 16, t);
+      __syncthreads();
+      if (threadIdx.x < nr) {
+        const int c = threadIdx.x;
+        float yh = b2;
+        for (int wv = 0; wv < kTrainWaves; ++wv) yh += t.red[wv * kTrainB + c];
+        if (plist) {
+          const int64_t e = rent[c];
+          dfo[e] = yh - offsets[static_cast<int64_t>(pair[rowq[c]]) * F + f];
+        } else {
+          out[(r0 + c) * F + f] = yh;
+        }
+      }
+      __syncthreads();  // the next batch overwrites the rows, the batch and the sums
+    }
+  }
+}
+
 // Shapes the matrix-core training serves: inputs and hidden units multiples
 // of 16, at most 256 each.
 bool train_mfma_ok(int m, int h) { return m % 16 == 0 && h % 16 == 0 && m <= 256 && h <= 16 * kTrainHT * kTrainWaves; }
@@ -972,10 +1130,46 @@ void launch_sgd_mfma_mt(float *w, int F, int m, int h, const float *x, const flo
   LAUNCH_OK("mlp_sgd_step_mfma");
 }
 
+template <int MT>
+void infer_ws_mt(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, const int64_t *plist,
+                 const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets, float *dfo,
+                 int rows_cap, hipStream_t st) {
+  const size_t lds = train_lds_floats(m) * 4 + 2 * kTrainB * sizeof(int64_t) + 16;
+  auto kern = k_mlp_infer_ws<MT>;
+  allow_lds(reinterpret_cast<const void *>(kern), lds);
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  const int grid = F < cus ? F : cus;  // one resident work-group per CU (registers), each taking whole filters
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kTrainThreads), lds, st, w, F, m, h, x, nq, out, plist, pcnt, stride, N,
+                     pair, offsets, dfo, rows_cap);
+  LAUNCH_OK("mlp_infer_ws");
+}
+
+// The weights-in-registers inference for the shapes the matrix-core training
+// serves; false (nothing launched) for others.
+bool infer_ws(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, const int64_t *plist,
+              const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets, float *dfo,
+              int rows_cap, hipStream_t st) {
+  if (!train_mfma_ok(m, h)) return false;
+  switch (m / 16) {
+#define LEAFI_WS(k) \
+  case k: infer_ws_mt<k>(w, F, m, h, x, nq, out, plist, pcnt, stride, N, pair, offsets, dfo, rows_cap, st); return true;
+    LEAFI_WS(1) LEAFI_WS(2) LEAFI_WS(3) LEAFI_WS(4) LEAFI_WS(5) LEAFI_WS(6) LEAFI_WS(7) LEAFI_WS(8)
+    LEAFI_WS(9) LEAFI_WS(10) LEAFI_WS(11) LEAFI_WS(12) LEAFI_WS(13) LEAFI_WS(14) LEAFI_WS(15) LEAFI_WS(16)
+#undef LEAFI_WS
+  }
+  return false;
+}
+
 }  // namespace
 
 void launch_mlp_infer(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, hipStream_t st) {
   if (nq <= 0 || F <= 0) return;
+  if (infer_ws(w, F, m, h, x, nq, out, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr, kTrainB, st)) return;
   const int64_t tiles = ceil_div(nq, kMlpQ);
   dim3 grid(F, static_cast<unsigned>(tiles < 65535 ? tiles : 65535));
   const size_t lds = mlp_infer_lds(m);
@@ -988,6 +1182,10 @@ void launch_mlp_infer_pairs(const float *w, int F, int m, int h, const float *x,
                             const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets,
                             int32_t *tile_prefix, float *dfo, hipStream_t st, int tile_mode) {
   if (F <= 0 || stride <= 0) return;
+  // weights in registers: tile_mode 1 takes 32 rows per batch, else 64 (the values do not depend on it)
+  if (infer_ws(w, F, m, h, x, 0, nullptr, plist, pcnt, stride, N, pair, offsets, dfo, tile_mode == 1 ? 32 : kTrainB,
+               st))
+    return;
   // up to kLocalPrefixMax filters the inference kernel computes the tile
   // prefix itself (one launch instead of two)
   constexpr int kLocalPrefixMax = 4096;
