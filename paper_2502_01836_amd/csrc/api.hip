@@ -180,6 +180,7 @@ RoundBufs views(Workspace &w) {
   b.item_row = w.item_row.get();
   b.item_cnt = w.item_cnt.get();
   b.item_bound = w.item_bound.get();
+  b.item_live = w.item_live.get();
   b.fb_q = w.fb_q.get();
   b.fb_leaf = w.fb_leaf.get();
   b.chunk = kChunkRows;
@@ -265,6 +266,7 @@ void ensure_items(leafi_index *ix, int64_t items, int kmax) {
     w.item_leaf.alloc(cap);
     w.item_cnt.alloc(cap);
     w.item_bound.alloc(cap);
+    w.item_live.alloc(cap);
     w.fb_q.alloc(cap);
     w.fb_leaf.alloc(cap);
     w.item_d2.alloc(cap * kmax);
@@ -425,9 +427,11 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : 12)));
   // a search round's rerank skips candidates that cannot enter their query's top k
   const bool bound = bf16 && ro->use_tau;
-  if (bound)
+  if (bound) {
     launch_query_bound(s, q, b, nq, mq, kprime, kmax, ix->max_chunks_for(chunk), ix->leaf_eps_max, w.cand.get(),
                        w.qbound.get(), st);
+    launch_rerank_skip(s, q, b, mq, kprime, w.cand.get(), w.qbound.get(), ib, ro->small ? 1 : ix->num_cus, st);
+  }
   launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks_for(chunk), st,
                      bound ? w.qbound.get() : nullptr);
   return items;

@@ -143,7 +143,7 @@ struct Workspace {
   // leaves
   DevBuf<int32_t> leaf_cnt, leaf_fill, leaf_istart, tile_start;
   // items
-  DevBuf<int32_t> item_q, item_leaf, item_row, item_cnt, fb_q, fb_leaf;
+  DevBuf<int32_t> item_q, item_leaf, item_row, item_cnt, item_live, fb_q, fb_leaf;
   DevBuf<double> item_d2;
   DevBuf<float> item_bound;
   DevBuf<uint64_t> cand;

@@ -249,6 +249,7 @@ __device__ inline bool leaf_scan_body(int N, const int64_t *__restrict__ leaf_of
     b.tile_start[N] = static_cast<int32_t>(tot_t);
     b.ctl[kCtlItems] = over ? 0 : tot_i;
     b.ctl[kCtlTiles] = over ? 0 : tot_t;
+    b.ctl[kCtlLive] = 0;
     if (over) b.ctl[kCtlOverflow] = 1;
     if (!over && row_bytes > 0 && tot_i > 0) {
       b.ctl[kCtlScanBytes] += tot_r * row_bytes;
@@ -403,8 +404,8 @@ __global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b
 // for a rescan (by the next round's scan, or an exact FP32 pass after the
 // last round).  Every list is already sorted (the running top-k and each
 // item's exact top-k), so the k smallest of their union are selected by a
-// tournament over the list heads (merge_pass): k rounds of a wavefront
-// minimum, not a sort of everything.  A row met twice (a rescan of a leaf
+// tournament over the list heads (merge_pass_staged): k rounds of a
+// wavefront minimum per pass, not a sort of everything.  A row met twice (a rescan of a leaf
 // already merged) carries the same (distance, row) in both lists and is kept
 // once.
 constexpr int kMergePreFp = 4;  // visit positions per lane whose filter-pair inputs the merge prefetches
@@ -415,106 +416,15 @@ __device__ __forceinline__ uint64_t dbl_bits(double v) { return static_cast<uint
 
 // One pass of the tournament: the k smallest distinct (distance, row)
 // entries of the sorted list in (in_v, in_t) (n_in entries, LDS) and of the
-// item lists qitem_idx[q N + it0 .. it0 + nb) (nb <= 64 kMergeSlots) go to
-// (out_v, out_t) in ascending order; returns how many.  Lane l holds items
-// it0 + l + 64 i: the head of each in registers and the next two entries in
-// flight behind it, so a list that wins several rounds in a row rarely waits.
-__device__ inline int merge_pass(int64_t q, int N, int kmax, int k, const RoundBufs &b, int it0, int nb,
-                                 const double *in_v, const uint32_t *in_t, int n_in, double *out_v,
-                                 uint32_t *out_t, int lane) {
-  constexpr double kInf = __builtin_inf();
-  double hv[kMergeSlots], n1v[kMergeSlots], n2v[kMergeSlots];
-  uint32_t ht[kMergeSlots], n1t[kMergeSlots], n2t[kMergeSlots];
-  int64_t base[kMergeSlots];
-  int pos[kMergeSlots], cnt[kMergeSlots];
-#pragma unroll
-  for (int i = 0; i < kMergeSlots; ++i) {
-    const int j = lane + kWave * i;
-    int idx = 0, c = 0;
-    if (j < nb) {
-      idx = b.qitem_idx[q * N + it0 + j];
-      c = b.item_cnt[idx];
-      c = c < k ? c : k;
-    }
-    base[i] = static_cast<int64_t>(idx) * kmax;
-    cnt[i] = c;
-  }
-#pragma unroll
-  for (int i = 0; i < kMergeSlots; ++i) {
-    hv[i] = n1v[i] = n2v[i] = kInf;
-    ht[i] = n1t[i] = n2t[i] = 0xffffffffu;
-    if (cnt[i] > 0) {
-      hv[i] = b.item_d2[base[i]];
-      ht[i] = static_cast<uint32_t>(b.item_row[base[i]]);
-    }
-    if (cnt[i] > 1) {
-      n1v[i] = b.item_d2[base[i] + 1];
-      n1t[i] = static_cast<uint32_t>(b.item_row[base[i] + 1]);
-    }
-    if (cnt[i] > 2) {
-      n2v[i] = b.item_d2[base[i] + 2];
-      n2t[i] = static_cast<uint32_t>(b.item_row[base[i] + 2]);
-    }
-    pos[i] = 3;
-  }
-  int out = 0, rp = 0;
-  while (out < k) {
-    // this lane's smallest head, then the wavefront's: value first, then row
-    double lv = kInf;
-    uint32_t lt = 0xffffffffu;
-#pragma unroll
-    for (int i = 0; i < kMergeSlots; ++i)
-      if (hv[i] < lv || (hv[i] == lv && ht[i] < lt)) {
-        lv = hv[i];
-        lt = ht[i];
-      }
-    const uint64_t mvb = wave_min_u64(dbl_bits(lv));
-    const uint64_t mtb = wave_min_u64(dbl_bits(lv) == mvb ? static_cast<uint64_t>(lt) : ~0ull);
-    double gv = __longlong_as_double(static_cast<long long>(mvb));
-    uint32_t gt = static_cast<uint32_t>(mtb);
-    // the running list's head (uniform)
-    const double rv = rp < n_in ? in_v[rp] : kInf;
-    const uint32_t rt = rp < n_in ? in_t[rp] : 0xffffffffu;
-    if (rv < gv || (rv == gv && rt < gt)) {
-      gv = rv;
-      gt = rt;
-    }
-    if (gt == 0xffffffffu) break;  // every list is exhausted
-    if (lane == 0) {
-      out_v[out] = gv;
-      out_t[out] = gt;
-    }
-    ++out;
-    // every head equal to the winner advances (a row met twice is emitted once)
-    if (rv == gv && rt == gt) ++rp;
-#pragma unroll
-    for (int i = 0; i < kMergeSlots; ++i) {
-      if (hv[i] == gv && ht[i] == gt) {
-        hv[i] = n1v[i];
-        ht[i] = n1t[i];
-        n1v[i] = n2v[i];
-        n1t[i] = n2t[i];
-        n2v[i] = kInf;
-        n2t[i] = 0xffffffffu;
-        if (pos[i] < cnt[i]) {
-          n2v[i] = b.item_d2[base[i] + pos[i]];
-          n2t[i] = static_cast<uint32_t>(b.item_row[base[i] + pos[i]]);
-        }
-        ++pos[i];
-      }
-    }
-  }
-  wave_lds_sync();
-  return out;
-}
-
-// The same pass with the pass's lists staged in LDS first: every entry of
+// item lists qitem_idx[q N + it0 ..] go to (out_v, out_t) in ascending order;
+// returns how many.  The pass's lists are staged in LDS first: every entry of
 // the (at most 64 kMergeSlots) lists, each cut to k, is loaded at once (all
 // loads in flight together, not one dependent load per round), so the
-// tournament's rounds read LDS only.  Returns -1, having changed nothing,
-// when the lists hold more than kMergeStage entries in all (the caller then
-// runs merge_pass).  stage_v / stage_t hold kMergeStage entries, soff and
-// sidx 64 kMergeSlots + 1 ints.
+// tournament's rounds read LDS only.  Takes the leading items whose entries
+// fit kMergeStage (at least one: an item has at most k <= 256 entries) and
+// sets *consumed to their number; the caller passes the rest again.
+// stage_v / stage_t hold kMergeStage entries, soff and sidx 64 kMergeSlots + 1
+// ints.
 constexpr int kMergeStage = 1024;
 
 // LDS of one merge wavefront: the two kmax-entry lists (16-byte multiple),
@@ -531,7 +441,7 @@ __host__ __device__ inline size_t merge_slice_bytes(int kmax) {
 __device__ inline int merge_pass_staged(int64_t q, int N, int kmax, int k, const RoundBufs &b, int it0, int nb,
                                         const double *in_v, const uint32_t *in_t, int n_in, double *out_v,
                                         uint32_t *out_t, int lane, double *stage_v, uint32_t *stage_t, int *soff,
-                                        int *sidx) {
+                                        int *sidx, int *consumed) {
   constexpr double kInf = __builtin_inf();
   constexpr int kSlots = kWave * kMergeSlots;
   int cnt[kMergeSlots], off[kMergeSlots];
@@ -557,12 +467,20 @@ __device__ inline int merge_pass_staged(int64_t q, int N, int kmax, int k, const
     cnt[i] = c;
     sidx[j] = idx;
   }
-  if (total > kMergeStage) {  // uniform
-    wave_lds_sync();
-    return -1;
-  }
+  // the leading items whose entries fit the staging area (slot order
+  // follows item order, so they are a prefix); the rest wait for the next call
+  int used = 0, staged = 0;
 #pragma unroll
-  for (int i = 0; i < kMergeSlots; ++i) soff[lane + kWave * i] = off[i];
+  for (int i = 0; i < kMergeSlots; ++i) {
+    const bool fit = lane + kWave * i < nb && off[i] + cnt[i] <= kMergeStage;
+    used += __popcll(__ballot(fit));
+    if (!fit) cnt[i] = 0;
+    staged = max(staged, wave_max(fit ? off[i] + cnt[i] : 0));
+  }
+  *consumed = used;
+  total = staged;
+#pragma unroll
+  for (int i = 0; i < kMergeSlots; ++i) soff[lane + kWave * i] = cnt[i] > 0 ? off[i] : min(off[i], total);
   if (lane == 0) soff[kSlots] = total;
   wave_lds_sync();
   // entry e of the staged lists belongs to the last slot s with soff[s] <= e
@@ -714,11 +632,12 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
       }
       wave_lds_sync();
       int n_in = have < k ? have : k;
-      for (int it0 = 0; it0 < n_it; it0 += kWave * kMergeSlots) {
+      for (int it0 = 0; it0 < n_it;) {
         const int nb = n_it - it0 < kWave * kMergeSlots ? n_it - it0 : kWave * kMergeSlots;
-        const int got =
-            merge_pass_staged(q, N, kmax, k, b, it0, nb, vals, tags, n_in, ov, ot, lane, stage_v, stage_t, soff, sidx);
-        n_in = got >= 0 ? got : merge_pass(q, N, kmax, k, b, it0, nb, vals, tags, n_in, ov, ot, lane);
+        int used = 0;
+        n_in = merge_pass_staged(q, N, kmax, k, b, it0, nb, vals, tags, n_in, ov, ot, lane, stage_v, stage_t, soff,
+                                 sidx, &used);
+        it0 += used;
         double *sv = vals;
         vals = ov;
         ov = sv;

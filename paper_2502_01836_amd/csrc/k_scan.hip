@@ -688,6 +688,68 @@ __global__ void __launch_bounds__(256) k_query_bound(StoreView s, QueryView qv, 
   }
 }
 
+// Per item of a search round, one lane each: each chunk list is sorted, so
+// its first key is its smallest, and every row of the item has a key at least
+// the smallest of them (or was never a candidate: key >= the tau threshold).
+// When even that bound exceeds the query's bound U, no row of the item can
+// enter the query's top k: the item contributes nothing and is certified by
+// that bound (no sort, no rerank).  The others are appended to item_live.
+__global__ void __launch_bounds__(256) k_rerank_skip(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
+                                                     const uint64_t *__restrict__ cand,
+                                                     const float *__restrict__ qbound) {
+  const int n_items = static_cast<int>(b.ctl[kCtlItems]);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int m = s.m;
+  // whole wavefronts step together (the append below is wavefront-wide)
+  for (int base = blockIdx.x * blockDim.x + (threadIdx.x - lane); base < n_items; base += gridDim.x * blockDim.x) {
+    const int item = base + lane;
+    bool live = false;
+    if (item < n_items) {
+      const int L = b.item_leaf[item];
+      const int64_t q = b.item_q[item];
+      const int ist0 = b.leaf_istart[L], ist1 = b.leaf_istart[L + 1];
+      const int64_t off0 = s.leaf_off[L], off1 = s.leaf_off[L + 1];
+      const float tau_q = b.tau[q], qn_q = qv.qn16[q], qe_q = qv.qeps[q], le_L = s.leaf_eps[L];
+      const float U = qbound[q];
+      const int64_t t0 = b.tile_start[L];
+      const int pos = item - ist0;
+      const int g = pos / mq, j = pos - g * mq;
+      const int C = static_cast<int>((off1 - off0 + b.chunk - 1) / b.chunk);
+      const int G = (ist1 - ist0 + mq - 1) / mq;
+      uint64_t h = kKeyMax;
+      for (int c = 0; c < C; ++c) {
+        const uint64_t v = cand[((t0 + static_cast<int64_t>(c) * G + g) * mq + j) * kprime];
+        h = v < h ? v : h;
+      }
+      float kd = h != kKeyMax ? key_d2(h) : __builtin_inff();
+      kd = fminf(kd, tau_threshold(tau_q, qn_q, qe_q, le_L, m));
+      double lower = -1.0;
+      if (kd < __builtin_inff()) {
+        const double v = static_cast<double>(kd) - bf16_delta(qn_q, m);
+        lower = (v > 0.0 ? sqrt(v) : 0.0) - qe_q - le_L;
+      }
+      if (lower > static_cast<double>(U)) {
+        float lb = static_cast<float>(lower);
+        if (static_cast<double>(lb) > lower) lb = nextafterf(lb, -__builtin_inff());
+        b.item_cnt[item] = 0;
+        b.item_bound[item] = lb;
+      } else {
+        live = true;
+      }
+    }
+    const uint64_t mask = __ballot(live);
+    if (mask != 0) {
+      const int lead = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+      int at = 0;
+      if (lane == lead)
+        at = static_cast<int>(atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlLive),
+                                        static_cast<unsigned long long>(__popcll(mask))));
+      at = __shfl(at, lead, kWave);
+      if (live) b.item_live[at + __popcll(mask & ((1ull << lane) - 1))] = item;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
                                                      int kmax, int bf16, int PB, int slice_u64,
                                                      const uint64_t *__restrict__ cand,
@@ -711,7 +773,10 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
   // error constants (see the certificate below)
   const double u = 1.0 / 16777216.0;  // 2^-24
   const float delta32 = static_cast<float>(2.0 * (m + 4) * u);
-  for (int item = blockIdx.x * wpb + wave; item < n_items; item += gridDim.x * wpb) {
+  // a search round reranks only the items k_rerank_skip listed
+  const int n_work = qbound ? static_cast<int>(b.ctl[kCtlLive]) : n_items;
+  for (int w_i = blockIdx.x * wpb + wave; w_i < n_work; w_i += gridDim.x * wpb) {
+    const int item = qbound ? b.item_live[w_i] : w_i;
     const int L = b.item_leaf[item];
     const int64_t q = b.item_q[item];
     // everything else the item needs from memory, requested together
@@ -727,38 +792,6 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
     const int kp = item_kprime(b.kp_query, kprime, k, bf16 != 0);
     const int PKi = pow2_at_least(kp < 2 ? 2 : kp);
     int n = C * kprime;
-    if (qbound) {
-      // Each chunk list is sorted, so its first key is its smallest; every
-      // row of the item has a key at least the smallest of them (or was never
-      // a candidate: key >= the tau threshold).  When even that bound exceeds
-      // the query's bound U, no row of the item can enter the query's top k:
-      // the item contributes nothing and is certified by that bound (no sort,
-      // no rerank).
-      const float U = qbound[q];
-      const int64_t t0 = b.tile_start[L];
-      uint64_t h = kKeyMax;
-      for (int c = lane; c < C; c += kWave) {
-        const uint64_t v = cand[((t0 + static_cast<int64_t>(c) * G + g) * mq + j) * kprime];
-        h = v < h ? v : h;
-      }
-      h = wave_min_u64(h);
-      float kd = h != kKeyMax ? key_d2(h) : __builtin_inff();
-      kd = fminf(kd, tau_threshold(tau_q, qn_q, qe_q, le_L, m));
-      double lower = -1.0;
-      if (kd < __builtin_inff()) {
-        const double v = static_cast<double>(kd) - bf16_delta(qn_q, m);
-        lower = (v > 0.0 ? sqrt(v) : 0.0) - qe_q - le_L;
-      }
-      if (lower > static_cast<double>(U)) {  // uniform
-        if (lane == 0) {
-          float lb = static_cast<float>(lower);
-          if (static_cast<double>(lb) > lower) lb = nextafterf(lb, -__builtin_inff());
-          b.item_cnt[item] = 0;
-          b.item_bound[item] = lb;
-        }
-        continue;
-      }
-    }
     if (kp <= kSelectMax && n <= kWave * kSelectPerLane) {
       // few keys wanted from many: kp rounds of a wavefront minimum, each
       // lane holding as few registers as n needs
@@ -1149,6 +1182,14 @@ void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprim
   hipLaunchKernelGGL(k_item_rerank, dim3(blocks), dim3(64 * wpb), lds, st, s, q, b, mq, kprime, kmax, bf16 ? 1 : 0, PB,
                      static_cast<int>(slice / 8), cand, qbound);
   LAUNCH_OK("item_rerank");
+}
+
+void launch_rerank_skip(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, const uint64_t *cand,
+                        const float *qbound, int64_t items_bound, int num_cus, hipStream_t st) {
+  const int64_t want = ceil_div(std::max<int64_t>(items_bound, 1), 256);
+  const int blocks = static_cast<int>(std::min<int64_t>(want, static_cast<int64_t>(num_cus) * 8));
+  hipLaunchKernelGGL(k_rerank_skip, dim3(blocks), dim3(256), 0, st, s, q, b, mq, kprime, cand, qbound);
+  LAUNCH_OK("rerank_skip");
 }
 
 }  // namespace leafi

@@ -69,6 +69,7 @@ struct RoundBufs {
   int32_t *item_row;    // [items, kmax]
   int32_t *item_cnt;
   float *item_bound;    // lower bound on any row of the item that is not a candidate
+  int32_t *item_live;   // a search round's items that its bounds did not certify (ctl[kCtlLive] of them)
   // fallback list of (query, leaf) pairs
   int32_t *fb_q;
   int32_t *fb_leaf;
@@ -129,7 +130,8 @@ enum Ctl : int {
   kCtlRounds = 10 * kCtlStride,     // regular rounds with at least one item
   kCtlFEvals = 11 * kCtlStride,     // (query, leaf) pairs queued for filter inference
   kCtlOverflow = 12 * kCtlStride,   // nonzero: a round's items exceeded the buffers' capacity (cap_items)
-  kCtlCount = 13 * kCtlStride,
+  kCtlLive = 13 * kCtlStride,       // a search round's items left to rerank (item_live)
+  kCtlCount = 14 * kCtlStride,
   kCtlRoundWords = kCtlFallback + 1  // words a round starts from zero (items .. fallback)
 };
 
@@ -237,7 +239,9 @@ void launch_scan_fp32(StoreView s, QueryView q, RoundBufs b, int mq, int kprime,
                       hipStream_t st);
 
 // Per item: merge its tiles' candidates, rerank in FP32 (FP64 for the band
-// around the k-th), write the item's top-k and its certificate bound.
+// around the k-th), write the item's top-k and its certificate bound.  With
+// qbound (a search round) only the items launch_rerank_skip listed are
+// reranked.
 // Per query of a search round after its BF16 scan: qbound[q] = an upper bound
 // of the query's k-th distance after the round (from the k-th smallest key
 // over all its candidate lists, and its tau), for the rerank to skip
@@ -247,6 +251,12 @@ void launch_query_bound(StoreView s, QueryView q, RoundBufs b, int64_t nq, int m
                         float eps_max, const uint64_t *cand, float *qbound, hipStream_t st);
 void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int kmax, bool bf16,
                         const uint64_t *cand, int grid, int max_chunks, hipStream_t st, const float *qbound = nullptr);
+// Per item of a search round after launch_query_bound: an item whose every
+// row is provably farther than its query's bound gets no results and that
+// bound as its certificate; the others are listed in item_live for the
+// rerank.  items_bound >= the round's item count sizes the grid.
+void launch_rerank_skip(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, const uint64_t *cand,
+                        const float *qbound, int64_t items_bound, int num_cus, hipStream_t st);
 
 // Candidate-list geometry for kprime kept keys: queries per tile and list
 // capacity.  BF16: mq_pref queries per tile (16, 32, 48 or 64; others mean
