@@ -20,8 +20,13 @@ timing starts.  Beside the steps: the serving engine under Poisson arrivals
 filters off (exact search), the plain FP32 per-query path, and the FP64 CPU
 oracle on a bounded sample, whose exact answers also give recall per class.
 
-`--workload rw1m` runs the 1M x 256 learned-filter configuration instead
-(k = 1, target 0.99, three batches of 1,000 queries at noise 0.05/0.1/0.2).
+Other workloads (`--workload`): rw1m, the 1M x 256 learned-filter
+configuration (k = 1, target 0.99, three batches of 1,000 queries at noise
+0.05/0.1/0.2); rw10m, the 10M x 256 precision configuration (k = 10, target
+0.99, three batches of 1,024 queries at those noise levels); gm25m, 25M
+length-96 Gaussian-mixture series with ragged leaves (four batches of 4,096
+queries at noise 0.1, k in {1, 10, 50}, target 0.99); rw50m_isax, the default
+collection and queries in an iSAX tree.  Those are generated on the host.
 
 Prints one JSON line.
 """
@@ -41,6 +46,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "queries/sec + p50/p99 latency at recall@k≥0.99; leaf-scan HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 matrix-core peak of one MI355X
 
 
 def log(*a):
@@ -89,7 +95,10 @@ def make_collection(wl, dev):
                 gen_time[0] += time.perf_counter() - t
                 yield lo, h
         return raw_d, None, chunks
-    raw = W.random_walk(n, m, wl["seed"])
+    if wl["kind"] == "gaussian_mixture":
+        raw = W.gaussian_mixture(n, m, wl["n_comp"], wl["spread"], wl["seed_means"], wl["seed_members"])
+    else:
+        raw = W.random_walk(n, m, wl["seed"])
 
     def chunks(gen_time):
         step = 1 << 20
@@ -116,10 +125,20 @@ def make_queries(wl, raw_d, raw):
         c, _, _ = W.noisy_queries(raw, wl["n_calib"], tuple(wl["train_sigma"]), wl["calib_seed"], wl["calib_seed"] + 100)
         calib = torch.from_numpy(c).to(dev)
         batches = []
-        for s, sd in zip(wl["sigmas"], wl["test_seeds"]):
-            q, _, _ = W.noisy_queries(raw, nq, s, sd, sd + 100)
-            batches.append(torch.from_numpy(q).to(dev))
-        sig_desc = "noise " + "/".join(str(s) for s in wl["sigmas"])
+        if "sigmas" in wl:
+            # one batch per noise level
+            seeds = wl.get("test_seeds") or tuple(wl["test_seed"] + i for i in range(len(wl["sigmas"])))
+            for s, sd in zip(wl["sigmas"], seeds):
+                q, _, _ = W.noisy_queries(raw, nq, s, sd, sd + 100)
+                batches.append(torch.from_numpy(q).to(dev))
+            sig_desc = "noise " + "/".join(str(s) for s in wl["sigmas"])
+        else:
+            # four batches at one noise level
+            for i in range(4):
+                sd = wl["q_seed"] + 1000 * i
+                q, _, _ = W.noisy_queries(raw, nq, wl["sigma"], sd, sd + 100)
+                batches.append(torch.from_numpy(q).to(dev))
+            sig_desc = f"noise {wl['sigma']}"
     rng = np.random.default_rng(wl.get("mix_seed", 0))
     classes = [(k, t) for k in ks for t in targets]
     cls = [rng.integers(0, len(classes), nq) for _ in batches]
@@ -286,7 +305,7 @@ def main():
     ms_per_step = 1e3 * t_total / a.steps
     log(f"timed {a.steps} steps: {qps:.0f} queries/s, {ms_per_step:.2f} ms per batch")
 
-    t_scan_ms, t_scan_bytes, t_scans, paths, stats_all = 0.0, 0.0, 0, set(), []
+    t_scan_ms, t_scan_bytes, t_scans, t_series, paths, stats_all = 0.0, 0.0, 0, 0, set(), []
     for i in range(a.warmup):
         sbound[i % nb]()
     torch.cuda.synchronize()
@@ -296,12 +315,18 @@ def main():
         t_scan_ms += st["ms_scan"]
         t_scan_bytes += st["scan_bytes"]
         t_scans += st["rounds"]
+        t_series += st["series_scanned"]
         paths.add(st["path"])
         if i < nb:
             stats_all.append(st)
     stats_qps = a.steps * nq / (time.perf_counter() - p0)
     achieved = t_scan_bytes / (t_scan_ms * 1e-3) / 1e9 if t_scan_ms > 0 else 0.0
-    log(f"roofline pass: {stats_qps:.0f} queries/s, scan {achieved:.0f} GB/s, paths {sorted(paths)}")
+    # the same launches as matrix-core work: 2m flops per (query, series)
+    # pair the regular rounds scanned
+    t_scan_flops = 2.0 * m * t_series
+    scan_tflops = t_scan_flops / (t_scan_ms * 1e-3) / 1e12 if t_scan_ms > 0 else 0.0
+    log(f"roofline pass: {stats_qps:.0f} queries/s, scan {achieved:.0f} GB/s and {scan_tflops:.0f} TFLOP/s, "
+        f"paths {sorted(paths)}")
 
     # results of each batch (filters on) and recall against the exact search
     got = []
@@ -445,6 +470,8 @@ def main():
         rec_oracle["exact_search_max_rel_err"] = float(np.max(errs))
 
     lat_ms = np.array(lat) * 1e3
+    kind_desc = ("Gaussian-mixture series ({} components, spread {})".format(wl["n_comp"], wl["spread"])
+                 if wl["kind"] == "gaussian_mixture" else "random walks")
     line = {
         "metric": METRIC,
         "value": qps,
@@ -458,7 +485,7 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": f"{a.workload}: {n} random walks x {m}, "
+        "config": {"workload": f"{a.workload}: {n} {kind_desc} x {m}, "
                                f"{'iSAX tree of ' + str(wl['segments']) + ' segments, ' if wl.get('split') == 'isax' else ''}"
                                f"leaf capacity {wl['capacity']}, "
                                f"{info['n_leaves']} leaves, {rep['n_filters']} MLP filters {m}->{m}->1; batches of "
@@ -483,6 +510,10 @@ def main():
                      "bytes_per_launch": t_scan_bytes / max(t_scans, 1),
                      "bytes_are": "unique leaf rows (real series, no padding) x (2m + 4) per round",
                      "scan_ms_per_step": t_scan_ms / a.steps, "scan_bytes_per_step": t_scan_bytes / a.steps},
+        "scan_mfma": {"achieved": scan_tflops, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": scan_tflops / BF16_MFMA_PEAK_TFLOPS, "kernel": "k_scan_bf16",
+                      "flops_are": "2m per (query, series) pair the regular rounds scanned (real series)",
+                      "flops_per_step": t_scan_flops / a.steps},
         "search_paths": {"timed_steps": "default execution", "roofline_pass": sorted(paths)},
         "roofline_pass_qps": stats_qps,
         "scan_tiling": tune,

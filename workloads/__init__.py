@@ -196,5 +196,6 @@ WORKLOADS = {
     # ragged-leaf case: 25M length-96 Gaussian-mixture series, midpoint splits
     "gm25m": dict(kind="gaussian_mixture", n=25_000_000, m=96, n_comp=1_000, spread=0.3,
                   seed_means=4001, seed_members=4002, capacity=10_000, split="midpoint",
-                  nq=4_096, q_seed=4003, sigma=0.1, ks=(1, 10, 50), target=0.99),
+                  nq=4_096, q_seed=4003, sigma=0.1, ks=(1, 10, 50), target=0.99, n_calib=500,
+                  calib_seed=4004, train_seed=4005, train_sigma=(0.05, 0.2)),
 }
