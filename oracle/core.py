@@ -729,6 +729,86 @@ def select_leaves(sizes, th: float, w: float, cM: float) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Leaf selection as a knapsack (Section "Leaf Node Selection", Equations 1-2)
+# ---------------------------------------------------------------------------
+
+def knapsack_01(values, weights, capacity: int) -> np.ndarray:
+    """Equation 1: the 0/1 knapsack, maximise sum v_i x_i subject to
+    sum w_i x_i <= capacity, solved exactly by dynamic programming over the
+    (non-negative integer) weights.  best[c] after item i is the largest value
+    of a subset of items 0..i of weight <= c; the chosen subset is read back
+    from the table.  Returns the chosen item indices, ascending."""
+    v = np.asarray(values, dtype=np.float64)
+    wt = np.asarray(weights, dtype=np.int64)
+    n = len(v)
+    C = int(capacity)
+    if n == 0 or C < 0:
+        return np.zeros(0, dtype=np.int64)
+    best = np.zeros((n + 1, C + 1))
+    for i in range(n):
+        best[i + 1] = best[i]
+        if wt[i] <= C:
+            cand = best[i, : C + 1 - wt[i]] + v[i]
+            best[i + 1, wt[i]:] = np.maximum(best[i, wt[i]:], cand)
+    chosen = []
+    c = C
+    for i in range(n - 1, -1, -1):
+        if best[i + 1, c] != best[i, c]:  # item i is needed for this optimum
+            chosen.append(i)
+            c -= wt[i]
+    return np.array(sorted(chosen), dtype=np.int64)
+
+
+def selection_estimates(lb: np.ndarray, leaf_d1: np.ndarray, order: np.ndarray):
+    """Per-leaf pruning probabilities for Equation 2, estimated on training
+    queries by following the exact 1-NN search (no filters) in visit order.
+
+    Reading (the paper leaves the estimator open): with d^bsf the best
+    distance over the leaves ahead of leaf i in the query's visit order,
+    p^lb_i is the share of queries whose bound prunes leaf i (d^lb > d^bsf),
+    and the ideal filter rate p^F*_i is the share of the remaining visits in
+    which leaf i holds nothing closer than d^bsf (d^L > d^bsf), i.e. what a
+    filter that predicts d^L exactly would prune (0 when no query reaches the
+    leaf).  lb, leaf_d1 [nq, N] by leaf id (leaf_d1 = node-wise 1-NN
+    distance d^L); order [nq, N].  Returns (p_lb, p_f_ideal), each [N]."""
+    nq, N = lb.shape
+    dbsf = bsf_before(leaf_d1[:, :, None], order, 1)
+    pruned = lb > dbsf
+    reached = ~pruned
+    ideal = reached & (leaf_d1 > dbsf)
+    p_lb = pruned.sum(axis=0) / nq
+    n_reach = reached.sum(axis=0)
+    p_f = np.where(n_reach > 0, ideal.sum(axis=0) / np.maximum(n_reach, 1), 0.0)
+    return p_lb, p_f
+
+
+def leaf_benefit(sizes, p_lb, p_f, tS: float, tF: float) -> np.ndarray:
+    """Equation 2: the expected search time a filter saves on leaf i,
+    b_i = (1 - p^lb_i) (p^F_i t^S |N_i| - t^F)."""
+    sizes = np.asarray(sizes, dtype=np.float64)
+    return (1.0 - np.asarray(p_lb, dtype=np.float64)) * (np.asarray(p_f, dtype=np.float64) * tS * sizes - tF)
+
+
+def select_knapsack(sizes, p_lb, p_f_ideal, a: float, tS: float, tF: float, w: int, cM: int):
+    """Leaf selection by Equations 1-2 with per-leaf estimates: p^F_i is the
+    ideal rate discounted by the hyperparameter a (p^F_i = p^F*_i / a, which
+    is Algorithm 3's p^F = 1 / a when every leaf's ideal rate is 1); leaves
+    with b_i <= 0 are never taken (they would slow the search); the rest go
+    into the knapsack of capacity c^M with weight w bytes per filter (one
+    architecture for all filters, so the weights are equal).  Returns
+    (selected leaf ids ordered by benefit, largest first, ties by leaf id;
+    b [N])."""
+    b = leaf_benefit(sizes, p_lb, np.asarray(p_f_ideal, dtype=np.float64) / a, tS, tF)
+    cand = np.flatnonzero(b > 0)
+    # equal weights: sum w x <= c^M is "at most floor(c^M / w) filters", so
+    # each filter weighs one unit (capacity beyond the candidates is unused)
+    cap = min(int(cM) // int(w), len(cand)) if w > 0 else len(cand)
+    chosen = cand[knapsack_01(b[cand], np.ones(len(cand), dtype=np.int64), cap)]
+    o = np.lexsort((chosen, -b[chosen]))
+    return chosen[o].astype(np.int64), b
+
+
+# ---------------------------------------------------------------------------
 # Quality measure (Section "Evaluation Setup", evaluation measures)
 # ---------------------------------------------------------------------------
 

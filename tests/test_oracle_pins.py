@@ -514,6 +514,109 @@ def test_select_leaves_cases():
     assert O.size_threshold(2.0, 46.0, 0.16) == pytest.approx(575.0)
 
 
+# ---------------------------------------------------------------- leaf selection as a knapsack (Equations 1-2)
+
+def test_knapsack_textbook_case():
+    # the classic three-item instance: the two heavier items beat the lightest pair
+    assert list(O.knapsack_01([60, 100, 120], [10, 20, 30], 50)) == [1, 2]
+    assert list(O.knapsack_01([60, 100, 120], [10, 20, 30], 0)) == []
+    assert list(O.knapsack_01([60, 100, 120], [10, 20, 30], 10)) == [0]
+    assert list(O.knapsack_01([5.0], [7], 6)) == []
+
+
+def test_knapsack_matches_brute_force():
+    rng = np.random.default_rng(21)
+    for _ in range(300):
+        n = int(rng.integers(1, 9))
+        v = rng.normal(1.0, 1.5, n)
+        wt = rng.integers(0, 7, n)
+        C = int(rng.integers(0, 16))
+        got = O.knapsack_01(v, wt, C)
+        assert wt[got].sum() <= C
+        best = max(sum(v[i] for i in range(n) if mask >> i & 1)
+                   for mask in range(1 << n) if sum(wt[i] for i in range(n) if mask >> i & 1) <= C)
+        assert v[got].sum() == pytest.approx(best, abs=1e-12)
+
+
+def test_knapsack_equal_weights_takes_the_largest_values():
+    rng = np.random.default_rng(22)
+    v = rng.normal(0.0, 1.0, 40)
+    for cap in (0, 1, 5, 17, 40):
+        got = O.knapsack_01(v, np.ones(40, dtype=np.int64), cap)
+        pos = np.flatnonzero(v > 0)
+        want = pos[np.argsort(-v[pos])][:cap]
+        assert set(got) == set(want)
+
+
+def test_selection_estimates_hand_case():
+    # two queries, three leaves; lb <= d^L everywhere
+    lb = np.array([[0.0, 1.0, 3.0], [0.5, 2.5, 0.1]])
+    dL = np.array([[2.0, 1.5, 4.0], [1.0, 3.0, 0.8]])
+    order = np.array([[0, 1, 2], [2, 0, 1]])
+    # query 0: leaf 0 (bsf inf) -> 2.0; leaf 1 reached (1.5 < 2.0) -> 1.5; leaf 2 pruned (3.0 > 1.5)
+    # query 1: leaf 2 (bsf inf) -> 0.8; leaf 0 reached, nothing below 0.8 (ideal prune); leaf 1 pruned
+    p_lb, p_f = O.selection_estimates(lb, dL, order)
+    assert list(p_lb) == [0.0, 0.5, 0.5]
+    assert list(p_f) == [0.5, 0.0, 0.0]
+
+
+def test_selection_estimates_equal_the_search_simulation():
+    """p^lb is the share of queries whose exact sequential search (Algorithm 2,
+    no filters) prunes the leaf by its bound; the ideal filter rate is the
+    share of its visits that Algorithm 2 with exact filters (d^F = d^L)
+    prunes by the filter: exact filters prune only leaves holding nothing
+    better, so the best-so-far sequence is unchanged."""
+    rng = np.random.default_rng(23)
+    nq, N = 30, 12
+    dL = rng.uniform(1.0, 10.0, (nq, N))
+    lb = dL * rng.uniform(0.0, 1.0, (nq, N))
+    order = O.visit_order(lb)
+    p_lb, p_f = O.selection_estimates(lb, dL, order)
+    ids = np.arange(nq * N, dtype=np.int64).reshape(nq, N, 1)
+    plain = O.leafi_search(lb, order, dL[:, :, None], ids, 1, schedule=(1,))
+    assert np.array_equal(p_lb, plain.lb_pruned.mean(axis=0))
+    filt = O.leafi_search(lb, order, dL[:, :, None], ids, 1, has_filter=np.ones(N, dtype=bool), dF=dL,
+                          schedule=(1,))
+    assert np.array_equal(filt.lb_pruned, plain.lb_pruned)
+    assert np.array_equal(filt.ids, plain.ids)
+    reach = (~plain.lb_pruned).sum(axis=0)
+    want = np.where(reach > 0, filt.f_pruned.sum(axis=0) / np.maximum(reach, 1), 0.0)
+    assert np.array_equal(p_f, want)
+
+
+def test_leaf_benefit_hand_case():
+    # (1 - 0.25) * (0.5 * 2 * 100 - 30) = 52.5; a tiny leaf loses time
+    b = O.leaf_benefit([100, 10], [0.25, 0.0], [0.5, 0.5], 2.0, 30.0)
+    assert b[0] == pytest.approx(52.5) and b[1] == pytest.approx(-20.0)
+
+
+def test_select_knapsack_reduces_to_algorithm3_under_uniform_rates():
+    """With the same p^lb everywhere and ideal filters everywhere (p^F = 1/a),
+    b_i > 0 is |N_i| > a t^F / t^S and b grows with |N_i|: the knapsack picks
+    Algorithm 3's leaves, in its order (sizes kept off the threshold)."""
+    rng = np.random.default_rng(24)
+    for trial in range(20):
+        N = 60
+        sizes = rng.choice(np.arange(1, 400), N, replace=False)
+        sizes = sizes[sizes != 100]
+        a, tS, tF = 2.0, 1e-3, 0.05        # th = a tF / tS = 100
+        w, cM = 10, int(rng.integers(0, 400))
+        sel, b = O.select_knapsack(sizes, np.full(len(sizes), 0.3), np.ones(len(sizes)), a, tS, tF, w, cM)
+        want = O.select_leaves(sizes, O.size_threshold(a, tF, tS), w, cM)
+        assert list(sel) == list(want)
+
+
+def test_select_knapsack_uses_per_leaf_rates():
+    # the largest leaf is always pruned by its bound (no benefit); the filter
+    # of leaf 2 would prune nothing; the budget holds two filters
+    sizes = np.array([1000, 500, 800, 300])
+    p_lb = np.array([1.0, 0.2, 0.1, 0.1])
+    p_f = np.array([1.0, 1.0, 0.0, 0.9])
+    sel, b = O.select_knapsack(sizes, p_lb, p_f, 2.0, 1.0, 10.0, 4, 8)
+    assert b[0] == 0.0 and b[2] < 0
+    assert list(sel) == [1, 3]
+
+
 # ---------------------------------------------------------------- recall
 
 def test_recall_at_k_hand_cases():
