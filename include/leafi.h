@@ -168,13 +168,24 @@ typedef struct {
   int32_t patience;      /* epochs without validation improvement before lr /= 10 */
   uint64_t seed;
   int32_t keep_examples; /* 1: keep the training queries and targets for leafi_get_examples */
-  int32_t reserved;
+  int32_t selection;     /* LEAFI_SELECT_SIZE (Algorithm 3) or LEAFI_SELECT_KNAPSACK (Equations 1-2) */
 } leafi_train_opts;
+
+/* Leaf selection rules of leafi_train_filters (opts.selection).
+ * SIZE: Algorithm 3 - leaves of size >= th = a t^F / t^S, largest first,
+ *   while the filters fit in mem_budget (th_override replaces th).
+ * KNAPSACK: Equation 1 with the benefit of Equation 2 estimated per leaf on
+ *   the global training queries, as leafi_select_knapsack computes it, with
+ *   t^F and t^S measured, or, when th_override >= 0, with the ratio
+ *   t^F / t^S = th_override / a (the benefits' signs and order depend on the
+ *   ratio alone). */
+#define LEAFI_SELECT_SIZE 0
+#define LEAFI_SELECT_KNAPSACK 1
 
 /* Fill opts with the defaults listed above (n_global 1500, n_local 500,
  * noise 0.1..0.4, a 2, val 0.2, th measured, budget 8 GiB, h = m, 1000
  * epochs, lr 0.01 -> 1e-5, batch 64, patience 10, seed 1, examples not
- * kept). */
+ * kept, selection SIZE). */
 void leafi_default_train_opts(leafi_train_opts *opts);
 
 typedef struct {
@@ -189,7 +200,8 @@ typedef struct {
 } leafi_train_report;
 
 /*
- * Algorithm 1: select leaves (Algorithm 3), generate global and local
+ * Algorithm 1: select leaves (Algorithm 3, or the knapsack of Equations 1-2
+ * per opts.selection), generate global and local
  * training queries (collection series plus Gaussian noise), compute their
  * node-wise nearest-neighbour distances d^L with the leaf scan, and train one
  * MLP per selected leaf by SGD on the mean squared error.  `report` may be
@@ -526,6 +538,33 @@ int leafi_mlp_sgd_step(float *weights_dev, int32_t n_filters, int32_t m, int32_t
  * (distance, id), empty slots -1 / +inf.  d_dev[q, L, 0] is d^L(q, L). */
 int leafi_leaf_knn(leafi_index *index, const float *queries_dev, int64_t nq, int32_t k, float *d_dev,
                    int64_t *ids_dev, void *stream);
+
+/*
+ * Leaf selection as a knapsack (paper: Section "Leaf Node Selection",
+ * Equations 1-2; the per-leaf rates are the estimates that section leaves
+ * open).  For n_queries raw training queries (device, [n_queries, m] fp32)
+ * each query's exact 1-NN search (no filters) is followed in its visit
+ * order, with the index's summary bounds d^lb and the node-wise 1-NN
+ * distances d^L from the leaf scan; d^bsf is the best distance over the
+ * leaves ahead of leaf i.  Per leaf i:
+ *   p_lb[i] = share of queries with d^lb > d^bsf (the bound prunes leaf i);
+ *   p_f[i]  = share of the remaining visits with d^L > d^bsf (what a filter
+ *             predicting d^L exactly prunes; 0 if no query reaches leaf i);
+ *   benefit[i] = b_i = (1 - p_lb[i]) (p_f[i] / a * t^S * |N_i| - t^F).
+ * The knapsack (capacity mem_budget bytes, one filter of the hidden width
+ * weighs 4 (h m + 2 h + 1) bytes, hidden 0 = m) takes the leaves with
+ * b_i > 0, largest first (ties by leaf id), at most floor(mem_budget /
+ * weight) of them: with equal weights that is the exact optimum.
+ * t_filter_s / t_series_s: t^F and t^S in seconds; either <= 0: both are
+ * measured on this GPU as leafi_train_filters measures them.
+ * Outputs (host, each may be NULL): leaf_ids [n_leaves capacity] the
+ * selection in that order, *n_selected its length, benefit, p_lb and p_f
+ * [n_leaves].  Installs nothing.
+ */
+int leafi_select_knapsack(leafi_index *index, const float *queries_dev, int64_t n_queries, float a,
+                          double t_filter_s, double t_series_s, int32_t hidden, int64_t mem_budget,
+                          int32_t *leaf_ids_host, int32_t *n_selected, double *benefit_host, double *p_lb_host,
+                          double *p_f_host, void *stream);
 
 #ifdef __cplusplus
 }

@@ -147,11 +147,16 @@ class Index:
 
     # -------------------------------------------------------------- filters
     def train_filters(self, **kw) -> dict:
+        """Algorithm 1 (leafi_train_filters); options are leafi_train_opts
+        fields, with selection given as "size" (Algorithm 3) or "knapsack"
+        (Equations 1-2)."""
         o = _lib.TrainOpts()
         load().leafi_default_train_opts(ctypes.byref(o))
         for k, v in kw.items():
             if not hasattr(o, k):
                 raise TypeError(f"unknown training option {k}")
+            if k == "selection" and isinstance(v, str):
+                v = {"size": _lib.LEAFI_SELECT_SIZE, "knapsack": _lib.LEAFI_SELECT_KNAPSACK}[v]
             setattr(o, k, v)
         r = _lib.TrainReport()
         check(load().leafi_train_filters(self._h, ctypes.byref(o), ctypes.byref(r), _stream()))
@@ -368,6 +373,24 @@ class Index:
         check(load().leafi_lower_bounds(self._h, _dev(queries, torch.float32, "queries"), nq,
                                         _dev(lb, torch.float32, "lb"), _stream()))
         return lb
+
+    def select_knapsack(self, queries, a: float = 2.0, t_filter: float = 0.0, t_series: float = 0.0,
+                        hidden: int = 0, mem_budget: int = 8 << 30) -> dict:
+        """Leaf selection as a knapsack (leafi_select_knapsack) over raw
+        training queries (device [nq, m] fp32): the selected leaves (by
+        benefit, largest first) and per leaf the benefit b, p_lb and the ideal
+        filter rate p_f.  t_filter / t_series <= 0: measured on this GPU."""
+        torch = _torch()
+        nq = queries.shape[0]
+        N = self.info()["n_leaves"]
+        ids = np.zeros(N, dtype=np.int32)
+        ns = ctypes.c_int32()
+        b, pl, pf = (np.zeros(N, dtype=np.float64) for _ in range(3))
+        check(load().leafi_select_knapsack(self._h, _dev(queries, torch.float32, "queries"), nq, a, t_filter, t_series,
+                                           hidden, mem_budget, ids.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ns),
+                                           b.ctypes.data_as(ctypes.c_void_p), pl.ctypes.data_as(ctypes.c_void_p),
+                                           pf.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return {"leaves": ids[:ns.value].copy(), "benefit": b, "p_lb": pl, "p_f": pf}
 
     def leaf_knn(self, queries, k: int):
         torch = _torch()

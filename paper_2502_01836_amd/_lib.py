@@ -25,6 +25,8 @@ LEAFI_SEARCH_FILTER_TILE_LARGE = 8
 LEAFI_CALIB_STEP = 0
 LEAFI_CALIB_STEFFEN = 1
 LEAFI_CALIB_NO_CORRECTION = 2
+LEAFI_SELECT_SIZE = 0
+LEAFI_SELECT_KNAPSACK = 1
 
 
 class LeafiError(RuntimeError):
@@ -51,7 +53,7 @@ class TrainOpts(ctypes.Structure):
                 ("th_override", ctypes.c_double), ("mem_budget", ctypes.c_int64), ("hidden", ctypes.c_int32),
                 ("max_epochs", ctypes.c_int32), ("lr0", ctypes.c_float), ("lr_min", ctypes.c_float),
                 ("batch", ctypes.c_int32), ("patience", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("keep_examples", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("keep_examples", ctypes.c_int32), ("selection", ctypes.c_int32)]
 
 
 class TrainReport(ctypes.Structure):
@@ -153,6 +155,8 @@ SIGNATURES = [
     ("leafi_mlp_infer", ctypes.c_int, [P, I32, I32, I32, P, I64, P, P]),
     ("leafi_mlp_sgd_step", ctypes.c_int, [P, I32, I32, I32, P, P, I32, F32, P, P]),
     ("leafi_leaf_knn", ctypes.c_int, [P, P, I64, I32, P, P, P]),
+    ("leafi_select_knapsack", ctypes.c_int, [P, P, I64, ctypes.c_float, ctypes.c_double, ctypes.c_double, I32, I64,
+                                             P, P, P, P, P, P]),
 ]
 
 _lib = None

@@ -1243,6 +1243,105 @@ void leafi_default_train_opts(leafi_train_opts *o) {
   o->seed = 1;
 }
 
+// Algorithm 3's measured costs: t^F, the amortised time of one (query,
+// filter) inference in a batch, and t^S, of one (query, series) distance in
+// the batched scan with one query group per leaf (the search regime).  The
+// probe queries' rows are drawn from rng.
+static void measure_costs(leafi_index *ix, int h, uint64_t seed, std::mt19937_64 &rng, hipStream_t st, double *t_filter,
+                          double *t_series) {
+  const int m = ix->m, N = ix->N;
+  const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
+  const int qf = 1024, ff = std::min(N, 64);
+  DevBuf<float> wp(static_cast<size_t>(ff) * P), xp(static_cast<size_t>(qf) * m), outp(static_cast<size_t>(qf) * ff);
+  fill_f32(wp.get(), wp.size(), 0.01f, st);
+  fill_f32(xp.get(), xp.size(), 0.5f, st);
+  launch_mlp_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);  // warm-up
+  hipEvent_t a, b;
+  HIP_OK(hipEventCreate(&a));
+  HIP_OK(hipEventCreate(&b));
+  HIP_OK(hipEventRecord(a, st));
+  launch_mlp_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);
+  HIP_OK(hipEventRecord(b, st));
+  HIP_OK(hipEventSynchronize(b));
+  float msf = 0;
+  HIP_OK(hipEventElapsedTime(&msf, a, b));
+  *t_filter = msf * 1e-3 / (static_cast<double>(qf) * ff);
+  // scan probe: 32 training-like queries against every leaf
+  const int qs = 32;
+  std::vector<int64_t> prow(qs);
+  std::vector<float> psig(qs, 0.1f);
+  for (int j = 0; j < qs; ++j) {
+    int L = static_cast<int>(rng() % N);
+    prow[j] = ix->h_leaf_off[L] + static_cast<int64_t>(rng() % ix->h_leaf_n[L]);
+  }
+  DevBuf<int64_t> drow(qs);
+  DevBuf<float> dsig(qs), qraw(static_cast<size_t>(qs) * m);
+  h2d(drow.get(), prow.data(), qs, st);
+  h2d(dsig.get(), psig.data(), qs, st);
+  launch_make_queries(ix->x32.get(), drow.get(), dsig.get(), qs, m, seed ^ 0x5eed, qraw.get(), st);
+  ensure_queries(ix, qs, 1);
+  prep_queries(ix, qraw.get(), qs, st);
+  DevBuf<float> pd(static_cast<size_t>(qs) * N);
+  DevBuf<int64_t> pi(static_cast<size_t>(qs) * N);
+  Timing tmp;
+  leaf_knn_prepared(ix, qs, 1, pd.get(), pi.get(), st, &tmp);
+  *t_series = tmp.scan_ms * 1e-3 / (static_cast<double>(qs) * ix->n);
+  HIP_OK(hipEventDestroy(a));
+  HIP_OK(hipEventDestroy(b));
+}
+
+// Per-leaf rates for the knapsack selection, from nq raw queries (device):
+// each query's exact 1-NN search in visit order (bounds and node-wise 1-NN
+// distances d^L from the leaf scan); p_lb[i] = share of queries whose bound
+// prunes leaf i (d^lb > d^bsf), p_f[i] = share of the other visits with
+// d^L > d^bsf (what an exact filter prunes; 0 if no query reaches leaf i).
+static void selection_estimates(leafi_index *ix, const float *raw, int64_t nq, hipStream_t st, std::vector<double> *p_lb,
+                                std::vector<double> *p_f) {
+  const int N = ix->N, m = ix->m;
+  std::vector<int64_t> pruned(N, 0), reached(N, 0), ideal(N, 0);
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t(1) << 22) / N));
+  std::vector<float> hlb, hd;
+  std::vector<int32_t> hord;
+  DevBuf<float> dd;
+  DevBuf<int64_t> di;
+  for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
+    const int64_t nc = std::min(chunk, nq - q0);
+    const size_t cells = static_cast<size_t>(nc) * N;
+    ensure_queries(ix, nc, 1);
+    prep_queries(ix, raw + q0 * m, nc, st);
+    hlb.resize(cells);
+    hord.resize(cells);
+    hd.resize(cells);
+    d2h(hlb.data(), ix->ws.lb.get(), cells, st);
+    d2h(hord.data(), ix->ws.order.get(), cells, st);
+    dd.reserve(cells);
+    di.reserve(cells);
+    leaf_knn_prepared(ix, nc, 1, dd.get(), di.get(), st, nullptr);
+    d2h(hd.data(), dd.get(), cells, st);
+    HIP_OK(hipStreamSynchronize(st));
+    for (int64_t c = 0; c < nc; ++c) {
+      double bsf = INFINITY;
+      for (int pos = 0; pos < N; ++pos) {
+        const int L = hord[c * N + pos];
+        const double lbv = hlb[c * N + L], dl = hd[c * N + L];
+        if (lbv > bsf) {
+          ++pruned[L];
+        } else {
+          ++reached[L];
+          if (dl > bsf) ++ideal[L];
+        }
+        bsf = std::min(bsf, dl);
+      }
+    }
+  }
+  p_lb->assign(N, 0.0);
+  p_f->assign(N, 0.0);
+  for (int L = 0; L < N; ++L) {
+    (*p_lb)[L] = static_cast<double>(pruned[L]) / static_cast<double>(nq);
+    (*p_f)[L] = reached[L] > 0 ? static_cast<double>(ideal[L]) / static_cast<double>(reached[L]) : 0.0;
+  }
+}
+
 static void install_filters(leafi_index *ix, int F, int h, const std::vector<int32_t> &leaves, hipStream_t st) {
   ix->examples = Examples();
   ix->filt.F = F;
@@ -1305,6 +1404,9 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     LEAFI_CHECK_ARG(o->lr0 > 0 && o->lr_min > 0, "learning rates must be > 0");
     const int h = o->hidden > 0 ? o->hidden : ix->m;
     LEAFI_CHECK_ARG(h <= 256 && h % 4 == 0, "training supports hidden <= 256, a multiple of 4");
+    LEAFI_CHECK_ARG(o->selection == LEAFI_SELECT_SIZE || o->selection == LEAFI_SELECT_KNAPSACK,
+                    "selection must be LEAFI_SELECT_SIZE or LEAFI_SELECT_KNAPSACK");
+    LEAFI_CHECK_ARG(o->a > 0, "a must be > 0");
     hipStream_t st = as_stream(stream);
     Workspace &w = ix->ws;
     const int m = ix->m, N = ix->N;
@@ -1313,54 +1415,49 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     std::memset(&report, 0, sizeof(report));
     std::mt19937_64 rng(o->seed);
 
-    // ---- Algorithm 3: size threshold and greedy selection
+    // ---- leaf selection: Algorithm 3 (size threshold, greedy by size) or
+    // the knapsack of Equations 1-2 with per-leaf rates estimated on the
+    // global training queries
+    const bool knap = o->selection == LEAFI_SELECT_KNAPSACK;
     double th = o->th_override;
+    // the knapsack's benefits in units of t^S when th_override fixes the
+    // ratio t^F / t^S = th / a (their signs and order depend on it alone)
+    double kn_tF = th / o->a, kn_tS = 1.0;
     if (th < 0) {
-      // t^F: amortised time of one (query, filter) inference in a batch;
-      // t^S: amortised time of one (query, series) distance in the batched
-      // scan with one query group per leaf (the search regime).
-      const int qf = 1024, ff = std::min(N, 64);
-      DevBuf<float> wp(static_cast<size_t>(ff) * P), xp(static_cast<size_t>(qf) * m), outp(static_cast<size_t>(qf) * ff);
-      fill_f32(wp.get(), wp.size(), 0.01f, st);
-      fill_f32(xp.get(), xp.size(), 0.5f, st);
-      launch_mlp_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);  // warm-up
-      hipEvent_t a, b;
-      HIP_OK(hipEventCreate(&a));
-      HIP_OK(hipEventCreate(&b));
-      HIP_OK(hipEventRecord(a, st));
-      launch_mlp_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);
-      HIP_OK(hipEventRecord(b, st));
-      HIP_OK(hipEventSynchronize(b));
-      float msf = 0;
-      HIP_OK(hipEventElapsedTime(&msf, a, b));
-      report.t_filter_s = msf * 1e-3 / (static_cast<double>(qf) * ff);
-      // scan probe: 32 training-like queries against every leaf
-      const int qs = 32;
-      std::vector<int64_t> prow(qs);
-      std::vector<float> psig(qs, 0.1f);
-      for (int j = 0; j < qs; ++j) {
-        int L = static_cast<int>(rng() % N);
-        prow[j] = ix->h_leaf_off[L] + static_cast<int64_t>(rng() % ix->h_leaf_n[L]);
-      }
-      DevBuf<int64_t> drow(qs);
-      DevBuf<float> dsig(qs), qraw(static_cast<size_t>(qs) * m);
-      h2d(drow.get(), prow.data(), qs, st);
-      h2d(dsig.get(), psig.data(), qs, st);
-      launch_make_queries(ix->x32.get(), drow.get(), dsig.get(), qs, m, o->seed ^ 0x5eed, qraw.get(), st);
-      ensure_queries(ix, qs, 1);
-      prep_queries(ix, qraw.get(), qs, st);
-      DevBuf<float> pd(static_cast<size_t>(qs) * N);
-      DevBuf<int64_t> pi(static_cast<size_t>(qs) * N);
-      Timing tmp;
-      leaf_knn_prepared(ix, qs, 1, pd.get(), pi.get(), st, &tmp);
-      report.t_series_s = tmp.scan_ms * 1e-3 / (static_cast<double>(qs) * ix->n);
-      HIP_OK(hipEventDestroy(a));
-      HIP_OK(hipEventDestroy(b));
+      measure_costs(ix, h, o->seed, rng, st, &report.t_filter_s, &report.t_series_s);
       th = report.t_series_s > 0 ? o->a * report.t_filter_s / report.t_series_s : 0.0;
+      kn_tF = report.t_filter_s;
+      kn_tS = report.t_series_s;
     }
     report.th = th;
-    std::vector<int32_t> sel = select_leaves(ix->h_leaf_n, th, static_cast<double>(P) * 4.0,
-                                             static_cast<double>(o->mem_budget));
+    // the global training queries' rows and noise levels (drawn before the
+    // selection: the knapsack estimates its rates on them)
+    const int n_g = o->n_global, n_l = o->n_local;
+    std::uniform_real_distribution<double> unif(o->noise_lo, o->noise_hi);
+    std::vector<int64_t> cum(N + 1, 0);
+    for (int L = 0; L < N; ++L) cum[L + 1] = cum[L] + ix->h_leaf_n[L];
+    std::vector<int64_t> rows(n_g);
+    std::vector<float> sig(n_g);
+    for (int j = 0; j < n_g; ++j) {  // uniform over the collection
+      int64_t u = static_cast<int64_t>(rng() % static_cast<uint64_t>(ix->n));
+      int L = static_cast<int>(std::upper_bound(cum.begin(), cum.end(), u) - cum.begin()) - 1;
+      rows[j] = ix->h_leaf_off[L] + (u - cum[L]);
+      sig[j] = static_cast<float>(unif(rng));
+    }
+    std::vector<int32_t> sel;
+    if (knap) {
+      DevBuf<int64_t> grows(n_g);
+      DevBuf<float> gsig(n_g), graw(static_cast<size_t>(n_g) * m);
+      h2d(grows.get(), rows.data(), n_g, st);
+      h2d(gsig.get(), sig.data(), n_g, st);
+      launch_make_queries(ix->x32.get(), grows.get(), gsig.get(), n_g, m, o->seed, graw.get(), st);
+      std::vector<double> p_lb, p_f;
+      selection_estimates(ix, graw.get(), n_g, st, &p_lb, &p_f);
+      sel = select_knapsack(ix->h_leaf_n, p_lb, p_f, o->a, kn_tS, kn_tF, static_cast<double>(P) * 4.0,
+                            static_cast<double>(o->mem_budget), nullptr);
+    } else {
+      sel = select_leaves(ix->h_leaf_n, th, static_cast<double>(P) * 4.0, static_cast<double>(o->mem_budget));
+    }
     const int F = static_cast<int>(sel.size());
     install_filters(ix, F, h, sel, st);
     ix->filt.w.alloc(static_cast<size_t>(std::max(F, 1)) * P);
@@ -1372,21 +1469,11 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     }
 
     // ---- training queries: global (train + validation) and local per filter
-    const int n_g = o->n_global, n_l = o->n_local;
     const int n_gv = std::max(1, static_cast<int>(std::lround(o->val_fraction * n_g)));
     const int n_gt = n_g - n_gv;
     const int64_t nqt = n_g + static_cast<int64_t>(F) * n_l;
-    std::vector<int64_t> rows(nqt);
-    std::vector<float> sig(nqt);
-    std::uniform_real_distribution<double> unif(o->noise_lo, o->noise_hi);
-    std::vector<int64_t> cum(N + 1, 0);
-    for (int L = 0; L < N; ++L) cum[L + 1] = cum[L] + ix->h_leaf_n[L];
-    for (int j = 0; j < n_g; ++j) {  // uniform over the collection
-      int64_t u = static_cast<int64_t>(rng() % static_cast<uint64_t>(ix->n));
-      int L = static_cast<int>(std::upper_bound(cum.begin(), cum.end(), u) - cum.begin()) - 1;
-      rows[j] = ix->h_leaf_off[L] + (u - cum[L]);
-      sig[j] = static_cast<float>(unif(rng));
-    }
+    rows.resize(nqt);
+    sig.resize(nqt);
     for (int f = 0; f < F; ++f) {  // uniform over the filtered leaf
       int L = sel[f];
       for (int j = 0; j < n_l; ++j) {
@@ -1865,6 +1952,37 @@ int leafi_leaf_knn(leafi_index *ix, const float *queries, int64_t nq, int32_t k,
     ensure_queries(ix, nq, k);
     prep_queries(ix, queries, nq, st);
     leaf_knn_prepared(ix, nq, k, d, ids, st, nullptr);
+  });
+}
+
+int leafi_select_knapsack(leafi_index *ix, const float *queries, int64_t nq, float a, double t_filter_s,
+                          double t_series_s, int32_t hidden, int64_t mem_budget, int32_t *leaf_ids, int32_t *n_selected,
+                          double *benefit, double *p_lb, double *p_f, void *stream) {
+  return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
+    require_built(ix);
+    check_queries(ix, queries, nq);
+    LEAFI_CHECK_ARG(nq >= 1, "need at least one query");
+    LEAFI_CHECK_ARG(a > 0, "a must be > 0");
+    LEAFI_CHECK_ARG(mem_budget >= 0, "mem_budget must be >= 0");
+    const int h = hidden > 0 ? hidden : ix->m;
+    LEAFI_CHECK_ARG(h <= 256 && h % 4 == 0, "hidden must be <= 256, a multiple of 4");
+    hipStream_t st = as_stream(stream);
+    double tF = t_filter_s, tS = t_series_s;
+    if (!(tF > 0) || !(tS > 0)) {
+      std::mt19937_64 rng(1);
+      measure_costs(ix, h, 1, rng, st, &tF, &tS);
+    }
+    std::vector<double> pl, pf, b;
+    selection_estimates(ix, queries, nq, st, &pl, &pf);
+    const double wbytes = 4.0 * (static_cast<double>(h) * ix->m + 2 * h + 1);
+    std::vector<int32_t> sel = select_knapsack(ix->h_leaf_n, pl, pf, a, tS, tF, wbytes,
+                                               static_cast<double>(mem_budget), &b);
+    if (n_selected) *n_selected = static_cast<int32_t>(sel.size());
+    if (leaf_ids) std::copy(sel.begin(), sel.end(), leaf_ids);
+    if (benefit) std::copy(b.begin(), b.end(), benefit);
+    if (p_lb) std::copy(pl.begin(), pl.end(), p_lb);
+    if (p_f) std::copy(pf.begin(), pf.end(), p_f);
   });
 }
 

@@ -39,11 +39,20 @@ TreeResult build_isax_tree(const std::vector<float> &seg_mu, int64_t n, int S, i
 std::vector<float> leaf_boxes(const std::vector<float> &seg_mu, const std::vector<float> &seg_sd, int S,
                               const TreeResult &t);
 
-// ---- leaf selection (select.cpp) ---------------------------------------------
+// ---- leaf selection (tree.cpp) -----------------------------------------------
 
 // Algorithm 3: leaves by size (largest first, ties by id) with size >= th
 // while the filters fit in cM bytes.
 std::vector<int32_t> select_leaves(const std::vector<int64_t> &sizes, double th, double w, double cM);
+
+// Equations 1-2: the benefit b_i = (1 - p^lb_i) (p^F_i t^S |N_i| - t^F) with
+// p^F_i = p_f[i] / a (p_f: the ideal filter rate), and the 0/1 knapsack of
+// capacity cM over filters of w bytes each: the leaves with b_i > 0 by
+// benefit (largest first, ties by id), at most floor(cM / w) of them.
+// benefit (optional) receives b [N].
+std::vector<int32_t> select_knapsack(const std::vector<int64_t> &sizes, const std::vector<double> &p_lb,
+                                     const std::vector<double> &p_f, double a, double tS, double tF, double w,
+                                     double cM, std::vector<double> *benefit);
 
 // ---- calibration (calib.cpp) ---------------------------------------------------
 

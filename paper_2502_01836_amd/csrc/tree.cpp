@@ -392,4 +392,23 @@ std::vector<int32_t> select_leaves(const std::vector<int64_t> &sizes, double th,
   return sel;
 }
 
+std::vector<int32_t> select_knapsack(const std::vector<int64_t> &sizes, const std::vector<double> &p_lb,
+                                     const std::vector<double> &p_f, double a, double tS, double tF, double w,
+                                     double cM, std::vector<double> *benefit) {
+  const size_t N = sizes.size();
+  std::vector<double> b(N);
+  std::vector<int32_t> cand;
+  for (size_t i = 0; i < N; ++i) {
+    b[i] = (1.0 - p_lb[i]) * (p_f[i] / a * tS * static_cast<double>(sizes[i]) - tF);
+    if (b[i] > 0.0) cand.push_back(static_cast<int32_t>(i));
+  }
+  // Every filter weighs w bytes, so the knapsack holds floor(c^M / w) of
+  // them and its optimum is that many of the largest positive benefits.
+  std::stable_sort(cand.begin(), cand.end(), [&](int32_t x, int32_t y) { return b[x] > b[y]; });
+  const double room = w > 0.0 ? std::floor(cM / w) : static_cast<double>(cand.size());
+  if (room < static_cast<double>(cand.size())) cand.resize(room > 0.0 ? static_cast<size_t>(room) : 0);
+  if (benefit) *benefit = std::move(b);
+  return cand;
+}
+
 }  // namespace leafi
