@@ -161,6 +161,80 @@ def recall_rows(got_ids, got_d, want_ids, want_d, k):
     return out
 
 
+ABLATION_TARGETS = (0.95, 0.97, 0.99, 0.995, 0.999)
+
+
+def ablation(workloads, a):
+    """Local training data off and on (n_local 0 / 500) x recall targets
+    0.95 ... 0.999, per workload: training and calibration as in the
+    benchmark, then every test batch searched at one target for all its
+    queries (k = the workload's first k).  Per row: queries/s (best of three
+    passes over the batches), recall against the exact (filters-off) search,
+    series pruned and leaves pruned by filters.  One JSON line."""
+    import torch
+    import workloads as W
+    import paper_2502_01836_amd as pkg
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pkg.load()
+    dev = torch.device("cuda:0")
+    sched = tuple(int(x) for x in a.schedule.split(","))
+    out = []
+    for name in workloads:
+        wl = W.WORKLOADS[name]
+        n, m = wl["n"], wl["m"]
+        t0 = time.time()
+        raw_d, raw, _ = make_collection(wl, dev)
+        calib, batches, _, _, ks, _, sig_desc = make_queries(wl, raw_d, raw)
+        ix = pkg.Index()
+        ix.build(raw_d, leaf_capacity=wl["capacity"], n_segments=wl.get("segments", 16),
+                 split_rule=wl.get("split", "median"))
+        del raw_d, raw
+        torch.cuda.empty_cache()
+        k = int(ks[0])
+        exact = []
+        for q in batches:
+            ids, d = ix.search(q, k=k, use_filters=False, schedule=sched)
+            exact.append((ids.cpu().numpy(), d.cpu().numpy().astype(np.float64)))
+        log(f"ablation {name}: data, index and exact answers in {time.time() - t0:.1f}s")
+        for n_local in (0, 500):
+            rep = ix.train_filters(n_global=1500, n_local=n_local, noise_lo=wl["train_sigma"][0],
+                                   noise_hi=wl["train_sigma"][1], a=2.0, max_epochs=a.max_epochs,
+                                   seed=wl["train_seed"])
+            ix.calibrate(calib, [k], list(ABLATION_TARGETS))
+            for t in ABLATION_TARGETS:
+                got, st_all = [], []
+                for q in batches:
+                    ids, d, st = ix.search(q, k=k, target=t, use_filters=True, schedule=sched, with_stats=True)
+                    got.append((ids.cpu().numpy(), d.cpu().numpy().astype(np.float64)))
+                    st_all.append(st)
+                best = None
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    s0 = time.perf_counter()
+                    for q in batches:
+                        ix.search(q, k=k, target=t, use_filters=True, schedule=sched)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - s0
+                    best = dt if best is None else min(best, dt)
+                nq_all = sum(len(q) for q in batches)
+                rec = float(np.concatenate([recall_rows(g[0], g[1], e[0], e[1], k)
+                                            for g, e in zip(got, exact)]).mean())
+                pruned = 1.0 - sum(s["series_scanned"] for s in st_all) / (nq_all * n)
+                row = {"workload": name, "local": n_local > 0, "n_local": n_local, "n_filters": rep["n_filters"],
+                       "k": k, "target": t, "recall_vs_exact_search": rec, "target_met": rec >= t,
+                       "queries_per_s": nq_all / best, "series_pruning_ratio": pruned,
+                       "leaves_filter_pruned": int(sum(s["leaves_filter_pruned"] for s in st_all)),
+                       "queries": nq_all}
+                out.append(row)
+                log(f"ablation {name} {'+' if n_local else '-'}Local target {t}: recall {rec:.4f}, "
+                    f"{row['queries_per_s']:.0f} queries/s, series pruned {pruned:.4f}")
+        del ix
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "recall and queries/s per recall target, without and with local training data",
+                      "unit": "queries/s", "data": "synthetic", "n_gpus": 1, "schedule": list(sched),
+                      "rows": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,11 +255,17 @@ def main():
                     help="collection rows the one-thread oracle sample scans (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for hardware byte counters)")
+    ap.add_argument("--ablation", default="",
+                    help="instead of the benchmark: the local-data ablation and recall-target sweep on these "
+                         "workloads (comma-separated, e.g. rw1m,rw10m); prints its own JSON line")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU layout is a design "
               "note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if a.ablation:
+        ablation([w for w in a.ablation.split(",") if w], a)
+        return
 
     import torch
     import workloads as W
