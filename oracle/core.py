@@ -471,6 +471,88 @@ def mlp_mse_grad(w: np.ndarray, X: np.ndarray, y: np.ndarray, m: int, h: int):
 
 
 # ---------------------------------------------------------------------------
+# Learned filter: two-layer 1-D CNN (Section "Varying Model Type": two
+# convolutional layers, kernel size 3, latent channels equal to the series
+# length).  Readings where the paper is silent: both layers are
+# cross-correlations over the series positions with one zero of padding at
+# each end (output length = input length), each followed by ReLU, and the
+# prediction is a linear readout of the second layer's channels averaged over
+# the positions.
+# ---------------------------------------------------------------------------
+
+def cnn_param_count(C: int) -> int:
+    """Floats of a packed CNN filter with C channels:
+    [W1 (C, 3) | b1 (C) | W2 (C_out, C_in, 3) | b2 (C) | w3 (C) | b3]."""
+    return 3 * C + C + 3 * C * C + C + C + 1
+
+
+def unpack_cnn(w: np.ndarray, C: int):
+    w = np.asarray(w, dtype=np.float64)
+    o = 0
+    W1 = w[o: o + 3 * C].reshape(C, 3); o += 3 * C
+    b1 = w[o: o + C]; o += C
+    W2 = w[o: o + 3 * C * C].reshape(C, C, 3); o += 3 * C * C
+    b2 = w[o: o + C]; o += C
+    w3 = w[o: o + C]; o += C
+    b3 = w[o]
+    return W1, b1, W2, b2, w3, b3
+
+
+def _cnn_layers(w, X, C):
+    """Pre-activations z1 [B, C, m], z2 [B, C, m] for query rows X [B, m]."""
+    W1, b1, W2, b2, w3, b3 = unpack_cnn(w, C)
+    X = np.asarray(X, dtype=np.float64)
+    B, m = X.shape
+    xp = np.zeros((B, m + 2))
+    xp[:, 1:m + 1] = X
+    # tap t reads position p + t - 1
+    z1 = b1[None, :, None] + sum(W1[None, :, t, None] * xp[:, None, t:t + m] for t in range(3))
+    h1 = np.maximum(z1, 0.0)
+    hp = np.zeros((B, C, m + 2))
+    hp[:, :, 1:m + 1] = h1
+    z2 = b2[None, :, None] + sum(np.einsum("oc,bcp->bop", W2[:, :, t], hp[:, :, t:t + m]) for t in range(3))
+    return z1, h1, hp, z2
+
+
+def cnn_forward(w: np.ndarray, q_s: np.ndarray, C: int) -> np.ndarray:
+    """CNN filter prediction d^f(q) = b3 + sum_c w3[c] mean_p ReLU(z2[c, p]),
+    FP64, for each query row (the series are the single input channel)."""
+    W1, b1, W2, b2, w3, b3 = unpack_cnn(w, C)
+    _, _, _, z2 = _cnn_layers(w, q_s, C)
+    return np.maximum(z2, 0.0).mean(axis=2) @ w3 + b3
+
+
+def cnn_mse_grad(w: np.ndarray, X: np.ndarray, y: np.ndarray, C: int):
+    """Loss mean((d^f - y)^2) over a batch and its gradient in the packed
+    CNN layout, FP64 (backpropagation through the two correlations)."""
+    W1, b1, W2, b2, w3, b3 = unpack_cnn(w, C)
+    X = np.asarray(X, dtype=np.float64)
+    B, m = X.shape
+    z1, h1, hp, z2 = _cnn_layers(w, X, C)
+    h2 = np.maximum(z2, 0.0)
+    pooled = h2.mean(axis=2)                       # [B, C]
+    r = pooled @ w3 + b3 - y
+    loss = float((r ** 2).mean())
+    g = 2.0 * r / B                                # dL/dprediction
+    gw3 = pooled.T @ g
+    gb3 = g.sum()
+    d2 = (g[:, None, None] * w3[None, :, None] / m) * (z2 > 0)      # dL/dz2 [B, C, m]
+    gb2 = d2.sum(axis=(0, 2))
+    gW2 = np.stack([np.einsum("bop,bcp->oc", d2, hp[:, :, t:t + m]) for t in range(3)], axis=2)
+    # dL/dh1[c, q] = sum_o sum_t W2[o, c, t] d2[o, q - t + 1]
+    dhp = np.zeros((B, C, m + 2))
+    for t in range(3):
+        dhp[:, :, t:t + m] += np.einsum("oc,bop->bcp", W2[:, :, t], d2)
+    d1 = dhp[:, :, 1:m + 1] * (z1 > 0)                                # dL/dz1
+    gb1 = d1.sum(axis=(0, 2))
+    xp = np.zeros((B, m + 2))
+    xp[:, 1:m + 1] = X
+    gW1 = np.stack([np.einsum("bcp,bp->c", d1, xp[:, t:t + m]) for t in range(3)], axis=1)
+    grad = np.concatenate([gW1.reshape(-1), gb1, gW2.reshape(-1), gb2, gw3, [gb3]])
+    return loss, grad
+
+
+# ---------------------------------------------------------------------------
 # Search (Algorithm 2) in a round schedule
 # ---------------------------------------------------------------------------
 

@@ -514,6 +514,89 @@ def test_select_leaves_cases():
     assert O.size_threshold(2.0, 46.0, 0.16) == pytest.approx(575.0)
 
 
+# ---------------------------------------------------------------- CNN filter (two correlations, kernel 3)
+
+def _cnn_pack(W1, b1, W2, b2, w3, b3):
+    return np.concatenate([np.ravel(W1), b1, np.ravel(W2), b2, w3, [b3]]).astype(np.float64)
+
+
+def test_cnn_hand_case_fixes_tap_order_and_padding():
+    # tap 0 reads position p - 1, tap 2 reads p + 1; one zero pad at each end
+    w = _cnn_pack([[1.0, 0.0, 0.0]], [0.0], [[[0.0, 0.0, 1.0]]], [0.0], [2.0], 0.5)
+    assert len(w) == O.cnn_param_count(1)
+    # z1 = x[p-1] = [0, 1, 2]; z2 = h1[p+1] = [1, 2, 0]; mean 1; 2 * 1 + 0.5
+    assert O.cnn_forward(w, np.array([[1.0, 2.0, 3.0]]), 1)[0] == pytest.approx(2.5, abs=1e-15)
+
+
+def test_cnn_linear_regime_matches_numpy_correlate():
+    """With biases that keep every pre-activation positive the network is two
+    zero-padded cross-correlations and a mean; numpy's correlate computes them."""
+    rng = np.random.default_rng(41)
+    C, m = 5, 17
+    W1, W2 = rng.normal(0, 0.3, (C, 3)), rng.normal(0, 0.3, (C, C, 3))
+    b1, b2, w3, b3 = rng.uniform(20, 30, C), rng.uniform(200, 300, C), rng.normal(0, 1, C), 0.7
+    w = _cnn_pack(W1, b1, W2, b2, w3, b3)
+    X = rng.normal(0, 1, (4, m))
+    got = O.cnn_forward(w, X, C)
+    for i, x in enumerate(X):
+        h1 = np.stack([b1[c] + np.correlate(np.pad(x, 1), W1[c], "valid") for c in range(C)])
+        assert h1.min() > 0
+        z2 = np.stack([b2[o] + sum(np.correlate(np.pad(h1[c], 1), W2[o, c], "valid") for c in range(C))
+                       for o in range(C)])
+        assert z2.min() > 0
+        assert got[i] == pytest.approx(b3 + w3 @ z2.mean(axis=1), rel=1e-12)
+
+
+def test_cnn_center_taps_are_a_per_position_network():
+    """Outer taps zero: each position runs the same two-layer network on its
+    own value, and the readout averages it over the positions."""
+    rng = np.random.default_rng(42)
+    C, m = 6, 11
+    W1, W2 = rng.normal(0, 1, (C, 3)), rng.normal(0, 1, (C, C, 3))
+    W1[:, [0, 2]] = 0.0
+    W2[:, :, [0, 2]] = 0.0
+    b1, b2, w3 = rng.normal(0, 1, C), rng.normal(0, 1, C), rng.normal(0, 1, C)
+    w = _cnn_pack(W1, b1, W2, b2, w3, -0.3)
+    X = rng.normal(0, 1, (5, m))
+    h1 = np.maximum(X[:, :, None] * W1[:, 1] + b1, 0.0)          # [B, m, C]
+    h2 = np.maximum(h1 @ W2[:, :, 1].T + b2, 0.0)               # [B, m, C]
+    want = h2.mean(axis=1) @ w3 - 0.3
+    assert np.allclose(O.cnn_forward(w, X, C), want, rtol=1e-12, atol=1e-12)
+
+
+def test_cnn_output_is_shift_invariant_inside_a_zero_border():
+    """With b1, b2 <= 0 a zero input region maps to zero activations, so moving
+    the series by one position inside a zero border leaves the mean unchanged."""
+    rng = np.random.default_rng(43)
+    C, m = 4, 20
+    W1, W2 = rng.normal(0, 1, (C, 3)), rng.normal(0, 1, (C, C, 3))
+    w = _cnn_pack(W1, -np.abs(rng.normal(0, 0.2, C)), W2, -np.abs(rng.normal(0, 0.2, C)), rng.normal(0, 1, C), 0.1)
+    x = np.zeros((1, m))
+    x[0, 4:14] = rng.normal(0, 1, 10)
+    y = np.roll(x, 2, axis=1)
+    assert O.cnn_forward(w, x, C)[0] == pytest.approx(O.cnn_forward(w, y, C)[0], rel=1e-12)
+    # a non-zero bias breaks it (the border activations are then not zero)
+    w2 = w.copy()
+    w2[3 * C: 4 * C] = 1.0
+    assert abs(O.cnn_forward(w2, x, C)[0] - O.cnn_forward(w2, np.roll(x, 5, axis=1), C)[0]) > 1e-6
+
+
+def test_cnn_gradient_central_differences():
+    rng = np.random.default_rng(44)
+    C, m, B = 3, 7, 4
+    w = rng.normal(0, 0.6, O.cnn_param_count(C))
+    X, y = rng.normal(0, 1, (B, m)), rng.normal(0, 1, B)
+    loss, g = O.cnn_mse_grad(w, X, y, C)
+    assert loss == pytest.approx(float(((O.cnn_forward(w, X, C) - y) ** 2).mean()), rel=1e-12)
+    eps = 1e-6
+    num = np.empty_like(w)
+    for i in range(len(w)):
+        e = np.zeros_like(w)
+        e[i] = eps
+        num[i] = (O.cnn_mse_grad(w + e, X, y, C)[0] - O.cnn_mse_grad(w - e, X, y, C)[0]) / (2 * eps)
+    assert np.allclose(g, num, rtol=1e-5, atol=1e-7)
+
+
 # ---------------------------------------------------------------- leaf selection as a knapsack (Equations 1-2)
 
 def test_knapsack_textbook_case():
