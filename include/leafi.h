@@ -128,10 +128,12 @@ typedef struct {
   int32_t n_leaves;
   int32_t n_segments;
   int32_t n_filters;   /* 0 until filters are trained or set */
-  int32_t hidden;      /* filter hidden width h */
+  int32_t hidden;      /* filter hidden width h (MLP) or channel count (CNN) */
   int32_t n_calibrated;/* number of calibrated (k, target) pairs */
   int64_t padded_rows; /* rows of the leaf store including per-leaf padding */
   int64_t device_bytes;/* resident device memory owned by the handle */
+  int32_t filter_arch; /* LEAFI_FILTER_MLP or LEAFI_FILTER_CNN */
+  int32_t reserved;
 } leafi_info;
 
 int leafi_get_info(const leafi_index *index, leafi_info *out);
@@ -160,7 +162,7 @@ typedef struct {
   float val_fraction;    /* share of the global queries held out for validation (0.2) */
   double th_override;    /* < 0: th = a * t^F / t^S measured on this GPU; >= 0: use as th */
   int64_t mem_budget;    /* c^M: device bytes available for filter weights */
-  int32_t hidden;        /* h; 0 = m (paper: hidden width = series length) */
+  int32_t hidden;        /* h (MLP) or channels (CNN); 0 = m (paper: width = series length) */
   int32_t max_epochs;    /* paper: 1,000 */
   float lr0;             /* paper: 0.01 */
   float lr_min;          /* paper: 1e-5 (training stops below it) */
@@ -169,7 +171,27 @@ typedef struct {
   uint64_t seed;
   int32_t keep_examples; /* 1: keep the training queries and targets for leafi_get_examples */
   int32_t selection;     /* LEAFI_SELECT_SIZE (Algorithm 3) or LEAFI_SELECT_KNAPSACK (Equations 1-2) */
+  int32_t arch;          /* LEAFI_FILTER_MLP (default) or LEAFI_FILTER_CNN */
+  int32_t reserved;
 } leafi_train_opts;
+
+/* Filter architectures (paper: Section "Evaluation Setup" for the MLP,
+ * Section "Varying Model Type" for the CNN).
+ * MLP: d^f(q) = w2 . ReLU(W1 q + b1) + b2, hidden width h; packed as
+ *   [W1 (input-major: element (i, j) at i*h + j) | b1 (h) | w2 (h) | b2],
+ *   P = h*m + 2h + 1 floats.
+ * CNN: two cross-correlations of kernel 3 over the series positions with one
+ *   zero of padding at each end (tap t reads position p + t - 1), 1 -> C then
+ *   C -> C channels, ReLU after each, the second layer's channels averaged
+ *   over the positions and read out linearly:
+ *   d^f(q) = b3 + sum_c w3[c] mean_p ReLU(z2[c][p]); packed as
+ *   [W1 (C, 3) | b1 (C) | W2 (C_out, C_in, 3) | b2 (C) | w3 (C) | b3],
+ *   P = 3C^2 + 6C + 1 floats.  m and C multiples of 4 whose inference fits
+ *   the 160 KiB LDS (C = m = 96 does); else LEAFI_EINVAL.  Inference and
+ *   training are plain FP32 (no matrix cores): t^F, and so Algorithm 3's
+ *   size threshold, is far larger than the MLP's. */
+#define LEAFI_FILTER_MLP 0
+#define LEAFI_FILTER_CNN 1
 
 /* Leaf selection rules of leafi_train_filters (opts.selection).
  * SIZE: Algorithm 3 - leaves of size >= th = a t^F / t^S, largest first,
@@ -247,8 +269,13 @@ int leafi_get_train_trace(const leafi_index *index, int32_t *max_epochs, int32_t
 int leafi_set_filters(leafi_index *index, int32_t n_filters, int32_t hidden, const int32_t *leaf_ids_host,
                       const float *weights_dev, void *stream);
 
+/* Install given CNN filters (LEAFI_FILTER_CNN packing, `channels` C) on the
+ * leaves leaf_ids_host[n_filters] (distinct).  Clears calibration. */
+int leafi_set_cnn_filters(leafi_index *index, int32_t n_filters, int32_t channels, const int32_t *leaf_ids_host,
+                          const float *weights_dev, void *stream);
+
 /* Copy the filters out: leaf_ids_host [n_filters] and weights_dev [n_filters, P]
- * (same packing as leafi_set_filters).  Either pointer may be NULL. */
+ * (the packing of the installed architecture).  Either pointer may be NULL. */
 int leafi_get_filters(const leafi_index *index, int32_t *leaf_ids_host, float *weights_dev, void *stream);
 
 /* ------------------------------------------------------------------------
@@ -530,6 +557,17 @@ int leafi_mlp_infer(const float *weights_dev, int32_t n_filters, int32_t m, int3
  * w -= lr * grad of mean((d^f - y)^2).  loss_dev [n_filters] receives the
  * batch loss before the step (may be NULL). */
 int leafi_mlp_sgd_step(float *weights_dev, int32_t n_filters, int32_t m, int32_t hidden, const float *x_dev,
+                       const float *y_dev, int32_t batch, float lr, float *loss_dev, void *stream);
+
+/* CNN filter predictions for z-normalised inputs x_dev [nq, m]: out_dev
+ * [nq, n_filters] = d^f, fp32 (LEAFI_FILTER_CNN packing, C channels). */
+int leafi_cnn_infer(const float *weights_dev, int32_t n_filters, int32_t m, int32_t channels, const float *x_dev,
+                    int64_t nq, float *out_dev, void *stream);
+
+/* One plain SGD step per CNN filter on its own batch (as leafi_mlp_sgd_step):
+ * x_dev [n_filters, batch, m], y_dev [n_filters, batch]; loss_dev
+ * [n_filters] receives the batch loss before the step. */
+int leafi_cnn_sgd_step(float *weights_dev, int32_t n_filters, int32_t m, int32_t channels, const float *x_dev,
                        const float *y_dev, int32_t batch, float lr, float *loss_dev, void *stream);
 
 /* Node-wise k nearest neighbours of raw queries in every leaf (the scan in

@@ -18,6 +18,7 @@ from ._lib import LEAFI_SEARCH_HOST_ROUNDS as SEARCH_HOST_ROUNDS
 from ._lib import LEAFI_SEARCH_NO_GRAPH as SEARCH_NO_GRAPH
 
 __all__ = ["Index", "Server", "TorchAllocator", "LeafiError", "load", "znorm", "mlp_infer", "mlp_sgd_step",
+           "cnn_infer", "cnn_sgd_step",
            "version"]
 
 
@@ -149,7 +150,7 @@ class Index:
     def train_filters(self, **kw) -> dict:
         """Algorithm 1 (leafi_train_filters); options are leafi_train_opts
         fields, with selection given as "size" (Algorithm 3) or "knapsack"
-        (Equations 1-2)."""
+        (Equations 1-2) and arch as "mlp" or "cnn"."""
         o = _lib.TrainOpts()
         load().leafi_default_train_opts(ctypes.byref(o))
         for k, v in kw.items():
@@ -157,6 +158,8 @@ class Index:
                 raise TypeError(f"unknown training option {k}")
             if k == "selection" and isinstance(v, str):
                 v = {"size": _lib.LEAFI_SELECT_SIZE, "knapsack": _lib.LEAFI_SELECT_KNAPSACK}[v]
+            if k == "arch" and isinstance(v, str):
+                v = {"mlp": _lib.LEAFI_FILTER_MLP, "cnn": _lib.LEAFI_FILTER_CNN}[v]
             setattr(o, k, v)
         r = _lib.TrainReport()
         check(load().leafi_train_filters(self._h, ctypes.byref(o), ctypes.byref(r), _stream()))
@@ -199,12 +202,20 @@ class Index:
         check(load().leafi_set_filters(self._h, len(ids), hidden, ids.ctypes.data_as(ctypes.c_void_p),
                                        _dev(weights, torch.float32, "weights"), _stream()))
 
+    def set_cnn_filters(self, leaf_ids, weights, channels: int):
+        """Install CNN filters (LEAFI_FILTER_CNN packing) on the given leaves."""
+        torch = _torch()
+        ids = np.ascontiguousarray(leaf_ids, dtype=np.int32)
+        check(load().leafi_set_cnn_filters(self._h, len(ids), channels, ids.ctypes.data_as(ctypes.c_void_p),
+                                           _dev(weights, torch.float32, "weights"), _stream()))
+
     def get_filters(self):
         torch = _torch()
         inf = self.info()
         F, h, m = inf["n_filters"], inf["hidden"], inf["m"]
         ids = np.zeros(F, dtype=np.int32)
-        w = torch.empty((F, h * m + 2 * h + 1), dtype=torch.float32, device="cuda")
+        P = 3 * h * h + 6 * h + 1 if inf["filter_arch"] == _lib.LEAFI_FILTER_CNN else h * m + 2 * h + 1
+        w = torch.empty((F, P), dtype=torch.float32, device="cuda")
         check(load().leafi_get_filters(self._h, ids.ctypes.data_as(ctypes.c_void_p),
                                        ctypes.c_void_p(w.data_ptr()) if F else None, _stream()))
         return ids, w
@@ -506,6 +517,28 @@ def mlp_sgd_step(weights, m: int, hidden: int, x, y, lr: float):
     F, B, _ = x.shape
     loss = torch.empty((F,), dtype=torch.float32, device=x.device)
     check(load().leafi_mlp_sgd_step(_dev(weights, torch.float32, "weights"), F, m, hidden,
+                                    _dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), B, lr,
+                                    _dev(loss, torch.float32, "loss"), _stream()))
+    return loss
+
+
+def cnn_infer(weights, m: int, channels: int, x):
+    """CNN filter predictions d^f [nq, F] for z-normalised x [nq, m]."""
+    torch = _torch()
+    F = weights.shape[0]
+    nq = x.shape[0]
+    out = torch.empty((nq, F), dtype=torch.float32, device=x.device)
+    check(load().leafi_cnn_infer(_dev(weights, torch.float32, "weights"), F, m, channels,
+                                 _dev(x, torch.float32, "x"), nq, _dev(out, torch.float32, "out"), _stream()))
+    return out
+
+
+def cnn_sgd_step(weights, m: int, channels: int, x, y, lr: float):
+    """One SGD step per CNN filter in place; x [F, B, m], y [F, B]; returns the batch losses."""
+    torch = _torch()
+    F, B, _ = x.shape
+    loss = torch.empty((F,), dtype=torch.float32, device=x.device)
+    check(load().leafi_cnn_sgd_step(_dev(weights, torch.float32, "weights"), F, m, channels,
                                     _dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"), B, lr,
                                     _dev(loss, torch.float32, "loss"), _stream()))
     return loss

@@ -27,6 +27,8 @@ LEAFI_CALIB_STEFFEN = 1
 LEAFI_CALIB_NO_CORRECTION = 2
 LEAFI_SELECT_SIZE = 0
 LEAFI_SELECT_KNAPSACK = 1
+LEAFI_FILTER_MLP = 0
+LEAFI_FILTER_CNN = 1
 
 
 class LeafiError(RuntimeError):
@@ -44,7 +46,7 @@ class Info(ctypes.Structure):
     _fields_ = [("n_series", ctypes.c_int64), ("m", ctypes.c_int32), ("n_leaves", ctypes.c_int32),
                 ("n_segments", ctypes.c_int32), ("n_filters", ctypes.c_int32), ("hidden", ctypes.c_int32),
                 ("n_calibrated", ctypes.c_int32), ("padded_rows", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("filter_arch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -53,7 +55,8 @@ class TrainOpts(ctypes.Structure):
                 ("th_override", ctypes.c_double), ("mem_budget", ctypes.c_int64), ("hidden", ctypes.c_int32),
                 ("max_epochs", ctypes.c_int32), ("lr0", ctypes.c_float), ("lr_min", ctypes.c_float),
                 ("batch", ctypes.c_int32), ("patience", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("keep_examples", ctypes.c_int32), ("selection", ctypes.c_int32)]
+                ("keep_examples", ctypes.c_int32), ("selection", ctypes.c_int32), ("arch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class TrainReport(ctypes.Structure):
@@ -127,6 +130,7 @@ SIGNATURES = [
     ("leafi_default_train_opts", None, [ctypes.POINTER(TrainOpts)]),
     ("leafi_train_filters", ctypes.c_int, [P, ctypes.POINTER(TrainOpts), ctypes.POINTER(TrainReport), P]),
     ("leafi_set_filters", ctypes.c_int, [P, I32, I32, P, P, P]),
+    ("leafi_set_cnn_filters", ctypes.c_int, [P, I32, I32, P, P, P]),
     ("leafi_get_filters", ctypes.c_int, [P, P, P, P]),
     ("leafi_get_train_trace", ctypes.c_int, [P, ctypes.POINTER(I32), P, P]),
     ("leafi_get_examples", ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P,
@@ -154,6 +158,8 @@ SIGNATURES = [
     ("leafi_lower_bounds", ctypes.c_int, [P, P, I64, P, P]),
     ("leafi_mlp_infer", ctypes.c_int, [P, I32, I32, I32, P, I64, P, P]),
     ("leafi_mlp_sgd_step", ctypes.c_int, [P, I32, I32, I32, P, P, I32, F32, P, P]),
+    ("leafi_cnn_infer", ctypes.c_int, [P, I32, I32, I32, P, I64, P, P]),
+    ("leafi_cnn_sgd_step", ctypes.c_int, [P, I32, I32, I32, P, P, I32, F32, P, P]),
     ("leafi_leaf_knn", ctypes.c_int, [P, P, I64, I32, P, P, P]),
     ("leafi_select_knapsack", ctypes.c_int, [P, P, I64, ctypes.c_float, ctypes.c_double, ctypes.c_double, I32, I64,
                                              P, P, P, P, P, P]),

@@ -471,8 +471,19 @@ void begin_batch(leafi_index *ix, const float *raw, int64_t nq, const int32_t *k
 // later rounds (filter-pair counts were zeroed by begin_batch).
 void infer_filter_pairs(leafi_index *ix, int64_t nq, int ftile, hipStream_t st) {
   Workspace &w = ix->ws;
-  launch_mlp_infer_pairs(ix->filt.w.get(), ix->filt.F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(),
-                         nq, ix->N, w.pair.get(), ix->cal.offsets.get(), w.ptile.get(), w.dfo.get(), st, ftile);
+  if (ix->filt.arch == LEAFI_FILTER_CNN)
+    launch_cnn_infer_pairs(ix->filt.w.get(), ix->filt.F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(),
+                           nq, ix->N, w.pair.get(), ix->cal.offsets.get(), w.dfo.get(), st);
+  else
+    launch_mlp_infer_pairs(ix->filt.w.get(), ix->filt.F, ix->m, ix->filt.h, w.q32.get(), w.plist.get(),
+                           w.pcnt.get(), nq, ix->N, w.pair.get(), ix->cal.offsets.get(), w.ptile.get(), w.dfo.get(), st,
+                           ftile);
+}
+
+// d^f of every (query, filter) with the installed filters: out [nq, F].
+void infer_filters_dense(leafi_index *ix, const float *x, int64_t nq, float *out, hipStream_t st) {
+  if (ix->filt.arch == LEAFI_FILTER_CNN) launch_cnn_infer(ix->filt.w.get(), ix->filt.F, ix->m, ix->filt.h, x, nq, out, st);
+  else launch_mlp_infer(ix->filt.w.get(), ix->filt.F, ix->m, ix->filt.h, x, nq, out, st);
 }
 
 void eval_filters(leafi_index *ix, int64_t nq, int ftile, hipStream_t st) {
@@ -805,7 +816,7 @@ std::vector<uint64_t> plan_key(leafi_index *ix, const float *raw, int64_t nq, co
   for (int64_t v : {nq, static_cast<int64_t>(p.kmax), static_cast<int64_t>(p.kprime), static_cast<int64_t>(use_f),
                     static_cast<int64_t>(timed), static_cast<int64_t>(ix->N), static_cast<int64_t>(ix->m),
                     static_cast<int64_t>(ix->S), static_cast<int64_t>(ix->filt.F), static_cast<int64_t>(ix->filt.h),
-                    static_cast<int64_t>(ix->cal.pairs()), ix->rows,
+                    static_cast<int64_t>(ix->filt.arch), static_cast<int64_t>(ix->cal.pairs()), ix->rows,
                     static_cast<int64_t>(ix->tune_chunk), static_cast<int64_t>(ix->tune_mq),
                     static_cast<int64_t>(p.ftile), static_cast<int64_t>(p.kp_query), ix->plan_cap_items,
                     ix->plan_items_seen, ix->plan_tiles_seen,
@@ -1196,6 +1207,7 @@ int leafi_get_info(const leafi_index *ix, leafi_info *out) {
     out->n_segments = ix->S;
     out->n_filters = ix->filt.F;
     out->hidden = ix->filt.h;
+    out->filter_arch = ix->filt.arch;
     out->n_calibrated = ix->cal.pairs();
     out->padded_rows = ix->rows;
     out->device_bytes = static_cast<int64_t>(ix->x32.bytes() + ix->x16.bytes() + ix->xn16.bytes() + ix->rowid.bytes() +
@@ -1243,24 +1255,35 @@ void leafi_default_train_opts(leafi_train_opts *o) {
   o->seed = 1;
 }
 
+// Floats of one packed filter of the architecture.
+static int64_t filter_params(int arch, int m, int h) {
+  return arch == LEAFI_FILTER_CNN ? cnn_param_count(h) : static_cast<int64_t>(h) * m + 2 * h + 1;
+}
+
 // Algorithm 3's measured costs: t^F, the amortised time of one (query,
 // filter) inference in a batch, and t^S, of one (query, series) distance in
 // the batched scan with one query group per leaf (the search regime).  The
 // probe queries' rows are drawn from rng.
-static void measure_costs(leafi_index *ix, int h, uint64_t seed, std::mt19937_64 &rng, hipStream_t st, double *t_filter,
-                          double *t_series) {
+static void measure_costs(leafi_index *ix, int arch, int h, uint64_t seed, std::mt19937_64 &rng, hipStream_t st,
+                          double *t_filter, double *t_series) {
   const int m = ix->m, N = ix->N;
-  const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
-  const int qf = 1024, ff = std::min(N, 64);
+  const bool cnn = arch == LEAFI_FILTER_CNN;
+  const int64_t P = filter_params(arch, m, h);
+  // a CNN filter costs thousands of MLP ones: fewer queries, a filter per CU
+  const int qf = cnn ? 64 : 1024, ff = cnn ? 256 : std::min(N, 64);
   DevBuf<float> wp(static_cast<size_t>(ff) * P), xp(static_cast<size_t>(qf) * m), outp(static_cast<size_t>(qf) * ff);
   fill_f32(wp.get(), wp.size(), 0.01f, st);
   fill_f32(xp.get(), xp.size(), 0.5f, st);
-  launch_mlp_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);  // warm-up
+  auto infer = [&] {
+    if (cnn) launch_cnn_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);
+    else launch_mlp_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);
+  };
+  infer();  // warm-up
   hipEvent_t a, b;
   HIP_OK(hipEventCreate(&a));
   HIP_OK(hipEventCreate(&b));
   HIP_OK(hipEventRecord(a, st));
-  launch_mlp_infer(wp.get(), ff, m, h, xp.get(), qf, outp.get(), st);
+  infer();
   HIP_OK(hipEventRecord(b, st));
   HIP_OK(hipEventSynchronize(b));
   float msf = 0;
@@ -1342,11 +1365,13 @@ static void selection_estimates(leafi_index *ix, const float *raw, int64_t nq, h
   }
 }
 
-static void install_filters(leafi_index *ix, int F, int h, const std::vector<int32_t> &leaves, hipStream_t st) {
+static void install_filters(leafi_index *ix, int arch, int F, int h, const std::vector<int32_t> &leaves,
+                            hipStream_t st) {
   ix->examples = Examples();
   ix->filt.F = F;
+  ix->filt.arch = arch;
   ix->filt.h = h;
-  ix->filt.P = static_cast<int64_t>(h) * ix->m + 2 * h + 1;
+  ix->filt.P = filter_params(arch, ix->m, h);
   ix->filt.leaf_of_filter = leaves;
   std::vector<int32_t> fol(ix->N, -1);
   for (int f = 0; f < F; ++f) fol[leaves[f]] = f;
@@ -1355,14 +1380,14 @@ static void install_filters(leafi_index *ix, int F, int h, const std::vector<int
   ix->cal = Calibration();
 }
 
-int leafi_set_filters(leafi_index *ix, int32_t F, int32_t hidden, const int32_t *leaf_ids, const float *weights,
-                      void *stream) {
-  return guarded([&] {
-    INDEX_ALLOC_SCOPE(ix);
+static void set_filters(leafi_index *ix, int arch, int32_t F, int32_t hidden, const int32_t *leaf_ids,
+                        const float *weights, void *stream) {
+  {
     require_built(ix);
     LEAFI_CHECK_ARG(F >= 0 && F <= ix->N, "n_filters must be in [0, n_leaves]");
     LEAFI_CHECK_ARG(F == 0 || (leaf_ids && weights), "NULL leaf ids or weights");
-    LEAFI_CHECK_ARG(hidden >= 4 && hidden <= 1024 && hidden % 4 == 0, "hidden must be a multiple of 4 in [4, 1024]");
+    if (arch == LEAFI_FILTER_CNN) cnn_check(ix->m, hidden);
+    else LEAFI_CHECK_ARG(hidden >= 4 && hidden <= 1024 && hidden % 4 == 0, "hidden must be a multiple of 4 in [4, 1024]");
     std::vector<int32_t> leaves(leaf_ids, leaf_ids + F);
     std::vector<char> seen(ix->N, 0);
     for (int32_t L : leaves) {
@@ -1371,11 +1396,27 @@ int leafi_set_filters(leafi_index *ix, int32_t F, int32_t hidden, const int32_t 
       seen[L] = 1;
     }
     hipStream_t st = as_stream(stream);
-    install_filters(ix, F, hidden, leaves, st);
+    install_filters(ix, arch, F, hidden, leaves, st);
     ix->filt.w.alloc(static_cast<size_t>(F) * ix->filt.P);
     if (F) HIP_OK(hipMemcpyAsync(ix->filt.w.get(), weights, static_cast<size_t>(F) * ix->filt.P * sizeof(float),
                                  hipMemcpyDeviceToDevice, st));
     HIP_OK(hipStreamSynchronize(st));
+  }
+}
+
+int leafi_set_filters(leafi_index *ix, int32_t F, int32_t hidden, const int32_t *leaf_ids, const float *weights,
+                      void *stream) {
+  return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
+    set_filters(ix, LEAFI_FILTER_MLP, F, hidden, leaf_ids, weights, stream);
+  });
+}
+
+int leafi_set_cnn_filters(leafi_index *ix, int32_t F, int32_t channels, const int32_t *leaf_ids, const float *weights,
+                          void *stream) {
+  return guarded([&] {
+    INDEX_ALLOC_SCOPE(ix);
+    set_filters(ix, LEAFI_FILTER_CNN, F, channels, leaf_ids, weights, stream);
   });
 }
 
@@ -1403,14 +1444,17 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     LEAFI_CHECK_ARG(o->max_epochs >= 1 && o->patience >= 1, "max_epochs and patience must be >= 1");
     LEAFI_CHECK_ARG(o->lr0 > 0 && o->lr_min > 0, "learning rates must be > 0");
     const int h = o->hidden > 0 ? o->hidden : ix->m;
-    LEAFI_CHECK_ARG(h <= 256 && h % 4 == 0, "training supports hidden <= 256, a multiple of 4");
+    LEAFI_CHECK_ARG(o->arch == LEAFI_FILTER_MLP || o->arch == LEAFI_FILTER_CNN, "arch must be MLP or CNN");
+    const bool cnn = o->arch == LEAFI_FILTER_CNN;
+    if (cnn) cnn_check(ix->m, h);
+    else LEAFI_CHECK_ARG(h <= 256 && h % 4 == 0, "training supports hidden <= 256, a multiple of 4");
     LEAFI_CHECK_ARG(o->selection == LEAFI_SELECT_SIZE || o->selection == LEAFI_SELECT_KNAPSACK,
                     "selection must be LEAFI_SELECT_SIZE or LEAFI_SELECT_KNAPSACK");
     LEAFI_CHECK_ARG(o->a > 0, "a must be > 0");
     hipStream_t st = as_stream(stream);
     Workspace &w = ix->ws;
     const int m = ix->m, N = ix->N;
-    const int64_t P = static_cast<int64_t>(h) * m + 2 * h + 1;
+    const int64_t P = filter_params(o->arch, m, h);
     leafi_train_report report;
     std::memset(&report, 0, sizeof(report));
     std::mt19937_64 rng(o->seed);
@@ -1424,7 +1468,7 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     // ratio t^F / t^S = th / a (their signs and order depend on it alone)
     double kn_tF = th / o->a, kn_tS = 1.0;
     if (th < 0) {
-      measure_costs(ix, h, o->seed, rng, st, &report.t_filter_s, &report.t_series_s);
+      measure_costs(ix, o->arch, h, o->seed, rng, st, &report.t_filter_s, &report.t_series_s);
       th = report.t_series_s > 0 ? o->a * report.t_filter_s / report.t_series_s : 0.0;
       kn_tF = report.t_filter_s;
       kn_tS = report.t_series_s;
@@ -1459,7 +1503,7 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
       sel = select_leaves(ix->h_leaf_n, th, static_cast<double>(P) * 4.0, static_cast<double>(o->mem_budget));
     }
     const int F = static_cast<int>(sel.size());
-    install_filters(ix, F, h, sel, st);
+    install_filters(ix, o->arch, F, h, sel, st);
     ix->filt.w.alloc(static_cast<size_t>(std::max(F, 1)) * P);
     report.n_filters = F;
     if (F == 0) {
@@ -1554,11 +1598,19 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
     std::vector<float> w0(static_cast<size_t>(F) * P);
     for (int f = 0; f < F; ++f) {
       std::mt19937_64 g(o->seed * 0x9e3779b97f4a7c15ull + static_cast<uint64_t>(f) + 1);
-      float a1 = 1.0f / std::sqrt(static_cast<float>(m)), a2 = 1.0f / std::sqrt(static_cast<float>(h));
-      std::uniform_real_distribution<float> u1(-a1, a1), u2(-a2, a2);
       float *wf = &w0[static_cast<size_t>(f) * P];
-      for (int64_t i = 0; i < static_cast<int64_t>(h) * m + h; ++i) wf[i] = u1(g);
-      for (int64_t i = static_cast<int64_t>(h) * m + h; i < P; ++i) wf[i] = u2(g);
+      // [layer end, fan-in] of each layer's weights and bias, in packed order
+      std::vector<std::pair<int64_t, int>> layers;
+      if (cnn)  // [W1 | b1] fan-in 3, [W2 | b2] fan-in 3C, [w3 | b3] fan-in C
+        layers = {{4LL * h, 3}, {4LL * h + 3LL * h * h + h, 3 * h}, {P, h}};
+      else  // [W1 | b1] fan-in m, [w2 | b2] fan-in h
+        layers = {{static_cast<int64_t>(h) * m + h, m}, {P, h}};
+      int64_t i = 0;
+      for (const auto &L : layers) {
+        const float bound = 1.0f / std::sqrt(static_cast<float>(L.second));
+        std::uniform_real_distribution<float> u(-bound, bound);
+        for (; i < L.first; ++i) wf[i] = u(g);
+      }
     }
     h2d(ix->filt.w.get(), w0.data(), w0.size(), st);
     DevBuf<float> wbest(static_cast<size_t>(F) * P), vmse(F);
@@ -1589,7 +1641,13 @@ int leafi_train_filters(leafi_index *ix, const leafi_train_opts *o, leafi_train_
       ta.val_trace = vtrace.get();
     }
     auto t2 = std::chrono::steady_clock::now();
-    launch_mlp_train(ta, st);
+    if (cnn) {
+      DevBuf<float> gbuf(static_cast<size_t>(F) * P);
+      launch_cnn_train(ta, gbuf.get(), st);
+      HIP_OK(hipStreamSynchronize(st));  // gbuf is freed on leaving the scope
+    } else {
+      launch_mlp_train(ta, st);
+    }
     std::vector<float> hv(F);
     std::vector<int32_t> he(F);
     d2h(hv.data(), vmse.get(), F, st);
@@ -1669,7 +1727,7 @@ int leafi_calibrate(leafi_index *ix, const float *calib, int32_t nc, const int32
     const int N = ix->N, F = ix->filt.F;
     ensure_queries(ix, nc, kc);
     prep_queries(ix, calib, nc, st);
-    launch_mlp_infer(ix->filt.w.get(), F, ix->m, ix->filt.h, w.q32.get(), nc, w.dfilt.get(), st);
+    infer_filters_dense(ix, w.q32.get(), nc, w.dfilt.get(), st);
     CalibInput in;
     in.nc = nc;
     in.N = N;
@@ -1939,6 +1997,34 @@ int leafi_mlp_sgd_step(float *w, int32_t F, int32_t m, int32_t h, const float *x
   });
 }
 
+int leafi_cnn_infer(const float *w, int32_t F, int32_t m, int32_t C, const float *x, int64_t nq, float *out,
+                    void *stream) {
+  return guarded([&] {
+    LEAFI_CHECK_ARG(F >= 0 && nq >= 0, "bad sizes");
+    cnn_check(m, C);
+    if (F == 0 || nq == 0) return;
+    LEAFI_CHECK_ARG(w && x && out, "NULL pointer");
+    LEAFI_CHECK_ARG(F <= 65535, "too many filters in one call");
+    launch_cnn_infer(w, F, m, C, x, nq, out, as_stream(stream));
+  });
+}
+
+int leafi_cnn_sgd_step(float *w, int32_t F, int32_t m, int32_t C, const float *x, const float *y, int32_t batch,
+                       float lr, float *loss, void *stream) {
+  return guarded([&] {
+    LEAFI_CHECK_ARG(F >= 0, "bad sizes");
+    cnn_check(m, C);
+    LEAFI_CHECK_ARG(batch >= 1, "batch must be >= 1");
+    if (F == 0) return;
+    LEAFI_CHECK_ARG(w && x && y && loss, "NULL pointer");
+    LEAFI_CHECK_ARG(F <= 65535, "too many filters in one call");
+    hipStream_t st = as_stream(stream);
+    DevBuf<float> gbuf(static_cast<size_t>(F) * cnn_param_count(C));
+    launch_cnn_sgd_step(w, F, m, C, x, y, batch, lr, loss, gbuf.get(), st);
+    HIP_OK(hipStreamSynchronize(st));  // gbuf is freed on return
+  });
+}
+
 int leafi_leaf_knn(leafi_index *ix, const float *queries, int64_t nq, int32_t k, float *d, int64_t *ids,
                    void *stream) {
   return guarded([&] {
@@ -1971,7 +2057,7 @@ int leafi_select_knapsack(leafi_index *ix, const float *queries, int64_t nq, flo
     double tF = t_filter_s, tS = t_series_s;
     if (!(tF > 0) || !(tS > 0)) {
       std::mt19937_64 rng(1);
-      measure_costs(ix, h, 1, rng, st, &tF, &tS);
+      measure_costs(ix, LEAFI_FILTER_MLP, h, 1, rng, st, &tF, &tS);
     }
     std::vector<double> pl, pf, b;
     selection_estimates(ix, queries, nq, st, &pl, &pf);

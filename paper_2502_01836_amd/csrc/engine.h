@@ -102,6 +102,9 @@ double round_bytes_bound(const leafi_index *ix, int64_t nq, int64_t items_bound,
 // Queries per scan tile and list capacity of a pass (one_leaf: see RoundOpts).
 void pass_geometry(const leafi_index *ix, bool bf16, int kprime, int *mq, int *cap, bool one_leaf = false);
 int default_kprime(int kmax, bool bf16);
+// d^f - offset for the (query, visit position) pairs listed per filter
+// (plist / pcnt, nq queries) with the installed filters, MLP or CNN.
+void infer_filter_pairs(leafi_index *ix, int64_t nq, int ftile, hipStream_t st);
 
 // How a batch search runs (from leafi_search_opts).
 struct SearchPlan {

@@ -81,7 +81,8 @@ double steffen_eval(const std::vector<double> &x, const std::vector<double> &y, 
 
 struct Filters {
   int F = 0;
-  int h = 0;
+  int arch = LEAFI_FILTER_MLP;         // LEAFI_FILTER_MLP or LEAFI_FILTER_CNN
+  int h = 0;                           // MLP hidden width, or CNN channels
   int64_t P = 0;                       // floats per filter
   DevBuf<float> w;                     // [F, P]
   std::vector<int32_t> leaf_of_filter; // [F]

@@ -339,4 +339,24 @@ void launch_mlp_train(const TrainArgs &a, hipStream_t st);
 void launch_mlp_sgd_step(float *w, int F, int m, int h, const float *x, const float *y, int batch, float lr,
                          float *loss, hipStream_t st);
 
+// ---- CNN filters (k_cnn.hip) -------------------------------------------------
+
+// Floats of a packed CNN filter with C channels (3C^2 + 6C + 1).
+int64_t cnn_param_count(int C);
+// LEAFI_EINVAL unless length m and C channels are multiples of 4 whose
+// inference fits in LDS.
+void cnn_check(int m, int C);
+// d^f of every (query, filter): out [nq, F].
+void launch_cnn_infer(const float *w, int F, int m, int C, const float *x, int64_t nq, float *out, hipStream_t st);
+// Listed pairs, as launch_mlp_infer_pairs: dfo[e] = d^f - offsets[pair[q] F + f].
+void launch_cnn_infer_pairs(const float *w, int F, int m, int C, const float *x, const int64_t *plist,
+                            const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets,
+                            float *dfo, hipStream_t st);
+// Full SGD training, one work-group per filter (a.h = channels); gbuf [F, P]
+// is gradient scratch.
+void launch_cnn_train(const TrainArgs &a, float *gbuf, hipStream_t st);
+// One SGD step per filter on explicit batches; gbuf [F, P] scratch.
+void launch_cnn_sgd_step(float *w, int F, int m, int C, const float *x, const float *y, int batch, float lr,
+                         float *loss, float *gbuf, hipStream_t st);
+
 }  // namespace leafi

@@ -162,8 +162,7 @@ void leafi_server::engine_round(int n_new, int &n_active) {
     fill_i32(w.pcnt.get(), F, 0, st);
     launch_filter_pairs(slots, N, w.lbs.get(), w.order.get(), ix->filt.filt_of_leaf.get(), views(w), w.plist.get(),
                         w.pcnt.get(), w.dfo.get(), st, qround.get());
-    launch_mlp_infer_pairs(ix->filt.w.get(), F, m, ix->filt.h, w.q32.get(), w.plist.get(), w.pcnt.get(), slots, N,
-                           w.pair.get(), ix->cal.offsets.get(), w.ptile.get(), w.dfo.get(), st);
+    infer_filter_pairs(ix, slots, 0, st);
   }
   reset_round(ix, st);
   launch_worklist(slots, N, w.lbs.get(), w.order.get(), use_f ? w.dfo.get() : nullptr, ix->leaf_n.get(), 0, views(w),

@@ -47,13 +47,35 @@ def test_version_and_defaults(lib):
     assert s.k_max == 1 and s.scan == 0 and s.n_schedule == 2 and list(s.schedule[:2]) == [1, 0]
 
 
-def test_struct_sizes_match_header_layout():
+def test_struct_sizes_match_header_layout(tmp_path):
+    """The binding's structs have the sizes and field offsets a C compiler
+    gives the header's (a program built against include/leafi.h prints them)."""
+    import shutil
+    import subprocess
     from paper_2502_01836_amd import _lib
-    assert ctypes.sizeof(_lib.BuildOpts) == 16
-    assert ctypes.sizeof(_lib.SearchOpts) == 4 * 4 + 8 * 4 + 4 + 3 * 4
-    assert ctypes.sizeof(_lib.SearchStats) == 5 * 8 + 2 * 4 + 3 * 8 + 8
-    assert ctypes.sizeof(_lib.Info) == 8 + 6 * 4 + 8 + 8
-    assert ctypes.sizeof(_lib.TrainOpts) == 6 * 4 + 2 * 8 + 6 * 4 + 8 + 2 * 4
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [("leafi_build_opts", _lib.BuildOpts), ("leafi_search_opts", _lib.SearchOpts),
+             ("leafi_search_stats", _lib.SearchStats), ("leafi_info", _lib.Info),
+             ("leafi_train_opts", _lib.TrainOpts), ("leafi_train_report", _lib.TrainReport)]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "leafi.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "sizes"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = []
+    for _, py in pairs:
+        want.append(ctypes.sizeof(py))
+        want += [getattr(py, fname).offset for fname, _ in py._fields_]
+    assert got == want
 
 
 def test_null_handles_are_rejected_without_touching_the_gpu(lib):

@@ -167,6 +167,22 @@ def mlp_weights(n_filters: int, m: int, h: int, seed: int, out_bias: float = 0.0
     return w
 
 
+def cnn_weights(n_filters: int, C: int, seed: int, out_bias: float = 0.0) -> np.ndarray:
+    """Seeded CNN filter weights packed per filter as
+    [W1 (C, 3) | b1 (C) | W2 (C, C, 3) | b2 (C) | w3 (C) | b3], each layer
+    uniform in +-1/sqrt(fan_in) (fan-in 3, 3C and C).  Returns fp32
+    [n_filters, 3C^2 + 6C + 1]."""
+    g = _rng(seed)
+    P = 3 * C * C + 6 * C + 1
+    w = np.empty((n_filters, P), dtype=np.float32)
+    a1, a2, a3 = 1.0 / np.sqrt(3.0), 1.0 / np.sqrt(3.0 * C), 1.0 / np.sqrt(C)
+    w[:, : 4 * C] = g.uniform(-a1, a1, size=(n_filters, 4 * C))
+    w[:, 4 * C: 5 * C + 3 * C * C] = g.uniform(-a2, a2, size=(n_filters, C + 3 * C * C))
+    w[:, 5 * C + 3 * C * C:] = g.uniform(-a3, a3, size=(n_filters, C + 1))
+    w[:, -1] += out_bias
+    return w
+
+
 # Named workloads: the shapes and seeds every test and benchmark uses.
 WORKLOADS = {
     # small plain-search case: exact 1-NN with lower-bound pruning only
