@@ -53,14 +53,24 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+SCAN_SOURCES = ("k_scan.hip", "scan_bounds.h")
+
+
+def scan_source_digest():
+    """SHA-256 over the BF16 scan kernel's own sources, in order."""
+    h = hashlib.sha256()
+    for name in SCAN_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2502_01836_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload):
     """HBM bytes per scan dispatch from the committed counter summary of this
-    workload, if it was taken with the scan source as it is now (else None)."""
-    src = os.path.join(ROOT, "paper_2502_01836_amd", "csrc", "k_scan.hip")
+    workload, if it was taken with the scan sources as they are now (else None)."""
     summ = os.path.join(ROOT, "profiles", f"scan_bf16_{workload}_traffic.md")
     try:
         text = open(summ).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        digest = scan_source_digest()
     except OSError:
         return None
     vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_", "k_scan_")))

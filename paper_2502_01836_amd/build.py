@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libleafi.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "serve.hip", "noalloc.hip", "k_prep.hip", "k_rounds.hip", "k_scan.hip", "k_mlp.hip", "k_cnn.hip", "tree.cpp",
+SOURCES = ["api.hip", "serve.hip", "noalloc.hip", "k_prep.hip", "k_rounds.hip", "k_scan.hip", "k_rerank.hip", "k_mlp.hip", "k_cnn.hip", "tree.cpp",
            "calib.cpp"]
 ARCH = os.environ.get("LEAFI_OFFLOAD_ARCH", "gfx950")
 
