@@ -71,9 +71,10 @@ __device__ inline void select_keys(const uint64_t *__restrict__ cand, int64_t t0
 // before the round).  A candidate whose lower bound sqrt(key - delta16) -
 // eps_q - eps_L exceeds U can never enter the query's top k, so the rerank
 // skips its FP32 and FP64 distances.  The k-th smallest key is found by a
-// tournament over the list heads (k rounds of a wavefront minimum), 64 x
-// kBoundSlots lists per pass; a pass keeps the k smallest so far in LDS for
-// the next.
+// tournament over the list heads, 64 x kBoundSlots lists per pass; a pass
+// keeps the k smallest so far in LDS for the next, and each round emits the
+// run of those below the lists' smallest head (up to 64 at once) or that
+// head.
 constexpr int kBoundSlots = 4;
 
 __device__ inline int bound_pass(int64_t q, int N, int k, int kprime, int mq, int chunk, int cmax, const RoundBufs &b,
@@ -113,13 +114,22 @@ __device__ inline int bound_pass(int64_t q, int N, int k, int kprime, int mq, in
     uint64_t lo = kKeyMax;
 #pragma unroll
     for (int i = 0; i < kBoundSlots; ++i) lo = hd[i] < lo ? hd[i] : lo;
-    uint64_t g = wave_min_u64(lo);
-    const uint64_t rv = rp < n_in ? in[rp] : kKeyMax;
-    g = rv < g ? rv : g;
+    const uint64_t g = wave_min_u64(lo);
+    // the running list's keys below the lists' smallest head come next, as
+    // one run (lane j checks entry rp + j)
+    const bool below = rp + lane < n_in && o + lane < k && in[rp + lane] < g;
+    const uint64_t bm = __ballot(below);
+    const int run = ~bm == 0 ? kWave : __builtin_ctzll(~bm);
+    if (run > 0) {
+      if (lane < run) out[o + lane] = in[rp + lane];
+      o += run;
+      rp += run;
+      continue;
+    }
     if (g == kKeyMax) break;  // every list is exhausted
     if (lane == 0) out[o] = g;
     ++o;
-    if (rv == g) ++rp;
+    if (rp < n_in && in[rp] == g) ++rp;
 #pragma unroll
     for (int i = 0; i < kBoundSlots; ++i) {
       if (hd[i] == g) {  // the row may sit in two lists (a leaf rescanned): every copy advances

@@ -404,10 +404,12 @@ __global__ void __launch_bounds__(1024) k_scatter(int64_t nq, int N, RoundBufs b
 // for a rescan (by the next round's scan, or an exact FP32 pass after the
 // last round).  Every list is already sorted (the running top-k and each
 // item's exact top-k), so the k smallest of their union are selected by a
-// tournament over the list heads (merge_pass_staged): k rounds of a
-// wavefront minimum per pass, not a sort of everything.  A row met twice (a rescan of a leaf
-// already merged) carries the same (distance, row) in both lists and is kept
-// once.
+// tournament over the list heads (merge_pass_staged), not a sort of
+// everything: each round takes the wavefront minimum of the items' heads and
+// emits either the run of running-list entries below it (up to 64 at once)
+// or that minimum, so a pass costs about as many rounds as item entries
+// enter the top k.  A row met twice (a rescan of a leaf already merged)
+// carries the same (distance, row) in both lists and is kept once.
 constexpr int kMergePreFp = 4;  // visit positions per lane whose filter-pair inputs the merge prefetches
 constexpr int kMergeSlots = 4;  // item lists per lane in one tournament pass (256 items per pass)
 
@@ -527,6 +529,7 @@ __device__ inline int merge_pass_staged(int64_t q, int N, int kmax, int k, const
   }
   int out = 0, rp = 0;
   while (out < k) {
+    // smallest head of the staged lists
     double lv = kInf;
     uint32_t lt = 0xffffffffu;
 #pragma unroll
@@ -537,21 +540,88 @@ __device__ inline int merge_pass_staged(int64_t q, int N, int kmax, int k, const
       }
     const uint64_t mvb = wave_min_u64(dbl_bits(lv));
     const uint64_t mtb = wave_min_u64(dbl_bits(lv) == mvb ? static_cast<uint64_t>(lt) : ~0ull);
-    double gv = __longlong_as_double(static_cast<long long>(mvb));
-    uint32_t gt = static_cast<uint32_t>(mtb);
-    const double rv = rp < n_in ? in_v[rp] : kInf;
-    const uint32_t rt = rp < n_in ? in_t[rp] : 0xffffffffu;
-    if (rv < gv || (rv == gv && rt < gt)) {
-      gv = rv;
-      gt = rt;
+    const double gv = __longlong_as_double(static_cast<long long>(mvb));
+    const uint32_t gt = static_cast<uint32_t>(mtb);
+    // the running list's entries below it come next, as one run (up to a
+    // wavefront's worth per round; lane j checks entry rp + j)
+    bool below = false;
+    if (rp + lane < n_in && out + lane < k) {
+      const double v = in_v[rp + lane];
+      const uint32_t t = in_t[rp + lane];
+      below = v < gv || (v == gv && t < gt);
+    }
+    const uint64_t bm = __ballot(below);
+    const int run = ~bm == 0 ? kWave : __builtin_ctzll(~bm);
+    if (run > 0) {
+      if (lane < run) {
+        out_v[out + lane] = in_v[rp + lane];
+        out_t[out + lane] = in_t[rp + lane];
+      }
+      out += run;
+      rp += run;
+      continue;
     }
     if (gt == 0xffffffffu) break;  // every list is exhausted
+    // With one staged list left (a query's first round has one item), its
+    // entries below the running head come next, as one run likewise.
+    int live = 0, owner = 0, oslot = 0;
+#pragma unroll
+    for (int i = 0; i < kMergeSlots; ++i) {
+      const uint64_t bl = __ballot(pos[i] < cnt[i]);
+      if (bl != 0 && live == 0) {
+        owner = __builtin_ctzll(bl);
+        oslot = i;
+      }
+      live += __popcll(bl);
+    }
+    if (live == 1) {
+      int po = 0, oo = 0, co = 0;
+#pragma unroll
+      for (int i = 0; i < kMergeSlots; ++i)
+        if (i == oslot) {
+          po = pos[i];
+          oo = off[i];
+          co = cnt[i];
+        }
+      po = __shfl(po, owner, kWave);
+      oo = __shfl(oo, owner, kWave);
+      co = __shfl(co, owner, kWave);
+      const double rv = rp < n_in ? in_v[rp] : kInf;
+      const uint32_t rt = rp < n_in ? in_t[rp] : 0xffffffffu;
+      bool take = false;
+      if (po + lane < co && out + lane < k) {
+        const double v = stage_v[oo + po + lane];
+        const uint32_t t = stage_t[oo + po + lane];
+        take = v < rv || (v == rv && t < rt);
+      }
+      const uint64_t tm = __ballot(take);
+      const int run2 = ~tm == 0 ? kWave : __builtin_ctzll(~tm);
+      if (run2 > 0) {
+        if (lane < run2) {
+          out_v[out + lane] = stage_v[oo + po + lane];
+          out_t[out + lane] = stage_t[oo + po + lane];
+        }
+        out += run2;
+        if (lane == owner) {
+#pragma unroll
+          for (int i = 0; i < kMergeSlots; ++i)
+            if (i == oslot) {
+              pos[i] += run2;
+              const bool more = pos[i] < cnt[i];
+              hv[i] = more ? stage_v[off[i] + pos[i]] : kInf;
+              ht[i] = more ? stage_t[off[i] + pos[i]] : 0xffffffffu;
+            }
+        }
+        continue;
+      }
+    }
+    // else the staged minimum (the running head too when it is the same row)
     if (lane == 0) {
       out_v[out] = gv;
       out_t[out] = gt;
     }
     ++out;
-    if (rv == gv && rt == gt) ++rp;
+    if (rp < n_in && in_v[rp] == gv && in_t[rp] == gt) ++rp;
 #pragma unroll
     for (int i = 0; i < kMergeSlots; ++i) {
       if (hv[i] == gv && ht[i] == gt) {
