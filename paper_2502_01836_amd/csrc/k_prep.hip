@@ -213,8 +213,25 @@ __device__ inline void block_sort_u64(uint64_t *keys, int P) {
 // The same arithmetic as the separate kernels (k_qprep, k_lb, k_order,
 // select_pair_of).  Work-group 0 also zeroes the batch's control words, leaf
 // counts and filter-pair counts.
+// summary_lb of leaf L from the boxes laid out as [S][4][N] (consecutive
+// leaves read consecutive words): the same operations in the same order, so
+// the same value.
+__device__ __forceinline__ float summary_lb_cols(const float *qs, const float *__restrict__ bt, int N, int L, int S,
+                                                 int m) {
+  float acc = 0.0f;
+  for (int s = 0; s < S; ++s) {
+    const float *b = bt + static_cast<int64_t>(4 * s) * N + L;
+    float len = static_cast<float>(((s + 1) * m) / S - (s * m) / S);
+    float mq = qs[2 * s], sq = qs[2 * s + 1];
+    float gm = fmaxf(fmaxf(b[0] - mq, mq - b[N]), 0.0f);
+    float gs = fmaxf(fmaxf(b[2 * N] - sq, sq - b[3 * N]), 0.0f);
+    acc += len * (gm * gm + gs * gs);
+  }
+  return sqrtf(acc);
+}
+
 __global__ void __launch_bounds__(256) k_query_setup(const float *__restrict__ raw, int m, int S,
-                                                     const float *__restrict__ boxes, int N, int P, float *q32,
+                                                     const float *__restrict__ boxes_t, int N, int P, float *q32,
                                                      uint16_t *q16, float *qn16, float *qeps, float *qstat, float *lb, int32_t *order, float *lbs,
                                                      const int32_t *__restrict__ k_dev, const float *__restrict__ t_dev,
                                                      int n_pairs, const int32_t *__restrict__ pair_k,
@@ -274,7 +291,7 @@ __global__ void __launch_bounds__(256) k_query_setup(const float *__restrict__ r
   for (int i = threadIdx.x; i < P; i += blockDim.x) {
     uint64_t key = kKeyMax;
     if (i < N) {
-      const float v = summary_lb(st, boxes + static_cast<int64_t>(i) * S * 4, S, m);
+      const float v = summary_lb_cols(st, boxes_t, N, i, S, m);
       lb[q * N + i] = v;
       key = make_key(v, static_cast<uint32_t>(i));
     }
@@ -552,7 +569,7 @@ void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float 
   const int P = pow2_at_least(N < 2 ? 2 : N);
   const size_t lds = static_cast<size_t>(P) * sizeof(uint64_t) + (static_cast<size_t>(m) + 2 * S) * sizeof(float);
   allow_lds(reinterpret_cast<const void *>(k_query_setup), lds);
-  hipLaunchKernelGGL(k_query_setup, dim3(static_cast<unsigned>(nq)), dim3(256), lds, st, raw, m, S, boxes, N, P, q32,
+  hipLaunchKernelGGL(k_query_setup, dim3(static_cast<unsigned>(nq)), dim3(256), lds, st, raw, m, S, boxes_t, N, P, q32,
                      q16, qn16, qeps, qstat, lb, order, lbs, k_dev, t_dev, n_pairs, pair_k, pair_t, kmax, b, F, pcnt);
   LAUNCH_OK("query_setup");
 }

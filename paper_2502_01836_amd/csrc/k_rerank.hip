@@ -319,6 +319,7 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
     const int kp = item_kprime(b.kp_query, kprime, k, bf16 != 0);
     const int PKi = pow2_at_least(kp < 2 ? 2 : kp);
     int n = C * kprime;
+    uint64_t kth_override = 0;  // nonzero: the certificate's key (see below)
     if (kp <= kSelectMax && n <= kWave * kSelectPerLane) {
       // few keys wanted from many: kp rounds of a wavefront minimum, each
       // lane holding as few registers as n needs
@@ -327,6 +328,43 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
       else if (n <= 4 * kWave) select_keys<4>(cand, t0, G, g, mq, j, kprime, kp, n, lane, buf);
       else select_keys<kSelectPerLane>(cand, t0, G, g, mq, j, kprime, kp, n, lane, buf);
       wave_lds_sync();
+    } else if (qbound) {
+      // Search rounds: only keys whose lower bound does not exceed the
+      // query's bound U can enter its top k.  They are a prefix of the sorted
+      // keys (the bound grows with the key), so they are gathered and sorted
+      // alone and the item's results do not change.  With fewer than kp of
+      // them the kp-th key is among the dropped ones: the smallest dropped
+      // key, whose bound exceeds U, certifies every row left out.
+      const double Ud = static_cast<double>(qbound[q]);
+      const double dq = bf16_delta(static_cast<double>(qn_q), m);
+      const uint64_t lanes_below = (1ull << lane) - 1ull;
+      int nf = 0;
+      uint64_t dropped = kKeyMax;
+      for (int e0 = 0; e0 < n; e0 += kWave) {
+        const int e = e0 + lane;
+        uint64_t v = kKeyMax;
+        if (e < n) {
+          const int c = e / kprime;
+          v = cand[(tile_of(b.tile_start, L, g, c, G) * mq + j) * kprime + (e - c * kprime)];
+        }
+        bool keep = false;
+        if (v != kKeyMax) {
+          const double x = static_cast<double>(key_d2(v)) - dq;
+          const double lower = (x > 0.0 ? sqrt(x) : 0.0) - qe_q - le_L;
+          keep = !(lower > Ud);
+          if (!keep) dropped = v < dropped ? v : dropped;
+        }
+        const uint64_t km = __ballot(keep);
+        if (keep) buf[nf + __popcll(km & lanes_below)] = v;
+        nf += __popcll(km);
+      }
+      dropped = wave_min_u64(dropped);
+      const int want = nf > kp ? nf : kp;
+      const int P = pow2_at_least(want < 2 ? 2 : want);
+      for (int e = nf + lane; e < P; e += kWave) buf[e] = kKeyMax;
+      wave_lds_sync();
+      wave_sort_u64(buf, P, lane);
+      if (nf < kp) kth_override = dropped;
     } else {
       int P = pow2_at_least(n < 2 ? 2 : n);
       for (int e = lane; e < P; e += kWave) {
@@ -340,7 +378,7 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
       wave_lds_sync();
       wave_sort_u64(buf, P, lane);
     }
-    uint64_t kth = buf[kp - 1];
+    uint64_t kth = kth_override != 0 ? kth_override : buf[kp - 1];
     // number of real candidates among the first kp
     int nc = 0;
     for (int e = 0; e < kp; ++e) nc += buf[e] != kKeyMax ? 1 : 0;
