@@ -187,10 +187,69 @@ __global__ void __launch_bounds__(256) k_lb(const float *__restrict__ qstat, int
   lb[q * N + L] = summary_lb(qstat + q * S * 2, boxes + static_cast<int64_t>(L) * S * 4, S, m);
 }
 
-// Work-group bitonic sort of P keys in LDS (P a power of two).
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+  const uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), mask, kWave);
+  const uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), mask, kWave);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Bitonic stage `size`, strides smax .. 1, on a wavefront's chunk of 128 keys
+// at `base` held in registers (x: element lane, y: element 64 + lane): the
+// same compare-exchanges as the work-group passes below, without LDS or
+// barriers.  A pair (lo, lo + stride) ascends when (base + lo) & size is 0.
+__device__ inline void chunk_stages(uint64_t &x, uint64_t &y, int base, int size, int smax, int lane) {
+  for (int stride = smax; stride >= 1; stride >>= 1) {
+    if (stride == kWave) {
+      const bool up = ((base + lane) & size) == 0;
+      const uint64_t a = x < y ? x : y, b = x < y ? y : x;
+      x = up ? a : b;
+      y = up ? b : a;
+    } else {
+      const uint64_t px = shfl_xor_u64(x, stride), py = shfl_xor_u64(y, stride);
+      const int lo = lane & ~stride;
+      const bool am_lo = (lane & stride) == 0;
+      const bool upx = ((base + lo) & size) == 0, upy = ((base + kWave + lo) & size) == 0;
+      x = (am_lo == upx) ? (x < px ? x : px) : (x < px ? px : x);
+      y = (am_lo == upy) ? (y < py ? y : py) : (y < py ? py : y);
+    }
+  }
+}
+
+// Work-group bitonic sort of P keys in LDS (P a power of two; the
+// work-group a multiple of 64 threads).  Stages of stride below 128 run in
+// registers on chunks of 128 keys, one wavefront per chunk; only the larger
+// strides go through LDS with a barrier each.
 __device__ inline void block_sort_u64(uint64_t *keys, int P) {
-  for (int size = 2; size <= P; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+  if (P < 2 * kWave) {
+    for (int size = 2; size <= P; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < (P >> 1); i += blockDim.x) {
+          int lo = 2 * i - (i & (stride - 1));
+          int hi = lo + stride;
+          bool up = (lo & size) == 0;
+          uint64_t x = keys[lo], y = keys[hi];
+          if ((x > y) == up) {
+            keys[lo] = y;
+            keys[hi] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    return;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  constexpr int kChunk = 2 * kWave;
+  for (int c = wave; c < P / kChunk; c += nw) {
+    const int base = c * kChunk;
+    uint64_t x = keys[base + lane], y = keys[base + kWave + lane];
+    for (int size = 2; size <= kChunk; size <<= 1) chunk_stages(x, y, base, size, size >> 1, lane);
+    keys[base + lane] = x;
+    keys[base + kWave + lane] = y;
+  }
+  __syncthreads();
+  for (int size = 2 * kChunk; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride >= kChunk; stride >>= 1) {
       for (int i = threadIdx.x; i < (P >> 1); i += blockDim.x) {
         int lo = 2 * i - (i & (stride - 1));
         int hi = lo + stride;
@@ -203,6 +262,14 @@ __device__ inline void block_sort_u64(uint64_t *keys, int P) {
       }
       __syncthreads();
     }
+    for (int c = wave; c < P / kChunk; c += nw) {
+      const int base = c * kChunk;
+      uint64_t x = keys[base + lane], y = keys[base + kWave + lane];
+      chunk_stages(x, y, base, size, kWave, lane);
+      keys[base + lane] = x;
+      keys[base + kWave + lane] = y;
+    }
+    __syncthreads();
   }
 }
 
@@ -230,7 +297,7 @@ __device__ __forceinline__ float summary_lb_cols(const float *qs, const float *_
   return sqrtf(acc);
 }
 
-__global__ void __launch_bounds__(256) k_query_setup(const float *__restrict__ raw, int m, int S,
+__global__ void __launch_bounds__(512) k_query_setup(const float *__restrict__ raw, int m, int S,
                                                      const float *__restrict__ boxes_t, int N, int P, float *q32,
                                                      uint16_t *q16, float *qn16, float *qeps, float *qstat, float *lb, int32_t *order, float *lbs,
                                                      const int32_t *__restrict__ k_dev, const float *__restrict__ t_dev,
@@ -569,7 +636,7 @@ void launch_query_setup(const float *raw, int64_t nq, int m, int S, const float 
   const int P = pow2_at_least(N < 2 ? 2 : N);
   const size_t lds = static_cast<size_t>(P) * sizeof(uint64_t) + (static_cast<size_t>(m) + 2 * S) * sizeof(float);
   allow_lds(reinterpret_cast<const void *>(k_query_setup), lds);
-  hipLaunchKernelGGL(k_query_setup, dim3(static_cast<unsigned>(nq)), dim3(256), lds, st, raw, m, S, boxes_t, N, P, q32,
+  hipLaunchKernelGGL(k_query_setup, dim3(static_cast<unsigned>(nq)), dim3(512), lds, st, raw, m, S, boxes_t, N, P, q32,
                      q16, qn16, qeps, qstat, lb, order, lbs, k_dev, t_dev, n_pairs, pair_k, pair_t, kmax, b, F, pcnt);
   LAUNCH_OK("query_setup");
 }
