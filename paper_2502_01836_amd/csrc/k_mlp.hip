@@ -1150,11 +1150,20 @@ void infer_ws_mt(const float *w, int F, int m, int h, const float *x, int64_t nq
 }
 
 // The weights-in-registers inference for the shapes the matrix-core training
-// serves; false (nothing launched) for others.
+// serves and at least one filter per CU; false (nothing launched) otherwise.
 bool infer_ws(const float *w, int F, int m, int h, const float *x, int64_t nq, float *out, const int64_t *plist,
               const int32_t *pcnt, int64_t stride, int N, const int32_t *pair, const float *offsets, float *dfo,
               int rows_cap, hipStream_t st) {
   if (!train_mfma_ok(m, h)) return false;
+  // one work-group per filter: with fewer filters than CUs the query-tile
+  // kernels, which spread a filter's rows over several work-groups, finish first
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  if (F < cus) return false;
   switch (m / 16) {
 #define LEAFI_WS(k) \
   case k: infer_ws_mt<k>(w, F, m, h, x, nq, out, plist, pcnt, stride, N, pair, offsets, dfo, rows_cap, st); return true;

@@ -214,7 +214,9 @@ def test_duplicates_tie_break_by_id_and_empty_batch():
 
 def test_mlp_infer_matches_oracle():
     pkg = _pkg()
-    for (F, m, h, nq) in [(5, 256, 256, 100), (3, 96, 96, 70), (2, 64, 36, 5)]:
+    # a few filters run the query-tile kernels; 300 (at least one per CU) the
+    # weights-in-registers kernel
+    for (F, m, h, nq) in [(5, 256, 256, 100), (3, 96, 96, 70), (2, 64, 36, 5), (300, 64, 64, 40), (260, 256, 256, 9)]:
         w = W.mlp_weights(F, m, h, seed=F + m)
         x = O.znorm(W.random_walk(nq, m, seed=m))
         got = pkg.mlp_infer(torch.from_numpy(w).cuda(), m, h, torch.from_numpy(x).cuda()).cpu().numpy()
