@@ -240,16 +240,17 @@ __device__ __forceinline__ void load_rows(const uint16_t *x16, int64_t base, int
 // `nxt`, MFMAs on `cur`, candidate appends, then list maintenance.
 template <int KS, int QB>
 __device__ __forceinline__ void scan_block(const StoreView &s, const TileInfo &ti, int64_t base, bf16x8 (&cur)[KS],
-                                           bf16x8 (&nxt)[KS], bool more, const uint16_t *qs, int qstride,
+                                           bf16x8 (&nxt)[KS], int64_t pre, const uint16_t *qs, int qstride,
                                            const float (&qn)[QB], uint32_t *keys, int *cnt, uint32_t *thr, int cap,
                                            const int *kpl, bool check, int room, int wave, int lane) {
   constexpr int kWaves = 4;
   const int64_t rowc = base + 16 * wave + 4 * (lane >> 4);
   const float4 xn = *reinterpret_cast<const float4 *>(s.xn16 + rowc);
-  // unconditional (the last block of a tile re-reads its own rows, which are
-  // cached): a branch here would leave the in-flight load count ambiguous and
-  // make the compiler drain every load before the MFMAs
-  load_rows<KS>(s.x16, more ? base + 64 : base, wave, lane, s.m, nxt);
+  // rows `pre` into nxt, unconditionally (past the tile's last block a valid
+  // block is read again, from cache): a branch here would leave the
+  // in-flight load count ambiguous and make the compiler drain every load
+  // before the MFMAs
+  load_rows<KS>(s.x16, pre, wave, lane, s.m, nxt);
   floatx4 acc[QB];
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) acc[qb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -336,8 +337,19 @@ __global__ void __launch_bounds__(256, QB >= 3 ? 2 : 4) k_scan_bf16(StoreView s,
     TileInfo ti = decode_tile(t, s, b, MQ, s_leaf);
     // The tile's first rows are requested before its queries are staged, so
     // the two sets of loads are in flight together.
-    bf16x8 a0[KS], a1[KS];
+    // Row buffers: two (ping-pong, the next block in flight), or four
+    // (three blocks in flight) for 48 and 64 queries per tile, whose two
+    // work-groups per CU leave the registers for them, on rows of up to 128
+    // elements: a block of those carries too few products to cover a load's
+    // latency, while rows of 256 gain nothing from the deeper pipeline
+    // (measured: 25M x 96 +9 %, 10M and 50M x 256 flat or slower).
+    constexpr int kBufs = (QB >= 3 && KS <= 4) ? 4 : 2;
+    bf16x8 a0[KS], a1[KS], a2[kBufs > 2 ? KS : 1], a3[kBufs > 2 ? KS : 1];
     load_rows<KS>(s.x16, ti.r0, wave, lane, m, a0);
+    if constexpr (kBufs > 2) {
+      load_rows<KS>(s.x16, ti.r0 + 64 < ti.r1 ? ti.r0 + 64 : ti.r0, wave, lane, m, a1);
+      load_rows<KS>(s.x16, ti.r0 + 128 < ti.r1 ? ti.r0 + 128 : ti.r0, wave, lane, m, a2);
+    }
     if (threadIdx.x < MQ) {
       const int j = threadIdx.x;
       cnt[j] = 0;
@@ -382,11 +394,30 @@ __global__ void __launch_bounds__(256, QB >= 3 ? 2 : 4) k_scan_bf16(StoreView s,
     // of appends when the capacity allows (uniform)
     const bool pair = cap - kprime >= 128;
     const int room = pair ? 128 : 64;
-    for (int64_t base = ti.r0; base < ti.r1; base += 128) {
-      scan_block<KS, QB>(s, ti, base, a0, a1, true, qs, qstride, qn, keys, cnt, thr, cap, kpl, !pair, room, wave,
-                         lane);
-      scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1, qs, qstride, qn, keys, cnt, thr, cap, kpl,
-                         true, room, wave, lane);
+    if constexpr (kBufs == 2) {
+      for (int64_t base = ti.r0; base < ti.r1; base += 128) {
+        scan_block<KS, QB>(s, ti, base, a0, a1, base + 64, qs, qstride, qn, keys, cnt, thr, cap, kpl, !pair, room,
+                           wave, lane);
+        scan_block<KS, QB>(s, ti, base + 64, a1, a0, base + 128 < ti.r1 ? base + 128 : base + 64, qs, qstride, qn,
+                           keys, cnt, thr, cap, kpl, true, room, wave, lane);
+      }
+    } else {
+      // block b is in buffer b mod 4 and requests block b + 3 (a re-read of
+      // the tile's first block past its end); blocks come in pairs, so a
+      // group of four may end after its second
+      auto pre = [&](int64_t row) { return row < ti.r1 ? row : ti.r0; };
+      for (int64_t base = ti.r0; base < ti.r1; base += 256) {
+        scan_block<KS, QB>(s, ti, base, a0, a3, pre(base + 192), qs, qstride, qn, keys, cnt, thr, cap, kpl, !pair,
+                           room, wave, lane);
+        scan_block<KS, QB>(s, ti, base + 64, a1, a0, pre(base + 256), qs, qstride, qn, keys, cnt, thr, cap, kpl, true,
+                           room, wave, lane);
+        if (base + 128 < ti.r1) {  // uniform
+          scan_block<KS, QB>(s, ti, base + 128, a2, a1, pre(base + 320), qs, qstride, qn, keys, cnt, thr, cap, kpl,
+                             !pair, room, wave, lane);
+          scan_block<KS, QB>(s, ti, base + 192, a3, a2, pre(base + 384), qs, qstride, qn, keys, cnt, thr, cap, kpl,
+                             true, room, wave, lane);
+        }
+      }
     }
     finish_tile(keys, cnt, thr, kpl, t, MQ, ti.nqt, cap, kprime, ti.r0, wave, kWaves, lane, cand);
     __syncthreads();
