@@ -430,7 +430,6 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   if (bound) {
     launch_query_bound(s, q, b, nq, mq, kprime, kmax, ix->max_chunks_for(chunk), ix->leaf_eps_max, w.cand.get(),
                        w.qbound.get(), st);
-    launch_rerank_skip(s, q, b, mq, kprime, w.cand.get(), w.qbound.get(), ib, ro->small ? 1 : ix->num_cus, st);
   }
   launch_item_rerank(s, q, b, mq, kprime, kmax, bf16, w.cand.get(), grid_r, ix->max_chunks_for(chunk), st,
                      bound ? w.qbound.get() : nullptr);

@@ -4,9 +4,9 @@
 //
 // After a pass's scan every (query, tile) list holds its kprime best keys
 // (truncated BF16 or FP32 squared distances with rows).  k_query_bound finds
-// per query an upper bound U of its k-th distance after the round;
-// k_rerank_skip certifies the items whose every candidate is provably beyond
-// U and lists the rest; k_item_rerank merges each listed item's chunk lists
+// per query an upper bound U of its k-th distance after the round, then
+// certifies the query's items whose every candidate is provably beyond U and
+// lists the rest; k_item_rerank merges each listed item's chunk lists
 // and reranks its candidates in FP32 (FP64 within the error band of the k-th),
 // writing the item's exact top-k and the bound that certifies the rest.
 #include <algorithm>
@@ -144,10 +144,52 @@ __device__ inline int bound_pass(int64_t q, int N, int k, int kprime, int mq, in
   return o;
 }
 
+// One item of a search round: each chunk list is sorted, so its first key is
+// its smallest, and every row of the item has a key at least the smallest of
+// them (or was never a candidate: key >= the tau threshold).  When even that
+// bound exceeds the query's bound U, no row of the item can enter the query's
+// top k: the item contributes nothing and is certified by that bound (no
+// sort, no rerank).  Returns whether the item still needs its rerank.
+__device__ inline bool item_live_after_bound(const StoreView &s, const QueryView &qv, const RoundBufs &b, int mq,
+                                             int kprime, const uint64_t *__restrict__ cand, int item, int64_t q,
+                                             float U) {
+  const int m = s.m;
+  const int L = b.item_leaf[item];
+  const int ist0 = b.leaf_istart[L], ist1 = b.leaf_istart[L + 1];
+  const int64_t off0 = s.leaf_off[L], off1 = s.leaf_off[L + 1];
+  const float tau_q = b.tau[q], qn_q = qv.qn16[q], qe_q = qv.qeps[q], le_L = s.leaf_eps[L];
+  const int64_t t0 = b.tile_start[L];
+  const int pos = item - ist0;
+  const int g = pos / mq, j = pos - g * mq;
+  const int C = static_cast<int>((off1 - off0 + b.chunk - 1) / b.chunk);
+  const int G = (ist1 - ist0 + mq - 1) / mq;
+  uint64_t h = kKeyMax;
+  for (int c = 0; c < C; ++c) {
+    const uint64_t v = cand[((t0 + static_cast<int64_t>(c) * G + g) * mq + j) * kprime];
+    h = v < h ? v : h;
+  }
+  float kd = h != kKeyMax ? key_d2(h) : __builtin_inff();
+  kd = fminf(kd, tau_threshold(tau_q, qn_q, qe_q, le_L, m));
+  double lower = -1.0;
+  if (kd < __builtin_inff()) {
+    const double v = static_cast<double>(kd) - bf16_delta(qn_q, m);
+    lower = (v > 0.0 ? sqrt(v) : 0.0) - qe_q - le_L;
+  }
+  if (lower > static_cast<double>(U)) {
+    float lb = static_cast<float>(lower);
+    if (static_cast<double>(lb) > lower) lb = nextafterf(lb, -__builtin_inff());
+    b.item_cnt[item] = 0;
+    b.item_bound[item] = lb;
+    return false;
+  }
+  return true;
+}
+
 // One work-group per query: its four wavefronts take every fourth pass of
 // 64 x kBoundSlots lists each and keep their k smallest keys; wavefront 0
 // then merges the four sorted results (a key held by two of them is one row,
-// counted once) up to the k-th.
+// counted once) up to the k-th.  With U known, the work-group certifies the
+// query's items by it and lists the others for the rerank.
 __global__ void __launch_bounds__(256) k_query_bound(StoreView s, QueryView qv, RoundBufs b, int64_t nq, int mq,
                                                      int kprime, int kmax, int cmax, float eps_max,
                                                      const uint64_t *__restrict__ cand, float *qbound) {
@@ -156,6 +198,7 @@ __global__ void __launch_bounds__(256) k_query_bound(StoreView s, QueryView qv, 
   uint64_t *buf0 = bsm + static_cast<size_t>(wave) * 2 * kmax, *buf1 = buf0 + kmax;
   int *s_n = reinterpret_cast<int *>(bsm + 8 * static_cast<size_t>(kmax));  // [4] result sizes
   int *s_res = s_n + 4;                                                     // [4] result offsets
+  float *s_u = reinterpret_cast<float *>(s_res + 4);                         // the query's bound
   // after a capacity overflow the item lists were never placed
   if (b.ctl[kCtlOverflow] != 0) return;
   const int N = s.N, m = s.m;
@@ -208,72 +251,28 @@ __global__ void __launch_bounds__(256) k_query_bound(StoreView s, QueryView qv, 
           if (static_cast<double>(u) < v) u = nextafterf(u, __builtin_inff());
           U = u < U ? u : U;
         }
+        if (lane == 0) *s_u = U;
+      }
+      __syncthreads();
+      U = *s_u;
+      // the query's items: certify by U what can be, list the rest in item_live
+      for (int r0 = wave * kWave; r0 < n_it; r0 += 4 * kWave) {
+        const int r = r0 + lane;
+        const bool live = r < n_it && item_live_after_bound(s, qv, b, mq, kprime, cand, b.qitem_idx[q * N + r], q, U);
+        const uint64_t mask = __ballot(live);
+        if (mask != 0) {
+          const int lead = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+          int at = 0;
+          if (lane == lead)
+            at = static_cast<int>(atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlLive),
+                                            static_cast<unsigned long long>(__popcll(mask))));
+          at = __shfl(at, lead, kWave);
+          if (live) b.item_live[at + __popcll(mask & ((1ull << lane) - 1))] = b.qitem_idx[q * N + r];
+        }
       }
     }
     if (threadIdx.x == 0) qbound[q] = U;
     __syncthreads();  // LDS is reused by the next query
-  }
-}
-
-// Per item of a search round, one lane each: each chunk list is sorted, so
-// its first key is its smallest, and every row of the item has a key at least
-// the smallest of them (or was never a candidate: key >= the tau threshold).
-// When even that bound exceeds the query's bound U, no row of the item can
-// enter the query's top k: the item contributes nothing and is certified by
-// that bound (no sort, no rerank).  The others are appended to item_live.
-__global__ void __launch_bounds__(256) k_rerank_skip(StoreView s, QueryView qv, RoundBufs b, int mq, int kprime,
-                                                     const uint64_t *__restrict__ cand,
-                                                     const float *__restrict__ qbound) {
-  const int n_items = static_cast<int>(b.ctl[kCtlItems]);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int m = s.m;
-  // whole wavefronts step together (the append below is wavefront-wide)
-  for (int base = blockIdx.x * blockDim.x + (threadIdx.x - lane); base < n_items; base += gridDim.x * blockDim.x) {
-    const int item = base + lane;
-    bool live = false;
-    if (item < n_items) {
-      const int L = b.item_leaf[item];
-      const int64_t q = b.item_q[item];
-      const int ist0 = b.leaf_istart[L], ist1 = b.leaf_istart[L + 1];
-      const int64_t off0 = s.leaf_off[L], off1 = s.leaf_off[L + 1];
-      const float tau_q = b.tau[q], qn_q = qv.qn16[q], qe_q = qv.qeps[q], le_L = s.leaf_eps[L];
-      const float U = qbound[q];
-      const int64_t t0 = b.tile_start[L];
-      const int pos = item - ist0;
-      const int g = pos / mq, j = pos - g * mq;
-      const int C = static_cast<int>((off1 - off0 + b.chunk - 1) / b.chunk);
-      const int G = (ist1 - ist0 + mq - 1) / mq;
-      uint64_t h = kKeyMax;
-      for (int c = 0; c < C; ++c) {
-        const uint64_t v = cand[((t0 + static_cast<int64_t>(c) * G + g) * mq + j) * kprime];
-        h = v < h ? v : h;
-      }
-      float kd = h != kKeyMax ? key_d2(h) : __builtin_inff();
-      kd = fminf(kd, tau_threshold(tau_q, qn_q, qe_q, le_L, m));
-      double lower = -1.0;
-      if (kd < __builtin_inff()) {
-        const double v = static_cast<double>(kd) - bf16_delta(qn_q, m);
-        lower = (v > 0.0 ? sqrt(v) : 0.0) - qe_q - le_L;
-      }
-      if (lower > static_cast<double>(U)) {
-        float lb = static_cast<float>(lower);
-        if (static_cast<double>(lb) > lower) lb = nextafterf(lb, -__builtin_inff());
-        b.item_cnt[item] = 0;
-        b.item_bound[item] = lb;
-      } else {
-        live = true;
-      }
-    }
-    const uint64_t mask = __ballot(live);
-    if (mask != 0) {
-      const int lead = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-      int at = 0;
-      if (lane == lead)
-        at = static_cast<int>(atomicAdd(reinterpret_cast<unsigned long long *>(b.ctl + kCtlLive),
-                                        static_cast<unsigned long long>(__popcll(mask))));
-      at = __shfl(at, lead, kWave);
-      if (live) b.item_live[at + __popcll(mask & ((1ull << lane) - 1))] = item;
-    }
   }
 }
 
@@ -300,7 +299,7 @@ __global__ void __launch_bounds__(256, 3) k_item_rerank(StoreView s, QueryView q
   // error constants (see the certificate below)
   const double u = 1.0 / 16777216.0;  // 2^-24
   const float delta32 = static_cast<float>(2.0 * (m + 4) * u);
-  // a search round reranks only the items k_rerank_skip listed
+  // a search round reranks only the items k_query_bound listed
   const int n_work = qbound ? static_cast<int>(b.ctl[kCtlLive]) : n_items;
   for (int w_i = blockIdx.x * wpb + wave; w_i < n_work; w_i += gridDim.x * wpb) {
     const int item = qbound ? b.item_live[w_i] : w_i;
@@ -580,7 +579,7 @@ int rerank_lds_bytes(int max_chunks, int kprime, int *PB) {
 void launch_query_bound(StoreView s, QueryView q, RoundBufs b, int64_t nq, int mq, int kprime, int kmax, int cmax,
                         float eps_max, const uint64_t *cand, float *qbound, hipStream_t st) {
   if (nq <= 0) return;
-  const size_t lds = 4 * 2 * static_cast<size_t>(kmax) * sizeof(uint64_t) + 8 * sizeof(int);
+  const size_t lds = 4 * 2 * static_cast<size_t>(kmax) * sizeof(uint64_t) + 12 * sizeof(int);
   const int64_t blocks = nq;  // one work-group per query
   hipLaunchKernelGGL(k_query_bound, dim3(static_cast<unsigned>(blocks < 65536 ? blocks : 65536)), dim3(256), lds, st, s,
                      q, b, nq, mq, kprime, kmax, cmax, eps_max, cand, qbound);
@@ -598,14 +597,6 @@ void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprim
   hipLaunchKernelGGL(k_item_rerank, dim3(blocks), dim3(64 * wpb), lds, st, s, q, b, mq, kprime, kmax, bf16 ? 1 : 0, PB,
                      static_cast<int>(slice / 8), cand, qbound);
   LAUNCH_OK("item_rerank");
-}
-
-void launch_rerank_skip(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, const uint64_t *cand,
-                        const float *qbound, int64_t items_bound, int num_cus, hipStream_t st) {
-  const int64_t want = ceil_div(std::max<int64_t>(items_bound, 1), 256);
-  const int blocks = static_cast<int>(std::min<int64_t>(want, static_cast<int64_t>(num_cus) * 8));
-  hipLaunchKernelGGL(k_rerank_skip, dim3(blocks), dim3(256), 0, st, s, q, b, mq, kprime, cand, qbound);
-  LAUNCH_OK("rerank_skip");
 }
 
 }  // namespace leafi

@@ -238,25 +238,22 @@ void launch_scan_bf16(StoreView s, QueryView q, RoundBufs b, int mq, int kprime,
 void launch_scan_fp32(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, uint64_t *cand, int grid,
                       hipStream_t st);
 
-// Per item: merge its tiles' candidates, rerank in FP32 (FP64 for the band
-// around the k-th), write the item's top-k and its certificate bound.  With
-// qbound (a search round) only the items launch_rerank_skip listed are
-// reranked.
 // Per query of a search round after its BF16 scan: qbound[q] = an upper bound
 // of the query's k-th distance after the round (from the k-th smallest key
 // over all its candidate lists, and its tau), for the rerank to skip
-// candidates that cannot enter its top k.  cmax = chunks of the largest leaf;
+// candidates that cannot enter its top k.  With the bound known, each of the
+// query's items whose every row is provably farther gets no results and that
+// bound as its certificate; the others are listed in item_live
+// (ctl[kCtlLive] of them) for the rerank.  cmax = chunks of the largest leaf;
 // eps_max = the largest leaf rounding radius.
 void launch_query_bound(StoreView s, QueryView q, RoundBufs b, int64_t nq, int mq, int kprime, int kmax, int cmax,
                         float eps_max, const uint64_t *cand, float *qbound, hipStream_t st);
+// Per item: merge its tiles' candidates, rerank in FP32 (FP64 for the band
+// around the k-th), write the item's top-k and its certificate bound.  With
+// qbound (a search round) only the items launch_query_bound listed are
+// reranked.
 void launch_item_rerank(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, int kmax, bool bf16,
                         const uint64_t *cand, int grid, int max_chunks, hipStream_t st, const float *qbound = nullptr);
-// Per item of a search round after launch_query_bound: an item whose every
-// row is provably farther than its query's bound gets no results and that
-// bound as its certificate; the others are listed in item_live for the
-// rerank.  items_bound >= the round's item count sizes the grid.
-void launch_rerank_skip(StoreView s, QueryView q, RoundBufs b, int mq, int kprime, const uint64_t *cand,
-                        const float *qbound, int64_t items_bound, int num_cus, hipStream_t st);
 
 // Candidate-list geometry for kprime kept keys: queries per tile and list
 // capacity.  BF16: mq_pref queries per tile (16, 32, 48 or 64; others mean
