@@ -425,8 +425,10 @@ int64_t scan_round(leafi_index *ix, int64_t nq, bool bf16, int kprime, int kmax,
   // one wavefront per item, a persistent grid of what is resident at once
   // (three four-wavefront work-groups per CU)
   int grid_r = static_cast<int>(std::min<int64_t>(ib, static_cast<int64_t>(ix->num_cus) * (ro->small ? 1 : 12)));
-  // a search round's rerank skips candidates that cannot enter their query's top k
-  const bool bound = bf16 && ro->use_tau;
+  // a search round's rerank skips candidates that cannot enter their query's
+  // top k; not in a round of one leaf per query, whose bound comes from that
+  // one item's own keys: it certifies no item and trims few candidates
+  const bool bound = bf16 && ro->use_tau && !ro->one_leaf;
   if (bound) {
     launch_query_bound(s, q, b, nq, mq, kprime, kmax, ix->max_chunks_for(chunk), ix->leaf_eps_max, w.cand.get(),
                        w.qbound.get(), st);
