@@ -42,50 +42,78 @@ __device__ inline CascadeCount cascade_query(int64_t q, int N, const float *__re
     const float *fq = use_f ? dfo + q * N : nullptr;
     const int32_t *oq = order + q * N;
     const uint64_t lt = (1ull << lane) - 1ull;
-    while (pos < N && (want == 0 || c.cnt < want)) {
-      const int p = pos + lane;
-      const bool valid = p < N;
-      // three independent coalesced loads per position: leaf, bound, filter value
-      const int L = valid ? oq[p] : 0;
-      const bool lbbad = valid && lbq[p] > tau_lb;
-      const float fv = valid && use_f ? fq[p] : -__builtin_inff();
-      const uint64_t mbad = __ballot(lbbad);
-      const int nvalid = N - pos < kWave ? N - pos : kWave;
-      const int s = mbad ? __ffsll(static_cast<unsigned long long>(mbad)) - 1 : kWave;
-      const int stop = s < nvalid ? s : nvalid;
-      const bool in = lane < stop;
-      const bool fpr = in && fv > tau;
-      const bool surv = in && !fpr;
-      uint64_t msurv = __ballot(surv);
-      int end = stop;
-      bool cut = false;
-      if (want > 0 && __popcll(msurv) > want - c.cnt) {
-        const int need = want - c.cnt;
-        const int rank = __popcll(msurv & lt);
-        const uint64_t mlast = __ballot(surv && rank == need - 1);
-        end = __ffsll(static_cast<unsigned long long>(mlast));  // one past the need-th survivor
-        msurv &= end >= kWave ? ~0ull : ((1ull << end) - 1ull);
-        cut = true;
+    // the loads of kAhead steps of 64 positions are in flight together (the
+    // walk is a chain of steps, each otherwise waiting on its own loads)
+    constexpr int kAhead = 4;
+    bool done = false;
+    while (!done && pos < N && (want == 0 || c.cnt < want)) {
+      int Lv[kAhead];
+      bool badv[kAhead];
+      float fvv[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int p = pos + kWave * u + lane;
+        const bool valid = p < N;
+        // three independent coalesced loads per position: leaf, bound, filter value
+        Lv[u] = valid ? oq[p] : 0;
+        badv[u] = valid && lbq[p] > tau_lb;
+        fvv[u] = valid && use_f ? fq[p] : -__builtin_inff();
       }
-      const uint64_t mend = end >= kWave ? ~0ull : ((1ull << end) - 1ull);
-      if ((msurv >> lane) & 1ull) {
-        const int rank = __popcll(msurv & lt);
-        b.qitem_leaf[q * N + base + c.cnt + rank] = L;
-        atomicAdd(b.leaf_cnt + L, 1);
-        c.series += leaf_n[L];
+      // the leaves' series counts, all requested before any is used
+      int nv[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) nv[u] = leaf_n[Lv[u]];
+      // step u starts at the iteration's first position + 64 u: every step
+      // before it was a full 64 positions, or the walk has ended
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        if (pos >= N || (want != 0 && c.cnt >= want)) {
+          done = true;
+          break;
+        }
+        const int L = Lv[u];
+        const bool lbbad = badv[u];
+        const float fv = fvv[u];
+        const uint64_t mbad = __ballot(lbbad);
+        const int nvalid = N - pos < kWave ? N - pos : kWave;
+        const int s = mbad ? __ffsll(static_cast<unsigned long long>(mbad)) - 1 : kWave;
+        const int stop = s < nvalid ? s : nvalid;
+        const bool in = lane < stop;
+        const bool fpr = in && fv > tau;
+        const bool surv = in && !fpr;
+        uint64_t msurv = __ballot(surv);
+        int end = stop;
+        bool cut = false;
+        if (want > 0 && __popcll(msurv) > want - c.cnt) {
+          const int need = want - c.cnt;
+          const int rank = __popcll(msurv & lt);
+          const uint64_t mlast = __ballot(surv && rank == need - 1);
+          end = __ffsll(static_cast<unsigned long long>(mlast));  // one past the need-th survivor
+          msurv &= end >= kWave ? ~0ull : ((1ull << end) - 1ull);
+          cut = true;
+        }
+        const uint64_t mend = end >= kWave ? ~0ull : ((1ull << end) - 1ull);
+        if ((msurv >> lane) & 1ull) {
+          const int rank = __popcll(msurv & lt);
+          b.qitem_leaf[q * N + base + c.cnt + rank] = L;
+          atomicAdd(b.leaf_cnt + L, 1);
+          c.series += nv[u];
+        }
+        c.cnt += __popcll(msurv);
+        c.fp += __popcll(__ballot(fpr) & mend);
+        if (cut) {
+          pos += end;
+          done = true;
+          break;
+        }
+        if (s < nvalid) {
+          c.lbp += N - (pos + s);
+          pos = N;
+          done = true;
+          break;
+        }
+        pos += nvalid;
       }
-      c.cnt += __popcll(msurv);
-      c.fp += __popcll(__ballot(fpr) & mend);
-      if (cut) {
-        pos += end;
-        break;
-      }
-      if (s < nvalid) {
-        c.lbp += N - (pos + s);
-        pos = N;
-        break;
-      }
-      pos += nvalid;
     }
   }
   c.series = wave_sum(c.series);
