@@ -830,15 +830,46 @@ __global__ void __launch_bounds__(256) k_query_merge(int64_t nq, int N, int kmax
             }
           }
         } else {
-          for (int pos = cur + lane; pos < N; pos += kWave) {
-            const int64_t idx = q * N + pos;
-            const int f = fp.filt_of_leaf[fp.order[idx]];
-            if (f < 0 || fp.lbs[idx] > tau_now * (1.0f + kLbSlack)) {
-              fp.dfo[idx] = -__builtin_inff();
-            } else {
-              fp.plist[static_cast<int64_t>(f) * nq + atomicAdd(fp.pcnt + f, 1)] = idx;
-              ++n_fe;
+          // The bounds ascend along the visit order, so the positions within
+          // the cutoff are a prefix: the walk ends at the first one past it.
+          // No later cascade reaches a position past it (tau only falls), so
+          // those keep no filter value.  Four steps of 64 positions have
+          // their loads in flight together.
+          const float cutoff = tau_now * (1.0f + kLbSlack);
+          constexpr int kAhead = 4;
+          for (int pos0 = cur; pos0 < N; pos0 += kAhead * kWave) {
+            float lv[kAhead];
+            int ov[kAhead], fv[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+              const int pos = pos0 + kWave * u + lane;
+              const int64_t idx = q * N + pos;
+              lv[u] = pos < N ? fp.lbs[idx] : __builtin_inff();
+              ov[u] = pos < N ? fp.order[idx] : 0;
             }
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) fv[u] = fp.filt_of_leaf[ov[u]];
+            bool end = false;
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+              const int pos = pos0 + kWave * u + lane;
+              const int64_t idx = q * N + pos;
+              const bool within = pos < N && lv[u] <= cutoff;
+              if (within) {
+                const int f = fv[u];
+                if (f < 0) {
+                  fp.dfo[idx] = -__builtin_inff();
+                } else {
+                  fp.plist[static_cast<int64_t>(f) * nq + atomicAdd(fp.pcnt + f, 1)] = idx;
+                  ++n_fe;
+                }
+              }
+              if (__ballot(!within) != 0) {  // uniform: every later position is past the cutoff
+                end = true;
+                break;
+              }
+            }
+            if (end) break;
           }
         }
       }
