@@ -170,9 +170,9 @@ __global__ void __launch_bounds__(64 * kListWaves) k_worklist(int64_t nq, int N,
 // Filter pairs worth evaluating once tau is known: every (query, visit
 // position) ahead of the cursor whose leaf has a filter and whose bound does
 // not prune it.  Later rounds only lower tau, so no other pair can reach the
-// filter test.  Filter f collects its entries q * N + position in
-// plist[f * nq + ...]; every other position ahead of the cursor gets
-// dfo = -inf.
+// filter test, and no cascade reaches a position whose bound prunes it now.
+// Filter f collects its entries q * N + position in plist[f * nq + ...]; the
+// other positions ahead of the cursor within the bound get dfo = -inf.
 __global__ void __launch_bounds__(256) k_filter_pairs(int64_t nq, int N, const float *__restrict__ lbs,
                                                       const int32_t *__restrict__ order,
                                                       const int32_t *__restrict__ filt_of_leaf, RoundBufs b,
@@ -187,8 +187,9 @@ __global__ void __launch_bounds__(256) k_filter_pairs(int64_t nq, int N, const f
     const int pos = static_cast<int>(idx - q * N);
     if (qround && qround[q] != 1) continue;  // serving: only queries that just finished their first round
     if (pos < b.cursor[q] || b.pair[q] < 0) continue;
+    if (lbs[idx] > b.tau[q] * (1.0f + kLbSlack)) continue;  // pruned by its bound in every later round
     const int f = filt_of_leaf[order[idx]];
-    if (f < 0 || lbs[idx] > b.tau[q] * (1.0f + kLbSlack)) {
+    if (f < 0) {
       dfo[idx] = -__builtin_inff();
       continue;
     }
